@@ -1,0 +1,139 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only builds inputs: point geometries, wavenumbers, the random
+test columns of the error metric, and the random factors of an exactly
+butterfly-structured matrix.  It holds none of the factorization's arithmetic
+(no range finder, no pivoted QR, no butterfly apply); both the oracle and the
+HIP path receive what it builds as plain arrays.
+
+Workload recipes (the paper's own operators are not available, so these
+synthetic operators of the same geometry class stand in for them):
+
+* Segment pair (the 2D parallel-line geometry of Sec. 6.2: two parallel lines
+  of unit length at unit distance).  Targets x_i = ((i+1/2)/m, 0), sources
+  y_j = ((j+1/2)/n, 1), kernel exp(i k r)/r with r = |x_i - y_j|.  The
+  wavenumber gives ``ppw`` points per wavelength at spacing 1/n:
+  k = 2 pi n / ppw.
+* Three parallel segments at y = 0, 1, 2 for the composition of two
+  oscillatory operators (category (ii) of Sec. 1).
+* 1D Fourier integral operator A_jk = exp(2 pi i (x_j xi_k + c(x_j)|xi_k|)),
+  x_j = j/n, xi_k = k - n/2, c(x) = (2 + sin 2 pi x)/16 ("low-dimensional
+  Fourier operators", Sec. 4.4.1).
+* Exact butterfly (Sec. 6.1): random unitary leaf bases and transfer blocks
+  and Gaussian centre blocks, all ranks r, leaves of 8 points, n = 2^(L+3).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "SegmentGeometry", "segment_pair", "segment_triple", "fio_params",
+    "test_columns", "ExactButterflyFactors", "exact_butterfly_factors",
+    "node_range_host",
+]
+
+
+@dataclass(frozen=True)
+class SegmentGeometry:
+    """Points of the target line (rows) and source line (columns)."""
+    targets: np.ndarray   # (m, 2) float64
+    sources: np.ndarray   # (n, 2) float64
+    k: float              # wavenumber of exp(i k r)/r
+    ppw: float            # points per wavelength at spacing 1/n
+
+
+def _line(npts: int, y: float) -> np.ndarray:
+    x = (np.arange(npts, dtype=np.float64) + 0.5) / npts
+    return np.stack([x, np.full(npts, float(y))], axis=1)
+
+
+def segment_pair(n: int, ppw: float = 8.0, m: int | None = None,
+                 y_target: float = 0.0, y_source: float = 1.0) -> SegmentGeometry:
+    """Two parallel unit segments at distance |y_source - y_target|.
+
+    ``k = 2 pi n / ppw`` puts ``ppw`` source points in one wavelength.
+    """
+    m = n if m is None else m
+    k = 2.0 * math.pi * n / ppw
+    return SegmentGeometry(_line(m, y_target), _line(n, y_source), k, ppw)
+
+
+def segment_triple(n: int, ppw: float = 8.0):
+    """Three parallel unit segments at y = 0, 1, 2 (same n and wavenumber).
+
+    Returns (A(X0, X1) geometry, A(X1, X2) geometry): the product of the two
+    kernels maps sources on y=2 to targets on y=0 through y=1.
+    """
+    g01 = segment_pair(n, ppw, y_target=0.0, y_source=1.0)
+    g12 = segment_pair(n, ppw, y_target=1.0, y_source=2.0)
+    return g01, g12
+
+
+def fio_params(n: int):
+    """Sample points x_j = j/n and frequencies xi_k = k - n/2 (integers)."""
+    if n % 2:
+        raise ValueError("FIO workload needs even n")
+    x = np.arange(n, dtype=np.float64) / n
+    xi = np.arange(n, dtype=np.int64) - n // 2
+    return x, xi
+
+
+def test_columns(n: int, ncols: int = 16, seed: int = 1001) -> np.ndarray:
+    """Gaussian complex test matrix of the error metric (Sec. 6, 16 columns)."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n, ncols)) + 1j * rng.standard_normal((n, ncols))
+    return (z / math.sqrt(2.0)).astype(np.complex128)
+
+
+def node_range_host(npts: int, level: int, idx: int) -> tuple[int, int]:
+    """Index range of node ``idx`` at ``level`` of a bisection tree over
+    ``npts`` sorted points: [floor(idx*N/2^l), floor((idx+1)*N/2^l))."""
+    return (idx * npts) >> level, ((idx + 1) * npts) >> level
+
+
+@dataclass
+class ExactButterflyFactors:
+    """Random factors of an L-level hybrid butterfly with all ranks r.
+
+    Block (l, i, j): T-node i at T-level l, S-node j at S-level L-l.
+    U[i]: (leaf, r) for leaves of the T-tree; V[j]: (leaf, r) for leaves of
+    the S-tree; R[l][(i, j)] (l_m <= l < L): (2r, r); W[l][(i, j)]
+    (1 <= l <= l_m): (2r, r); B[(i, j)] at l_m: (r, r).
+    """
+    L: int
+    r: int
+    n: int
+    U: list
+    V: list
+    R: dict
+    W: dict
+    B: dict
+
+
+def _unitary(rng, rows, cols):
+    z = rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))
+    q, _ = np.linalg.qr(z)
+    return q[:, :cols]
+
+
+def exact_butterfly_factors(L: int, r: int, seed: int = 7, leaf: int = 8) -> ExactButterflyFactors:
+    """Random exact butterfly of Sec. 6.1 (n = leaf * 2^L, every rank = r)."""
+    if r > leaf:
+        raise ValueError("rank cannot exceed the leaf size")
+    rng = np.random.default_rng(seed)
+    n = leaf << L
+    lm = L // 2
+    U = [_unitary(rng, leaf, r) for _ in range(1 << L)]
+    V = [_unitary(rng, leaf, r) for _ in range(1 << L)]
+    R = {l: {(i, j): _unitary(rng, 2 * r, r)
+             for i in range(1 << l) for j in range(1 << (L - l))}
+         for l in range(lm, L)}
+    W = {l: {(i, j): _unitary(rng, 2 * r, r)
+             for i in range(1 << l) for j in range(1 << (L - l))}
+         for l in range(1, lm + 1)}
+    B = {(i, j): (rng.standard_normal((r, r)) + 1j * rng.standard_normal((r, r))) / math.sqrt(2)
+         for i in range(1 << lm) for j in range(1 << (L - lm))}
+    return ExactButterflyFactors(L, r, n, U, V, R, W, B)
