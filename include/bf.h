@@ -1,0 +1,246 @@
+/*
+ * bf.h -- C ABI of the MI355X (gfx950) randomized butterfly library.
+ *
+ * The library builds the hybrid butterfly factorization of an m x n complex
+ * operator A that it sees only through products with A and A^H (Liu, Xing,
+ * Guo, Michielssen, Ghysels, Li, "Butterfly factorization via randomized
+ * matrix-vector multiplications", arXiv:2002.03400, Alg. 2), and applies the
+ * result.  Output form (Alg. 2 output, eq. hybrid_butterfly_mat):
+ *
+ *     A ~ (U^L R^{L-1} ... R^{l_m}) B^{l_m} (W^{l_m} ... W^1 V^0),
+ *     l_m = floor(L/2).
+ *
+ * Conventions shared by every call:
+ *   - complex numbers are interleaved (re, im); bf_c64 = two floats,
+ *     bf_c128 = two doubles;
+ *   - matrices are column-major with an explicit leading dimension (ld >=
+ *     rows); all device pointers are HIP device (HBM) addresses;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     calls enqueue work on it and return; results are valid once the stream
+ *     has reached the call;
+ *   - every call returns BF_OK (0) or a negative error code and never aborts;
+ *     on failure nothing is leaked and output handles are left untouched;
+ *   - transposes of the paper are conjugate transposes (Sec. 2.1 extends the
+ *     real algorithms to complex matrices): "rmatvec" is Y = A^H X.
+ */
+#ifndef BF_H
+#define BF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } bf_c64;
+typedef struct { double re, im; } bf_c128;
+
+enum {
+  BF_OK = 0,
+  BF_EINVAL = -1,     /* bad argument: sizes <= 0, tol not in (0,1), leaf < 1, NULL */
+  BF_ENOMEM = -2,     /* device or pinned host allocation failed */
+  BF_ECALLBACK = -3,  /* a black-box callback returned nonzero */
+  BF_ERANK = -4,      /* rank estimate passed opts.max_rank, or a block exceeds the
+                         kernels' size limits (BF_MAX_BLOCK_ROWS / _COLS) */
+  BF_EHIP = -5,       /* a HIP runtime call failed */
+  BF_ENOTSUP = -6     /* no usable GPU / wrong architecture */
+};
+
+/* Largest Z block the batched QR kernels accept (rows x columns). */
+#define BF_MAX_BLOCK_ROWS 256
+#define BF_MAX_BLOCK_COLS 256
+
+/*
+ * Black-box product (the input of Alg. 2: "routine for multiplying K(T,S)
+ * and its transpose with arbitrary matrices").  Writes Y = op(A) X on
+ * `stream`, op = A for the matvec callback (X has n rows, Y has m rows) and
+ * op = A^H for the rmatvec callback (X has m rows, Y has n rows).
+ *
+ *   seg == NULL : plain product of the ncols columns of X.
+ *   seg != NULL : structured samples of Sec. 4.1.  `seg` is a HOST array of
+ *                 nseg+1 increasing row offsets that partition the rows of X;
+ *                 group g is the row range [seg[g], seg[g+1]).  Y has
+ *                 nseg*ncols columns and its columns [g*ncols, (g+1)*ncols)
+ *                 receive op(A)(:, seg_g) * X(seg_g, :) -- the product with
+ *                 the random matrix that is zero outside node g.
+ *
+ * X and Y are device buffers owned by the library for the duration of the
+ * call; the callback must not keep them.  Return 0 on success; any nonzero
+ * value aborts the construction with BF_ECALLBACK.
+ */
+typedef int (*bf_op_fn)(void* user, const bf_c64* X, int64_t ldx, int64_t ncols,
+                        bf_c64* Y, int64_t ldy, const int64_t* seg, int32_t nseg,
+                        void* stream);
+
+/* A black box with both products (built-in operators fill this in). */
+typedef struct {
+  bf_op_fn matvec;
+  bf_op_fn rmatvec;
+  void* user;
+  int64_t m, n;
+} bf_operator;
+
+/* Knobs of Alg. 2.  Pass NULL for the defaults p = 2, r0 = 4 (the values of
+   Sec. 6.1 and 6.2), seed = 0, no rank cap. */
+typedef struct {
+  int32_t p;          /* over-sampling (Alg. 1 input), >= 0 */
+  int32_t r0;         /* initial rank guess of the adaptive loops, >= 1 */
+  int32_t max_rank;   /* 0 = none; else BF_ERANK when a rank estimate passes it */
+  int32_t flags;      /* reserved, 0 */
+  uint64_t seed;      /* key of the counter-based random matrices */
+} bf_opts;
+
+typedef struct bf_factors bf_factors;
+
+/*
+ * Alg. 2: adaptive randomized hybrid butterfly construction.
+ *   matvec, rmatvec, user : the black box (see bf_op_fn); both required.
+ *   m, n                  : operator size (rows = targets T, cols = sources S).
+ *   tol                   : truncation tolerance eps of Alg. 1, in (0, 1);
+ *                           read as the relative Frobenius tail of each
+ *                           sample, ||R[k:,k:]||_F <= eps ||Y||_F.
+ *   leaf                  : leaf size n0 of the bisection trees (Sec. 3.1);
+ *                           L is the smallest level count with
+ *                           ceil(max(m,n)/2^L) <= leaf.
+ *   opts                  : NULL or knobs above.
+ *   stream                : all device work and callbacks use this stream.
+ *   out                   : receives the factor handle (owned by the caller,
+ *                           release with bf_free).
+ * The random matrices are drawn in complex64 from Philox4x64-10 keyed by
+ * (seed, phase, level, node, row, col); black-box products are complex64;
+ * every pivoted QR and least-squares solve runs in FP64 on the device.
+ * Blocks on the host: syncs once per adaptive iteration and per level.
+ */
+int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64_t n,
+                 double tol, int64_t leaf, const bf_opts* opts, void* stream,
+                 bf_factors** out);
+
+/*
+ * Apply the factorization (eq. hybrid_butterfly_mat, right to left):
+ *   trans = 0 : Y = F X,   X is n x ncols (ldx >= n), Y is m x ncols (ldy >= m)
+ *   trans = 1 : Y = F^H X, X is m x ncols,            Y is n x ncols
+ * complex64 data, FP32 accumulation.  X, Y are caller-owned device buffers
+ * and must not overlap.  Reentrant across streams for one handle.
+ */
+int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
+             bf_c64* Y, int64_t ldy, void* stream);
+
+/* Summary of a factorization. */
+typedef struct {
+  int64_t m, n;
+  int32_t L, lm;
+  int32_t max_rank;          /* over every block of every level */
+  int32_t v_iters, u_iters;  /* passes of the two adaptive leaf loops */
+  int64_t matvec_cols;       /* black-box columns used: products with A ... */
+  int64_t rmatvec_cols;      /* ... and with A^H (structured samples count s each) */
+  int64_t factor_entries;    /* complex entries stored over all factors */
+  int64_t device_bytes;      /* device memory held by the handle */
+} bf_info;
+int bf_stats(const bf_factors* F, bf_info* info);
+
+/*
+ * Ranks of every block.  kU receives (L - lm + 1) * 2^L ints: level l in
+ * lm..L, block (l, i, j) at [(l - lm) * 2^L + i * 2^(L-l) + j].  kV receives
+ * (lm + 1) * 2^L ints: level l in 0..lm at [l * 2^L + i * 2^(L-l) + j].
+ * Host buffers; either may be NULL.
+ */
+int bf_ranks(const bf_factors* F, int32_t* kU, int32_t* kV);
+
+/*
+ * Factor data exchange in FP64 (host buffers).  Canonical order, each block
+ * column-major with ld = its row count:
+ *   U_{L,i} (i = 0..2^L-1), then R^{l} for l = L-1 down to lm (blocks (i, j)
+ *   i-major), then B (i, j), then W^{l} for l = lm down to 1, then V_{0,j}.
+ * Shapes follow from the ranks (bf_ranks layout): U_{L,i}: m_i x kU(L,i,0);
+ * R_{l,i,j}: (kU(l+1,2i,j>>1) + kU(l+1,2i+1,j>>1)) x kU(l,i,j);
+ * B_{i,j}: kU(lm,i,j) x kV(lm,i,j);
+ * W_{l,i,j}: (kV(l-1,i>>1,2j) + kV(l-1,i>>1,2j+1)) x kV(l,i,j);
+ * V_{0,j}: n_j x kV(0,0,j).
+ * bf_export writes `count` entries (query with data == NULL to get count).
+ * bf_import builds a handle from ranks + data (used for exact-butterfly black
+ * boxes and for applying externally built factors).
+ */
+int bf_export(const bf_factors* F, bf_c128* data, int64_t* count);
+int bf_import(int64_t m, int64_t n, int64_t leaf, const int32_t* kU, const int32_t* kV,
+              const bf_c128* data, int64_t count, void* stream, bf_factors** out);
+
+/* Release a handle (waits for `stream` work that uses it to be enqueued before). */
+int bf_free(bf_factors* F, void* stream);
+
+/* Text for an error code (static storage). */
+const char* bf_strerror(int code);
+
+/* Detail message of the calling thread's last failed call (thread-local storage,
+   valid until that thread's next failing call). */
+const char* bf_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Kernel-level entry points: the batched building blocks of Alg. 2 exposed
+ * on their own so that each can be checked against a reference.  All buffers
+ * are device buffers unless marked HOST.
+ * ------------------------------------------------------------------------ */
+
+/* Complex Gaussians of the random matrices of Alg. 2: out[r + c*rows] =
+ * g(seed, tag, row0 + r, c) for r < rows, c < cols, in FP64, where
+ * g = sqrt(-2 ln u0) (cos 2 pi u1 + i sin 2 pi u1) / sqrt(2),
+ * u_q = ((o_q >> 12) + 1/2) 2^-52 and (o_0, o_1, ..) = Philox4x64-10 of
+ * counter (row, col, tag, 0) under key (seed, 0) (Salmon et al., SC'11). */
+int bf_gauss(uint64_t seed, uint64_t tag, int64_t row0, int64_t rows, int64_t cols,
+             bf_c128* out, void* stream);
+
+/* Alg. 1 step 3 on a batch: block b is M[b] x N[b] (HOST arrays), stored
+ * column-major (ld = M[b]) at Z + zoff[b] (HOST offsets, in elements).  Its
+ * truncated pivoted-QR basis Q_k (M[b] x k, ld = M[b]) is written at
+ * Q + qoff[b] (room for M[b] x min(M[b], N[b]) entries) and k into
+ * ranks[b] (HOST).  Rank rule: first k >= 1 with ||R[k:,k:]||_F <= tol ||Z||_F,
+ * else min(M, N); 0 for an empty block.  Synchronizes `stream`. */
+int bf_cpqr_batched(int32_t nblk, const int32_t* M, const int32_t* N, const bf_c128* Z,
+                    const int64_t* zoff, double tol, bf_c128* Q, const int64_t* qoff,
+                    int32_t* ranks, void* stream);
+
+/* Centre blocks by least squares (Sec. 4.4, eq. Bij read from its argmin):
+ * B_b = argmin ||C_b - B X_b||_F with C_b kU[b] x s[b] at C + coff[b],
+ * X_b kV[b] x s[b] at X + xoff[b], B_b kU[b] x kV[b] at B + boff[b]
+ * (column-major, ld = row count; HOST shape/offset arrays; s[b] >= kV[b]). */
+int bf_lsq_batched(int32_t nblk, const int32_t* kU, const int32_t* kV, const int32_t* s,
+                   const bf_c128* C, const int64_t* coff, const bf_c128* X, const int64_t* xoff,
+                   bf_c128* B, const int64_t* boff, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Built-in black boxes.  Each fills a bf_operator whose callbacks run HIP
+ * kernels on the stream they are given; release with bf_operator_destroy.
+ * ------------------------------------------------------------------------ */
+
+/* A_ij = exp(i k r_ij) / r_ij, r_ij = |x_i - y_j| (2D points), evaluated on the
+ * fly: phase k r reduced in FP64, sin/cos and 1/r in FP32, complex64 products
+ * with FP32 accumulation.  targets: m x 2 row-major doubles (host), sources:
+ * n x 2 (host); copied to the device.  The kernel family of Sec. 3 on the
+ * parallel-line geometry of Sec. 6.2. */
+int bf_op_segkernel(const double* targets, int64_t m, const double* sources, int64_t n,
+                    double k, bf_operator* out);
+
+/* A_jk = exp(2 pi i (x_j xi_k + c(x_j) |xi_k|)), x_j = j/n, xi_k = k - n/2,
+ * c(x) = (2 + sin 2 pi x)/16: a 1D Fourier integral operator (Sec. 4.4.1,
+ * "low-dimensional Fourier operators").  x_j xi_k is reduced modulo 1 exactly
+ * in integers.  n even. */
+int bf_op_fio(int64_t n, bf_operator* out);
+
+/* Explicit matrix: A is a device m x n complex64 matrix with leading
+ * dimension lda (>= m); the operator keeps the pointer, the caller keeps the
+ * memory alive while the operator is used. */
+int bf_op_dense(const bf_c64* A, int64_t m, int64_t n, int64_t lda, bf_operator* out);
+
+/* A built factorization as a black box (category (ii) of Sec. 1: operators
+ * applied in quasi-linear time).  Keeps a reference to F. */
+int bf_op_factors(const bf_factors* F, bf_operator* out);
+
+/* Composition A = A1 A2 (A1: m x k, A2: k x n), e.g. the product of two
+ * butterflies to be recompressed.  Keeps references to both. */
+int bf_op_compose(const bf_operator* a1, const bf_operator* a2, bf_operator* out);
+
+int bf_operator_destroy(bf_operator* op);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BF_H */

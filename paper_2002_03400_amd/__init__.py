@@ -1,0 +1,379 @@
+"""Python binding of libbf (MI355X randomized butterfly factorization).
+
+Argument marshalling only: every step of the factorization runs in the HIP
+kernels of ``libbf.so`` through its C ABI (``include/bf.h``).  PyTorch provides
+device memory and the current HIP stream.  There is no CPU fallback: if the
+library is not built, or no gfx950 device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbf.so")
+
+__all__ = ["BFError", "lib", "Operator", "Factors", "construct", "segkernel", "fio", "dense",
+           "from_factors", "compose", "import_factors", "gauss", "cpqr_batched", "lsq_batched",
+           "num_levels", "LIB_PATH"]
+
+
+class BFError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = f"{where}: {lib().bf_strerror(code).decode()} ({code})"
+        detail = lib().bf_last_error()
+        if detail:
+            msg += f": {detail.decode()}"
+        super().__init__(msg)
+
+
+class bf_c64(C.Structure):
+    _fields_ = [("re", C.c_float), ("im", C.c_float)]
+
+
+OPFN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                   C.POINTER(C.c_int64), C.c_int32, C.c_void_p)
+
+
+class bf_operator(C.Structure):
+    _fields_ = [("matvec", C.c_void_p), ("rmatvec", C.c_void_p), ("user", C.c_void_p),
+                ("m", C.c_int64), ("n", C.c_int64)]
+
+
+class bf_opts(C.Structure):
+    _fields_ = [("p", C.c_int32), ("r0", C.c_int32), ("max_rank", C.c_int32),
+                ("flags", C.c_int32), ("seed", C.c_uint64)]
+
+
+class bf_info(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("L", C.c_int32), ("lm", C.c_int32),
+                ("max_rank", C.c_int32), ("v_iters", C.c_int32), ("u_iters", C.c_int32),
+                ("matvec_cols", C.c_int64), ("rmatvec_cols", C.c_int64),
+                ("factor_entries", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+_LIB = None
+_P = C.c_void_p
+_I64P = C.POINTER(C.c_int64)
+_I32P = C.POINTER(C.c_int32)
+
+# name -> (restype, argtypes); every symbol of include/bf.h
+SIGNATURES = {
+    "bf_construct": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, C.c_double, C.c_int64,
+                               C.POINTER(bf_opts), _P, C.POINTER(_P)]),
+    "bf_apply": (C.c_int, [_P, C.c_int, _P, C.c_int64, C.c_int64, _P, C.c_int64, _P]),
+    "bf_stats": (C.c_int, [_P, C.POINTER(bf_info)]),
+    "bf_ranks": (C.c_int, [_P, _I32P, _I32P]),
+    "bf_export": (C.c_int, [_P, _P, _I64P]),
+    "bf_import": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _I32P, _I32P, _P, C.c_int64, _P,
+                            C.POINTER(_P)]),
+    "bf_free": (C.c_int, [_P, _P]),
+    "bf_strerror": (C.c_char_p, [C.c_int]),
+    "bf_last_error": (C.c_char_p, []),
+    "bf_gauss": (C.c_int, [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
+    "bf_cpqr_batched": (C.c_int, [C.c_int32, _I32P, _I32P, _P, _I64P, C.c_double, _P, _I64P,
+                                  _I32P, _P]),
+    "bf_lsq_batched": (C.c_int, [C.c_int32, _I32P, _I32P, _I32P, _P, _I64P, _P, _I64P, _P,
+                                 _I64P, _P]),
+    "bf_op_segkernel": (C.c_int, [_P, C.c_int64, _P, C.c_int64, C.c_double,
+                                  C.POINTER(bf_operator)]),
+    "bf_op_fio": (C.c_int, [C.c_int64, C.POINTER(bf_operator)]),
+    "bf_op_dense": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, C.POINTER(bf_operator)]),
+    "bf_op_factors": (C.c_int, [_P, C.POINTER(bf_operator)]),
+    "bf_op_compose": (C.c_int, [C.POINTER(bf_operator), C.POINTER(bf_operator),
+                                C.POINTER(bf_operator)]),
+    "bf_operator_destroy": (C.c_int, [C.POINTER(bf_operator)]),
+}
+
+
+def lib():
+    """Load libbf.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2002_03400_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise BFError(rc, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_c64(x):
+    torch = _torch()
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64):
+        raise TypeError("expected a complex64 CUDA tensor")
+    return x
+
+
+def _colmajor(x):
+    """(rows, cols) tensor -> column-major storage (returns tensor, ld)."""
+    if x.dim() == 1:
+        x = x[:, None]
+    if x.stride(0) == 1 and x.stride(1) >= max(1, x.shape[0]):
+        return x, x.stride(1)
+    y = x.t().contiguous().t()
+    return y, max(1, y.shape[0])
+
+
+def _empty_colmajor(rows, cols, dtype, device):
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def num_levels(m, n, leaf):
+    L = 0
+    while -(-max(m, n) // (1 << L)) > leaf:
+        L += 1
+    return L
+
+
+class Operator:
+    """A black box with products by A and A^H (a bf_operator)."""
+
+    def __init__(self, op: bf_operator, keep=()):
+        self._op = op
+        self._keep = keep
+        self.m, self.n = op.m, op.n
+
+    def _call(self, fnptr, X, seg, stream):
+        X = _dev_c64(X)
+        X, ldx = _colmajor(X)
+        rows_out = self.n if fnptr == self._op.rmatvec else self.m
+        ncols = X.shape[1]
+        if seg is None:
+            ycols, segp, nseg = ncols, None, 0
+        else:
+            seg = np.ascontiguousarray(seg, dtype=np.int64)
+            nseg = len(seg) - 1
+            ycols = nseg * ncols
+            segp = seg.ctypes.data_as(_I64P)
+        Y = _empty_colmajor(rows_out, ycols, X.dtype, X.device)
+        fn = OPFN(fnptr)
+        rc = fn(self._op.user, X.data_ptr(), ldx, ncols, Y.data_ptr(), max(1, rows_out), segp,
+                nseg, _stream(stream))
+        _check(rc, "operator callback")
+        return Y
+
+    def matvec(self, X, seg=None, stream=None):
+        return self._call(self._op.matvec, X, seg, stream)
+
+    def rmatvec(self, X, seg=None, stream=None):
+        return self._call(self._op.rmatvec, X, seg, stream)
+
+    def close(self):
+        if self._op.user:
+            lib().bf_operator_destroy(C.byref(self._op))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def segkernel(targets, sources, k) -> Operator:
+    t = np.ascontiguousarray(targets, dtype=np.float64)
+    s = np.ascontiguousarray(sources, dtype=np.float64)
+    op = bf_operator()
+    _check(lib().bf_op_segkernel(t.ctypes.data, len(t), s.ctypes.data, len(s), float(k),
+                                 C.byref(op)), "bf_op_segkernel")
+    return Operator(op)
+
+
+def fio(n) -> Operator:
+    op = bf_operator()
+    _check(lib().bf_op_fio(int(n), C.byref(op)), "bf_op_fio")
+    return Operator(op)
+
+
+def dense(A) -> Operator:
+    A = _dev_c64(A)
+    A, lda = _colmajor(A)
+    op = bf_operator()
+    _check(lib().bf_op_dense(A.data_ptr(), A.shape[0], A.shape[1], lda, C.byref(op)), "bf_op_dense")
+    return Operator(op, keep=(A,))
+
+
+def from_factors(F: "Factors") -> Operator:
+    op = bf_operator()
+    _check(lib().bf_op_factors(F._h, C.byref(op)), "bf_op_factors")
+    return Operator(op, keep=(F,))
+
+
+def compose(a1: Operator, a2: Operator) -> Operator:
+    op = bf_operator()
+    _check(lib().bf_op_compose(C.byref(a1._op), C.byref(a2._op), C.byref(op)), "bf_op_compose")
+    return Operator(op, keep=(a1, a2))
+
+
+@dataclass
+class Info:
+    m: int
+    n: int
+    L: int
+    lm: int
+    max_rank: int
+    v_iters: int
+    u_iters: int
+    matvec_cols: int
+    rmatvec_cols: int
+    factor_entries: int
+    device_bytes: int
+
+
+class Factors:
+    """Handle of a hybrid butterfly factorization (owned; freed on close)."""
+
+    def __init__(self, handle, leaf):
+        self._h = handle
+        self.leaf = leaf
+        inf = self.stats()
+        self.m, self.n, self.L, self.lm = inf.m, inf.n, inf.L, inf.lm
+
+    def stats(self) -> Info:
+        i = bf_info()
+        _check(lib().bf_stats(self._h, C.byref(i)), "bf_stats")
+        return Info(*[getattr(i, f) for f, _ in bf_info._fields_])
+
+    def ranks(self):
+        nb = 1 << self.L
+        kU = np.zeros((self.L - self.lm + 1) * nb, np.int32)
+        kV = np.zeros((self.lm + 1) * nb, np.int32)
+        _check(lib().bf_ranks(self._h, kU.ctypes.data_as(_I32P), kV.ctypes.data_as(_I32P)),
+               "bf_ranks")
+        return kU.reshape(self.L - self.lm + 1, nb), kV.reshape(self.lm + 1, nb)
+
+    def export(self) -> np.ndarray:
+        cnt = C.c_int64(0)
+        _check(lib().bf_export(self._h, None, C.byref(cnt)), "bf_export")
+        data = np.zeros(cnt.value, np.complex128)
+        _check(lib().bf_export(self._h, data.ctypes.data, C.byref(cnt)), "bf_export")
+        return data
+
+    def apply(self, X, trans=False, out=None, stream=None):
+        X = _dev_c64(X)
+        X, ldx = _colmajor(X)
+        rows_out = self.n if trans else self.m
+        if out is None:
+            out = _empty_colmajor(rows_out, X.shape[1], X.dtype, X.device)
+        Y, ldy = _colmajor(out)
+        _check(lib().bf_apply(self._h, int(bool(trans)), X.data_ptr(), ldx, X.shape[1],
+                              Y.data_ptr(), ldy, _stream(stream)), "bf_apply")
+        return Y
+
+    def close(self, stream=None):
+        if self._h:
+            lib().bf_free(self._h, _stream(stream) if stream is not None else None)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed: int = 0,
+              max_rank: int = 0, stream=None) -> Factors:
+    """Alg. 2 on the device; returns the factor handle."""
+    o = bf_opts(p, r0, max_rank, 0, seed)
+    h = C.c_void_p()
+    _check(lib().bf_construct(op._op.matvec, op._op.rmatvec, op._op.user, op.m, op.n, float(tol),
+                              int(leaf), C.byref(o), _stream(stream), C.byref(h)), "bf_construct")
+    return Factors(h, leaf)
+
+
+def import_factors(m, n, leaf, kU, kV, data, stream=None) -> Factors:
+    kU = np.ascontiguousarray(kU, np.int32).ravel()
+    kV = np.ascontiguousarray(kV, np.int32).ravel()
+    data = np.ascontiguousarray(data, np.complex128)
+    h = C.c_void_p()
+    _check(lib().bf_import(m, n, leaf, kU.ctypes.data_as(_I32P), kV.ctypes.data_as(_I32P),
+                           data.ctypes.data, len(data), _stream(stream), C.byref(h)), "bf_import")
+    return Factors(h, leaf)
+
+
+def gauss(seed, tag, row0, rows, cols, device="cuda"):
+    torch = _torch()
+    out = _empty_colmajor(rows, cols, torch.complex128, device)
+    _check(lib().bf_gauss(seed, tag, row0, rows, cols, out.data_ptr(), _stream()), "bf_gauss")
+    return out
+
+
+def cpqr_batched(blocks, tol, device="cuda"):
+    """Truncated pivoted QR of each block (list of 2D complex arrays) on the GPU."""
+    torch = _torch()
+    M = np.array([b.shape[0] for b in blocks], np.int32)
+    N = np.array([b.shape[1] for b in blocks], np.int32)
+    zoff = np.zeros(len(blocks), np.int64)
+    qoff = np.zeros(len(blocks), np.int64)
+    parts, zo, qo = [], 0, 0
+    for t, b in enumerate(blocks):
+        zoff[t], qoff[t] = zo, qo
+        parts.append(np.asarray(b, np.complex128).ravel(order="F"))
+        zo += b.size
+        qo += b.shape[0] * min(b.shape)
+    Z = torch.from_numpy(np.concatenate(parts) if parts else np.zeros(1, np.complex128)).to(device)
+    Q = torch.zeros(max(qo, 1), dtype=torch.complex128, device=device)
+    ranks = np.zeros(len(blocks), np.int32)
+    _check(lib().bf_cpqr_batched(len(blocks), M.ctypes.data_as(_I32P), N.ctypes.data_as(_I32P),
+                                 Z.data_ptr(), zoff.ctypes.data_as(_I64P), float(tol), Q.data_ptr(),
+                                 qoff.ctypes.data_as(_I64P), ranks.ctypes.data_as(_I32P),
+                                 _stream()), "bf_cpqr_batched")
+    Qh = Q.cpu().numpy()
+    out = []
+    for t, b in enumerate(blocks):
+        k = int(ranks[t])
+        out.append(Qh[qoff[t]:qoff[t] + b.shape[0] * k].reshape((b.shape[0], k), order="F"))
+    return out, ranks
+
+
+def lsq_batched(Cs, Xs, device="cuda"):
+    """B_b = argmin ||C_b - B X_b||_F for each pair, on the GPU."""
+    torch = _torch()
+    kU = np.array([c.shape[0] for c in Cs], np.int32)
+    kV = np.array([x.shape[0] for x in Xs], np.int32)
+    s = np.array([x.shape[1] for x in Xs], np.int32)
+    coff, xoff, boff = (np.zeros(len(Cs), np.int64) for _ in range(3))
+    cp, xp, co, xo, bo = [], [], 0, 0, 0
+    for t in range(len(Cs)):
+        coff[t], xoff[t], boff[t] = co, xo, bo
+        cp.append(np.asarray(Cs[t], np.complex128).ravel(order="F"))
+        xp.append(np.asarray(Xs[t], np.complex128).ravel(order="F"))
+        co += Cs[t].size
+        xo += Xs[t].size
+        bo += kU[t] * kV[t]
+    Cd = torch.from_numpy(np.concatenate(cp)).to(device)
+    Xd = torch.from_numpy(np.concatenate(xp)).to(device)
+    Bd = torch.zeros(max(bo, 1), dtype=torch.complex128, device=device)
+    _check(lib().bf_lsq_batched(len(Cs), kU.ctypes.data_as(_I32P), kV.ctypes.data_as(_I32P),
+                                s.ctypes.data_as(_I32P), Cd.data_ptr(), coff.ctypes.data_as(_I64P),
+                                Xd.data_ptr(), xoff.ctypes.data_as(_I64P), Bd.data_ptr(),
+                                boff.ctypes.data_as(_I64P), _stream()), "bf_lsq_batched")
+    Bh = Bd.cpu().numpy()
+    return [Bh[boff[t]:boff[t] + kU[t] * kV[t]].reshape((kU[t], kV[t]), order="F")
+            for t in range(len(Cs))]

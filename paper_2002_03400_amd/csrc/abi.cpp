@@ -1,0 +1,626 @@
+// C ABI of libbf: argument checks, error codes, memory utilities, factor
+// import/export and the built-in black-box operators.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+
+#include "factors.h"
+
+namespace bf {
+
+bf_factors* construct(bf_op_fn mv, bf_op_fn rmv, void* user, int64_t m, int64_t n, double tol,
+                      int64_t leaf, const bf_opts* o, hipStream_t s);
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// ---- memory ---------------------------------------------------------------
+static std::once_flag g_pool_once[64];
+
+bool validating() {
+  static const bool on = [] {
+    const char* v = std::getenv("BF_VALIDATE");
+    return v && v[0] && v[0] != '0';
+  }();
+  return on;
+}
+
+static std::mutex g_reg_mu;
+static std::map<uintptr_t, size_t> g_reg;   // live allocations (validation mode)
+
+void check_extent(const void* p, size_t bytes, const char* what) {
+  if (!validating() || bytes == 0) return;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  auto it = g_reg.upper_bound(a);
+  if (it != g_reg.begin()) {
+    --it;
+    if (a >= it->first && a + bytes <= it->first + it->second) return;
+  }
+  throw Error(BF_EINVAL, std::string("bounds check failed: ") + what);
+}
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+  int dev = 0;
+  BF_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64) {
+    std::call_once(g_pool_once[dev], [dev]() {
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+      }
+    });
+  }
+  void* p = nullptr;
+  BF_HIP(hipMallocAsync(&p, bytes, s));
+  if (validating()) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_reg[reinterpret_cast<uintptr_t>(p)] = bytes;
+  }
+  return p;
+}
+
+void dev_free(void* p, hipStream_t s) {
+  if (!p) return;
+  if (validating()) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_reg.erase(reinterpret_cast<uintptr_t>(p));
+  }
+  (void)hipFreeAsync(p, s);
+}
+
+Staging::~Staging() {
+  if (h) (void)hipHostFree(h);
+}
+
+void* Staging::alloc(size_t bytes, hipStream_t s) {
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (off + need > cap) {
+    if (h) {
+      // earlier copies from the old block may still be in flight
+      BF_HIP(hipStreamSynchronize(s));
+      BF_HIP(hipHostFree(h));
+      h = nullptr;
+    }
+    cap = std::max<size_t>(std::max<size_t>(2 * cap, need), 1 << 20);
+    void* p = nullptr;
+    BF_HIP(hipHostMalloc(&p, cap, hipHostMallocDefault));
+    h = static_cast<char*>(p);
+    off = 0;
+  }
+  void* r = h + off;
+  off += need;
+  return r;
+}
+
+// ---- operators --------------------------------------------------------------
+struct SegCtx {
+  DevBuf<double> tx, ty, sx, sy;
+  int64_t m, n;
+  double kk;
+};
+struct FioCtx {
+  DevBuf<double> cx;
+  int64_t n;
+};
+struct DenseCtx {
+  const bf_c64* A;
+  int64_t m, n, lda;
+};
+struct FactorsCtx {
+  const bf_factors* F;
+};
+struct ComposeCtx {
+  bf_operator a1, a2;
+};
+
+enum OpKind { OP_SEG = 1, OP_FIO, OP_DENSE, OP_FACTORS, OP_COMPOSE };
+struct OpHeader {
+  int kind;
+  void* ctx;
+};
+
+template <typename Fn>
+static int guarded(Fn&& fn) {
+  try {
+    fn();
+    return BF_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return BF_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return BF_EHIP;
+  }
+}
+
+static int seg_apply(void* user, bool adj, const bf_c64* X, int64_t ldx, int64_t ncols, bf_c64* Y,
+                     int64_t ldy, const int64_t* seg, int32_t nseg, void* stream) {
+  return guarded([&] {
+    auto* c = static_cast<SegCtx*>(static_cast<OpHeader*>(user)->ctx);
+    PointSet T{c->tx.p, c->ty.p}, S{c->sx.p, c->sy.p};
+    if (!adj)
+      launch_segkernel(T, c->m, S, c->n, c->kk, +1, X, ldx, ncols, Y, ldy, seg, nseg,
+                       (hipStream_t)stream);
+    else
+      launch_segkernel(S, c->n, T, c->m, c->kk, -1, X, ldx, ncols, Y, ldy, seg, nseg,
+                       (hipStream_t)stream);
+  });
+}
+static int seg_mv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                  const int64_t* seg, int32_t nseg, void* st) {
+  return seg_apply(u, false, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+static int seg_rmv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                   const int64_t* seg, int32_t nseg, void* st) {
+  return seg_apply(u, true, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+
+static int fio_apply(void* user, int adj, const bf_c64* X, int64_t ldx, int64_t ncols, bf_c64* Y,
+                     int64_t ldy, const int64_t* seg, int32_t nseg, void* stream) {
+  return guarded([&] {
+    auto* c = static_cast<FioCtx*>(static_cast<OpHeader*>(user)->ctx);
+    launch_fio(c->n, c->cx.p, adj, X, ldx, ncols, Y, ldy, seg, nseg, (hipStream_t)stream);
+  });
+}
+static int fio_mv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                  const int64_t* seg, int32_t nseg, void* st) {
+  return fio_apply(u, 0, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+static int fio_rmv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                   const int64_t* seg, int32_t nseg, void* st) {
+  return fio_apply(u, 1, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+
+static int dense_apply(void* user, int adj, const bf_c64* X, int64_t ldx, int64_t ncols,
+                       bf_c64* Y, int64_t ldy, const int64_t* seg, int32_t nseg, void* stream) {
+  return guarded([&] {
+    auto* c = static_cast<DenseCtx*>(static_cast<OpHeader*>(user)->ctx);
+    launch_dense(c->A, c->m, c->n, c->lda, adj, X, ldx, ncols, Y, ldy, seg, nseg,
+                 (hipStream_t)stream);
+  });
+}
+static int dense_mv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                    const int64_t* seg, int32_t nseg, void* st) {
+  return dense_apply(u, 0, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+static int dense_rmv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                     const int64_t* seg, int32_t nseg, void* st) {
+  return dense_apply(u, 1, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+
+// Segment-stacked input for an operator that only has plain products: expand
+// X into the block-diagonal nrows x (nseg*ncols) matrix, then multiply.
+static void expand(const bf_c64* X, int64_t ldx, int64_t rows, int64_t ncols, const int64_t* seg,
+                   int32_t nseg, DevBuf<bf_c64>& out, hipStream_t s) {
+  std::vector<int64_t> sv(seg, seg + nseg + 1);
+  DevBuf<int64_t> sd(sv.size(), s);
+  BF_HIP(hipMemcpyAsync(sd.p, sv.data(), sv.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  out = DevBuf<bf_c64>((size_t)rows * nseg * ncols, s);
+  launch_expand_segments(X, ldx, rows, ncols, sd.p, nseg, out.p, rows, s);
+}
+
+static int factors_apply(void* user, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
+                         bf_c64* Y, int64_t ldy, const int64_t* seg, int32_t nseg, void* stream) {
+  return guarded([&] {
+    auto* c = static_cast<FactorsCtx*>(static_cast<OpHeader*>(user)->ctx);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t rows_in = trans ? c->F->m : c->F->n;
+    if (!seg) {
+      apply_factors(c->F, trans, X, ldx, ncols, Y, ldy, s);
+      return;
+    }
+    DevBuf<bf_c64> Xe;
+    expand(X, ldx, rows_in, ncols, seg, nseg, Xe, s);
+    apply_factors(c->F, trans, Xe.p, rows_in, (int64_t)nseg * ncols, Y, ldy, s);
+  });
+}
+static int factors_mv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                      const int64_t* seg, int32_t nseg, void* st) {
+  return factors_apply(u, 0, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+static int factors_rmv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                       const int64_t* seg, int32_t nseg, void* st) {
+  return factors_apply(u, 1, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+
+static int compose_apply(void* user, int adj, const bf_c64* X, int64_t ldx, int64_t ncols,
+                         bf_c64* Y, int64_t ldy, const int64_t* seg, int32_t nseg, void* stream) {
+  auto* c = static_cast<ComposeCtx*>(static_cast<OpHeader*>(user)->ctx);
+  int rc = BF_OK;
+  int rc2 = guarded([&] {
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t k = c->a1.n;   // inner dimension
+    const int64_t tcols = seg ? (int64_t)nseg * ncols : ncols;
+    DevBuf<bf_c64> T((size_t)k * tcols, s);
+    if (!adj) {
+      rc = c->a2.matvec(c->a2.user, X, ldx, ncols, T.p, k, seg, nseg, stream);
+      if (rc) return;
+      rc = c->a1.matvec(c->a1.user, T.p, k, tcols, Y, ldy, nullptr, 0, stream);
+    } else {
+      rc = c->a1.rmatvec(c->a1.user, X, ldx, ncols, T.p, k, seg, nseg, stream);
+      if (rc) return;
+      rc = c->a2.rmatvec(c->a2.user, T.p, k, tcols, Y, ldy, nullptr, 0, stream);
+    }
+  });
+  return rc2 != BF_OK ? rc2 : rc;
+}
+static int compose_mv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                      const int64_t* seg, int32_t nseg, void* st) {
+  return compose_apply(u, 0, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+static int compose_rmv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
+                       const int64_t* seg, int32_t nseg, void* st) {
+  return compose_apply(u, 1, X, ldx, nc, Y, ldy, seg, nseg, st);
+}
+
+static void check_device() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  BF_CHECK(hipGetDevice(&dev) == hipSuccess, BF_ENOTSUP, "no HIP device");
+  BF_HIP(hipGetDeviceProperties(&prop, dev));
+  BF_CHECK(std::string(prop.gcnArchName).rfind("gfx950", 0) == 0, BF_ENOTSUP,
+           std::string("libbf is built for gfx950, device is ") + prop.gcnArchName);
+}
+
+}  // namespace bf
+
+using namespace bf;
+
+extern "C" {
+
+const char* bf_strerror(int code) {
+  switch (code) {
+    case BF_OK: return "success";
+    case BF_EINVAL: return "invalid argument";
+    case BF_ENOMEM: return "out of memory";
+    case BF_ECALLBACK: return "black-box callback failed";
+    case BF_ERANK: return "rank cap exceeded or block too large";
+    case BF_EHIP: return "HIP runtime error";
+    case BF_ENOTSUP: return "unsupported device";
+    default: return "unknown error";
+  }
+}
+
+const char* bf_last_error(void) { return g_last_error.c_str(); }
+
+int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64_t n, double tol,
+                 int64_t leaf, const bf_opts* opts, void* stream, bf_factors** out) {
+  if (!matvec || !rmatvec || !out || m <= 0 || n <= 0 || !(tol > 0.0 && tol < 1.0) || leaf < 1) {
+    set_last_error("bf_construct: invalid argument");
+    return BF_EINVAL;
+  }
+  bf_factors* F = nullptr;
+  int rc = guarded([&] {
+    check_device();
+    F = construct(matvec, rmatvec, user, m, n, tol, leaf, opts, (hipStream_t)stream);
+  });
+  if (rc == BF_OK) *out = F;
+  return rc;
+}
+
+int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
+             bf_c64* Y, int64_t ldy, void* stream) {
+  if (!F || !X || !Y || ncols < 0 || (trans != 0 && trans != 1)) return BF_EINVAL;
+  const int64_t rin = trans ? F->m : F->n, rout = trans ? F->n : F->m;
+  if (ldx < rin || ldy < rout) return BF_EINVAL;
+  return guarded([&] { apply_factors(F, trans, X, ldx, ncols, Y, ldy, (hipStream_t)stream); });
+}
+
+int bf_stats(const bf_factors* F, bf_info* info) {
+  if (!F || !info) return BF_EINVAL;
+  *info = F->info;
+  return BF_OK;
+}
+
+int bf_ranks(const bf_factors* F, int32_t* kU, int32_t* kV) {
+  if (!F) return BF_EINVAL;
+  if (kU) std::copy(F->kU.begin(), F->kU.end(), kU);
+  if (kV) std::copy(F->kV.begin(), F->kV.end(), kV);
+  return BF_OK;
+}
+
+int bf_export(const bf_factors* F, bf_c128* data, int64_t* count) {
+  if (!F || !count) return BF_EINVAL;
+  auto blocks = canonical_blocks(F);
+  int64_t tot = 0;
+  for (auto& b : blocks) tot += (int64_t)b.rows * b.cols;
+  if (!data) {
+    *count = tot;
+    return BF_OK;
+  }
+  if (*count < tot) return BF_EINVAL;
+  int rc = guarded([&] {
+    hipStream_t s = nullptr;
+    BF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    try {
+      std::vector<PackDesc> d;
+      int64_t off = 0;
+      for (auto& b : blocks) {
+        if ((int64_t)b.rows * b.cols > 0) d.push_back(PackDesc{b.p, off, b.rows, 0, b.rows, b.cols, 0, 0});
+        off += (int64_t)b.rows * b.cols;
+      }
+      {
+        DevBuf<bf_c128> arena((size_t)std::max<int64_t>(tot, 1), s);
+        Staging st;
+        for (size_t o = 0; o < d.size(); o += 60000) {
+          size_t cnt = std::min<size_t>(60000, d.size() - o);
+          std::vector<PackDesc> part(d.begin() + o, d.begin() + o + cnt);
+          auto dd = upload(part, s, st);
+          launch_pack_c128(dd.p, (int32_t)cnt, arena.p, s);
+        }
+        if (tot > 0)
+          BF_HIP(hipMemcpyAsync(data, arena.p, tot * sizeof(bf_c128), hipMemcpyDeviceToHost, s));
+        BF_HIP(hipStreamSynchronize(s));
+      }
+      BF_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+      throw;
+    }
+    BF_HIP(hipStreamDestroy(s));
+  });
+  if (rc == BF_OK) *count = tot;
+  return rc;
+}
+
+int bf_import(int64_t m, int64_t n, int64_t leaf, const int32_t* kU, const int32_t* kV,
+              const bf_c128* data, int64_t count, void* stream, bf_factors** out) {
+  if (m <= 0 || n <= 0 || leaf < 1 || !kU || !kV || !out || (count > 0 && !data)) return BF_EINVAL;
+  bf_factors* F = new (std::nothrow) bf_factors();
+  if (!F) return BF_ENOMEM;
+  int rc = guarded([&] {
+    check_device();
+    hipStream_t s = (hipStream_t)stream;
+    F->m = m;
+    F->n = n;
+    F->leaf = leaf;
+    F->L = num_levels(m, n, leaf);
+    F->lm = F->L / 2;
+    BF_CHECK(F->L <= 24, BF_EINVAL, "too many levels");
+    BF_HIP(hipGetDevice(&F->device));
+    const int L = F->L, lm = F->lm;
+    const size_t nb = size_t(1) << L;
+    F->kU.assign(kU, kU + (size_t)(L - lm + 1) * nb);
+    F->kV.assign(kV, kV + (size_t)(lm + 1) * nb);
+    for (auto k : F->kU) BF_CHECK(k >= 0, BF_EINVAL, "negative rank");
+    for (auto k : F->kV) BF_CHECK(k >= 0, BF_EINVAL, "negative rank");
+    // shapes in canonical order
+    std::vector<std::pair<int32_t, int32_t>> shp;
+    for (size_t i = 0; i < nb; ++i) shp.push_back({(int32_t)node_size(m, L, i), F->ku(L, i, 0)});
+    for (int l = L - 1; l >= lm; --l)
+      for (int64_t i = 0; i < (int64_t(1) << l); ++i)
+        for (int64_t j = 0; j < (int64_t(1) << (L - l)); ++j)
+          shp.push_back({F->ku(l + 1, 2 * i, j >> 1) + F->ku(l + 1, 2 * i + 1, j >> 1), F->ku(l, i, j)});
+    for (int64_t i = 0; i < (int64_t(1) << lm); ++i)
+      for (int64_t j = 0; j < (int64_t(1) << (L - lm)); ++j) shp.push_back({F->ku(lm, i, j), F->kv(lm, i, j)});
+    for (int l = lm; l >= 1; --l)
+      for (int64_t i = 0; i < (int64_t(1) << l); ++i)
+        for (int64_t j = 0; j < (int64_t(1) << (L - l)); ++j)
+          shp.push_back({F->kv(l - 1, i >> 1, 2 * j) + F->kv(l - 1, i >> 1, 2 * j + 1), F->kv(l, i, j)});
+    for (size_t j = 0; j < nb; ++j) shp.push_back({(int32_t)node_size(n, L, j), F->kv(0, 0, j)});
+    int64_t tot = 0;
+    for (auto& p : shp) tot += (int64_t)p.first * p.second;
+    BF_CHECK(tot == count, BF_EINVAL, "data size does not match the ranks");
+    DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s);
+    if (tot > 0) BF_HIP(hipMemcpyAsync(buf.p, data, tot * sizeof(bf_c128), hipMemcpyHostToDevice, s));
+    BF_HIP(hipStreamSynchronize(s));
+    std::vector<Block> blocks;
+    int64_t off = 0;
+    for (auto& p : shp) {
+      blocks.push_back(Block{buf.p + off, p.first, p.second});
+      off += (int64_t)p.first * p.second;
+    }
+    size_t q = 0;
+    F->U.assign(blocks.begin(), blocks.begin() + nb);
+    q = nb;
+    F->R.assign(L - lm, {});
+    for (int l = L - 1; l >= lm; --l) {
+      size_t cnt = nb;
+      F->R[l - lm].assign(blocks.begin() + q, blocks.begin() + q + cnt);
+      q += cnt;
+    }
+    F->B.assign(blocks.begin() + q, blocks.begin() + q + nb);
+    q += nb;
+    F->W.assign(lm + 1, {});
+    for (int l = lm; l >= 1; --l) {
+      F->W[l].assign(blocks.begin() + q, blocks.begin() + q + nb);
+      q += nb;
+    }
+    F->V.assign(blocks.begin() + q, blocks.begin() + q + nb);
+    F->store.push_back(std::move(buf));
+    build_apply_plans(F, s);
+    int32_t kmax = 0;
+    for (auto k : F->kU) kmax = std::max(kmax, k);
+    for (auto k : F->kV) kmax = std::max(kmax, k);
+    F->info.m = m;
+    F->info.n = n;
+    F->info.L = L;
+    F->info.lm = lm;
+    F->info.max_rank = kmax;
+    F->info.factor_entries = tot;
+    F->info.device_bytes = tot * (int64_t)sizeof(bf_c128) +
+                           (int64_t)(F->fwd.G.n + F->adj.G.n) * (int64_t)sizeof(bf_c64);
+  });
+  if (rc != BF_OK) {
+    delete F;
+    return rc;
+  }
+  *out = F;
+  return BF_OK;
+}
+
+int bf_free(bf_factors* F, void* stream) {
+  if (!F) return BF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  for (auto& b : F->store) b.s = s;
+  F->fwd.G.s = s;
+  F->fwd.desc.s = s;
+  F->adj.G.s = s;
+  F->adj.desc.s = s;
+  delete F;
+  return BF_OK;
+}
+
+int bf_gauss(uint64_t seed, uint64_t tag, int64_t row0, int64_t rows, int64_t cols,
+             bf_c128* out, void* stream) {
+  if (rows < 0 || cols < 0 || cols > 65535 || row0 < 0 || (!out && rows * cols > 0)) return BF_EINVAL;
+  return guarded([&] { launch_gauss_f64(out, rows, cols, row0, tag, seed, (hipStream_t)stream); });
+}
+
+int bf_cpqr_batched(int32_t nblk, const int32_t* M, const int32_t* N, const bf_c128* Z,
+                    const int64_t* zoff, double tol, bf_c128* Q, const int64_t* qoff,
+                    int32_t* ranks, void* stream) {
+  if (nblk < 0 || (nblk > 0 && (!M || !N || !Z || !zoff || !Q || !qoff || !ranks)) ||
+      !(tol >= 0.0 && tol < 1.0))
+    return BF_EINVAL;
+  return guarded([&] {
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<QRDesc> d(nblk);
+    int maxM = 0, maxN = 0;
+    for (int b = 0; b < nblk; ++b) {
+      BF_CHECK(M[b] >= 0 && N[b] >= 0, BF_EINVAL, "negative block size");
+      d[b] = QRDesc{Z + zoff[b], Q + qoff[b], std::max(M[b], 1), M[b], N[b]};
+      maxM = std::max(maxM, M[b]);
+      maxN = std::max(maxN, N[b]);
+    }
+    Staging st;
+    auto dd = upload(d, s, st);
+    DevBuf<int32_t> rk((size_t)std::max(nblk, 1), s);
+    launch_cpqr(dd.p, nblk, maxM, maxN, tol, false, rk.p, s);
+    if (nblk > 0)
+      BF_HIP(hipMemcpyAsync(ranks, rk.p, nblk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BF_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int bf_lsq_batched(int32_t nblk, const int32_t* kU, const int32_t* kV, const int32_t* s_,
+                   const bf_c128* C, const int64_t* coff, const bf_c128* X, const int64_t* xoff,
+                   bf_c128* B, const int64_t* boff, void* stream) {
+  if (nblk < 0 || (nblk > 0 && (!kU || !kV || !s_ || !C || !coff || !X || !xoff || !B || !boff)))
+    return BF_EINVAL;
+  return guarded([&] {
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<LSDesc> d;
+    int maxS = 0, maxK = 0;
+    for (int b = 0; b < nblk; ++b) {
+      BF_CHECK(kU[b] >= 0 && kV[b] >= 0 && s_[b] >= kV[b], BF_EINVAL, "bad least-squares block");
+      if (kU[b] == 0 || kV[b] == 0) continue;
+      d.push_back(LSDesc{C + coff[b], X + xoff[b], B + boff[b], kU[b], kV[b], kU[b], kV[b], s_[b], 0});
+      maxS = std::max(maxS, s_[b]);
+      maxK = std::max(maxK, std::max(kU[b], kV[b]));
+    }
+    Staging st;
+    auto dd = upload(d, s, st);
+    launch_lsq(dd.p, (int32_t)d.size(), maxS, maxK, s);
+    BF_HIP(hipStreamSynchronize(s));
+  });
+}
+
+// ---- built-in operators -----------------------------------------------------
+
+int bf_op_segkernel(const double* targets, int64_t m, const double* sources, int64_t n, double k,
+                    bf_operator* out) {
+  if (!targets || !sources || m <= 0 || n <= 0 || !out || !std::isfinite(k)) return BF_EINVAL;
+  return guarded([&] {
+    check_device();
+    auto* c = new SegCtx();
+    try {
+      std::vector<double> tx(m), ty(m), sx(n), sy(n);
+      for (int64_t i = 0; i < m; ++i) { tx[i] = targets[2 * i]; ty[i] = targets[2 * i + 1]; }
+      for (int64_t j = 0; j < n; ++j) { sx[j] = sources[2 * j]; sy[j] = sources[2 * j + 1]; }
+      hipStream_t s = nullptr;
+      c->tx = DevBuf<double>(m, s);
+      c->ty = DevBuf<double>(m, s);
+      c->sx = DevBuf<double>(n, s);
+      c->sy = DevBuf<double>(n, s);
+      BF_HIP(hipMemcpy(c->tx.p, tx.data(), m * 8, hipMemcpyHostToDevice));
+      BF_HIP(hipMemcpy(c->ty.p, ty.data(), m * 8, hipMemcpyHostToDevice));
+      BF_HIP(hipMemcpy(c->sx.p, sx.data(), n * 8, hipMemcpyHostToDevice));
+      BF_HIP(hipMemcpy(c->sy.p, sy.data(), n * 8, hipMemcpyHostToDevice));
+      c->m = m;
+      c->n = n;
+      c->kk = k / (2.0 * M_PI);
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    out->matvec = seg_mv;
+    out->rmatvec = seg_rmv;
+    out->user = new OpHeader{OP_SEG, c};
+    out->m = m;
+    out->n = n;
+  });
+}
+
+int bf_op_fio(int64_t n, bf_operator* out) {
+  if (n <= 0 || (n & 1) || !out) return BF_EINVAL;
+  return guarded([&] {
+    check_device();
+    auto* c = new FioCtx();
+    std::vector<double> cx(n);
+    for (int64_t j = 0; j < n; ++j) cx[j] = (2.0 + std::sin(2.0 * M_PI * (double)j / (double)n)) / 16.0;
+    c->cx = DevBuf<double>(n, nullptr);
+    BF_HIP(hipMemcpy(c->cx.p, cx.data(), n * 8, hipMemcpyHostToDevice));
+    c->n = n;
+    out->matvec = fio_mv;
+    out->rmatvec = fio_rmv;
+    out->user = new OpHeader{OP_FIO, c};
+    out->m = out->n = n;
+  });
+}
+
+int bf_op_dense(const bf_c64* A, int64_t m, int64_t n, int64_t lda, bf_operator* out) {
+  if (!A || m <= 0 || n <= 0 || lda < m || !out) return BF_EINVAL;
+  out->matvec = dense_mv;
+  out->rmatvec = dense_rmv;
+  out->user = new OpHeader{OP_DENSE, new DenseCtx{A, m, n, lda}};
+  out->m = m;
+  out->n = n;
+  return BF_OK;
+}
+
+int bf_op_factors(const bf_factors* F, bf_operator* out) {
+  if (!F || !out) return BF_EINVAL;
+  out->matvec = factors_mv;
+  out->rmatvec = factors_rmv;
+  out->user = new OpHeader{OP_FACTORS, new FactorsCtx{F}};
+  out->m = F->m;
+  out->n = F->n;
+  return BF_OK;
+}
+
+int bf_op_compose(const bf_operator* a1, const bf_operator* a2, bf_operator* out) {
+  if (!a1 || !a2 || !out || a1->n != a2->m) return BF_EINVAL;
+  out->matvec = compose_mv;
+  out->rmatvec = compose_rmv;
+  out->user = new OpHeader{OP_COMPOSE, new ComposeCtx{*a1, *a2}};
+  out->m = a1->m;
+  out->n = a2->n;
+  return BF_OK;
+}
+
+int bf_operator_destroy(bf_operator* op) {
+  if (!op || !op->user) return BF_EINVAL;
+  auto* h = static_cast<OpHeader*>(op->user);
+  switch (h->kind) {
+    case OP_SEG: delete static_cast<SegCtx*>(h->ctx); break;
+    case OP_FIO: delete static_cast<FioCtx*>(h->ctx); break;
+    case OP_DENSE: delete static_cast<DenseCtx*>(h->ctx); break;
+    case OP_FACTORS: delete static_cast<FactorsCtx*>(h->ctx); break;
+    case OP_COMPOSE: delete static_cast<ComposeCtx*>(h->ctx); break;
+    default: return BF_EINVAL;
+  }
+  delete h;
+  op->user = nullptr;
+  return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+// Internal declarations shared by the HIP sources of libbf (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/bf.h"
+
+namespace bf {
+
+// ---------------------------------------------------------------- errors --
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& msg) : std::runtime_error(msg), code(c) {}
+};
+
+#define BF_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::bf::Error(e_ == hipErrorOutOfMemory ? BF_ENOMEM : BF_EHIP,          \
+                        std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+#define BF_CHECK(cond, code, msg)                    \
+  do {                                               \
+    if (!(cond)) throw ::bf::Error((code), (msg));   \
+  } while (0)
+
+void set_last_error(const std::string& msg);
+
+// Host-side bounds validation of device accesses (enabled by the environment
+// variable BF_VALIDATE=1): the library records its own live allocations and
+// checks every descriptor's extent against them before a launch, so an
+// indexing error surfaces as BF_EINVAL instead of a GPU memory fault.
+bool validating();
+void check_extent(const void* p, size_t bytes, const char* what);
+
+// ------------------------------------------------------- device buffers --
+// Stream-ordered device memory (hipMallocAsync from the device's default pool,
+// whose release threshold is raised at first use so freed memory is reused).
+
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  DevBuf() = default;
+  DevBuf(size_t count, hipStream_t st) : n(count), s(st) {
+    p = count ? static_cast<T*>(dev_alloc(count * sizeof(T), st)) : nullptr;
+  }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p) dev_free(p, s);
+    p = nullptr;
+    n = 0;
+  }
+  T* release() { T* q = p; p = nullptr; n = 0; return q; }
+};
+
+// Pinned host staging for descriptor uploads: a bump allocator whose space is
+// recycled only after the owning stream has been synchronized (reset()), so
+// in-flight host-to-device copies never see their source overwritten.
+struct Staging {
+  char* h = nullptr;
+  size_t cap = 0, off = 0;
+  ~Staging();
+  void* alloc(size_t bytes, hipStream_t s);   // may synchronize s to grow
+  void reset() { off = 0; }                    // caller has synchronized the stream
+};
+
+template <typename T>
+DevBuf<T> upload(const std::vector<T>& v, hipStream_t s, Staging& st) {
+  DevBuf<T> d(v.size(), s);
+  if (!v.empty()) {
+    void* h = st.alloc(v.size() * sizeof(T), s);
+    std::memcpy(h, v.data(), v.size() * sizeof(T));
+    BF_HIP(hipMemcpyAsync(d.p, h, v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  return d;
+}
+
+// ---------------------------------------------------------------- kernels --
+
+// Philox4x64-10 complex Gaussians for structured samples (Alg. 2, random
+// matrix lines; Sec. 4.1).  Fills X (rows x ncols, ld = rows) in complex64:
+// row r belongs to node g = the level-`level` node of a bisection tree over
+// `rows` points; entry (r, c) = gauss(seed, tags[g], r, c) if c < widths[g],
+// else 0.
+void launch_gauss_samples(bf_c64* X, int64_t rows, int64_t ncols, int32_t level,
+                          const uint64_t* tags_dev, const int32_t* widths_dev,
+                          uint64_t seed, hipStream_t s);
+
+// FP64 variant used by the self-test of the generator.
+void launch_gauss_f64(bf_c128* X, int64_t rows, int64_t ncols, int64_t row0, uint64_t tag,
+                      uint64_t seed, hipStream_t s);
+
+// Batched small complex GEMM with up to two terms:
+//   out[r, c] = sum_t sum_k op_t(F_t)[r, k] * in_t[k, c],   r < M, c < ncols,
+// op = 0: F is M x K column-major (ld f_ld); op = 1: F^H with F K x M.
+struct GemmTerm {
+  const bf_c128* F;
+  const void* in;    // bf_c64* or bf_c128* (kernel template parameter)
+  int64_t in_ld;
+  int32_t f_ld;
+  int32_t K;
+  int32_t op;
+  int32_t pad;
+};
+struct GemmDesc {
+  bf_c128* out;
+  int64_t out_ld;
+  int32_t M;
+  int32_t ncols;
+  int32_t nterm;
+  int32_t pad;
+  GemmTerm t[2];
+};
+// in_c64: the inputs are complex64 (samples straight from the black box).
+void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, bool in_c64,
+                       hipStream_t s);
+
+// Batched truncated column-pivoted QR (Alg. 1 step 3) on FP64.
+struct QRDesc {
+  const void* in;    // bf_c64* or bf_c128*
+  bf_c128* q;        // M x min(M,N) capacity, ld = M; first k columns written
+  int64_t in_ld;
+  int32_t M;
+  int32_t N;
+};
+void launch_cpqr(const QRDesc* d_dev, int32_t nblk, int32_t maxM, int32_t maxN, double tol,
+                 bool in_c64, int32_t* ranks_dev, hipStream_t s);
+
+// Batched centre blocks: B = C X^+ (least squares, eq. Bij read from its argmin).
+struct LSDesc {
+  const bf_c128* C;  // kU x s, ld = ldc
+  const bf_c128* X;  // kV x s, ld = ldx
+  bf_c128* B;        // kU x kV, ld = kU
+  int64_t ldc, ldx;
+  int32_t kU, kV, s, pad;
+};
+void launch_lsq(const LSDesc* d_dev, int32_t nblk, int32_t maxS, int32_t maxK, hipStream_t s);
+
+// complex128 -> complex64 copy (contiguous)
+void launch_c128_to_c64(const bf_c128* in, bf_c64* out, int64_t n, hipStream_t s);
+
+// Apply stage (complex64 factors, FP32 accumulation).  Buffer ids select
+// among up to 3 base pointers given at launch (0: user input, 1/2: ping-pong
+// intermediates, 3: user output); row offsets are fixed at finalize.
+struct ApplyTerm {
+  int64_t g_off;     // element offset of this term's block G (M x K, row-major)
+  int64_t in_row;    // first row of the input block in its buffer
+  int32_t K;
+  int32_t in_buf;
+};
+struct ApplyDesc {
+  int64_t out_row;
+  int32_t M;
+  int32_t nterm;
+  int32_t out_buf;
+  int32_t pad;
+  ApplyTerm t[2];
+};
+void launch_apply_stage(const ApplyDesc* d_dev, int32_t ndesc, const bf_c64* G,
+                        const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
+                        int32_t maxM, hipStream_t s);
+
+// Gather (and optionally conjugate-transpose) factor sub-blocks into a
+// contiguous column-major arena: dst[dst_off + r + k*M] =
+//   conjT ? conj(src[(row0 + k) + r*src_ld]) : src[(row0 + r) + k*src_ld].
+struct PackDesc {
+  const bf_c128* src;
+  int64_t dst_off;
+  int32_t src_ld;
+  int32_t row0;
+  int32_t M;
+  int32_t K;
+  int32_t conjT;
+  int32_t pad;
+};
+void launch_pack_c64(const PackDesc* d_dev, int32_t ndesc, bf_c64* dst, hipStream_t s);
+void launch_pack_c128(const PackDesc* d_dev, int32_t ndesc, bf_c128* dst, hipStream_t s);
+
+// Segment-stacked expansion: out[:, g*ncols + c] = X restricted to rows seg_g,
+// zero elsewhere (rows x nseg*ncols, ld = ldo).
+void launch_expand_segments(const bf_c64* X, int64_t ldx, int64_t rows, int64_t ncols,
+                            const int64_t* seg_dev, int32_t nseg, bf_c64* out, int64_t ldo,
+                            hipStream_t s);
+
+// ------------------------------------------------- matrix-free operators --
+struct PointSet {     // structure-of-arrays FP64 coordinates on the device
+  const double* x;
+  const double* y;
+};
+// Y[:, g*ncols + c] = sum_{j in seg_g} E(i, j) X[j, c], E = kernel entries of
+// op(A) (sign = +1: A, sign = -1: A^H, points swapped by the caller).
+void launch_segkernel(PointSet out_pts, int64_t nout, PointSet in_pts, int64_t nin,
+                      double k_over_2pi, int sign, const bf_c64* X, int64_t ldx, int64_t ncols,
+                      bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
+                      hipStream_t s);
+void launch_fio(int64_t n, const double* cx_dev, int adjoint, const bf_c64* X, int64_t ldx,
+                int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
+                hipStream_t s);
+void launch_dense(const bf_c64* A, int64_t m, int64_t n, int64_t lda, int adjoint,
+                  const bf_c64* X, int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
+                  const int64_t* seg_host, int32_t nseg, hipStream_t s);
+
+}  // namespace bf

@@ -1,0 +1,695 @@
+// Host driver of Alg. 2 (adaptive randomized hybrid butterfly construction).
+//
+// Per adaptive iteration / per level the driver
+//   1. draws the structured random block of every sample of the level in one
+//      launch (segment-stacked: the samples' supports partition the rows),
+//   2. hands it to the black box once (one callback for the whole level),
+//   3. applies the already-built factors to all samples (batched GEMMs of the
+//      partial chains: V-chain^H, U-chain^H, X-chain),
+//   4. runs the truncated pivoted QR of every block of the level in one
+//      batched launch (FP64) and reads the ranks back (the one host sync of
+//      the level: the next level's widths depend on them).
+// The W sweep (row side) and the R sweep (column side) follow the paper's
+// order; B is computed with the last R level (l = l_m).
+//
+// Readings of the paper taken here (the CPU oracle takes the same ones):
+// conjugate transposes for complex data; Alg. 1's tolerance is the relative
+// Frobenius tail of each sample; the adaptive loops draw a fresh random block
+// per pass, stop without doubling once r > max rank, and restart from r0 for
+// the U loop; the R sweep's tau ranges over T-level l; eq. (Bij) is read from
+// its argmin, B = (R^H Z) X^+; at l = l_m the sample width also covers the
+// V-side ranks; every sample has its own width.
+#include <algorithm>
+#include <cmath>
+
+#include "factors.h"
+
+namespace bf {
+
+namespace {
+
+constexpr uint64_t PHASE_V0 = 1, PHASE_U0 = 2, PHASE_W = 3, PHASE_R = 4;
+inline uint64_t make_tag(uint64_t phase, uint64_t level, uint64_t node) {
+  return (phase << 56) | (level << 40) | node;
+}
+
+// A stack of blocks of one sample ("tall matrix"): block b occupies rows
+// [roff[b], roff[b] + k_b) of a column-major matrix with leading dimension ld;
+// `base` already points at the sample's first column.
+template <typename T>
+struct Tall {
+  const T* base = nullptr;
+  int64_t ld = 0;
+  std::vector<int64_t> roff;
+};
+
+class Builder {
+ public:
+  Builder(bf_op_fn mv, bf_op_fn rmv, void* user, int64_t m, int64_t n, double tol, int64_t leaf,
+          const bf_opts* o, hipStream_t s)
+      : mv_(mv), rmv_(rmv), user_(user), tol_(tol), s_(s) {
+    F_ = new bf_factors();
+    F_->m = m;
+    F_->n = n;
+    F_->leaf = leaf;
+    if (o) {
+      p_ = o->p;
+      r0_ = o->r0;
+      cap_ = o->max_rank;
+      seed_ = o->seed;
+    }
+    BF_CHECK(p_ >= 0 && r0_ >= 1 && cap_ >= 0, BF_EINVAL, "bad bf_opts");
+    F_->L = num_levels(m, n, leaf);
+    F_->lm = F_->L / 2;
+    BF_CHECK(F_->L <= 24, BF_EINVAL, "too many levels");
+    BF_HIP(hipGetDevice(&F_->device));
+    const size_t nb = size_t(1) << F_->L;
+    F_->kU.assign((size_t)(F_->L - F_->lm + 1) * nb, 0);
+    F_->kV.assign((size_t)(F_->lm + 1) * nb, 0);
+    F_->R.resize(F_->L - F_->lm);
+    F_->W.resize(F_->lm + 1);
+  }
+  ~Builder() { delete F_; }
+
+  bf_factors* run() {
+    leaf_loop(false);
+    leaf_loop(true);
+    for (int l = 1; l <= F_->lm; ++l) w_level(l);
+    for (int l = F_->L - 1; l >= F_->lm; --l) r_level(l);
+    if (F_->L == 0) centre_single_block();
+    finalize();
+    bf_factors* out = F_;
+    F_ = nullptr;
+    return out;
+  }
+
+ private:
+  bf_op_fn mv_, rmv_;
+  void* user_;
+  double tol_;
+  hipStream_t s_;
+  int p_ = 2, r0_ = 4, cap_ = 0;
+  uint64_t seed_ = 0;
+  bf_factors* F_;
+  Staging st_;
+  int64_t mv_cols_ = 0, rmv_cols_ = 0;
+  int v_iters_ = 0, u_iters_ = 0;
+
+  int L() const { return F_->L; }
+  int lm() const { return F_->lm; }
+  int64_t nb() const { return int64_t(1) << F_->L; }
+
+  void check_cap(int64_t r) {
+    if (cap_ > 0 && r > cap_)
+      throw Error(BF_ERANK, "rank estimate " + std::to_string(r) + " exceeds max_rank " +
+                                std::to_string(cap_));
+  }
+
+  void call_op(bool adjoint, const bf_c64* X, int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
+               const std::vector<int64_t>* seg) {
+    bf_op_fn fn = adjoint ? rmv_ : mv_;
+    int rc = fn(user_, X, ldx, ncols, Y, ldy, seg ? seg->data() : nullptr,
+                seg ? (int32_t)(seg->size() - 1) : 0, (void*)s_);
+    if (rc != 0)
+      throw Error(BF_ECALLBACK, std::string(adjoint ? "rmatvec" : "matvec") +
+                                    " callback returned " + std::to_string(rc));
+  }
+
+  DevBuf<bf_c64> gauss(int64_t rows, int64_t ncols, int level, const std::vector<uint64_t>& tags,
+                       const std::vector<int32_t>& widths) {
+    DevBuf<bf_c64> X((size_t)rows * ncols, s_);
+    if (validating()) {
+      BF_CHECK(tags.size() == (size_t(1) << level) && widths.size() == tags.size(), BF_EINVAL,
+               "bounds check failed: sample tags");
+      for (auto w : widths) BF_CHECK(w <= ncols, BF_EINVAL, "bounds check failed: sample width");
+    }
+    auto dt = upload(tags, s_, st_);
+    auto dw = upload(widths, s_, st_);
+    launch_gauss_samples(X.p, rows, ncols, level, dt.p, dw.p, seed_, s_);
+    return X;
+  }
+
+  void gemm(const std::vector<GemmDesc>& d, bool in_c64) {
+    if (d.empty()) return;
+    int maxc = 0;
+    for (auto& x : d) maxc = std::max(maxc, x.ncols);
+    if (validating()) {
+      const size_t isz = in_c64 ? sizeof(bf_c64) : sizeof(bf_c128);
+      for (auto& x : d) {
+        if (x.M <= 0 || x.ncols <= 0) continue;
+        check_extent(x.out, ((size_t)(x.ncols - 1) * x.out_ld + x.M) * sizeof(bf_c128), "gemm out");
+        for (int t = 0; t < x.nterm; ++t) {
+          const GemmTerm& T = x.t[t];
+          if (T.K <= 0) continue;
+          size_t fe = T.op == 0 ? (size_t)(T.K - 1) * T.f_ld + x.M : (size_t)(x.M - 1) * T.f_ld + T.K;
+          check_extent(T.F, fe * sizeof(bf_c128), "gemm factor");
+          check_extent(T.in, ((size_t)(x.ncols - 1) * T.in_ld + T.K) * isz, "gemm input");
+        }
+      }
+    }
+    auto dd = upload(d, s_, st_);
+    launch_chain_gemm(dd.p, (int32_t)d.size(), maxc, in_c64, s_);
+  }
+
+  // Batched Alg. 1 step 3; Q blocks go to a fresh capacity buffer that becomes
+  // the factor storage of the level.  Returns ranks (host) and fills `out`.
+  std::vector<int32_t> cpqr(const std::vector<QRDesc>& in, bool in_c64, std::vector<Block>& out) {
+    const size_t nblk = in.size();
+    std::vector<int64_t> off(nblk);
+    int64_t tot = 0;
+    int maxM = 0, maxN = 0;
+    for (size_t b = 0; b < nblk; ++b) {
+      off[b] = tot;
+      tot += (int64_t)in[b].M * std::min(in[b].M, in[b].N);
+      maxM = std::max(maxM, in[b].M);
+      maxN = std::max(maxN, in[b].N);
+    }
+    DevBuf<bf_c128> store((size_t)std::max<int64_t>(tot, 1), s_);
+    std::vector<QRDesc> d = in;
+    for (size_t b = 0; b < nblk; ++b) d[b].q = store.p + off[b];
+    if (validating())
+      for (auto& x : d) {
+        if (x.M <= 0 || x.N <= 0) continue;
+        check_extent(x.in, ((size_t)(x.N - 1) * x.in_ld + x.M) * (in_c64 ? sizeof(bf_c64) : sizeof(bf_c128)),
+                     "cpqr input");
+        check_extent(x.q, (size_t)x.M * std::min(x.M, x.N) * sizeof(bf_c128), "cpqr output");
+      }
+    auto dd = upload(d, s_, st_);
+    DevBuf<int32_t> rk(nblk, s_);
+    launch_cpqr(dd.p, (int32_t)nblk, maxM, maxN, tol_, in_c64, rk.p, s_);
+    std::vector<int32_t> ranks(nblk);
+    int32_t* hr = static_cast<int32_t*>(st_.alloc(nblk * sizeof(int32_t), s_));
+    BF_HIP(hipMemcpyAsync(hr, rk.p, nblk * sizeof(int32_t), hipMemcpyDeviceToHost, s_));
+    BF_HIP(hipStreamSynchronize(s_));
+    std::memcpy(ranks.data(), hr, nblk * sizeof(int32_t));
+    st_.reset();
+    out.resize(nblk);
+    for (size_t b = 0; b < nblk; ++b) out[b] = Block{store.p + off[b], in[b].M, ranks[b]};
+    F_->store.push_back(std::move(store));
+    return ranks;
+  }
+
+  // ---- adaptive leaf loops (first two loops of Alg. 2) ---------------------
+  void leaf_loop(bool col_side) {
+    const int64_t rows_in = col_side ? F_->n : F_->m;   // rows of the random block
+    const int64_t rows_out = col_side ? F_->m : F_->n;  // rows of the sample
+    int64_t r = r0_;
+    for (int it = 0;; ++it) {
+      check_cap(r);
+      const int64_t s = r + p_;
+      BF_CHECK(s <= 65535, BF_ERANK, "sample width too large");
+      auto G = gauss(rows_in, s, 0, {make_tag(col_side ? PHASE_U0 : PHASE_V0, it, 0)},
+                     {(int32_t)s});
+      DevBuf<bf_c64> Y((size_t)rows_out * s, s_);
+      call_op(!col_side, G.p, rows_in, s, Y.p, rows_out, nullptr);
+      (col_side ? mv_cols_ : rmv_cols_) += s;
+      std::vector<QRDesc> d(nb());
+      for (int64_t b = 0; b < nb(); ++b) {
+        const int64_t lo = node_lo(rows_out, L(), b);
+        d[b] = QRDesc{Y.p + lo, nullptr, rows_out, (int32_t)node_size(rows_out, L(), b),
+                      (int32_t)s};
+      }
+      // the previous iteration's store is superseded
+      size_t nstore = F_->store.size();
+      std::vector<Block> blocks;
+      auto ranks = cpqr(d, true, blocks);
+      int32_t kmax = *std::max_element(ranks.begin(), ranks.end());
+      (col_side ? u_iters_ : v_iters_)++;
+      if (col_side) {
+        F_->U = blocks;
+        for (int64_t i = 0; i < nb(); ++i) F_->ku_ref(L(), i, 0) = ranks[i];
+      } else {
+        F_->V = blocks;
+        for (int64_t j = 0; j < nb(); ++j) F_->kv_ref(0, 0, j) = ranks[j];
+      }
+      if (it > 0) {
+        // drop the superseded store of the previous pass
+        F_->store.erase(F_->store.begin() + (nstore - 1));
+      }
+      if (r > kmax) break;
+      r *= 2;
+    }
+  }
+
+  // ---- W sweep, level l (Sec. 4.3) ------------------------------------------
+  void w_level(int l) {
+    const int64_t m = F_->m, n = F_->n;
+    const int64_t nT = int64_t(1) << l, nS = int64_t(1) << (L() - l);
+    std::vector<int32_t> width(nT);
+    std::vector<uint64_t> tags(nT);
+    int32_t smax = 0;
+    for (int64_t i = 0; i < nT; ++i) {
+      int32_t w = 0;
+      for (int64_t j = 0; j < nS; ++j)
+        w = std::max(w, F_->kv(l - 1, i >> 1, 2 * j) + F_->kv(l - 1, i >> 1, 2 * j + 1));
+      width[i] = w + p_;
+      check_cap(w);
+      tags[i] = make_tag(PHASE_W, l, i);
+      smax = std::max(smax, width[i]);
+    }
+    auto G = gauss(m, smax, l, tags, width);
+    std::vector<int64_t> seg(nT + 1);
+    for (int64_t i = 0; i <= nT; ++i) seg[i] = node_lo(m, l, i);
+    const int64_t ycols = nT * smax;
+    DevBuf<bf_c64> Yp((size_t)n * ycols, s_);
+    call_op(true, G.p, m, smax, Yp.p, n, &seg);
+    for (auto w : width) rmv_cols_ += w;
+    G.reset();
+
+    // V stage (shared by all samples): P0 = V^H Y', rows ordered by leaf j
+    Tall<bf_c128> P0;
+    int64_t rows0 = 0;
+    P0.roff.resize(nb());
+    for (int64_t j = 0; j < nb(); ++j) { P0.roff[j] = rows0; rows0 += F_->kv(0, 0, j); }
+    DevBuf<bf_c128> P0buf((size_t)std::max<int64_t>(rows0, 1) * ycols, s_);
+    {
+      std::vector<GemmDesc> d;
+      for (int64_t j = 0; j < nb(); ++j) {
+        const Block& V = F_->V[j];
+        GemmDesc g{};
+        g.out = P0buf.p + P0.roff[j];
+        g.out_ld = rows0;
+        g.M = V.cols;
+        g.ncols = (int32_t)ycols;
+        g.nterm = 1;
+        g.t[0] = GemmTerm{V.p, Yp.p + node_lo(n, L(), j), n, V.rows, V.rows, 1, 0};
+        if (g.M > 0) d.push_back(g);
+      }
+      gemm(d, true);
+    }
+    // per-sample views of level l' (starting from the shared level 0)
+    std::vector<Tall<bf_c128>> view(nT);
+    for (int64_t i = 0; i < nT; ++i) {
+      view[i].base = P0buf.p + (int64_t)i * smax * rows0;
+      view[i].ld = rows0;
+      view[i].roff = P0.roff;
+    }
+    std::vector<DevBuf<bf_c128>> keep;
+    for (int lp = 1; lp < l; ++lp) {
+      const int64_t nSl = int64_t(1) << (L() - lp);
+      std::vector<int64_t> base(nT);
+      std::vector<Tall<bf_c128>> next(nT);
+      int64_t tot = 0;
+      for (int64_t i = 0; i < nT; ++i) {
+        const int64_t ip = i >> (l - lp);
+        int64_t rows = 0;
+        next[i].roff.resize(nSl);
+        for (int64_t j = 0; j < nSl; ++j) { next[i].roff[j] = rows; rows += F_->kv(lp, ip, j); }
+        next[i].ld = std::max<int64_t>(rows, 1);
+        base[i] = tot;
+        tot += next[i].ld * width[i];
+      }
+      DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
+      std::vector<GemmDesc> d;
+      for (int64_t i = 0; i < nT; ++i) {
+        const int64_t ip = i >> (l - lp);
+        next[i].base = buf.p + base[i];
+        for (int64_t j = 0; j < nSl; ++j) {
+          const Block& Wb = F_->W[lp][(size_t)((ip << (L() - lp)) + j)];
+          const int32_t ka = F_->kv(lp - 1, ip >> 1, 2 * j);
+          const int32_t kb = F_->kv(lp - 1, ip >> 1, 2 * j + 1);
+          GemmDesc g{};
+          g.out = const_cast<bf_c128*>(next[i].base) + next[i].roff[j];
+          g.out_ld = next[i].ld;
+          g.M = Wb.cols;
+          g.ncols = width[i];
+          g.nterm = 2;
+          g.t[0] = GemmTerm{Wb.p, view[i].base + view[i].roff[2 * j], view[i].ld, Wb.rows, ka, 1, 0};
+          g.t[1] = GemmTerm{Wb.p + ka, view[i].base + view[i].roff[2 * j + 1], view[i].ld, Wb.rows,
+                            kb, 1, 0};
+          if (g.M > 0) d.push_back(g);
+        }
+      }
+      gemm(d, false);
+      keep.push_back(std::move(buf));
+      view.swap(next);
+    }
+    // Z_{l,i,j} = [P_{2j}; P_{2j+1}] of sample i  ->  W_{l,i,j}
+    std::vector<QRDesc> q((size_t)nb());
+    for (int64_t i = 0; i < nT; ++i)
+      for (int64_t j = 0; j < nS; ++j) {
+        const int32_t M = F_->kv(l - 1, i >> 1, 2 * j) + F_->kv(l - 1, i >> 1, 2 * j + 1);
+        q[(size_t)((i << (L() - l)) + j)] =
+            QRDesc{view[i].base + view[i].roff[2 * j], nullptr, view[i].ld, M, width[i]};
+      }
+    std::vector<Block> blocks;
+    auto ranks = cpqr(q, false, blocks);
+    F_->W[l] = blocks;
+    for (int64_t i = 0; i < nT; ++i)
+      for (int64_t j = 0; j < nS; ++j) F_->kv_ref(l, i, j) = ranks[(size_t)((i << (L() - l)) + j)];
+  }
+
+  // ---- R sweep, level l (Sec. 4.2) and B at l_m (Sec. 4.4) -----------------
+  void r_level(int l) {
+    const int64_t m = F_->m, n = F_->n;
+    const int64_t nT = int64_t(1) << l, nS = int64_t(1) << (L() - l);
+    std::vector<int32_t> width(nS);
+    std::vector<uint64_t> tags(nS);
+    int32_t smax = 0;
+    for (int64_t j = 0; j < nS; ++j) {
+      int32_t w = 0;
+      for (int64_t i = 0; i < nT; ++i)
+        w = std::max(w, F_->ku(l + 1, 2 * i, j >> 1) + F_->ku(l + 1, 2 * i + 1, j >> 1));
+      if (l == lm())
+        for (int64_t i = 0; i < nT; ++i) w = std::max(w, F_->kv(lm(), i, j));
+      check_cap(w);
+      width[j] = w + p_;
+      tags[j] = make_tag(PHASE_R, l, j);
+      smax = std::max(smax, width[j]);
+    }
+    auto Om = gauss(n, smax, L() - l, tags, width);
+    std::vector<int64_t> seg(nS + 1);
+    for (int64_t j = 0; j <= nS; ++j) seg[j] = node_lo(n, L() - l, j);
+    const int64_t ycols = nS * smax;
+    DevBuf<bf_c64> Y((size_t)m * ycols, s_);
+    call_op(false, Om.p, n, smax, Y.p, m, &seg);
+    for (auto w : width) mv_cols_ += w;
+
+    // U^H stage (shared): PL rows ordered by leaf i
+    int64_t rowsL = 0;
+    std::vector<int64_t> roffL(nb());
+    for (int64_t i = 0; i < nb(); ++i) { roffL[i] = rowsL; rowsL += F_->ku(L(), i, 0); }
+    DevBuf<bf_c128> PL((size_t)std::max<int64_t>(rowsL, 1) * ycols, s_);
+    {
+      std::vector<GemmDesc> d;
+      for (int64_t i = 0; i < nb(); ++i) {
+        const Block& U = F_->U[i];
+        GemmDesc g{};
+        g.out = PL.p + roffL[i];
+        g.out_ld = rowsL;
+        g.M = U.cols;
+        g.ncols = (int32_t)ycols;
+        g.nterm = 1;
+        g.t[0] = GemmTerm{U.p, Y.p + node_lo(m, L(), i), m, U.rows, U.rows, 1, 0};
+        if (g.M > 0) d.push_back(g);
+      }
+      gemm(d, true);
+    }
+    std::vector<Tall<bf_c128>> view(nS);
+    for (int64_t j = 0; j < nS; ++j) {
+      view[j].base = PL.p + (int64_t)j * smax * rowsL;
+      view[j].ld = rowsL;
+      view[j].roff = roffL;
+    }
+    std::vector<DevBuf<bf_c128>> keep;
+    for (int lp = L() - 1; lp > l; --lp) {
+      const int64_t nTl = int64_t(1) << lp;
+      std::vector<int64_t> base(nS);
+      std::vector<Tall<bf_c128>> next(nS);
+      int64_t tot = 0;
+      for (int64_t j = 0; j < nS; ++j) {
+        const int64_t jp = j >> (lp - l);
+        int64_t rows = 0;
+        next[j].roff.resize(nTl);
+        for (int64_t i = 0; i < nTl; ++i) { next[j].roff[i] = rows; rows += F_->ku(lp, i, jp); }
+        next[j].ld = std::max<int64_t>(rows, 1);
+        base[j] = tot;
+        tot += next[j].ld * width[j];
+      }
+      DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
+      std::vector<GemmDesc> d;
+      for (int64_t j = 0; j < nS; ++j) {
+        const int64_t jp = j >> (lp - l);
+        next[j].base = buf.p + base[j];
+        for (int64_t i = 0; i < nTl; ++i) {
+          const Block& Rb = F_->R[lp - lm()][(size_t)((i << (L() - lp)) + jp)];
+          const int32_t k1 = F_->ku(lp + 1, 2 * i, jp >> 1);
+          const int32_t k2 = F_->ku(lp + 1, 2 * i + 1, jp >> 1);
+          GemmDesc g{};
+          g.out = const_cast<bf_c128*>(next[j].base) + next[j].roff[i];
+          g.out_ld = next[j].ld;
+          g.M = Rb.cols;
+          g.ncols = width[j];
+          g.nterm = 2;
+          g.t[0] = GemmTerm{Rb.p, view[j].base + view[j].roff[2 * i], view[j].ld, Rb.rows, k1, 1, 0};
+          g.t[1] = GemmTerm{Rb.p + k1, view[j].base + view[j].roff[2 * i + 1], view[j].ld, Rb.rows,
+                            k2, 1, 0};
+          if (g.M > 0) d.push_back(g);
+        }
+      }
+      gemm(d, false);
+      keep.push_back(std::move(buf));
+      view.swap(next);
+    }
+    // Z_{l,i,j} = [P_{2i}; P_{2i+1}] of sample j  ->  R_{l,i,j}
+    std::vector<QRDesc> q((size_t)nb());
+    for (int64_t i = 0; i < nT; ++i)
+      for (int64_t j = 0; j < nS; ++j) {
+        const int32_t M = F_->ku(l + 1, 2 * i, j >> 1) + F_->ku(l + 1, 2 * i + 1, j >> 1);
+        q[(size_t)((i << (L() - l)) + j)] =
+            QRDesc{view[j].base + view[j].roff[2 * i], nullptr, view[j].ld, M, width[j]};
+      }
+    std::vector<Block> blocks;
+    auto ranks = cpqr(q, false, blocks);
+    F_->R[l - lm()] = blocks;
+    for (int64_t i = 0; i < nT; ++i)
+      for (int64_t j = 0; j < nS; ++j) F_->ku_ref(l, i, j) = ranks[(size_t)((i << (L() - l)) + j)];
+    if (l == lm()) centre_blocks(Om, width, smax, q);
+  }
+
+  // X_{lm,i,j} = V_{tau,nu}^H Omega_nu by the nested row bases (V^0 on the
+  // leaves under nu, then W^1..W^{lm} restricted to nu's subtree), then
+  // C = R^H Z and B = C X^+ for every block of level l_m.
+  void centre_blocks(const DevBuf<bf_c64>& Om, const std::vector<int32_t>& width, int32_t smax,
+                     const std::vector<QRDesc>& zq) {
+    (void)smax;
+    const int64_t n = F_->n;
+    const int lmv = lm();
+    const int64_t nS = int64_t(1) << (L() - lmv), nT = int64_t(1) << lmv;
+    // level 0 (leaves under nu): per-sample tall, blocks j' local in [0, 2^lm)
+    const int64_t nl0 = int64_t(1) << lmv;
+    std::vector<Tall<bf_c128>> view(nS);
+    std::vector<int64_t> base(nS);
+    int64_t tot = 0;
+    for (int64_t j = 0; j < nS; ++j) {
+      int64_t rows = 0;
+      view[j].roff.resize(nl0);
+      for (int64_t t = 0; t < nl0; ++t) {
+        view[j].roff[t] = rows;
+        rows += F_->kv(0, 0, (j << lmv) + t);
+      }
+      view[j].ld = std::max<int64_t>(rows, 1);
+      base[j] = tot;
+      tot += view[j].ld * width[j];
+    }
+    DevBuf<bf_c128> buf0((size_t)std::max<int64_t>(tot, 1), s_);
+    {
+      std::vector<GemmDesc> d;
+      for (int64_t j = 0; j < nS; ++j) {
+        view[j].base = buf0.p + base[j];
+        for (int64_t t = 0; t < nl0; ++t) {
+          const int64_t jl = (j << lmv) + t;
+          const Block& V = F_->V[jl];
+          GemmDesc g{};
+          g.out = const_cast<bf_c128*>(view[j].base) + view[j].roff[t];
+          g.out_ld = view[j].ld;
+          g.M = V.cols;
+          g.ncols = width[j];
+          g.nterm = 1;
+          g.t[0] = GemmTerm{V.p, Om.p + node_lo(n, L(), jl), n, V.rows, V.rows, 1, 0};
+          if (g.M > 0) d.push_back(g);
+        }
+      }
+      gemm(d, true);
+    }
+    std::vector<DevBuf<bf_c128>> keep;
+    keep.push_back(std::move(buf0));
+    for (int lp = 1; lp <= lmv; ++lp) {
+      const int64_t nTl = int64_t(1) << lp;
+      const int64_t nSub = int64_t(1) << (lmv - lp);       // S-nodes of nu's subtree at S-level L-lp
+      const int64_t nSubPrev = int64_t(1) << (lmv - lp + 1);
+      std::vector<Tall<bf_c128>> next(nS);
+      tot = 0;
+      for (int64_t j = 0; j < nS; ++j) {
+        int64_t rows = 0;
+        next[j].roff.resize(nTl * nSub);
+        for (int64_t i = 0; i < nTl; ++i)
+          for (int64_t t = 0; t < nSub; ++t) {
+            next[j].roff[i * nSub + t] = rows;
+            rows += F_->kv(lp, i, (j << (lmv - lp)) + t);
+          }
+        next[j].ld = std::max<int64_t>(rows, 1);
+        base[j] = tot;
+        tot += next[j].ld * width[j];
+      }
+      DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
+      std::vector<GemmDesc> d;
+      for (int64_t j = 0; j < nS; ++j) {
+        next[j].base = buf.p + base[j];
+        for (int64_t i = 0; i < nTl; ++i)
+          for (int64_t t = 0; t < nSub; ++t) {
+            const int64_t jj = (j << (lmv - lp)) + t;   // global S-node at S-level L-lp
+            const Block& Wb = F_->W[lp][(size_t)((i << (L() - lp)) + jj)];
+            const int32_t ka = F_->kv(lp - 1, i >> 1, 2 * jj);
+            const int32_t kb = F_->kv(lp - 1, i >> 1, 2 * jj + 1);
+            // previous level's local indices: (i >> 1, 2t) and (i >> 1, 2t + 1)
+            const int64_t pa = (lp == 1) ? 2 * t : (i >> 1) * nSubPrev + 2 * t;
+            GemmDesc g{};
+            g.out = const_cast<bf_c128*>(next[j].base) + next[j].roff[i * nSub + t];
+            g.out_ld = next[j].ld;
+            g.M = Wb.cols;
+            g.ncols = width[j];
+            g.nterm = 2;
+            g.t[0] = GemmTerm{Wb.p, view[j].base + view[j].roff[pa], view[j].ld, Wb.rows, ka, 1, 0};
+            g.t[1] = GemmTerm{Wb.p + ka, view[j].base + view[j].roff[pa + 1], view[j].ld, Wb.rows, kb,
+                              1, 0};
+            if (g.M > 0) d.push_back(g);
+          }
+      }
+      gemm(d, false);
+      keep.push_back(std::move(buf));
+      view.swap(next);
+    }
+    // C = R^H Z (kU x s) for every block (i, j)
+    std::vector<int64_t> coff((size_t)nb());
+    tot = 0;
+    for (int64_t i = 0; i < nT; ++i)
+      for (int64_t j = 0; j < nS; ++j) {
+        coff[(size_t)((i << (L() - lmv)) + j)] = tot;
+        tot += (int64_t)F_->ku(lmv, i, j) * width[j];
+      }
+    DevBuf<bf_c128> C((size_t)std::max<int64_t>(tot, 1), s_);
+    {
+      std::vector<GemmDesc> d;
+      for (int64_t i = 0; i < nT; ++i)
+        for (int64_t j = 0; j < nS; ++j) {
+          const size_t b = (size_t)((i << (L() - lmv)) + j);
+          const Block& Rb = F_->R[0][b];
+          GemmDesc g{};
+          g.out = C.p + coff[b];
+          g.out_ld = std::max(Rb.cols, 1);
+          g.M = Rb.cols;
+          g.ncols = width[j];
+          g.nterm = 1;
+          g.t[0] = GemmTerm{Rb.p, zq[b].in, zq[b].in_ld, Rb.rows, Rb.rows, 1, 0};
+          if (g.M > 0) d.push_back(g);
+        }
+      gemm(d, false);
+    }
+    solve_b(C.p, coff, view, width, [&](int64_t i, int64_t j) { return i; });
+  }
+
+  template <typename IdxFn>
+  void solve_b(const bf_c128* C, const std::vector<int64_t>& coff,
+               const std::vector<Tall<bf_c128>>& xview, const std::vector<int32_t>& width,
+               IdxFn xblock) {
+    const int lmv = lm();
+    const int64_t nS = int64_t(1) << (L() - lmv), nT = int64_t(1) << lmv;
+    std::vector<int64_t> boff((size_t)nb());
+    int64_t tot = 0;
+    for (int64_t i = 0; i < nT; ++i)
+      for (int64_t j = 0; j < nS; ++j) {
+        boff[(size_t)((i << (L() - lmv)) + j)] = tot;
+        tot += (int64_t)F_->ku(lmv, i, j) * F_->kv(lmv, i, j);
+      }
+    DevBuf<bf_c128> Bst((size_t)std::max<int64_t>(tot, 1), s_);
+    std::vector<LSDesc> d;
+    int32_t maxS = 0, maxK = 0;
+    F_->B.assign((size_t)nb(), Block{});
+    for (int64_t i = 0; i < nT; ++i)
+      for (int64_t j = 0; j < nS; ++j) {
+        const size_t b = (size_t)((i << (L() - lmv)) + j);
+        const int32_t ku = F_->ku(lmv, i, j), kv = F_->kv(lmv, i, j);
+        F_->B[b] = Block{Bst.p + boff[b], ku, kv};
+        if (ku == 0 || kv == 0) continue;
+        BF_CHECK(width[j] >= kv, BF_EINVAL, "centre sample narrower than the row rank");
+        const Tall<bf_c128>& xv = xview[j];
+        LSDesc ls{C + coff[b], xv.base + xv.roff[xblock(i, j)], Bst.p + boff[b],
+                  (int64_t)std::max(ku, 1), xv.ld, ku, kv, width[j], 0};
+        d.push_back(ls);
+        maxS = std::max(maxS, width[j]);
+        maxK = std::max(maxK, std::max(ku, kv));
+      }
+    if (validating())
+      for (auto& x : d) {
+        check_extent(x.C, ((size_t)(x.s - 1) * x.ldc + x.kU) * sizeof(bf_c128), "lsq C");
+        check_extent(x.X, ((size_t)(x.s - 1) * x.ldx + x.kV) * sizeof(bf_c128), "lsq X");
+        check_extent(x.B, (size_t)x.kU * x.kV * sizeof(bf_c128), "lsq B");
+      }
+    if (!d.empty()) {
+      auto dd = upload(d, s_, st_);
+      launch_lsq(dd.p, (int32_t)d.size(), maxS, maxK, s_);
+    }
+    F_->store.push_back(std::move(Bst));
+  }
+
+  // L = 0: the whole matrix is one block, A ~ U B V^H with the leaf bases.
+  void centre_single_block() {
+    const int64_t m = F_->m, n = F_->n;
+    const int32_t ku = F_->ku(0, 0, 0), kv = F_->kv(0, 0, 0);
+    const int32_t s = std::max(ku, kv) + p_;
+    std::vector<int32_t> width{s};
+    auto Om = gauss(n, s, 0, {make_tag(PHASE_R, 0, 0)}, width);
+    DevBuf<bf_c64> Y((size_t)m * s, s_);
+    std::vector<int64_t> seg{0, n};
+    call_op(false, Om.p, n, s, Y.p, m, nullptr);
+    mv_cols_ += s;
+    DevBuf<bf_c128> C((size_t)std::max(ku, 1) * s, s_);
+    DevBuf<bf_c128> X((size_t)std::max(kv, 1) * s, s_);
+    std::vector<GemmDesc> d1, d2;
+    const Block& U = F_->U[0];
+    const Block& V = F_->V[0];
+    GemmDesc g{};
+    g.out = C.p; g.out_ld = std::max(ku, 1); g.M = ku; g.ncols = s; g.nterm = 1;
+    g.t[0] = GemmTerm{U.p, Y.p, m, U.rows, U.rows, 1, 0};
+    if (ku > 0) d1.push_back(g);
+    g.out = X.p; g.out_ld = std::max(kv, 1); g.M = kv;
+    g.t[0] = GemmTerm{V.p, Om.p, n, V.rows, V.rows, 1, 0};
+    if (kv > 0) d1.push_back(g);
+    gemm(d1, true);
+    std::vector<Tall<bf_c128>> xv(1);
+    xv[0].base = X.p;
+    xv[0].ld = std::max(kv, 1);
+    xv[0].roff = {0};
+    solve_b(C.p, {0}, xv, width, [](int64_t, int64_t) { return 0; });
+  }
+
+  void finalize() {
+    int32_t kmax = 0;
+    int64_t entries = 0;
+    for (auto k : F_->kU) kmax = std::max(kmax, k);
+    for (auto k : F_->kV) kmax = std::max(kmax, k);
+    for (auto& b : canonical_blocks(F_)) entries += (int64_t)b.rows * b.cols;
+    build_apply_plans(F_, s_);
+    BF_HIP(hipStreamSynchronize(s_));
+    st_.reset();
+    int64_t bytes = 0;
+    for (auto& b : F_->store) bytes += (int64_t)(b.n * sizeof(bf_c128));
+    bytes += (int64_t)(F_->fwd.G.n + F_->adj.G.n) * (int64_t)sizeof(bf_c64);
+    bf_info& I = F_->info;
+    I.m = F_->m;
+    I.n = F_->n;
+    I.L = F_->L;
+    I.lm = F_->lm;
+    I.max_rank = kmax;
+    I.v_iters = v_iters_;
+    I.u_iters = u_iters_;
+    I.matvec_cols = mv_cols_;
+    I.rmatvec_cols = rmv_cols_;
+    I.factor_entries = entries;
+    I.device_bytes = bytes;
+  }
+};
+
+}  // namespace
+
+std::vector<Block> canonical_blocks(const bf_factors* F) {
+  std::vector<Block> out;
+  const int L = F->L, lm = F->lm;
+  for (auto& b : F->U) out.push_back(b);
+  for (int l = L - 1; l >= lm; --l)
+    for (auto& b : F->R[l - lm]) out.push_back(b);
+  for (auto& b : F->B) out.push_back(b);
+  for (int l = lm; l >= 1; --l)
+    for (auto& b : F->W[l]) out.push_back(b);
+  for (auto& b : F->V) out.push_back(b);
+  return out;
+}
+
+bf_factors* construct(bf_op_fn mv, bf_op_fn rmv, void* user, int64_t m, int64_t n, double tol,
+                      int64_t leaf, const bf_opts* o, hipStream_t s) {
+  Builder b(mv, rmv, user, m, n, tol, leaf, o, s);
+  return b.run();
+}
+
+}  // namespace bf

@@ -1,0 +1,78 @@
+// Factor store of a hybrid butterfly (output of Alg. 2) and its apply plan.
+#pragma once
+
+#include "bf_internal.h"
+
+namespace bf {
+
+// Node (l, i) of a bisection tree over N sorted points covers
+// [floor(i N / 2^l), floor((i+1) N / 2^l)) (Sec. 3.1; exact nesting for any N).
+inline int64_t node_lo(int64_t N, int l, int64_t i) { return (i * N) >> l; }
+inline int64_t node_hi(int64_t N, int l, int64_t i) { return ((i + 1) * N) >> l; }
+inline int64_t node_size(int64_t N, int l, int64_t i) { return node_hi(N, l, i) - node_lo(N, l, i); }
+
+inline int num_levels(int64_t m, int64_t n, int64_t leaf) {
+  int64_t big = m > n ? m : n;
+  int L = 0;
+  while ((big + (int64_t(1) << L) - 1) >> L > leaf) ++L;
+  return L;
+}
+
+// A factor block: column-major, ld = rows, FP64.
+struct Block {
+  bf_c128* p = nullptr;
+  int32_t rows = 0, cols = 0;
+};
+
+// One apply stage: descriptors [off, off+count) of the stage arrays.
+struct Stage {
+  int64_t off = 0;
+  int32_t count = 0;
+  int32_t maxM = 0;
+};
+
+struct ApplyPlan {
+  DevBuf<bf_c64> G;              // packed blocks of every stage (column-major per term)
+  DevBuf<ApplyDesc> desc;
+  std::vector<Stage> stages;     // in execution order
+  std::vector<int> in_buf, out_buf;
+  int64_t tmp_rows = 0;          // rows of each ping-pong intermediate
+};
+
+}  // namespace bf
+
+struct bf_factors {
+  int64_t m = 0, n = 0, leaf = 0;
+  int L = 0, lm = 0;
+  std::vector<bf::DevBuf<bf_c128>> store;   // owning FP64 level buffers
+  std::vector<bf::Block> U, V, B;           // U_{L,i}, V_{0,j}, B_{i,j} (i * 2^(L-lm) + j)
+  std::vector<std::vector<bf::Block>> R;    // R[l - lm][i * 2^(L-l) + j], lm <= l < L
+  std::vector<std::vector<bf::Block>> W;    // W[l][i * 2^(L-l) + j], 1 <= l <= lm
+  std::vector<int32_t> kU, kV;              // ranks, layout of bf_ranks
+  bf::ApplyPlan fwd, adj;
+  bf_info info{};
+  int device = 0;
+
+  int32_t ku(int l, int64_t i, int64_t j) const {
+    return kU[(size_t)(l - lm) * ((size_t)1 << L) + (size_t)(i << (L - l)) + (size_t)j];
+  }
+  int32_t kv(int l, int64_t i, int64_t j) const {
+    return kV[(size_t)l * ((size_t)1 << L) + (size_t)(i << (L - l)) + (size_t)j];
+  }
+  int32_t& ku_ref(int l, int64_t i, int64_t j) {
+    return kU[(size_t)(l - lm) * ((size_t)1 << L) + (size_t)(i << (L - l)) + (size_t)j];
+  }
+  int32_t& kv_ref(int l, int64_t i, int64_t j) {
+    return kV[(size_t)l * ((size_t)1 << L) + (size_t)(i << (L - l)) + (size_t)j];
+  }
+};
+
+namespace bf {
+// Build the forward and adjoint apply plans (packs the complex64 blocks).
+void build_apply_plans(bf_factors* F, hipStream_t s);
+// Apply (Y = F X or F^H X), complex64.
+void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
+                   bf_c64* Y, int64_t ldy, hipStream_t s);
+// Canonical-order block list (U, R^{L-1..lm}, B, W^{lm..1}, V).
+std::vector<Block> canonical_blocks(const bf_factors* F);
+}  // namespace bf

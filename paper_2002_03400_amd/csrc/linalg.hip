@@ -1,0 +1,399 @@
+// Batched small FP64 complex linear algebra of Alg. 2:
+//  * chain_gemm : products with the partially built factors (the V-chain^H,
+//                 U-chain^H and X-chain products of the W/R sweeps, and
+//                 R^H Z for the centre blocks);
+//  * cpqr       : truncated column-pivoted Householder QR (Alg. 1 step 3);
+//  * lsq        : centre blocks B = C X^+ (eq. Bij, read from its argmin).
+// One workgroup per block; blocks are ragged and described by host-built
+// descriptor arrays.  All arithmetic is FP64.
+#include "bf_internal.h"
+#include "cplx.h"
+
+namespace bf {
+
+template <typename T> __device__ __forceinline__ cd load_c(const T* p);
+template <> __device__ __forceinline__ cd load_c<bf_c64>(const bf_c64* p) {
+  bf_c64 v = *p;
+  return cd{(double)v.re, (double)v.im};
+}
+template <> __device__ __forceinline__ cd load_c<bf_c128>(const bf_c128* p) {
+  bf_c128 v = *p;
+  return cd{v.re, v.im};
+}
+
+// ---------------------------------------------------------------- gemm ----
+// grid (ndesc, ceil(max_ncols / 64)); each workgroup: rows 0..M-1 of one
+// descriptor, 64 columns.  Consecutive threads take consecutive rows so the
+// output and op = 0 factor reads are coalesced.
+constexpr int CG_COLS = 64;
+
+template <typename Tin>
+__global__ __launch_bounds__(256) void chain_gemm_kernel(const GemmDesc* __restrict__ descs) {
+  const GemmDesc d = descs[blockIdx.x];
+  const int c0 = blockIdx.y * CG_COLS;
+  if (c0 >= d.ncols) return;
+  const int cw = (d.ncols - c0 < CG_COLS) ? d.ncols - c0 : CG_COLS;
+  for (int idx = threadIdx.x; idx < d.M * cw; idx += blockDim.x) {
+    const int r = idx % d.M;
+    const int c = c0 + idx / d.M;
+    cd acc = {0.0, 0.0};
+    for (int t = 0; t < d.nterm; ++t) {
+      const GemmTerm& T = d.t[t];
+      const Tin* in = static_cast<const Tin*>(T.in) + (int64_t)c * T.in_ld;
+      if (T.op == 0) {
+        for (int k = 0; k < T.K; ++k) {
+          bf_c128 f = T.F[(int64_t)k * T.f_ld + r];
+          cd_fma(acc, cd{f.re, f.im}, load_c<Tin>(in + k));
+        }
+      } else {
+        const bf_c128* fr = T.F + (int64_t)r * T.f_ld;
+        for (int k = 0; k < T.K; ++k) {
+          bf_c128 f = fr[k];
+          cd_cfma(acc, cd{f.re, f.im}, load_c<Tin>(in + k));
+        }
+      }
+    }
+    d.out[(int64_t)c * d.out_ld + r] = bf_c128{acc.re, acc.im};
+  }
+}
+
+void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, bool in_c64,
+                       hipStream_t s) {
+  if (ndesc <= 0 || max_ncols <= 0) return;
+  dim3 grid((unsigned)ndesc, (unsigned)((max_ncols + CG_COLS - 1) / CG_COLS));
+  if (in_c64)
+    hipLaunchKernelGGL(chain_gemm_kernel<bf_c64>, grid, dim3(256), 0, s, d_dev);
+  else
+    hipLaunchKernelGGL(chain_gemm_kernel<bf_c128>, grid, dim3(256), 0, s, d_dev);
+  BF_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- cpqr ----
+// Businger-Golub pivoting, complex Householder reflectors
+// H = I - 2 v v^H / (v^H v), v = x - alpha e1, alpha = -exp(i arg x0) ||x||;
+// column norms of the trailing rows are recomputed after every update (never
+// downdated).  Rank: first k >= 1 with ||A[k:, k:]||_F <= tol ||Z||_F, else
+// min(M, N); an empty block has rank 0.
+//
+// Work mapping: 4 waves; wave w updates columns j = k+1+w, k+5+w, ...; its 64
+// lanes stride over the rows and reduce the reflector dot products with
+// butterfly shuffles.  The block lives in LDS (column-major, ld = M) when it
+// fits, else in a global scratch slot.  After the loop the reflectors (stored
+// in the dead columns of A) are accumulated backwards into Q, which overwrites
+// A column by column.
+constexpr int QR_THREADS = 256;
+constexpr int QR_WAVES = QR_THREADS / 64;
+
+struct QRShared {
+  double tail2;
+  int piv;
+  int stop;
+};
+
+__device__ __forceinline__ void reflect_column(cd* A, int M, int k, int j, const cd* v, double tau,
+                                               int lane, double* norm_out) {
+  // w = v^H A[k:, j];  A[k:, j] -= tau v w;  optionally the new norm^2 of rows k+1..
+  cd w = {0.0, 0.0};
+  for (int i = k + lane; i < M; i += 64) cd_cfma(w, v[i - k], A[(int64_t)j * M + i]);
+  w = wave_sum(w);
+  double nn = 0.0;
+  for (int i = k + lane; i < M; i += 64) {
+    cd a = A[(int64_t)j * M + i];
+    cd tv = cd_mul(v[i - k], w);
+    a.re -= tau * tv.re;
+    a.im -= tau * tv.im;
+    A[(int64_t)j * M + i] = a;
+    if (i > k) nn += cd_abs2(a);
+  }
+  if (norm_out) {
+    nn = wave_sum(nn);
+    if (lane == 0) *norm_out = nn;
+  }
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(QR_THREADS) void cpqr_kernel(const QRDesc* __restrict__ descs,
+                                                          double tol, int32_t* __restrict__ ranks,
+                                                          bf_c128* __restrict__ gscratch,
+                                                          int64_t scratch_slot, int use_lds) {
+  extern __shared__ double smem_raw[];
+  const QRDesc d = descs[blockIdx.x];
+  const int M = d.M, N = d.N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (M == 0 || N == 0) {
+    if (tid == 0) ranks[blockIdx.x] = 0;
+    return;
+  }
+  // LDS layout: [norm2 N][vn2 N][tmp M (cd)][QRShared][A M*N (cd) if use_lds]
+  double* norm2 = smem_raw;
+  double* vn2 = norm2 + N;
+  cd* tmp = reinterpret_cast<cd*>(vn2 + N);
+  QRShared* sh = reinterpret_cast<QRShared*>(tmp + M);
+  cd* A = use_lds ? reinterpret_cast<cd*>(reinterpret_cast<char*>(sh) + 64)
+                  : reinterpret_cast<cd*>(gscratch + (int64_t)blockIdx.x * scratch_slot);
+  const Tin* in = static_cast<const Tin*>(d.in);
+  for (int idx = tid; idx < M * N; idx += QR_THREADS) {
+    int i = idx % M, j = idx / M;
+    A[idx] = load_c<Tin>(in + (int64_t)j * d.in_ld + i);
+  }
+  __syncthreads();
+  // initial column norms (wave per column) and the total
+  for (int j = wave; j < N; j += QR_WAVES) {
+    double nn = 0.0;
+    for (int i = lane; i < M; i += 64) nn += cd_abs2(A[(int64_t)j * M + i]);
+    nn = wave_sum(nn);
+    if (lane == 0) norm2[j] = nn;
+  }
+  __syncthreads();
+  double total2 = 0.0;
+  {
+    double part = 0.0;
+    for (int j = lane; j < N; j += 64) part += norm2[j];
+    total2 = wave_sum(part);  // every wave computes the same value
+  }
+  const double thr2 = tol * tol * total2;
+  const int kmax = M < N ? M : N;
+  int rank = kmax;
+  for (int k = 0; k < kmax; ++k) {
+    if (wave == 0) {
+      // trailing Frobenius norm^2 and first argmax of the trailing column norms
+      double part = 0.0, best = -1.0;
+      int bidx = N;
+      for (int j = k + lane; j < N; j += 64) {
+        double v = norm2[j];
+        part += v;
+        if (v > best) { best = v; bidx = j; }
+      }
+      double tail2 = wave_sum(part);
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        double ob = __shfl_xor(best, off, 64);
+        int oi = __shfl_xor(bidx, off, 64);
+        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+      }
+      if (lane == 0) {
+        sh->tail2 = tail2;
+        sh->piv = bidx;
+        sh->stop = (k >= 1 && tail2 <= thr2) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    if (sh->stop) { rank = k; break; }
+    const int p = sh->piv;
+    if (p != k) {
+      for (int i = tid; i < M; i += QR_THREADS) {
+        cd a = A[(int64_t)k * M + i];
+        A[(int64_t)k * M + i] = A[(int64_t)p * M + i];
+        A[(int64_t)p * M + i] = a;
+      }
+      if (tid == 0) { double t = norm2[k]; norm2[k] = norm2[p]; norm2[p] = t; }
+    }
+    __syncthreads();
+    // Householder vector of column k, stored in place (A[k:, k] <- v)
+    if (wave == 0) {
+      double xn2 = 0.0;
+      for (int i = k + lane; i < M; i += 64) xn2 += cd_abs2(A[(int64_t)k * M + i]);
+      xn2 = wave_sum(xn2);
+      const double xn = sqrt(xn2);
+      if (lane == 0) {
+        cd x0 = A[(int64_t)k * M + k];
+        double ax0 = sqrt(cd_abs2(x0));
+        cd ph = ax0 > 0.0 ? cd{x0.re / ax0, x0.im / ax0} : cd{1.0, 0.0};
+        cd alpha = cd{-ph.re * xn, -ph.im * xn};
+        A[(int64_t)k * M + k] = cd_sub(x0, alpha);
+        vn2[k] = 2.0 * (xn2 + ax0 * xn);
+      }
+    }
+    __syncthreads();
+    const double vv = vn2[k];
+    if (vv > 0.0) {
+      const double tau = 2.0 / vv;
+      const cd* v = A + (int64_t)k * M + k;
+      for (int j = k + 1 + wave; j < N; j += QR_WAVES)
+        reflect_column(A, M, k, j, v, tau, lane, &norm2[j]);
+    } else {
+      // x = 0: H = I; trailing norms just lose row k
+      for (int j = k + 1 + wave; j < N; j += QR_WAVES) {
+        double nn = 0.0;
+        for (int i = k + 1 + lane; i < M; i += 64) nn += cd_abs2(A[(int64_t)j * M + i]);
+        nn = wave_sum(nn);
+        if (lane == 0) norm2[j] = nn;
+      }
+    }
+    __syncthreads();
+  }
+  // Q = H_0 ... H_{rank-1} [I; 0], accumulated backwards; column k of Q stays
+  // e_k until step k, and H_k only touches columns k..rank-1.
+  for (int k = rank - 1; k >= 0; --k) {
+    for (int i = tid; i < M; i += QR_THREADS) {
+      if (i >= k) tmp[i - k] = A[(int64_t)k * M + i];
+      A[(int64_t)k * M + i] = cd{i == k ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    const double vv = vn2[k];
+    if (vv > 0.0) {
+      const double tau = 2.0 / vv;
+      for (int j = k + wave; j < rank; j += QR_WAVES)
+        reflect_column(A, M, k, j, tmp, tau, lane, nullptr);
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < M * rank; idx += QR_THREADS) {
+    cd a = A[idx];
+    d.q[idx] = bf_c128{a.re, a.im};
+  }
+  if (tid == 0) ranks[blockIdx.x] = rank;
+}
+
+static size_t cpqr_lds_bytes(int M, int N, bool with_block) {
+  size_t b = 2 * sizeof(double) * N + sizeof(cd) * M + 64;
+  if (with_block) b += sizeof(cd) * (size_t)M * N;
+  return b;
+}
+
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+void launch_cpqr(const QRDesc* d_dev, int32_t nblk, int32_t maxM, int32_t maxN, double tol,
+                 bool in_c64, int32_t* ranks_dev, hipStream_t s) {
+  if (nblk <= 0) return;
+  BF_CHECK(maxM <= BF_MAX_BLOCK_ROWS && maxN <= BF_MAX_BLOCK_COLS, BF_ERANK,
+           "block exceeds BF_MAX_BLOCK_ROWS/COLS");
+  size_t lds = cpqr_lds_bytes(maxM, maxN, true);
+  int use_lds = lds <= LDS_LIMIT;
+  DevBuf<bf_c128> scratch;
+  int64_t slot = 0;
+  if (!use_lds) {
+    lds = cpqr_lds_bytes(maxM, maxN, false);
+    slot = (int64_t)maxM * maxN;
+    scratch = DevBuf<bf_c128>((size_t)slot * nblk, s);
+  }
+  auto kern = in_c64 ? cpqr_kernel<bf_c64> : cpqr_kernel<bf_c128>;
+  if (lds > 64 * 1024)
+    BF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(QR_THREADS), lds, s, d_dev, tol, ranks_dev,
+                     scratch.p, slot, use_lds);
+  BF_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- lsq -----
+// B = argmin ||C - B X||_F for C (kU x s), X (kV x s), s >= kV:
+//   X^H = Q_x R_x (Householder, no pivoting), then R_x B^H = Q_x^H C^H.
+// Both X^H (s x kV) and C^H (s x kU) are held in LDS and reduced together.
+__global__ __launch_bounds__(QR_THREADS) void lsq_kernel(const LSDesc* __restrict__ descs) {
+  extern __shared__ double smem_raw[];
+  const LSDesc d = descs[blockIdx.x];
+  const int S = d.s, KV = d.kV, KU = d.kU;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (KU == 0 || KV == 0) return;
+  // LDS: [vn2 KV][diag KV (cd)][XH S*KV][CH S*KU]
+  double* vn2 = smem_raw;
+  cd* diag = reinterpret_cast<cd*>(vn2 + KV);
+  cd* XH = diag + KV;                      // X^H, S x KV, ld S
+  cd* CH = XH + (int64_t)S * KV;           // C^H, S x KU, ld S
+  for (int idx = tid; idx < S * KV; idx += QR_THREADS) {
+    int i = idx % S, j = idx / S;          // XH[i, j] = conj(X[j, i])
+    bf_c128 x = d.X[(int64_t)i * d.ldx + j];
+    XH[idx] = cd{x.re, -x.im};
+  }
+  for (int idx = tid; idx < S * KU; idx += QR_THREADS) {
+    int i = idx % S, j = idx / S;
+    bf_c128 c = d.C[(int64_t)i * d.ldc + j];
+    CH[idx] = cd{c.re, -c.im};
+  }
+  __syncthreads();
+  const int kmax = KV < S ? KV : S;
+  for (int k = 0; k < kmax; ++k) {
+    if (wave == 0) {
+      double xn2 = 0.0;
+      for (int i = k + lane; i < S; i += 64) xn2 += cd_abs2(XH[(int64_t)k * S + i]);
+      xn2 = wave_sum(xn2);
+      const double xn = sqrt(xn2);
+      if (lane == 0) {
+        cd x0 = XH[(int64_t)k * S + k];
+        double ax0 = sqrt(cd_abs2(x0));
+        cd ph = ax0 > 0.0 ? cd{x0.re / ax0, x0.im / ax0} : cd{1.0, 0.0};
+        cd alpha = cd{-ph.re * xn, -ph.im * xn};
+        diag[k] = alpha;                                // R_x(k, k)
+        XH[(int64_t)k * S + k] = cd_sub(x0, alpha);     // v stored in place
+        vn2[k] = 2.0 * (xn2 + ax0 * xn);
+      }
+    }
+    __syncthreads();
+    const double vv = vn2[k];
+    if (vv > 0.0) {
+      const double tau = 2.0 / vv;
+      const cd* v = XH + (int64_t)k * S + k;
+      for (int j = k + 1 + wave; j < KV; j += QR_WAVES)
+        reflect_column(XH, S, k, j, v, tau, lane, nullptr);
+      for (int j = wave; j < KU; j += QR_WAVES)
+        reflect_column(CH, S, k, j, v, tau, lane, nullptr);
+    }
+    __syncthreads();
+  }
+  // R_x b = (Q_x^H C^H)[0:KV, c] for every column c; R_x(r, q) = XH[r, q]
+  // for q > r, R_x(r, r) = diag[r].
+  for (int c = tid; c < KU; c += QR_THREADS) {
+    cd* y = CH + (int64_t)c * S;
+    for (int r = KV - 1; r >= 0; --r) {
+      cd acc = y[r];
+      for (int q = r + 1; q < KV; ++q) acc = cd_sub(acc, cd_mul(XH[(int64_t)q * S + r], y[q]));
+      cd dg = diag[r];
+      double den = cd_abs2(dg);
+      y[r] = den > 0.0 ? cd{(acc.re * dg.re + acc.im * dg.im) / den,
+                            (acc.im * dg.re - acc.re * dg.im) / den}
+                       : cd{0.0, 0.0};
+    }
+    for (int r = 0; r < KV; ++r) {          // B[c, r] = conj(b[r])
+      cd bv = y[r];
+      d.B[(int64_t)r * KU + c] = bf_c128{bv.re, -bv.im};
+    }
+  }
+}
+
+void launch_lsq(const LSDesc* d_dev, int32_t nblk, int32_t maxS, int32_t maxK, hipStream_t s) {
+  if (nblk <= 0) return;
+  size_t lds = (sizeof(double) + sizeof(cd)) * maxK + sizeof(cd) * (size_t)maxS * (2 * maxK);
+  BF_CHECK(lds <= LDS_LIMIT, BF_ERANK, "centre block too large for the LDS least-squares kernel");
+  if (lds > 64 * 1024)
+    BF_HIP(hipFuncSetAttribute((const void*)lsq_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+  hipLaunchKernelGGL(lsq_kernel, dim3((unsigned)nblk), dim3(QR_THREADS), lds, s, d_dev);
+  BF_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- misc ----
+__global__ void c128_to_c64_kernel(const bf_c128* in, bf_c64* out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = bf_c64{(float)in[i].re, (float)in[i].im};
+}
+void launch_c128_to_c64(const bf_c128* in, bf_c64* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(c128_to_c64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in,
+                     out, n);
+  BF_HIP(hipGetLastError());
+}
+
+__global__ void expand_segments_kernel(const bf_c64* X, int64_t ldx, int64_t rows, int64_t ncols,
+                                       const int64_t* seg, int32_t nseg, bf_c64* out,
+                                       int64_t ldo) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t col = blockIdx.y;           // 0 .. nseg*ncols-1
+  if (r >= rows) return;
+  int64_t g = col / ncols, c = col % ncols;
+  bf_c64 v = {0.f, 0.f};
+  if (r >= seg[g] && r < seg[g + 1]) v = X[c * ldx + r];
+  out[col * ldo + r] = v;
+}
+void launch_expand_segments(const bf_c64* X, int64_t ldx, int64_t rows, int64_t ncols,
+                            const int64_t* seg_dev, int32_t nseg, bf_c64* out, int64_t ldo,
+                            hipStream_t s) {
+  if (rows <= 0 || ncols <= 0 || nseg <= 0) return;
+  BF_CHECK((int64_t)nseg * ncols <= 65535, BF_EINVAL, "too many expanded columns");
+  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)(nseg * ncols));
+  hipLaunchKernelGGL(expand_segments_kernel, grid, dim3(256), 0, s, X, ldx, rows, ncols, seg_dev,
+                     nseg, out, ldo);
+  BF_HIP(hipGetLastError());
+}
+
+}  // namespace bf

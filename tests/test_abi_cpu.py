@@ -1,0 +1,51 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/bf.h declares, and rejects bad arguments before it
+touches a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2002_03400_amd as bf
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "bf.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bf_[a-z0-9_]+)\s*\(", text)) - {"bf_op_fn"})
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(bf.LIB_PATH):
+        pytest.skip("libbf.so not built")
+    L = C.CDLL(bf.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(bf.SIGNATURES)
+
+
+def test_argument_errors_without_device():
+    if not os.path.exists(bf.LIB_PATH):
+        pytest.skip("libbf.so not built")
+    lib = bf.lib()
+    h = C.c_void_p()
+    o = bf.bf_opts(2, 4, 0, 0, 0)
+    # NULL callbacks, m <= 0, tol outside (0,1), leaf < 1
+    assert lib.bf_construct(None, None, None, 10, 10, 1e-6, 4, C.byref(o), None, C.byref(h)) == -1
+    assert lib.bf_apply(None, 0, None, 1, 1, None, 1, None) == -1
+    assert lib.bf_stats(None, None) == -1
+    assert lib.bf_free(None, None) == -1
+    assert lib.bf_strerror(-4) == b"rank cap exceeded or block too large"
+    assert lib.bf_op_fio(7, None) == -1
+
+
+def test_error_codes_match_header():
+    text = open(HEADER).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"(BF_E[A-Z]+)\s*=\s*(-\d+)", text))
+    assert codes == {"BF_EINVAL": -1, "BF_ENOMEM": -2, "BF_ECALLBACK": -3, "BF_ERANK": -4,
+                     "BF_EHIP": -5, "BF_ENOTSUP": -6}

@@ -1,0 +1,154 @@
+"""End-to-end parity of the GPU construction (Alg. 2) with the oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import butterfly as obf
+from oracle import metrics as om
+from oracle import operators as ops
+from tests.bfconv import canonical_to_oracle, oracle_to_canonical
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2002_03400_amd as m
+    m.lib()
+    return m
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.asarray(x, np.complex64)).cuda()
+
+
+def _err(AOm, FOm):
+    return float(np.linalg.norm(AOm - FOm) / np.linalg.norm(AOm))
+
+
+def _exported(bf, H):
+    kU, kV = H.ranks()
+    return canonical_to_oracle(H.m, H.n, H.L, kU, kV, H.export())
+
+
+@pytest.fixture(scope="module")
+def c1(bf):
+    """n = m = 1024, 8 points per wavelength, leaf 32, tol 1e-6, seed 1."""
+    g = wl.segment_pair(1024, ppw=8.0)
+    op_o = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    Fo = obf.construct(op_o, 1e-6, 32, seed=1)
+    say("construct C1 on GPU")
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    H = bf.construct(op, 1e-6, 32, seed=1)
+    return g, op_o, Fo, op, H
+
+
+def test_c1_error_parity(bf, c1):
+    g, op_o, Fo, op, H = c1
+    Om = wl.test_columns(1024, 16, 1001)
+    AOm = op_o.matvec(Om)
+    e_or = _err(AOm, obf.apply(Fo, Om))
+    e_gpu = _err(AOm, H.apply(_t(Om)).cpu().numpy())
+    say("C1 errors oracle", e_or, "gpu", e_gpu)
+    assert e_gpu <= 2 * e_or
+    assert e_gpu <= math.sqrt(1.25 * (H.L + 2)) * 1e-6 * 1.2
+
+
+def test_c1_ranks_and_exported_factors(bf, c1):
+    g, op_o, Fo, op, H = c1
+    kU, kV = H.ranks()
+    ko_U, ko_V, _ = oracle_to_canonical(Fo)
+    assert np.abs(kU.astype(int) - ko_U).max() <= 2
+    assert np.abs(kV.astype(int) - ko_V).max() <= 2
+    Fg = _exported(bf, H)
+    A = op_o.dense()
+    D = obf.dense(Fg)       # the oracle's independent assembly of the GPU factors
+    rel = np.linalg.norm(A - D) / np.linalg.norm(A)
+    say("C1 dense reconstruction of GPU factors", rel)
+    assert rel <= math.sqrt(1.25 * (H.L + 2)) * 1e-6 * 1.2
+    # orthonormal bases
+    for U in Fg.U:
+        np.testing.assert_allclose(U.conj().T @ U, np.eye(U.shape[1]), atol=1e-12)
+    for d in Fg.R.values():
+        for Rb in d.values():
+            np.testing.assert_allclose(Rb.conj().T @ Rb, np.eye(Rb.shape[1]), atol=1e-12)
+    info = H.stats()
+    assert info.max_rank == max(kU.max(), kV.max())
+    assert info.factor_entries == sum(x.size for x in [*Fg.U, *Fg.V]) + sum(
+        b.size for b in Fg.B.values()) + sum(x.size for d in Fg.R.values() for x in d.values()) + sum(
+        x.size for d in Fg.W.values() for x in d.values())
+
+
+def test_c1_apply_adjoint(bf, c1):
+    g, op_o, Fo, op, H = c1
+    Fg = _exported(bf, H)
+    X = wl.test_columns(1024, 5, 3)
+    np.testing.assert_allclose(H.apply(_t(X), trans=True).cpu().numpy(),
+                               obf.apply_adjoint(Fg, X), atol=2e-6 * np.abs(obf.apply_adjoint(Fg, X)).max())
+
+
+def test_deterministic(bf):
+    g = wl.segment_pair(512, ppw=8.0)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    say("determinism n=512")
+    a = bf.construct(op, 1e-6, 32, seed=3).export()
+    b = bf.construct(op, 1e-6, 32, seed=3).export()
+    c = bf.construct(op, 1e-6, 32, seed=4).export()
+    assert np.array_equal(a, b)
+    assert not (a.shape == c.shape and np.array_equal(a, c))
+
+
+@pytest.mark.parametrize("L,r", [(3, 2), (4, 4), (5, 8), (6, 8)])
+def test_exact_butterfly_recovery(bf, L, r):
+    """Sec. 6.1: the GPU recovers an exact butterfly (black box = GPU apply of
+    the imported factors, complex64) to single-precision level, all ranks r."""
+    fx = wl.exact_butterfly_factors(L, r, seed=L * 10 + r)
+    F0 = obf.from_exact(fx)
+    kU, kV, data = oracle_to_canonical(F0)
+    say("exact butterfly", L, r)
+    src = bf.import_factors(fx.n, fx.n, 8, kU, kV, data)
+    op = bf.from_factors(src)
+    H = bf.construct(op, 1e-5, 8, seed=5)
+    gU, gV = H.ranks()
+    assert set(np.unique(gU)) == {r} and set(np.unique(gV)) == {r}
+    Om = wl.test_columns(fx.n, 16, 2)
+    e = _err(obf.apply(F0, Om), H.apply(_t(Om)).cpu().numpy())
+    say("exact err", e)
+    assert e < 5e-6
+
+
+@pytest.mark.parametrize("m,n,leaf", [(300, 257, 16), (100, 1000, 40), (24, 24, 32), (50, 20, 8)])
+def test_ragged_and_degenerate_shapes(bf, m, n, leaf):
+    g = wl.segment_pair(n, ppw=10.0, m=m)
+    op_o = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    say("ragged", m, n, leaf)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    H = bf.construct(op, 1e-6, leaf, seed=4)
+    Fo = obf.construct(op_o, 1e-6, leaf, seed=4)
+    Om = wl.test_columns(n, 16, 9)
+    AOm = op_o.matvec(Om)
+    e_gpu = _err(AOm, H.apply(_t(Om)).cpu().numpy())
+    e_or = _err(AOm, obf.apply(Fo, Om))
+    say("ragged errors", e_or, e_gpu)
+    assert e_gpu <= 2 * e_or + 2e-6
+
+
+def test_rank_cap_error(bf):
+    g = wl.segment_pair(256, ppw=8.0)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    say("rank cap")
+    with pytest.raises(bf.BFError) as ei:
+        bf.construct(op, 1e-6, 64, seed=1, max_rank=4)
+    assert ei.value.code == -4

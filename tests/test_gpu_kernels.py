@@ -1,0 +1,177 @@
+"""GPU parity of the batched building blocks against the oracle (through the
+C ABI).  Each test prints the case it runs before touching the device."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import butterfly as obf
+from oracle import cpqr as ocpqr
+from oracle import operators as ops
+from oracle import philox
+from tests.bfconv import oracle_to_canonical
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2002_03400_amd as m
+    m.lib()
+    return m
+
+
+def _cg(rng, *shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2)
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.asarray(x, np.complex64)).cuda()
+
+
+# ---------------------------------------------------------------- RNG -------
+@pytest.mark.parametrize("seed,phase,level,node,row0,rows,cols",
+                         [(1, 1, 0, 0, 0, 1000, 6), (7, 4, 3, 5, 12345, 300, 40),
+                          (2**63 + 5, 3, 9, 511, 65000, 536, 3)])
+def test_gauss_matches_oracle(bf, seed, phase, level, node, row0, rows, cols):
+    tg = philox.tag(phase, level, node)
+    say("gauss", seed, tg, row0, rows, cols)
+    g = bf.gauss(seed, tg, row0, rows, cols).cpu().numpy()
+    ref = philox.gaussian_block(seed, tg, row0, rows, cols)
+    # same Philox bits; FP64 log / sincospi on the device vs the host libm
+    np.testing.assert_allclose(g, ref, rtol=0, atol=4e-15 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- CPQR ------
+def _cpqr_cases():
+    rng = np.random.default_rng(11)
+    cases = []
+    for (M, N) in [(24, 26), (36, 40), (64, 34), (72, 74), (5, 9), (9, 5), (1, 1), (130, 70),
+                   (200, 200), (64, 6)]:
+        cases.append(_cg(rng, M, N) * rng.uniform(0.3, 3.0, N)[None, :])
+    cases.append(_cg(rng, 40, 6) @ _cg(rng, 6, 30))              # exact rank 6
+    U = np.linalg.qr(_cg(rng, 50, 30))[0]
+    cases.append((U * 0.5 ** np.arange(30)) @ _cg(rng, 30, 32))  # geometric spectrum
+    cases.append(np.zeros((10, 7), complex))                     # zero block
+    cases.append(np.zeros((0, 5), complex))                      # empty
+    return cases
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-3])
+def test_cpqr_matches_oracle(bf, tol):
+    blocks = _cpqr_cases()
+    say("cpqr batch", [b.shape for b in blocks], tol)
+    Qs, ranks = bf.cpqr_batched(blocks, tol)
+    for b, Q, k in zip(blocks, Qs, ranks):
+        Qo, ko = ocpqr.range_basis(b, tol)
+        assert k == ko, (b.shape, k, ko)
+        if k:
+            np.testing.assert_allclose(Q, Qo, atol=1e-10)
+            np.testing.assert_allclose(Q.conj().T @ Q, np.eye(k), atol=1e-12)
+
+
+# ---------------------------------------------------------------- LS --------
+def test_lsq_matches_oracle(bf):
+    rng = np.random.default_rng(5)
+    shapes = [(13, 13, 20), (20, 18, 40), (1, 1, 3), (35, 33, 72), (7, 12, 12)]
+    Cs = [_cg(rng, ku, s) for ku, kv, s in shapes]
+    Xs = [_cg(rng, kv, s) for ku, kv, s in shapes]
+    say("lsq", shapes)
+    Bs = bf.lsq_batched(Cs, Xs)
+    for C, X, B in zip(Cs, Xs, Bs):
+        ref = obf._lstsq_right(C, X)
+        np.testing.assert_allclose(B, ref, atol=1e-10 * max(1, np.abs(ref).max()))
+
+
+# ------------------------------------------------------- black boxes -------
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("m,n,ppw", [(1024, 1024, 8.0), (700, 1500, 5.0)])
+def test_segkernel_products(bf, m, n, ppw):
+    g = wl.segment_pair(n, ppw=ppw, m=m)
+    say("segkernel", m, n, ppw)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    ref = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    rng = np.random.default_rng(1)
+    X = _cg(rng, n, 7)
+    Y = op.matvec(_t(X)).cpu().numpy()
+    assert _rel(Y, ref.matvec(X)) < 2e-6
+    Xt = _cg(rng, m, 5)
+    Yt = op.rmatvec(_t(Xt)).cpu().numpy()
+    assert _rel(Yt, ref.rmatvec(Xt)) < 2e-6
+    # structured samples: ragged segments, per-segment products
+    seg = np.array([0, 3, 400, 401, n], np.int64)
+    Ys = op.matvec(_t(X), seg=seg).cpu().numpy()
+    for q in range(4):
+        Xq = np.zeros_like(X)
+        Xq[seg[q]:seg[q + 1]] = X[seg[q]:seg[q + 1]]
+        exp = ref.matvec(Xq)
+        got = Ys[:, q * 7:(q + 1) * 7]
+        assert np.linalg.norm(got - exp) <= 2e-6 * max(np.linalg.norm(exp), 1e-30) + 1e-12
+
+
+def test_segkernel_wide_and_split(bf):
+    """65 columns (two column chunks) and a long inner range (split-K path)."""
+    n = 20000
+    g = wl.segment_pair(n, ppw=8.0, m=300)
+    say("segkernel wide", n)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    ref = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    X = _cg(np.random.default_rng(2), n, 65)
+    Y = op.matvec(_t(X)).cpu().numpy()
+    assert _rel(Y, ref.matvec(X)) < 3e-6
+
+
+def test_fio_products(bf):
+    n = 2048
+    x, xi = wl.fio_params(n)
+    say("fio", n)
+    op = bf.fio(n)
+    ref = ops.FIOOp(x, xi)
+    X = _cg(np.random.default_rng(3), n, 4)
+    assert _rel(op.matvec(_t(X)).cpu().numpy(), ref.matvec(X)) < 2e-6
+    assert _rel(op.rmatvec(_t(X)).cpu().numpy(), ref.rmatvec(X)) < 2e-6
+
+
+def test_dense_products(bf):
+    import torch
+    rng = np.random.default_rng(4)
+    A = _cg(rng, 300, 200)
+    say("dense", A.shape)
+    op = bf.dense(torch.from_numpy(A.astype(np.complex64)).cuda())
+    X = _cg(rng, 200, 3)
+    Z = _cg(rng, 300, 3)
+    assert _rel(op.matvec(_t(X)).cpu().numpy(), A @ X) < 1e-6
+    assert _rel(op.rmatvec(_t(Z)).cpu().numpy(), A.conj().T @ Z) < 1e-6
+
+
+# ---------------------------------------------------------------- apply -----
+@pytest.mark.parametrize("n,leaf", [(1024, 32), (600, 40), (20, 32)])
+def test_apply_of_oracle_factors(bf, n, leaf):
+    g = wl.segment_pair(n, ppw=8.0)
+    op = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    F = obf.construct(op, 1e-6, leaf, seed=1)
+    kU, kV, data = oracle_to_canonical(F)
+    say("apply import", n, leaf, F.L)
+    H = bf.import_factors(n, n, leaf, kU, kV, data)
+    X = _cg(np.random.default_rng(6), n, 9)
+    Y = H.apply(_t(X)).cpu().numpy()
+    assert _rel(Y, obf.apply(F, X)) < 1e-6
+    Yh = H.apply(_t(X), trans=True).cpu().numpy()
+    assert _rel(Yh, obf.apply_adjoint(F, X)) < 1e-6
+    back = H.export()
+    np.testing.assert_array_equal(back, data)
+    H.close()
