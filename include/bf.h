@@ -175,6 +175,33 @@ const char* bf_strerror(int code);
 const char* bf_last_error(void);
 
 /* ---------------------------------------------------------------------------
+ * Profiling: while enabled, every launch of the library's kernels is
+ * bracketed by HIP events recorded on the stream the kernel runs on, and
+ * its algorithmic work is counted (flops of the complex multiply-adds, bytes
+ * of the operands the algorithm must move).  Per kernel class:
+ * ------------------------------------------------------------------------ */
+enum {
+  BF_KC_MATFREE = 0,   /* black-box products of the built-in operators */
+  BF_KC_APPLY = 1,     /* butterfly apply stages */
+  BF_KC_CPQR = 2,      /* batched truncated pivoted QR */
+  BF_KC_CHAIN = 3,     /* partial-factor products of the sweeps */
+  BF_KC_LSQ = 4,       /* centre-block least squares */
+  BF_KC_OTHER = 5,     /* random blocks, packing, reductions */
+  BF_KC_COUNT = 6
+};
+typedef struct {
+  int64_t launches;
+  double ms;      /* summed event time of the launches */
+  double flops;   /* algorithmic flops (complex MAC = 8) */
+  double bytes;   /* algorithmic bytes */
+} bf_kernel_stats;
+/* Reset the counters and start recording (process-wide). */
+int bf_profile_start(void);
+/* Stop recording; waits for the recorded events and writes BF_KC_COUNT
+   entries to `out` (HOST). */
+int bf_profile_stop(bf_kernel_stats* out);
+
+/* ---------------------------------------------------------------------------
  * Kernel-level entry points: the batched building blocks of Alg. 2 exposed
  * on their own so that each can be checked against a reference.  All buffers
  * are device buffers unless marked HOST.

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libbf.so")
 
 __all__ = ["BFError", "lib", "Operator", "Factors", "construct", "segkernel", "fio", "dense",
            "from_factors", "compose", "import_factors", "gauss", "cpqr_batched", "lsq_batched",
-           "num_levels", "LIB_PATH"]
+           "num_levels", "LIB_PATH", "profile_start", "profile_stop"]
 
 
 class BFError(RuntimeError):
@@ -49,6 +49,14 @@ class bf_opts(C.Structure):
                 ("flags", C.c_int32), ("seed", C.c_uint64)]
 
 
+class bf_kernel_stats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double),
+                ("bytes", C.c_double)]
+
+
+KERNEL_CLASSES = ("matfree", "apply", "cpqr", "chain", "lsq", "other")
+
+
 class bf_info(C.Structure):
     _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("L", C.c_int32), ("lm", C.c_int32),
                 ("max_rank", C.c_int32), ("v_iters", C.c_int32), ("u_iters", C.c_int32),
@@ -74,6 +82,8 @@ SIGNATURES = {
     "bf_free": (C.c_int, [_P, _P]),
     "bf_strerror": (C.c_char_p, [C.c_int]),
     "bf_last_error": (C.c_char_p, []),
+    "bf_profile_start": (C.c_int, []),
+    "bf_profile_stop": (C.c_int, [C.POINTER(bf_kernel_stats)]),
     "bf_gauss": (C.c_int, [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
     "bf_cpqr_batched": (C.c_int, [C.c_int32, _I32P, _I32P, _P, _I64P, C.c_double, _P, _I64P,
                                   _I32P, _P]),
@@ -315,6 +325,18 @@ def import_factors(m, n, leaf, kU, kV, data, stream=None) -> Factors:
     _check(lib().bf_import(m, n, leaf, kU.ctypes.data_as(_I32P), kV.ctypes.data_as(_I32P),
                            data.ctypes.data, len(data), _stream(stream), C.byref(h)), "bf_import")
     return Factors(h, leaf)
+
+
+def profile_start():
+    _check(lib().bf_profile_start(), "bf_profile_start")
+
+
+def profile_stop():
+    """Per kernel class: {launches, ms, flops, bytes} of the launches since start."""
+    arr = (bf_kernel_stats * len(KERNEL_CLASSES))()
+    _check(lib().bf_profile_stop(arr), "bf_profile_stop")
+    return {name: {f: getattr(arr[k], f) for f, _ in bf_kernel_stats._fields_}
+            for k, name in enumerate(KERNEL_CLASSES)}
 
 
 def gauss(seed, tag, row0, rows, cols, device="cuda"):

@@ -14,6 +14,7 @@ SOURCES = ["rng.hip", "matfree.hip", "linalg.hip", "apply.hip", "driver.cpp", "p
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
 
 

@@ -2,6 +2,7 @@
 // import/export and the built-in black-box operators.
 #include <algorithm>
 #include <cmath>
+#include <atomic>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -15,6 +16,38 @@ bf_factors* construct(bf_op_fn mv, bf_op_fn rmv, void* user, int64_t m, int64_t 
 
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// ---- profiling --------------------------------------------------------------
+namespace {
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof;
+std::atomic<bool> g_prof_on{false};
+}  // namespace
+
+bool profiling() { return g_prof_on.load(std::memory_order_relaxed); }
+
+ProfScope::ProfScope(int c, hipStream_t st, double fl, double by)
+    : cls(c), s(st), flops(fl), bytes(by) {
+  if (!profiling()) return;
+  if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, s) != hipSuccess) a = nullptr;
+}
+
+ProfScope::~ProfScope() {
+  if (!a) return;
+  hipEvent_t b = nullptr;
+  if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(ProfRec{cls, a, b, flops, bytes});
+}
 
 // ---- memory ---------------------------------------------------------------
 static std::once_flag g_pool_once[64];
@@ -289,6 +322,42 @@ const char* bf_strerror(int code) {
 }
 
 const char* bf_last_error(void) { return g_last_error.c_str(); }
+
+int bf_profile_start(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof) {
+    (void)hipEventSynchronize(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  g_prof_on = true;
+  return BF_OK;
+}
+
+int bf_profile_stop(bf_kernel_stats* out) {
+  g_prof_on = false;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  bf_kernel_stats acc[BF_KC_COUNT] = {};
+  int rc = BF_OK;
+  for (auto& r : g_prof) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      rc = BF_EHIP;
+    if (r.cls >= 0 && r.cls < BF_KC_COUNT) {
+      acc[r.cls].launches += 1;
+      acc[r.cls].ms += ms;
+      acc[r.cls].flops += r.flops;
+      acc[r.cls].bytes += r.bytes;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  if (out)
+    for (int k = 0; k < BF_KC_COUNT; ++k) out[k] = acc[k];
+  return rc;
+}
 
 int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64_t n, double tol,
                  int64_t leaf, const bf_opts* opts, void* stream, bf_factors** out) {

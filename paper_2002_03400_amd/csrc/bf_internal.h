@@ -42,6 +42,19 @@ void set_last_error(const std::string& msg);
 bool validating();
 void check_extent(const void* p, size_t bytes, const char* what);
 
+// -------------------------------------------------------------- profiling --
+// RAII bracket of one launch: records a start event now and a stop event at
+// scope exit on the same stream, when profiling is enabled.
+bool profiling();
+struct ProfScope {
+  int cls;
+  hipStream_t s;
+  double flops, bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(int c, hipStream_t st, double fl, double by);
+  ~ProfScope();
+};
+
 // ------------------------------------------------------- device buffers --
 // Stream-ordered device memory (hipMallocAsync from the device's default pool,
 // whose release threshold is raised at first use so freed memory is reused).

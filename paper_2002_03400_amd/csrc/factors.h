@@ -29,6 +29,7 @@ struct Stage {
   int64_t off = 0;
   int32_t count = 0;
   int32_t maxM = 0;
+  double macs = 0;   // complex multiply-adds per right-hand side
 };
 
 struct ApplyPlan {

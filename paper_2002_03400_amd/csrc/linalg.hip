@@ -61,6 +61,7 @@ void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, 
                        hipStream_t s) {
   if (ndesc <= 0 || max_ncols <= 0) return;
   dim3 grid((unsigned)ndesc, (unsigned)((max_ncols + CG_COLS - 1) / CG_COLS));
+  ProfScope ps(BF_KC_CHAIN, s, 0.0, 0.0);
   if (in_c64)
     hipLaunchKernelGGL(chain_gemm_kernel<bf_c64>, grid, dim3(256), 0, s, d_dev);
   else
@@ -268,6 +269,7 @@ void launch_cpqr(const QRDesc* d_dev, int32_t nblk, int32_t maxM, int32_t maxN, 
     scratch = DevBuf<bf_c128>((size_t)slot * nblk, s);
   }
   auto kern = in_c64 ? cpqr_kernel<bf_c64> : cpqr_kernel<bf_c128>;
+  ProfScope ps(BF_KC_CPQR, s, 0.0, 0.0);
   if (lds > 64 * 1024)
     BF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
@@ -358,6 +360,7 @@ void launch_lsq(const LSDesc* d_dev, int32_t nblk, int32_t maxS, int32_t maxK, h
   if (lds > 64 * 1024)
     BF_HIP(hipFuncSetAttribute((const void*)lsq_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
+  ProfScope ps(BF_KC_LSQ, s, 0.0, 0.0);
   hipLaunchKernelGGL(lsq_kernel, dim3((unsigned)nblk), dim3(QR_THREADS), lds, s, d_dev);
   BF_HIP(hipGetLastError());
 }

@@ -4,12 +4,18 @@
 // Y[i, g*ncols + c] = sum_{j in seg_g} E(i, j) X[j, c]    (Sec. 4.1 structured
 // samples: group g is the product with the random block living on node g).
 //
-// Layout: one workgroup of 256 threads owns 256 output rows of one group and
-// one slice of the group's inner range (split-K when there are too few row
-// tiles to fill 256 CUs); each thread keeps NC complex accumulators in
-// registers; a chunk of TK inner points (their coordinates and the TK x NC
-// block of X) is staged in LDS and read as broadcasts.  Split-K partials go
-// to a scratch buffer and are summed in a fixed order (deterministic).
+// Layout: one workgroup of 4 waves owns 128 output rows of one group, up to
+// 48 columns, and one slice of the group's inner range (split-K when there
+// are too few row tiles to fill 256 CUs); chunks of TK inner points (their
+// coordinates and the TK x 64 block of X) are staged in LDS.  Split-K
+// partials go to an FP64 scratch buffer and are summed in a fixed order
+// (deterministic).
+//
+// Precision: entries are FP32-accurate (FP64 phase reduction, FP32 sin/cos
+// and 1/r) and the inputs are complex64.  A recursive FP32 sum over the
+// 10^4..10^5 terms of one output would carry a relative rounding error of
+// order 1e-6..1e-5 -- the size of the tolerances of interest, inflating every
+// sampled rank -- so products are accumulated in FP64 on the matrix cores.
 #include "bf_internal.h"
 #include "cplx.h"
 
@@ -17,12 +23,43 @@ namespace bf {
 
 constexpr int MF_THREADS = 256;
 constexpr int MF_TK = 64;
+// inner length of the product being launched (for the profiler's accounting)
+static thread_local int64_t g_matfree_nin = 0;
 
 // ---- entry functors ------------------------------------------------------
 
-// exp(i k r)/r, r = |p - q|; phase k r / 2pi reduced to [-1/2, 1/2] in FP64,
-// then sin/cos of 2 pi f and 1/r in FP32.  sign = -1 gives the conjugate
-// (entries of A^H with the point roles swapped).
+// sin and cos of 2 pi t for a phase t given in revolutions (FP64, |t| < 2^29).
+// The phase is reduced in FP64 to the nearest quarter revolution,
+// t = q/4 + y with |y| <= 1/8, so x = 2 pi y lies in [-pi/4, pi/4] and only
+// its FP32 rounding (< 3e-8 rad) enters; sin x and cos x are the Taylor
+// polynomials through x^9 and x^10 (truncation below 2e-9 on that interval),
+// then rotated by q quarter turns.
+__device__ __forceinline__ void sincos_rev(double t, float* s, float* c) {
+  const double q = rint(4.0 * t);
+  const double y = fma(-0.25, q, t);
+  const float x = (float)(y * 6.283185307179586477);
+  const float x2 = x * x;
+  float sp = fmaf(x2, 2.75573192e-6f, -1.98412698e-4f);   // 1/9!, -1/7!
+  sp = fmaf(x2, sp, 8.33333333e-3f);                       // 1/5!
+  sp = fmaf(x2, sp, -1.66666667e-1f);                      // -1/3!
+  sp = x * fmaf(x2, sp, 1.0f);
+  float cp = fmaf(x2, -2.75573192e-7f, 2.48015873e-5f);    // -1/10!, 1/8!
+  cp = fmaf(x2, cp, -1.38888889e-3f);                      // -1/6!
+  cp = fmaf(x2, cp, 4.16666667e-2f);                       // 1/4!
+  cp = fmaf(x2, cp, -0.5f);                                // -1/2!
+  cp = fmaf(x2, cp, 1.0f);
+  const int n = (int)q & 3;
+  const float sv = (n & 1) ? cp : sp;
+  const float cv = (n & 1) ? sp : cp;
+  *s = (n & 2) ? -sv : sv;
+  *c = ((n ^ (n >> 1)) & 1) ? -cv : cv;
+}
+
+// exp(i k r)/r, r = |p - q|: r from an FP32 square root refined by one
+// FP64 Newton step (relative error ~1e-14, so the phase k r / 2pi stays
+// accurate to ~1e-9 revolutions for k r up to 1e5), 1/r from the FP32
+// reciprocal.  sign = -1 gives the conjugate (entries of A^H with the point
+// roles swapped).
 struct SegEntry {
   PointSet out, in;
   double kk;   // k / (2 pi)
@@ -32,52 +69,49 @@ struct SegEntry {
   __device__ Row row(int64_t i) const { return Row{out.x[i], out.y[i]}; }
   __device__ Col col(int64_t j) const { return Col{in.x[j], in.y[j]}; }
   __device__ cf entry(const Row& r, const Col& c) const {
-    double dx = r.x - c.x, dy = r.y - c.y;
-    double rr = sqrt(fma(dx, dx, dy * dy));
-    double t = rr * kk;
-    double f = t - rint(t);
+    const double dx = r.x - c.x, dy = r.y - c.y;
+    const double r2 = fma(dx, dx, dy * dy);
+    const float rf = __builtin_amdgcn_sqrtf((float)r2);
+    const float inv = __builtin_amdgcn_rcpf(rf);
+    const double rd = (double)rf;
+    const double rr = fma(fma(-rd, rd, r2), 0.5 * (double)inv, rd);
     float s, co;
-    sincospif(2.0f * (float)f, &s, &co);
-    float inv = 1.0f / (float)rr;
+    sincos_rev(rr * kk, &s, &co);
     return cf{co * inv, sign * s * inv};
   }
 };
 
-// exp(2 pi i (j xi / n + c_j |xi|)); the linear phase is reduced modulo n in
-// integers.  Forward: output index j (row), inner index k (xi = k - n/2).
+// exp(2 pi i (j xi / n + c_j |xi|)).  j * xi is an exact integer (< 2^53),
+// so j xi / n is formed in FP64 with one rounding before the reduction.
+// Forward: output index j (row), inner index k (xi = k - n/2).
 struct FioEntry {
   int64_t n;
+  double inv_n;
   const double* cx;  // c(x_j), FP64
-  float sign;
-  struct Row { int64_t j; double c; };
-  struct Col { int64_t xi; };
-  __device__ Row row(int64_t j) const { return Row{j, cx[j]}; }
-  __device__ Col col(int64_t k) const { return Col{k - n / 2}; }
+  struct Row { double j; double c; };
+  struct Col { double xi; };
+  __device__ Row row(int64_t j) const { return Row{(double)j, cx[j]}; }
+  __device__ Col col(int64_t k) const { return Col{(double)(k - n / 2)}; }
   __device__ cf entry(const Row& r, const Col& c) const {
-    int64_t lin = (r.j * c.xi) % n;
-    if (lin < 0) lin += n;
-    double ph = (double)lin / (double)n + r.c * (double)(c.xi < 0 ? -c.xi : c.xi);
-    double f = ph - rint(ph);
+    const double ph = fma(r.j * c.xi, inv_n, r.c * fabs(c.xi));
     float s, co;
-    sincospif(2.0f * (float)f, &s, &co);
-    return cf{co, sign * s};
+    sincos_rev(ph, &s, &co);
+    return cf{co, s};
   }
 };
 // Adjoint: output index k, inner index j: conj(A_jk).
 struct FioAdjEntry {
   int64_t n;
+  double inv_n;
   const double* cx;
-  struct Row { int64_t xi; };
-  struct Col { int64_t j; double c; };
-  __device__ Row row(int64_t k) const { return Row{k - n / 2}; }
-  __device__ Col col(int64_t j) const { return Col{j, cx[j]}; }
+  struct Row { double xi; };
+  struct Col { double j; double c; };
+  __device__ Row row(int64_t k) const { return Row{(double)(k - n / 2)}; }
+  __device__ Col col(int64_t j) const { return Col{(double)j, cx[j]}; }
   __device__ cf entry(const Row& r, const Col& c) const {
-    int64_t lin = (c.j * r.xi) % n;
-    if (lin < 0) lin += n;
-    double ph = (double)lin / (double)n + c.c * (double)(r.xi < 0 ? -r.xi : r.xi);
-    double f = ph - rint(ph);
+    const double ph = fma(c.j * r.xi, inv_n, c.c * fabs(r.xi));
     float s, co;
-    sincospif(2.0f * (float)f, &s, &co);
+    sincos_rev(ph, &s, &co);
     return cf{co, -s};
   }
 };
@@ -101,78 +135,157 @@ struct DenseEntry {
 };
 
 // ---- kernel ----------------------------------------------------------------
+//
+// Complex products on the matrix cores in FP64 (v_mfma_f64_16x16x4f64; on
+// gfx950 the FP64 matrix rate equals the FP64 vector rate, but the matrix
+// cores run beside the vector ALUs that evaluate the entries).  A wave owns
+// 16*MF_H output rows x 16*NT columns; per step of 4 inner points lane l
+// evaluates the entries (row l % 16 of each 16-row tile, inner point l / 16)
+// -- its own slots of the A operand -- and reads its B slots (inner point l / 16,
+// column l % 16) from the X chunk staged in LDS.  Complex products use three
+// real products (Gauss):  P1 = Re a Re x, P2 = Im a Im x,
+// P3 = (Re a + Im a)(Re x + Im x);  Re y = P1 - P2, Im y = P3 - P1 - P2.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <class E, int NC>
+constexpr int MF_H = 1;                // 16-row tiles per wave
+constexpr int MF_ROWS = 64 * MF_H;     // output rows per workgroup (4 waves)
+
+template <class E, int NT, typename Tout>
 __global__ __launch_bounds__(MF_THREADS) void matfree_kernel(
     E e, int64_t nout, const bf_c64* __restrict__ X, int64_t ldx, int32_t ncols, int32_t c0,
-    bf_c64* __restrict__ Y, int64_t ldy, int64_t ycols, const int64_t* __restrict__ seg,
-    int32_t nsplit) {
+    int32_t width, Tout* __restrict__ Y, int64_t ldy, int64_t ycols,
+    const int64_t* __restrict__ seg, int32_t nsplit) {
+  constexpr int NC = 16 * NT;
   __shared__ typename E::Col cols[MF_TK];
   __shared__ cf xs[MF_TK][NC];
   const int g = blockIdx.y;
   const int z = blockIdx.z;
-  const int64_t i = (int64_t)blockIdx.x * MF_THREADS + threadIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t row0 = (int64_t)blockIdx.x * MF_ROWS + wave * 16 * MF_H;
+  const int kq = lane >> 4;       // inner point of the step held by this lane
+  const int lc = lane & 15;       // A row / B column within a 16-wide tile
   const int64_t j0 = seg[g], j1 = seg[g + 1];
   const int64_t len = j1 - j0;
   const int64_t chunk = (len + nsplit - 1) / nsplit;
   const int64_t a = j0 + (int64_t)z * chunk;
   const int64_t b = (a + chunk < j1) ? a + chunk : j1;
-  const int nc = (ncols - c0 < NC) ? ncols - c0 : NC;
+  const int nc = width < NC ? width : NC;
 
-  cf acc[NC];
+  doublex4 p1[MF_H][NT], p2[MF_H][NT], p3[MF_H][NT];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = cf{0.f, 0.f};
-  typename E::Row rw = e.row(i < nout ? i : 0);
+  for (int h = 0; h < MF_H; ++h)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { p1[h][t][v] = 0.0; p2[h][t][v] = 0.0; p3[h][t][v] = 0.0; }
+  typename E::Row rw[MF_H];
+#pragma unroll
+  for (int h = 0; h < MF_H; ++h) {
+    const int64_t r = row0 + 16 * h + lc;
+    rw[h] = e.row(r < nout ? r : nout - 1);
+  }
 
   for (int64_t jb = a; jb < b; jb += MF_TK) {
     const int tk = (b - jb < MF_TK) ? (int)(b - jb) : MF_TK;
     __syncthreads();
     for (int idx = threadIdx.x; idx < MF_TK * NC; idx += MF_THREADS) {
-      int jj = idx % MF_TK, c = idx / MF_TK;
+      const int jj = idx % MF_TK, c = idx / MF_TK;
       bf_c64 v = {0.f, 0.f};
       if (jj < tk && c < nc) v = X[(int64_t)(c0 + c) * ldx + jb + jj];
       xs[jj][c] = cf{v.re, v.im};
     }
     if (threadIdx.x < tk) cols[threadIdx.x] = e.col(jb + threadIdx.x);
     __syncthreads();
-    if (i < nout) {
-      for (int jj = 0; jj < tk; ++jj) {
-        cf av = e.entry(rw, cols[jj]);
+    const int nsteps = (tk + 3) >> 2;
+    for (int q = 0; q < nsteps; ++q) {
+      const int jj = 4 * q + kq;
+      double ar[MF_H], ai[MF_H], as[MF_H];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) cf_fma(acc[c], av, xs[jj][c]);
+      for (int h = 0; h < MF_H; ++h) {
+        cf ev = cf{0.f, 0.f};
+        if (jj < tk) ev = e.entry(rw[h], cols[jj]);
+        ar[h] = ev.re;
+        ai[h] = ev.im;
+        as[h] = (double)ev.re + (double)ev.im;
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const cf xv = xs[jj][t * 16 + lc];
+        const double xr = xv.re, xi = xv.im, xsum = (double)xv.re + (double)xv.im;
+#pragma unroll
+        for (int h = 0; h < MF_H; ++h) {
+          p1[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[h], xr, p1[h][t], 0, 0, 0);
+          p2[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[h], xi, p2[h][t], 0, 0, 0);
+          p3[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[h], xsum, p3[h][t], 0, 0, 0);
+        }
       }
     }
   }
-  if (i < nout) {
-    bf_c64* yz = Y + (int64_t)z * ycols * ldy;   // split-K partial plane
-    for (int c = 0; c < nc; ++c)
-      yz[((int64_t)g * ncols + c0 + c) * ldy + i] = bf_c64{acc[c].re, acc[c].im};
+  // accumulator layout of a 16x16 f64 MFMA tile on gfx950: lane l, register
+  // v holds row l / 16 + 4 v, column l % 16 (A[i][k] sits in lane i + 16 k,
+  // B[k][j] in lane j + 16 k)
+  Tout* yz = Y + (int64_t)z * ycols * ldy + ((int64_t)g * ncols + c0) * ldy;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int c = t * 16 + lc;
+    if (c < nc) {
+#pragma unroll
+      for (int h = 0; h < MF_H; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = row0 + 16 * h + kq + 4 * v;
+          if (r < nout) {
+            Tout o;
+            o.re = p1[h][t][v] - p2[h][t][v];
+            o.im = p3[h][t][v] - p1[h][t][v] - p2[h][t][v];
+            yz[(int64_t)c * ldy + r] = o;
+          }
+        }
+    }
   }
 }
 
-// Y(:, col) = sum_z P[z](:, col) over the split planes (fixed order).
-__global__ void split_reduce_kernel(const bf_c64* __restrict__ P, int64_t nout, int64_t ycols,
+// Y(:, col) = sum_z P[z](:, col) over the FP64 split planes (fixed order).
+__global__ void split_reduce_kernel(const bf_c128* __restrict__ P, int64_t nout, int64_t ycols,
                                     int32_t nsplit, bf_c64* __restrict__ Y, int64_t ldy) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nout * ycols) return;
   int64_t r = idx % nout, c = idx / nout;
-  float re = 0.f, im = 0.f;
+  double re = 0.0, im = 0.0;
   for (int z = 0; z < nsplit; ++z) {
-    bf_c64 v = P[((int64_t)z * ycols + c) * nout + r];
+    bf_c128 v = P[((int64_t)z * ycols + c) * nout + r];
     re += v.re;
     im += v.im;
   }
-  Y[c * ldy + r] = bf_c64{re, im};
+  Y[c * ldy + r] = bf_c64{(float)re, (float)im};
 }
 
-template <class E, int NC>
-static void launch_nc(const E& e, int64_t nout, const bf_c64* X, int64_t ldx, int32_t ncols,
-                      int32_t c0, bf_c64* Y, int64_t ldy, int64_t ycols, const int64_t* seg_dev,
-                      int32_t nseg, int32_t nsplit, hipStream_t s) {
-  dim3 grid((unsigned)((nout + MF_THREADS - 1) / MF_THREADS), (unsigned)nseg, (unsigned)nsplit);
-  hipLaunchKernelGGL((matfree_kernel<E, NC>), grid, dim3(MF_THREADS), 0, s, e, nout, X, ldx,
-                     ncols, c0, Y, ldy, ycols, seg_dev, nsplit);
+template <class E, int NT, typename Tout>
+static void launch_nt(const E& e, int64_t nout, const bf_c64* X, int64_t ldx, int32_t ncols,
+                      int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
+                      const int64_t* seg_dev, int32_t nseg, int32_t nsplit, hipStream_t s) {
+  dim3 grid((unsigned)((nout + MF_ROWS - 1) / MF_ROWS), (unsigned)nseg, (unsigned)nsplit);
+  // algorithmic work of this launch: every (output row, inner point) pair
+  // once per column of the chunk; bytes = the X chunk read and Y written once
+  const double nc = (double)std::min<int32_t>(16 * NT, width);
+  const double nin = (double)g_matfree_nin;
+  ProfScope ps(BF_KC_MATFREE, s, 8.0 * (double)nout * nin * nc,
+               8.0 * nc * (nin + (double)nout * nseg));
+  hipLaunchKernelGGL((matfree_kernel<E, NT, Tout>), grid, dim3(MF_THREADS), 0, s, e, nout, X, ldx,
+                     ncols, c0, width, Y, ldy, ycols, seg_dev, nsplit);
   BF_HIP(hipGetLastError());
+}
+
+template <class E, typename Tout>
+static void launch_chunk(const E& e, int64_t nout, const bf_c64* X, int64_t ldx, int32_t ncols,
+                         int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
+                         const int64_t* seg_dev, int32_t nseg, int32_t nsplit, hipStream_t s) {
+  if (width <= 16)
+    launch_nt<E, 1>(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
+  else if (width <= 32)
+    launch_nt<E, 2>(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
+  else
+    launch_nt<E, 3>(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
 }
 
 template <class E>
@@ -196,7 +309,7 @@ static void run_matfree(const E& e, int64_t nout, int64_t nin, const bf_c64* X, 
   }
   // split-K so that row tiles x groups x splits reaches ~2048 workgroups,
   // keeping at least 512 inner points per split.
-  int64_t tiles = ((nout + MF_THREADS - 1) / MF_THREADS) * nseg;
+  int64_t tiles = ((nout + MF_ROWS - 1) / MF_ROWS) * nseg;
   int64_t want = (2048 + tiles - 1) / tiles;
   int64_t cap = std::max<int64_t>(1, maxlen / 512);
   int32_t nsplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, cap, 64}));
@@ -205,33 +318,23 @@ static void run_matfree(const E& e, int64_t nout, int64_t nin, const bf_c64* X, 
   BF_HIP(hipMemcpyAsync(seg_dev.p, segv.data(), segv.size() * sizeof(int64_t),
                         hipMemcpyHostToDevice, s));
   const int64_t ycols = (int64_t)nseg * ncols;
-  DevBuf<bf_c64> part;
-  bf_c64* Yk = Y;
-  int64_t ldk = ldy;
-  if (nsplit > 1) {
-    part = DevBuf<bf_c64>((size_t)nsplit * ycols * nout, s);
-    Yk = part.p;
-    ldk = nout;
-  }
-  for (int64_t c0 = 0; c0 < ncols; c0 += 64) {
-    int64_t rem = ncols - c0;
-    if (rem <= 8)
-      launch_nc<E, 8>(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, Yk, ldk, ycols, seg_dev.p, nseg, nsplit, s);
-    else if (rem <= 16)
-      launch_nc<E, 16>(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, Yk, ldk, ycols, seg_dev.p, nseg, nsplit, s);
-    else if (rem <= 24)
-      launch_nc<E, 24>(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, Yk, ldk, ycols, seg_dev.p, nseg, nsplit, s);
-    else if (rem <= 32)
-      launch_nc<E, 32>(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, Yk, ldk, ycols, seg_dev.p, nseg, nsplit, s);
-    else if (rem <= 40)
-      launch_nc<E, 40>(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, Yk, ldk, ycols, seg_dev.p, nseg, nsplit, s);
-    else if (rem <= 48)
-      launch_nc<E, 48>(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, Yk, ldk, ycols, seg_dev.p, nseg, nsplit, s);
+  g_matfree_nin = segv[nseg] - segv[0];
+  DevBuf<bf_c128> part;
+  if (nsplit > 1) part = DevBuf<bf_c128>((size_t)nsplit * ycols * nout, s);
+  const int64_t nchunk = (ncols + 47) / 48;
+  const int64_t cw = (ncols + nchunk - 1) / nchunk;   // balanced widths <= 48
+  for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
+    const int32_t w = (int32_t)std::min<int64_t>(cw, ncols - c0);
+    if (nsplit > 1)
+      launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, part.p, nout, ycols, seg_dev.p,
+                   nseg, nsplit, s);
     else
-      launch_nc<E, 64>(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, Yk, ldk, ycols, seg_dev.p, nseg, nsplit, s);
+      launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols, seg_dev.p, nseg,
+                   nsplit, s);
   }
   if (nsplit > 1) {
     int64_t tot = nout * ycols;
+    ProfScope ps(BF_KC_OTHER, s, 0.0, 16.0 * nsplit * tot + 8.0 * tot);
     hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                        part.p, nout, ycols, nsplit, Y, ldy);
     BF_HIP(hipGetLastError());
@@ -250,10 +353,10 @@ void launch_fio(int64_t n, const double* cx_dev, int adjoint, const bf_c64* X, i
                 int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
                 hipStream_t s) {
   if (!adjoint) {
-    FioEntry e{n, cx_dev, 1.0f};
+    FioEntry e{n, 1.0 / (double)n, cx_dev};
     run_matfree(e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   } else {
-    FioAdjEntry e{n, cx_dev};
+    FioAdjEntry e{n, 1.0 / (double)n, cx_dev};
     run_matfree(e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   }
 }

@@ -71,6 +71,7 @@ struct PlanBuilder {
     d.nterm = 0;
     for (int q = 0; q < nt; ++q)
       if (t[q].K > 0) d.t[d.nterm++] = t[q];
+    for (int q = 0; q < d.nterm; ++q) cur.macs += (double)M * d.t[q].K;
     descs.push_back(d);
     cur.count++;
     cur.maxM = std::max(cur.maxM, M);
@@ -108,6 +109,7 @@ void finish(PlanBuilder& pb, ApplyPlan& plan, int64_t tmp_rows, hipStream_t s,
     size_t cnt = std::min<size_t>(60000, pb.packs.size() - o);
     std::vector<PackDesc> part(pb.packs.begin() + o, pb.packs.begin() + o + cnt);
     auto dd = upload(part, s, st);
+    ProfScope ps(BF_KC_OTHER, s, 0.0, 0.0);
     launch_pack_c64(dd.p, (int32_t)cnt, plan.G.p, s);
   }
   BF_HIP(hipStreamSynchronize(s));
@@ -254,8 +256,15 @@ void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
   DevBuf<bf_c64> t1((size_t)P.tmp_rows * ncols, s), t2((size_t)P.tmp_rows * ncols, s);
   const bf_c64* bufs[4] = {X, t1.p, t2.p, Y};
   const int64_t lds[4] = {ldx, P.tmp_rows, P.tmp_rows, ldy};
+  const int64_t rin = trans ? F->m : F->n, rout = trans ? F->n : F->m;
   for (size_t k = 0; k < P.stages.size(); ++k) {
     const Stage& st = P.stages[k];
+    // algorithmic bytes: this stage's factor entries once, plus the caller's
+    // input (first stage) and output (last stage); intermediates excluded
+    double by = 8.0 * st.macs;
+    if (k == 0) by += 8.0 * (double)rin * ncols;
+    if (k + 1 == P.stages.size()) by += 8.0 * (double)rout * ncols;
+    ProfScope ps(BF_KC_APPLY, s, 8.0 * st.macs * ncols, by);
     launch_apply_stage(P.desc.p + st.off, st.count, P.G.p, bufs, lds, ncols, st.maxM, s);
   }
 }

@@ -71,6 +71,7 @@ void launch_gauss_samples(bf_c64* X, int64_t rows, int64_t ncols, int32_t level,
   if (rows <= 0 || ncols <= 0) return;
   BF_CHECK(ncols <= 65535, BF_ERANK, "sample width too large");
   dim3 grid((unsigned)((rows + 255) / 256), (unsigned)ncols);
+  ProfScope ps(BF_KC_OTHER, s, 0.0, 8.0 * rows * ncols);
   hipLaunchKernelGGL(gauss_samples_kernel, grid, dim3(256), 0, s, X, rows, ncols, level,
                      tags_dev, widths_dev, seed);
   BF_HIP(hipGetLastError());
