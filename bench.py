@@ -49,6 +49,26 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic():
+    """HBM bytes per launch of the black-box kernel from the committed rocprofv3
+    byte-counter summary, if it was taken on the current kernel source."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "matfree_segkernel_n65536_hbm_bytes.md")
+    src = os.path.join(ROOT, "paper_2002_03400_amd", "csrc", "matfree.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line)
+    if vals.get("source_sha256 paper_2002_03400_amd/csrc/matfree.hip", "").strip() != sha:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def pct(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -182,7 +202,8 @@ def main():
             "peak": PEAK_FP64_VECTOR_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
             "avg_launch_ms": mf["ms"] / max(1, mf["launches"]),
             "launches": mf["launches"],
         },

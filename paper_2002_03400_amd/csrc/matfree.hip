@@ -4,7 +4,7 @@
 // Y[i, g*ncols + c] = sum_{j in seg_g} E(i, j) X[j, c]    (Sec. 4.1 structured
 // samples: group g is the product with the random block living on node g).
 //
-// Layout: one workgroup of 4 waves owns 128 output rows of one group, up to
+// Layout: one workgroup of 8 waves owns 128 output rows of one group, up to
 // 48 columns, and one slice of the group's inner range (split-K when there
 // are too few row tiles to fill 256 CUs); chunks of TK inner points (their
 // coordinates and the TK x 64 block of X) are staged in LDS.  Split-K
@@ -21,7 +21,7 @@
 
 namespace bf {
 
-constexpr int MF_THREADS = 256;
+constexpr int MF_THREADS = 512;   // 8 waves share each staged chunk of X
 constexpr int MF_TK = 64;
 // inner length of the product being launched (for the profiler's accounting)
 static thread_local int64_t g_matfree_nin = 0;
@@ -147,8 +147,8 @@ struct DenseEntry {
 // P3 = (Re a + Im a)(Re x + Im x);  Re y = P1 - P2, Im y = P3 - P1 - P2.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-constexpr int MF_H = 1;                // 16-row tiles per wave
-constexpr int MF_ROWS = 64 * MF_H;     // output rows per workgroup (4 waves)
+constexpr int MF_H = 1;                                  // 16-row tiles per wave
+constexpr int MF_ROWS = (MF_THREADS / 64) * 16 * MF_H;   // output rows per workgroup
 
 template <class E, int NT, typename Tout>
 __global__ __launch_bounds__(MF_THREADS) void matfree_kernel(
@@ -157,7 +157,9 @@ __global__ __launch_bounds__(MF_THREADS) void matfree_kernel(
     const int64_t* __restrict__ seg, int32_t nsplit) {
   constexpr int NC = 16 * NT;
   __shared__ typename E::Col cols[MF_TK];
-  __shared__ cf xs[MF_TK][NC];
+  // row stride NC + 1: consecutive inner points (the staging write pattern)
+  // land in distinct banks
+  __shared__ cf xs[MF_TK][NC + 1];
   const int g = blockIdx.y;
   const int z = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
