@@ -175,6 +175,51 @@ const char* bf_strerror(int code);
 const char* bf_last_error(void);
 
 /* ---------------------------------------------------------------------------
+ * Request engine (serving): constructions and applies of many requests run
+ * concurrently on `slots` device streams, each driven by a host worker
+ * thread.  A request is admitted when a slot is idle and its estimated device
+ * footprint fits under `hbm_budget` next to the requests in flight (first fit
+ * in arrival order; a request passed over 8 times holds back later ones until
+ * it fits; a request larger than the budget runs when the device is otherwise
+ * idle).  An apply waits for the construction it references.  Factors stay on
+ * the device until their ticket is released.  Results are independent of the
+ * mix: every random matrix is keyed by its own request's seed, and every
+ * reduction has a fixed order.  The calls are thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct bf_server bf_server;
+typedef struct {
+  int32_t slots;        /* concurrent requests (streams); 0 = 4 */
+  int32_t reserved;     /* 0 */
+  int64_t hbm_budget;   /* bytes; 0 = 64 GiB */
+} bf_server_opts;
+typedef struct {
+  int32_t status;       /* BF_OK or the request's error code */
+  int32_t reserved;
+  int64_t arrival_ns;   /* submit, start, completion: ns since server creation */
+  int64_t start_ns;
+  int64_t finish_ns;
+  int64_t footprint;    /* device bytes reserved for admission */
+} bf_request_info;
+int bf_server_create(const bf_server_opts* opts, bf_server** out);
+/* Finishes every request that can still run, then frees all resident factors. */
+int bf_server_destroy(bf_server* S);
+/* Queue a construction; the operator (its callbacks and user data) must stay
+   valid until the request completes.  Writes the request's ticket. */
+int bf_server_submit_construct(bf_server* S, const bf_operator* op, double tol, int64_t leaf,
+                               const bf_opts* opts, int64_t* ticket);
+/* Queue Y = F X (trans 0) or F^H X (trans 1) with the factors of construction
+   `factors_ticket`; X, Y are device buffers that must stay valid until done. */
+int bf_server_submit_apply(bf_server* S, int64_t factors_ticket, int trans, const bf_c64* X,
+                           int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy, int64_t* ticket);
+/* Block until the request is done; returns its status (info may be NULL). */
+int bf_server_wait(bf_server* S, int64_t ticket, bf_request_info* info);
+/* Borrow the factors of a completed construction (valid until released). */
+int bf_server_factors(bf_server* S, int64_t ticket, const bf_factors** F);
+/* Forget a finished request; for a construction, free its factors (refused
+   while applies that reference it are queued or running). */
+int bf_server_release(bf_server* S, int64_t ticket);
+
+/* ---------------------------------------------------------------------------
  * Profiling: while enabled, every launch of the library's kernels is
  * bracketed by HIP events recorded on the stream the kernel runs on, and
  * its algorithmic work is counted (flops of the complex multiply-adds, bytes

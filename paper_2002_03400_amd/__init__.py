@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libbf.so")
 
 __all__ = ["BFError", "lib", "Operator", "Factors", "construct", "segkernel", "fio", "dense",
            "from_factors", "compose", "import_factors", "gauss", "cpqr_batched", "lsq_batched",
-           "num_levels", "LIB_PATH", "profile_start", "profile_stop"]
+           "num_levels", "LIB_PATH", "profile_start", "profile_stop", "Server"]
 
 
 class BFError(RuntimeError):
@@ -57,6 +57,15 @@ class bf_kernel_stats(C.Structure):
 KERNEL_CLASSES = ("matfree", "apply", "cpqr", "chain", "lsq", "other")
 
 
+class bf_server_opts(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("reserved", C.c_int32), ("hbm_budget", C.c_int64)]
+
+
+class bf_request_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("arrival_ns", C.c_int64),
+                ("start_ns", C.c_int64), ("finish_ns", C.c_int64), ("footprint", C.c_int64)]
+
+
 class bf_info(C.Structure):
     _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("L", C.c_int32), ("lm", C.c_int32),
                 ("max_rank", C.c_int32), ("v_iters", C.c_int32), ("u_iters", C.c_int32),
@@ -82,6 +91,15 @@ SIGNATURES = {
     "bf_free": (C.c_int, [_P, _P]),
     "bf_strerror": (C.c_char_p, [C.c_int]),
     "bf_last_error": (C.c_char_p, []),
+    "bf_server_create": (C.c_int, [C.POINTER(bf_server_opts), C.POINTER(_P)]),
+    "bf_server_destroy": (C.c_int, [_P]),
+    "bf_server_submit_construct": (C.c_int, [_P, C.POINTER(bf_operator), C.c_double, C.c_int64,
+                                             C.POINTER(bf_opts), C.POINTER(C.c_int64)]),
+    "bf_server_submit_apply": (C.c_int, [_P, C.c_int64, C.c_int, _P, C.c_int64, C.c_int64, _P,
+                                         C.c_int64, C.POINTER(C.c_int64)]),
+    "bf_server_wait": (C.c_int, [_P, C.c_int64, C.POINTER(bf_request_info)]),
+    "bf_server_factors": (C.c_int, [_P, C.c_int64, C.POINTER(_P)]),
+    "bf_server_release": (C.c_int, [_P, C.c_int64]),
     "bf_profile_start": (C.c_int, []),
     "bf_profile_stop": (C.c_int, [C.POINTER(bf_kernel_stats)]),
     "bf_gauss": (C.c_int, [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
@@ -325,6 +343,85 @@ def import_factors(m, n, leaf, kU, kV, data, stream=None) -> Factors:
     _check(lib().bf_import(m, n, leaf, kU.ctypes.data_as(_I32P), kV.ctypes.data_as(_I32P),
                            data.ctypes.data, len(data), _stream(stream), C.byref(h)), "bf_import")
     return Factors(h, leaf)
+
+
+class _Borrowed(Factors):
+    """Factors owned by a Server (not freed by this handle)."""
+
+    def close(self, stream=None):
+        self._h = None
+
+
+class Server:
+    """Request engine: concurrent constructions and applies on `slots` streams
+    with admission by estimated device footprint (see include/bf.h)."""
+
+    def __init__(self, slots=4, hbm_budget=0):
+        h = C.c_void_p()
+        _check(lib().bf_server_create(C.byref(bf_server_opts(slots, 0, int(hbm_budget))),
+                                      C.byref(h)), "bf_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit_construct(self, op: Operator, tol, leaf, p=2, r0=4, seed=0, max_rank=0):
+        t = C.c_int64()
+        o = bf_opts(p, r0, max_rank, 0, seed)
+        _check(lib().bf_server_submit_construct(self._h, C.byref(op._op), float(tol), int(leaf),
+                                                C.byref(o), C.byref(t)), "submit_construct")
+        self._keep[t.value] = (op,)
+        return t.value
+
+    def submit_apply(self, ticket, X, trans=False, out=None):
+        X = _dev_c64(X)
+        X, ldx = _colmajor(X)
+        F = self._keep[ticket][0]
+        rows_out = F.n if trans else F.m
+        if out is None:
+            out = _empty_colmajor(rows_out, X.shape[1], X.dtype, X.device)
+        Y, ldy = _colmajor(out)
+        # the device buffers are read/written on a worker stream: order them
+        # after the caller's pending work on its own stream
+        _torch().cuda.current_stream().synchronize()
+        t = C.c_int64()
+        _check(lib().bf_server_submit_apply(self._h, ticket, int(bool(trans)), X.data_ptr(), ldx,
+                                            X.shape[1], Y.data_ptr(), ldy, C.byref(t)),
+               "submit_apply")
+        self._keep[t.value] = (X, Y)
+        return t.value
+
+    def wait(self, ticket):
+        """Block until done; returns (status, info dict).  Raises on failure."""
+        i = bf_request_info()
+        rc = lib().bf_server_wait(self._h, ticket, C.byref(i))
+        info = {f: getattr(i, f) for f, _ in bf_request_info._fields_}
+        if rc != 0:
+            raise BFError(rc, f"request {ticket}")
+        return info
+
+    def result(self, ticket):
+        """Output of a finished apply request (the Y tensor)."""
+        return self._keep[ticket][1]
+
+    def factors(self, ticket) -> Factors:
+        h = C.c_void_p()
+        _check(lib().bf_server_factors(self._h, ticket, C.byref(h)), "bf_server_factors")
+        return _Borrowed(h, 0)
+
+    def release(self, ticket):
+        _check(lib().bf_server_release(self._h, ticket), "bf_server_release")
+        self._keep.pop(ticket, None)
+
+    def close(self):
+        if self._h:
+            lib().bf_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_start():

@@ -1,0 +1,94 @@
+"""Request engine on the GPU: results are the same alone and in a concurrent
+mix (bitwise), applies against resident factors, failure propagation."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import operators as ops
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2002_03400_amd as m
+    m.lib()
+    return m
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.asarray(x, np.complex64)).cuda()
+
+
+def test_mix_equals_alone(bf):
+    import torch
+    specs = [(2048, 8.0, 1e-6, 11), (3000, 4.0, 1e-4, 12), (4096, 16.0, 1e-6, 13),
+             (2500, 6.0, 1e-6, 14), (5000, 8.0, 1e-4, 15), (2048, 12.0, 1e-4, 16)]
+    opsl = []
+    for n, ppw, tol, seed in specs:
+        g = wl.segment_pair(n, ppw=ppw)
+        opsl.append(bf.segkernel(g.targets, g.sources, g.k))
+    say("alone")
+    alone = []
+    for op, (n, ppw, tol, seed) in zip(opsl, specs):
+        F = bf.construct(op, tol, 64, seed=seed)
+        alone.append(F.export())
+        F.close()
+    say("mix")
+    S = bf.Server(slots=4)
+    tickets = [S.submit_construct(op, tol, 64, seed=seed) for op, (n, ppw, tol, seed) in zip(opsl, specs)]
+    for t, a in zip(tickets, alone):
+        info = S.wait(t)
+        assert info["finish_ns"] >= info["start_ns"] >= info["arrival_ns"]
+        got = S.factors(t).export()
+        assert np.array_equal(got, a)
+    # applies against resident factors, from several requests at once
+    X = [_t(wl.test_columns(n, 3, 5)) for (n, _, _, _) in specs]
+    at = [S.submit_apply(t, x) for t, x in zip(tickets, X)]
+    for k, (t, a_t) in enumerate(zip(tickets, at)):
+        S.wait(a_t)
+        ref = S.factors(t).apply(X[k])
+        torch.cuda.synchronize()
+        assert torch.equal(S.result(a_t), ref)
+    S.close()
+
+
+def test_failed_construction_fails_its_applies(bf):
+    g = wl.segment_pair(512, ppw=8.0)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    S = bf.Server(slots=2)
+    t = S.submit_construct(op, 1e-6, 64, seed=1, max_rank=2)     # rank cap -> BF_ERANK
+    a = S.submit_apply(t, _t(np.ones((512, 1))))
+    with pytest.raises(bf.BFError) as e1:
+        S.wait(t)
+    assert e1.value.code == -4
+    with pytest.raises(bf.BFError):
+        S.wait(a)
+    S.close()
+
+
+def test_budget_serializes_but_completes(bf):
+    """A budget smaller than one request still runs every request (alone)."""
+    g = wl.segment_pair(1024, ppw=8.0)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    S = bf.Server(slots=3, hbm_budget=1 << 20)
+    ts = [S.submit_construct(op, 1e-6, 32, seed=s) for s in range(4)]
+    spans = []
+    for t in ts:
+        i = S.wait(t)
+        spans.append((i["start_ns"], i["finish_ns"]))
+    spans.sort()
+    for (s0, f0), (s1, f1) in zip(spans, spans[1:]):
+        assert s1 >= f0          # never two in flight under this budget
+    S.close()

@@ -91,3 +91,21 @@ def test_compose_op():
     X = np.random.default_rng(2).standard_normal((40, 2)) + 0j
     np.testing.assert_allclose(c.matvec(X), o1.dense() @ (o2.dense() @ X), atol=1e-10)
     np.testing.assert_allclose(c.rmatvec(X), (o1.dense() @ o2.dense()).conj().T @ X, atol=1e-10)
+
+
+def test_serving_streams_are_seeded_and_well_formed():
+    a = wl.mixed_stream(200, rate=10.0, seed=3)
+    b = wl.mixed_stream(200, rate=10.0, seed=3)
+    assert a == b
+    ts = [r.t for r in a]
+    assert ts == sorted(ts) and ts[0] > 0
+    cons = [i for i, r in enumerate(a) if r.kind == "construct"]
+    assert 0.55 < len(cons) / len(a) < 0.85
+    for i, r in enumerate(a):
+        if r.kind == "construct":
+            assert 2048 <= r.n <= 65536 and 4.0 <= r.ppw <= 16.0 and r.tol in (1e-4, 1e-6)
+        else:
+            assert 1 <= r.nrhs <= 64 and a[r.target].kind == "construct" and r.target < i
+    p = wl.poisson_stream(50, rate=2.0, seed=1)
+    gaps = np.diff([0.0] + [r.t for r in p])
+    assert abs(gaps.mean() - 0.5) < 0.2 and len({r.seed for r in p}) == 50

@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "SegmentGeometry", "segment_pair", "segment_triple", "fio_params",
     "test_columns", "ExactButterflyFactors", "exact_butterfly_factors",
-    "node_range_host",
+    "node_range_host", "Request", "poisson_stream", "mixed_stream",
 ]
 
 
@@ -137,3 +137,45 @@ def exact_butterfly_factors(L: int, r: int, seed: int = 7, leaf: int = 8) -> Exa
     B = {(i, j): (rng.standard_normal((r, r)) + 1j * rng.standard_normal((r, r))) / math.sqrt(2)
          for i in range(1 << lm) for j in range(1 << (L - lm))}
     return ExactButterflyFactors(L, r, n, U, V, R, W, B)
+
+
+@dataclass
+class Request:
+    """One request of a synthetic serving stream."""
+    t: float            # arrival time (s) after the stream starts
+    kind: str           # "construct" or "apply"
+    n: int = 0          # construct: problem size (m = n)
+    ppw: float = 8.0    # construct: points per wavelength
+    tol: float = 1e-6   # construct: truncation tolerance
+    seed: int = 0       # construct: key of its random matrices
+    nrhs: int = 0       # apply: right-hand sides
+    target: int = -1    # apply: index (in the stream) of the construction it uses
+
+
+def poisson_stream(nreq: int, rate: float, seed: int = 4242, n: int = 65536, ppw: float = 8.0,
+                   tol: float = 2e-7) -> list:
+    """Constructions of one fixed size arriving as a Poisson process."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    return [Request(float(t[i]), "construct", n, ppw, tol, 3 + i) for i in range(nreq)]
+
+
+def mixed_stream(nreq: int = 256, rate: float = 20.0, seed: int = 4242, nmin: int = 2048,
+                 nmax: int = 65536, tols=(1e-4, 1e-6), frac_construct: float = 0.7) -> list:
+    """Serving mix: Poisson arrivals; 70% constructions with n log-uniform in
+    [nmin, nmax], 4..16 points per wavelength and a tolerance drawn from
+    `tols`; 30% applies of 1..64 right-hand sides against a construction that
+    arrived earlier (uniformly chosen)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    out, built = [], []
+    for i in range(nreq):
+        if not built or rng.uniform() < frac_construct:
+            n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+            out.append(Request(float(t[i]), "construct", n, float(rng.uniform(4.0, 16.0)),
+                               float(tols[int(rng.integers(len(tols)))]), 100 + i))
+            built.append(i)
+        else:
+            out.append(Request(float(t[i]), "apply", nrhs=int(rng.integers(1, 65)),
+                               target=int(built[int(rng.integers(len(built)))])))
+    return out
