@@ -412,7 +412,8 @@ int bf_export(const bf_factors* F, bf_c128* data, int64_t* count) {
       std::vector<PackDesc> d;
       int64_t off = 0;
       for (auto& b : blocks) {
-        if ((int64_t)b.rows * b.cols > 0) d.push_back(PackDesc{b.p, off, b.rows, 0, b.rows, b.cols, 0, 0});
+        if ((int64_t)b.rows * b.cols > 0)
+          d.push_back(PackDesc{b.p, off, b.rows, 0, b.rows, b.cols, 0, 1, b.rows, 0});
         off += (int64_t)b.rows * b.cols;
       }
       {
@@ -530,10 +531,11 @@ int bf_free(bf_factors* F, void* stream) {
   if (!F) return BF_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   for (auto& b : F->store) b.s = s;
-  F->fwd.G.s = s;
-  F->fwd.desc.s = s;
-  F->adj.G.s = s;
-  F->adj.desc.s = s;
+  for (auto* P : {&F->fwd, &F->adj}) {
+    P->G.s = s;
+    P->blks.s = s;
+    P->rows.s = s;
+  }
   delete F;
   return BF_OK;
 }

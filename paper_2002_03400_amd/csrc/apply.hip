@@ -12,53 +12,155 @@
 
 namespace bf {
 
-constexpr int AP_COLS = 64;
-
+// Two work mappings, by right-hand-side count:
+//  * ncols <= 4 (streaming): a group of 16 lanes per output row splits the
+//    inner dimension, so each row of the packed block is read as contiguous
+//    bytes; partial sums are combined with shuffles inside the group.
+//  * ncols > 4 (blocked): one workgroup per (output block, 64-column chunk);
+//    the packed block and the input chunk are staged in LDS and each thread
+//    accumulates 4 rows of one column.
 struct ApplyBufs {
   bf_c64* p[4];
   int64_t ld[4];
 };
 
-__global__ __launch_bounds__(256) void apply_stage_kernel(const ApplyDesc* __restrict__ descs,
-                                                          const bf_c64* __restrict__ G,
-                                                          ApplyBufs B, int64_t ncols) {
-  const ApplyDesc d = descs[blockIdx.x];
-  const int64_t c0 = (int64_t)blockIdx.y * AP_COLS;
-  if (c0 >= ncols) return;
-  const int cw = (int)((ncols - c0 < AP_COLS) ? ncols - c0 : AP_COLS);
-  const int M = d.M;
-  for (int idx = threadIdx.x; idx < M * cw; idx += blockDim.x) {
-    const int r = idx % M;
-    const int64_t c = c0 + idx / M;
-    cf acc = {0.f, 0.f};
-    for (int t = 0; t < d.nterm; ++t) {
-      const ApplyTerm T = d.t[t];
-      const bf_c64* g = G + T.g_off + r;
-      const bf_c64* in = B.p[T.in_buf] + c * B.ld[T.in_buf] + T.in_row;
-      for (int k = 0; k < T.K; ++k) {
-        bf_c64 gv = g[(int64_t)k * M];
-        bf_c64 xv = in[k];
-        cf_fma(acc, cf{gv.re, gv.im}, cf{xv.re, xv.im});
-      }
+constexpr int AP_SMALL = 4;
+
+// ncols <= 4: a group of 16 lanes per output row; the row's record holds
+// every address it needs (one dependent load), the inner loop is unrolled so
+// the factor and input loads of a row issue together.
+__global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __restrict__ rows,
+                                                           int32_t nrows,
+                                                           const bf_c64* __restrict__ G,
+                                                           ApplyBufs B, int32_t ncols) {
+  const int q = threadIdx.x & 15;
+  const int64_t R = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const bool live = R < nrows;
+  const ApplyRowRec rr = rows[live ? R : 0];
+  const int KK = live ? rr.KK : 0;
+  const bf_c64* g = G + rr.g;
+  const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
+  const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
+  const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
+  cf acc[AP_SMALL];
+#pragma unroll
+  for (int c = 0; c < AP_SMALL; ++c) acc[c] = cf{0.f, 0.f};
+  for (int kb = 0; kb < KK; kb += 64) {
+    bf_c64 gv[4], xv[4][AP_SMALL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = kb + q + 16 * u;
+      const bool kv = k < KK;
+      gv[u] = kv ? g[k] : bf_c64{0.f, 0.f};
+      const bf_c64* inp = k < rr.K0 ? in0 + k : in1 + k;
+      const int64_t ldk = k < rr.K0 ? ld0 : ld1;
+#pragma unroll
+      for (int c = 0; c < AP_SMALL; ++c)
+        xv[u][c] = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
     }
-    B.p[d.out_buf][c * B.ld[d.out_buf] + d.out_row + r] = bf_c64{acc.re, acc.im};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < AP_SMALL; ++c)
+        cf_fma(acc[c], cf{gv[u].re, gv[u].im}, cf{xv[u][c].re, xv[u][c].im});
+  }
+#pragma unroll
+  for (int c = 0; c < AP_SMALL; ++c) {
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+      acc[c].re += __shfl_xor(acc[c].re, off, 16);
+      acc[c].im += __shfl_xor(acc[c].im, off, 16);
+    }
+  }
+  if (live && q == 0) {
+    bf_c64* out = B.p[rr.out_buf] + rr.out;
+    const int64_t ldo = B.ld[rr.out_buf];
+#pragma unroll
+    for (int c = 0; c < AP_SMALL; ++c)
+      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{acc[c].re, acc[c].im};
   }
 }
 
-void launch_apply_stage(const ApplyDesc* d_dev, int32_t ndesc, const bf_c64* G,
+constexpr int AP_CW = 64;   // columns per workgroup in the blocked mapping
+
+__global__ __launch_bounds__(256) void apply_blocked_kernel(const ApplyBlk* __restrict__ blks,
+                                                            const bf_c64* __restrict__ G,
+                                                            ApplyBufs B, int64_t ncols) {
+  extern __shared__ cf lds_ap[];
+  const ApplyBlk bk = blks[blockIdx.x];
+  const int64_t c0 = (int64_t)blockIdx.y * AP_CW;
+  const int cw = (int)((ncols - c0 < AP_CW) ? ncols - c0 : AP_CW);
+  const int M = bk.M, KK = bk.K0 + bk.K1;
+  cf* Gs = lds_ap;                 // M x KK, row-major
+  cf* Xs = lds_ap + M * KK;        // KK x AP_CW
+  const bf_c64* gsrc = G + bk.g_off;
+  for (int idx = threadIdx.x; idx < M * KK; idx += 256) {
+    const bf_c64 v = gsrc[idx];
+    Gs[idx] = cf{v.re, v.im};
+  }
+  for (int idx = threadIdx.x; idx < KK * AP_CW; idx += 256) {
+    const int k = idx % KK, c = idx / KK;
+    bf_c64 v = {0.f, 0.f};
+    if (c < cw) {
+      if (k < bk.K0)
+        v = B.p[bk.in_buf0][(c0 + c) * B.ld[bk.in_buf0] + bk.in_row0 + k];
+      else
+        v = B.p[bk.in_buf1][(c0 + c) * B.ld[bk.in_buf1] + bk.in_row1 + (k - bk.K0)];
+    }
+    Xs[k * AP_CW + c] = cf{v.re, v.im};
+  }
+  __syncthreads();
+  const int c = threadIdx.x % AP_CW;
+  const int rg = threadIdx.x / AP_CW;    // 0..3
+  bf_c64* out = B.p[bk.out_buf] + (c0 + c) * B.ld[bk.out_buf] + bk.out_row;
+  for (int rb = rg; rb < M; rb += 16) {  // rows rb, rb+4, rb+8, rb+12
+    cf acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = cf{0.f, 0.f};
+    for (int k = 0; k < KK; ++k) {
+      const cf x = Xs[k * AP_CW + c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = rb + 4 * j;
+        if (r < M) cf_fma(acc[j], Gs[r * KK + k], x);
+      }
+    }
+    if (c < cw) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = rb + 4 * j;
+        if (r < M) out[r] = bf_c64{acc[j].re, acc[j].im};
+      }
+    }
+  }
+}
+
+constexpr size_t AP_LDS_LIMIT = 160 * 1024;
+
+void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
+                        int32_t nrows, int32_t maxMK, int32_t maxKK, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
-                        int32_t maxM, hipStream_t s) {
-  (void)maxM;
-  if (ndesc <= 0 || ncols <= 0) return;
+                        hipStream_t s) {
+  if (nblk <= 0 || ncols <= 0) return;
   ApplyBufs B;
   for (int i = 0; i < 4; ++i) {
     B.p[i] = const_cast<bf_c64*>(bufs[i]);
     B.ld[i] = lds[i];
   }
-  int64_t ychunks = (ncols + AP_COLS - 1) / AP_COLS;
-  BF_CHECK(ychunks <= 65535, BF_EINVAL, "too many right-hand sides");
-  hipLaunchKernelGGL(apply_stage_kernel, dim3((unsigned)ndesc, (unsigned)ychunks), dim3(256), 0,
-                     s, d_dev, G, B, ncols);
+  if (ncols <= AP_SMALL) {
+    hipLaunchKernelGGL(apply_stream_kernel, dim3((unsigned)((nrows + 15) / 16)), dim3(256), 0, s,
+                       rows_dev, nrows, G, B, (int32_t)ncols);
+  } else {
+    const size_t lds_b = sizeof(cf) * ((size_t)maxMK + (size_t)maxKK * AP_CW);
+    BF_CHECK(lds_b <= AP_LDS_LIMIT, BF_ERANK, "apply block too large for LDS");
+    if (lds_b > 64 * 1024)
+      BF_HIP(hipFuncSetAttribute((const void*)apply_blocked_kernel,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_b));
+    const int64_t ych = (ncols + AP_CW - 1) / AP_CW;
+    BF_CHECK(ych <= 65535, BF_EINVAL, "too many right-hand sides");
+    hipLaunchKernelGGL(apply_blocked_kernel, dim3((unsigned)nblk, (unsigned)ych), dim3(256), lds_b,
+                       s, blks_dev, G, B, ncols);
+  }
   BF_HIP(hipGetLastError());
 }
 
@@ -78,7 +180,7 @@ __global__ void pack_kernel(const PackDesc* __restrict__ descs, Tout* __restrict
     Tout o;
     o.re = v.re;
     o.im = v.im;
-    dst[d.dst_off + idx] = o;
+    dst[d.dst_off + (int64_t)r * d.dst_rs + (int64_t)k * d.dst_cs] = o;
   }
 }
 

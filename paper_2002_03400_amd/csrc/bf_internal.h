@@ -173,30 +173,36 @@ void launch_lsq(const LSDesc* d_dev, int32_t nblk, int32_t maxS, int32_t maxK, h
 // complex128 -> complex64 copy (contiguous)
 void launch_c128_to_c64(const bf_c128* in, bf_c64* out, int64_t n, hipStream_t s);
 
-// Apply stage (complex64 factors, FP32 accumulation).  Buffer ids select
-// among up to 3 base pointers given at launch (0: user input, 1/2: ping-pong
-// intermediates, 3: user output); row offsets are fixed at finalize.
-struct ApplyTerm {
-  int64_t g_off;     // element offset of this term's block G (M x K, row-major)
-  int64_t in_row;    // first row of the input block in its buffer
-  int32_t K;
-  int32_t in_buf;
-};
-struct ApplyDesc {
+// Apply stage (complex64 factors, FP32 accumulation).  Every output block of
+// a stage is out = [G_0 G_1] [in_0; in_1]: one packed row-major M x (K0+K1)
+// factor block and two input row ranges.  Buffer ids select among 4 base
+// pointers given at launch (0: caller input, 1/2: ping-pong intermediates,
+// 3: caller output); row offsets are fixed when the plan is built.
+struct ApplyBlk {
+  int64_t g_off;      // element offset of the packed block (row-major, M x (K0+K1))
   int64_t out_row;
-  int32_t M;
-  int32_t nterm;
-  int32_t out_buf;
-  int32_t pad;
-  ApplyTerm t[2];
+  int64_t in_row0, in_row1;
+  int32_t M, K0, K1;
+  int8_t out_buf, in_buf0, in_buf1, pad;
 };
-void launch_apply_stage(const ApplyDesc* d_dev, int32_t ndesc, const bf_c64* G,
+// One output row of a stage with every address it needs (few right-hand sides).
+struct ApplyRowRec {
+  int64_t g;          // element offset of the row in the packed arena
+  int64_t in0, in1;   // input row offsets (in1 already shifted by -K0)
+  int64_t out;        // output row
+  int32_t K0, KK;
+  int8_t out_buf, in_buf0, in_buf1, pad[5];
+};
+// maxMK / maxKK: largest M*(K0+K1) and K0+K1 over the stage's blocks.
+void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
+                        int32_t nrows, int32_t maxMK, int32_t maxKK, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
-                        int32_t maxM, hipStream_t s);
+                        hipStream_t s);
 
-// Gather (and optionally conjugate-transpose) factor sub-blocks into a
-// contiguous column-major arena: dst[dst_off + r + k*M] =
-//   conjT ? conj(src[(row0 + k) + r*src_ld]) : src[(row0 + r) + k*src_ld].
+// Gather (and optionally conjugate-transpose) factor sub-blocks into an
+// arena: element (r, k) of the M x K result goes to
+//   dst[dst_off + r * dst_rs + k * dst_cs],
+// taken from conjT ? conj(src[(row0 + k) + r*src_ld]) : src[(row0 + r) + k*src_ld].
 struct PackDesc {
   const bf_c128* src;
   int64_t dst_off;
@@ -205,6 +211,8 @@ struct PackDesc {
   int32_t M;
   int32_t K;
   int32_t conjT;
+  int32_t dst_rs;    // destination stride between rows
+  int32_t dst_cs;    // destination stride between columns
   int32_t pad;
 };
 void launch_pack_c64(const PackDesc* d_dev, int32_t ndesc, bf_c64* dst, hipStream_t s);

@@ -24,19 +24,21 @@ struct Block {
   int32_t rows = 0, cols = 0;
 };
 
-// One apply stage: descriptors [off, off+count) of the stage arrays.
+// One apply stage: output blocks [blk_off, blk_off + nblk) of the plan.
 struct Stage {
-  int64_t off = 0;
-  int32_t count = 0;
-  int32_t maxM = 0;
+  int64_t blk_off = 0;
+  int32_t nblk = 0;
+  int64_t row_off = 0;
+  int32_t nrows = 0;
+  int32_t maxMK = 0, maxKK = 0;
   double macs = 0;   // complex multiply-adds per right-hand side
 };
 
 struct ApplyPlan {
-  DevBuf<bf_c64> G;              // packed blocks of every stage (column-major per term)
-  DevBuf<ApplyDesc> desc;
+  DevBuf<bf_c64> G;              // packed blocks of every stage (row-major per block)
+  DevBuf<ApplyBlk> blks;         // output blocks of all stages, stage after stage
+  DevBuf<ApplyRowRec> rows;      // output rows of all stages (few right-hand sides)
   std::vector<Stage> stages;     // in execution order
-  std::vector<int> in_buf, out_buf;
   int64_t tmp_rows = 0;          // rows of each ping-pong intermediate
 };
 

@@ -34,76 +34,110 @@ LevelIndex index_level(const bf_factors* F, int l, bool col_side) {
   return ix;
 }
 
+// One term of an output block: rows [row0, ...) of factor block b, taken as
+// is (conjT = 0, an M x K slice) or conjugate-transposed (conjT = 1, the
+// K x M slice's adjoint), multiplying input rows [in_row, in_row + K).
+struct TermSpec {
+  const Block* b;
+  int row0, M, K, conjT;
+  int in_buf;
+  int64_t in_row;
+};
+
 struct PlanBuilder {
   const bf_factors* F;
-  std::vector<ApplyDesc> descs;
+  std::vector<ApplyBlk> blks;
+  std::vector<ApplyRowRec> rows;
   std::vector<PackDesc> packs;
   std::vector<Stage> stages;
-  std::vector<int> in_buf, out_buf;
   int64_t goff = 0;
   int cur_in = 0, cur_out = 1;
   Stage cur;
 
   void begin(int in, int out) {
-    cur = Stage{(int64_t)descs.size(), 0, 0};
+    cur = Stage{};
+    cur.blk_off = (int64_t)blks.size();
+    cur.row_off = (int64_t)rows.size();
     cur_in = in;
     cur_out = out;
   }
-  void end() {
-    stages.push_back(cur);
-    in_buf.push_back(cur_in);
-    out_buf.push_back(cur_out);
+  void end() { stages.push_back(cur); }
+  TermSpec term(const Block& b, int row0, int M, int K, int conjT, int64_t in_row) {
+    return TermSpec{&b, row0, M, K, conjT, cur_in, in_row};
   }
-  // term with G = conjT ? (src rows [row0, row0+K))^H : src rows [row0, row0+M)
-  ApplyTerm term(const Block& b, int row0, int M, int K, int conjT, int64_t in_row) {
-    PackDesc p{b.p, goff, b.rows, row0, M, K, conjT, 0};
-    packs.push_back(p);
-    ApplyTerm t{goff, in_row, K, cur_in};
-    goff += (int64_t)M * K;
-    return t;
-  }
-  void add(int64_t out_row, int M, const ApplyTerm* t, int nt) {
+  // out rows [out_row, out_row + M) = sum of the terms; the terms' factor
+  // slices are packed side by side into one row-major M x (K0 + K1) block
+  void add(int64_t out_row, int M, const TermSpec* t, int nt) {
     if (M <= 0) return;
-    ApplyDesc d{};
-    d.out_row = out_row;
-    d.M = M;
-    d.out_buf = cur_out;
-    d.nterm = 0;
-    for (int q = 0; q < nt; ++q)
-      if (t[q].K > 0) d.t[d.nterm++] = t[q];
-    for (int q = 0; q < d.nterm; ++q) cur.macs += (double)M * d.t[q].K;
-    descs.push_back(d);
-    cur.count++;
-    cur.maxM = std::max(cur.maxM, M);
+    const int K0 = nt > 0 ? t[0].K : 0, K1 = nt > 1 ? t[1].K : 0;
+    const int KK = K0 + K1;
+    ApplyBlk bk{};
+    bk.g_off = goff;
+    bk.out_row = out_row;
+    bk.M = M;
+    bk.K0 = K0;
+    bk.K1 = K1;
+    bk.out_buf = (int8_t)cur_out;
+    bk.in_buf0 = (int8_t)(nt > 0 ? t[0].in_buf : cur_in);
+    bk.in_row0 = nt > 0 ? t[0].in_row : 0;
+    bk.in_buf1 = (int8_t)(nt > 1 ? t[1].in_buf : bk.in_buf0);
+    bk.in_row1 = nt > 1 ? t[1].in_row : bk.in_row0;
+    int koff = 0;
+    for (int q = 0; q < nt; ++q) {
+      if (t[q].K > 0)
+        packs.push_back(PackDesc{t[q].b->p, goff + koff, t[q].b->rows, t[q].row0, M, t[q].K,
+                                 t[q].conjT, KK, 1, 0});
+      koff += t[q].K;
+    }
+    goff += (int64_t)M * KK;
+    blks.push_back(bk);
+    for (int r = 0; r < M; ++r) {
+      ApplyRowRec rr{};
+      rr.g = bk.g_off + (int64_t)r * KK;
+      rr.in0 = bk.in_row0;
+      rr.in1 = bk.in_row1 - K0;
+      rr.out = out_row + r;
+      rr.K0 = K0;
+      rr.KK = KK;
+      rr.out_buf = bk.out_buf;
+      rr.in_buf0 = bk.in_buf0;
+      rr.in_buf1 = bk.in_buf1;
+      rows.push_back(rr);
+    }
+    cur.nrows += M;
+    cur.nblk += 1;
+    cur.maxMK = std::max(cur.maxMK, M * KK);
+    cur.maxKK = std::max(cur.maxKK, KK);
+    cur.macs += (double)M * KK;
   }
 };
 
 void finish(PlanBuilder& pb, ApplyPlan& plan, int64_t tmp_rows, hipStream_t s,
             int64_t rows_in, int64_t rows_out) {
   if (validating()) {
-    const int64_t rows[4] = {rows_in, tmp_rows, tmp_rows, rows_out};
-    for (auto& d : pb.descs) {
-      BF_CHECK(d.out_row >= 0 && d.out_row + d.M <= rows[d.out_buf], BF_EINVAL,
+    const int64_t nr[4] = {rows_in, tmp_rows, tmp_rows, rows_out};
+    for (auto& b : pb.blks) {
+      BF_CHECK(b.out_row >= 0 && b.out_row + b.M <= nr[b.out_buf], BF_EINVAL,
                "bounds check failed: apply output rows");
-      for (int t = 0; t < d.nterm; ++t) {
-        BF_CHECK(d.t[t].in_row >= 0 && d.t[t].in_row + d.t[t].K <= rows[d.t[t].in_buf], BF_EINVAL,
-                 "bounds check failed: apply input rows");
-        BF_CHECK(d.t[t].g_off + (int64_t)d.M * d.t[t].K <= pb.goff, BF_EINVAL,
-                 "bounds check failed: apply factor block");
-      }
+      BF_CHECK(b.in_row0 >= 0 && b.in_row0 + b.K0 <= nr[b.in_buf0], BF_EINVAL,
+               "bounds check failed: apply input rows");
+      BF_CHECK(b.K1 == 0 || (b.in_row1 >= 0 && b.in_row1 + b.K1 <= nr[b.in_buf1]), BF_EINVAL,
+               "bounds check failed: apply input rows");
+      BF_CHECK(b.g_off + (int64_t)b.M * (b.K0 + b.K1) <= pb.goff, BF_EINVAL,
+               "bounds check failed: apply factor block");
     }
     for (auto& p : pb.packs) {
       const int64_t r = p.conjT ? (int64_t)p.row0 + p.K : (int64_t)p.row0 + p.M;
       const int64_t c = p.conjT ? p.M : p.K;
-      if (p.M > 0 && p.K > 0) check_extent(p.src, ((size_t)(c - 1) * p.src_ld + r) * sizeof(bf_c128), "pack source");
+      if (p.M > 0 && p.K > 0)
+        check_extent(p.src, ((size_t)(c - 1) * p.src_ld + r) * sizeof(bf_c128), "pack source");
     }
   }
   Staging st;
   plan.G = DevBuf<bf_c64>((size_t)std::max<int64_t>(pb.goff, 1), s);
-  plan.desc = upload(pb.descs, s, st);
+  plan.blks = upload(pb.blks, s, st);
+  plan.rows = upload(pb.rows, s, st);
   plan.stages = pb.stages;
-  plan.in_buf = pb.in_buf;
-  plan.out_buf = pb.out_buf;
   plan.tmp_rows = std::max<int64_t>(tmp_rows, 1);
   for (size_t o = 0; o < pb.packs.size(); o += 60000) {
     size_t cnt = std::min<size_t>(60000, pb.packs.size() - o);
@@ -133,7 +167,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
     pb.begin(0, a);
     for (int64_t j = 0; j < (int64_t(1) << L); ++j) {
       const Block& V = F->V[j];
-      ApplyTerm t = pb.term(V, 0, V.cols, V.rows, 1, node_lo(n, L, j));
+      TermSpec t = pb.term(V, 0, V.cols, V.rows, 1, node_lo(n, L, j));
       pb.add(iv[0].off[j], V.cols, &t, 1);
     }
     pb.end();
@@ -143,7 +177,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
         for (int64_t j = 0; j < (int64_t(1) << (L - l)); ++j) {
           const Block& Wb = F->W[l][bidx(l, i, j)];
           const int ka = F->kv(l - 1, i >> 1, 2 * j), kb = F->kv(l - 1, i >> 1, 2 * j + 1);
-          ApplyTerm t[2] = {pb.term(Wb, 0, Wb.cols, ka, 1, iv[l - 1].off[bidx(l - 1, i >> 1, 2 * j)]),
+          TermSpec t[2] = {pb.term(Wb, 0, Wb.cols, ka, 1, iv[l - 1].off[bidx(l - 1, i >> 1, 2 * j)]),
                             pb.term(Wb, ka, Wb.cols, kb, 1, iv[l - 1].off[bidx(l - 1, i >> 1, 2 * j + 1)])};
           pb.add(iv[l].off[bidx(l, i, j)], Wb.cols, t, 2);
         }
@@ -154,7 +188,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
     for (int64_t i = 0; i < (int64_t(1) << lm); ++i)
       for (int64_t j = 0; j < (int64_t(1) << (L - lm)); ++j) {
         const Block& Bb = F->B[bidx(lm, i, j)];
-        ApplyTerm t = pb.term(Bb, 0, Bb.rows, Bb.cols, 0, iv[lm].off[bidx(lm, i, j)]);
+        TermSpec t = pb.term(Bb, 0, Bb.rows, Bb.cols, 0, iv[lm].off[bidx(lm, i, j)]);
         pb.add(iu[lm].off[bidx(lm, i, j)], Bb.rows, &t, 1);
       }
     pb.end();
@@ -165,7 +199,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
         for (int64_t jc = 0; jc < (int64_t(1) << (L - l - 1)); ++jc) {
           const int64_t i = ic >> 1;
           const int Mo = F->ku(l + 1, ic, jc);
-          ApplyTerm t[2];
+          TermSpec t[2];
           for (int q = 0; q < 2; ++q) {
             const int64_t j = 2 * jc + q;
             const Block& Rb = F->R[l - lm][bidx(l, i, j)];
@@ -180,7 +214,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
     pb.begin(a, 3);
     for (int64_t i = 0; i < (int64_t(1) << L); ++i) {
       const Block& U = F->U[i];
-      ApplyTerm t = pb.term(U, 0, U.rows, U.cols, 0, iu[L].off[i]);
+      TermSpec t = pb.term(U, 0, U.rows, U.cols, 0, iu[L].off[i]);
       pb.add(node_lo(m, L, i), U.rows, &t, 1);
     }
     pb.end();
@@ -194,7 +228,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
     pb.begin(0, a);
     for (int64_t i = 0; i < (int64_t(1) << L); ++i) {
       const Block& U = F->U[i];
-      ApplyTerm t = pb.term(U, 0, U.cols, U.rows, 1, node_lo(m, L, i));
+      TermSpec t = pb.term(U, 0, U.cols, U.rows, 1, node_lo(m, L, i));
       pb.add(iu[L].off[i], U.cols, &t, 1);
     }
     pb.end();
@@ -204,7 +238,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
         for (int64_t j = 0; j < (int64_t(1) << (L - l)); ++j) {
           const Block& Rb = F->R[l - lm][bidx(l, i, j)];
           const int k1 = F->ku(l + 1, 2 * i, j >> 1), k2 = F->ku(l + 1, 2 * i + 1, j >> 1);
-          ApplyTerm t[2] = {pb.term(Rb, 0, Rb.cols, k1, 1, iu[l + 1].off[bidx(l + 1, 2 * i, j >> 1)]),
+          TermSpec t[2] = {pb.term(Rb, 0, Rb.cols, k1, 1, iu[l + 1].off[bidx(l + 1, 2 * i, j >> 1)]),
                             pb.term(Rb, k1, Rb.cols, k2, 1, iu[l + 1].off[bidx(l + 1, 2 * i + 1, j >> 1)])};
           pb.add(iu[l].off[bidx(l, i, j)], Rb.cols, t, 2);
         }
@@ -215,7 +249,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
     for (int64_t i = 0; i < (int64_t(1) << lm); ++i)
       for (int64_t j = 0; j < (int64_t(1) << (L - lm)); ++j) {
         const Block& Bb = F->B[bidx(lm, i, j)];
-        ApplyTerm t = pb.term(Bb, 0, Bb.cols, Bb.rows, 1, iu[lm].off[bidx(lm, i, j)]);
+        TermSpec t = pb.term(Bb, 0, Bb.cols, Bb.rows, 1, iu[lm].off[bidx(lm, i, j)]);
         pb.add(iv[lm].off[bidx(lm, i, j)], Bb.cols, &t, 1);
       }
     pb.end();
@@ -226,7 +260,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
         for (int64_t jp = 0; jp < (int64_t(1) << (L - l + 1)); ++jp) {
           const int64_t j = jp >> 1;
           const int Mo = F->kv(l - 1, ip, jp);
-          ApplyTerm t[2];
+          TermSpec t[2];
           for (int q = 0; q < 2; ++q) {
             const int64_t i = 2 * ip + q;
             const Block& Wb = F->W[l][bidx(l, i, j)];
@@ -241,7 +275,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
     pb.begin(a, 3);
     for (int64_t j = 0; j < (int64_t(1) << L); ++j) {
       const Block& V = F->V[j];
-      ApplyTerm t = pb.term(V, 0, V.rows, V.cols, 0, iv[0].off[j]);
+      TermSpec t = pb.term(V, 0, V.rows, V.cols, 0, iv[0].off[j]);
       pb.add(node_lo(n, L, j), V.rows, &t, 1);
     }
     pb.end();
@@ -265,7 +299,8 @@ void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
     if (k == 0) by += 8.0 * (double)rin * ncols;
     if (k + 1 == P.stages.size()) by += 8.0 * (double)rout * ncols;
     ProfScope ps(BF_KC_APPLY, s, 8.0 * st.macs * ncols, by);
-    launch_apply_stage(P.desc.p + st.off, st.count, P.G.p, bufs, lds, ncols, st.maxM, s);
+    launch_apply_stage(P.blks.p + st.blk_off, st.nblk, P.rows.p + st.row_off, st.nrows, st.maxMK,
+                       st.maxKK, P.G.p, bufs, lds, ncols, s);
   }
 }
 

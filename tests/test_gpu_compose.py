@@ -1,0 +1,64 @@
+"""Recompression of a product of two butterflies (category (ii) of Sec. 1):
+the GPU builds B1 ~ A(X0, X1) and B2 ~ A(X1, X2), then recompresses the
+composition B1 B2 with Alg. 2 using the butterfly applies as the black box."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import butterfly as obf
+from oracle import operators as ops
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2002_03400_amd as m
+    m.lib()
+    return m
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.asarray(x, np.complex64)).cuda()
+
+
+@pytest.mark.parametrize("n,leaf", [(1024, 32), (2000, 40)])
+def test_recompress_product(bf, n, leaf):
+    g01, g12 = wl.segment_triple(n, ppw=8.0)
+    tol = 1e-6
+    say("compose", n, leaf)
+    o1 = bf.segkernel(g01.targets, g01.sources, g01.k)
+    o2 = bf.segkernel(g12.targets, g12.sources, g12.k)
+    B1 = bf.construct(o1, tol, leaf, seed=21)
+    B2 = bf.construct(o2, tol, leaf, seed=22)
+    prod = bf.compose(bf.from_factors(B1), bf.from_factors(B2))
+    F = bf.construct(prod, tol, leaf, seed=23)
+    # oracle: the same pipeline in FP64
+    r1 = ops.SegmentKernelOp(g01.targets, g01.sources, g01.k)
+    r2 = ops.SegmentKernelOp(g12.targets, g12.sources, g12.k)
+    P1 = obf.construct(r1, tol, leaf, seed=21)
+    P2 = obf.construct(r2, tol, leaf, seed=22)
+    Fo = obf.construct(ops.ComposeOp(obf.FactorsOp(P1), obf.FactorsOp(P2)), tol, leaf, seed=23)
+    Om = wl.test_columns(n, 16, 1001)
+    exact = r1.matvec(r2.matvec(Om))          # the FP64 composition of the kernels
+    e_gpu = np.linalg.norm(F.apply(_t(Om)).cpu().numpy() - exact) / np.linalg.norm(exact)
+    e_or = np.linalg.norm(obf.apply(Fo, Om) - exact) / np.linalg.norm(exact)
+    say("compose errors oracle", e_or, "gpu", e_gpu, "ranks", F.stats().max_rank)
+    assert e_gpu <= 2 * e_or + 1e-6
+    # the product's adjoint through the recompressed factors
+    Z = wl.test_columns(n, 3, 7)
+    exactH = r2.rmatvec(r1.rmatvec(Z))
+    e_h = np.linalg.norm(F.apply(_t(Z), trans=True).cpu().numpy() - exactH) / np.linalg.norm(exactH)
+    assert e_h <= 2 * e_or + 1e-6
