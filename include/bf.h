@@ -312,6 +312,19 @@ int bf_op_compose(const bf_operator* a1, const bf_operator* a2, bf_operator* out
 
 int bf_operator_destroy(bf_operator* op);
 
+/* Arithmetic of the built-in matrix-free products (segment kernel, FIO,
+ * dense).  Entries are FP32-accurate in both modes (FP64 phase reduction);
+ * the complex multiply-adds run
+ *   BF_PREC_FP64   : on the FP64 matrix cores, FP64 accumulation;
+ *   BF_PREC_BF16X3 : on the BF16 matrix cores with every entry and input
+ *                    split into three BF16 terms (products kept to 2^-24
+ *                    relative), 16-term FP32 sums folded into FP64.  The BF16
+ *                    matrix cores run beside the vector ALUs that evaluate the
+ *                    entries, so this mode is the faster one.
+ * Default: BF_PREC_BF16X3.  Returns BF_EINVAL for other operators. */
+enum { BF_PREC_FP64 = 0, BF_PREC_BF16X3 = 1 };
+int bf_op_set_precision(bf_operator* op, int precision);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,7 @@ SIGNATURES = {
     "bf_op_compose": (C.c_int, [C.POINTER(bf_operator), C.POINTER(bf_operator),
                                 C.POINTER(bf_operator)]),
     "bf_operator_destroy": (C.c_int, [C.POINTER(bf_operator)]),
+    "bf_op_set_precision": (C.c_int, [C.POINTER(bf_operator), C.c_int]),
 }
 
 
@@ -211,6 +212,12 @@ class Operator:
 
     def rmatvec(self, X, seg=None, stream=None):
         return self._call(self._op.rmatvec, X, seg, stream)
+
+    def set_precision(self, precision):
+        """'bf16x3' (split-BF16 matrix cores, default) or 'fp64' (FP64 matrix cores)."""
+        code = {"fp64": 0, "bf16x3": 1}[precision]
+        _check(lib().bf_op_set_precision(C.byref(self._op), code), "bf_op_set_precision")
+        return self
 
     def close(self):
         if self._op.user:

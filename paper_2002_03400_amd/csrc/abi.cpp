@@ -134,14 +134,17 @@ struct SegCtx {
   DevBuf<double> tx, ty, sx, sy;
   int64_t m, n;
   double kk;
+  int prec = BF_PREC_BF16X3;
 };
 struct FioCtx {
   DevBuf<double> cx;
   int64_t n;
+  int prec = BF_PREC_BF16X3;
 };
 struct DenseCtx {
   const bf_c64* A;
   int64_t m, n, lda;
+  int prec = BF_PREC_BF16X3;
 };
 struct FactorsCtx {
   const bf_factors* F;
@@ -179,10 +182,10 @@ static int seg_apply(void* user, bool adj, const bf_c64* X, int64_t ldx, int64_t
     auto* c = static_cast<SegCtx*>(static_cast<OpHeader*>(user)->ctx);
     PointSet T{c->tx.p, c->ty.p}, S{c->sx.p, c->sy.p};
     if (!adj)
-      launch_segkernel(T, c->m, S, c->n, c->kk, +1, X, ldx, ncols, Y, ldy, seg, nseg,
+      launch_segkernel(c->prec, T, c->m, S, c->n, c->kk, +1, X, ldx, ncols, Y, ldy, seg, nseg,
                        (hipStream_t)stream);
     else
-      launch_segkernel(S, c->n, T, c->m, c->kk, -1, X, ldx, ncols, Y, ldy, seg, nseg,
+      launch_segkernel(c->prec, S, c->n, T, c->m, c->kk, -1, X, ldx, ncols, Y, ldy, seg, nseg,
                        (hipStream_t)stream);
   });
 }
@@ -199,7 +202,7 @@ static int fio_apply(void* user, int adj, const bf_c64* X, int64_t ldx, int64_t 
                      int64_t ldy, const int64_t* seg, int32_t nseg, void* stream) {
   return guarded([&] {
     auto* c = static_cast<FioCtx*>(static_cast<OpHeader*>(user)->ctx);
-    launch_fio(c->n, c->cx.p, adj, X, ldx, ncols, Y, ldy, seg, nseg, (hipStream_t)stream);
+    launch_fio(c->prec, c->n, c->cx.p, adj, X, ldx, ncols, Y, ldy, seg, nseg, (hipStream_t)stream);
   });
 }
 static int fio_mv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
@@ -215,7 +218,7 @@ static int dense_apply(void* user, int adj, const bf_c64* X, int64_t ldx, int64_
                        bf_c64* Y, int64_t ldy, const int64_t* seg, int32_t nseg, void* stream) {
   return guarded([&] {
     auto* c = static_cast<DenseCtx*>(static_cast<OpHeader*>(user)->ctx);
-    launch_dense(c->A, c->m, c->n, c->lda, adj, X, ldx, ncols, Y, ldy, seg, nseg,
+    launch_dense(c->prec, c->A, c->m, c->n, c->lda, adj, X, ldx, ncols, Y, ldy, seg, nseg,
                  (hipStream_t)stream);
   });
 }
@@ -652,7 +655,7 @@ int bf_op_dense(const bf_c64* A, int64_t m, int64_t n, int64_t lda, bf_operator*
   if (!A || m <= 0 || n <= 0 || lda < m || !out) return BF_EINVAL;
   out->matvec = dense_mv;
   out->rmatvec = dense_rmv;
-  out->user = new OpHeader{OP_DENSE, new DenseCtx{A, m, n, lda}};
+  out->user = new OpHeader{OP_DENSE, new DenseCtx{A, m, n, lda, BF_PREC_BF16X3}};
   out->m = m;
   out->n = n;
   return BF_OK;
@@ -676,6 +679,18 @@ int bf_op_compose(const bf_operator* a1, const bf_operator* a2, bf_operator* out
   out->m = a1->m;
   out->n = a2->n;
   return BF_OK;
+}
+
+int bf_op_set_precision(bf_operator* op, int precision) {
+  if (!op || !op->user || (precision != BF_PREC_FP64 && precision != BF_PREC_BF16X3))
+    return BF_EINVAL;
+  auto* h = static_cast<OpHeader*>(op->user);
+  switch (h->kind) {
+    case OP_SEG: static_cast<SegCtx*>(h->ctx)->prec = precision; return BF_OK;
+    case OP_FIO: static_cast<FioCtx*>(h->ctx)->prec = precision; return BF_OK;
+    case OP_DENSE: static_cast<DenseCtx*>(h->ctx)->prec = precision; return BF_OK;
+    default: return BF_EINVAL;
+  }
 }
 
 int bf_operator_destroy(bf_operator* op) {

@@ -231,14 +231,14 @@ struct PointSet {     // structure-of-arrays FP64 coordinates on the device
 };
 // Y[:, g*ncols + c] = sum_{j in seg_g} E(i, j) X[j, c], E = kernel entries of
 // op(A) (sign = +1: A, sign = -1: A^H, points swapped by the caller).
-void launch_segkernel(PointSet out_pts, int64_t nout, PointSet in_pts, int64_t nin,
+void launch_segkernel(int prec, PointSet out_pts, int64_t nout, PointSet in_pts, int64_t nin,
                       double k_over_2pi, int sign, const bf_c64* X, int64_t ldx, int64_t ncols,
                       bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
                       hipStream_t s);
-void launch_fio(int64_t n, const double* cx_dev, int adjoint, const bf_c64* X, int64_t ldx,
+void launch_fio(int prec, int64_t n, const double* cx_dev, int adjoint, const bf_c64* X, int64_t ldx,
                 int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
                 hipStream_t s);
-void launch_dense(const bf_c64* A, int64_t m, int64_t n, int64_t lda, int adjoint,
+void launch_dense(int prec, const bf_c64* A, int64_t m, int64_t n, int64_t lda, int adjoint,
                   const bf_c64* X, int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
                   const int64_t* seg_host, int32_t nseg, hipStream_t s);
 

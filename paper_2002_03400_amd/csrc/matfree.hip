@@ -247,6 +247,139 @@ __global__ __launch_bounds__(MF_THREADS) void matfree_kernel(
   }
 }
 
+// ---- split-BF16 kernel --------------------------------------------------
+//
+// The same product on the BF16 matrix cores (v_mfma_f32_32x32x16_bf16), which
+// on gfx950 run concurrently with the vector ALUs that evaluate the entries
+// (the FP32/FP64 matrix instructions do not).  Every entry a and input x is
+// split into three BF16 terms, a = a1 + a2 + a3 (a1 = bf16(a),
+// a2 = bf16(a - a1), a3 = bf16(a - a1 - a2)), and the products keep every
+// term down to 2^-24 relative:  a x ~ a1x1 + a1x2 + a2x1 + a1x3 + a3x1 + a2x2
+// -- six MFMAs per real product, 24 per complex tile step
+// (Re += ar xr - ai xi, Im += ar xi + ai xr).  A wave owns 32 rows x 32 NT
+// columns; per step of 16 inner points lane l evaluates its 8 A-operand
+// entries (row l % 32, inner points 8 (l / 32) .. +7) and reads its B operands
+// (8 inner points of column l % 32) from the split planes staged in LDS.
+// Each step's FP32 tile sums (16 terms) are added into FP64 registers, so the
+// only FP32 summation error is that of 16-term sums.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r1 = x - (float)h;
+  m = (__bf16)r1;
+  l = (__bf16)(r1 - (float)m);
+}
+
+constexpr int BF_TK = 64;            // inner points per staged chunk (4 MFMA steps)
+constexpr int BF_KP = BF_TK + 8;     // padded k stride of the split planes (bank spread)
+constexpr int BF_WAVES = 4;
+constexpr int BF_ROWS = 32 * BF_WAVES;
+
+template <class E, int NT, typename Tout>
+__global__ __launch_bounds__(64 * BF_WAVES) void matfree_bf16_kernel(
+    E e, int64_t nout, const bf_c64* __restrict__ X, int64_t ldx, int32_t ncols, int32_t c0,
+    int32_t width, Tout* __restrict__ Y, int64_t ldy, int64_t ycols,
+    const int64_t* __restrict__ seg, int32_t nsplit) {
+  constexpr int NC = 32 * NT;
+  __shared__ typename E::Col cols[BF_TK];
+  // split planes: [term 0..2][re/im][column][k], 16 bytes = 8 consecutive k
+  __shared__ __attribute__((aligned(16))) __bf16 xs[3][2][NC][BF_KP];
+  const int g = blockIdx.y;
+  const int z = blockIdx.z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t row0 = (int64_t)blockIdx.x * BF_ROWS + wave * 32;
+  const int64_t myrow = row0 + (lane & 31);
+  const int kh = lane >> 5;       // which 8 of the step's 16 inner points
+  const int lc = lane & 31;
+  const int64_t j0 = seg[g], j1 = seg[g + 1];
+  const int64_t len = j1 - j0;
+  const int64_t chunk = (len + nsplit - 1) / nsplit;
+  const int64_t a = j0 + (int64_t)z * chunk;
+  const int64_t b = (a + chunk < j1) ? a + chunk : j1;
+  const int nc = width < NC ? width : NC;
+
+  double fr[NT][16], fi[NT][16];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { fr[t][v] = 0.0; fi[t][v] = 0.0; }
+  const typename E::Row rw = e.row(myrow < nout ? myrow : nout - 1);
+
+  for (int64_t jb = a; jb < b; jb += BF_TK) {
+    const int tk = (b - jb < BF_TK) ? (int)(b - jb) : BF_TK;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < BF_TK * NC; idx += 64 * BF_WAVES) {
+      const int kk = idx % BF_TK, c = idx / BF_TK;
+      bf_c64 v = {0.f, 0.f};
+      if (kk < tk && c < nc) v = X[(int64_t)(c0 + c) * ldx + jb + kk];
+      split3(v.re, xs[0][0][c][kk], xs[1][0][c][kk], xs[2][0][c][kk]);
+      split3(v.im, xs[0][1][c][kk], xs[1][1][c][kk], xs[2][1][c][kk]);
+    }
+    if (threadIdx.x < tk) cols[threadIdx.x] = e.col(jb + threadIdx.x);
+    __syncthreads();
+    const int nsteps = (tk + 15) >> 4;
+    for (int q = 0; q < nsteps; ++q) {
+      const int kb = 16 * q + 8 * kh;
+      bf16x8 ar[3], ai[3], an[3];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        cf ev = cf{0.f, 0.f};
+        if (kb + u < tk) ev = e.entry(rw, cols[kb + u]);
+        __bf16 h, m, l;
+        split3(ev.re, h, m, l);
+        ar[0][u] = h; ar[1][u] = m; ar[2][u] = l;
+        split3(ev.im, h, m, l);
+        ai[0][u] = h; ai[1][u] = m; ai[2][u] = l;
+        an[0][u] = -h; an[1][u] = -m; an[2][u] = -l;
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        bf16x8 xr[3], xi[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          xr[p] = *reinterpret_cast<const bf16x8*>(&xs[p][0][t * 32 + lc][kb]);
+          xi[p] = *reinterpret_cast<const bf16x8*>(&xs[p][1][t * 32 + lc][kb]);
+        }
+        floatx16 R = {}, I = {};
+        // term pairs (p, q) with p + q <= 2 (0-based): 00 01 10 02 20 11
+#define BF_PAIR(P, Q)                                                              \
+        R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[P], xr[Q], R, 0, 0, 0);      \
+        R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[P], xi[Q], R, 0, 0, 0);      \
+        I = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[P], xi[Q], I, 0, 0, 0);      \
+        I = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[P], xr[Q], I, 0, 0, 0);
+        BF_PAIR(2, 0) BF_PAIR(0, 2) BF_PAIR(1, 1) BF_PAIR(1, 0) BF_PAIR(0, 1) BF_PAIR(0, 0)
+#undef BF_PAIR
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          fr[t][v] += (double)R[v];
+          fi[t][v] += (double)I[v];
+        }
+      }
+    }
+  }
+  // accumulator layout of a 32x32 MFMA tile on gfx950: lane l, register v
+  // holds row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+  Tout* yz = Y + (int64_t)z * ycols * ldy + ((int64_t)g * ncols + c0) * ldy;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int c = t * 32 + lc;
+    if (c < nc) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t r = row0 + 8 * (v >> 2) + 4 * kh + (v & 3);
+        if (r < nout) {
+          Tout o;
+          o.re = fr[t][v];
+          o.im = fi[t][v];
+          yz[(int64_t)c * ldy + r] = o;
+        }
+      }
+    }
+  }
+}
+
 // Y(:, col) = sum_z P[z](:, col) over the FP64 split planes (fixed order).
 __global__ void split_reduce_kernel(const bf_c128* __restrict__ P, int64_t nout, int64_t ycols,
                                     int32_t nsplit, bf_c64* __restrict__ Y, int64_t ldy) {
@@ -278,6 +411,20 @@ static void launch_nt(const E& e, int64_t nout, const bf_c64* X, int64_t ldx, in
   BF_HIP(hipGetLastError());
 }
 
+template <class E, int NT, typename Tout>
+static void launch_bf16(const E& e, int64_t nout, const bf_c64* X, int64_t ldx, int32_t ncols,
+                        int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
+                        const int64_t* seg_dev, int32_t nseg, int32_t nsplit, hipStream_t s) {
+  dim3 grid((unsigned)((nout + BF_ROWS - 1) / BF_ROWS), (unsigned)nseg, (unsigned)nsplit);
+  const double nc = (double)std::min<int32_t>(32 * NT, width);
+  const double nin = (double)g_matfree_nin;
+  ProfScope ps(BF_KC_MATFREE, s, 8.0 * (double)nout * nin * nc,
+               8.0 * nc * (nin + (double)nout * nseg));
+  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout>), grid, dim3(64 * BF_WAVES), 0, s, e, nout,
+                     X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nsplit);
+  BF_HIP(hipGetLastError());
+}
+
 template <class E, typename Tout>
 static void launch_chunk(const E& e, int64_t nout, const bf_c64* X, int64_t ldx, int32_t ncols,
                          int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
@@ -290,10 +437,25 @@ static void launch_chunk(const E& e, int64_t nout, const bf_c64* X, int64_t ldx,
     launch_nt<E, 3>(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
 }
 
+template <class E, typename Tout>
+static void launch_chunk_prec(int prec, const E& e, int64_t nout, const bf_c64* X, int64_t ldx,
+                              int32_t ncols, int32_t c0, int32_t width, Tout* Y, int64_t ldy,
+                              int64_t ycols, const int64_t* seg_dev, int32_t nseg, int32_t nsplit,
+                              hipStream_t s) {
+  if (prec == BF_PREC_BF16X3) {
+    if (width <= 32)
+      launch_bf16<E, 1>(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
+    else
+      launch_bf16<E, 2>(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
+  } else {
+    launch_chunk(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
+  }
+}
+
 template <class E>
-static void run_matfree(const E& e, int64_t nout, int64_t nin, const bf_c64* X, int64_t ldx,
-                        int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg_host,
-                        int32_t nseg, hipStream_t s) {
+static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const bf_c64* X,
+                        int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
+                        const int64_t* seg_host, int32_t nseg, hipStream_t s) {
   if (nout <= 0 || ncols <= 0) return;
   std::vector<int64_t> segv;
   if (seg_host) {
@@ -311,7 +473,8 @@ static void run_matfree(const E& e, int64_t nout, int64_t nin, const bf_c64* X, 
   }
   // split-K so that row tiles x groups x splits reaches ~2048 workgroups,
   // keeping at least 512 inner points per split.
-  int64_t tiles = ((nout + MF_ROWS - 1) / MF_ROWS) * nseg;
+  const int64_t rows_per_wg = prec == BF_PREC_BF16X3 ? BF_ROWS : MF_ROWS;
+  int64_t tiles = ((nout + rows_per_wg - 1) / rows_per_wg) * nseg;
   int64_t want = (2048 + tiles - 1) / tiles;
   int64_t cap = std::max<int64_t>(1, maxlen / 512);
   int32_t nsplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, cap, 64}));
@@ -323,16 +486,17 @@ static void run_matfree(const E& e, int64_t nout, int64_t nin, const bf_c64* X, 
   g_matfree_nin = segv[nseg] - segv[0];
   DevBuf<bf_c128> part;
   if (nsplit > 1) part = DevBuf<bf_c128>((size_t)nsplit * ycols * nout, s);
-  const int64_t nchunk = (ncols + 47) / 48;
-  const int64_t cw = (ncols + nchunk - 1) / nchunk;   // balanced widths <= 48
+  const int64_t maxw = prec == BF_PREC_BF16X3 ? 64 : 48;
+  const int64_t nchunk = (ncols + maxw - 1) / maxw;
+  const int64_t cw = (ncols + nchunk - 1) / nchunk;   // balanced widths <= maxw
   for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
     const int32_t w = (int32_t)std::min<int64_t>(cw, ncols - c0);
     if (nsplit > 1)
-      launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, part.p, nout, ycols, seg_dev.p,
-                   nseg, nsplit, s);
+      launch_chunk_prec(prec, e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, part.p, nout, ycols,
+                        seg_dev.p, nseg, nsplit, s);
     else
-      launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols, seg_dev.p, nseg,
-                   nsplit, s);
+      launch_chunk_prec(prec, e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols,
+                        seg_dev.p, nseg, nsplit, s);
   }
   if (nsplit > 1) {
     int64_t tot = nout * ycols;
@@ -343,34 +507,34 @@ static void run_matfree(const E& e, int64_t nout, int64_t nin, const bf_c64* X, 
   }
 }
 
-void launch_segkernel(PointSet out_pts, int64_t nout, PointSet in_pts, int64_t nin,
+void launch_segkernel(int prec, PointSet out_pts, int64_t nout, PointSet in_pts, int64_t nin,
                       double k_over_2pi, int sign, const bf_c64* X, int64_t ldx, int64_t ncols,
                       bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
                       hipStream_t s) {
   SegEntry e{out_pts, in_pts, k_over_2pi, (float)sign};
-  run_matfree(e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
+  run_matfree(prec, e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
 }
 
-void launch_fio(int64_t n, const double* cx_dev, int adjoint, const bf_c64* X, int64_t ldx,
-                int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
-                hipStream_t s) {
+void launch_fio(int prec, int64_t n, const double* cx_dev, int adjoint, const bf_c64* X,
+                int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg_host,
+                int32_t nseg, hipStream_t s) {
   if (!adjoint) {
     FioEntry e{n, 1.0 / (double)n, cx_dev};
-    run_matfree(e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
+    run_matfree(prec, e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   } else {
     FioAdjEntry e{n, 1.0 / (double)n, cx_dev};
-    run_matfree(e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
+    run_matfree(prec, e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   }
 }
 
-void launch_dense(const bf_c64* A, int64_t m, int64_t n, int64_t lda, int adjoint,
+void launch_dense(int prec, const bf_c64* A, int64_t m, int64_t n, int64_t lda, int adjoint,
                   const bf_c64* X, int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
                   const int64_t* seg_host, int32_t nseg, hipStream_t s) {
   DenseEntry e{A, lda, adjoint};
   if (!adjoint)
-    run_matfree(e, m, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
+    run_matfree(prec, e, m, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   else
-    run_matfree(e, n, m, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
+    run_matfree(prec, e, n, m, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
 }
 
 }  // namespace bf
