@@ -28,41 +28,40 @@ static thread_local int64_t g_matfree_nin = 0;
 
 // ---- entry functors ------------------------------------------------------
 
-// sin and cos of 2 pi t for a phase t given in revolutions (FP64, |t| < 2^29).
-// The phase is reduced in FP64 to the nearest quarter revolution,
-// t = q/4 + y with |y| <= 1/8, so x = 2 pi y lies in [-pi/4, pi/4] and only
-// its FP32 rounding (< 3e-8 rad) enters; sin x and cos x are the Taylor
-// polynomials through x^9 and x^10 (truncation below 2e-9 on that interval),
-// then rotated by q quarter turns.
-__device__ __forceinline__ void sincos_rev(double t, float* s, float* c) {
-  const double q = rint(4.0 * t);
-  const double y = fma(-0.25, q, t);
-  const float x = (float)(y * 6.283185307179586477);
+// sin and cos of (pi / 2) t for a phase t given in quarter revolutions (FP64,
+// |t| < 2^31).  The phase is reduced in FP64 to the nearest quarter
+// revolution, t = q + y with |y| <= 1/2 (exact), so x = (pi / 2) y lies in
+// [-pi/4, pi/4] and only its FP32 rounding (< 5e-8 rad) enters; sin x and
+// cos x are minimax polynomials on that interval (Remez exchange, FP32
+// coefficients; errors 3.6e-9 relative and 5.4e-11 absolute before FP32
+// rounding), then rotated by q quarter turns.
+__device__ __forceinline__ void sincos_quarter(double t, float* s, float* c) {
+  const double q = rint(t);
+  const float x = (float)((t - q) * 1.5707963267948966);
   const float x2 = x * x;
-  float sp = fmaf(x2, 2.75573192e-6f, -1.98412698e-4f);   // 1/9!, -1/7!
-  sp = fmaf(x2, sp, 8.33333333e-3f);                       // 1/5!
-  sp = fmaf(x2, sp, -1.66666667e-1f);                      // -1/3!
-  sp = x * fmaf(x2, sp, 1.0f);
-  float cp = fmaf(x2, -2.75573192e-7f, 2.48015873e-5f);    // -1/10!, 1/8!
-  cp = fmaf(x2, cp, -1.38888889e-3f);                      // -1/6!
-  cp = fmaf(x2, cp, 4.16666667e-2f);                       // 1/4!
-  cp = fmaf(x2, cp, -0.5f);                                // -1/2!
-  cp = fmaf(x2, cp, 1.0f);
-  const int n = (int)q & 3;
-  const float sv = (n & 1) ? cp : sp;
-  const float cv = (n & 1) ? sp : cp;
-  *s = (n & 2) ? -sv : sv;
-  *c = ((n ^ (n >> 1)) & 1) ? -cv : cv;
+  float sp = fmaf(x2, -1.951729937e-4f, 8.332177997e-3f);
+  sp = fmaf(x2, sp, -1.666665524e-1f);
+  const float sv0 = fmaf(x * x2, sp, x);
+  float cp = fmaf(x2, 2.439045056e-5f, -1.388676348e-3f);
+  cp = fmaf(x2, cp, 4.166662320e-2f);
+  cp = fmaf(x2, cp, -0.5f);
+  const float cv0 = fmaf(x2, cp, 1.0f);
+  // quarter turns: (sin, cos) -> (cos, -sin) -> (-sin, -cos) -> (-cos, sin)
+  const int n = (int)q;
+  const float sv = (n & 1) ? cv0 : sv0;
+  const float cv = (n & 1) ? sv0 : cv0;
+  *s = __int_as_float(__float_as_int(sv) ^ ((n & 2) << 30));
+  *c = __int_as_float(__float_as_int(cv) ^ (((n + 1) & 2) << 30));
 }
 
-// exp(i k r)/r, r = |p - q|: r from an FP32 square root refined by one
-// FP64 Newton step (relative error ~1e-14, so the phase k r / 2pi stays
-// accurate to ~1e-9 revolutions for k r up to 1e5), 1/r from the FP32
-// reciprocal.  sign = -1 gives the conjugate (entries of A^H with the point
-// roles swapped).
+// exp(i k r)/r, r = |p - q|: 1/r from the FP32 reciprocal square root, r
+// from it and refined by one FP64 Newton step (relative error ~1e-14, so the
+// phase k r stays accurate to ~1e-9 revolutions for k r / 2pi up to 1e5).
+// sign = -1 gives the conjugate (entries of A^H with the point roles
+// swapped).
 struct SegEntry {
   PointSet out, in;
-  double kk;   // k / (2 pi)
+  double k4;   // k / (pi / 2): k r in quarter revolutions
   float sign;
   struct Row { double x, y; };
   struct Col { double x, y; };
@@ -71,47 +70,48 @@ struct SegEntry {
   __device__ cf entry(const Row& r, const Col& c) const {
     const double dx = r.x - c.x, dy = r.y - c.y;
     const double r2 = fma(dx, dx, dy * dy);
-    const float rf = __builtin_amdgcn_sqrtf((float)r2);
-    const float inv = __builtin_amdgcn_rcpf(rf);
-    const double rd = (double)rf;
-    const double rr = fma(fma(-rd, rd, r2), 0.5 * (double)inv, rd);
+    const float r2f = (float)r2;
+    const float inv = __builtin_amdgcn_rsqf(r2f);
+    const double rd = (double)(r2f * inv);
+    const double rr = fma(fma(-rd, rd, r2), (double)(0.5f * inv), rd);
     float s, co;
-    sincos_rev(rr * kk, &s, &co);
-    return cf{co * inv, sign * s * inv};
+    sincos_quarter(rr * k4, &s, &co);
+    return cf{co * inv, s * (sign * inv)};
   }
 };
 
 // exp(2 pi i (j xi / n + c_j |xi|)).  j * xi is an exact integer (< 2^53),
-// so j xi / n is formed in FP64 with one rounding before the reduction.
+// so the phase (in quarter revolutions: the exact scalings 4/n and 4 c_j) is
+// formed in FP64 with one rounding before the reduction.
 // Forward: output index j (row), inner index k (xi = k - n/2).
 struct FioEntry {
   int64_t n;
-  double inv_n;
+  double inv_n4;     // 4 / n
   const double* cx;  // c(x_j), FP64
-  struct Row { double j; double c; };
+  struct Row { double j; double c4; };
   struct Col { double xi; };
-  __device__ Row row(int64_t j) const { return Row{(double)j, cx[j]}; }
+  __device__ Row row(int64_t j) const { return Row{(double)j, 4.0 * cx[j]}; }
   __device__ Col col(int64_t k) const { return Col{(double)(k - n / 2)}; }
   __device__ cf entry(const Row& r, const Col& c) const {
-    const double ph = fma(r.j * c.xi, inv_n, r.c * fabs(c.xi));
+    const double ph = fma(r.j * c.xi, inv_n4, r.c4 * fabs(c.xi));
     float s, co;
-    sincos_rev(ph, &s, &co);
+    sincos_quarter(ph, &s, &co);
     return cf{co, s};
   }
 };
 // Adjoint: output index k, inner index j: conj(A_jk).
 struct FioAdjEntry {
   int64_t n;
-  double inv_n;
+  double inv_n4;
   const double* cx;
   struct Row { double xi; };
-  struct Col { double j; double c; };
+  struct Col { double j; double c4; };
   __device__ Row row(int64_t k) const { return Row{(double)(k - n / 2)}; }
-  __device__ Col col(int64_t j) const { return Col{(double)j, cx[j]}; }
+  __device__ Col col(int64_t j) const { return Col{(double)j, 4.0 * cx[j]}; }
   __device__ cf entry(const Row& r, const Col& c) const {
-    const double ph = fma(c.j * r.xi, inv_n, c.c * fabs(r.xi));
+    const double ph = fma(c.j * r.xi, inv_n4, c.c4 * fabs(r.xi));
     float s, co;
-    sincos_rev(ph, &s, &co);
+    sincos_quarter(ph, &s, &co);
     return cf{co, -s};
   }
 };
@@ -196,7 +196,8 @@ __global__ __launch_bounds__(MF_THREADS) void matfree_kernel(
       if (jj < tk && c < nc) v = X[(int64_t)(c0 + c) * ldx + jb + jj];
       xs[jj][c] = cf{v.re, v.im};
     }
-    if (threadIdx.x < tk) cols[threadIdx.x] = e.col(jb + threadIdx.x);
+    // points past the chunk's end repeat its last point (their X rows are zero)
+    if (threadIdx.x < MF_TK) cols[threadIdx.x] = e.col(jb + min((int)threadIdx.x, tk - 1));
     __syncthreads();
     const int nsteps = (tk + 3) >> 2;
     for (int q = 0; q < nsteps; ++q) {
@@ -204,8 +205,7 @@ __global__ __launch_bounds__(MF_THREADS) void matfree_kernel(
       double ar[MF_H], ai[MF_H], as[MF_H];
 #pragma unroll
       for (int h = 0; h < MF_H; ++h) {
-        cf ev = cf{0.f, 0.f};
-        if (jj < tk) ev = e.entry(rw[h], cols[jj]);
+        const cf ev = e.entry(rw[h], cols[jj]);
         ar[h] = ev.re;
         ai[h] = ev.im;
         as[h] = (double)ev.re + (double)ev.im;
@@ -262,30 +262,78 @@ __global__ __launch_bounds__(MF_THREADS) void matfree_kernel(
 // (8 inner points of column l % 32) from the split planes staged in LDS.
 // Each step's FP32 tile sums (16 terms) are added into FP64 registers, so the
 // only FP32 summation error is that of 16-term sums.
+//
+// X is split once per call (split_planes_kernel) into six BF16 planes laid
+// out per column along the inner index, each segment padded with zeros to a
+// multiple of the 64-point chunk, so a workgroup stages a chunk with 16-byte
+// copies and a ragged tail needs no masking: its X terms are zero and its
+// entries are evaluated at a clamped (valid) inner point.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
-  h = (__bf16)x;
-  const float r1 = x - (float)h;
-  m = (__bf16)r1;
-  l = (__bf16)(r1 - (float)m);
+// bf16(x0) in the low half, bf16(x1) in the high half (round to nearest even)
+__device__ __forceinline__ uint32_t pk_bf16(float x0, float x1) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){x0, x1}, bf16x2));
+}
+
+// three-term split of two values at once: h + m + l = x to 2^-24 relative
+// (x - bf16(x) and the next difference are exact in FP32)
+__device__ __forceinline__ void split3_pk(float x0, float x1, uint32_t& h, uint32_t& m,
+                                          uint32_t& l) {
+  h = pk_bf16(x0, x1);
+  const float r0 = x0 - __uint_as_float(h << 16);
+  const float r1 = x1 - __uint_as_float(h & 0xffff0000u);
+  m = pk_bf16(r0, r1);
+  l = pk_bf16(r0 - __uint_as_float(m << 16), r1 - __uint_as_float(m & 0xffff0000u));
 }
 
 constexpr int BF_TK = 64;            // inner points per staged chunk (4 MFMA steps)
 constexpr int BF_KP = BF_TK + 8;     // padded k stride of the split planes (bank spread)
 constexpr int BF_WAVES = 4;
 constexpr int BF_ROWS = 32 * BF_WAVES;
+constexpr int BF_PLANES = 6;         // (term 0..2) x (re, im)
+
+// Xp[(c * 6 + 2 term + part) * kpad + pofs[g] + (j - seg[g])] = term of
+// X[j, c] (part 0 real, 1 imaginary); zero from seg[g+1] to pofs[g+1].
+// One thread splits 8 consecutive inner points of one column.
+__global__ void split_planes_kernel(const bf_c64* __restrict__ X, int64_t ldx,
+                                    const int64_t* __restrict__ seg,
+                                    const int64_t* __restrict__ pofs, int64_t kpad,
+                                    uint16_t* __restrict__ Xp) {
+  const int g = blockIdx.y, c = blockIdx.z;
+  const int64_t kk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+  if (kk >= pofs[g + 1] - pofs[g]) return;
+  const int64_t j0 = seg[g] + kk, j1 = seg[g + 1];
+  const bf_c64* xc = X + (int64_t)c * ldx;
+  u32x4 t[BF_PLANES];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    bf_c64 x0 = {0.f, 0.f}, x1 = {0.f, 0.f};
+    if (j0 + 2 * d < j1) x0 = xc[j0 + 2 * d];
+    if (j0 + 2 * d + 1 < j1) x1 = xc[j0 + 2 * d + 1];
+    uint32_t h, m, l;
+    split3_pk(x0.re, x1.re, h, m, l);
+    t[0][d] = h; t[2][d] = m; t[4][d] = l;
+    split3_pk(x0.im, x1.im, h, m, l);
+    t[1][d] = h; t[3][d] = m; t[5][d] = l;
+  }
+  uint16_t* dst = Xp + (int64_t)c * BF_PLANES * kpad + pofs[g] + kk;
+#pragma unroll
+  for (int p = 0; p < BF_PLANES; ++p) *reinterpret_cast<u32x4*>(dst + p * kpad) = t[p];
+}
 
 template <class E, int NT, typename Tout>
 __global__ __launch_bounds__(64 * BF_WAVES) void matfree_bf16_kernel(
-    E e, int64_t nout, const bf_c64* __restrict__ X, int64_t ldx, int32_t ncols, int32_t c0,
+    E e, int64_t nout, const uint16_t* __restrict__ Xp, int64_t kpad, int32_t ncols, int32_t c0,
     int32_t width, Tout* __restrict__ Y, int64_t ldy, int64_t ycols,
-    const int64_t* __restrict__ seg, int32_t nsplit) {
+    const int64_t* __restrict__ seg, const int64_t* __restrict__ pofs, int32_t nsplit) {
   constexpr int NC = 32 * NT;
   __shared__ typename E::Col cols[BF_TK];
   // split planes: [term 0..2][re/im][column][k], 16 bytes = 8 consecutive k
-  __shared__ __attribute__((aligned(16))) __bf16 xs[3][2][NC][BF_KP];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[3][2][NC][BF_KP];
   const int g = blockIdx.y;
   const int z = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -295,10 +343,12 @@ __global__ __launch_bounds__(64 * BF_WAVES) void matfree_bf16_kernel(
   const int lc = lane & 31;
   const int64_t j0 = seg[g], j1 = seg[g + 1];
   const int64_t len = j1 - j0;
-  const int64_t chunk = (len + nsplit - 1) / nsplit;
+  // split-K slices are whole chunks, so only a segment's last chunk is ragged
+  const int64_t chunk = ((len + nsplit - 1) / nsplit + BF_TK - 1) / BF_TK * BF_TK;
   const int64_t a = j0 + (int64_t)z * chunk;
   const int64_t b = (a + chunk < j1) ? a + chunk : j1;
   const int nc = width < NC ? width : NC;
+  const uint16_t* xg = Xp + (int64_t)c0 * BF_PLANES * kpad + pofs[g] - j0;
 
   double fr[NT][16], fi[NT][16];
 #pragma unroll
@@ -308,49 +358,55 @@ __global__ __launch_bounds__(64 * BF_WAVES) void matfree_bf16_kernel(
   const typename E::Row rw = e.row(myrow < nout ? myrow : nout - 1);
 
   for (int64_t jb = a; jb < b; jb += BF_TK) {
-    const int tk = (b - jb < BF_TK) ? (int)(b - jb) : BF_TK;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < BF_TK * NC; idx += 64 * BF_WAVES) {
-      const int kk = idx % BF_TK, c = idx / BF_TK;
-      bf_c64 v = {0.f, 0.f};
-      if (kk < tk && c < nc) v = X[(int64_t)(c0 + c) * ldx + jb + kk];
-      split3(v.re, xs[0][0][c][kk], xs[1][0][c][kk], xs[2][0][c][kk]);
-      split3(v.im, xs[0][1][c][kk], xs[1][1][c][kk], xs[2][1][c][kk]);
+    // NC columns x 6 planes x 8 copies of 16 bytes
+    for (int idx = threadIdx.x; idx < NC * BF_PLANES * 8; idx += 64 * BF_WAVES) {
+      const int q8 = idx & 7, pl = (idx >> 3) % BF_PLANES, c = (idx >> 3) / BF_PLANES;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (c < nc)
+        v = *reinterpret_cast<const u32x4*>(xg + ((int64_t)c * BF_PLANES + pl) * kpad + jb + 8 * q8);
+      *reinterpret_cast<u32x4*>(&xs[pl >> 1][pl & 1][c][8 * q8]) = v;
     }
-    if (threadIdx.x < tk) cols[threadIdx.x] = e.col(jb + threadIdx.x);
+    if (threadIdx.x < BF_TK) {
+      const int64_t j = jb + threadIdx.x;
+      cols[threadIdx.x] = e.col(j < j1 ? j : j1 - 1);
+    }
     __syncthreads();
-    const int nsteps = (tk + 15) >> 4;
+    const int nsteps = (int)((b - jb < BF_TK ? b - jb : BF_TK) + 15) >> 4;
     for (int q = 0; q < nsteps; ++q) {
       const int kb = 16 * q + 8 * kh;
-      bf16x8 ar[3], ai[3], an[3];
+      cf ev[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        cf ev = cf{0.f, 0.f};
-        if (kb + u < tk) ev = e.entry(rw, cols[kb + u]);
-        __bf16 h, m, l;
-        split3(ev.re, h, m, l);
-        ar[0][u] = h; ar[1][u] = m; ar[2][u] = l;
-        split3(ev.im, h, m, l);
-        ai[0][u] = h; ai[1][u] = m; ai[2][u] = l;
-        an[0][u] = -h; an[1][u] = -m; an[2][u] = -l;
+      for (int u = 0; u < 8; ++u) ev[u] = e.entry(rw, cols[kb + u]);
+      u32x4 ar[3], ai[3], an[3];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        uint32_t h, m, l;
+        split3_pk(ev[2 * d].re, ev[2 * d + 1].re, h, m, l);
+        ar[0][d] = h; ar[1][d] = m; ar[2][d] = l;
+        split3_pk(ev[2 * d].im, ev[2 * d + 1].im, h, m, l);
+        ai[0][d] = h; ai[1][d] = m; ai[2][d] = l;
       }
 #pragma unroll
+      for (int p = 0; p < 3; ++p) an[p] = ai[p] ^ 0x80008000u;   // -ai, both halves
+#pragma unroll
       for (int t = 0; t < NT; ++t) {
-        bf16x8 xr[3], xi[3];
+        u32x4 xr[3], xi[3];
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-          xr[p] = *reinterpret_cast<const bf16x8*>(&xs[p][0][t * 32 + lc][kb]);
-          xi[p] = *reinterpret_cast<const bf16x8*>(&xs[p][1][t * 32 + lc][kb]);
+          xr[p] = *reinterpret_cast<const u32x4*>(&xs[p][0][t * 32 + lc][kb]);
+          xi[p] = *reinterpret_cast<const u32x4*>(&xs[p][1][t * 32 + lc][kb]);
         }
         floatx16 R = {}, I = {};
-        // term pairs (p, q) with p + q <= 2 (0-based): 00 01 10 02 20 11
-#define BF_PAIR(P, Q)                                                              \
-        R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[P], xr[Q], R, 0, 0, 0);      \
-        R = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[P], xi[Q], R, 0, 0, 0);      \
-        I = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[P], xi[Q], I, 0, 0, 0);      \
-        I = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[P], xr[Q], I, 0, 0, 0);
+        // term pairs (p, q) with p + q <= 2 (0-based): 20 02 11 10 01 00
+#define BF_MM(A, B, C) \
+  C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A), \
+                                              __builtin_bit_cast(bf16x8, B), C, 0, 0, 0);
+#define BF_PAIR(P, Q) BF_MM(ar[P], xr[Q], R) BF_MM(an[P], xi[Q], R) \
+                      BF_MM(ar[P], xi[Q], I) BF_MM(ai[P], xr[Q], I)
         BF_PAIR(2, 0) BF_PAIR(0, 2) BF_PAIR(1, 1) BF_PAIR(1, 0) BF_PAIR(0, 1) BF_PAIR(0, 0)
 #undef BF_PAIR
+#undef BF_MM
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           fr[t][v] += (double)R[v];
@@ -411,20 +467,6 @@ static void launch_nt(const E& e, int64_t nout, const bf_c64* X, int64_t ldx, in
   BF_HIP(hipGetLastError());
 }
 
-template <class E, int NT, typename Tout>
-static void launch_bf16(const E& e, int64_t nout, const bf_c64* X, int64_t ldx, int32_t ncols,
-                        int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
-                        const int64_t* seg_dev, int32_t nseg, int32_t nsplit, hipStream_t s) {
-  dim3 grid((unsigned)((nout + BF_ROWS - 1) / BF_ROWS), (unsigned)nseg, (unsigned)nsplit);
-  const double nc = (double)std::min<int32_t>(32 * NT, width);
-  const double nin = (double)g_matfree_nin;
-  ProfScope ps(BF_KC_MATFREE, s, 8.0 * (double)nout * nin * nc,
-               8.0 * nc * (nin + (double)nout * nseg));
-  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout>), grid, dim3(64 * BF_WAVES), 0, s, e, nout,
-                     X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nsplit);
-  BF_HIP(hipGetLastError());
-}
-
 template <class E, typename Tout>
 static void launch_chunk(const E& e, int64_t nout, const bf_c64* X, int64_t ldx, int32_t ncols,
                          int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
@@ -437,19 +479,32 @@ static void launch_chunk(const E& e, int64_t nout, const bf_c64* X, int64_t ldx,
     launch_nt<E, 3>(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
 }
 
+template <class E, int NT, typename Tout>
+static void launch_bf16(const E& e, int64_t nout, const uint16_t* Xp, int64_t kpad, int32_t ncols,
+                        int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
+                        const int64_t* seg_dev, const int64_t* pofs_dev, int32_t nseg,
+                        int32_t nsplit, hipStream_t s) {
+  dim3 grid((unsigned)((nout + BF_ROWS - 1) / BF_ROWS), (unsigned)nseg, (unsigned)nsplit);
+  const double nc = (double)std::min<int32_t>(32 * NT, width);
+  const double nin = (double)g_matfree_nin;
+  ProfScope ps(BF_KC_MATFREE, s, 8.0 * (double)nout * nin * nc,
+               8.0 * nc * (nin + (double)nout * nseg));
+  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout>), grid, dim3(64 * BF_WAVES), 0, s, e, nout,
+                     Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nsplit);
+  BF_HIP(hipGetLastError());
+}
+
 template <class E, typename Tout>
-static void launch_chunk_prec(int prec, const E& e, int64_t nout, const bf_c64* X, int64_t ldx,
+static void launch_chunk_bf16(const E& e, int64_t nout, const uint16_t* Xp, int64_t kpad,
                               int32_t ncols, int32_t c0, int32_t width, Tout* Y, int64_t ldy,
-                              int64_t ycols, const int64_t* seg_dev, int32_t nseg, int32_t nsplit,
-                              hipStream_t s) {
-  if (prec == BF_PREC_BF16X3) {
-    if (width <= 32)
-      launch_bf16<E, 1>(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
-    else
-      launch_bf16<E, 2>(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
-  } else {
-    launch_chunk(e, nout, X, ldx, ncols, c0, width, Y, ldy, ycols, seg_dev, nseg, nsplit, s);
-  }
+                              int64_t ycols, const int64_t* seg_dev, const int64_t* pofs_dev,
+                              int32_t nseg, int32_t nsplit, hipStream_t s) {
+  if (width <= 32)
+    launch_bf16<E, 1>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
+                      nsplit, s);
+  else
+    launch_bf16<E, 2>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
+                      nsplit, s);
 }
 
 template <class E>
@@ -457,6 +512,7 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
                         int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
                         const int64_t* seg_host, int32_t nseg, hipStream_t s) {
   if (nout <= 0 || ncols <= 0) return;
+  const bool bf16 = prec == BF_PREC_BF16X3;
   std::vector<int64_t> segv;
   if (seg_host) {
     segv.assign(seg_host, seg_host + nseg + 1);
@@ -465,6 +521,7 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
     segv = {0, nin};
   }
   BF_CHECK(nseg >= 1 && nseg <= 65535, BF_EINVAL, "bad segment count");
+  BF_CHECK(ncols <= 65535, BF_EINVAL, "too many columns");
   int64_t maxlen = 0;
   for (int g = 0; g < nseg; ++g) {
     BF_CHECK(segv[g] <= segv[g + 1] && segv[g] >= 0 && segv[g + 1] <= nin, BF_EINVAL,
@@ -473,30 +530,65 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
   }
   // split-K so that row tiles x groups x splits reaches ~2048 workgroups,
   // keeping at least 512 inner points per split.
-  const int64_t rows_per_wg = prec == BF_PREC_BF16X3 ? BF_ROWS : MF_ROWS;
+  const int64_t rows_per_wg = bf16 ? BF_ROWS : MF_ROWS;
   int64_t tiles = ((nout + rows_per_wg - 1) / rows_per_wg) * nseg;
   int64_t want = (2048 + tiles - 1) / tiles;
   int64_t cap = std::max<int64_t>(1, maxlen / 512);
   int32_t nsplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>({want, cap, 64}));
 
-  DevBuf<int64_t> seg_dev(segv.size(), s);
-  BF_HIP(hipMemcpyAsync(seg_dev.p, segv.data(), segv.size() * sizeof(int64_t),
+  // segment offsets (and, for the split planes, their chunk-padded offsets)
+  // travel in one upload
+  std::vector<int64_t> offs(segv);
+  int64_t kpad = 0, maxpad = 0;
+  if (bf16) {
+    offs.resize(2 * (size_t)(nseg + 1));
+    offs[nseg + 1] = 0;
+    for (int g = 0; g < nseg; ++g) {
+      const int64_t padded = (segv[g + 1] - segv[g] + BF_TK - 1) / BF_TK * BF_TK;
+      offs[nseg + 2 + g] = offs[nseg + 1 + g] + padded;
+      maxpad = std::max(maxpad, padded);
+    }
+    kpad = offs[2 * (size_t)nseg + 1];
+  }
+  DevBuf<int64_t> seg_dev(offs.size(), s);
+  BF_HIP(hipMemcpyAsync(seg_dev.p, offs.data(), offs.size() * sizeof(int64_t),
                         hipMemcpyHostToDevice, s));
+  const int64_t* pofs_dev = seg_dev.p + nseg + 1;
   const int64_t ycols = (int64_t)nseg * ncols;
   g_matfree_nin = segv[nseg] - segv[0];
+
+  DevBuf<uint16_t> planes;
+  if (bf16) planes = DevBuf<uint16_t>(std::max<size_t>((size_t)ncols * BF_PLANES * kpad, 8), s);
+  if (bf16 && kpad > 0) {
+    ProfScope ps(BF_KC_OTHER, s, 0.0, 8.0 * ncols * (double)g_matfree_nin + 12.0 * ncols * kpad);
+    dim3 grid((unsigned)((maxpad / 8 + 255) / 256), (unsigned)nseg, (unsigned)ncols);
+    hipLaunchKernelGGL(split_planes_kernel, grid, dim3(256), 0, s, X, ldx, seg_dev.p, pofs_dev,
+                       kpad, planes.p);
+    BF_HIP(hipGetLastError());
+  }
+
   DevBuf<bf_c128> part;
   if (nsplit > 1) part = DevBuf<bf_c128>((size_t)nsplit * ycols * nout, s);
-  const int64_t maxw = prec == BF_PREC_BF16X3 ? 64 : 48;
+  const int64_t maxw = bf16 ? 64 : 48;
   const int64_t nchunk = (ncols + maxw - 1) / maxw;
   const int64_t cw = (ncols + nchunk - 1) / nchunk;   // balanced widths <= maxw
   for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
     const int32_t w = (int32_t)std::min<int64_t>(cw, ncols - c0);
-    if (nsplit > 1)
-      launch_chunk_prec(prec, e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, part.p, nout, ycols,
-                        seg_dev.p, nseg, nsplit, s);
-    else
-      launch_chunk_prec(prec, e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols,
-                        seg_dev.p, nseg, nsplit, s);
+    if (bf16) {
+      if (nsplit > 1)
+        launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, part.p, nout,
+                          ycols, seg_dev.p, pofs_dev, nseg, nsplit, s);
+      else
+        launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols,
+                          seg_dev.p, pofs_dev, nseg, nsplit, s);
+    } else {
+      if (nsplit > 1)
+        launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, part.p, nout, ycols,
+                     seg_dev.p, nseg, nsplit, s);
+      else
+        launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols, seg_dev.p,
+                     nseg, nsplit, s);
+    }
   }
   if (nsplit > 1) {
     int64_t tot = nout * ycols;
@@ -511,7 +603,7 @@ void launch_segkernel(int prec, PointSet out_pts, int64_t nout, PointSet in_pts,
                       double k_over_2pi, int sign, const bf_c64* X, int64_t ldx, int64_t ncols,
                       bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
                       hipStream_t s) {
-  SegEntry e{out_pts, in_pts, k_over_2pi, (float)sign};
+  SegEntry e{out_pts, in_pts, 4.0 * k_over_2pi, (float)sign};
   run_matfree(prec, e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
 }
 
@@ -519,10 +611,10 @@ void launch_fio(int prec, int64_t n, const double* cx_dev, int adjoint, const bf
                 int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg_host,
                 int32_t nseg, hipStream_t s) {
   if (!adjoint) {
-    FioEntry e{n, 1.0 / (double)n, cx_dev};
+    FioEntry e{n, 4.0 / (double)n, cx_dev};
     run_matfree(prec, e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   } else {
-    FioAdjEntry e{n, 1.0 / (double)n, cx_dev};
+    FioAdjEntry e{n, 4.0 / (double)n, cx_dev};
     run_matfree(prec, e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   }
 }
