@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cstdlib>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 
 #include "factors.h"
@@ -75,20 +76,91 @@ void check_extent(const void* p, size_t bytes, const char* what) {
   throw Error(BF_EINVAL, std::string("bounds check failed: ") + what);
 }
 
+static void ensure_pool(int dev) {
+  if (dev < 0 || dev >= 64) return;
+  std::call_once(g_pool_once[dev], [dev]() {
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  });
+}
+
+struct AllocScope::Cache {
+  hipStream_t s = nullptr;
+  std::multimap<size_t, void*> free_;          // capacity -> block
+  std::unordered_map<void*, size_t> cap_;      // every block this scope allocated
+  size_t free_bytes = 0;
+  Staging st;
+  Cache* prev = nullptr;
+  void trim() {
+    for (auto& kv : free_) {
+      (void)hipFreeAsync(kv.second, s);
+      cap_.erase(kv.second);
+    }
+    free_.clear();
+    free_bytes = 0;
+  }
+};
+static thread_local AllocScope::Cache* t_cache = nullptr;
+// free blocks a scope may hold before it returns them to the pool
+static constexpr size_t kScopeFreeLimit = size_t(8) << 30;
+
+static size_t round_block(size_t b) {
+  if (b <= 4096) return (b + 255) & ~size_t(255);
+  const int e = 63 - __builtin_clzll(b);
+  const size_t step = size_t(1) << (e - 3);
+  return (b + step - 1) / step * step;
+}
+
+AllocScope::AllocScope(hipStream_t s) {
+  if (t_cache && t_cache->s == s) return;   // join the active scope
+  c_ = new Cache();
+  c_->s = s;
+  c_->prev = t_cache;
+  t_cache = c_;
+  owner_ = true;
+}
+
+AllocScope::~AllocScope() {
+  if (!owner_) return;
+  c_->trim();
+  t_cache = c_->prev;
+  delete c_;
+}
+
+Staging* scope_staging(hipStream_t s) {
+  return (t_cache && t_cache->s == s) ? &t_cache->st : nullptr;
+}
+
 void* dev_alloc(size_t bytes, hipStream_t s) {
   int dev = 0;
   BF_HIP(hipGetDevice(&dev));
-  if (dev >= 0 && dev < 64) {
-    std::call_once(g_pool_once[dev], [dev]() {
-      hipMemPool_t pool;
-      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-      }
-    });
-  }
+  ensure_pool(dev);
   void* p = nullptr;
-  BF_HIP(hipMallocAsync(&p, bytes, s));
+  AllocScope::Cache* c = t_cache;
+  if (c && c->s == s) {
+    const size_t want = round_block(bytes);
+    auto it = c->free_.lower_bound(want);
+    if (it != c->free_.end() && it->first <= 2 * want) {
+      p = it->second;
+      c->free_bytes -= it->first;
+      c->free_.erase(it);
+    } else {
+      if (c->free_bytes > kScopeFreeLimit) c->trim();
+      hipError_t e = hipMallocAsync(&p, want, s);
+      if (e != hipSuccess && !c->free_.empty()) {   // give the pool our spare blocks, retry
+        (void)hipGetLastError();
+        c->trim();
+        e = hipMallocAsync(&p, want, s);
+      }
+      BF_HIP(e);
+      c->cap_[p] = want;
+    }
+  } else {
+    BF_HIP(hipMallocAsync(&p, bytes, s));
+  }
   if (validating()) {
     std::lock_guard<std::mutex> lk(g_reg_mu);
     g_reg[reinterpret_cast<uintptr_t>(p)] = bytes;
@@ -101,6 +173,15 @@ void dev_free(void* p, hipStream_t s) {
   if (validating()) {
     std::lock_guard<std::mutex> lk(g_reg_mu);
     g_reg.erase(reinterpret_cast<uintptr_t>(p));
+  }
+  AllocScope::Cache* c = t_cache;
+  if (c && c->s == s) {
+    auto it = c->cap_.find(p);
+    if (it != c->cap_.end()) {
+      c->free_.emplace(it->second, p);
+      c->free_bytes += it->second;
+      return;
+    }
   }
   (void)hipFreeAsync(p, s);
 }
@@ -371,6 +452,7 @@ int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64
   bf_factors* F = nullptr;
   int rc = guarded([&] {
     check_device();
+    AllocScope scope((hipStream_t)stream);
     F = construct(matvec, rmatvec, user, m, n, tol, leaf, opts, (hipStream_t)stream);
   });
   if (rc == BF_OK) *out = F;
@@ -382,7 +464,10 @@ int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64
   if (!F || !X || !Y || ncols < 0 || (trans != 0 && trans != 1)) return BF_EINVAL;
   const int64_t rin = trans ? F->m : F->n, rout = trans ? F->n : F->m;
   if (ldx < rin || ldy < rout) return BF_EINVAL;
-  return guarded([&] { apply_factors(F, trans, X, ldx, ncols, Y, ldy, (hipStream_t)stream); });
+  return guarded([&] {
+    AllocScope scope((hipStream_t)stream);
+    apply_factors(F, trans, X, ldx, ncols, Y, ldy, (hipStream_t)stream);
+  });
 }
 
 int bf_stats(const bf_factors* F, bf_info* info) {

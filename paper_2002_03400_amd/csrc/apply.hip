@@ -137,6 +137,34 @@ __global__ __launch_bounds__(256) void apply_blocked_kernel(const ApplyBlk* __re
 
 constexpr size_t AP_LDS_LIMIT = 160 * 1024;
 
+// One workgroup per block: row r of block b multiplies packed row r of its
+// factor slice by the block's input rows and writes output row out_row + r.
+__global__ void expand_rows_kernel(const ApplyBlk* __restrict__ blks,
+                                   ApplyRowRec* __restrict__ rows) {
+  const ApplyBlk b = blks[blockIdx.x];
+  const int KK = b.K0 + b.K1;
+  for (int r = threadIdx.x; r < b.M; r += blockDim.x) {
+    ApplyRowRec rr{};
+    rr.g = b.g_off + (int64_t)r * KK;
+    rr.in0 = b.in_row0;
+    rr.in1 = b.in_row1 - b.K0;
+    rr.out = b.out_row + r;
+    rr.K0 = b.K0;
+    rr.KK = KK;
+    rr.out_buf = b.out_buf;
+    rr.in_buf0 = b.in_buf0;
+    rr.in_buf1 = b.in_buf1;
+    rows[b.row_rec + r] = rr;
+  }
+}
+
+void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* rows_dev,
+                        hipStream_t s) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(expand_rows_kernel, dim3((unsigned)nblk), dim3(64), 0, s, blks_dev, rows_dev);
+  BF_HIP(hipGetLastError());
+}
+
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
                         int32_t nrows, int32_t maxMK, int32_t maxKK, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,

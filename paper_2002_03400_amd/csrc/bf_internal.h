@@ -62,6 +62,34 @@ struct ProfScope {
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
 
+struct Staging;
+// Recycling scope of one request.  While an AllocScope is alive on a thread,
+// device blocks the thread allocates and frees on the scope's stream are kept
+// and handed out again (best fit, at most twice the request, sizes rounded
+// to 1/8 of their power of two) instead of going through the pool's
+// allocation calls, whose host cost (tens of microseconds each) would
+// otherwise sit between dependent launches; uploads share the scope's pinned
+// staging.  Reuse is safe because every use of a block is ordered on the one
+// stream.  The scope returns its free blocks to the pool when it ends (blocks
+// still in use, such as factor storage, are freed to the pool by their
+// owners).  A scope opened while one for the same stream is active on the
+// thread joins it.
+class AllocScope {
+ public:
+  explicit AllocScope(hipStream_t s);
+  ~AllocScope();
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+  struct Cache;
+
+ private:
+  Cache* c_ = nullptr;
+  bool owner_ = false;
+};
+// Pinned staging of the active scope on stream s of this thread, or nullptr.
+// Its users reset it only after synchronizing s.
+Staging* scope_staging(hipStream_t s);
+
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
@@ -182,6 +210,7 @@ struct ApplyBlk {
   int64_t g_off;      // element offset of the packed block (row-major, M x (K0+K1))
   int64_t out_row;
   int64_t in_row0, in_row1;
+  int64_t row_rec;    // index of the block's first row record
   int32_t M, K0, K1;
   int8_t out_buf, in_buf0, in_buf1, pad;
 };
@@ -193,6 +222,9 @@ struct ApplyRowRec {
   int32_t K0, KK;
   int8_t out_buf, in_buf0, in_buf1, pad[5];
 };
+// Writes the row records of every block (rows[b.row_rec + r], r < b.M).
+void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* rows_dev,
+                        hipStream_t s);
 // maxMK / maxKK: largest M*(K0+K1) and K0+K1 over the stage's blocks.
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
                         int32_t nrows, int32_t maxMK, int32_t maxKK, const bf_c64* G,

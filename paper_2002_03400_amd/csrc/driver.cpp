@@ -91,7 +91,9 @@ class Builder {
   int p_ = 2, r0_ = 4, cap_ = 0;
   uint64_t seed_ = 0;
   bf_factors* F_;
-  Staging st_;
+  Staging own_st_;
+  // uploads go through the request scope's pinned staging when there is one
+  Staging& st_ = scope_staging(s_) ? *scope_staging(s_) : own_st_;
   int64_t mv_cols_ = 0, rmv_cols_ = 0;
   int v_iters_ = 0, u_iters_ = 0;
 

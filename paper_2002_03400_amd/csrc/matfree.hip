@@ -551,8 +551,15 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
     kpad = offs[2 * (size_t)nseg + 1];
   }
   DevBuf<int64_t> seg_dev(offs.size(), s);
-  BF_HIP(hipMemcpyAsync(seg_dev.p, offs.data(), offs.size() * sizeof(int64_t),
-                        hipMemcpyHostToDevice, s));
+  if (Staging* st = scope_staging(s)) {
+    // pinned source: the copy does not wait for the stream to drain
+    void* h = st->alloc(offs.size() * sizeof(int64_t), s);
+    std::memcpy(h, offs.data(), offs.size() * sizeof(int64_t));
+    BF_HIP(hipMemcpyAsync(seg_dev.p, h, offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  } else {
+    BF_HIP(hipMemcpyAsync(seg_dev.p, offs.data(), offs.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+  }
   const int64_t* pofs_dev = seg_dev.p + nseg + 1;
   const int64_t ycols = (int64_t)nseg * ncols;
   g_matfree_nin = segv[nseg] - segv[0];

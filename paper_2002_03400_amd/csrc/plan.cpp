@@ -47,7 +47,7 @@ struct TermSpec {
 struct PlanBuilder {
   const bf_factors* F;
   std::vector<ApplyBlk> blks;
-  std::vector<ApplyRowRec> rows;
+  int64_t nrows = 0;   // row records (expanded from the blocks on the device)
   std::vector<PackDesc> packs;
   std::vector<Stage> stages;
   int64_t goff = 0;
@@ -57,7 +57,7 @@ struct PlanBuilder {
   void begin(int in, int out) {
     cur = Stage{};
     cur.blk_off = (int64_t)blks.size();
-    cur.row_off = (int64_t)rows.size();
+    cur.row_off = nrows;
     cur_in = in;
     cur_out = out;
   }
@@ -90,20 +90,9 @@ struct PlanBuilder {
       koff += t[q].K;
     }
     goff += (int64_t)M * KK;
+    bk.row_rec = nrows;
+    nrows += M;
     blks.push_back(bk);
-    for (int r = 0; r < M; ++r) {
-      ApplyRowRec rr{};
-      rr.g = bk.g_off + (int64_t)r * KK;
-      rr.in0 = bk.in_row0;
-      rr.in1 = bk.in_row1 - K0;
-      rr.out = out_row + r;
-      rr.K0 = K0;
-      rr.KK = KK;
-      rr.out_buf = bk.out_buf;
-      rr.in_buf0 = bk.in_buf0;
-      rr.in_buf1 = bk.in_buf1;
-      rows.push_back(rr);
-    }
     cur.nrows += M;
     cur.nblk += 1;
     cur.maxMK = std::max(cur.maxMK, M * KK);
@@ -133,10 +122,12 @@ void finish(PlanBuilder& pb, ApplyPlan& plan, int64_t tmp_rows, hipStream_t s,
         check_extent(p.src, ((size_t)(c - 1) * p.src_ld + r) * sizeof(bf_c128), "pack source");
     }
   }
-  Staging st;
+  Staging local;
+  Staging& st = scope_staging(s) ? *scope_staging(s) : local;
   plan.G = DevBuf<bf_c64>((size_t)std::max<int64_t>(pb.goff, 1), s);
   plan.blks = upload(pb.blks, s, st);
-  plan.rows = upload(pb.rows, s, st);
+  plan.rows = DevBuf<ApplyRowRec>((size_t)std::max<int64_t>(pb.nrows, 1), s);
+  launch_expand_rows(plan.blks.p, (int32_t)pb.blks.size(), plan.rows.p, s);
   plan.stages = pb.stages;
   plan.tmp_rows = std::max<int64_t>(tmp_rows, 1);
   for (size_t o = 0; o < pb.packs.size(); o += 60000) {
@@ -147,6 +138,7 @@ void finish(PlanBuilder& pb, ApplyPlan& plan, int64_t tmp_rows, hipStream_t s,
     launch_pack_c64(dd.p, (int32_t)cnt, plan.G.p, s);
   }
   BF_HIP(hipStreamSynchronize(s));
+  st.reset();
 }
 
 }  // namespace
