@@ -111,7 +111,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None) -> Factors:
     while True:
         cap(r)
         s = r + p
-        G = philox.gaussian_block(seed, philox.tag(philox.PHASE_V0, it, 0), 0, m, s)
+        G = philox.sample_block(seed, philox.tag(philox.PHASE_V0, it, 0), 0, m, s)
         Yp = op.rmatvec(G)
         cols["rmatvec"] += s
         F.V = []
@@ -131,7 +131,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None) -> Factors:
     while True:
         cap(r)
         s = r + p
-        Om = philox.gaussian_block(seed, philox.tag(philox.PHASE_U0, it, 0), 0, n, s)
+        Om = philox.sample_block(seed, philox.tag(philox.PHASE_U0, it, 0), 0, n, s)
         Y = op.matvec(Om)
         cols["matvec"] += s
         F.U = []
@@ -153,7 +153,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None) -> Factors:
                     for j in range(1 << (L - l))) + p
             lo, hi = F.trange(l, i)
             G = np.zeros((m, s), np.complex128)
-            G[lo:hi] = philox.gaussian_block(seed, philox.tag(philox.PHASE_W, l, i), lo, hi - lo, s)
+            G[lo:hi] = philox.sample_block(seed, philox.tag(philox.PHASE_W, l, i), lo, hi - lo, s)
             Yp = op.rmatvec(G, support=(lo, hi))
             cols["rmatvec"] += s
             # V-chain^H: V^0 then W^1 .. W^{l-1} on the T-ancestors of tau
@@ -178,7 +178,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None) -> Factors:
             s += p
             lo, hi = F.srange(L - l, j)
             Om = np.zeros((n, s), np.complex128)
-            Om[lo:hi] = philox.gaussian_block(seed, philox.tag(philox.PHASE_R, l, j), lo, hi - lo, s)
+            Om[lo:hi] = philox.sample_block(seed, philox.tag(philox.PHASE_R, l, j), lo, hi - lo, s)
             Y = op.matvec(Om, support=(lo, hi))
             cols["matvec"] += s
             # U-chain^H: U^L then R^{L-1} .. R^{l+1} on the S-ancestors of nu
@@ -203,7 +203,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None) -> Factors:
     if L == 0:
         # single block: A ~ U B V^H with the leaf bases themselves
         s = max(F.kU[0][(0, 0)], F.kV[0][(0, 0)]) + p
-        Om = philox.gaussian_block(seed, philox.tag(philox.PHASE_R, 0, 0), 0, n, s)
+        Om = philox.sample_block(seed, philox.tag(philox.PHASE_R, 0, 0), 0, n, s)
         Y = op.matvec(Om)
         cols["matvec"] += s
         C = _H(F.U[0]) @ Y
