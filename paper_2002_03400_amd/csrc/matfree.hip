@@ -249,19 +249,21 @@ __global__ __launch_bounds__(MF_THREADS) void matfree_kernel(
 
 // ---- split-BF16 kernel --------------------------------------------------
 //
-// The same product on the BF16 matrix cores (v_mfma_f32_32x32x16_bf16), which
+// The same product on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16), which
 // on gfx950 run concurrently with the vector ALUs that evaluate the entries
 // (the FP32/FP64 matrix instructions do not).  Every entry a and input x is
 // split into three BF16 terms, a = a1 + a2 + a3 (a1 = bf16(a),
 // a2 = bf16(a - a1), a3 = bf16(a - a1 - a2)), and the products keep every
 // term down to 2^-24 relative:  a x ~ a1x1 + a1x2 + a2x1 + a1x3 + a3x1 + a2x2
 // -- six MFMAs per real product, 24 per complex tile step
-// (Re += ar xr - ai xi, Im += ar xi + ai xr).  A wave owns 32 rows x 32 NT
-// columns; per step of 16 inner points lane l evaluates its 8 A-operand
-// entries (row l % 32, inner points 8 (l / 32) .. +7) and reads its B operands
-// (8 inner points of column l % 32) from the split planes staged in LDS.
-// Each step's FP32 tile sums (16 terms) are added into FP64 registers, so the
-// only FP32 summation error is that of 16-term sums.
+// (Re += ar xr - ai xi, Im += ar xi + ai xr).  A wave owns 16 rows x 16 NT
+// columns; per step of 32 inner points lane l evaluates its 8 A-operand
+// entries (row l % 16, inner points 8 (l / 16) .. +7) and reads its B operands
+// (the same 8 inner points of column l % 16 of each 16-column tile) from the
+// split planes staged in LDS.  Each step's FP32 tile sums (32 terms) are
+// added into FP64 registers, so the only FP32 summation error is that of
+// 32-term sums.  Sixteen-column tiles keep the padding of odd sample widths
+// (the adaptive passes use r + p columns) to less than 16 columns.
 //
 // X is split once per call (split_planes_kernel) into six BF16 planes laid
 // out per column along the inner index, each segment padded with zeros to a
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(MF_THREADS) void matfree_kernel(
 // entries are evaluated at a clamped (valid) inner point.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
@@ -292,55 +294,78 @@ __device__ __forceinline__ void split3_pk(float x0, float x1, uint32_t& h, uint3
 
 constexpr int BF_TK = 64;            // inner points per staged chunk (4 MFMA steps)
 constexpr int BF_KP = BF_TK + 8;     // padded k stride of the split planes (bank spread)
-constexpr int BF_WAVES = 4;
-constexpr int BF_ROWS = 32 * BF_WAVES;
+constexpr int BF_WAVES = 8;
+constexpr int BF_ROWS = 16 * BF_WAVES;
 constexpr int BF_PLANES = 6;         // (term 0..2) x (re, im)
 
 // Xp[(c * 6 + 2 term + part) * kpad + pofs[g] + (j - seg[g])] = term of
 // X[j, c] (part 0 real, 1 imaginary); zero from seg[g+1] to pofs[g+1].
-// One thread splits 8 consecutive inner points of one column.
+// One thread splits 8 consecutive inner points of one column.  *inexact
+// (zero on entry) becomes nonzero if any value needs more than its first
+// term, i.e. if X is not exactly representable in BF16.
 __global__ void split_planes_kernel(const bf_c64* __restrict__ X, int64_t ldx,
                                     const int64_t* __restrict__ seg,
                                     const int64_t* __restrict__ pofs, int64_t kpad,
-                                    uint16_t* __restrict__ Xp) {
+                                    uint16_t* __restrict__ Xp,
+                                    unsigned long long* __restrict__ inexact) {
   const int g = blockIdx.y, c = blockIdx.z;
   const int64_t kk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
-  if (kk >= pofs[g + 1] - pofs[g]) return;
-  const int64_t j0 = seg[g] + kk, j1 = seg[g + 1];
-  const bf_c64* xc = X + (int64_t)c * ldx;
-  u32x4 t[BF_PLANES];
+  const bool live = kk < pofs[g + 1] - pofs[g];
+  uint32_t rest = 0;
+  if (live) {
+    const int64_t j0 = seg[g] + kk, j1 = seg[g + 1];
+    const bf_c64* xc = X + (int64_t)c * ldx;
+    u32x4 t[BF_PLANES];
 #pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    bf_c64 x0 = {0.f, 0.f}, x1 = {0.f, 0.f};
-    if (j0 + 2 * d < j1) x0 = xc[j0 + 2 * d];
-    if (j0 + 2 * d + 1 < j1) x1 = xc[j0 + 2 * d + 1];
-    uint32_t h, m, l;
-    split3_pk(x0.re, x1.re, h, m, l);
-    t[0][d] = h; t[2][d] = m; t[4][d] = l;
-    split3_pk(x0.im, x1.im, h, m, l);
-    t[1][d] = h; t[3][d] = m; t[5][d] = l;
+    for (int d = 0; d < 4; ++d) {
+      bf_c64 x0 = {0.f, 0.f}, x1 = {0.f, 0.f};
+      if (j0 + 2 * d < j1) x0 = xc[j0 + 2 * d];
+      if (j0 + 2 * d + 1 < j1) x1 = xc[j0 + 2 * d + 1];
+      uint32_t h, m, l;
+      split3_pk(x0.re, x1.re, h, m, l);
+      t[0][d] = h; t[2][d] = m; t[4][d] = l;
+      split3_pk(x0.im, x1.im, h, m, l);
+      t[1][d] = h; t[3][d] = m; t[5][d] = l;
+    }
+    uint16_t* dst = Xp + (int64_t)c * BF_PLANES * kpad + pofs[g] + kk;
+#pragma unroll
+    for (int p = 0; p < BF_PLANES; ++p) *reinterpret_cast<u32x4*>(dst + p * kpad) = t[p];
+#pragma unroll
+    for (int p = 2; p < BF_PLANES; ++p) rest |= t[p][0] | t[p][1] | t[p][2] | t[p][3];
   }
-  uint16_t* dst = Xp + (int64_t)c * BF_PLANES * kpad + pofs[g] + kk;
-#pragma unroll
-  for (int p = 0; p < BF_PLANES; ++p) *reinterpret_cast<u32x4*>(dst + p * kpad) = t[p];
+  // one vector atomic per wave that saw a nonzero lower term
+  const unsigned long long any = __ballot(rest != 0u);
+  if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(inexact, 1ull);
 }
 
-template <class E, int NT, typename Tout>
-__global__ __launch_bounds__(64 * BF_WAVES) void matfree_bf16_kernel(
+// Two instantiations per shape: EXACT (X exact in BF16, e.g. the random
+// blocks of Alg. 2, so x = x1 and a real product needs the three MFMAs
+// a1x1 + a2x1 + a3x1) and general (six).  Both are launched; the one that
+// does not match the flag written by split_planes_kernel exits at once.
+// Four waves per SIMD (at most 128 VGPRs): for the 48- and 64-column tiles
+// of the general path this costs a few spilled registers outside the inner
+// loop and is still ~25% faster than the two waves their unconstrained
+// register count allows.
+template <class E, int NT, typename Tout, bool EXACT>
+__global__ __launch_bounds__(64 * BF_WAVES) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void matfree_bf16_kernel(
     E e, int64_t nout, const uint16_t* __restrict__ Xp, int64_t kpad, int32_t ncols, int32_t c0,
     int32_t width, Tout* __restrict__ Y, int64_t ldy, int64_t ycols,
-    const int64_t* __restrict__ seg, const int64_t* __restrict__ pofs, int32_t nsplit) {
-  constexpr int NC = 32 * NT;
+    const int64_t* __restrict__ seg, const int64_t* __restrict__ pofs, int32_t nsplit,
+    const unsigned long long* __restrict__ inexact) {
+  if ((*inexact == 0ull) != EXACT) return;
+  constexpr int NC = 16 * NT;
+  constexpr int NTERM = EXACT ? 1 : 3;      // staged terms of X
   __shared__ typename E::Col cols[BF_TK];
-  // split planes: [term 0..2][re/im][column][k], 16 bytes = 8 consecutive k
-  __shared__ __attribute__((aligned(16))) uint16_t xs[3][2][NC][BF_KP];
+  // split planes: [term][re/im][column][k], 16 bytes = 8 consecutive k
+  __shared__ __attribute__((aligned(16))) uint16_t xs[NTERM][2][NC][BF_KP];
   const int g = blockIdx.y;
   const int z = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t row0 = (int64_t)blockIdx.x * BF_ROWS + wave * 32;
-  const int64_t myrow = row0 + (lane & 31);
-  const int kh = lane >> 5;       // which 8 of the step's 16 inner points
-  const int lc = lane & 31;
+  const int64_t row0 = (int64_t)blockIdx.x * BF_ROWS + wave * 16;
+  const int64_t myrow = row0 + (lane & 15);
+  const int kq = lane >> 4;       // which 8 of the step's 32 inner points
+  const int lc = lane & 15;
   const int64_t j0 = seg[g], j1 = seg[g + 1];
   const int64_t len = j1 - j0;
   // split-K slices are whole chunks, so only a segment's last chunk is ragged
@@ -350,18 +375,18 @@ __global__ __launch_bounds__(64 * BF_WAVES) void matfree_bf16_kernel(
   const int nc = width < NC ? width : NC;
   const uint16_t* xg = Xp + (int64_t)c0 * BF_PLANES * kpad + pofs[g] - j0;
 
-  double fr[NT][16], fi[NT][16];
+  double fr[NT][4], fi[NT][4];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) { fr[t][v] = 0.0; fi[t][v] = 0.0; }
+    for (int v = 0; v < 4; ++v) { fr[t][v] = 0.0; fi[t][v] = 0.0; }
   const typename E::Row rw = e.row(myrow < nout ? myrow : nout - 1);
 
   for (int64_t jb = a; jb < b; jb += BF_TK) {
     __syncthreads();
-    // NC columns x 6 planes x 8 copies of 16 bytes
-    for (int idx = threadIdx.x; idx < NC * BF_PLANES * 8; idx += 64 * BF_WAVES) {
-      const int q8 = idx & 7, pl = (idx >> 3) % BF_PLANES, c = (idx >> 3) / BF_PLANES;
+    // NC columns x (2 NTERM) planes x 8 copies of 16 bytes
+    for (int idx = threadIdx.x; idx < NC * 2 * NTERM * 8; idx += 64 * BF_WAVES) {
+      const int q8 = idx & 7, pl = (idx >> 3) % (2 * NTERM), c = (idx >> 3) / (2 * NTERM);
       u32x4 v = {0u, 0u, 0u, 0u};
       if (c < nc)
         v = *reinterpret_cast<const u32x4*>(xg + ((int64_t)c * BF_PLANES + pl) * kpad + jb + 8 * q8);
@@ -372,9 +397,9 @@ __global__ __launch_bounds__(64 * BF_WAVES) void matfree_bf16_kernel(
       cols[threadIdx.x] = e.col(j < j1 ? j : j1 - 1);
     }
     __syncthreads();
-    const int nsteps = (int)((b - jb < BF_TK ? b - jb : BF_TK) + 15) >> 4;
+    const int nsteps = (int)((b - jb < BF_TK ? b - jb : BF_TK) + 31) >> 5;
     for (int q = 0; q < nsteps; ++q) {
-      const int kb = 16 * q + 8 * kh;
+      const int kb = 32 * q + 8 * kq;
       cf ev[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) ev[u] = e.entry(rw, cols[kb + u]);
@@ -391,40 +416,45 @@ __global__ __launch_bounds__(64 * BF_WAVES) void matfree_bf16_kernel(
       for (int p = 0; p < 3; ++p) an[p] = ai[p] ^ 0x80008000u;   // -ai, both halves
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        u32x4 xr[3], xi[3];
+        u32x4 xr[NTERM], xi[NTERM];
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-          xr[p] = *reinterpret_cast<const u32x4*>(&xs[p][0][t * 32 + lc][kb]);
-          xi[p] = *reinterpret_cast<const u32x4*>(&xs[p][1][t * 32 + lc][kb]);
+        for (int p = 0; p < NTERM; ++p) {
+          xr[p] = *reinterpret_cast<const u32x4*>(&xs[p][0][t * 16 + lc][kb]);
+          xi[p] = *reinterpret_cast<const u32x4*>(&xs[p][1][t * 16 + lc][kb]);
         }
-        floatx16 R = {}, I = {};
-        // term pairs (p, q) with p + q <= 2 (0-based): 20 02 11 10 01 00
+        floatx4 R = {}, I = {};
 #define BF_MM(A, B, C) \
-  C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A), \
+  C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A), \
                                               __builtin_bit_cast(bf16x8, B), C, 0, 0, 0);
 #define BF_PAIR(P, Q) BF_MM(ar[P], xr[Q], R) BF_MM(an[P], xi[Q], R) \
                       BF_MM(ar[P], xi[Q], I) BF_MM(ai[P], xr[Q], I)
-        BF_PAIR(2, 0) BF_PAIR(0, 2) BF_PAIR(1, 1) BF_PAIR(1, 0) BF_PAIR(0, 1) BF_PAIR(0, 0)
+        if constexpr (EXACT) {
+          // x = x1: a1x1 + a2x1 + a3x1, smallest first
+          BF_PAIR(2, 0) BF_PAIR(1, 0) BF_PAIR(0, 0)
+        } else {
+          // term pairs (p, q) with p + q <= 2 (0-based): 20 02 11 10 01 00
+          BF_PAIR(2, 0) BF_PAIR(0, 2) BF_PAIR(1, 1) BF_PAIR(1, 0) BF_PAIR(0, 1) BF_PAIR(0, 0)
+        }
 #undef BF_PAIR
 #undef BF_MM
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
+        for (int v = 0; v < 4; ++v) {
           fr[t][v] += (double)R[v];
           fi[t][v] += (double)I[v];
         }
       }
     }
   }
-  // accumulator layout of a 32x32 MFMA tile on gfx950: lane l, register v
-  // holds row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+  // accumulator layout of a 16x16 MFMA tile on gfx950: lane l, register v
+  // holds row 4 (l / 16) + v, column l % 16
   Tout* yz = Y + (int64_t)z * ycols * ldy + ((int64_t)g * ncols + c0) * ldy;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int c = t * 32 + lc;
+    const int c = t * 16 + lc;
     if (c < nc) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t r = row0 + 8 * (v >> 2) + 4 * kh + (v & 3);
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = row0 + 4 * kq + v;
         if (r < nout) {
           Tout o;
           o.re = fr[t][v];
@@ -483,14 +513,18 @@ template <class E, int NT, typename Tout>
 static void launch_bf16(const E& e, int64_t nout, const uint16_t* Xp, int64_t kpad, int32_t ncols,
                         int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
                         const int64_t* seg_dev, const int64_t* pofs_dev, int32_t nseg,
-                        int32_t nsplit, hipStream_t s) {
+                        int32_t nsplit, const unsigned long long* inexact, hipStream_t s) {
   dim3 grid((unsigned)((nout + BF_ROWS - 1) / BF_ROWS), (unsigned)nseg, (unsigned)nsplit);
-  const double nc = (double)std::min<int32_t>(32 * NT, width);
+  const double nc = (double)std::min<int32_t>(16 * NT, width);
   const double nin = (double)g_matfree_nin;
   ProfScope ps(BF_KC_MATFREE, s, 8.0 * (double)nout * nin * nc,
                8.0 * nc * (nin + (double)nout * nseg));
-  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout>), grid, dim3(64 * BF_WAVES), 0, s, e, nout,
-                     Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nsplit);
+  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout, true>), grid, dim3(64 * BF_WAVES), 0, s, e,
+                     nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nsplit,
+                     inexact);
+  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout, false>), grid, dim3(64 * BF_WAVES), 0, s, e,
+                     nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nsplit,
+                     inexact);
   BF_HIP(hipGetLastError());
 }
 
@@ -498,13 +532,20 @@ template <class E, typename Tout>
 static void launch_chunk_bf16(const E& e, int64_t nout, const uint16_t* Xp, int64_t kpad,
                               int32_t ncols, int32_t c0, int32_t width, Tout* Y, int64_t ldy,
                               int64_t ycols, const int64_t* seg_dev, const int64_t* pofs_dev,
-                              int32_t nseg, int32_t nsplit, hipStream_t s) {
-  if (width <= 32)
+                              int32_t nseg, int32_t nsplit, const unsigned long long* inexact,
+                              hipStream_t s) {
+  if (width <= 16)
     launch_bf16<E, 1>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
-                      nsplit, s);
-  else
+                      nsplit, inexact, s);
+  else if (width <= 32)
     launch_bf16<E, 2>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
-                      nsplit, s);
+                      nsplit, inexact, s);
+  else if (width <= 48)
+    launch_bf16<E, 3>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
+                      nsplit, inexact, s);
+  else
+    launch_bf16<E, 4>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
+                      nsplit, inexact, s);
 }
 
 template <class E>
@@ -549,6 +590,7 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
       maxpad = std::max(maxpad, padded);
     }
     kpad = offs[2 * (size_t)nseg + 1];
+    offs.push_back(0);   // the inexact flag of split_planes_kernel
   }
   DevBuf<int64_t> seg_dev(offs.size(), s);
   if (Staging* st = scope_staging(s)) {
@@ -561,6 +603,7 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
                           hipMemcpyHostToDevice, s));
   }
   const int64_t* pofs_dev = seg_dev.p + nseg + 1;
+  auto* inexact = bf16 ? reinterpret_cast<unsigned long long*>(seg_dev.p + offs.size() - 1) : nullptr;
   const int64_t ycols = (int64_t)nseg * ncols;
   g_matfree_nin = segv[nseg] - segv[0];
 
@@ -570,7 +613,7 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
     ProfScope ps(BF_KC_OTHER, s, 0.0, 8.0 * ncols * (double)g_matfree_nin + 12.0 * ncols * kpad);
     dim3 grid((unsigned)((maxpad / 8 + 255) / 256), (unsigned)nseg, (unsigned)ncols);
     hipLaunchKernelGGL(split_planes_kernel, grid, dim3(256), 0, s, X, ldx, seg_dev.p, pofs_dev,
-                       kpad, planes.p);
+                       kpad, planes.p, inexact);
     BF_HIP(hipGetLastError());
   }
 
@@ -584,10 +627,10 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
     if (bf16) {
       if (nsplit > 1)
         launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, part.p, nout,
-                          ycols, seg_dev.p, pofs_dev, nseg, nsplit, s);
+                          ycols, seg_dev.p, pofs_dev, nseg, nsplit, inexact, s);
       else
         launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols,
-                          seg_dev.p, pofs_dev, nseg, nsplit, s);
+                          seg_dev.p, pofs_dev, nseg, nsplit, inexact, s);
     } else {
       if (nsplit > 1)
         launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, part.p, nout, ycols,

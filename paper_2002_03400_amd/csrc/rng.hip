@@ -7,7 +7,9 @@
 //   g = sqrt(-2 ln u_0) (cos 2 pi u_1 + i sin 2 pi u_1) / sqrt(2)
 // Philox4x64-10 follows Salmon et al., SC'11 (published multipliers and Weyl
 // key increments).  The draw is therefore independent of launch order, grid
-// shape and of which other requests share the device.
+// shape and of which other requests share the device.  The random matrices
+// of the construction round each part of g to the nearest BF16 value (ties
+// to even), so the black-box products can take them as exact BF16 operands.
 #include "bf_internal.h"
 #include "cplx.h"
 
@@ -39,6 +41,15 @@ __device__ cd gauss_entry(uint64_t seed, uint64_t tag, uint64_t row, uint64_t co
   return cd{rad * co, rad * s};
 }
 
+// Nearest BF16 value of an FP64 value (8 significant bits, ties to even),
+// by integer rounding of the 52-bit fraction to 7 bits.
+__device__ __forceinline__ double round_bf16(double x) {
+  const uint64_t drop = (uint64_t(1) << 45) - 1, half = (uint64_t(1) << 44) - 1;
+  uint64_t b = (uint64_t)__double_as_longlong(x);
+  b = (b + half + ((b >> 45) & 1)) & ~drop;
+  return __longlong_as_double((long long)b);
+}
+
 // One thread per entry of a column: grid (ceil(rows/256), ncols).
 __global__ void gauss_samples_kernel(bf_c64* X, int64_t rows, int64_t ncols, int32_t level,
                                      const uint64_t* tags, const int32_t* widths, uint64_t seed) {
@@ -50,8 +61,8 @@ __global__ void gauss_samples_kernel(bf_c64* X, int64_t rows, int64_t ncols, int
   bf_c64 out = {0.f, 0.f};
   if (c < widths[g]) {
     cd v = gauss_entry(seed, tags[g], (uint64_t)r, (uint64_t)c);
-    out.re = (float)v.re;
-    out.im = (float)v.im;
+    out.re = (float)round_bf16(v.re);   // exact: 8 significant bits
+    out.im = (float)round_bf16(v.im);
   }
   X[c * rows + r] = out;
 }

@@ -135,6 +135,37 @@ def test_segkernel_wide_and_split(bf):
     assert _rel(Y, ref.matvec(X)) < 3e-6
 
 
+@pytest.mark.parametrize("ncols", [5, 23, 40, 64])
+def test_segkernel_bf16_exact_inputs(bf, ncols):
+    """Inputs exact in BF16 (the construction's random blocks) take the
+    three-product path, general inputs the six-product path, a mix the general
+    one; all agree with the FP64 products (ragged chunks, split-K, every tile
+    width)."""
+    from oracle import philox
+    m, n = 517, 9000
+    g = wl.segment_pair(n, ppw=8.0, m=m)
+    say("segkernel exact inputs", ncols)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    ref = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    X = _cg(np.random.default_rng(ncols), n, ncols)
+    Xb = philox.round_bf16(X.real) + 1j * philox.round_bf16(X.imag)
+    Xm = Xb.copy()
+    Xm[1234, ncols - 1] = X[1234, ncols - 1]
+    for Z in (Xb, X, Xm):
+        Y = op.matvec(_t(Z)).cpu().numpy()
+        E = ref.matvec(Z)
+        assert _rel(Y, E) < 5e-7
+        # column by column: no column is computed on a stale or wrong path
+        for c in range(ncols):
+            assert np.linalg.norm(Y[:, c] - E[:, c]) <= 1e-6 * np.linalg.norm(E[:, c])
+    Ys = op.rmatvec(_t(Xb[:m]), seg=np.array([0, 17, 300, m], np.int64)).cpu().numpy()
+    for q, (lo, hi) in enumerate([(0, 17), (17, 300), (300, m)]):
+        Zq = np.zeros((m, ncols), complex)
+        Zq[lo:hi] = Xb[lo:hi]
+        exp = ref.rmatvec(Zq)
+        assert _rel(Ys[:, q * ncols:(q + 1) * ncols], exp) < 5e-7
+
+
 def test_fio_products(bf):
     n = 2048
     x, xi = wl.fio_params(n)
