@@ -173,9 +173,10 @@ struct GemmDesc {
   int32_t pad;
   GemmTerm t[2];
 };
-// in_c64: the inputs are complex64 (samples straight from the black box).
-void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, bool in_c64,
-                       hipStream_t s);
+// in_c64: the inputs are complex64 (samples straight from the black box);
+// max_M bounds every descriptor's M.
+void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, int32_t max_M,
+                       bool in_c64, hipStream_t s);
 
 // Batched truncated column-pivoted QR (Alg. 1 step 3) on FP64.
 struct QRDesc {

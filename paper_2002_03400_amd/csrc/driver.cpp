@@ -133,8 +133,11 @@ class Builder {
 
   void gemm(const std::vector<GemmDesc>& d, bool in_c64) {
     if (d.empty()) return;
-    int maxc = 0;
-    for (auto& x : d) maxc = std::max(maxc, x.ncols);
+    int maxc = 0, maxm = 0;
+    for (auto& x : d) {
+      maxc = std::max(maxc, x.ncols);
+      maxm = std::max(maxm, x.M);
+    }
     if (validating()) {
       const size_t isz = in_c64 ? sizeof(bf_c64) : sizeof(bf_c128);
       for (auto& x : d) {
@@ -150,7 +153,7 @@ class Builder {
       }
     }
     auto dd = upload(d, s_, st_);
-    launch_chain_gemm(dd.p, (int32_t)d.size(), maxc, in_c64, s_);
+    launch_chain_gemm(dd.p, (int32_t)d.size(), maxc, maxm, in_c64, s_);
   }
 
   // Batched Alg. 1 step 3; Q blocks go to a fresh capacity buffer that becomes

@@ -22,44 +22,93 @@ template <> __device__ __forceinline__ cd load_c<bf_c128>(const bf_c128* p) {
 }
 
 // ---------------------------------------------------------------- gemm ----
-// grid (ndesc, ceil(max_ncols / 64)); each workgroup: rows 0..M-1 of one
-// descriptor, 64 columns.  Consecutive threads take consecutive rows so the
-// output and op = 0 factor reads are coalesced.
+// grid (ndesc, ceil(max_ncols / 64)); a workgroup of 4 waves computes rows
+// 0..M-1 of one descriptor (in row blocks of 32) for 64 columns.  Lane l of
+// every wave owns column 64 blockIdx.y + l and wave w the rows w, w+4, ...
+// of the block.  op(F) is staged in LDS in chunks of 64 inner indices as
+// [k][row] and read as a broadcast; each lane reads its own input column
+// straight from global memory (contiguous along k, shared by the 4 waves
+// through L1), and writes its results directly.  The small LDS footprint
+// (32 KB) lets several workgroups per CU hide the load latency.
 constexpr int CG_COLS = 64;
+constexpr int CG_KT = 64;
+constexpr int CG_ROWS = 32;
 
 template <typename Tin>
 __global__ __launch_bounds__(256) void chain_gemm_kernel(const GemmDesc* __restrict__ descs) {
+  __shared__ cd fs[CG_KT][CG_ROWS];
   const GemmDesc d = descs[blockIdx.x];
   const int c0 = blockIdx.y * CG_COLS;
-  if (c0 >= d.ncols) return;
-  const int cw = (d.ncols - c0 < CG_COLS) ? d.ncols - c0 : CG_COLS;
-  for (int idx = threadIdx.x; idx < d.M * cw; idx += blockDim.x) {
-    const int r = idx % d.M;
-    const int c = c0 + idx / d.M;
-    cd acc = {0.0, 0.0};
+  if (c0 >= d.ncols || d.M <= 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = c0 + lane;
+  const bool live = c < d.ncols;
+  for (int rb = 0; rb < d.M; rb += CG_ROWS) {
+    const int mr = (d.M - rb < CG_ROWS) ? d.M - rb : CG_ROWS;
+    cd acc[CG_ROWS / 4];
+#pragma unroll
+    for (int i = 0; i < CG_ROWS / 4; ++i) acc[i] = cd{0.0, 0.0};
     for (int t = 0; t < d.nterm; ++t) {
-      const GemmTerm& T = d.t[t];
-      const Tin* in = static_cast<const Tin*>(T.in) + (int64_t)c * T.in_ld;
-      if (T.op == 0) {
-        for (int k = 0; k < T.K; ++k) {
-          bf_c128 f = T.F[(int64_t)k * T.f_ld + r];
-          cd_fma(acc, cd{f.re, f.im}, load_c<Tin>(in + k));
+      const GemmTerm T = d.t[t];
+      const Tin* inp = static_cast<const Tin*>(T.in) + (int64_t)(live ? c : c0) * T.in_ld;
+      for (int k0 = 0; k0 < T.K; k0 += CG_KT) {
+        const int kt = (T.K - k0 < CG_KT) ? T.K - k0 : CG_KT;
+        __syncthreads();
+        if (T.op == 0) {   // F is M x K column-major: op(F)[r][k] = F[k f_ld + r]
+          for (int idx = threadIdx.x; idx < CG_KT * CG_ROWS; idx += 256) {
+            const int r = idx % CG_ROWS, k = idx / CG_ROWS;
+            cd v = {0.0, 0.0};
+            if (r < mr && k < kt) {
+              const bf_c128 f = T.F[(int64_t)(k0 + k) * T.f_ld + rb + r];
+              v = cd{f.re, f.im};
+            }
+            fs[k][r] = v;
+          }
+        } else {           // F is K x M column-major: op(F)[r][k] = conj(F[r f_ld + k])
+          for (int idx = threadIdx.x; idx < CG_KT * CG_ROWS; idx += 256) {
+            const int k = idx % CG_KT, r = idx / CG_KT;
+            cd v = {0.0, 0.0};
+            if (r < mr && k < kt) {
+              const bf_c128 f = T.F[(int64_t)(rb + r) * T.f_ld + k0 + k];
+              v = cd{f.re, -f.im};
+            }
+            fs[k][r] = v;
+          }
         }
-      } else {
-        const bf_c128* fr = T.F + (int64_t)r * T.f_ld;
-        for (int k = 0; k < T.K; ++k) {
-          bf_c128 f = fr[k];
-          cd_cfma(acc, cd{f.re, f.im}, load_c<Tin>(in + k));
+        __syncthreads();
+        const Tin* ip = inp + k0;
+        int k = 0;
+        for (; k + 4 <= kt; k += 4) {
+          cd x[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) x[u] = load_c<Tin>(ip + k + u);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int i = 0; i < CG_ROWS / 4; ++i)
+              if (wave + 4 * i < mr) cd_fma(acc[i], fs[k + u][wave + 4 * i], x[u]);
+        }
+        for (; k < kt; ++k) {
+          const cd x = load_c<Tin>(ip + k);
+#pragma unroll
+          for (int i = 0; i < CG_ROWS / 4; ++i)
+            if (wave + 4 * i < mr) cd_fma(acc[i], fs[k][wave + 4 * i], x);
         }
       }
     }
-    d.out[(int64_t)c * d.out_ld + r] = bf_c128{acc.re, acc.im};
+    if (live) {
+      bf_c128* o = d.out + (int64_t)c * d.out_ld + rb;
+#pragma unroll
+      for (int i = 0; i < CG_ROWS / 4; ++i)
+        if (wave + 4 * i < mr) o[wave + 4 * i] = bf_c128{acc[i].re, acc[i].im};
+    }
   }
 }
 
-void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, bool in_c64,
-                       hipStream_t s) {
-  if (ndesc <= 0 || max_ncols <= 0) return;
+void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, int32_t max_M,
+                       bool in_c64, hipStream_t s) {
+  if (ndesc <= 0 || max_ncols <= 0 || max_M <= 0) return;
+  BF_CHECK((max_ncols + CG_COLS - 1) / CG_COLS <= 65535, BF_EINVAL, "chain product too wide");
   dim3 grid((unsigned)ndesc, (unsigned)((max_ncols + CG_COLS - 1) / CG_COLS));
   ProfScope ps(BF_KC_CHAIN, s, 0.0, 0.0);
   if (in_c64)
