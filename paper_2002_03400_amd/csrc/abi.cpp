@@ -333,9 +333,20 @@ static int factors_apply(void* user, int trans, const bf_c64* X, int64_t ldx, in
       apply_factors(c->F, trans, X, ldx, ncols, Y, ldy, s);
       return;
     }
-    DevBuf<bf_c64> Xe;
-    expand(X, ldx, rows_in, ncols, seg, nseg, Xe, s);
-    apply_factors(c->F, trans, Xe.p, rows_in, (int64_t)nseg * ncols, Y, ldy, s);
+    // segments in chunks: the expanded input and the apply's two intermediates
+    // take 8 (rows_in + 2 tmp_rows) bytes per expanded column; keep them
+    // under 4 GiB per chunk
+    const ApplyPlan& P = trans ? c->F->adj : c->F->fwd;
+    const double per_col = 8.0 * (double)(rows_in + 2 * P.tmp_rows);
+    const int64_t max_cols = std::max<int64_t>(ncols, (int64_t)((double)(int64_t(4) << 30) / per_col));
+    const int32_t per_chunk = (int32_t)std::max<int64_t>(1, max_cols / std::max<int64_t>(ncols, 1));
+    for (int32_t g0 = 0; g0 < nseg; g0 += per_chunk) {
+      const int32_t ng = std::min(per_chunk, nseg - g0);
+      DevBuf<bf_c64> Xe;
+      expand(X, ldx, rows_in, ncols, seg + g0, ng, Xe, s);
+      apply_factors(c->F, trans, Xe.p, rows_in, (int64_t)ng * ncols, Y + (int64_t)g0 * ncols * ldy,
+                    ldy, s);
+    }
   });
 }
 static int factors_mv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64* Y, int64_t ldy,
