@@ -318,12 +318,25 @@ int bf_operator_destroy(bf_operator* op);
  *   BF_PREC_FP64   : on the FP64 matrix cores, FP64 accumulation;
  *   BF_PREC_BF16X3 : on the BF16 matrix cores with every entry and input
  *                    split into three BF16 terms (products kept to 2^-24
- *                    relative), 16-term FP32 sums folded into FP64.  The BF16
+ *                    relative; inputs exact in BF16, such as the random
+ *                    blocks of the construction, need only their first
+ *                    term), 32-term FP32 sums folded into FP64.  The BF16
  *                    matrix cores run beside the vector ALUs that evaluate the
  *                    entries, so this mode is the faster one.
- * Default: BF_PREC_BF16X3.  Returns BF_EINVAL for other operators. */
-enum { BF_PREC_FP64 = 0, BF_PREC_BF16X3 = 1 };
+ * Default: BF_PREC_BF16X3.  Returns BF_EINVAL for other operators or values. */
+enum { BF_PREC_FP64 = 0, BF_PREC_BF16X3 = 1, BF_PREC_FP32 = 2 };
 int bf_op_set_precision(bf_operator* op, int precision);
+
+/* Arithmetic of bf_apply (and of the factors as a black box, bf_op_factors)
+ * for F (eq. hybrid_butterfly_mat, complex64 data in both modes):
+ *   BF_PREC_FP32   : FP32 multiply-adds on the vector ALUs (default);
+ *   BF_PREC_BF16X3 : stages with 16 or more right-hand sides on the BF16
+ *                    matrix cores, factor entries and inputs split into three
+ *                    BF16 terms (products kept to 2^-24 relative), FP32
+ *                    accumulation; fewer right-hand sides use the FP32 path.
+ * Not synchronized with applies in flight on F: set it before applying.
+ * Returns BF_EINVAL for a null F or another value. */
+int bf_set_apply_precision(bf_factors* F, int precision);
 
 #ifdef __cplusplus
 }

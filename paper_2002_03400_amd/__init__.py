@@ -116,6 +116,7 @@ SIGNATURES = {
                                 C.POINTER(bf_operator)]),
     "bf_operator_destroy": (C.c_int, [C.POINTER(bf_operator)]),
     "bf_op_set_precision": (C.c_int, [C.POINTER(bf_operator), C.c_int]),
+    "bf_set_apply_precision": (C.c_int, [_P, C.c_int]),
 }
 
 
@@ -308,6 +309,14 @@ class Factors:
         data = np.zeros(cnt.value, np.complex128)
         _check(lib().bf_export(self._h, data.ctypes.data, C.byref(cnt)), "bf_export")
         return data
+
+    def set_precision(self, precision):
+        """Arithmetic of apply and of the factors as a black box: 'fp32' (vector
+        ALUs, default) or 'bf16x3' (BF16 matrix cores for >= 16 right-hand
+        sides, operands split into three BF16 terms)."""
+        code = {"fp32": 2, "bf16x3": 1}[precision]
+        _check(lib().bf_set_apply_precision(self._h, code), "bf_set_apply_precision")
+        return self
 
     def apply(self, X, trans=False, out=None, stream=None):
         X = _dev_c64(X)

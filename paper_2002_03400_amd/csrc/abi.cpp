@@ -481,6 +481,12 @@ int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64
   });
 }
 
+int bf_set_apply_precision(bf_factors* F, int precision) {
+  if (!F || (precision != BF_PREC_FP32 && precision != BF_PREC_BF16X3)) return BF_EINVAL;
+  F->apply_prec = precision;
+  return BF_OK;
+}
+
 int bf_stats(const bf_factors* F, bf_info* info) {
   if (!F || !info) return BF_EINVAL;
   *info = F->info;

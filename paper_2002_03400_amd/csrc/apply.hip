@@ -135,6 +135,147 @@ __global__ __launch_bounds__(256) void apply_blocked_kernel(const ApplyBlk* __re
   }
 }
 
+// ---- split-BF16 stage (right-hand-side count >= AM_MIN_COLS) ------------
+//
+// Same stage as apply_blocked_kernel on the BF16 matrix cores: every factor
+// entry and input value is split into three BF16 terms, g = g1 + g2 + g3,
+// x = x1 + x2 + x3 (g2 = bf16(g - g1), ...), and the six products with
+// p + q <= 2 keep every term down to 2^-24 relative, so the result matches
+// the FP32 stage.  One workgroup (4 waves) per (output block, 64 columns);
+// the inner dimension (both terms' inputs, one after the other) goes through
+// LDS in chunks of 32, split while staged, as planes [term][re/im][row or
+// column][k].  Wave w owns the 16-column tile w and every 16-row tile of the
+// block (row blocks of 64): per tile and chunk 24 v_mfma_f32_16x16x32_bf16
+// (Re += gr xr - gi xi, Im += gr xi + gi xr), FP32 accumulation.
+typedef __bf16 abf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int au32x4 __attribute__((ext_vector_type(4)));
+typedef float afloatx4 __attribute__((ext_vector_type(4)));
+typedef float af32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 abf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t apk_bf16(float x0, float x1) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((af32x2){x0, x1}, abf16x2));
+}
+__device__ __forceinline__ void asplit3(float x0, float x1, uint32_t& h, uint32_t& m, uint32_t& l) {
+  h = apk_bf16(x0, x1);
+  const float r0 = x0 - __uint_as_float(h << 16);
+  const float r1 = x1 - __uint_as_float(h & 0xffff0000u);
+  m = apk_bf16(r0, r1);
+  l = apk_bf16(r0 - __uint_as_float(m << 16), r1 - __uint_as_float(m & 0xffff0000u));
+}
+
+constexpr int AM_KT = 32;            // inner indices per staged chunk
+constexpr int AM_KP = AM_KT + 8;     // padded k stride of a plane row
+constexpr int AM_R = 64;             // rows per row block
+constexpr int AM_MIN_COLS = 16;
+
+__global__ __launch_bounds__(256) void apply_mfma_kernel(const ApplyBlk* __restrict__ blks,
+                                                         const bf_c64* __restrict__ G,
+                                                         ApplyBufs B, int64_t ncols) {
+  __shared__ __attribute__((aligned(16))) uint16_t gs[6][AM_R][AM_KP];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[6][AP_CW][AM_KP];
+  const ApplyBlk bk = blks[blockIdx.x];
+  const int64_t c0 = (int64_t)blockIdx.y * AP_CW;
+  const int cw = (int)((ncols - c0 < AP_CW) ? ncols - c0 : AP_CW);
+  const int M = bk.M, K0 = bk.K0, KK = bk.K0 + bk.K1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lc = lane & 15, kq = lane >> 4;
+  const bf_c64* gsrc = G + bk.g_off;
+  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0;
+  const bf_c64* in1 = B.p[bk.in_buf1] + bk.in_row1;
+  const int64_t ld0 = B.ld[bk.in_buf0], ld1 = B.ld[bk.in_buf1];
+  for (int rb = 0; rb < M; rb += AM_R) {
+    const int mr = (M - rb < AM_R) ? M - rb : AM_R;
+    const int rt_n = (mr + 15) >> 4;
+    afloatx4 R[4], I[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) { R[t] = afloatx4{0.f, 0.f, 0.f, 0.f}; I[t] = R[t]; }
+    for (int k0 = 0; k0 < KK; k0 += AM_KT) {
+      __syncthreads();
+      // factor chunk: rows rb..rb+63, two consecutive k per thread step
+      for (int idx = threadIdx.x; idx < AM_R * (AM_KT / 2); idx += 256) {
+        const int r = idx / (AM_KT / 2), k = 2 * (idx % (AM_KT / 2));
+        bf_c64 v0 = {0.f, 0.f}, v1 = {0.f, 0.f};
+        if (r < mr) {
+          const bf_c64* gr = gsrc + (int64_t)(rb + r) * KK + k0;
+          if (k0 + k < KK) v0 = gr[k];
+          if (k0 + k + 1 < KK) v1 = gr[k + 1];
+        }
+        uint32_t h, m, l;
+        asplit3(v0.re, v1.re, h, m, l);
+        *reinterpret_cast<uint32_t*>(&gs[0][r][k]) = h;
+        *reinterpret_cast<uint32_t*>(&gs[2][r][k]) = m;
+        *reinterpret_cast<uint32_t*>(&gs[4][r][k]) = l;
+        asplit3(v0.im, v1.im, h, m, l);
+        *reinterpret_cast<uint32_t*>(&gs[1][r][k]) = h;
+        *reinterpret_cast<uint32_t*>(&gs[3][r][k]) = m;
+        *reinterpret_cast<uint32_t*>(&gs[5][r][k]) = l;
+      }
+      // input chunk: inner rows k0..k0+31 (term 0 rows, then term 1 rows)
+      for (int idx = threadIdx.x; idx < AP_CW * (AM_KT / 2); idx += 256) {
+        const int c = idx / (AM_KT / 2), k = 2 * (idx % (AM_KT / 2));
+        bf_c64 v[2] = {{0.f, 0.f}, {0.f, 0.f}};
+        if (c < cw) {
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int kk = k0 + k + u;
+            if (kk < K0)
+              v[u] = in0[(c0 + c) * ld0 + kk];
+            else if (kk < KK)
+              v[u] = in1[(c0 + c) * ld1 + (kk - K0)];
+          }
+        }
+        uint32_t h, m, l;
+        asplit3(v[0].re, v[1].re, h, m, l);
+        *reinterpret_cast<uint32_t*>(&xs[0][c][k]) = h;
+        *reinterpret_cast<uint32_t*>(&xs[2][c][k]) = m;
+        *reinterpret_cast<uint32_t*>(&xs[4][c][k]) = l;
+        asplit3(v[0].im, v[1].im, h, m, l);
+        *reinterpret_cast<uint32_t*>(&xs[1][c][k]) = h;
+        *reinterpret_cast<uint32_t*>(&xs[3][c][k]) = m;
+        *reinterpret_cast<uint32_t*>(&xs[5][c][k]) = l;
+      }
+      __syncthreads();
+      au32x4 xb[6];
+#pragma unroll
+      for (int p = 0; p < 6; ++p)
+        xb[p] = *reinterpret_cast<const au32x4*>(&xs[p][wave * 16 + lc][8 * kq]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < rt_n) {
+          au32x4 ga[6], gn[3];
+#pragma unroll
+          for (int p = 0; p < 6; ++p)
+            ga[p] = *reinterpret_cast<const au32x4*>(&gs[p][t * 16 + lc][8 * kq]);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) gn[q] = ga[2 * q + 1] ^ 0x80008000u;
+#define AM_MM(A, Bv, C) \
+  C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(abf16x8, A), \
+                                              __builtin_bit_cast(abf16x8, Bv), C, 0, 0, 0);
+#define AM_PAIR(P, Q) AM_MM(ga[2 * P], xb[2 * Q], R[t]) AM_MM(gn[P], xb[2 * Q + 1], R[t]) \
+                      AM_MM(ga[2 * P], xb[2 * Q + 1], I[t]) AM_MM(ga[2 * P + 1], xb[2 * Q], I[t])
+          AM_PAIR(2, 0) AM_PAIR(0, 2) AM_PAIR(1, 1) AM_PAIR(1, 0) AM_PAIR(0, 1) AM_PAIR(0, 0)
+#undef AM_PAIR
+#undef AM_MM
+        }
+      }
+    }
+    // accumulator layout of a 16x16 tile: lane l, register v -> row
+    // 4 (l / 16) + v, column l % 16
+    const int c = wave * 16 + lc;
+    if (c < cw) {
+      bf_c64* out = B.p[bk.out_buf] + (c0 + c) * B.ld[bk.out_buf] + bk.out_row + rb;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = t * 16 + 4 * kq + v;
+          if (t < rt_n && r < mr) out[r] = bf_c64{R[t][v], I[t][v]};
+        }
+    }
+  }
+}
+
 constexpr size_t AP_LDS_LIMIT = 160 * 1024;
 
 // One workgroup per block: row r of block b multiplies packed row r of its
@@ -168,7 +309,7 @@ void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* row
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
                         int32_t nrows, int32_t maxMK, int32_t maxKK, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
-                        hipStream_t s) {
+                        int prec, hipStream_t s) {
   if (nblk <= 0 || ncols <= 0) return;
   ApplyBufs B;
   for (int i = 0; i < 4; ++i) {
@@ -178,6 +319,11 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
   if (ncols <= AP_SMALL) {
     hipLaunchKernelGGL(apply_stream_kernel, dim3((unsigned)((nrows + 15) / 16)), dim3(256), 0, s,
                        rows_dev, nrows, G, B, (int32_t)ncols);
+  } else if (prec == BF_PREC_BF16X3 && ncols >= AM_MIN_COLS) {
+    const int64_t ych = (ncols + AP_CW - 1) / AP_CW;
+    BF_CHECK(ych <= 65535, BF_EINVAL, "too many right-hand sides");
+    hipLaunchKernelGGL(apply_mfma_kernel, dim3((unsigned)nblk, (unsigned)ych), dim3(256), 0, s,
+                       blks_dev, G, B, ncols);
   } else {
     const size_t lds_b = sizeof(cf) * ((size_t)maxMK + (size_t)maxKK * AP_CW);
     BF_CHECK(lds_b <= AP_LDS_LIMIT, BF_ERANK, "apply block too large for LDS");

@@ -174,9 +174,9 @@ struct GemmDesc {
   GemmTerm t[2];
 };
 // in_c64: the inputs are complex64 (samples straight from the black box);
-// max_M bounds every descriptor's M.
+// max_M and max_Ksum bound every descriptor's M and summed terms' K.
 void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, int32_t max_M,
-                       bool in_c64, hipStream_t s);
+                       int32_t max_Ksum, bool in_c64, hipStream_t s);
 
 // Batched truncated column-pivoted QR (Alg. 1 step 3) on FP64.
 struct QRDesc {
@@ -227,10 +227,12 @@ struct ApplyRowRec {
 void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* rows_dev,
                         hipStream_t s);
 // maxMK / maxKK: largest M*(K0+K1) and K0+K1 over the stage's blocks.
+// prec: BF_PREC_BF16X3 runs stages of >= 16 right-hand sides on the BF16
+// matrix cores (split operands), anything else in FP32 on the vector ALUs.
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
                         int32_t nrows, int32_t maxMK, int32_t maxKK, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
-                        hipStream_t s);
+                        int prec, hipStream_t s);
 
 // Gather (and optionally conjugate-transpose) factor sub-blocks into an
 // arena: element (r, k) of the M x K result goes to

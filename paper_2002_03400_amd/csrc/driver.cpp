@@ -133,10 +133,13 @@ class Builder {
 
   void gemm(const std::vector<GemmDesc>& d, bool in_c64) {
     if (d.empty()) return;
-    int maxc = 0, maxm = 0;
+    int maxc = 0, maxm = 0, maxk = 0;
     for (auto& x : d) {
       maxc = std::max(maxc, x.ncols);
       maxm = std::max(maxm, x.M);
+      int ks = 0;
+      for (int t = 0; t < x.nterm; ++t) ks += x.t[t].K;
+      maxk = std::max(maxk, ks);
     }
     if (validating()) {
       const size_t isz = in_c64 ? sizeof(bf_c64) : sizeof(bf_c128);
@@ -153,7 +156,7 @@ class Builder {
       }
     }
     auto dd = upload(d, s_, st_);
-    launch_chain_gemm(dd.p, (int32_t)d.size(), maxc, maxm, in_c64, s_);
+    launch_chain_gemm(dd.p, (int32_t)d.size(), maxc, maxm, maxk, in_c64, s_);
   }
 
   // Batched Alg. 1 step 3; Q blocks go to a fresh capacity buffer that becomes
@@ -188,9 +191,32 @@ class Builder {
     BF_HIP(hipStreamSynchronize(s_));
     std::memcpy(ranks.data(), hr, nblk * sizeof(int32_t));
     st_.reset();
+    // keep only the k leading columns of every Q (the capacity holds
+    // min(M, N) of them): factor storage becomes sum M k instead of
+    // sum M min(M, N)
+    std::vector<int64_t> coff(nblk);
+    int64_t ctot = 0;
+    for (size_t b = 0; b < nblk; ++b) {
+      coff[b] = ctot;
+      ctot += (int64_t)in[b].M * std::max(ranks[b], 0);
+    }
+    DevBuf<bf_c128> compact((size_t)std::max<int64_t>(ctot, 1), s_);
+    std::vector<PackDesc> pd;
+    pd.reserve(nblk);
+    for (size_t b = 0; b < nblk; ++b)
+      if (in[b].M > 0 && ranks[b] > 0)
+        pd.push_back(PackDesc{store.p + off[b], coff[b], in[b].M, 0, in[b].M, ranks[b], 0, 1,
+                              in[b].M, 0});
+    for (size_t o = 0; o < pd.size(); o += 60000) {
+      const size_t cnt = std::min<size_t>(60000, pd.size() - o);
+      std::vector<PackDesc> part(pd.begin() + o, pd.begin() + o + cnt);
+      auto dd = upload(part, s_, st_);
+      launch_pack_c128(dd.p, (int32_t)cnt, compact.p, s_);
+    }
+    store.reset();
     out.resize(nblk);
-    for (size_t b = 0; b < nblk; ++b) out[b] = Block{store.p + off[b], in[b].M, ranks[b]};
-    F_->store.push_back(std::move(store));
+    for (size_t b = 0; b < nblk; ++b) out[b] = Block{compact.p + coff[b], in[b].M, ranks[b]};
+    F_->store.push_back(std::move(compact));
     return ranks;
   }
 

@@ -23,98 +23,124 @@ template <> __device__ __forceinline__ cd load_c<bf_c128>(const bf_c128* p) {
 
 // ---------------------------------------------------------------- gemm ----
 // grid (ndesc, ceil(max_ncols / 64)); a workgroup of 4 waves computes rows
-// 0..M-1 of one descriptor (in row blocks of 32) for 64 columns.  Lane l of
-// every wave owns column 64 blockIdx.y + l and wave w the rows w, w+4, ...
-// of the block.  op(F) is staged in LDS in chunks of 64 inner indices as
-// [k][row] and read as a broadcast; each lane reads its own input column
-// straight from global memory (contiguous along k, shared by the 4 waves
-// through L1), and writes its results directly.  The small LDS footprint
-// (32 KB) lets several workgroups per CU hide the load latency.
+// 0..M-1 of one descriptor (in row blocks of 32, or 64 when some M > 32) for
+// the 64-column chunk blockIdx.y.
+// Lane l of every wave owns column l of the chunk and wave w the rows w,
+// w+4, ... of the block.  op(F) is staged in LDS in chunks of 64 (or 32)
+// inner indices as [k][row] and read as a broadcast; each lane reads its own input
+// column straight from global memory (contiguous along k, shared by the 4
+// waves through L1) and writes its results directly.  The 32 KB of LDS lets
+// several workgroups per CU hide the load latency.
 constexpr int CG_COLS = 64;
-constexpr int CG_KT = 64;
-constexpr int CG_ROWS = 32;
+constexpr int CG_YMAX = 65535;
 
-template <typename Tin>
-__global__ __launch_bounds__(256) void chain_gemm_kernel(const GemmDesc* __restrict__ descs) {
-  __shared__ cd fs[CG_KT][CG_ROWS];
-  const GemmDesc d = descs[blockIdx.x];
-  const int c0 = blockIdx.y * CG_COLS;
-  if (c0 >= d.ncols || d.M <= 0) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = c0 + lane;
-  const bool live = c < d.ncols;
-  for (int rb = 0; rb < d.M; rb += CG_ROWS) {
-    const int mr = (d.M - rb < CG_ROWS) ? d.M - rb : CG_ROWS;
-    cd acc[CG_ROWS / 4];
-#pragma unroll
-    for (int i = 0; i < CG_ROWS / 4; ++i) acc[i] = cd{0.0, 0.0};
-    for (int t = 0; t < d.nterm; ++t) {
-      const GemmTerm T = d.t[t];
-      const Tin* inp = static_cast<const Tin*>(T.in) + (int64_t)(live ? c : c0) * T.in_ld;
-      for (int k0 = 0; k0 < T.K; k0 += CG_KT) {
-        const int kt = (T.K - k0 < CG_KT) ? T.K - k0 : CG_KT;
-        __syncthreads();
-        if (T.op == 0) {   // F is M x K column-major: op(F)[r][k] = F[k f_ld + r]
-          for (int idx = threadIdx.x; idx < CG_KT * CG_ROWS; idx += 256) {
-            const int r = idx % CG_ROWS, k = idx / CG_ROWS;
-            cd v = {0.0, 0.0};
-            if (r < mr && k < kt) {
-              const bf_c128 f = T.F[(int64_t)(k0 + k) * T.f_ld + rb + r];
-              v = cd{f.re, f.im};
-            }
-            fs[k][r] = v;
-          }
-        } else {           // F is K x M column-major: op(F)[r][k] = conj(F[r f_ld + k])
-          for (int idx = threadIdx.x; idx < CG_KT * CG_ROWS; idx += 256) {
-            const int k = idx % CG_KT, r = idx / CG_KT;
-            cd v = {0.0, 0.0};
-            if (r < mr && k < kt) {
-              const bf_c128 f = T.F[(int64_t)(rb + r) * T.f_ld + k0 + k];
-              v = cd{f.re, -f.im};
-            }
-            fs[k][r] = v;
-          }
-        }
-        __syncthreads();
-        const Tin* ip = inp + k0;
-        int k = 0;
-        for (; k + 4 <= kt; k += 4) {
-          cd x[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) x[u] = load_c<Tin>(ip + k + u);
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int i = 0; i < CG_ROWS / 4; ++i)
-              if (wave + 4 * i < mr) cd_fma(acc[i], fs[k + u][wave + 4 * i], x[u]);
-        }
-        for (; k < kt; ++k) {
-          const cd x = load_c<Tin>(ip + k);
-#pragma unroll
-          for (int i = 0; i < CG_ROWS / 4; ++i)
-            if (wave + 4 * i < mr) cd_fma(acc[i], fs[k][wave + 4 * i], x);
-        }
+// op(F) rows [rb, rb + mr), inner indices [k0, k0 + kt) -> fs[k][r]
+template <int ROWS, int KT>
+__device__ __forceinline__ void cg_stage(cd (*fs)[ROWS], const GemmTerm& T, int rb, int mr,
+                                         int k0, int kt) {
+  if (T.op == 0) {   // F is M x K column-major: op(F)[r][k] = F[k f_ld + r]
+    for (int idx = threadIdx.x; idx < KT * ROWS; idx += 256) {
+      const int r = idx % ROWS, k = idx / ROWS;
+      cd v = {0.0, 0.0};
+      if (r < mr && k < kt) {
+        const bf_c128 f = T.F[(int64_t)(k0 + k) * T.f_ld + rb + r];
+        v = cd{f.re, f.im};
       }
+      fs[k][r] = v;
     }
-    if (live) {
-      bf_c128* o = d.out + (int64_t)c * d.out_ld + rb;
-#pragma unroll
-      for (int i = 0; i < CG_ROWS / 4; ++i)
-        if (wave + 4 * i < mr) o[wave + 4 * i] = bf_c128{acc[i].re, acc[i].im};
+  } else {           // F is K x M column-major: op(F)[r][k] = conj(F[r f_ld + k])
+    for (int idx = threadIdx.x; idx < KT * ROWS; idx += 256) {
+      const int k = idx % KT, r = idx / KT;
+      cd v = {0.0, 0.0};
+      if (r < mr && k < kt) {
+        const bf_c128 f = T.F[(int64_t)(rb + r) * T.f_ld + k0 + k];
+        v = cd{f.re, -f.im};
+      }
+      fs[k][r] = v;
     }
   }
 }
 
-void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, int32_t max_M,
-                       bool in_c64, hipStream_t s) {
-  if (ndesc <= 0 || max_ncols <= 0 || max_M <= 0) return;
-  BF_CHECK((max_ncols + CG_COLS - 1) / CG_COLS <= 65535, BF_EINVAL, "chain product too wide");
-  dim3 grid((unsigned)ndesc, (unsigned)((max_ncols + CG_COLS - 1) / CG_COLS));
-  ProfScope ps(BF_KC_CHAIN, s, 0.0, 0.0);
-  if (in_c64)
-    hipLaunchKernelGGL(chain_gemm_kernel<bf_c64>, grid, dim3(256), 0, s, d_dev);
+template <typename Tin, int ROWS>
+__device__ __forceinline__ void cg_accum(cd* acc, const cd (*fs)[ROWS], const Tin* ip, int kt,
+                                         int wave, int mr) {
+  int k = 0;
+  for (; k + 4 <= kt; k += 4) {
+    cd x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = load_c<Tin>(ip + k + u);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < ROWS / 4; ++i)
+        if (wave + 4 * i < mr) cd_fma(acc[i], fs[k + u][wave + 4 * i], x[u]);
+  }
+  for (; k < kt; ++k) {
+    const cd x = load_c<Tin>(ip + k);
+#pragma unroll
+    for (int i = 0; i < ROWS / 4; ++i)
+      if (wave + 4 * i < mr) cd_fma(acc[i], fs[k][wave + 4 * i], x);
+  }
+}
+
+// ROWS x KT = 2048 entries of op(F) in LDS (32 KB): 32 x 64 or 64 x 32.
+template <typename Tin, int ROWS>
+__global__ __launch_bounds__(256) void chain_gemm_kernel(const GemmDesc* __restrict__ descs) {
+  constexpr int KT = 2048 / ROWS;
+  __shared__ cd fs[KT][ROWS];
+  const GemmDesc d = descs[blockIdx.x];
+  if (d.M <= 0 || (int)blockIdx.y * CG_COLS >= d.ncols) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nchunk = (d.ncols + CG_COLS - 1) / CG_COLS;
+  for (int ch = blockIdx.y; ch < nchunk; ch += gridDim.y) {
+    const int c = ch * CG_COLS + lane;
+    const bool live = c < d.ncols;
+    for (int rb = 0; rb < d.M; rb += ROWS) {
+      const int mr = (d.M - rb < ROWS) ? d.M - rb : ROWS;
+      cd acc[ROWS / 4];
+#pragma unroll
+      for (int i = 0; i < ROWS / 4; ++i) acc[i] = cd{0.0, 0.0};
+      for (int t = 0; t < d.nterm; ++t) {
+        const GemmTerm T = d.t[t];
+        const Tin* inp =
+            static_cast<const Tin*>(T.in) + (int64_t)(live ? c : ch * CG_COLS) * T.in_ld;
+        for (int k0 = 0; k0 < T.K; k0 += KT) {
+          const int kt = (T.K - k0 < KT) ? T.K - k0 : KT;
+          __syncthreads();
+          cg_stage<ROWS, KT>(fs, T, rb, mr, k0, kt);
+          __syncthreads();
+          cg_accum<Tin, ROWS>(acc, fs, inp + k0, kt, wave, mr);
+        }
+      }
+      if (live) {
+        bf_c128* o = d.out + (int64_t)c * d.out_ld + rb;
+#pragma unroll
+        for (int i = 0; i < ROWS / 4; ++i)
+          if (wave + 4 * i < mr) o[wave + 4 * i] = bf_c128{acc[i].re, acc[i].im};
+      }
+    }
+  }
+}
+
+template <typename Tin>
+static void launch_chain_t(const GemmDesc* d_dev, dim3 grid, int32_t max_M, hipStream_t s) {
+  if (max_M <= 32)
+    hipLaunchKernelGGL((chain_gemm_kernel<Tin, 32>), grid, dim3(256), 0, s, d_dev);
   else
-    hipLaunchKernelGGL(chain_gemm_kernel<bf_c128>, grid, dim3(256), 0, s, d_dev);
+    hipLaunchKernelGGL((chain_gemm_kernel<Tin, 64>), grid, dim3(256), 0, s, d_dev);
+}
+
+void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, int32_t max_M,
+                       int32_t max_Ksum, bool in_c64, hipStream_t s) {
+  if (ndesc <= 0 || max_ncols <= 0 || max_M <= 0) return;
+  (void)max_Ksum;
+  ProfScope ps(BF_KC_CHAIN, s, 0.0, 0.0);
+  const int nchunk = (max_ncols + CG_COLS - 1) / CG_COLS;
+  dim3 grid((unsigned)ndesc, (unsigned)std::min(nchunk, CG_YMAX));
+  if (in_c64)
+    launch_chain_t<bf_c64>(d_dev, grid, max_M, s);
+  else
+    launch_chain_t<bf_c128>(d_dev, grid, max_M, s);
   BF_HIP(hipGetLastError());
 }
 

@@ -292,7 +292,7 @@ void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
     if (k + 1 == P.stages.size()) by += 8.0 * (double)rout * ncols;
     ProfScope ps(BF_KC_APPLY, s, 8.0 * st.macs * ncols, by);
     launch_apply_stage(P.blks.p + st.blk_off, st.nblk, P.rows.p + st.row_off, st.nrows, st.maxMK,
-                       st.maxKK, P.G.p, bufs, lds, ncols, s);
+                       st.maxKK, P.G.p, bufs, lds, ncols, F->apply_prec, s);
   }
 }
 

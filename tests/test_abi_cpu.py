@@ -42,6 +42,14 @@ def test_argument_errors_without_device():
     assert lib.bf_free(None, None) == -1
     assert lib.bf_strerror(-4) == b"rank cap exceeded or block too large"
     assert lib.bf_op_fio(7, None) == -1
+    assert lib.bf_set_apply_precision(None, 1) == -1
+    assert lib.bf_op_set_precision(None, 1) == -1
+
+
+def test_precision_enum_matches_header():
+    text = open(HEADER).read()
+    vals = dict((k, int(v)) for k, v in re.findall(r"(BF_PREC_[A-Z0-9]+)\s*=\s*(\d+)", text))
+    assert vals == {"BF_PREC_FP64": 0, "BF_PREC_BF16X3": 1, "BF_PREC_FP32": 2}
 
 
 def test_error_codes_match_header():

@@ -62,3 +62,43 @@ def test_recompress_product(bf, n, leaf):
     exactH = r2.rmatvec(r1.rmatvec(Z))
     e_h = np.linalg.norm(F.apply(_t(Z), trans=True).cpu().numpy() - exactH) / np.linalg.norm(exactH)
     assert e_h <= 2 * e_or + 1e-6
+
+
+@pytest.mark.parametrize("n,leaf", [(2048, 16), (3000, 24)])
+def test_fio_construction_and_recompression(bf, n, leaf):
+    """1D FIO (low-dimensional Fourier operator, Sec. 4.4.1) built matrix-free
+    with both black-box precisions (split-BF16 matrix cores and FP64 matrix
+    cores), then recompressed with its own butterfly as the black box; each
+    against the oracle's construction of the same operator (FP64 entries)."""
+    if n % 2:
+        n += 1
+    tol = 1e-6
+    x, xi = wl.fio_params(n)
+    ref = ops.FIOOp(x, xi)
+    say("fio", n, leaf)
+    Fo = obf.construct(ref, tol, leaf, seed=31)
+    Om = wl.test_columns(n, 16, 1003)
+    AOm = ref.matvec(Om)
+    e_or = np.linalg.norm(obf.apply(Fo, Om) - AOm) / np.linalg.norm(AOm)
+    op = bf.fio(n)
+    errs = {}
+    for prec in ("bf16x3", "fp64"):
+        op.set_precision(prec)
+        F = bf.construct(op, tol, leaf, seed=31)
+        errs[prec] = np.linalg.norm(F.apply(_t(Om)).cpu().numpy() - AOm) / np.linalg.norm(AOm)
+        if prec == "bf16x3":
+            Fk = F
+        else:
+            F.close()
+    say("fio errors oracle", e_or, "gpu", errs)
+    for e in errs.values():
+        assert e <= 2 * e_or + 1e-6
+    # the two black-box precisions agree to the tolerance's order
+    assert abs(errs["bf16x3"] - errs["fp64"]) <= 0.5 * e_or + 1e-6
+    G = bf.construct(bf.from_factors(Fk), tol, leaf, seed=32)
+    e_re = np.linalg.norm(G.apply(_t(Om)).cpu().numpy() - AOm) / np.linalg.norm(AOm)
+    say("fio recompressed", e_re)
+    # recompressing a tol-accurate butterfly at tol: errors add at most
+    assert e_re <= errs["bf16x3"] + 2 * e_or + 1e-6
+    G.close()
+    Fk.close()

@@ -206,3 +206,36 @@ def test_apply_of_oracle_factors(bf, n, leaf):
     back = H.export()
     np.testing.assert_array_equal(back, data)
     H.close()
+
+
+@pytest.mark.parametrize("n,leaf", [(2000, 40), (4096, 16)])
+def test_apply_precisions(bf, n, leaf):
+    """Applies of imported oracle factors with FP32 vector arithmetic and
+    with split-BF16 matrix cores (>= 16 right-hand sides; fewer fall back to
+    FP32), forward and adjoint, against the oracle's FP64 apply."""
+    g = wl.segment_pair(n, ppw=6.0)
+    op = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    F = obf.construct(op, 1e-6, leaf, seed=2)
+    kU, kV, data = oracle_to_canonical(F)
+    say("apply precisions", n, leaf, F.L)
+    H = bf.import_factors(n, n, leaf, kU, kV, data)
+    rng = np.random.default_rng(7)
+    for s in (3, 16, 40, 100):
+        X = _cg(rng, n, s)
+        ref = obf.apply(F, X)
+        refh = obf.apply_adjoint(F, X)
+        out = {}
+        for prec in ("fp32", "bf16x3"):
+            H.set_precision(prec)
+            out[prec] = (H.apply(_t(X)).cpu().numpy(), H.apply(_t(X), trans=True).cpu().numpy())
+            assert _rel(out[prec][0], ref) < 1e-6, (s, prec)
+            assert _rel(out[prec][1], refh) < 1e-6, (s, prec)
+            for c in range(s):    # every column, so no tile or chunk is skipped
+                assert np.linalg.norm(out[prec][0][:, c] - ref[:, c]) <= 2e-6 * np.linalg.norm(ref[:, c])
+        # below 16 columns both settings run the same FP32 stages
+        if s < 16:
+            np.testing.assert_array_equal(out["fp32"][0], out["bf16x3"][0])
+    with pytest.raises(bf.BFError):
+        lib_rc = bf.lib().bf_set_apply_precision(H._h, 0)
+        bf._check(lib_rc, "bf_set_apply_precision")
+    H.close()
