@@ -58,11 +58,13 @@ enum {
  *
  *   seg == NULL : plain product of the ncols columns of X.
  *   seg != NULL : structured samples of Sec. 4.1.  `seg` is a HOST array of
- *                 nseg+1 increasing row offsets that partition the rows of X;
+ *                 nseg+1 nondecreasing row offsets within the rows of X;
  *                 group g is the row range [seg[g], seg[g+1]).  Y has
  *                 nseg*ncols columns and its columns [g*ncols, (g+1)*ncols)
  *                 receive op(A)(:, seg_g) * X(seg_g, :) -- the product with
- *                 the random matrix that is zero outside node g.
+ *                 the random matrix that is zero outside node g.  Rows of X
+ *                 outside [seg[0], seg[nseg]) are not used: a level's nodes
+ *                 may come in several calls (see bf_opts.work_bytes).
  *
  * X and Y are device buffers owned by the library for the duration of the
  * call; the callback must not keep them.  Return 0 on success; any nonzero
@@ -81,13 +83,19 @@ typedef struct {
 } bf_operator;
 
 /* Knobs of Alg. 2.  Pass NULL for the defaults p = 2, r0 = 4 (the values of
-   Sec. 6.1 and 6.2), seed = 0, no rank cap. */
+   Sec. 6.1 and 6.2), seed = 0, no rank cap, 8 GiB of sweep workspace. */
 typedef struct {
   int32_t p;          /* over-sampling (Alg. 1 input), >= 0 */
   int32_t r0;         /* initial rank guess of the adaptive loops, >= 1 */
   int32_t max_rank;   /* 0 = none; else BF_ERANK when a rank estimate passes it */
   int32_t flags;      /* reserved, 0 */
   uint64_t seed;      /* key of the counter-based random matrices */
+  int64_t work_bytes; /* device bytes a sweep level's samples may occupy at once
+                         (black-box output and partial-factor products); the
+                         level's samples are processed in groups under this
+                         bound (at least one sample per group).  0 = 8 GiB.
+                         Only the summation order inside black-box products
+                         can change with it. */
 } bf_opts;
 
 typedef struct bf_factors bf_factors;
@@ -329,11 +337,12 @@ int bf_op_set_precision(bf_operator* op, int precision);
 
 /* Arithmetic of bf_apply (and of the factors as a black box, bf_op_factors)
  * for F (eq. hybrid_butterfly_mat, complex64 data in both modes):
- *   BF_PREC_FP32   : FP32 multiply-adds on the vector ALUs (default);
+ *   BF_PREC_FP32   : FP32 multiply-adds on the vector ALUs;
  *   BF_PREC_BF16X3 : stages with 16 or more right-hand sides on the BF16
  *                    matrix cores, factor entries and inputs split into three
  *                    BF16 terms (products kept to 2^-24 relative), FP32
- *                    accumulation; fewer right-hand sides use the FP32 path.
+ *                    accumulation; fewer right-hand sides use the FP32 path
+ *                    (default: as accurate as FP32 and about twice as fast).
  * Not synchronized with applies in flight on F: set it before applying.
  * Returns BF_EINVAL for a null F or another value. */
 int bf_set_apply_precision(bf_factors* F, int precision);

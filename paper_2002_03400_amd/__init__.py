@@ -46,7 +46,7 @@ class bf_operator(C.Structure):
 
 class bf_opts(C.Structure):
     _fields_ = [("p", C.c_int32), ("r0", C.c_int32), ("max_rank", C.c_int32),
-                ("flags", C.c_int32), ("seed", C.c_uint64)]
+                ("flags", C.c_int32), ("seed", C.c_uint64), ("work_bytes", C.c_int64)]
 
 
 class bf_kernel_stats(C.Structure):
@@ -311,9 +311,9 @@ class Factors:
         return data
 
     def set_precision(self, precision):
-        """Arithmetic of apply and of the factors as a black box: 'fp32' (vector
-        ALUs, default) or 'bf16x3' (BF16 matrix cores for >= 16 right-hand
-        sides, operands split into three BF16 terms)."""
+        """Arithmetic of apply and of the factors as a black box: 'bf16x3' (BF16
+        matrix cores for >= 16 right-hand sides, operands split into three BF16
+        terms; default) or 'fp32' (vector ALUs)."""
         code = {"fp32": 2, "bf16x3": 1}[precision]
         _check(lib().bf_set_apply_precision(self._h, code), "bf_set_apply_precision")
         return self
@@ -342,9 +342,10 @@ class Factors:
 
 
 def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed: int = 0,
-              max_rank: int = 0, stream=None) -> Factors:
-    """Alg. 2 on the device; returns the factor handle."""
-    o = bf_opts(p, r0, max_rank, 0, seed)
+              max_rank: int = 0, stream=None, work_bytes: int = 0) -> Factors:
+    """Alg. 2 on the device; returns the factor handle.  work_bytes bounds the
+    device memory of one sweep level's samples (0: 8 GiB)."""
+    o = bf_opts(p, r0, max_rank, 0, seed, work_bytes)
     h = C.c_void_p()
     _check(lib().bf_construct(op._op.matvec, op._op.rmatvec, op._op.user, op.m, op.n, float(tol),
                               int(leaf), C.byref(o), _stream(stream), C.byref(h)), "bf_construct")
@@ -379,9 +380,10 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit_construct(self, op: Operator, tol, leaf, p=2, r0=4, seed=0, max_rank=0):
+    def submit_construct(self, op: Operator, tol, leaf, p=2, r0=4, seed=0, max_rank=0,
+                         work_bytes=0):
         t = C.c_int64()
-        o = bf_opts(p, r0, max_rank, 0, seed)
+        o = bf_opts(p, r0, max_rank, 0, seed, work_bytes)
         _check(lib().bf_server_submit_construct(self._h, C.byref(op._op), float(tol), int(leaf),
                                                 C.byref(o), C.byref(t)), "submit_construct")
         self._keep[t.value] = (op,)

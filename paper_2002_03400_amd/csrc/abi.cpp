@@ -318,7 +318,13 @@ static void expand(const bf_c64* X, int64_t ldx, int64_t rows, int64_t ncols, co
                    int32_t nseg, DevBuf<bf_c64>& out, hipStream_t s) {
   std::vector<int64_t> sv(seg, seg + nseg + 1);
   DevBuf<int64_t> sd(sv.size(), s);
-  BF_HIP(hipMemcpyAsync(sd.p, sv.data(), sv.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  if (Staging* st = scope_staging(s)) {   // pinned: no wait for the stream to drain
+    void* h = st->alloc(sv.size() * sizeof(int64_t), s);
+    std::memcpy(h, sv.data(), sv.size() * sizeof(int64_t));
+    BF_HIP(hipMemcpyAsync(sd.p, h, sv.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  } else {
+    BF_HIP(hipMemcpyAsync(sd.p, sv.data(), sv.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  }
   out = DevBuf<bf_c64>((size_t)rows * nseg * ncols, s);
   launch_expand_segments(X, ldx, rows, ncols, sd.p, nseg, out.p, rows, s);
 }

@@ -57,8 +57,10 @@ class Builder {
       r0_ = o->r0;
       cap_ = o->max_rank;
       seed_ = o->seed;
+      if (o->work_bytes > 0) work_ = o->work_bytes;
     }
-    BF_CHECK(p_ >= 0 && r0_ >= 1 && cap_ >= 0, BF_EINVAL, "bad bf_opts");
+    BF_CHECK(p_ >= 0 && r0_ >= 1 && cap_ >= 0 && (!o || o->work_bytes >= 0), BF_EINVAL,
+             "bad bf_opts");
     F_->L = num_levels(m, n, leaf);
     F_->lm = F_->L / 2;
     BF_CHECK(F_->L <= 24, BF_EINVAL, "too many levels");
@@ -90,6 +92,7 @@ class Builder {
   hipStream_t s_;
   int p_ = 2, r0_ = 4, cap_ = 0;
   uint64_t seed_ = 0;
+  int64_t work_ = int64_t(8) << 30;   // sweep workspace bound (bf_opts.work_bytes)
   bf_factors* F_;
   Staging own_st_;
   // uploads go through the request scope's pinned staging when there is one
@@ -262,6 +265,13 @@ class Builder {
     }
   }
 
+  // Samples of one level per group, so that a group's black-box output and
+  // partial products (bytes_per_sample each) stay within the workspace bound.
+  int64_t group_size(int64_t nsamples, double bytes_per_sample) const {
+    const double g = std::floor((double)work_ / std::max(bytes_per_sample, 1.0));
+    return std::max<int64_t>(1, std::min<int64_t>(nsamples, (int64_t)std::min(g, 1e15)));
+  }
+
   // ---- W sweep, level l (Sec. 4.3) ------------------------------------------
   void w_level(int l) {
     const int64_t m = F_->m, n = F_->n;
@@ -279,95 +289,108 @@ class Builder {
       smax = std::max(smax, width[i]);
     }
     auto G = gauss(m, smax, l, tags, width);
-    std::vector<int64_t> seg(nT + 1);
-    for (int64_t i = 0; i <= nT; ++i) seg[i] = node_lo(m, l, i);
-    const int64_t ycols = nT * smax;
-    DevBuf<bf_c64> Yp((size_t)n * ycols, s_);
-    call_op(true, G.p, m, smax, Yp.p, n, &seg);
     for (auto w : width) rmv_cols_ += w;
-    G.reset();
-
-    // V stage (shared by all samples): P0 = V^H Y', rows ordered by leaf j
-    Tall<bf_c128> P0;
     int64_t rows0 = 0;
-    P0.roff.resize(nb());
-    for (int64_t j = 0; j < nb(); ++j) { P0.roff[j] = rows0; rows0 += F_->kv(0, 0, j); }
-    DevBuf<bf_c128> P0buf((size_t)std::max<int64_t>(rows0, 1) * ycols, s_);
-    {
-      std::vector<GemmDesc> d;
-      for (int64_t j = 0; j < nb(); ++j) {
-        const Block& V = F_->V[j];
-        GemmDesc g{};
-        g.out = P0buf.p + P0.roff[j];
-        g.out_ld = rows0;
-        g.M = V.cols;
-        g.ncols = (int32_t)ycols;
-        g.nterm = 1;
-        g.t[0] = GemmTerm{V.p, Yp.p + node_lo(n, L(), j), n, V.rows, V.rows, 1, 0};
-        if (g.M > 0) d.push_back(g);
-      }
-      gemm(d, true);
-    }
-    // per-sample views of level l' (starting from the shared level 0)
-    std::vector<Tall<bf_c128>> view(nT);
-    for (int64_t i = 0; i < nT; ++i) {
-      view[i].base = P0buf.p + (int64_t)i * smax * rows0;
-      view[i].ld = rows0;
-      view[i].roff = P0.roff;
-    }
-    std::vector<DevBuf<bf_c128>> keep;
-    for (int lp = 1; lp < l; ++lp) {
-      const int64_t nSl = int64_t(1) << (L() - lp);
-      std::vector<int64_t> base(nT);
-      std::vector<Tall<bf_c128>> next(nT);
-      int64_t tot = 0;
-      for (int64_t i = 0; i < nT; ++i) {
-        const int64_t ip = i >> (l - lp);
-        int64_t rows = 0;
-        next[i].roff.resize(nSl);
-        for (int64_t j = 0; j < nSl; ++j) { next[i].roff[j] = rows; rows += F_->kv(lp, ip, j); }
-        next[i].ld = std::max<int64_t>(rows, 1);
-        base[i] = tot;
-        tot += next[i].ld * width[i];
-      }
-      DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
-      std::vector<GemmDesc> d;
-      for (int64_t i = 0; i < nT; ++i) {
-        const int64_t ip = i >> (l - lp);
-        next[i].base = buf.p + base[i];
-        for (int64_t j = 0; j < nSl; ++j) {
-          const Block& Wb = F_->W[lp][(size_t)((ip << (L() - lp)) + j)];
-          const int32_t ka = F_->kv(lp - 1, ip >> 1, 2 * j);
-          const int32_t kb = F_->kv(lp - 1, ip >> 1, 2 * j + 1);
+    std::vector<int64_t> roff0(nb());
+    for (int64_t j = 0; j < nb(); ++j) { roff0[j] = rows0; rows0 += F_->kv(0, 0, j); }
+    // per sample: Y' (n x smax c64), the leaf stage and two chain stages (FP64)
+    const int64_t gsz = group_size(nT, (double)smax * (8.0 * n + 48.0 * (double)rows0));
+    F_->W[l].assign((size_t)nb(), Block{});
+    for (int64_t i0 = 0; i0 < nT; i0 += gsz) {
+      const int64_t i1 = std::min(nT, i0 + gsz), ng = i1 - i0;
+      std::vector<int64_t> seg(ng + 1);
+      for (int64_t i = 0; i <= ng; ++i) seg[i] = node_lo(m, l, i0 + i);
+      const int64_t ycols = ng * smax;
+      DevBuf<bf_c64> Yp((size_t)n * ycols, s_);
+      call_op(true, G.p, m, smax, Yp.p, n, &seg);
+
+      // V stage (shared by the group's samples): P0 = V^H Y', rows by leaf j
+      DevBuf<bf_c128> P0buf((size_t)std::max<int64_t>(rows0, 1) * ycols, s_);
+      {
+        std::vector<GemmDesc> d;
+        for (int64_t j = 0; j < nb(); ++j) {
+          const Block& V = F_->V[j];
           GemmDesc g{};
-          g.out = const_cast<bf_c128*>(next[i].base) + next[i].roff[j];
-          g.out_ld = next[i].ld;
-          g.M = Wb.cols;
-          g.ncols = width[i];
-          g.nterm = 2;
-          g.t[0] = GemmTerm{Wb.p, view[i].base + view[i].roff[2 * j], view[i].ld, Wb.rows, ka, 1, 0};
-          g.t[1] = GemmTerm{Wb.p + ka, view[i].base + view[i].roff[2 * j + 1], view[i].ld, Wb.rows,
-                            kb, 1, 0};
+          g.out = P0buf.p + roff0[j];
+          g.out_ld = rows0;
+          g.M = V.cols;
+          g.ncols = (int32_t)ycols;
+          g.nterm = 1;
+          g.t[0] = GemmTerm{V.p, Yp.p + node_lo(n, L(), j), n, V.rows, V.rows, 1, 0};
           if (g.M > 0) d.push_back(g);
         }
+        gemm(d, true);
       }
-      gemm(d, false);
-      keep.push_back(std::move(buf));
-      view.swap(next);
+      Yp.reset();
+      // per-sample views of level l' (starting from the shared level 0);
+      // view[q] is sample i0 + q
+      std::vector<Tall<bf_c128>> view(ng);
+      for (int64_t q = 0; q < ng; ++q) {
+        view[q].base = P0buf.p + q * smax * rows0;
+        view[q].ld = rows0;
+        view[q].roff = roff0;
+      }
+      std::vector<DevBuf<bf_c128>> keep;
+      for (int lp = 1; lp < l; ++lp) {
+        const int64_t nSl = int64_t(1) << (L() - lp);
+        std::vector<int64_t> base(ng);
+        std::vector<Tall<bf_c128>> next(ng);
+        int64_t tot = 0;
+        for (int64_t q = 0; q < ng; ++q) {
+          const int64_t ip = (i0 + q) >> (l - lp);
+          int64_t rows = 0;
+          next[q].roff.resize(nSl);
+          for (int64_t j = 0; j < nSl; ++j) { next[q].roff[j] = rows; rows += F_->kv(lp, ip, j); }
+          next[q].ld = std::max<int64_t>(rows, 1);
+          base[q] = tot;
+          tot += next[q].ld * width[i0 + q];
+        }
+        DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
+        std::vector<GemmDesc> d;
+        for (int64_t q = 0; q < ng; ++q) {
+          const int64_t ip = (i0 + q) >> (l - lp);
+          next[q].base = buf.p + base[q];
+          for (int64_t j = 0; j < nSl; ++j) {
+            const Block& Wb = F_->W[lp][(size_t)((ip << (L() - lp)) + j)];
+            const int32_t ka = F_->kv(lp - 1, ip >> 1, 2 * j);
+            const int32_t kb = F_->kv(lp - 1, ip >> 1, 2 * j + 1);
+            GemmDesc g{};
+            g.out = const_cast<bf_c128*>(next[q].base) + next[q].roff[j];
+            g.out_ld = next[q].ld;
+            g.M = Wb.cols;
+            g.ncols = width[i0 + q];
+            g.nterm = 2;
+            g.t[0] = GemmTerm{Wb.p, view[q].base + view[q].roff[2 * j], view[q].ld, Wb.rows, ka, 1,
+                              0};
+            g.t[1] = GemmTerm{Wb.p + ka, view[q].base + view[q].roff[2 * j + 1], view[q].ld,
+                              Wb.rows, kb, 1, 0};
+            if (g.M > 0) d.push_back(g);
+          }
+        }
+        gemm(d, false);
+        if (keep.size() >= 1) keep.erase(keep.begin());   // two stages alive at most
+        keep.push_back(std::move(buf));
+        view.swap(next);
+        if (lp == 1) P0buf.reset();
+      }
+      // Z_{l,i,j} = [P_{2j}; P_{2j+1}] of sample i  ->  W_{l,i,j}
+      std::vector<QRDesc> q((size_t)(ng * nS));
+      for (int64_t a = 0; a < ng; ++a)
+        for (int64_t j = 0; j < nS; ++j) {
+          const int64_t i = i0 + a;
+          const int32_t M = F_->kv(l - 1, i >> 1, 2 * j) + F_->kv(l - 1, i >> 1, 2 * j + 1);
+          q[(size_t)(a * nS + j)] =
+              QRDesc{view[a].base + view[a].roff[2 * j], nullptr, view[a].ld, M, width[i]};
+        }
+      std::vector<Block> blocks;
+      auto ranks = cpqr(q, false, blocks);
+      for (int64_t a = 0; a < ng; ++a)
+        for (int64_t j = 0; j < nS; ++j) {
+          const size_t b = (size_t)(((i0 + a) << (L() - l)) + j);
+          F_->W[l][b] = blocks[(size_t)(a * nS + j)];
+          F_->kv_ref(l, i0 + a, j) = ranks[(size_t)(a * nS + j)];
+        }
     }
-    // Z_{l,i,j} = [P_{2j}; P_{2j+1}] of sample i  ->  W_{l,i,j}
-    std::vector<QRDesc> q((size_t)nb());
-    for (int64_t i = 0; i < nT; ++i)
-      for (int64_t j = 0; j < nS; ++j) {
-        const int32_t M = F_->kv(l - 1, i >> 1, 2 * j) + F_->kv(l - 1, i >> 1, 2 * j + 1);
-        q[(size_t)((i << (L() - l)) + j)] =
-            QRDesc{view[i].base + view[i].roff[2 * j], nullptr, view[i].ld, M, width[i]};
-      }
-    std::vector<Block> blocks;
-    auto ranks = cpqr(q, false, blocks);
-    F_->W[l] = blocks;
-    for (int64_t i = 0; i < nT; ++i)
-      for (int64_t j = 0; j < nS; ++j) F_->kv_ref(l, i, j) = ranks[(size_t)((i << (L() - l)) + j)];
   }
 
   // ---- R sweep, level l (Sec. 4.2) and B at l_m (Sec. 4.4) -----------------
@@ -389,131 +412,150 @@ class Builder {
       smax = std::max(smax, width[j]);
     }
     auto Om = gauss(n, smax, L() - l, tags, width);
-    std::vector<int64_t> seg(nS + 1);
-    for (int64_t j = 0; j <= nS; ++j) seg[j] = node_lo(n, L() - l, j);
-    const int64_t ycols = nS * smax;
-    DevBuf<bf_c64> Y((size_t)m * ycols, s_);
-    call_op(false, Om.p, n, smax, Y.p, m, &seg);
     for (auto w : width) mv_cols_ += w;
-
-    // U^H stage (shared): PL rows ordered by leaf i
     int64_t rowsL = 0;
     std::vector<int64_t> roffL(nb());
     for (int64_t i = 0; i < nb(); ++i) { roffL[i] = rowsL; rowsL += F_->ku(L(), i, 0); }
-    DevBuf<bf_c128> PL((size_t)std::max<int64_t>(rowsL, 1) * ycols, s_);
-    {
-      std::vector<GemmDesc> d;
-      for (int64_t i = 0; i < nb(); ++i) {
-        const Block& U = F_->U[i];
-        GemmDesc g{};
-        g.out = PL.p + roffL[i];
-        g.out_ld = rowsL;
-        g.M = U.cols;
-        g.ncols = (int32_t)ycols;
-        g.nterm = 1;
-        g.t[0] = GemmTerm{U.p, Y.p + node_lo(m, L(), i), m, U.rows, U.rows, 1, 0};
-        if (g.M > 0) d.push_back(g);
-      }
-      gemm(d, true);
-    }
-    std::vector<Tall<bf_c128>> view(nS);
-    for (int64_t j = 0; j < nS; ++j) {
-      view[j].base = PL.p + (int64_t)j * smax * rowsL;
-      view[j].ld = rowsL;
-      view[j].roff = roffL;
-    }
-    std::vector<DevBuf<bf_c128>> keep;
-    for (int lp = L() - 1; lp > l; --lp) {
-      const int64_t nTl = int64_t(1) << lp;
-      std::vector<int64_t> base(nS);
-      std::vector<Tall<bf_c128>> next(nS);
-      int64_t tot = 0;
-      for (int64_t j = 0; j < nS; ++j) {
-        const int64_t jp = j >> (lp - l);
-        int64_t rows = 0;
-        next[j].roff.resize(nTl);
-        for (int64_t i = 0; i < nTl; ++i) { next[j].roff[i] = rows; rows += F_->ku(lp, i, jp); }
-        next[j].ld = std::max<int64_t>(rows, 1);
-        base[j] = tot;
-        tot += next[j].ld * width[j];
-      }
-      DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
-      std::vector<GemmDesc> d;
-      for (int64_t j = 0; j < nS; ++j) {
-        const int64_t jp = j >> (lp - l);
-        next[j].base = buf.p + base[j];
-        for (int64_t i = 0; i < nTl; ++i) {
-          const Block& Rb = F_->R[lp - lm()][(size_t)((i << (L() - lp)) + jp)];
-          const int32_t k1 = F_->ku(lp + 1, 2 * i, jp >> 1);
-          const int32_t k2 = F_->ku(lp + 1, 2 * i + 1, jp >> 1);
+    // per sample: Y (m x smax c64), the leaf stage and two chain stages (FP64)
+    const int64_t gsz = group_size(nS, (double)smax * (8.0 * m + 48.0 * (double)rowsL));
+    F_->R[l - lm()].assign((size_t)nb(), Block{});
+    if (l == lm()) F_->B.assign((size_t)nb(), Block{});
+    for (int64_t j0 = 0; j0 < nS; j0 += gsz) {
+      const int64_t j1 = std::min(nS, j0 + gsz), ng = j1 - j0;
+      std::vector<int64_t> seg(ng + 1);
+      for (int64_t q = 0; q <= ng; ++q) seg[q] = node_lo(n, L() - l, j0 + q);
+      const int64_t ycols = ng * smax;
+      DevBuf<bf_c64> Y((size_t)m * ycols, s_);
+      call_op(false, Om.p, n, smax, Y.p, m, &seg);
+
+      // U^H stage (shared by the group's samples): PL rows by leaf i
+      DevBuf<bf_c128> PL((size_t)std::max<int64_t>(rowsL, 1) * ycols, s_);
+      {
+        std::vector<GemmDesc> d;
+        for (int64_t i = 0; i < nb(); ++i) {
+          const Block& U = F_->U[i];
           GemmDesc g{};
-          g.out = const_cast<bf_c128*>(next[j].base) + next[j].roff[i];
-          g.out_ld = next[j].ld;
-          g.M = Rb.cols;
-          g.ncols = width[j];
-          g.nterm = 2;
-          g.t[0] = GemmTerm{Rb.p, view[j].base + view[j].roff[2 * i], view[j].ld, Rb.rows, k1, 1, 0};
-          g.t[1] = GemmTerm{Rb.p + k1, view[j].base + view[j].roff[2 * i + 1], view[j].ld, Rb.rows,
-                            k2, 1, 0};
+          g.out = PL.p + roffL[i];
+          g.out_ld = rowsL;
+          g.M = U.cols;
+          g.ncols = (int32_t)ycols;
+          g.nterm = 1;
+          g.t[0] = GemmTerm{U.p, Y.p + node_lo(m, L(), i), m, U.rows, U.rows, 1, 0};
           if (g.M > 0) d.push_back(g);
         }
+        gemm(d, true);
       }
-      gemm(d, false);
-      keep.push_back(std::move(buf));
-      view.swap(next);
+      Y.reset();
+      // view[q] is sample j0 + q
+      std::vector<Tall<bf_c128>> view(ng);
+      for (int64_t q = 0; q < ng; ++q) {
+        view[q].base = PL.p + q * smax * rowsL;
+        view[q].ld = rowsL;
+        view[q].roff = roffL;
+      }
+      std::vector<DevBuf<bf_c128>> keep;
+      for (int lp = L() - 1; lp > l; --lp) {
+        const int64_t nTl = int64_t(1) << lp;
+        std::vector<int64_t> base(ng);
+        std::vector<Tall<bf_c128>> next(ng);
+        int64_t tot = 0;
+        for (int64_t q = 0; q < ng; ++q) {
+          const int64_t jp = (j0 + q) >> (lp - l);
+          int64_t rows = 0;
+          next[q].roff.resize(nTl);
+          for (int64_t i = 0; i < nTl; ++i) { next[q].roff[i] = rows; rows += F_->ku(lp, i, jp); }
+          next[q].ld = std::max<int64_t>(rows, 1);
+          base[q] = tot;
+          tot += next[q].ld * width[j0 + q];
+        }
+        DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
+        std::vector<GemmDesc> d;
+        for (int64_t q = 0; q < ng; ++q) {
+          const int64_t jp = (j0 + q) >> (lp - l);
+          next[q].base = buf.p + base[q];
+          for (int64_t i = 0; i < nTl; ++i) {
+            const Block& Rb = F_->R[lp - lm()][(size_t)((i << (L() - lp)) + jp)];
+            const int32_t k1 = F_->ku(lp + 1, 2 * i, jp >> 1);
+            const int32_t k2 = F_->ku(lp + 1, 2 * i + 1, jp >> 1);
+            GemmDesc g{};
+            g.out = const_cast<bf_c128*>(next[q].base) + next[q].roff[i];
+            g.out_ld = next[q].ld;
+            g.M = Rb.cols;
+            g.ncols = width[j0 + q];
+            g.nterm = 2;
+            g.t[0] = GemmTerm{Rb.p, view[q].base + view[q].roff[2 * i], view[q].ld, Rb.rows, k1,
+                              1, 0};
+            g.t[1] = GemmTerm{Rb.p + k1, view[q].base + view[q].roff[2 * i + 1], view[q].ld,
+                              Rb.rows, k2, 1, 0};
+            if (g.M > 0) d.push_back(g);
+          }
+        }
+        gemm(d, false);
+        if (!keep.empty()) keep.erase(keep.begin());   // two stages alive at most
+        keep.push_back(std::move(buf));
+        view.swap(next);
+        if (lp == L() - 1) PL.reset();
+      }
+      // Z_{l,i,j} = [P_{2i}; P_{2i+1}] of sample j  ->  R_{l,i,j}; local order
+      // i * ng + (j - j0)
+      std::vector<QRDesc> zq((size_t)(nT * ng));
+      for (int64_t i = 0; i < nT; ++i)
+        for (int64_t q = 0; q < ng; ++q) {
+          const int64_t j = j0 + q;
+          const int32_t M = F_->ku(l + 1, 2 * i, j >> 1) + F_->ku(l + 1, 2 * i + 1, j >> 1);
+          zq[(size_t)(i * ng + q)] =
+              QRDesc{view[q].base + view[q].roff[2 * i], nullptr, view[q].ld, M, width[j]};
+        }
+      std::vector<Block> blocks;
+      auto ranks = cpqr(zq, false, blocks);
+      for (int64_t i = 0; i < nT; ++i)
+        for (int64_t q = 0; q < ng; ++q) {
+          const size_t b = (size_t)((i << (L() - l)) + j0 + q);
+          F_->R[l - lm()][b] = blocks[(size_t)(i * ng + q)];
+          F_->ku_ref(l, i, j0 + q) = ranks[(size_t)(i * ng + q)];
+        }
+      if (l == lm()) centre_blocks(Om, width, j0, j1, zq);
     }
-    // Z_{l,i,j} = [P_{2i}; P_{2i+1}] of sample j  ->  R_{l,i,j}
-    std::vector<QRDesc> q((size_t)nb());
-    for (int64_t i = 0; i < nT; ++i)
-      for (int64_t j = 0; j < nS; ++j) {
-        const int32_t M = F_->ku(l + 1, 2 * i, j >> 1) + F_->ku(l + 1, 2 * i + 1, j >> 1);
-        q[(size_t)((i << (L() - l)) + j)] =
-            QRDesc{view[j].base + view[j].roff[2 * i], nullptr, view[j].ld, M, width[j]};
-      }
-    std::vector<Block> blocks;
-    auto ranks = cpqr(q, false, blocks);
-    F_->R[l - lm()] = blocks;
-    for (int64_t i = 0; i < nT; ++i)
-      for (int64_t j = 0; j < nS; ++j) F_->ku_ref(l, i, j) = ranks[(size_t)((i << (L() - l)) + j)];
-    if (l == lm()) centre_blocks(Om, width, smax, q);
   }
 
-  // X_{lm,i,j} = V_{tau,nu}^H Omega_nu by the nested row bases (V^0 on the
-  // leaves under nu, then W^1..W^{lm} restricted to nu's subtree), then
-  // C = R^H Z and B = C X^+ for every block of level l_m.
-  void centre_blocks(const DevBuf<bf_c64>& Om, const std::vector<int32_t>& width, int32_t smax,
-                     const std::vector<QRDesc>& zq) {
-    (void)smax;
+  // Samples j in [j0, j1) of level l_m: X_{lm,i,j} = V_{tau,nu}^H Omega_nu by
+  // the nested row bases (V^0 on the leaves under nu, then W^1..W^{lm}
+  // restricted to nu's subtree), then C = R^H Z and B = C X^+ for the blocks
+  // (i, j).  zq holds the Z blocks in the local order i * (j1 - j0) + (j - j0).
+  void centre_blocks(const DevBuf<bf_c64>& Om, const std::vector<int32_t>& width, int64_t j0,
+                     int64_t j1, const std::vector<QRDesc>& zq) {
     const int64_t n = F_->n;
     const int lmv = lm();
-    const int64_t nS = int64_t(1) << (L() - lmv), nT = int64_t(1) << lmv;
+    const int64_t nT = int64_t(1) << lmv, ng = j1 - j0;
     // level 0 (leaves under nu): per-sample tall, blocks j' local in [0, 2^lm)
     const int64_t nl0 = int64_t(1) << lmv;
-    std::vector<Tall<bf_c128>> view(nS);
-    std::vector<int64_t> base(nS);
+    std::vector<Tall<bf_c128>> view(ng);
+    std::vector<int64_t> base(ng);
     int64_t tot = 0;
-    for (int64_t j = 0; j < nS; ++j) {
+    for (int64_t q = 0; q < ng; ++q) {
+      const int64_t j = j0 + q;
       int64_t rows = 0;
-      view[j].roff.resize(nl0);
+      view[q].roff.resize(nl0);
       for (int64_t t = 0; t < nl0; ++t) {
-        view[j].roff[t] = rows;
+        view[q].roff[t] = rows;
         rows += F_->kv(0, 0, (j << lmv) + t);
       }
-      view[j].ld = std::max<int64_t>(rows, 1);
-      base[j] = tot;
-      tot += view[j].ld * width[j];
+      view[q].ld = std::max<int64_t>(rows, 1);
+      base[q] = tot;
+      tot += view[q].ld * width[j];
     }
     DevBuf<bf_c128> buf0((size_t)std::max<int64_t>(tot, 1), s_);
     {
       std::vector<GemmDesc> d;
-      for (int64_t j = 0; j < nS; ++j) {
-        view[j].base = buf0.p + base[j];
+      for (int64_t q = 0; q < ng; ++q) {
+        const int64_t j = j0 + q;
+        view[q].base = buf0.p + base[q];
         for (int64_t t = 0; t < nl0; ++t) {
           const int64_t jl = (j << lmv) + t;
           const Block& V = F_->V[jl];
           GemmDesc g{};
-          g.out = const_cast<bf_c128*>(view[j].base) + view[j].roff[t];
-          g.out_ld = view[j].ld;
+          g.out = const_cast<bf_c128*>(view[q].base) + view[q].roff[t];
+          g.out_ld = view[q].ld;
           g.M = V.cols;
           g.ncols = width[j];
           g.nterm = 1;
@@ -529,24 +571,26 @@ class Builder {
       const int64_t nTl = int64_t(1) << lp;
       const int64_t nSub = int64_t(1) << (lmv - lp);       // S-nodes of nu's subtree at S-level L-lp
       const int64_t nSubPrev = int64_t(1) << (lmv - lp + 1);
-      std::vector<Tall<bf_c128>> next(nS);
+      std::vector<Tall<bf_c128>> next(ng);
       tot = 0;
-      for (int64_t j = 0; j < nS; ++j) {
+      for (int64_t q = 0; q < ng; ++q) {
+        const int64_t j = j0 + q;
         int64_t rows = 0;
-        next[j].roff.resize(nTl * nSub);
+        next[q].roff.resize(nTl * nSub);
         for (int64_t i = 0; i < nTl; ++i)
           for (int64_t t = 0; t < nSub; ++t) {
-            next[j].roff[i * nSub + t] = rows;
+            next[q].roff[i * nSub + t] = rows;
             rows += F_->kv(lp, i, (j << (lmv - lp)) + t);
           }
-        next[j].ld = std::max<int64_t>(rows, 1);
-        base[j] = tot;
-        tot += next[j].ld * width[j];
+        next[q].ld = std::max<int64_t>(rows, 1);
+        base[q] = tot;
+        tot += next[q].ld * width[j];
       }
       DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
       std::vector<GemmDesc> d;
-      for (int64_t j = 0; j < nS; ++j) {
-        next[j].base = buf.p + base[j];
+      for (int64_t q = 0; q < ng; ++q) {
+        const int64_t j = j0 + q;
+        next[q].base = buf.p + base[q];
         for (int64_t i = 0; i < nTl; ++i)
           for (int64_t t = 0; t < nSub; ++t) {
             const int64_t jj = (j << (lmv - lp)) + t;   // global S-node at S-level L-lp
@@ -556,14 +600,14 @@ class Builder {
             // previous level's local indices: (i >> 1, 2t) and (i >> 1, 2t + 1)
             const int64_t pa = (lp == 1) ? 2 * t : (i >> 1) * nSubPrev + 2 * t;
             GemmDesc g{};
-            g.out = const_cast<bf_c128*>(next[j].base) + next[j].roff[i * nSub + t];
-            g.out_ld = next[j].ld;
+            g.out = const_cast<bf_c128*>(next[q].base) + next[q].roff[i * nSub + t];
+            g.out_ld = next[q].ld;
             g.M = Wb.cols;
             g.ncols = width[j];
             g.nterm = 2;
-            g.t[0] = GemmTerm{Wb.p, view[j].base + view[j].roff[pa], view[j].ld, Wb.rows, ka, 1, 0};
-            g.t[1] = GemmTerm{Wb.p + ka, view[j].base + view[j].roff[pa + 1], view[j].ld, Wb.rows, kb,
-                              1, 0};
+            g.t[0] = GemmTerm{Wb.p, view[q].base + view[q].roff[pa], view[q].ld, Wb.rows, ka, 1, 0};
+            g.t[1] = GemmTerm{Wb.p + ka, view[q].base + view[q].roff[pa + 1], view[q].ld, Wb.rows,
+                              kb, 1, 0};
             if (g.M > 0) d.push_back(g);
           }
       }
@@ -571,61 +615,64 @@ class Builder {
       keep.push_back(std::move(buf));
       view.swap(next);
     }
-    // C = R^H Z (kU x s) for every block (i, j)
-    std::vector<int64_t> coff((size_t)nb());
+    // C = R^H Z (kU x s) for every block (i, j) of the group
+    std::vector<int64_t> coff((size_t)(nT * ng));
     tot = 0;
     for (int64_t i = 0; i < nT; ++i)
-      for (int64_t j = 0; j < nS; ++j) {
-        coff[(size_t)((i << (L() - lmv)) + j)] = tot;
-        tot += (int64_t)F_->ku(lmv, i, j) * width[j];
+      for (int64_t q = 0; q < ng; ++q) {
+        coff[(size_t)(i * ng + q)] = tot;
+        tot += (int64_t)F_->ku(lmv, i, j0 + q) * width[j0 + q];
       }
     DevBuf<bf_c128> C((size_t)std::max<int64_t>(tot, 1), s_);
     {
       std::vector<GemmDesc> d;
       for (int64_t i = 0; i < nT; ++i)
-        for (int64_t j = 0; j < nS; ++j) {
-          const size_t b = (size_t)((i << (L() - lmv)) + j);
+        for (int64_t q = 0; q < ng; ++q) {
+          const size_t b = (size_t)((i << (L() - lmv)) + j0 + q);
+          const size_t lb = (size_t)(i * ng + q);
           const Block& Rb = F_->R[0][b];
           GemmDesc g{};
-          g.out = C.p + coff[b];
+          g.out = C.p + coff[lb];
           g.out_ld = std::max(Rb.cols, 1);
           g.M = Rb.cols;
-          g.ncols = width[j];
+          g.ncols = width[j0 + q];
           g.nterm = 1;
-          g.t[0] = GemmTerm{Rb.p, zq[b].in, zq[b].in_ld, Rb.rows, Rb.rows, 1, 0};
+          g.t[0] = GemmTerm{Rb.p, zq[lb].in, zq[lb].in_ld, Rb.rows, Rb.rows, 1, 0};
           if (g.M > 0) d.push_back(g);
         }
       gemm(d, false);
     }
-    solve_b(C.p, coff, view, width, [&](int64_t i, int64_t j) { return i; });
+    solve_b(C.p, coff, view, width, j0, j1, [&](int64_t i, int64_t) { return i; });
   }
 
+  // B = C X^+ for the blocks (i, j), j in [j0, j1), of level l_m; C and xview
+  // use the group's local order (C block i * (j1 - j0) + (j - j0), xview[j - j0]).
   template <typename IdxFn>
   void solve_b(const bf_c128* C, const std::vector<int64_t>& coff,
                const std::vector<Tall<bf_c128>>& xview, const std::vector<int32_t>& width,
-               IdxFn xblock) {
+               int64_t j0, int64_t j1, IdxFn xblock) {
     const int lmv = lm();
-    const int64_t nS = int64_t(1) << (L() - lmv), nT = int64_t(1) << lmv;
-    std::vector<int64_t> boff((size_t)nb());
+    const int64_t nT = int64_t(1) << lmv, ng = j1 - j0;
+    std::vector<int64_t> boff((size_t)(nT * ng));
     int64_t tot = 0;
     for (int64_t i = 0; i < nT; ++i)
-      for (int64_t j = 0; j < nS; ++j) {
-        boff[(size_t)((i << (L() - lmv)) + j)] = tot;
-        tot += (int64_t)F_->ku(lmv, i, j) * F_->kv(lmv, i, j);
+      for (int64_t q = 0; q < ng; ++q) {
+        boff[(size_t)(i * ng + q)] = tot;
+        tot += (int64_t)F_->ku(lmv, i, j0 + q) * F_->kv(lmv, i, j0 + q);
       }
     DevBuf<bf_c128> Bst((size_t)std::max<int64_t>(tot, 1), s_);
     std::vector<LSDesc> d;
     int32_t maxS = 0, maxK = 0;
-    F_->B.assign((size_t)nb(), Block{});
     for (int64_t i = 0; i < nT; ++i)
-      for (int64_t j = 0; j < nS; ++j) {
-        const size_t b = (size_t)((i << (L() - lmv)) + j);
+      for (int64_t q = 0; q < ng; ++q) {
+        const int64_t j = j0 + q;
+        const size_t b = (size_t)((i << (L() - lmv)) + j), lb = (size_t)(i * ng + q);
         const int32_t ku = F_->ku(lmv, i, j), kv = F_->kv(lmv, i, j);
-        F_->B[b] = Block{Bst.p + boff[b], ku, kv};
+        F_->B[b] = Block{Bst.p + boff[lb], ku, kv};
         if (ku == 0 || kv == 0) continue;
         BF_CHECK(width[j] >= kv, BF_EINVAL, "centre sample narrower than the row rank");
-        const Tall<bf_c128>& xv = xview[j];
-        LSDesc ls{C + coff[b], xv.base + xv.roff[xblock(i, j)], Bst.p + boff[b],
+        const Tall<bf_c128>& xv = xview[q];
+        LSDesc ls{C + coff[lb], xv.base + xv.roff[xblock(i, j)], Bst.p + boff[lb],
                   (int64_t)std::max(ku, 1), xv.ld, ku, kv, width[j], 0};
         d.push_back(ls);
         maxS = std::max(maxS, width[j]);
@@ -672,7 +719,8 @@ class Builder {
     xv[0].base = X.p;
     xv[0].ld = std::max(kv, 1);
     xv[0].roff = {0};
-    solve_b(C.p, {0}, xv, width, [](int64_t, int64_t) { return 0; });
+    F_->B.assign(1, Block{});
+    solve_b(C.p, {0}, xv, width, 0, 1, [](int64_t, int64_t) { return 0; });
   }
 
   void finalize() {

@@ -53,7 +53,7 @@ struct bf_factors {
   std::vector<std::vector<bf::Block>> W;    // W[l][i * 2^(L-l) + j], 1 <= l <= lm
   std::vector<int32_t> kU, kV;              // ranks, layout of bf_ranks
   bf::ApplyPlan fwd, adj;
-  int apply_prec = BF_PREC_FP32;            // bf_set_apply_precision
+  int apply_prec = BF_PREC_BF16X3;          // bf_set_apply_precision
   bf_info info{};
   int device = 0;
 

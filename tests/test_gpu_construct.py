@@ -152,3 +152,31 @@ def test_rank_cap_error(bf):
     with pytest.raises(bf.BFError) as ei:
         bf.construct(op, 1e-6, 64, seed=1, max_rank=4)
     assert ei.value.code == -4
+
+
+@pytest.mark.parametrize("m,n,leaf", [(2048, 2048, 16), (1500, 1100, 20)])
+def test_sample_groups(bf, m, n, leaf):
+    """Sweep levels processed one sample at a time (workspace bound of one
+    byte) give the factorization of the unbounded run: same ranks, same error
+    to rounding, and the error of the oracle's construction."""
+    g = wl.segment_pair(n, ppw=8.0, m=m)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    say("sample groups", m, n, leaf)
+    A = bf.construct(op, 1e-6, leaf, seed=12)
+    B = bf.construct(op, 1e-6, leaf, seed=12, work_bytes=1)
+    ua, va = A.ranks()
+    ub, vb = B.ranks()
+    assert np.abs(ua.astype(int) - ub).max() <= 1 and np.abs(va.astype(int) - vb).max() <= 1
+    assert (ua != ub).mean() < 0.01 and (va != vb).mean() < 0.01
+    ref = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    Om = wl.test_columns(n, 16, 5)
+    AOm = ref.matvec(Om)
+    ea = _err(AOm, A.apply(_t(Om)).cpu().numpy())
+    eb = _err(AOm, B.apply(_t(Om)).cpu().numpy())
+    Fo = obf.construct(ref, 1e-6, leaf, seed=12)
+    eo = _err(AOm, obf.apply(Fo, Om))
+    say("groups errors", ea, eb, "oracle", eo)
+    assert abs(ea - eb) <= 0.05 * ea + 1e-8
+    assert eb <= 2 * eo + 1e-7
+    with pytest.raises(bf.BFError):
+        bf.construct(op, 1e-6, leaf, seed=12, work_bytes=-1)

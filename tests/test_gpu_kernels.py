@@ -228,6 +228,8 @@ def test_apply_precisions(bf, n, leaf):
         for prec in ("fp32", "bf16x3"):
             H.set_precision(prec)
             out[prec] = (H.apply(_t(X)).cpu().numpy(), H.apply(_t(X), trans=True).cpu().numpy())
+            say("apply", prec, s, "forward", _rel(out[prec][0], ref), "adjoint",
+                _rel(out[prec][1], refh))
             assert _rel(out[prec][0], ref) < 1e-6, (s, prec)
             assert _rel(out[prec][1], refh) < 1e-6, (s, prec)
             for c in range(s):    # every column, so no tile or chunk is skipped
