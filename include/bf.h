@@ -127,7 +127,7 @@ int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64
  * Apply the factorization (eq. hybrid_butterfly_mat, right to left):
  *   trans = 0 : Y = F X,   X is n x ncols (ldx >= n), Y is m x ncols (ldy >= m)
  *   trans = 1 : Y = F^H X, X is m x ncols,            Y is n x ncols
- * complex64 data, FP32 accumulation.  X, Y are caller-owned device buffers
+ * complex64 data (arithmetic: bf_set_apply_precision).  X, Y are caller-owned device buffers
  * and must not overlap.  Reentrant across streams for one handle.
  */
 int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
@@ -337,12 +337,13 @@ int bf_op_set_precision(bf_operator* op, int precision);
 
 /* Arithmetic of bf_apply (and of the factors as a black box, bf_op_factors)
  * for F (eq. hybrid_butterfly_mat, complex64 data in both modes):
- *   BF_PREC_FP32   : FP32 multiply-adds on the vector ALUs;
- *   BF_PREC_BF16X3 : stages with 16 or more right-hand sides on the BF16
- *                    matrix cores, factor entries and inputs split into three
- *                    BF16 terms (products kept to 2^-24 relative), FP32
- *                    accumulation; fewer right-hand sides use the FP32 path
- *                    (default: as accurate as FP32 and about twice as fast).
+ *   BF_PREC_FP32   : FP32 multiply-adds and sums on the vector ALUs;
+ *   BF_PREC_BF16X3 : (default) stages with 5 or more right-hand sides on the
+ *                    BF16 matrix cores, factor entries and inputs split into
+ *                    three BF16 terms (products kept to 2^-24 relative),
+ *                    FP32 sums rounded once per 32-term matrix instruction
+ *                    (faster than FP32 and about twice as accurate); 1 to 4
+ *                    on the vector ALUs, with FP64 sums for a single one.
  * Not synchronized with applies in flight on F: set it before applying.
  * Returns BF_EINVAL for a null F or another value. */
 int bf_set_apply_precision(bf_factors* F, int precision);

@@ -312,8 +312,9 @@ class Factors:
 
     def set_precision(self, precision):
         """Arithmetic of apply and of the factors as a black box: 'bf16x3' (BF16
-        matrix cores for >= 16 right-hand sides, operands split into three BF16
-        terms; default) or 'fp32' (vector ALUs)."""
+        matrix cores for >= 5 right-hand sides, operands split into three BF16
+        terms; vector ALUs below, FP64 sums for one; default) or 'fp32' (vector
+        ALUs, FP32)."""
         code = {"fp32": 2, "bf16x3": 1}[precision]
         _check(lib().bf_set_apply_precision(self._h, code), "bf_set_apply_precision")
         return self

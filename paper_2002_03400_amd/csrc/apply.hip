@@ -28,7 +28,22 @@ constexpr int AP_SMALL = 4;
 
 // ncols <= 4: a group of 16 lanes per output row; the row's record holds
 // every address it needs (one dependent load), the inner loop is unrolled so
-// the factor and input loads of a row issue together.
+// the factor and input loads of a row issue together.  Acc is cf (FP32 sums)
+// or cd (FP64 sums of the FP32 products, used by the default mode for a
+// single right-hand side, where the extra registers cost no time: a stage
+// then rounds essentially once, at its complex64 output).
+template <typename Acc>
+__device__ __forceinline__ void acc_fma(Acc& a, bf_c64 g, bf_c64 x);
+template <>
+__device__ __forceinline__ void acc_fma<cf>(cf& a, bf_c64 g, bf_c64 x) {
+  cf_fma(a, cf{g.re, g.im}, cf{x.re, x.im});
+}
+template <>
+__device__ __forceinline__ void acc_fma<cd>(cd& a, bf_c64 g, bf_c64 x) {
+  cd_fma(a, cd{(double)g.re, (double)g.im}, cd{(double)x.re, (double)x.im});
+}
+
+template <typename Acc, int NC>
 __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __restrict__ rows,
                                                            int32_t nrows,
                                                            const bf_c64* __restrict__ G,
@@ -42,11 +57,11 @@ __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __
   const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
   const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
   const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
-  cf acc[AP_SMALL];
+  Acc acc[NC];
 #pragma unroll
-  for (int c = 0; c < AP_SMALL; ++c) acc[c] = cf{0.f, 0.f};
+  for (int c = 0; c < NC; ++c) acc[c] = Acc{0, 0};
   for (int kb = 0; kb < KK; kb += 64) {
-    bf_c64 gv[4], xv[4][AP_SMALL];
+    bf_c64 gv[4], xv[4][NC];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = kb + q + 16 * u;
@@ -55,17 +70,16 @@ __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __
       const bf_c64* inp = k < rr.K0 ? in0 + k : in1 + k;
       const int64_t ldk = k < rr.K0 ? ld0 : ld1;
 #pragma unroll
-      for (int c = 0; c < AP_SMALL; ++c)
+      for (int c = 0; c < NC; ++c)
         xv[u][c] = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int c = 0; c < AP_SMALL; ++c)
-        cf_fma(acc[c], cf{gv[u].re, gv[u].im}, cf{xv[u][c].re, xv[u][c].im});
+      for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[u], xv[u][c]);
   }
 #pragma unroll
-  for (int c = 0; c < AP_SMALL; ++c) {
+  for (int c = 0; c < NC; ++c) {
 #pragma unroll
     for (int off = 8; off >= 1; off >>= 1) {
       acc[c].re += __shfl_xor(acc[c].re, off, 16);
@@ -76,8 +90,8 @@ __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __
     bf_c64* out = B.p[rr.out_buf] + rr.out;
     const int64_t ldo = B.ld[rr.out_buf];
 #pragma unroll
-    for (int c = 0; c < AP_SMALL; ++c)
-      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{acc[c].re, acc[c].im};
+    for (int c = 0; c < NC; ++c)
+      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
   }
 }
 
@@ -135,7 +149,7 @@ __global__ __launch_bounds__(256) void apply_blocked_kernel(const ApplyBlk* __re
   }
 }
 
-// ---- split-BF16 stage (right-hand-side count >= AM_MIN_COLS) ------------
+// ---- split-BF16 stage (more than AP_SMALL right-hand sides) --------------
 //
 // Same stage as apply_blocked_kernel on the BF16 matrix cores: every factor
 // entry and input value is split into three BF16 terms, g = g1 + g2 + g3,
@@ -167,7 +181,7 @@ __device__ __forceinline__ void asplit3(float x0, float x1, uint32_t& h, uint32_
 constexpr int AM_KT = 32;            // inner indices per staged chunk
 constexpr int AM_KP = AM_KT + 8;     // padded k stride of a plane row
 constexpr int AM_R = 64;             // rows per row block
-constexpr int AM_MIN_COLS = 16;
+constexpr int AM_MIN_COLS = AP_SMALL + 1;
 
 __global__ __launch_bounds__(256) void apply_mfma_kernel(const ApplyBlk* __restrict__ blks,
                                                          const bf_c64* __restrict__ G,
@@ -317,8 +331,17 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
     B.ld[i] = lds[i];
   }
   if (ncols <= AP_SMALL) {
-    hipLaunchKernelGGL(apply_stream_kernel, dim3((unsigned)((nrows + 15) / 16)), dim3(256), 0, s,
-                       rows_dev, nrows, G, B, (int32_t)ncols);
+    const dim3 grid((unsigned)((nrows + 15) / 16));
+    const int nc = (int)ncols;
+#define AP_STREAM(ACC, N) \
+    hipLaunchKernelGGL((apply_stream_kernel<ACC, N>), grid, dim3(256), 0, s, rows_dev, nrows, G, B, nc)
+    if (prec == BF_PREC_FP32) {
+      if (nc == 1) AP_STREAM(cf, 1); else if (nc == 2) AP_STREAM(cf, 2); else AP_STREAM(cf, 4);
+    } else {
+      // FP64 sums cost nothing at one right-hand side and ~2x at four
+      if (nc == 1) AP_STREAM(cd, 1); else if (nc == 2) AP_STREAM(cf, 2); else AP_STREAM(cf, 4);
+    }
+#undef AP_STREAM
   } else if (prec == BF_PREC_BF16X3 && ncols >= AM_MIN_COLS) {
     const int64_t ych = (ncols + AP_CW - 1) / AP_CW;
     BF_CHECK(ych <= 65535, BF_EINVAL, "too many right-hand sides");

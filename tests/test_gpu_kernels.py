@@ -211,8 +211,9 @@ def test_apply_of_oracle_factors(bf, n, leaf):
 @pytest.mark.parametrize("n,leaf", [(2000, 40), (4096, 16)])
 def test_apply_precisions(bf, n, leaf):
     """Applies of imported oracle factors with FP32 vector arithmetic and
-    with split-BF16 matrix cores (>= 16 right-hand sides; fewer fall back to
-    FP32), forward and adjoint, against the oracle's FP64 apply."""
+    with the default arithmetic (split-BF16 matrix cores from 5 right-hand
+    sides, FP64 sums below), forward and adjoint, against the oracle's FP64
+    apply; the default is at least as accurate."""
     g = wl.segment_pair(n, ppw=6.0)
     op = ops.SegmentKernelOp(g.targets, g.sources, g.k)
     F = obf.construct(op, 1e-6, leaf, seed=2)
@@ -220,7 +221,7 @@ def test_apply_precisions(bf, n, leaf):
     say("apply precisions", n, leaf, F.L)
     H = bf.import_factors(n, n, leaf, kU, kV, data)
     rng = np.random.default_rng(7)
-    for s in (3, 16, 40, 100):
+    for s in (1, 3, 6, 16, 40, 100):
         X = _cg(rng, n, s)
         ref = obf.apply(F, X)
         refh = obf.apply_adjoint(F, X)
@@ -234,9 +235,8 @@ def test_apply_precisions(bf, n, leaf):
             assert _rel(out[prec][1], refh) < 1e-6, (s, prec)
             for c in range(s):    # every column, so no tile or chunk is skipped
                 assert np.linalg.norm(out[prec][0][:, c] - ref[:, c]) <= 2e-6 * np.linalg.norm(ref[:, c])
-        # below 16 columns both settings run the same FP32 stages
-        if s < 16:
-            np.testing.assert_array_equal(out["fp32"][0], out["bf16x3"][0])
+        e32, e16 = _rel(out["fp32"][0], ref), _rel(out["bf16x3"][0], ref)
+        assert e16 <= 1.2 * e32 + 1e-8, (s, e16, e32)
     with pytest.raises(bf.BFError):
         lib_rc = bf.lib().bf_set_apply_precision(H._h, 0)
         bf._check(lib_rc, "bf_set_apply_precision")
