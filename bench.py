@@ -56,10 +56,57 @@ def parse():
                     help="requests of the Poisson stream at the headline size (0 = skip)")
     ap.add_argument("--mix", type=int, default=0,
                     help="also run the mixed serving stream with this many requests")
+    ap.add_argument("--exact-scaling", default="",
+                    help="only recover exact random butterflies (Sec. 6.1: r = 8, leaf 8) "
+                         "through the butterfly black box at these comma-separated L and "
+                         "print one JSON line per L")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (reference "
                          "dispatch for calibrating rocprofv3 byte counters) and exit")
     return ap.parse_args()
+
+
+def exact_scaling(levels, r=8, leaf=8, tol=1e-5):
+    """Sec. 6.1 workload at growing L: random exact butterflies (all ranks r)
+    recovered with the butterfly as the black box; time of the construction
+    (second of two), ranks, factor entries and device bytes, error against
+    the source factors on 16 Gaussian columns."""
+    import torch
+
+    import paper_2002_03400_amd as bf
+    import workloads as wl
+    torch.cuda.init()
+    for L in levels:
+        n = leaf << L
+        kU, kV, data = wl.exact_butterfly_canonical(L, r, seed=L)
+        src = bf.import_factors(n, n, leaf, kU, kV, data)
+        del data
+        op = bf.from_factors(src)
+        Om = torch.from_numpy(wl.test_columns(n, 16, 1001).astype(np.complex64)).cuda()
+        ref = src.apply(Om)
+        for rep in range(2):
+            bf.profile_start()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F = bf.construct(op, tol, leaf, seed=3 + rep)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            prof = bf.profile_stop()
+            gU, gV = F.ranks()
+            st = F.stats()
+            err = float((F.apply(Om) - ref).norm() / ref.norm())
+            if rep == 1:
+                print(json.dumps({
+                    "workload": "exact random butterfly (Sec. 6.1), butterfly black box",
+                    "L": L, "n": n, "r": r, "leaf": leaf, "tol": tol, "seconds": dt,
+                    "rel_err": err, "ranks": sorted({int(x) for x in np.unique(gU)} |
+                                                    {int(x) for x in np.unique(gV)}),
+                    "factor_entries": st.factor_entries, "device_bytes": st.device_bytes,
+                    "phase_ms": {k: v["ms"] for k, v in prof.items()}}), flush=True)
+            F.close()
+        op.close()
+        src.close()
+        torch.cuda.empty_cache()
 
 
 def copy_calibration():
@@ -152,6 +199,34 @@ def cpu_baseline_leg(geom, F_gpu, args, passes):
     }
 
 
+def apply_roofline(bf, F, n, reps=20):
+    """bf_apply of the benchmarked factors (default arithmetic) at 1, 4, 16
+    and 64 right-hand sides: algorithmic bytes (8 per factor entry + 8 per
+    input and output value) over the stages' HIP-event time, against the HBM
+    peak; the wall time per apply includes the launches."""
+    import torch
+    out = {}
+    for s in (1, 4, 16, 64):
+        X = torch.randn(n, s, dtype=torch.complex64, device="cuda")
+        Y = F.apply(X)
+        torch.cuda.synchronize()
+        bf.profile_start()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            F.apply(X, out=Y)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        ap = bf.profile_stop()["apply"]
+        kms = ap["ms"] / reps
+        gbs = ap["bytes"] / reps / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+        out[f"s={s}"] = {"kernel_ms": kms, "wall_ms": wall * 1e3,
+                         "bytes": ap["bytes"] / reps, "GB_per_s": gbs,
+                         "frac_hbm": gbs / PEAK_HBM_GBS,
+                         "TFLOP_per_s": ap["flops"] / reps / (kms * 1e-3) / 1e12 if kms > 0 else 0.0,
+                         "stages": ap["launches"] // reps}
+    return out
+
+
 def run_served(bf, reqs, slots, leaf, keep_last=False):
     """Replay a request stream in real time through the request engine.
     Returns (wall seconds, [latency s of constructions], [latency s of applies],
@@ -199,6 +274,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.exact_scaling:
+        exact_scaling([int(x) for x in args.exact_scaling.split(",")])
         return
     import torch
 
@@ -260,6 +338,7 @@ def main():
                "apply_p50_ms": 1e3 * pct(lat_ma, 50), "apply_p99_ms": 1e3 * pct(lat_ma, 99)}
 
     rel_err, cpu = cpu_baseline_leg(geom, last, args, passes)
+    apply_rl = apply_roofline(bf, last, args.n)
 
     mf = prof["matfree"]
     achieved = mf["flops"] / (mf["ms"] * 1e-3) / 1e12 if mf["ms"] > 0 else 0.0
@@ -311,6 +390,7 @@ def main():
             "launches": mf["launches"],
         },
         "phase_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
+        "apply_roofline": apply_rl,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -180,3 +180,25 @@ def test_sample_groups(bf, m, n, leaf):
     assert eb <= 2 * eo + 1e-7
     with pytest.raises(bf.BFError):
         bf.construct(op, 1e-6, leaf, seed=12, work_bytes=-1)
+
+
+def test_exact_butterfly_at_scale(bf):
+    """Sec. 6.1 at L = 12 (n = 32768, leaf 8, r = 8, random factors drawn level
+    by level): recovered through the butterfly black box with every rank 8 and
+    complex64-level error; factor storage is that of the source (O(n log n))."""
+    L, r, leaf = 12, 8, 8
+    n = leaf << L
+    kU, kV, data = wl.exact_butterfly_canonical(L, r, seed=5)
+    say("exact at scale", L)
+    src = bf.import_factors(n, n, leaf, kU, kV, data)
+    H = bf.construct(bf.from_factors(src), 1e-5, leaf, seed=6)
+    gU, gV = H.ranks()
+    assert set(np.unique(gU)) == {r} and set(np.unique(gV)) == {r}
+    assert H.stats().factor_entries == src.stats().factor_entries
+    Om = _t(wl.test_columns(n, 16, 3))
+    ref = src.apply(Om)
+    e = float((H.apply(Om) - ref).norm() / ref.norm())
+    say("exact at scale err", e)
+    assert e < 2e-6
+    H.close()
+    src.close()

@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "SegmentGeometry", "segment_pair", "segment_triple", "fio_params",
     "test_columns", "ExactButterflyFactors", "exact_butterfly_factors",
-    "node_range_host", "Request", "poisson_stream", "mixed_stream",
+    "node_range_host", "Request", "poisson_stream", "mixed_stream", "exact_butterfly_canonical",
 ]
 
 
@@ -137,6 +137,40 @@ def exact_butterfly_factors(L: int, r: int, seed: int = 7, leaf: int = 8) -> Exa
     B = {(i, j): (rng.standard_normal((r, r)) + 1j * rng.standard_normal((r, r))) / math.sqrt(2)
          for i in range(1 << lm) for j in range(1 << (L - lm))}
     return ExactButterflyFactors(L, r, n, U, V, R, W, B)
+
+
+def _unitary_batch(rng, count, rows, cols):
+    z = rng.standard_normal((count, rows, cols)) + 1j * rng.standard_normal((count, rows, cols))
+    q, _ = np.linalg.qr(z)
+    return q[:, :, :cols]
+
+
+def exact_butterfly_canonical(L: int, r: int, seed: int = 7, leaf: int = 8):
+    """Random exact butterfly of Sec. 6.1 at scale (n = leaf * 2^L, every rank
+    r), drawn level by level with batched QR and laid out directly in the
+    library's canonical factor order: U (leaf x r per leaf), R^{L-1..lm}
+    (2r x r), B (r x r), W^{lm..1} (2r x r), V (leaf x r), each block column-
+    major, blocks of a level in the order i * 2^(L-l) + j.  Returns (kU, kV,
+    data) with kU of shape (L - lm + 1, 2^L) and kV of shape (lm + 1, 2^L).
+    A different draw than exact_butterfly_factors (batched), same law."""
+    if r > leaf:
+        raise ValueError("rank cannot exceed the leaf size")
+    rng = np.random.default_rng(seed)
+    nb = 1 << L
+    lm = L // 2
+    parts = []
+    colmajor = lambda a: np.ascontiguousarray(np.transpose(a, (0, 2, 1))).ravel()
+    parts.append(colmajor(_unitary_batch(rng, nb, leaf, r)))                 # U
+    for _ in range(L - 1, lm - 1, -1):
+        parts.append(colmajor(_unitary_batch(rng, nb, 2 * r, r)))            # R^l
+    b = (rng.standard_normal((nb, r, r)) + 1j * rng.standard_normal((nb, r, r))) / math.sqrt(2)
+    parts.append(colmajor(b))                                                # B
+    for _ in range(lm, 0, -1):
+        parts.append(colmajor(_unitary_batch(rng, nb, 2 * r, r)))            # W^l
+    parts.append(colmajor(_unitary_batch(rng, nb, leaf, r)))                 # V
+    kU = np.full((L - lm + 1, nb), r, np.int32)
+    kV = np.full((lm + 1, nb), r, np.int32)
+    return kU, kV, np.concatenate(parts).astype(np.complex128)
 
 
 @dataclass
