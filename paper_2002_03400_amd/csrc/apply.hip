@@ -290,6 +290,95 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(const ApplyBlk* __restr
   }
 }
 
+// Small blocks (every block of the stage has M <= 16): one wave per block
+// (its single 16-row tile) and 64 columns, four waves per workgroup.  The
+// wave loads its A operands (8 consecutive k of one factor row per lane) and
+// B operands (8 consecutive k of one input column per lane) straight into
+// registers and splits them there: no LDS, no barriers, so the per-block cost
+// is a few loads and 24 MFMAs per 16-column tile instead of a workgroup's
+// staging passes.
+__device__ __forceinline__ void am_split8(const bf_c64 (&v)[8], au32x4 (&pl)[6]) {
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    uint32_t h, m, l;
+    asplit3(v[2 * d].re, v[2 * d + 1].re, h, m, l);
+    pl[0][d] = h; pl[2][d] = m; pl[4][d] = l;
+    asplit3(v[2 * d].im, v[2 * d + 1].im, h, m, l);
+    pl[1][d] = h; pl[3][d] = m; pl[5][d] = l;
+  }
+}
+
+__global__ __launch_bounds__(256) void apply_mfma_small_kernel(const ApplyBlk* __restrict__ blks,
+                                                               int32_t nblk,
+                                                               const bf_c64* __restrict__ G,
+                                                               ApplyBufs B, int64_t ncols) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t bi = (int64_t)blockIdx.x * 4 + wave;
+  if (bi >= nblk) return;
+  const ApplyBlk bk = blks[bi];
+  const int64_t c0 = (int64_t)blockIdx.y * AP_CW;
+  const int cw = (int)((ncols - c0 < AP_CW) ? ncols - c0 : AP_CW);
+  const int M = bk.M, K0 = bk.K0, KK = bk.K0 + bk.K1;
+  const int lc = lane & 15, kq = lane >> 4;
+  const bf_c64* grow = G + bk.g_off + (int64_t)lc * KK;   // factor row lc (row-major M x KK)
+  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0;
+  const bf_c64* in1 = B.p[bk.in_buf1] + bk.in_row1 - K0;   // indexed by k >= K0
+  const int64_t ld0 = B.ld[bk.in_buf0], ld1 = B.ld[bk.in_buf1];
+  const int nct = (cw + 15) >> 4;
+  afloatx4 R[4], I[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) { R[t] = afloatx4{0.f, 0.f, 0.f, 0.f}; I[t] = R[t]; }
+  for (int k0 = 0; k0 < KK; k0 += 32) {
+    const int kb = k0 + 8 * kq;
+    bf_c64 v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      v[e] = (lc < M && kb + e < KK) ? grow[kb + e] : bf_c64{0.f, 0.f};
+    au32x4 ga[6], gn[3];
+    am_split8(v, ga);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) gn[q] = ga[2 * q + 1] ^ 0x80008000u;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < nct) {
+        const int c = t * 16 + lc;
+        const int64_t col = c0 + (c < cw ? c : 0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = kb + e;
+          bf_c64 x = {0.f, 0.f};
+          if (c < cw && k < KK) x = k < K0 ? in0[col * ld0 + k] : in1[col * ld1 + k];
+          v[e] = x;
+        }
+        au32x4 xb[6];
+        am_split8(v, xb);
+#define AM_MM(A, Bv, C) \
+  C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(abf16x8, A), \
+                                              __builtin_bit_cast(abf16x8, Bv), C, 0, 0, 0);
+#define AM_PAIR(P, Q) AM_MM(ga[2 * P], xb[2 * Q], R[t]) AM_MM(gn[P], xb[2 * Q + 1], R[t]) \
+                      AM_MM(ga[2 * P], xb[2 * Q + 1], I[t]) AM_MM(ga[2 * P + 1], xb[2 * Q], I[t])
+        AM_PAIR(2, 0) AM_PAIR(0, 2) AM_PAIR(1, 1) AM_PAIR(1, 0) AM_PAIR(0, 1) AM_PAIR(0, 0)
+#undef AM_PAIR
+#undef AM_MM
+      }
+    }
+  }
+  // 16x16 tile layout: lane l, register v -> row 4 (l / 16) + v, column l % 16
+  bf_c64* ob = B.p[bk.out_buf] + bk.out_row;
+  const int64_t ldo = B.ld[bk.out_buf];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int c = t * 16 + lc;
+    if (t < nct && c < cw) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * kq + v;
+        if (r < M) ob[(c0 + c) * ldo + r] = bf_c64{R[t][v], I[t][v]};
+      }
+    }
+  }
+}
+
 constexpr size_t AP_LDS_LIMIT = 160 * 1024;
 
 // One workgroup per block: row r of block b multiplies packed row r of its
@@ -321,7 +410,7 @@ void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* row
 }
 
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
-                        int32_t nrows, int32_t maxMK, int32_t maxKK, const bf_c64* G,
+                        int32_t nrows, int32_t maxMK, int32_t maxKK, int32_t maxM, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
                         int prec, hipStream_t s) {
   if (nblk <= 0 || ncols <= 0) return;
@@ -345,8 +434,12 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
   } else if (prec == BF_PREC_BF16X3 && ncols >= AM_MIN_COLS) {
     const int64_t ych = (ncols + AP_CW - 1) / AP_CW;
     BF_CHECK(ych <= 65535, BF_EINVAL, "too many right-hand sides");
-    hipLaunchKernelGGL(apply_mfma_kernel, dim3((unsigned)nblk, (unsigned)ych), dim3(256), 0, s,
-                       blks_dev, G, B, ncols);
+    if (maxM <= 16)
+      hipLaunchKernelGGL(apply_mfma_small_kernel, dim3((unsigned)((nblk + 3) / 4), (unsigned)ych),
+                         dim3(256), 0, s, blks_dev, nblk, G, B, ncols);
+    else
+      hipLaunchKernelGGL(apply_mfma_kernel, dim3((unsigned)nblk, (unsigned)ych), dim3(256), 0, s,
+                         blks_dev, G, B, ncols);
   } else {
     const size_t lds_b = sizeof(cf) * ((size_t)maxMK + (size_t)maxKK * AP_CW);
     BF_CHECK(lds_b <= AP_LDS_LIMIT, BF_ERANK, "apply block too large for LDS");

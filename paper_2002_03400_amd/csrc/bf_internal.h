@@ -230,7 +230,7 @@ void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* row
 // prec: BF_PREC_BF16X3 runs stages of >= 16 right-hand sides on the BF16
 // matrix cores (split operands), anything else in FP32 on the vector ALUs.
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
-                        int32_t nrows, int32_t maxMK, int32_t maxKK, const bf_c64* G,
+                        int32_t nrows, int32_t maxMK, int32_t maxKK, int32_t maxM, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
                         int prec, hipStream_t s);
 

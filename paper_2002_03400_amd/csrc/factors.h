@@ -30,7 +30,7 @@ struct Stage {
   int32_t nblk = 0;
   int64_t row_off = 0;
   int32_t nrows = 0;
-  int32_t maxMK = 0, maxKK = 0;
+  int32_t maxMK = 0, maxKK = 0, maxM = 0;
   double macs = 0;   // complex multiply-adds per right-hand side
 };
 

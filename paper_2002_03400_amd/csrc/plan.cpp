@@ -97,6 +97,7 @@ struct PlanBuilder {
     cur.nblk += 1;
     cur.maxMK = std::max(cur.maxMK, M * KK);
     cur.maxKK = std::max(cur.maxKK, KK);
+    cur.maxM = std::max(cur.maxM, M);
     cur.macs += (double)M * KK;
   }
 };
@@ -292,7 +293,7 @@ void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
     if (k + 1 == P.stages.size()) by += 8.0 * (double)rout * ncols;
     ProfScope ps(BF_KC_APPLY, s, 8.0 * st.macs * ncols, by);
     launch_apply_stage(P.blks.p + st.blk_off, st.nblk, P.rows.p + st.row_off, st.nrows, st.maxMK,
-                       st.maxKK, P.G.p, bufs, lds, ncols, F->apply_prec, s);
+                       st.maxKK, st.maxM, P.G.p, bufs, lds, ncols, F->apply_prec, s);
   }
 }
 
