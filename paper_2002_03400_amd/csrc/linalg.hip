@@ -122,8 +122,82 @@ __global__ __launch_bounds__(256) void chain_gemm_kernel(const GemmDesc* __restr
   }
 }
 
+// Small descriptors (every M <= RM, RM = 8 or 16), such as the transfer
+// blocks of rank-8 butterflies: a whole workgroup per descriptor would leave
+// most lanes and most of its staged tile empty, so each wave takes one
+// descriptor and a chunk of CS_TC * 64 / RM columns.  Lane l owns row l % RM
+// and columns cg + (64 / RM) u (cg = l / RM, u < CS_TC): per inner index it
+// loads op(F)[row][k] once and reuses it for its CS_TC columns, whose input
+// entries are shared by the RM lanes of the column through L1.  Same FP64
+// operation order as chain_gemm_kernel (terms, then k ascending), so the two
+// give identical results.
+constexpr int CS_TC = 4;
+
+template <typename Tin, int RM>
+__global__ __launch_bounds__(256) void chain_small_kernel(const GemmDesc* __restrict__ descs,
+                                                          int64_t ndesc) {
+  constexpr int CG = 64 / RM, CW = CG * CS_TC;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t di = (int64_t)blockIdx.x * 4 + wave;
+  if (di >= ndesc) return;
+  const GemmDesc& d = descs[di];
+  if (d.M <= 0) return;
+  const int r = lane % RM, cg = lane / RM;
+  const bool rlive = r < d.M;
+  for (int cb = (int)blockIdx.y * CW; cb < d.ncols; cb += (int)gridDim.y * CW) {
+    const int ncc = (d.ncols - cb < CW) ? d.ncols - cb : CW;
+    bool live[CS_TC];
+    int col[CS_TC];
+#pragma unroll
+    for (int u = 0; u < CS_TC; ++u) {
+      live[u] = rlive && cg + CG * u < ncc;
+      col[u] = live[u] ? cb + cg + CG * u : cb;
+    }
+    cd acc[CS_TC];
+#pragma unroll
+    for (int u = 0; u < CS_TC; ++u) acc[u] = cd{0.0, 0.0};
+    for (int t = 0; t < d.nterm; ++t) {
+      const GemmTerm& T = d.t[t];
+      const Tin* in = static_cast<const Tin*>(T.in);
+      const int rr = rlive ? r : 0;
+      const bf_c128* fp = T.F + (T.op == 0 ? rr : (int64_t)rr * T.f_ld);
+      const int64_t fs = T.op == 0 ? T.f_ld : 1;
+      const double sg = T.op == 0 ? 1.0 : -1.0;
+      const Tin* ip[CS_TC];
+#pragma unroll
+      for (int u = 0; u < CS_TC; ++u) ip[u] = in + (int64_t)col[u] * T.in_ld;
+#pragma unroll 2
+      for (int k = 0; k < T.K; ++k) {
+        const bf_c128 fv = fp[(int64_t)k * fs];
+        const cd f{fv.re, sg * fv.im};
+#pragma unroll
+        for (int u = 0; u < CS_TC; ++u)
+          if (CG * u < ncc) cd_fma(acc[u], f, load_c<Tin>(ip[u] + k));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CS_TC; ++u)
+      if (live[u]) d.out[(int64_t)col[u] * d.out_ld + r] = bf_c128{acc[u].re, acc[u].im};
+  }
+}
+
 template <typename Tin>
-static void launch_chain_t(const GemmDesc* d_dev, dim3 grid, int32_t max_M, hipStream_t s) {
+static void launch_chain_t(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols,
+                           int32_t max_M, hipStream_t s) {
+  if (max_M <= 16) {
+    const int cw = (max_M <= 8 ? 8 : 4) * CS_TC;
+    dim3 grid((unsigned)((ndesc + 3) / 4),
+              (unsigned)std::min((max_ncols + cw - 1) / cw, CG_YMAX));
+    if (max_M <= 8)
+      hipLaunchKernelGGL((chain_small_kernel<Tin, 8>), grid, dim3(256), 0, s, d_dev,
+                         (int64_t)ndesc);
+    else
+      hipLaunchKernelGGL((chain_small_kernel<Tin, 16>), grid, dim3(256), 0, s, d_dev,
+                         (int64_t)ndesc);
+    return;
+  }
+  const int nchunk = (max_ncols + CG_COLS - 1) / CG_COLS;
+  dim3 grid((unsigned)ndesc, (unsigned)std::min(nchunk, CG_YMAX));
   if (max_M <= 32)
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 32>), grid, dim3(256), 0, s, d_dev);
   else
@@ -135,12 +209,10 @@ void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, 
   if (ndesc <= 0 || max_ncols <= 0 || max_M <= 0) return;
   (void)max_Ksum;
   ProfScope ps(BF_KC_CHAIN, s, 0.0, 0.0);
-  const int nchunk = (max_ncols + CG_COLS - 1) / CG_COLS;
-  dim3 grid((unsigned)ndesc, (unsigned)std::min(nchunk, CG_YMAX));
   if (in_c64)
-    launch_chain_t<bf_c64>(d_dev, grid, max_M, s);
+    launch_chain_t<bf_c64>(d_dev, ndesc, max_ncols, max_M, s);
   else
-    launch_chain_t<bf_c128>(d_dev, grid, max_M, s);
+    launch_chain_t<bf_c128>(d_dev, ndesc, max_ncols, max_M, s);
   BF_HIP(hipGetLastError());
 }
 
