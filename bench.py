@@ -57,16 +57,22 @@ def parse():
     ap.add_argument("--mix", type=int, default=0,
                     help="also run the mixed serving stream with this many requests")
     ap.add_argument("--exact-scaling", default="",
-                    help="only recover exact random butterflies (Sec. 6.1: r = 8, leaf 8) "
-                         "through the butterfly black box at these comma-separated L and "
-                         "print one JSON line per L")
+                    help="only recover exact random butterflies (Sec. 6.1) through the "
+                         "butterfly black box: comma-separated entries L or L:r:leaf "
+                         "(default r = 8, leaf 8); one JSON line per entry")
+    ap.add_argument("--em3d", default="",
+                    help="only construct the 3D semi-sphere operator (Sec. 6.3, p = 4, "
+                         "r0 = 64): comma-separated entries n:L; one JSON line per n and "
+                         "tolerance")
+    ap.add_argument("--em3d-tols", default="1e-2,1e-3,1e-4",
+                    help="tolerances of --em3d")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (reference "
                          "dispatch for calibrating rocprofv3 byte counters) and exit")
     return ap.parse_args()
 
 
-def exact_scaling(levels, r=8, leaf=8, tol=1e-5):
+def exact_scaling(cases, tol=1e-5):
     """Sec. 6.1 workload at growing L: random exact butterflies (all ranks r)
     recovered with the butterfly as the black box; time of the construction
     (second of two), ranks, factor entries and device bytes, error against
@@ -76,9 +82,9 @@ def exact_scaling(levels, r=8, leaf=8, tol=1e-5):
     import paper_2002_03400_amd as bf
     import workloads as wl
     torch.cuda.init()
-    for L in levels:
+    for L, r, leaf in cases:
         n = leaf << L
-        kU, kV, data = wl.exact_butterfly_canonical(L, r, seed=L)
+        kU, kV, data = wl.exact_butterfly_canonical(L, r, seed=L, leaf=leaf)
         src = bf.import_factors(n, n, leaf, kU, kV, data)
         del data
         op = bf.from_factors(src)
@@ -92,6 +98,8 @@ def exact_scaling(levels, r=8, leaf=8, tol=1e-5):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             prof = bf.profile_stop()
+            print(f"exact L={L} r={r} leaf={leaf}: construction {rep} took {dt:.2f} s",
+                  file=sys.stderr, flush=True)
             gU, gV = F.ranks()
             st = F.stats()
             err = float((F.apply(Om) - ref).norm() / ref.norm())
@@ -106,6 +114,54 @@ def exact_scaling(levels, r=8, leaf=8, tol=1e-5):
             F.close()
         op.close()
         src.close()
+        torch.cuda.empty_cache()
+
+
+def em3d(cases, tols):
+    """Sec. 6.3 workload: exp(i k r)/r between two adjacent unit semi-spheres
+    (synthetic equal-area point sets, ten points per wavelength), built from
+    the matrix-free black box with p = 4, r0 = 64 and leaves of about n / 2^L
+    points.  Error: ||A W - F W|| / ||A W|| on 16 Gaussian columns W with A
+    the black-box product (complex64, FP32-accurate entries).  One untimed
+    construction at n = 8192 first loads every kernel."""
+    import torch
+
+    import paper_2002_03400_amd as bf
+    import workloads as wl
+    torch.cuda.init()
+    gw = wl.hemisphere_pair(8192, seed=1)
+    opw = bf.helmholtz3d(gw.targets, gw.sources, gw.k)
+    bf.construct(opw, min(tols), 93, p=4, r0=64, seed=1).close()
+    opw.close()
+    for n, L in cases:
+        leaf = -(-n // (1 << L))
+        g = wl.hemisphere_pair(n, seed=1)
+        op = bf.helmholtz3d(g.targets, g.sources, g.k)
+        Om = torch.from_numpy(wl.test_columns(n, 16, 1001).astype(np.complex64)).cuda()
+        ref = op.matvec(Om)
+        for tol in tols:
+            bf.profile_start()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+
+            def progress(phase, level, n=n, tol=tol, t0=t0):
+                print(f"em3d n={n} tol={tol:g}: {phase} {level} done at "
+                      f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            F = bf.construct(op, tol, leaf, p=4, r0=64, seed=1, progress=progress)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            prof = bf.profile_stop()
+            gU, gV = F.ranks()
+            st = F.stats()
+            err = float((F.apply(Om) - ref).norm() / ref.norm())
+            print(json.dumps({
+                "workload": "two adjacent unit semi-spheres (Sec. 6.3), matrix-free black box",
+                "n": n, "L": F.L, "leaf": leaf, "tol": tol, "k": g.k, "seconds": dt,
+                "rel_err": err, "max_rank": int(max(gU.max(), gV.max())),
+                "factor_entries": st.factor_entries, "device_bytes": st.device_bytes,
+                "phase_ms": {k: v["ms"] for k, v in prof.items()}}), flush=True)
+            F.close()
+        op.close()
         torch.cuda.empty_cache()
 
 
@@ -275,8 +331,16 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.em3d:
+        em3d([tuple(int(x) for x in e.split(":")) for e in args.em3d.split(",")],
+             [float(t) for t in args.em3d_tols.split(",")])
+        return
     if args.exact_scaling:
-        exact_scaling([int(x) for x in args.exact_scaling.split(",")])
+        cases = []
+        for e in args.exact_scaling.split(","):
+            f = [int(x) for x in e.split(":")]
+            cases.append((f[0], f[1], f[2]) if len(f) == 3 else (f[0], 8, 8))
+        exact_scaling(cases)
         return
     import torch
 

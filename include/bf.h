@@ -46,9 +46,12 @@ enum {
   BF_ENOTSUP = -6     /* no usable GPU / wrong architecture */
 };
 
-/* Largest Z block the batched QR kernels accept (rows x columns). */
-#define BF_MAX_BLOCK_ROWS 256
-#define BF_MAX_BLOCK_COLS 256
+/* Largest Z block the batched QR and least-squares kernels accept (rows x
+ * columns).  Blocks whose working set fits in the 160 KB LDS are factored
+ * there; larger ones in device scratch (at most 1 GiB per launch, blocks
+ * processed in as many launches as that takes). */
+#define BF_MAX_BLOCK_ROWS 2048
+#define BF_MAX_BLOCK_COLS 2048
 
 /*
  * Black-box product (the input of Alg. 2: "routine for multiplying K(T,S)
@@ -96,7 +99,16 @@ typedef struct {
                          bound (at least one sample per group).  0 = 8 GiB.
                          Only the summation order inside black-box products
                          can change with it. */
+  /* Optional progress report: called on the host, from the thread that runs
+     the construction, after each adaptive leaf-loop iteration and each sweep
+     level, with phase BF_PHASE_* and the iteration (leaf loops, from 1) or
+     level.  The level's ranks are known then (its samples have been
+     factored).  NULL = none. */
+  void (*progress)(void* user, int32_t phase, int32_t level);
+  void* progress_user;
 } bf_opts;
+
+enum { BF_PHASE_LEAF_V = 0, BF_PHASE_LEAF_U = 1, BF_PHASE_W = 2, BF_PHASE_R = 3 };
 
 typedef struct bf_factors bf_factors;
 
@@ -281,7 +293,8 @@ int bf_cpqr_batched(int32_t nblk, const int32_t* M, const int32_t* N, const bf_c
 /* Centre blocks by least squares (Sec. 4.4, eq. Bij read from its argmin):
  * B_b = argmin ||C_b - B X_b||_F with C_b kU[b] x s[b] at C + coff[b],
  * X_b kV[b] x s[b] at X + xoff[b], B_b kU[b] x kV[b] at B + boff[b]
- * (column-major, ld = row count; HOST shape/offset arrays; s[b] >= kV[b]). */
+ * (column-major, ld = row count; HOST shape/offset arrays; s[b] >= kV[b];
+ * kU, kV, s up to BF_MAX_BLOCK_COLS). */
 int bf_lsq_batched(int32_t nblk, const int32_t* kU, const int32_t* kV, const int32_t* s,
                    const bf_c128* C, const int64_t* coff, const bf_c128* X, const int64_t* xoff,
                    bf_c128* B, const int64_t* boff, void* stream);
@@ -298,6 +311,15 @@ int bf_lsq_batched(int32_t nblk, const int32_t* kU, const int32_t* kV, const int
  * parallel-line geometry of Sec. 6.2. */
 int bf_op_segkernel(const double* targets, int64_t m, const double* sources, int64_t n,
                     double k, bf_operator* out);
+
+/* The same kernel on 3D points (eq. 3dkernel of Sec. 6.3, there between two
+ * adjacent semi-spheres; written exp(i k r)/r here, k the wavenumber):
+ * targets m x 3 and sources n x 3 row-major doubles (host), copied to the
+ * device; same arithmetic as bf_op_segkernel.  Coincident points give
+ * non-finite entries (the kernel is singular there): the point sets must be
+ * disjoint. */
+int bf_op_helmholtz3d(const double* targets, int64_t m, const double* sources, int64_t n,
+                      double k, bf_operator* out);
 
 /* A_jk = exp(2 pi i (x_j xi_k + c(x_j) |xi_k|)), x_j = j/n, xi_k = k - n/2,
  * c(x) = (2 + sin 2 pi x)/16: a 1D Fourier integral operator (Sec. 4.4.1,

@@ -38,16 +38,19 @@ class DenseOp:
 
 
 def segment_kernel_entries(targets, sources, k, rows=slice(None), cols=slice(None)):
-    """A_ij = exp(i k r_ij) / r_ij with r_ij = |x_i - y_j| (2D points), FP64.
+    """A_ij = exp(i k r_ij) / r_ij with r_ij = |x_i - y_j| (2D or 3D points), FP64.
 
-    The 2D/3D Helmholtz-type kernel family of Sec. 3 (exp(i 2 pi kappa r)/r)
-    on the parallel-line geometry of Sec. 6.2.
+    The Helmholtz kernel of Sec. 3 (written there as exp(i 2 pi kappa r)/r):
+    on the parallel-line geometry of Sec. 6.2 (2D points) and on the two
+    semi-spheres of Sec. 6.3, eq. 3dkernel (3D points).
     """
     x = np.asarray(targets)[rows]
     y = np.asarray(sources)[cols]
-    d0 = x[:, None, 0] - y[None, :, 0]
-    d1 = x[:, None, 1] - y[None, :, 1]
-    r = np.sqrt(d0 * d0 + d1 * d1)
+    r2 = np.zeros((len(x), len(y)))
+    for d in range(x.shape[1]):
+        dd = x[:, None, d] - y[None, :, d]
+        r2 += dd * dd
+    r = np.sqrt(r2)
     return np.exp(1j * k * r) / r
 
 

@@ -16,7 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbf.so")
 
-__all__ = ["BFError", "lib", "Operator", "Factors", "construct", "segkernel", "fio", "dense",
+__all__ = ["BFError", "lib", "Operator", "Factors", "construct", "segkernel", "helmholtz3d", "fio",
+           "dense",
            "from_factors", "compose", "import_factors", "gauss", "cpqr_batched", "lsq_batched",
            "num_levels", "LIB_PATH", "profile_start", "profile_stop", "Server"]
 
@@ -44,9 +45,14 @@ class bf_operator(C.Structure):
                 ("m", C.c_int64), ("n", C.c_int64)]
 
 
+PROGRESSFN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32)
+PHASES = ("leaf V", "leaf U", "W", "R")
+
+
 class bf_opts(C.Structure):
     _fields_ = [("p", C.c_int32), ("r0", C.c_int32), ("max_rank", C.c_int32),
-                ("flags", C.c_int32), ("seed", C.c_uint64), ("work_bytes", C.c_int64)]
+                ("flags", C.c_int32), ("seed", C.c_uint64), ("work_bytes", C.c_int64),
+                ("progress", PROGRESSFN), ("progress_user", C.c_void_p)]
 
 
 class bf_kernel_stats(C.Structure):
@@ -109,6 +115,8 @@ SIGNATURES = {
                                  _I64P, _P]),
     "bf_op_segkernel": (C.c_int, [_P, C.c_int64, _P, C.c_int64, C.c_double,
                                   C.POINTER(bf_operator)]),
+    "bf_op_helmholtz3d": (C.c_int, [_P, C.c_int64, _P, C.c_int64, C.c_double,
+                                    C.POINTER(bf_operator)]),
     "bf_op_fio": (C.c_int, [C.c_int64, C.POINTER(bf_operator)]),
     "bf_op_dense": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, C.POINTER(bf_operator)]),
     "bf_op_factors": (C.c_int, [_P, C.POINTER(bf_operator)]),
@@ -232,11 +240,26 @@ class Operator:
 
 
 def segkernel(targets, sources, k) -> Operator:
+    """exp(i k r)/r between 2D target and source points ((m, 2), (n, 2))."""
     t = np.ascontiguousarray(targets, dtype=np.float64)
     s = np.ascontiguousarray(sources, dtype=np.float64)
+    if t.ndim != 2 or t.shape[1] != 2 or s.ndim != 2 or s.shape[1] != 2:
+        raise ValueError("segkernel needs (m, 2) targets and (n, 2) sources")
     op = bf_operator()
     _check(lib().bf_op_segkernel(t.ctypes.data, len(t), s.ctypes.data, len(s), float(k),
                                  C.byref(op)), "bf_op_segkernel")
+    return Operator(op)
+
+
+def helmholtz3d(targets, sources, k) -> Operator:
+    """exp(i k r)/r between 3D target and source points ((m, 3), (n, 3))."""
+    t = np.ascontiguousarray(targets, dtype=np.float64)
+    s = np.ascontiguousarray(sources, dtype=np.float64)
+    if t.ndim != 2 or t.shape[1] != 3 or s.ndim != 2 or s.shape[1] != 3:
+        raise ValueError("helmholtz3d needs (m, 3) targets and (n, 3) sources")
+    op = bf_operator()
+    _check(lib().bf_op_helmholtz3d(t.ctypes.data, len(t), s.ctypes.data, len(s), float(k),
+                                   C.byref(op)), "bf_op_helmholtz3d")
     return Operator(op)
 
 
@@ -343,10 +366,16 @@ class Factors:
 
 
 def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed: int = 0,
-              max_rank: int = 0, stream=None, work_bytes: int = 0) -> Factors:
+              max_rank: int = 0, stream=None, work_bytes: int = 0, progress=None) -> Factors:
     """Alg. 2 on the device; returns the factor handle.  work_bytes bounds the
-    device memory of one sweep level's samples (0: 8 GiB)."""
+    device memory of one sweep level's samples (0: 8 GiB).  progress(phase,
+    level), if given, is called after each leaf-loop iteration and sweep level
+    with phase one of PHASES."""
     o = bf_opts(p, r0, max_rank, 0, seed, work_bytes)
+    cb = None    # held until bf_construct returns
+    if progress is not None:
+        cb = PROGRESSFN(lambda _u, ph, lv: progress(PHASES[ph], lv))
+        o.progress = cb
     h = C.c_void_p()
     _check(lib().bf_construct(op._op.matvec, op._op.rmatvec, op._op.user, op.m, op.n, float(tol),
                               int(leaf), C.byref(o), _stream(stream), C.byref(h)), "bf_construct")

@@ -212,7 +212,7 @@ void* Staging::alloc(size_t bytes, hipStream_t s) {
 
 // ---- operators --------------------------------------------------------------
 struct SegCtx {
-  DevBuf<double> tx, ty, sx, sy;
+  DevBuf<double> tx, ty, tz, sx, sy, sz;   // tz, sz empty for 2D points
   int64_t m, n;
   double kk;
   int prec = BF_PREC_BF16X3;
@@ -261,7 +261,7 @@ static int seg_apply(void* user, bool adj, const bf_c64* X, int64_t ldx, int64_t
                      int64_t ldy, const int64_t* seg, int32_t nseg, void* stream) {
   return guarded([&] {
     auto* c = static_cast<SegCtx*>(static_cast<OpHeader*>(user)->ctx);
-    PointSet T{c->tx.p, c->ty.p}, S{c->sx.p, c->sy.p};
+    PointSet T{c->tx.p, c->ty.p, c->tz.p}, S{c->sx.p, c->sy.p, c->sz.p};
     if (!adj)
       launch_segkernel(c->prec, T, c->m, S, c->n, c->kk, +1, X, ldx, ncols, Y, ldy, seg, nseg,
                        (hipStream_t)stream);
@@ -708,25 +708,30 @@ int bf_lsq_batched(int32_t nblk, const int32_t* kU, const int32_t* kV, const int
 
 // ---- built-in operators -----------------------------------------------------
 
-int bf_op_segkernel(const double* targets, int64_t m, const double* sources, int64_t n, double k,
-                    bf_operator* out) {
+// One coordinate of `dim`-dimensional row-major host points -> device array.
+static DevBuf<double> coord_to_device(const double* pts, int64_t npts, int dim, int d) {
+  std::vector<double> v(npts);
+  for (int64_t i = 0; i < npts; ++i) v[i] = pts[dim * i + d];
+  DevBuf<double> b(npts, nullptr);
+  BF_HIP(hipMemcpy(b.p, v.data(), npts * 8, hipMemcpyHostToDevice));
+  return b;
+}
+
+static int op_pointkernel(const double* targets, int64_t m, const double* sources, int64_t n,
+                          double k, int dim, bf_operator* out) {
   if (!targets || !sources || m <= 0 || n <= 0 || !out || !std::isfinite(k)) return BF_EINVAL;
   return guarded([&] {
     check_device();
     auto* c = new SegCtx();
     try {
-      std::vector<double> tx(m), ty(m), sx(n), sy(n);
-      for (int64_t i = 0; i < m; ++i) { tx[i] = targets[2 * i]; ty[i] = targets[2 * i + 1]; }
-      for (int64_t j = 0; j < n; ++j) { sx[j] = sources[2 * j]; sy[j] = sources[2 * j + 1]; }
-      hipStream_t s = nullptr;
-      c->tx = DevBuf<double>(m, s);
-      c->ty = DevBuf<double>(m, s);
-      c->sx = DevBuf<double>(n, s);
-      c->sy = DevBuf<double>(n, s);
-      BF_HIP(hipMemcpy(c->tx.p, tx.data(), m * 8, hipMemcpyHostToDevice));
-      BF_HIP(hipMemcpy(c->ty.p, ty.data(), m * 8, hipMemcpyHostToDevice));
-      BF_HIP(hipMemcpy(c->sx.p, sx.data(), n * 8, hipMemcpyHostToDevice));
-      BF_HIP(hipMemcpy(c->sy.p, sy.data(), n * 8, hipMemcpyHostToDevice));
+      c->tx = coord_to_device(targets, m, dim, 0);
+      c->ty = coord_to_device(targets, m, dim, 1);
+      c->sx = coord_to_device(sources, n, dim, 0);
+      c->sy = coord_to_device(sources, n, dim, 1);
+      if (dim == 3) {
+        c->tz = coord_to_device(targets, m, dim, 2);
+        c->sz = coord_to_device(sources, n, dim, 2);
+      }
       c->m = m;
       c->n = n;
       c->kk = k / (2.0 * M_PI);
@@ -740,6 +745,16 @@ int bf_op_segkernel(const double* targets, int64_t m, const double* sources, int
     out->m = m;
     out->n = n;
   });
+}
+
+int bf_op_segkernel(const double* targets, int64_t m, const double* sources, int64_t n, double k,
+                    bf_operator* out) {
+  return op_pointkernel(targets, m, sources, n, k, 2, out);
+}
+
+int bf_op_helmholtz3d(const double* targets, int64_t m, const double* sources, int64_t n,
+                      double k, bf_operator* out) {
+  return op_pointkernel(targets, m, sources, n, k, 3, out);
 }
 
 int bf_op_fio(int64_t n, bf_operator* out) {

@@ -263,6 +263,7 @@ void launch_expand_segments(const bf_c64* X, int64_t ldx, int64_t rows, int64_t 
 struct PointSet {     // structure-of-arrays FP64 coordinates on the device
   const double* x;
   const double* y;
+  const double* z;    // nullptr for 2D points
 };
 // Y[:, g*ncols + c] = sum_{j in seg_g} E(i, j) X[j, c], E = kernel entries of
 // op(A) (sign = +1: A, sign = -1: A^H, points swapped by the caller).

@@ -58,6 +58,8 @@ class Builder {
       cap_ = o->max_rank;
       seed_ = o->seed;
       if (o->work_bytes > 0) work_ = o->work_bytes;
+      progress_ = o->progress;
+      progress_user_ = o->progress_user;
     }
     BF_CHECK(p_ >= 0 && r0_ >= 1 && cap_ >= 0 && (!o || o->work_bytes >= 0), BF_EINVAL,
              "bad bf_opts");
@@ -76,8 +78,14 @@ class Builder {
   bf_factors* run() {
     leaf_loop(false);
     leaf_loop(true);
-    for (int l = 1; l <= F_->lm; ++l) w_level(l);
-    for (int l = F_->L - 1; l >= F_->lm; --l) r_level(l);
+    for (int l = 1; l <= F_->lm; ++l) {
+      w_level(l);
+      report(BF_PHASE_W, l);
+    }
+    for (int l = F_->L - 1; l >= F_->lm; --l) {
+      r_level(l);
+      report(BF_PHASE_R, l);
+    }
     if (F_->L == 0) centre_single_block();
     finalize();
     bf_factors* out = F_;
@@ -99,6 +107,11 @@ class Builder {
   Staging& st_ = scope_staging(s_) ? *scope_staging(s_) : own_st_;
   int64_t mv_cols_ = 0, rmv_cols_ = 0;
   int v_iters_ = 0, u_iters_ = 0;
+  void (*progress_)(void*, int32_t, int32_t) = nullptr;
+  void* progress_user_ = nullptr;
+  void report(int32_t phase, int32_t level) const {
+    if (progress_) progress_(progress_user_, phase, level);
+  }
 
   int L() const { return F_->L; }
   int lm() const { return F_->lm; }
@@ -249,6 +262,7 @@ class Builder {
       auto ranks = cpqr(d, true, blocks);
       int32_t kmax = *std::max_element(ranks.begin(), ranks.end());
       (col_side ? u_iters_ : v_iters_)++;
+      report(col_side ? BF_PHASE_LEAF_U : BF_PHASE_LEAF_V, col_side ? u_iters_ : v_iters_);
       if (col_side) {
         F_->U = blocks;
         for (int64_t i = 0; i < nb(); ++i) F_->ku_ref(L(), i, 0) = ranks[i];

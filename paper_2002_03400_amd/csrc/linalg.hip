@@ -229,8 +229,9 @@ void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, 
 // fits, else in a global scratch slot.  After the loop the reflectors (stored
 // in the dead columns of A) are accumulated backwards into Q, which overwrites
 // A column by column.
-constexpr int QR_THREADS = 256;
-constexpr int QR_WAVES = QR_THREADS / 64;
+constexpr int QR_THREADS = 256;        // blocks held in LDS
+constexpr int QR_BIG_THREADS = 1024;   // blocks in global scratch
+constexpr int64_t QR_SCRATCH_BYTES = int64_t(1) << 30;
 
 struct QRShared {
   double tail2;
@@ -259,8 +260,8 @@ __device__ __forceinline__ void reflect_column(cd* A, int M, int k, int j, const
   }
 }
 
-template <typename Tin>
-__global__ __launch_bounds__(QR_THREADS) void cpqr_kernel(const QRDesc* __restrict__ descs,
+template <typename Tin, int NT>
+__global__ __launch_bounds__(NT) void cpqr_kernel(const QRDesc* __restrict__ descs,
                                                           double tol, int32_t* __restrict__ ranks,
                                                           bf_c128* __restrict__ gscratch,
                                                           int64_t scratch_slot, int use_lds) {
@@ -280,13 +281,13 @@ __global__ __launch_bounds__(QR_THREADS) void cpqr_kernel(const QRDesc* __restri
   cd* A = use_lds ? reinterpret_cast<cd*>(reinterpret_cast<char*>(sh) + 64)
                   : reinterpret_cast<cd*>(gscratch + (int64_t)blockIdx.x * scratch_slot);
   const Tin* in = static_cast<const Tin*>(d.in);
-  for (int idx = tid; idx < M * N; idx += QR_THREADS) {
+  for (int idx = tid; idx < M * N; idx += NT) {
     int i = idx % M, j = idx / M;
     A[idx] = load_c<Tin>(in + (int64_t)j * d.in_ld + i);
   }
   __syncthreads();
   // initial column norms (wave per column) and the total
-  for (int j = wave; j < N; j += QR_WAVES) {
+  for (int j = wave; j < N; j += (NT / 64)) {
     double nn = 0.0;
     for (int i = lane; i < M; i += 64) nn += cd_abs2(A[(int64_t)j * M + i]);
     nn = wave_sum(nn);
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(QR_THREADS) void cpqr_kernel(const QRDesc* __restri
     if (sh->stop) { rank = k; break; }
     const int p = sh->piv;
     if (p != k) {
-      for (int i = tid; i < M; i += QR_THREADS) {
+      for (int i = tid; i < M; i += NT) {
         cd a = A[(int64_t)k * M + i];
         A[(int64_t)k * M + i] = A[(int64_t)p * M + i];
         A[(int64_t)p * M + i] = a;
@@ -357,11 +358,11 @@ __global__ __launch_bounds__(QR_THREADS) void cpqr_kernel(const QRDesc* __restri
     if (vv > 0.0) {
       const double tau = 2.0 / vv;
       const cd* v = A + (int64_t)k * M + k;
-      for (int j = k + 1 + wave; j < N; j += QR_WAVES)
+      for (int j = k + 1 + wave; j < N; j += (NT / 64))
         reflect_column(A, M, k, j, v, tau, lane, &norm2[j]);
     } else {
       // x = 0: H = I; trailing norms just lose row k
-      for (int j = k + 1 + wave; j < N; j += QR_WAVES) {
+      for (int j = k + 1 + wave; j < N; j += (NT / 64)) {
         double nn = 0.0;
         for (int i = k + 1 + lane; i < M; i += 64) nn += cd_abs2(A[(int64_t)j * M + i]);
         nn = wave_sum(nn);
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(QR_THREADS) void cpqr_kernel(const QRDesc* __restri
   // Q = H_0 ... H_{rank-1} [I; 0], accumulated backwards; column k of Q stays
   // e_k until step k, and H_k only touches columns k..rank-1.
   for (int k = rank - 1; k >= 0; --k) {
-    for (int i = tid; i < M; i += QR_THREADS) {
+    for (int i = tid; i < M; i += NT) {
       if (i >= k) tmp[i - k] = A[(int64_t)k * M + i];
       A[(int64_t)k * M + i] = cd{i == k ? 1.0 : 0.0, 0.0};
     }
@@ -381,12 +382,12 @@ __global__ __launch_bounds__(QR_THREADS) void cpqr_kernel(const QRDesc* __restri
     const double vv = vn2[k];
     if (vv > 0.0) {
       const double tau = 2.0 / vv;
-      for (int j = k + wave; j < rank; j += QR_WAVES)
+      for (int j = k + wave; j < rank; j += (NT / 64))
         reflect_column(A, M, k, j, tmp, tau, lane, nullptr);
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < M * rank; idx += QR_THREADS) {
+  for (int idx = tid; idx < M * rank; idx += NT) {
     cd a = A[idx];
     d.q[idx] = bf_c128{a.re, a.im};
   }
@@ -406,46 +407,64 @@ void launch_cpqr(const QRDesc* d_dev, int32_t nblk, int32_t maxM, int32_t maxN, 
   if (nblk <= 0) return;
   BF_CHECK(maxM <= BF_MAX_BLOCK_ROWS && maxN <= BF_MAX_BLOCK_COLS, BF_ERANK,
            "block exceeds BF_MAX_BLOCK_ROWS/COLS");
-  size_t lds = cpqr_lds_bytes(maxM, maxN, true);
-  int use_lds = lds <= LDS_LIMIT;
-  DevBuf<bf_c128> scratch;
-  int64_t slot = 0;
-  if (!use_lds) {
-    lds = cpqr_lds_bytes(maxM, maxN, false);
-    slot = (int64_t)maxM * maxN;
-    scratch = DevBuf<bf_c128>((size_t)slot * nblk, s);
-  }
-  auto kern = in_c64 ? cpqr_kernel<bf_c64> : cpqr_kernel<bf_c128>;
   ProfScope ps(BF_KC_CPQR, s, 0.0, 0.0);
+  size_t lds = cpqr_lds_bytes(maxM, maxN, true);
+  if (lds <= LDS_LIMIT) {
+    auto kern = in_c64 ? cpqr_kernel<bf_c64, QR_THREADS> : cpqr_kernel<bf_c128, QR_THREADS>;
+    if (lds > 64 * 1024)
+      BF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(QR_THREADS), lds, s, d_dev, tol,
+                       ranks_dev, (bf_c128*)nullptr, (int64_t)0, 1);
+    BF_HIP(hipGetLastError());
+    return;
+  }
+  // Blocks too large for LDS live in a global scratch slot each (L2-resident
+  // working set); 16 waves per block hide the longer load latency.  Launched
+  // in chunks that bound the scratch to QR_SCRATCH_BYTES.
+  lds = cpqr_lds_bytes(maxM, maxN, false);
+  const int64_t slot = (int64_t)maxM * maxN;
+  const int64_t chunk = std::max<int64_t>(
+      1, std::min<int64_t>(nblk, QR_SCRATCH_BYTES / (slot * (int64_t)sizeof(bf_c128))));
+  DevBuf<bf_c128> scratch((size_t)(slot * chunk), s);
+  auto kern = in_c64 ? cpqr_kernel<bf_c64, QR_BIG_THREADS> : cpqr_kernel<bf_c128, QR_BIG_THREADS>;
   if (lds > 64 * 1024)
     BF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
-  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(QR_THREADS), lds, s, d_dev, tol, ranks_dev,
-                     scratch.p, slot, use_lds);
-  BF_HIP(hipGetLastError());
+  for (int64_t b0 = 0; b0 < nblk; b0 += chunk) {
+    const int64_t nb = std::min<int64_t>(chunk, nblk - b0);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(QR_BIG_THREADS), lds, s, d_dev + b0, tol,
+                       ranks_dev + b0, scratch.p, slot, 0);
+    BF_HIP(hipGetLastError());
+  }
 }
 
 // ---------------------------------------------------------------- lsq -----
 // B = argmin ||C - B X||_F for C (kU x s), X (kV x s), s >= kV:
 //   X^H = Q_x R_x (Householder, no pivoting), then R_x B^H = Q_x^H C^H.
 // Both X^H (s x kV) and C^H (s x kU) are held in LDS and reduced together.
-__global__ __launch_bounds__(QR_THREADS) void lsq_kernel(const LSDesc* __restrict__ descs) {
+template <int NT>
+__global__ __launch_bounds__(NT) void lsq_kernel(const LSDesc* __restrict__ descs,
+                                                 bf_c128* __restrict__ gscratch,
+                                                 int64_t scratch_slot, int use_lds) {
   extern __shared__ double smem_raw[];
   const LSDesc d = descs[blockIdx.x];
   const int S = d.s, KV = d.kV, KU = d.kU;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (KU == 0 || KV == 0) return;
-  // LDS: [vn2 KV][diag KV (cd)][XH S*KV][CH S*KU]
+  // LDS: [vn2 KV][diag KV (cd)][XH S*KV][CH S*KU]; XH and CH in a global
+  // scratch slot instead when they do not fit
   double* vn2 = smem_raw;
   cd* diag = reinterpret_cast<cd*>(vn2 + KV);
-  cd* XH = diag + KV;                      // X^H, S x KV, ld S
+  cd* XH = use_lds ? diag + KV                              // X^H, S x KV, ld S
+                   : reinterpret_cast<cd*>(gscratch + (int64_t)blockIdx.x * scratch_slot);
   cd* CH = XH + (int64_t)S * KV;           // C^H, S x KU, ld S
-  for (int idx = tid; idx < S * KV; idx += QR_THREADS) {
+  for (int idx = tid; idx < S * KV; idx += NT) {
     int i = idx % S, j = idx / S;          // XH[i, j] = conj(X[j, i])
     bf_c128 x = d.X[(int64_t)i * d.ldx + j];
     XH[idx] = cd{x.re, -x.im};
   }
-  for (int idx = tid; idx < S * KU; idx += QR_THREADS) {
+  for (int idx = tid; idx < S * KU; idx += NT) {
     int i = idx % S, j = idx / S;
     bf_c128 c = d.C[(int64_t)i * d.ldc + j];
     CH[idx] = cd{c.re, -c.im};
@@ -473,16 +492,16 @@ __global__ __launch_bounds__(QR_THREADS) void lsq_kernel(const LSDesc* __restric
     if (vv > 0.0) {
       const double tau = 2.0 / vv;
       const cd* v = XH + (int64_t)k * S + k;
-      for (int j = k + 1 + wave; j < KV; j += QR_WAVES)
+      for (int j = k + 1 + wave; j < KV; j += (NT / 64))
         reflect_column(XH, S, k, j, v, tau, lane, nullptr);
-      for (int j = wave; j < KU; j += QR_WAVES)
+      for (int j = wave; j < KU; j += (NT / 64))
         reflect_column(CH, S, k, j, v, tau, lane, nullptr);
     }
     __syncthreads();
   }
   // R_x b = (Q_x^H C^H)[0:KV, c] for every column c; R_x(r, q) = XH[r, q]
   // for q > r, R_x(r, r) = diag[r].
-  for (int c = tid; c < KU; c += QR_THREADS) {
+  for (int c = tid; c < KU; c += NT) {
     cd* y = CH + (int64_t)c * S;
     for (int r = KV - 1; r >= 0; --r) {
       cd acc = y[r];
@@ -502,14 +521,35 @@ __global__ __launch_bounds__(QR_THREADS) void lsq_kernel(const LSDesc* __restric
 
 void launch_lsq(const LSDesc* d_dev, int32_t nblk, int32_t maxS, int32_t maxK, hipStream_t s) {
   if (nblk <= 0) return;
-  size_t lds = (sizeof(double) + sizeof(cd)) * maxK + sizeof(cd) * (size_t)maxS * (2 * maxK);
-  BF_CHECK(lds <= LDS_LIMIT, BF_ERANK, "centre block too large for the LDS least-squares kernel");
-  if (lds > 64 * 1024)
-    BF_HIP(hipFuncSetAttribute((const void*)lsq_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
+  BF_CHECK(maxK <= BF_MAX_BLOCK_COLS && maxS <= 2 * BF_MAX_BLOCK_COLS, BF_ERANK,
+           "centre block exceeds BF_MAX_BLOCK_COLS");
   ProfScope ps(BF_KC_LSQ, s, 0.0, 0.0);
-  hipLaunchKernelGGL(lsq_kernel, dim3((unsigned)nblk), dim3(QR_THREADS), lds, s, d_dev);
-  BF_HIP(hipGetLastError());
+  const size_t head = (sizeof(double) + sizeof(cd)) * maxK;
+  const int64_t slot = (int64_t)maxS * (2 * maxK);
+  size_t lds = head + sizeof(cd) * (size_t)slot;
+  if (lds <= LDS_LIMIT) {
+    if (lds > 64 * 1024)
+      BF_HIP(hipFuncSetAttribute((const void*)lsq_kernel<QR_THREADS>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(lsq_kernel<QR_THREADS>, dim3((unsigned)nblk), dim3(QR_THREADS), lds, s,
+                       d_dev, (bf_c128*)nullptr, (int64_t)0, 1);
+    BF_HIP(hipGetLastError());
+    return;
+  }
+  lds = head;
+  BF_CHECK(lds <= LDS_LIMIT, BF_ERANK, "centre block too large for the least-squares kernel");
+  const int64_t chunk = std::max<int64_t>(
+      1, std::min<int64_t>(nblk, QR_SCRATCH_BYTES / (slot * (int64_t)sizeof(bf_c128))));
+  DevBuf<bf_c128> scratch((size_t)(slot * chunk), s);
+  if (lds > 64 * 1024)
+    BF_HIP(hipFuncSetAttribute((const void*)lsq_kernel<QR_BIG_THREADS>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  for (int64_t b0 = 0; b0 < nblk; b0 += chunk) {
+    const int64_t nb = std::min<int64_t>(chunk, nblk - b0);
+    hipLaunchKernelGGL(lsq_kernel<QR_BIG_THREADS>, dim3((unsigned)nb), dim3(QR_BIG_THREADS), lds,
+                       s, d_dev + b0, scratch.p, slot, 0);
+    BF_HIP(hipGetLastError());
+  }
 }
 
 // ---------------------------------------------------------------- misc ----

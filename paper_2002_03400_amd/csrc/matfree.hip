@@ -80,6 +80,28 @@ struct SegEntry {
   }
 };
 
+// The same kernel on 3D points (eq. 3dkernel: the two semi-spheres).
+struct Seg3Entry {
+  PointSet out, in;
+  double k4;
+  float sign;
+  struct Row { double x, y, z; };
+  struct Col { double x, y, z; };
+  __device__ Row row(int64_t i) const { return Row{out.x[i], out.y[i], out.z[i]}; }
+  __device__ Col col(int64_t j) const { return Col{in.x[j], in.y[j], in.z[j]}; }
+  __device__ cf entry(const Row& r, const Col& c) const {
+    const double dx = r.x - c.x, dy = r.y - c.y, dz = r.z - c.z;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const float r2f = (float)r2;
+    const float inv = __builtin_amdgcn_rsqf(r2f);
+    const double rd = (double)(r2f * inv);
+    const double rr = fma(fma(-rd, rd, r2), (double)(0.5f * inv), rd);
+    float s, co;
+    sincos_quarter(rr * k4, &s, &co);
+    return cf{co * inv, s * (sign * inv)};
+  }
+};
+
 // exp(2 pi i (j xi / n + c_j |xi|)).  j * xi is an exact integer (< 2^53),
 // so the phase (in quarter revolutions: the exact scalings 4/n and 4 c_j) is
 // formed in FP64 with one rounding before the reduction.
@@ -653,8 +675,13 @@ void launch_segkernel(int prec, PointSet out_pts, int64_t nout, PointSet in_pts,
                       double k_over_2pi, int sign, const bf_c64* X, int64_t ldx, int64_t ncols,
                       bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
                       hipStream_t s) {
-  SegEntry e{out_pts, in_pts, 4.0 * k_over_2pi, (float)sign};
-  run_matfree(prec, e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
+  if (out_pts.z && in_pts.z) {
+    Seg3Entry e{out_pts, in_pts, 4.0 * k_over_2pi, (float)sign};
+    run_matfree(prec, e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
+  } else {
+    SegEntry e{out_pts, in_pts, 4.0 * k_over_2pi, (float)sign};
+    run_matfree(prec, e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
+  }
 }
 
 void launch_fio(int prec, int64_t n, const double* cx_dev, int adjoint, const bf_c64* X,

@@ -81,10 +81,34 @@ def test_cpqr_matches_oracle(bf, tol):
             np.testing.assert_allclose(Q.conj().T @ Q, np.eye(k), atol=1e-12)
 
 
+def test_cpqr_large_blocks_in_chunks(bf):
+    """Blocks far beyond the LDS (ranks of the 3D regime of Sec. 6.3): 600 x 520
+    with a geometric spectrum, 200 copies (1.2 GB of scratch: two launches),
+    plus single 300 x 560 and 700 x 260 blocks."""
+    rng = np.random.default_rng(11)
+    U = np.linalg.qr(_cg(rng, 600, 300))[0]
+    big = (U * 0.93 ** np.arange(300)) @ _cg(rng, 300, 520)
+    odd = [_cg(rng, 300, 560) * rng.uniform(0.3, 3.0, 560)[None, :],
+           (np.linalg.qr(_cg(rng, 700, 200))[0] * 0.9 ** np.arange(200)) @ _cg(rng, 200, 260)]
+    tol = 1e-6
+    Qo, ko = ocpqr.range_basis(big, tol)
+    say("cpqr large", big.shape, "x200, oracle rank", ko)
+    Qs, ranks = bf.cpqr_batched([big] * 200 + odd, tol)
+    for t in range(200):
+        assert ranks[t] == ko
+        np.testing.assert_allclose(Qs[t], Qo, atol=1e-10)
+    for b, Q, k in zip(odd, Qs[200:], ranks[200:]):
+        Qb, kb = ocpqr.range_basis(b, tol)
+        assert k == kb, (b.shape, k, kb)
+        np.testing.assert_allclose(Q, Qb, atol=1e-10)
+        np.testing.assert_allclose(Q.conj().T @ Q, np.eye(k), atol=1e-12)
+
+
 # ---------------------------------------------------------------- LS --------
 def test_lsq_matches_oracle(bf):
     rng = np.random.default_rng(5)
-    shapes = [(13, 13, 20), (20, 18, 40), (1, 1, 3), (35, 33, 72), (7, 12, 12)]
+    shapes = [(13, 13, 20), (20, 18, 40), (1, 1, 3), (35, 33, 72), (7, 12, 12),
+              (150, 140, 300), (260, 250, 256)]   # the last two: device-scratch path
     Cs = [_cg(rng, ku, s) for ku, kv, s in shapes]
     Xs = [_cg(rng, kv, s) for ku, kv, s in shapes]
     say("lsq", shapes)
@@ -133,6 +157,32 @@ def test_segkernel_wide_and_split(bf):
     X = _cg(np.random.default_rng(2), n, 65)
     Y = op.matvec(_t(X)).cpu().numpy()
     assert _rel(Y, ref.matvec(X)) < 3e-6
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
+def test_helmholtz3d_products(bf, prec):
+    """eq. 3dkernel between the two semi-spheres: plain and structured
+    products, both directions, both arithmetic modes."""
+    n = 3000
+    g = wl.hemisphere_pair(n, seed=4, m=2500)
+    say("helmholtz3d", prec)
+    op = bf.helmholtz3d(g.targets, g.sources, g.k)
+    op.set_precision(prec)
+    ref = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    rng = np.random.default_rng(3)
+    X = _cg(rng, n, 9)
+    assert _rel(op.matvec(_t(X)).cpu().numpy(), ref.matvec(X)) < 3e-6
+    Xt = _cg(rng, 2500, 40)
+    assert _rel(op.rmatvec(_t(Xt)).cpu().numpy(), ref.rmatvec(Xt)) < 3e-6
+    seg = np.array([0, 700, 701, 2500], np.int64)
+    Ys = op.rmatvec(_t(Xt[:, :6]), seg=seg).cpu().numpy()
+    for q in range(3):
+        Xq = np.zeros_like(Xt[:, :6])
+        Xq[seg[q]:seg[q + 1]] = Xt[seg[q]:seg[q + 1], :6]
+        exp = ref.rmatvec(Xq)
+        assert np.linalg.norm(Ys[:, 6 * q:6 * q + 6] - exp) <= 3e-6 * np.linalg.norm(exp)
+    with pytest.raises(ValueError):
+        bf.helmholtz3d(g.targets[:, :2], g.sources, g.k)
 
 
 @pytest.mark.parametrize("ncols", [5, 23, 40, 64])

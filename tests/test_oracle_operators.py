@@ -109,3 +109,55 @@ def test_serving_streams_are_seeded_and_well_formed():
     p = wl.poisson_stream(50, rate=2.0, seed=1)
     gaps = np.diff([0.0] + [r.t for r in p])
     assert abs(gaps.mean() - 0.5) < 0.2 and len({r.seed for r in p}) == 50
+
+
+def test_helmholtz3d_entries_closed_form():
+    """eq. 3dkernel on hand-placed 3D points: a 3-4-5 offset and a unit one."""
+    t = np.array([[0.0, 0.0, 0.0], [1.0, 2.0, 2.0]])
+    s = np.array([[0.0, 3.0, 4.0], [1.0, 2.0, 3.0]])
+    k = 2.5
+    A = ops.segment_kernel_entries(t, s, k)
+    assert abs(A[0, 0] - cmath.exp(5j * k) / 5.0) < 1e-15
+    assert abs(A[1, 1] - cmath.exp(1j * k)) < 1e-15
+    r01 = math.sqrt(1.0 + 4.0 + 9.0)
+    assert abs(A[0, 1] - cmath.exp(1j * k * r01) / r01) < 1e-15
+    # reciprocity and |A| = 1/r on the semi-sphere pair
+    g = wl.hemisphere_pair(300, seed=3)
+    A = ops.segment_kernel_entries(g.targets, g.sources, g.k)
+    At = ops.segment_kernel_entries(g.sources, g.targets, g.k)
+    np.testing.assert_allclose(At, A.T, atol=1e-13)
+    R = np.linalg.norm(g.targets[:, None, :] - g.sources[None, :, :], axis=-1)
+    np.testing.assert_allclose(np.abs(A), 1.0 / R, rtol=1e-13)
+
+
+def test_hemisphere_pair_geometry():
+    n = 2000
+    g = wl.hemisphere_pair(n, seed=1)
+    h = math.sqrt(2 * math.pi / n)
+    assert g.targets.shape == (n, 3) and g.sources.shape == (n, 3)
+    np.testing.assert_allclose(np.linalg.norm(g.targets, axis=1), 1.0, atol=1e-14)
+    np.testing.assert_allclose(np.linalg.norm(g.sources - [0, 0, -h / 2], axis=1), 1.0, atol=1e-14)
+    assert g.targets[:, 2].min() > 0 and g.sources[:, 2].max() < -h / 2
+    # n = 50 k^2 / pi: ten points per wavelength
+    assert abs(50 * g.k ** 2 / math.pi - n) < 1e-9 * n
+    # adjacent but disjoint: closest pair at about the point spacing
+    R = np.linalg.norm(g.targets[:, None, :] - g.sources[None, :, :], axis=-1)
+    assert 0.5 * h < R.min() < 2 * h
+    # equal-area spiral: the heights are a permutation of (i + 1/2) / n
+    np.testing.assert_allclose(np.sort(g.targets[:, 2]), (np.arange(n) + 0.5) / n, atol=1e-15)
+
+
+def test_bisection_order_clusters():
+    """Every node range of the bisection tree splits into two children that
+    are separated along one coordinate axis (a spatial cluster tree)."""
+    g = wl.hemisphere_pair(1000, seed=2, depth=6)
+    for pts in (g.targets, g.sources):
+        N = len(pts)
+        for l in range(6):
+            for i in range(1 << l):
+                a, c, b = (i * N) >> l, ((2 * i + 1) * N) >> (l + 1), ((i + 1) * N) >> l
+                lo, hi = pts[a:c], pts[c:b]
+                assert any(lo[:, ax].max() <= hi[:, ax].min() for ax in range(3))
+    # a permutation: no point lost or duplicated
+    p = wl.bisection_order(np.random.default_rng(0).random((513, 3)), 5)
+    assert sorted(p.tolist()) == list(range(513))

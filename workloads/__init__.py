@@ -21,6 +21,15 @@ synthetic operators of the same geometry class stand in for them):
   Fourier operators", Sec. 4.4.1).
 * Exact butterfly (Sec. 6.1): random unitary leaf bases and transfer blocks
   and Gaussian centre blocks, all ranks r, leaves of 8 points, n = 2^(L+3).
+* Two adjacent unit semi-spheres (the 3D weak-admissibility geometry of
+  Sec. 6.3, whose Nystrom meshes are not available): n targets on the upper
+  unit hemisphere and n sources on a lower unit hemisphere whose rim lies
+  half a point spacing below the first one's.  Points follow an equal-area
+  golden-angle spiral (height uniform in (0, 1), azimuth advancing by the
+  golden angle from a seeded offset), then are reordered by recursive
+  bisection so that the index ranges of the butterfly's binary trees are
+  spatial clusters.  Kernel exp(i k r)/r with k = sqrt(pi n / 50), i.e.
+  n = 50 k^2 / pi: ten points per wavelength on the hemisphere's area 2 pi.
 """
 from __future__ import annotations
 
@@ -33,16 +42,17 @@ __all__ = [
     "SegmentGeometry", "segment_pair", "segment_triple", "fio_params",
     "test_columns", "ExactButterflyFactors", "exact_butterfly_factors",
     "node_range_host", "Request", "poisson_stream", "mixed_stream", "exact_butterfly_canonical",
+    "hemisphere_pair", "bisection_order",
 ]
 
 
 @dataclass(frozen=True)
 class SegmentGeometry:
-    """Points of the target line (rows) and source line (columns)."""
-    targets: np.ndarray   # (m, 2) float64
-    sources: np.ndarray   # (n, 2) float64
+    """Target points (rows) and source points (columns) of exp(i k r)/r."""
+    targets: np.ndarray   # (m, 2) or (m, 3) float64
+    sources: np.ndarray   # (n, 2) or (n, 3) float64
     k: float              # wavenumber of exp(i k r)/r
-    ppw: float            # points per wavelength at spacing 1/n
+    ppw: float            # points per wavelength at the source spacing
 
 
 def _line(npts: int, y: float) -> np.ndarray:
@@ -70,6 +80,51 @@ def segment_triple(n: int, ppw: float = 8.0):
     g01 = segment_pair(n, ppw, y_target=0.0, y_source=1.0)
     g12 = segment_pair(n, ppw, y_target=1.0, y_source=2.0)
     return g01, g12
+
+
+def bisection_order(pts: np.ndarray, depth: int) -> np.ndarray:
+    """Permutation that makes every node range [floor(i N / 2^l),
+    floor((i+1) N / 2^l)), l <= depth, a spatial cluster: each node is split
+    at its children's boundary floor((2i+1) N / 2^(l+1)) along the axis of
+    its largest extent (stable sort, so the order is deterministic)."""
+    N = len(pts)
+    perm = np.arange(N)
+    for l in range(depth):
+        for i in range(1 << l):
+            a, b = (i * N) >> l, ((i + 1) * N) >> l
+            if b - a < 2:
+                continue
+            idx = perm[a:b]
+            p = pts[idx]
+            ax = int(np.argmax(p.max(axis=0) - p.min(axis=0)))
+            perm[a:b] = idx[np.argsort(p[:, ax], kind="stable")]
+    return perm
+
+
+def _hemisphere(n: int, phase: float, sign: float, dz: float) -> np.ndarray:
+    z = (np.arange(n, dtype=np.float64) + 0.5) / n
+    phi = phase + np.arange(n, dtype=np.float64) * (math.pi * (3.0 - math.sqrt(5.0)))
+    rho = np.sqrt(1.0 - z * z)
+    return np.stack([rho * np.cos(phi), rho * np.sin(phi), sign * z + dz], axis=1)
+
+
+def hemisphere_pair(n: int, seed: int = 0, ppw: float = 10.0, depth: int | None = None,
+                    m: int | None = None) -> SegmentGeometry:
+    """Two adjacent unit semi-spheres (3D, weak admissibility), see the module
+    docstring.  ``depth`` bisection levels (default: down to about 8 points
+    per node); ``ppw`` points per wavelength (10 gives k = sqrt(pi n / 50))."""
+    m = n if m is None else m
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0.0, 2.0 * math.pi, 2)
+    h = math.sqrt(2.0 * math.pi / n)                 # mean spacing of the sources
+    t = _hemisphere(m, ph[0], +1.0, 0.0)
+    s = _hemisphere(n, ph[1], -1.0, -0.5 * h)
+    if depth is None:
+        depth = max(0, int(math.ceil(math.log2(max(m, n) / 8.0))))
+    t = t[bisection_order(t, depth)]
+    s = s[bisection_order(s, depth)]
+    k = 2.0 * math.pi / (ppw * h)
+    return SegmentGeometry(np.ascontiguousarray(t), np.ascontiguousarray(s), k, ppw)
 
 
 def fio_params(n: int):
