@@ -86,15 +86,27 @@ def _H(a):
 
 # ---------------------------------------------------------------- Alg. 2 --
 
-def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None) -> Factors:
-    """Alg. 2.  ``op`` has ``m, n, matvec(X, support), rmatvec(X, support)``."""
+def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Factors:
+    """Alg. 2.  ``op`` has ``m, n, matvec(X, support), rmatvec(X, support)``.
+
+    ``lm`` is the level of the centre factor B (eq. hybrid_butterfly_mat);
+    default floor(L/2), the hybrid factorization of Sec. 3.3.3.  lm = 0 gives
+    the column-wise factorization of Sec. 3.3.1 (E^0 = B^0 V^0) and lm = L
+    the row-wise one of Sec. 3.3.2 (F^L = U^L B^L), the variants Sec. 4 says
+    the same algorithm builds at a higher cost.  Negative lm counts from
+    L + 1 (-1 is L)."""
     m, n = op.m, op.n
     if m <= 0 or n <= 0:
         raise ValueError("empty operator")
     if not (0.0 < tol < 1.0):
         raise ValueError("tol must lie in (0, 1)")
     L = num_levels(m, n, leaf)
-    lm = center_level(L)
+    if lm is None:
+        lm = center_level(L)
+    elif lm < 0:
+        lm += L + 1
+    if not 0 <= lm <= L:
+        raise ValueError(f"centre level {lm} outside [0, {L}]")
     F = Factors(m, n, L, lm)
     F.kU = {l: {} for l in range(lm, L + 1)}
     F.kV = {l: {} for l in range(0, lm + 1)}
@@ -200,15 +212,18 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None) -> Factors:
                     C = _H(F.R[lm][(i, j)]) @ Zs[i]
                     F.B[(i, j)] = _lstsq_right(C, X[i])
 
-    if L == 0:
-        # single block: A ~ U B V^H with the leaf bases themselves
-        s = max(F.kU[0][(0, 0)], F.kV[0][(0, 0)]) + p
-        Om = philox.sample_block(seed, philox.tag(philox.PHASE_R, 0, 0), 0, n, s)
+    if lm == L:
+        # centre at the row leaves (the row-wise factorization, and L = 0):
+        # B_{i,0} = (U_i^H A Omega)(V_{i,0}^H Omega)^+ with the leaf column
+        # bases themselves (no R level) and the full-height row bases
+        s = max(max(F.kU[L][(i, 0)], F.kV[L][(i, 0)]) for i in range(1 << L)) + p
+        Om = philox.sample_block(seed, philox.tag(philox.PHASE_R, L, 0), 0, n, s)
         Y = op.matvec(Om)
         cols["matvec"] += s
-        C = _H(F.U[0]) @ Y
-        X = _H(F.V[0]) @ Om
-        F.B[(0, 0)] = _lstsq_right(C, X)
+        X = _x_chain(F, Om, 0)
+        for i in range(1 << L):
+            C = _H(F.U[i]) @ Y[slice(*F.trange(L, i))]
+            F.B[(i, 0)] = _lstsq_right(C, X[i])
 
     F.stats = cols
     return F

@@ -170,3 +170,51 @@ def test_planted_pivot_rule_is_caught(monkeypatch):
     monkeypatch.setattr(cpqr.np, "argmax", np.argmin)
     _, _, perm, _ = cpqr.cpqr_truncated(W, 1e-300)
     assert not np.array_equal(perm, sla.qr(W, pivoting=True, mode="economic")[2])
+
+
+@pytest.mark.parametrize("L,r", [(4, 3), (5, 4)])
+def test_centre_level_variants_exact(L, r):
+    """The column-wise (lm = 0, Sec. 3.3.1), row-wise (lm = L, Sec. 3.3.2) and
+    intermediate factorizations recover an exact butterfly (the complementary
+    low-rank property gives rank r at every level), and their black-box
+    column counts follow the sweep structure: an R level l costs 2^(L-l)
+    samples and a W level 2^l, each 2r + p wide, so the hybrid lm = L/2 needs
+    the fewest."""
+    fx = wl.exact_butterfly_factors(L, r, seed=L * 10 + r)
+    op = bf.FactorsOp(bf.from_exact(fx))
+    A = bf.dense(op.F)
+    p = 2
+    leaf_cols, rr = 0, 4            # adaptive leaf loop from r0 = 4: doubles until r > rank
+    while True:
+        leaf_cols += rr + p
+        if rr > r:
+            break
+        rr *= 2
+    counts = {}
+    for lm in range(L + 1):
+        F = bf.construct(op, 1e-6, 8, p=p, r0=4, seed=5, lm=lm)
+        assert F.lm == lm
+        assert np.linalg.norm(A - bf.dense(F)) <= 1e-12 * np.linalg.norm(A)
+        ks = {k for d in F.kU.values() for k in d.values()} | {k for d in F.kV.values() for k in d.values()}
+        assert ks == {r}
+        s = 2 * r + p
+        mv = leaf_cols + sum(2 ** (L - l) * s for l in range(lm, L)) + (r + p if lm == L else 0)
+        rmv = leaf_cols + sum(2 ** l * s for l in range(1, lm + 1))
+        assert (F.stats["matvec"], F.stats["rmatvec"]) == (mv, rmv)
+        counts[lm] = mv + rmv
+    assert min(counts, key=counts.get) == L // 2
+    assert bf.construct(op, 1e-6, 8, seed=5, lm=-1).lm == L
+    with pytest.raises(ValueError):
+        bf.construct(op, 1e-6, 8, seed=5, lm=L + 1)
+
+
+@pytest.mark.parametrize("lm", [0, 2, 5])
+def test_centre_level_variants_error(lm):
+    """Thm 4.3 bounds the error of the level-l factorization for any l: the
+    column- and row-wise variants of an oscillatory operator meet the same
+    tolerance model as the hybrid."""
+    op = _seg_op(512)
+    F = bf.construct(op, 1e-6, 16, seed=2, lm=lm)
+    assert F.L == 5 and F.lm == lm
+    A = op.dense()
+    assert np.linalg.norm(A - bf.dense(F)) / np.linalg.norm(A) <= 10 * math.sqrt(F.L + 2) * 1e-6
