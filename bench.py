@@ -66,6 +66,10 @@ def parse():
                          "tolerance")
     ap.add_argument("--em3d-tols", default="1e-2,1e-3,1e-4",
                     help="tolerances of --em3d")
+    ap.add_argument("--variants", default="",
+                    help="only compare the hybrid (l_m = L/2), column-wise (l_m = 0) and "
+                         "row-wise (l_m = L) constructions of the segment-kernel operator at "
+                         "these comma-separated n (leaf 64, tol 1e-6); one JSON line each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (reference "
                          "dispatch for calibrating rocprofv3 byte counters) and exit")
@@ -163,6 +167,46 @@ def em3d(cases, tols):
             F.close()
         op.close()
         torch.cuda.empty_cache()
+
+
+def variants(sizes, leaf=64, tol=1e-6):
+    """Sec. 3.3 / Sec. 4: the same algorithm building the column-wise and
+    row-wise factorizations instead of the hybrid one; time (second of two
+    runs), black-box columns, error on 16 Gaussian columns against the
+    black-box product, phases."""
+    import torch
+
+    import paper_2002_03400_amd as bf
+    import workloads as wl
+    torch.cuda.init()
+    for n in sizes:
+        g = wl.segment_pair(n, ppw=8.0)
+        op = bf.segkernel(g.targets, g.sources, g.k)
+        Om = torch.from_numpy(wl.test_columns(n, 16, 1001).astype(np.complex64)).cuda()
+        ref = op.matvec(Om)
+        for center in ("hybrid", "column", "row"):
+            for rep in range(2):
+                bf.profile_start()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F = bf.construct(op, tol, leaf, seed=1, center=center)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                prof = bf.profile_stop()
+                print(f"variants n={n} {center}: construction {rep} took {dt:.2f} s",
+                      file=sys.stderr, flush=True)
+                if rep == 1:
+                    st = F.stats()
+                    err = float((F.apply(Om) - ref).norm() / ref.norm())
+                    print(json.dumps({
+                        "workload": "segment pair (Sec. 6.2 geometry), factorization variants",
+                        "n": n, "leaf": leaf, "tol": tol, "center": center, "L": st.L,
+                        "lm": st.lm, "seconds": dt, "rel_err": err, "max_rank": st.max_rank,
+                        "matvec_cols": st.matvec_cols, "rmatvec_cols": st.rmatvec_cols,
+                        "factor_entries": st.factor_entries,
+                        "phase_ms": {k: v["ms"] for k, v in prof.items()}}), flush=True)
+                F.close()
+        op.close()
 
 
 def copy_calibration():
@@ -330,6 +374,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.variants:
+        variants([int(x) for x in args.variants.split(",")])
         return
     if args.em3d:
         em3d([tuple(int(x) for x in e.split(":")) for e in args.em3d.split(",")],

@@ -91,7 +91,7 @@ typedef struct {
   int32_t p;          /* over-sampling (Alg. 1 input), >= 0 */
   int32_t r0;         /* initial rank guess of the adaptive loops, >= 1 */
   int32_t max_rank;   /* 0 = none; else BF_ERANK when a rank estimate passes it */
-  int32_t flags;      /* reserved, 0 */
+  int32_t flags;      /* BF_OPT_CENTER_LEVEL or 0 */
   uint64_t seed;      /* key of the counter-based random matrices */
   int64_t work_bytes; /* device bytes a sweep level's samples may occupy at once
                          (black-box output and partial-factor products); the
@@ -106,7 +106,20 @@ typedef struct {
      factored).  NULL = none. */
   void (*progress)(void* user, int32_t phase, int32_t level);
   void* progress_user;
+  /* With BF_OPT_CENTER_LEVEL in flags: the level l_m of the centre factor B
+     (eq. hybrid_butterfly_mat), in [0, L]; negative values count from L + 1
+     (-1 is L).  0 builds the column-wise factorization of Sec. 3.3.1
+     (E^0 = B^0 V^0), L the row-wise one of Sec. 3.3.2 (F^L = U^L B^L); both
+     need far more black-box columns and partial products than the hybrid
+     (an R level l has 2^(L-l) samples, a W level 2^l).  With l_m = L the
+     centre blocks use the leaf column bases directly and the last progress
+     report is (BF_PHASE_R, L).  Default l_m = floor(L/2) (Sec. 3.3.3).
+     bf_import always assumes the default. */
+  int32_t center_level;
+  int32_t reserved;   /* 0 */
 } bf_opts;
+
+enum { BF_OPT_CENTER_LEVEL = 1 };
 
 enum { BF_PHASE_LEAF_V = 0, BF_PHASE_LEAF_U = 1, BF_PHASE_W = 2, BF_PHASE_R = 3 };
 

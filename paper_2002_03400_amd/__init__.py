@@ -52,7 +52,12 @@ PHASES = ("leaf V", "leaf U", "W", "R")
 class bf_opts(C.Structure):
     _fields_ = [("p", C.c_int32), ("r0", C.c_int32), ("max_rank", C.c_int32),
                 ("flags", C.c_int32), ("seed", C.c_uint64), ("work_bytes", C.c_int64),
-                ("progress", PROGRESSFN), ("progress_user", C.c_void_p)]
+                ("progress", PROGRESSFN), ("progress_user", C.c_void_p),
+                ("center_level", C.c_int32), ("reserved", C.c_int32)]
+
+
+BF_OPT_CENTER_LEVEL = 1
+CENTERS = {"hybrid": None, "column": 0, "row": -1}
 
 
 class bf_kernel_stats(C.Structure):
@@ -366,12 +371,19 @@ class Factors:
 
 
 def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed: int = 0,
-              max_rank: int = 0, stream=None, work_bytes: int = 0, progress=None) -> Factors:
+              max_rank: int = 0, stream=None, work_bytes: int = 0, progress=None,
+              center="hybrid") -> Factors:
     """Alg. 2 on the device; returns the factor handle.  work_bytes bounds the
     device memory of one sweep level's samples (0: 8 GiB).  progress(phase,
     level), if given, is called after each leaf-loop iteration and sweep level
-    with phase one of PHASES."""
+    with phase one of PHASES.  center: the level of the centre factor B --
+    "hybrid" (floor(L/2)), "column" (0: column-wise factorization), "row" (L:
+    row-wise), or an integer level (negative counts from L + 1)."""
     o = bf_opts(p, r0, max_rank, 0, seed, work_bytes)
+    lm = CENTERS[center] if isinstance(center, str) else int(center)
+    if lm is not None:
+        o.flags = BF_OPT_CENTER_LEVEL
+        o.center_level = lm
     cb = None    # held until bf_construct returns
     if progress is not None:
         cb = PROGRESSFN(lambda _u, ph, lv: progress(PHASES[ph], lv))

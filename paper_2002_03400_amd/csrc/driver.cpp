@@ -63,8 +63,14 @@ class Builder {
     }
     BF_CHECK(p_ >= 0 && r0_ >= 1 && cap_ >= 0 && (!o || o->work_bytes >= 0), BF_EINVAL,
              "bad bf_opts");
+    BF_CHECK(!o || (o->flags & ~BF_OPT_CENTER_LEVEL) == 0, BF_EINVAL, "unknown bf_opts flags");
     F_->L = num_levels(m, n, leaf);
     F_->lm = F_->L / 2;
+    if (o && (o->flags & BF_OPT_CENTER_LEVEL)) {
+      const int c = o->center_level < 0 ? o->center_level + F_->L + 1 : o->center_level;
+      BF_CHECK(c >= 0 && c <= F_->L, BF_EINVAL, "centre level outside [0, L]");
+      F_->lm = c;
+    }
     BF_CHECK(F_->L <= 24, BF_EINVAL, "too many levels");
     BF_HIP(hipGetDevice(&F_->device));
     const size_t nb = size_t(1) << F_->L;
@@ -86,7 +92,10 @@ class Builder {
       r_level(l);
       report(BF_PHASE_R, l);
     }
-    if (F_->L == 0) centre_single_block();
+    if (F_->lm == F_->L) {
+      centre_at_leaves();
+      if (F_->L > 0) report(BF_PHASE_R, F_->L);
+    }
     finalize();
     bf_factors* out = F_;
     F_ = nullptr;
@@ -532,18 +541,18 @@ class Builder {
     }
   }
 
-  // Samples j in [j0, j1) of level l_m: X_{lm,i,j} = V_{tau,nu}^H Omega_nu by
-  // the nested row bases (V^0 on the leaves under nu, then W^1..W^{lm}
-  // restricted to nu's subtree), then C = R^H Z and B = C X^+ for the blocks
-  // (i, j).  zq holds the Z blocks in the local order i * (j1 - j0) + (j - j0).
-  void centre_blocks(const DevBuf<bf_c64>& Om, const std::vector<int32_t>& width, int64_t j0,
-                     int64_t j1, const std::vector<QRDesc>& zq) {
+  // X_{lm,i,j} = V_{tau,nu}^H Omega_nu for the samples j in [j0, j1) of the
+  // centre level, by the nested row bases: V^0 on the leaves under nu, then
+  // W^1..W^{lm} restricted to nu's subtree.  view[j - j0] holds sample j's
+  // X blocks (rows by i); keep owns the buffers.
+  void x_chain(const DevBuf<bf_c64>& Om, const std::vector<int32_t>& width, int64_t j0, int64_t j1,
+               std::vector<Tall<bf_c128>>& view, std::vector<DevBuf<bf_c128>>& keep) {
     const int64_t n = F_->n;
     const int lmv = lm();
-    const int64_t nT = int64_t(1) << lmv, ng = j1 - j0;
+    const int64_t ng = j1 - j0;
     // level 0 (leaves under nu): per-sample tall, blocks j' local in [0, 2^lm)
     const int64_t nl0 = int64_t(1) << lmv;
-    std::vector<Tall<bf_c128>> view(ng);
+    view.assign(ng, Tall<bf_c128>{});
     std::vector<int64_t> base(ng);
     int64_t tot = 0;
     for (int64_t q = 0; q < ng; ++q) {
@@ -579,7 +588,7 @@ class Builder {
       }
       gemm(d, true);
     }
-    std::vector<DevBuf<bf_c128>> keep;
+    keep.clear();
     keep.push_back(std::move(buf0));
     for (int lp = 1; lp <= lmv; ++lp) {
       const int64_t nTl = int64_t(1) << lp;
@@ -629,9 +638,21 @@ class Builder {
       keep.push_back(std::move(buf));
       view.swap(next);
     }
-    // C = R^H Z (kU x s) for every block (i, j) of the group
+  }
+
+  // Samples j in [j0, j1) of level l_m: X by the x-chain, then C = R^H Z and
+  // B = C X^+ for the blocks (i, j).  zq holds the Z blocks in the local order
+  // i * (j1 - j0) + (j - j0).
+  void centre_blocks(const DevBuf<bf_c64>& Om, const std::vector<int32_t>& width, int64_t j0,
+                     int64_t j1, const std::vector<QRDesc>& zq) {
+    const int lmv = lm();
+    const int64_t nT = int64_t(1) << lmv, ng = j1 - j0;
+    std::vector<Tall<bf_c128>> view;
+    std::vector<DevBuf<bf_c128>> keep;
+    x_chain(Om, width, j0, j1, view, keep);
     std::vector<int64_t> coff((size_t)(nT * ng));
-    tot = 0;
+    int64_t tot = 0;
+    // C = R^H Z (kU x s) for every block (i, j) of the group
     for (int64_t i = 0; i < nT; ++i)
       for (int64_t q = 0; q < ng; ++q) {
         coff[(size_t)(i * ng + q)] = tot;
@@ -705,36 +726,46 @@ class Builder {
     F_->store.push_back(std::move(Bst));
   }
 
-  // L = 0: the whole matrix is one block, A ~ U B V^H with the leaf bases.
-  void centre_single_block() {
-    const int64_t m = F_->m, n = F_->n;
-    const int32_t ku = F_->ku(0, 0, 0), kv = F_->kv(0, 0, 0);
-    const int32_t s = std::max(ku, kv) + p_;
+  // l_m = L (the row-wise factorization, and L = 0): the centre blocks sit on
+  // the row leaves, B_{i,0} = (U_i^H A Omega)(V_{i,0}^H Omega)^+ with the leaf
+  // column bases themselves (no R level) and the full-height row bases of the
+  // x-chain.  One sample over all of S, max_i max(k_U, k_V) + p wide.
+  void centre_at_leaves() {
+    const int64_t m = F_->m, n = F_->n, nT = nb();
+    int32_t w = 0;
+    for (int64_t i = 0; i < nT; ++i) w = std::max(w, std::max(F_->ku(L(), i, 0), F_->kv(L(), i, 0)));
+    check_cap(w);
+    const int32_t s = w + p_;
     std::vector<int32_t> width{s};
-    auto Om = gauss(n, s, 0, {make_tag(PHASE_R, 0, 0)}, width);
+    auto Om = gauss(n, s, 0, {make_tag(PHASE_R, L(), 0)}, width);
     DevBuf<bf_c64> Y((size_t)m * s, s_);
-    std::vector<int64_t> seg{0, n};
     call_op(false, Om.p, n, s, Y.p, m, nullptr);
     mv_cols_ += s;
-    DevBuf<bf_c128> C((size_t)std::max(ku, 1) * s, s_);
-    DevBuf<bf_c128> X((size_t)std::max(kv, 1) * s, s_);
-    std::vector<GemmDesc> d1, d2;
-    const Block& U = F_->U[0];
-    const Block& V = F_->V[0];
-    GemmDesc g{};
-    g.out = C.p; g.out_ld = std::max(ku, 1); g.M = ku; g.ncols = s; g.nterm = 1;
-    g.t[0] = GemmTerm{U.p, Y.p, m, U.rows, U.rows, 1, 0};
-    if (ku > 0) d1.push_back(g);
-    g.out = X.p; g.out_ld = std::max(kv, 1); g.M = kv;
-    g.t[0] = GemmTerm{V.p, Om.p, n, V.rows, V.rows, 1, 0};
-    if (kv > 0) d1.push_back(g);
-    gemm(d1, true);
-    std::vector<Tall<bf_c128>> xv(1);
-    xv[0].base = X.p;
-    xv[0].ld = std::max(kv, 1);
-    xv[0].roff = {0};
-    F_->B.assign(1, Block{});
-    solve_b(C.p, {0}, xv, width, 0, 1, [](int64_t, int64_t) { return 0; });
+    std::vector<Tall<bf_c128>> xv;
+    std::vector<DevBuf<bf_c128>> keep;
+    x_chain(Om, width, 0, 1, xv, keep);
+    std::vector<int64_t> coff((size_t)nT);
+    int64_t tot = 0;
+    for (int64_t i = 0; i < nT; ++i) {
+      coff[(size_t)i] = tot;
+      tot += (int64_t)F_->ku(L(), i, 0) * s;
+    }
+    DevBuf<bf_c128> C((size_t)std::max<int64_t>(tot, 1), s_);
+    std::vector<GemmDesc> d;
+    for (int64_t i = 0; i < nT; ++i) {
+      const Block& U = F_->U[(size_t)i];
+      GemmDesc g{};
+      g.out = C.p + coff[(size_t)i];
+      g.out_ld = std::max(U.cols, 1);
+      g.M = U.cols;
+      g.ncols = s;
+      g.nterm = 1;
+      g.t[0] = GemmTerm{U.p, Y.p + node_lo(m, L(), i), m, U.rows, U.rows, 1, 0};
+      if (g.M > 0) d.push_back(g);
+    }
+    gemm(d, true);
+    F_->B.assign((size_t)nT, Block{});
+    solve_b(C.p, coff, xv, width, 0, 1, [](int64_t i, int64_t) { return i; });
   }
 
   void finalize() {

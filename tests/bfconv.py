@@ -27,8 +27,8 @@ def oracle_to_canonical(F):
     return kU, kV, data
 
 
-def canonical_to_oracle(m, n, L, kU, kV, data):
-    lm = L // 2
+def canonical_to_oracle(m, n, L, kU, kV, data, lm=None):
+    lm = L // 2 if lm is None else lm
     F = obf.Factors(m, n, L, lm)
     ku = lambda l, i, j: int(kU[l - lm, (i << (L - l)) + j])
     kv = lambda l, i, j: int(kV[l, (i << (L - l)) + j])

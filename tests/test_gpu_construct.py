@@ -202,3 +202,59 @@ def test_exact_butterfly_at_scale(bf):
     assert e < 2e-6
     H.close()
     src.close()
+
+
+@pytest.mark.parametrize("center,lm", [("column", 0), (1, 1), ("row", 5)])
+def test_centre_level_variants(bf, center, lm):
+    """Column-wise (Sec. 3.3.1), an intermediate level, and row-wise (Sec. 3.3.2)
+    factorizations of C1 against the oracle's, with the black-box column
+    counts of the two sides equal."""
+    g = wl.segment_pair(1024, ppw=8.0)
+    op_o = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    Fo = obf.construct(op_o, 1e-6, 32, seed=1, lm=lm)
+    say("centre level", center, lm)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    H = bf.construct(op, 1e-6, 32, seed=1, center=center)
+    assert (H.L, H.lm) == (5, lm)
+    Om = wl.test_columns(1024, 16, 1001)
+    AOm = op_o.matvec(Om)
+    e_or = _err(AOm, obf.apply(Fo, Om))
+    e_gpu = _err(AOm, H.apply(_t(Om)).cpu().numpy())
+    say("variant errors oracle", e_or, "gpu", e_gpu)
+    assert e_gpu <= 2 * e_or
+    kU, kV = H.ranks()
+    ko_U, ko_V, _ = oracle_to_canonical(Fo)
+    assert np.abs(kU.astype(int) - ko_U).max() <= 2
+    assert np.abs(kV.astype(int) - ko_V).max() <= 2
+    Fg = canonical_to_oracle(H.m, H.n, H.L, kU, kV, H.export(), lm=lm)
+    A = op_o.dense()
+    assert np.linalg.norm(A - obf.dense(Fg)) / np.linalg.norm(A) <= 2 * e_or
+    # adjoint of the variant's own factors
+    X = wl.test_columns(1024, 5, 3)
+    ref = obf.apply_adjoint(Fg, X)
+    np.testing.assert_allclose(H.apply(_t(X), trans=True).cpu().numpy(), ref,
+                               atol=2e-6 * np.abs(ref).max())
+    # black-box columns: equal up to the widths' dependence on ranks (+-2)
+    info = H.stats()
+    assert abs(info.matvec_cols - Fo.stats["matvec"]) <= 0.05 * Fo.stats["matvec"]
+    assert abs(info.rmatvec_cols - Fo.stats["rmatvec"]) <= 0.05 * Fo.stats["rmatvec"]
+
+
+@pytest.mark.parametrize("center", ["column", "row"])
+def test_centre_level_exact_recovery(bf, center):
+    """An exact rank-4 butterfly (L = 5) has rank 4 at every level, so the
+    column- and row-wise constructions recover it like the hybrid."""
+    fx = wl.exact_butterfly_factors(5, 4, seed=54)
+    F0 = obf.from_exact(fx)
+    kU, kV, data = oracle_to_canonical(F0)
+    src = bf.import_factors(fx.n, fx.n, 8, kU, kV, data)
+    op = bf.from_factors(src)
+    H = bf.construct(op, 1e-5, 8, seed=5, center=center)
+    gU, gV = H.ranks()
+    assert set(np.unique(gU)) == {4} and set(np.unique(gV)) == {4}
+    Om = wl.test_columns(fx.n, 16, 2)
+    e = _err(obf.apply(F0, Om), H.apply(_t(Om)).cpu().numpy())
+    say("exact variant", center, e)
+    assert e < 5e-6
+    with pytest.raises(bf.BFError):
+        bf.construct(op, 1e-5, 8, seed=5, center=6)
