@@ -91,7 +91,7 @@ typedef struct {
   int32_t p;          /* over-sampling (Alg. 1 input), >= 0 */
   int32_t r0;         /* initial rank guess of the adaptive loops, >= 1 */
   int32_t max_rank;   /* 0 = none; else BF_ERANK when a rank estimate passes it */
-  int32_t flags;      /* BF_OPT_CENTER_LEVEL or 0 */
+  int32_t flags;      /* BF_OPT_* bits, or 0 */
   uint64_t seed;      /* key of the counter-based random matrices */
   int64_t work_bytes; /* device bytes a sweep level's samples may occupy at once
                          (black-box output and partial-factor products); the
@@ -119,7 +119,14 @@ typedef struct {
   int32_t reserved;   /* 0 */
 } bf_opts;
 
-enum { BF_OPT_CENTER_LEVEL = 1 };
+/* BF_OPT_CENTER_LEVEL: use center_level.
+ * BF_OPT_SEQUENTIAL_LEAF: one black-box call per pass of the adaptive leaf
+ *   loops.  By default consecutive passes (each with its own fixed random
+ *   block) share one call while their widths add up to at most 48 columns,
+ *   which returns the same products in fewer calls; when the loop stops
+ *   before a merged pass, that pass's columns are wasted (and counted in
+ *   bf_info's column totals). */
+enum { BF_OPT_CENTER_LEVEL = 1, BF_OPT_SEQUENTIAL_LEAF = 2 };
 
 enum { BF_PHASE_LEAF_V = 0, BF_PHASE_LEAF_U = 1, BF_PHASE_W = 2, BF_PHASE_R = 3 };
 

@@ -57,6 +57,7 @@ class bf_opts(C.Structure):
 
 
 BF_OPT_CENTER_LEVEL = 1
+BF_OPT_SEQUENTIAL_LEAF = 2
 CENTERS = {"hybrid": None, "column": 0, "row": -1}
 
 
@@ -372,18 +373,22 @@ class Factors:
 
 def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed: int = 0,
               max_rank: int = 0, stream=None, work_bytes: int = 0, progress=None,
-              center="hybrid") -> Factors:
+              center="hybrid", merge_leaf: bool = True) -> Factors:
     """Alg. 2 on the device; returns the factor handle.  work_bytes bounds the
     device memory of one sweep level's samples (0: 8 GiB).  progress(phase,
     level), if given, is called after each leaf-loop iteration and sweep level
     with phase one of PHASES.  center: the level of the centre factor B --
     "hybrid" (floor(L/2)), "column" (0: column-wise factorization), "row" (L:
-    row-wise), or an integer level (negative counts from L + 1)."""
+    row-wise), or an integer level (negative counts from L + 1).  merge_leaf:
+    consecutive passes of the adaptive leaf loops share a black-box call
+    (same results, fewer calls); False makes one call per pass."""
     o = bf_opts(p, r0, max_rank, 0, seed, work_bytes)
     lm = CENTERS[center] if isinstance(center, str) else int(center)
     if lm is not None:
-        o.flags = BF_OPT_CENTER_LEVEL
+        o.flags |= BF_OPT_CENTER_LEVEL
         o.center_level = lm
+    if not merge_leaf:
+        o.flags |= BF_OPT_SEQUENTIAL_LEAF
     cb = None    # held until bf_construct returns
     if progress is not None:
         cb = PROGRESSFN(lambda _u, ph, lv: progress(PHASES[ph], lv))

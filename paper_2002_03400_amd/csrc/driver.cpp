@@ -60,10 +60,12 @@ class Builder {
       if (o->work_bytes > 0) work_ = o->work_bytes;
       progress_ = o->progress;
       progress_user_ = o->progress_user;
+      merge_leaf_ = (o->flags & BF_OPT_SEQUENTIAL_LEAF) == 0;
     }
     BF_CHECK(p_ >= 0 && r0_ >= 1 && cap_ >= 0 && (!o || o->work_bytes >= 0), BF_EINVAL,
              "bad bf_opts");
-    BF_CHECK(!o || (o->flags & ~BF_OPT_CENTER_LEVEL) == 0, BF_EINVAL, "unknown bf_opts flags");
+    BF_CHECK(!o || (o->flags & ~(BF_OPT_CENTER_LEVEL | BF_OPT_SEQUENTIAL_LEAF)) == 0, BF_EINVAL,
+             "unknown bf_opts flags");
     F_->L = num_levels(m, n, leaf);
     F_->lm = F_->L / 2;
     if (o && (o->flags & BF_OPT_CENTER_LEVEL)) {
@@ -116,6 +118,7 @@ class Builder {
   Staging& st_ = scope_staging(s_) ? *scope_staging(s_) : own_st_;
   int64_t mv_cols_ = 0, rmv_cols_ = 0;
   int v_iters_ = 0, u_iters_ = 0;
+  bool merge_leaf_ = true;
   void (*progress_)(void*, int32_t, int32_t) = nullptr;
   void* progress_user_ = nullptr;
   void report(int32_t phase, int32_t level) const {
@@ -246,23 +249,53 @@ class Builder {
   }
 
   // ---- adaptive leaf loops (first two loops of Alg. 2) ---------------------
+  // Every pass draws a fresh random block whose values are fixed in advance
+  // (its own tag), so consecutive passes are merged into one black-box call
+  // while their widths add up to at most LEAF_BATCH_COLS: a built-in product
+  // evaluates each matrix entry once per call, whatever the width.  Merging
+  // changes only how the products are grouped into calls, not their values;
+  // a pass the loop does not reach wastes its columns (counted in the stats).
+  // BF_OPT_SEQUENTIAL_LEAF makes one call per pass.
+  static constexpr int64_t LEAF_BATCH_COLS = 48;
+
   void leaf_loop(bool col_side) {
     const int64_t rows_in = col_side ? F_->n : F_->m;   // rows of the random block
     const int64_t rows_out = col_side ? F_->m : F_->n;  // rows of the sample
     int64_t r = r0_;
+    DevBuf<bf_c64> Y;                  // samples of the current batch of passes
+    std::vector<int64_t> boff;         // column offset of each pass in the batch
+    int bstart = 0, bend = 0;          // passes [bstart, bend) are in Y
     for (int it = 0;; ++it) {
       check_cap(r);
       const int64_t s = r + p_;
       BF_CHECK(s <= 65535, BF_ERANK, "sample width too large");
-      auto G = gauss(rows_in, s, 0, {make_tag(col_side ? PHASE_U0 : PHASE_V0, it, 0)},
-                     {(int32_t)s});
-      DevBuf<bf_c64> Y((size_t)rows_out * s, s_);
-      call_op(!col_side, G.p, rows_in, s, Y.p, rows_out, nullptr);
-      (col_side ? mv_cols_ : rmv_cols_) += s;
+      if (it == bend) {
+        // passes it, it+1, ... (stopping at the rank cap and the width bound)
+        std::vector<int64_t> widths{s};
+        int64_t tot = s;
+        for (int64_t rr = 2 * r; merge_leaf_; rr *= 2) {
+          if ((cap_ > 0 && rr > cap_) || tot + rr + p_ > LEAF_BATCH_COLS) break;
+          widths.push_back(rr + p_);
+          tot += rr + p_;
+        }
+        DevBuf<bf_c64> G((size_t)rows_in * tot, s_);
+        boff.assign(widths.size(), 0);
+        for (size_t q = 0; q < widths.size(); ++q) {
+          boff[q] = q ? boff[q - 1] + widths[q - 1] : 0;
+          gauss_into(G.p + boff[q] * rows_in, rows_in, widths[q],
+                     make_tag(col_side ? PHASE_U0 : PHASE_V0, it + (int)q, 0));
+        }
+        Y = DevBuf<bf_c64>((size_t)rows_out * tot, s_);
+        call_op(!col_side, G.p, rows_in, tot, Y.p, rows_out, nullptr);
+        (col_side ? mv_cols_ : rmv_cols_) += tot;
+        bstart = it;
+        bend = it + (int)widths.size();
+      }
+      const bf_c64* Yp = Y.p + boff[(size_t)(it - bstart)] * rows_out;
       std::vector<QRDesc> d(nb());
       for (int64_t b = 0; b < nb(); ++b) {
         const int64_t lo = node_lo(rows_out, L(), b);
-        d[b] = QRDesc{Y.p + lo, nullptr, rows_out, (int32_t)node_size(rows_out, L(), b),
+        d[b] = QRDesc{Yp + lo, nullptr, rows_out, (int32_t)node_size(rows_out, L(), b),
                       (int32_t)s};
       }
       // the previous iteration's store is superseded
@@ -288,8 +321,13 @@ class Builder {
     }
   }
 
-  // Samples of one level per group, so that a group's black-box output and
-  // partial products (bytes_per_sample each) stay within the workspace bound.
+  // One pass's random block (level 0, one tag) into rows x ncols at X.
+  void gauss_into(bf_c64* X, int64_t rows, int64_t ncols, uint64_t tag) {
+    auto dt = upload(std::vector<uint64_t>{tag}, s_, st_);
+    auto dw = upload(std::vector<int32_t>{(int32_t)ncols}, s_, st_);
+    launch_gauss_samples(X, rows, ncols, 0, dt.p, dw.p, seed_, s_);
+  }
+
   int64_t group_size(int64_t nsamples, double bytes_per_sample) const {
     const double g = std::floor((double)work_ / std::max(bytes_per_sample, 1.0));
     return std::max<int64_t>(1, std::min<int64_t>(nsamples, (int64_t)std::min(g, 1e15)));
