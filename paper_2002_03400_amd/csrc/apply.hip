@@ -19,12 +19,18 @@ namespace bf {
 //  * ncols > 4 (blocked): one workgroup per (output block, 64-column chunk);
 //    the packed block and the input chunk are staged in LDS and each thread
 //    accumulates 4 rows of one column.
+// Element (row r, column c) of buffer i is p[i][r * rs[i] + c * ld[i]]: the
+// caller's buffers are column-major (rs = 1, ld = leading dimension); with
+// more than AP_SMALL columns the intermediates are row-major (rs = ncols,
+// ld = 1), so a block's rows for a 64-column chunk are contiguous 512-byte
+// runs instead of 64 scattered columns.
 struct ApplyBufs {
   bf_c64* p[4];
   int64_t ld[4];
+  int64_t rs[4];
 };
 
-constexpr int AP_SMALL = 4;
+constexpr int AP_SMALL = kApplyFewCols;
 
 // ncols <= 4: a group of 16 lanes per output row; the row's record holds
 // every address it needs (one dependent load), the inner loop is unrolled so
@@ -117,16 +123,18 @@ __global__ __launch_bounds__(256) void apply_blocked_kernel(const ApplyBlk* __re
     bf_c64 v = {0.f, 0.f};
     if (c < cw) {
       if (k < bk.K0)
-        v = B.p[bk.in_buf0][(c0 + c) * B.ld[bk.in_buf0] + bk.in_row0 + k];
+        v = B.p[bk.in_buf0][(c0 + c) * B.ld[bk.in_buf0] + (bk.in_row0 + k) * B.rs[bk.in_buf0]];
       else
-        v = B.p[bk.in_buf1][(c0 + c) * B.ld[bk.in_buf1] + bk.in_row1 + (k - bk.K0)];
+        v = B.p[bk.in_buf1][(c0 + c) * B.ld[bk.in_buf1] +
+                            (bk.in_row1 + (k - bk.K0)) * B.rs[bk.in_buf1]];
     }
     Xs[k * AP_CW + c] = cf{v.re, v.im};
   }
   __syncthreads();
   const int c = threadIdx.x % AP_CW;
   const int rg = threadIdx.x / AP_CW;    // 0..3
-  bf_c64* out = B.p[bk.out_buf] + (c0 + c) * B.ld[bk.out_buf] + bk.out_row;
+  const int64_t rso = B.rs[bk.out_buf];
+  bf_c64* out = B.p[bk.out_buf] + (c0 + c) * B.ld[bk.out_buf] + bk.out_row * rso;
   for (int rb = rg; rb < M; rb += 16) {  // rows rb, rb+4, rb+8, rb+12
     cf acc[4];
 #pragma unroll
@@ -143,7 +151,7 @@ __global__ __launch_bounds__(256) void apply_blocked_kernel(const ApplyBlk* __re
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int r = rb + 4 * j;
-        if (r < M) out[r] = bf_c64{acc[j].re, acc[j].im};
+        if (r < M) out[r * rso] = bf_c64{acc[j].re, acc[j].im};
       }
     }
   }
@@ -195,8 +203,9 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(const ApplyBlk* __restr
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, kq = lane >> 4;
   const bf_c64* gsrc = G + bk.g_off;
-  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0;
-  const bf_c64* in1 = B.p[bk.in_buf1] + bk.in_row1;
+  const int64_t rs0 = B.rs[bk.in_buf0], rs1 = B.rs[bk.in_buf1];
+  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0 * rs0;
+  const bf_c64* in1 = B.p[bk.in_buf1] + bk.in_row1 * rs1;
   const int64_t ld0 = B.ld[bk.in_buf0], ld1 = B.ld[bk.in_buf1];
   for (int rb = 0; rb < M; rb += AM_R) {
     const int mr = (M - rb < AM_R) ? M - rb : AM_R;
@@ -234,9 +243,9 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(const ApplyBlk* __restr
           for (int u = 0; u < 2; ++u) {
             const int kk = k0 + k + u;
             if (kk < K0)
-              v[u] = in0[(c0 + c) * ld0 + kk];
+              v[u] = in0[(c0 + c) * ld0 + kk * rs0];
             else if (kk < KK)
-              v[u] = in1[(c0 + c) * ld1 + (kk - K0)];
+              v[u] = in1[(c0 + c) * ld1 + (kk - K0) * rs1];
           }
         }
         uint32_t h, m, l;
@@ -278,13 +287,14 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(const ApplyBlk* __restr
     // 4 (l / 16) + v, column l % 16
     const int c = wave * 16 + lc;
     if (c < cw) {
-      bf_c64* out = B.p[bk.out_buf] + (c0 + c) * B.ld[bk.out_buf] + bk.out_row + rb;
+      const int64_t rso = B.rs[bk.out_buf];
+      bf_c64* out = B.p[bk.out_buf] + (c0 + c) * B.ld[bk.out_buf] + (bk.out_row + rb) * rso;
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = t * 16 + 4 * kq + v;
-          if (t < rt_n && r < mr) out[r] = bf_c64{R[t][v], I[t][v]};
+          if (t < rt_n && r < mr) out[r * rso] = bf_c64{R[t][v], I[t][v]};
         }
     }
   }
@@ -321,8 +331,9 @@ __global__ __launch_bounds__(256) void apply_mfma_small_kernel(const ApplyBlk* _
   const int M = bk.M, K0 = bk.K0, KK = bk.K0 + bk.K1;
   const int lc = lane & 15, kq = lane >> 4;
   const bf_c64* grow = G + bk.g_off + (int64_t)lc * KK;   // factor row lc (row-major M x KK)
-  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0;
-  const bf_c64* in1 = B.p[bk.in_buf1] + bk.in_row1 - K0;   // indexed by k >= K0
+  const int64_t rs0 = B.rs[bk.in_buf0], rs1 = B.rs[bk.in_buf1];
+  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0 * rs0;
+  const bf_c64* in1 = B.p[bk.in_buf1] + (bk.in_row1 - K0) * rs1;   // indexed by k >= K0
   const int64_t ld0 = B.ld[bk.in_buf0], ld1 = B.ld[bk.in_buf1];
   const int nct = (cw + 15) >> 4;
   afloatx4 R[4], I[4];
@@ -347,7 +358,7 @@ __global__ __launch_bounds__(256) void apply_mfma_small_kernel(const ApplyBlk* _
         for (int e = 0; e < 8; ++e) {
           const int k = kb + e;
           bf_c64 x = {0.f, 0.f};
-          if (c < cw && k < KK) x = k < K0 ? in0[col * ld0 + k] : in1[col * ld1 + k];
+          if (c < cw && k < KK) x = k < K0 ? in0[col * ld0 + k * rs0] : in1[col * ld1 + k * rs1];
           v[e] = x;
         }
         au32x4 xb[6];
@@ -364,7 +375,8 @@ __global__ __launch_bounds__(256) void apply_mfma_small_kernel(const ApplyBlk* _
     }
   }
   // 16x16 tile layout: lane l, register v -> row 4 (l / 16) + v, column l % 16
-  bf_c64* ob = B.p[bk.out_buf] + bk.out_row;
+  const int64_t rso = B.rs[bk.out_buf];
+  bf_c64* ob = B.p[bk.out_buf] + bk.out_row * rso;
   const int64_t ldo = B.ld[bk.out_buf];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -373,7 +385,7 @@ __global__ __launch_bounds__(256) void apply_mfma_small_kernel(const ApplyBlk* _
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 4 * kq + v;
-        if (r < M) ob[(c0 + c) * ldo + r] = bf_c64{R[t][v], I[t][v]};
+        if (r < M) ob[(c0 + c) * ldo + r * rso] = bf_c64{R[t][v], I[t][v]};
       }
     }
   }
@@ -411,15 +423,18 @@ void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* row
 
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
                         int32_t nrows, int32_t maxMK, int32_t maxKK, int32_t maxM, const bf_c64* G,
-                        const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
-                        int prec, hipStream_t s) {
+                        const bf_c64* const bufs[4], const int64_t lds[4], const int64_t rss[4],
+                        int64_t ncols, int prec, hipStream_t s) {
   if (nblk <= 0 || ncols <= 0) return;
   ApplyBufs B;
   for (int i = 0; i < 4; ++i) {
     B.p[i] = const_cast<bf_c64*>(bufs[i]);
     B.ld[i] = lds[i];
+    B.rs[i] = rss[i];
   }
   if (ncols <= AP_SMALL) {
+    // the row records address column-major buffers
+    for (int i = 0; i < 4; ++i) BF_CHECK(rss[i] == 1, BF_EINVAL, "few-column apply needs column-major buffers");
     const dim3 grid((unsigned)((nrows + 15) / 16));
     const int nc = (int)ncols;
 #define AP_STREAM(ACC, N) \

@@ -226,13 +226,18 @@ struct ApplyRowRec {
 // Writes the row records of every block (rows[b.row_rec + r], r < b.M).
 void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* rows_dev,
                         hipStream_t s);
-// maxMK / maxKK: largest M*(K0+K1) and K0+K1 over the stage's blocks.
-// prec: BF_PREC_BF16X3 runs stages of >= 16 right-hand sides on the BF16
-// matrix cores (split operands), anything else in FP32 on the vector ALUs.
+// Up to this many right-hand sides a stage runs the few-column kernel, whose
+// row records address column-major buffers.
+constexpr int kApplyFewCols = 4;
+// maxMK / maxKK / maxM: largest M*(K0+K1), K0+K1 and M over the stage's
+// blocks.  Buffer i holds element (r, c) at bufs[i][r * rss[i] + c * lds[i]]
+// (column-major: rss = 1; with at most kApplyFewCols columns every buffer must be).
+// prec: BF_PREC_BF16X3 runs stages of >= 5 right-hand sides on the BF16
+// matrix cores (split operands), anything else on the vector ALUs.
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
                         int32_t nrows, int32_t maxMK, int32_t maxKK, int32_t maxM, const bf_c64* G,
-                        const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
-                        int prec, hipStream_t s);
+                        const bf_c64* const bufs[4], const int64_t lds[4], const int64_t rss[4],
+                        int64_t ncols, int prec, hipStream_t s);
 
 // Gather (and optionally conjugate-transpose) factor sub-blocks into an
 // arena: element (r, k) of the M x K result goes to

@@ -282,7 +282,11 @@ void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
   if (ncols <= 0) return;
   DevBuf<bf_c64> t1((size_t)P.tmp_rows * ncols, s), t2((size_t)P.tmp_rows * ncols, s);
   const bf_c64* bufs[4] = {X, t1.p, t2.p, Y};
-  const int64_t lds[4] = {ldx, P.tmp_rows, P.tmp_rows, ldy};
+  // intermediates row-major above the few-column path (see launch_apply_stage)
+  const bool rowmajor = ncols > kApplyFewCols;
+  const int64_t tld = rowmajor ? 1 : P.tmp_rows, trs = rowmajor ? ncols : 1;
+  const int64_t lds[4] = {ldx, tld, tld, ldy};
+  const int64_t rss[4] = {1, trs, trs, 1};
   const int64_t rin = trans ? F->m : F->n, rout = trans ? F->n : F->m;
   for (size_t k = 0; k < P.stages.size(); ++k) {
     const Stage& st = P.stages[k];
@@ -293,7 +297,7 @@ void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
     if (k + 1 == P.stages.size()) by += 8.0 * (double)rout * ncols;
     ProfScope ps(BF_KC_APPLY, s, 8.0 * st.macs * ncols, by);
     launch_apply_stage(P.blks.p + st.blk_off, st.nblk, P.rows.p + st.row_off, st.nrows, st.maxMK,
-                       st.maxKK, st.maxM, P.G.p, bufs, lds, ncols, F->apply_prec, s);
+                       st.maxKK, st.maxM, P.G.p, bufs, lds, rss, ncols, F->apply_prec, s);
   }
 }
 
