@@ -12,12 +12,16 @@
 
 namespace bf {
 
-// Two work mappings, by right-hand-side count:
+// Work mappings, by right-hand-side count and arithmetic:
 //  * ncols <= 4 (streaming): a group of 16 lanes per output row splits the
 //    inner dimension, so each row of the packed block is read as contiguous
 //    bytes; partial sums are combined with shuffles inside the group.
-//  * ncols > 4 (blocked): one workgroup per (output block, 64-column chunk);
-//    the packed block and the input chunk are staged in LDS and each thread
+//  * ncols > 4, split-BF16 (default): BF16 matrix-core tiles per (output
+//    block, 64-column chunk), operands split into three BF16 terms; one wave
+//    per block when every block of the stage has at most 16 rows, else one
+//    workgroup per block with the operands staged in LDS.
+//  * ncols > 4, FP32: one workgroup per (output block, 64-column chunk); the
+//    packed block and the input chunk are staged in LDS and each thread
 //    accumulates 4 rows of one column.
 // Element (row r, column c) of buffer i is p[i][r * rs[i] + c * ld[i]]: the
 // caller's buffers are column-major (rs = 1, ld = leading dimension); with

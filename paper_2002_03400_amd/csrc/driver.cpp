@@ -10,7 +10,10 @@
 //      batched launch (FP64) and reads the ranks back (the one host sync of
 //      the level: the next level's widths depend on them).
 // The W sweep (row side) and the R sweep (column side) follow the paper's
-// order; B is computed with the last R level (l = l_m).
+// order; B is computed with the last R level (l = l_m), or, when the centre
+// sits on the row leaves (l_m = L), from one full-height sample afterwards.
+// The passes of the adaptive leaf loops are merged into shared black-box
+// calls where their widths allow (same products, fewer entry sweeps).
 //
 // Readings of the paper taken here (the CPU oracle takes the same ones):
 // conjugate transposes for complex data; Alg. 1's tolerance is the relative

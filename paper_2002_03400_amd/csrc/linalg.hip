@@ -4,8 +4,10 @@
 //                 R^H Z for the centre blocks);
 //  * cpqr       : truncated column-pivoted Householder QR (Alg. 1 step 3);
 //  * lsq        : centre blocks B = C X^+ (eq. Bij, read from its argmin).
-// One workgroup per block; blocks are ragged and described by host-built
-// descriptor arrays.  All arithmetic is FP64.
+// Blocks are ragged and described by host-built descriptor arrays; one
+// workgroup per block (QR, least squares, chain products with blocks of more
+// than 16 rows) or one wave per block (chain products of smaller blocks).
+// All arithmetic is FP64.
 #include "bf_internal.h"
 #include "cplx.h"
 
