@@ -57,3 +57,33 @@ def test_error_codes_match_header():
     codes = dict((k, int(v)) for k, v in re.findall(r"(BF_E[A-Z]+)\s*=\s*(-\d+)", text))
     assert codes == {"BF_EINVAL": -1, "BF_ENOMEM": -2, "BF_ECALLBACK": -3, "BF_ERANK": -4,
                      "BF_EHIP": -5, "BF_ENOTSUP": -6}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the public structs have the C compiler's sizes
+    and field offsets (a mismatch would pass garbage across the ABI)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"bf_opts": bf.bf_opts, "bf_info": bf.bf_info, "bf_operator": bf.bf_operator,
+               "bf_kernel_stats": bf.bf_kernel_stats, "bf_server_opts": bf.bf_server_opts,
+               "bf_request_info": bf.bf_request_info}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bf.h"', "int main(void) {"]
+    for name, py in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, py in structs.items():
+        assert got[(name, "size")] == C.sizeof(py), name
+        for fname, _ in py._fields_:
+            assert got[(name, fname)] == getattr(py, fname).offset, (name, fname)

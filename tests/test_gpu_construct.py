@@ -275,3 +275,16 @@ def test_merged_leaf_passes_same_result(bf):
     assert np.array_equal(a, b)
     assert (ia.v_iters, ia.u_iters) == (ib.v_iters, ib.u_iters) and ia.v_iters >= 3
     assert ia.matvec_cols >= ib.matvec_cols and ia.rmatvec_cols >= ib.rmatvec_cols
+
+
+def test_unknown_option_flags_rejected(bf):
+    """bf_opts.flags bits the library does not know are an argument error, not
+    silently ignored."""
+    import ctypes as C
+    g = wl.segment_pair(256, ppw=8.0)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    o = bf.bf_opts(2, 4, 0, 8, 0, 0)
+    h = C.c_void_p()
+    rc = bf.lib().bf_construct(op._op.matvec, op._op.rmatvec, op._op.user, op.m, op.n, 1e-6, 32,
+                               C.byref(o), None, C.byref(h))
+    assert rc == -1 and not h.value
