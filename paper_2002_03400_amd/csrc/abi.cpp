@@ -695,7 +695,7 @@ int bf_lsq_batched(int32_t nblk, const int32_t* kU, const int32_t* kV, const int
     for (int b = 0; b < nblk; ++b) {
       BF_CHECK(kU[b] >= 0 && kV[b] >= 0 && s_[b] >= kV[b], BF_EINVAL, "bad least-squares block");
       if (kU[b] == 0 || kV[b] == 0) continue;
-      d.push_back(LSDesc{C + coff[b], X + xoff[b], B + boff[b], kU[b], kV[b], kU[b], kV[b], s_[b], 0});
+      d.push_back(LSDesc{C + coff[b], X + xoff[b], B + boff[b], kU[b], kV[b], kU[b], kV[b], s_[b]});
       maxS = std::max(maxS, s_[b]);
       maxK = std::max(maxK, std::max(kU[b], kV[b]));
     }

@@ -155,6 +155,12 @@ void launch_gauss_f64(bf_c128* X, int64_t rows, int64_t ncols, int64_t row0, uin
 // Batched small complex GEMM with up to two terms:
 //   out[r, c] = sum_t sum_k op_t(F_t)[r, k] * in_t[k, c],   r < M, c < ncols,
 // op = 0: F is M x K column-major (ld f_ld); op = 1: F^H with F K x M.
+// Strided operands: element (row k, column c) of `in` is in[c * in_ld +
+// k * in_rs] and output (r, c) is out[c * out_ld + r * out_rs]; column-major
+// operands have a row stride of 1, the row-major intermediates of the sweeps
+// a column stride of 1.
+// (Row strides are sample widths or column counts, so 32 bits hold them; the
+// descriptors stay at 40 / 112 bytes, millions of them per construction.)
 struct GemmTerm {
   const bf_c128* F;
   const void* in;    // bf_c64* or bf_c128* (kernel template parameter)
@@ -162,7 +168,7 @@ struct GemmTerm {
   int32_t f_ld;
   int32_t K;
   int32_t op;
-  int32_t pad;
+  int32_t in_rs = 1;
 };
 struct GemmDesc {
   bf_c128* out;
@@ -170,7 +176,7 @@ struct GemmDesc {
   int32_t M;
   int32_t ncols;
   int32_t nterm;
-  int32_t pad;
+  int32_t out_rs = 1;
   GemmTerm t[2];
 };
 // in_c64: the inputs are complex64 (samples straight from the black box);
@@ -180,11 +186,12 @@ void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, 
 
 // Batched truncated column-pivoted QR (Alg. 1 step 3) on FP64.
 struct QRDesc {
-  const void* in;    // bf_c64* or bf_c128*
+  const void* in;    // bf_c64* or bf_c128*; element (i, j) at in[j * in_ld + i * in_rs]
   bf_c128* q;        // M x min(M,N) capacity, ld = M; first k columns written
   int64_t in_ld;
   int32_t M;
   int32_t N;
+  int64_t in_rs = 1;
 };
 void launch_cpqr(const QRDesc* d_dev, int32_t nblk, int32_t maxM, int32_t maxN, double tol,
                  bool in_c64, int32_t* ranks_dev, hipStream_t s);
@@ -192,10 +199,11 @@ void launch_cpqr(const QRDesc* d_dev, int32_t nblk, int32_t maxM, int32_t maxN, 
 // Batched centre blocks: B = C X^+ (least squares, eq. Bij read from its argmin).
 struct LSDesc {
   const bf_c128* C;  // kU x s, ld = ldc
-  const bf_c128* X;  // kV x s, ld = ldx
+  const bf_c128* X;  // kV x s: element (j, i) at X[i * ldx + j * rsx]
   bf_c128* B;        // kU x kV, ld = kU
   int64_t ldc, ldx;
-  int32_t kU, kV, s, pad;
+  int32_t kU, kV, s;
+  int32_t rsx = 1;
 };
 void launch_lsq(const LSDesc* d_dev, int32_t nblk, int32_t maxS, int32_t maxK, hipStream_t s);
 

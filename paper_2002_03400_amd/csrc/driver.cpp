@@ -42,9 +42,25 @@ inline uint64_t make_tag(uint64_t phase, uint64_t level, uint64_t node) {
 template <typename T>
 struct Tall {
   const T* base = nullptr;
-  int64_t ld = 0;
+  int64_t ld = 0;      // column stride
+  int64_t rs = 1;      // row stride (row-major views: the sample's width)
   std::vector<int64_t> roff;
+  const T* at(int64_t row) const { return base + row * rs; }
+  T* out_at(int64_t row) const { return const_cast<T*>(base + row * rs); }
 };
+
+// Chain-product operands on a view: rows [row, row + K) of every column.
+inline GemmTerm view_term(const bf_c128* F, const Tall<bf_c128>& v, int64_t row, int32_t f_ld,
+                          int32_t K) {
+  GemmTerm t{F, v.at(row), v.ld, f_ld, K, 1};
+  t.in_rs = (int32_t)v.rs;
+  return t;
+}
+inline void view_out(GemmDesc& g, const Tall<bf_c128>& v, int64_t row) {
+  g.out = v.out_at(row);
+  g.out_ld = v.ld;
+  g.out_rs = (int32_t)v.rs;
+}
 
 class Builder {
  public:
@@ -176,13 +192,15 @@ class Builder {
       const size_t isz = in_c64 ? sizeof(bf_c64) : sizeof(bf_c128);
       for (auto& x : d) {
         if (x.M <= 0 || x.ncols <= 0) continue;
-        check_extent(x.out, ((size_t)(x.ncols - 1) * x.out_ld + x.M) * sizeof(bf_c128), "gemm out");
+        check_extent(x.out, ((size_t)(x.ncols - 1) * x.out_ld + (size_t)(x.M - 1) * x.out_rs + 1) *
+                                sizeof(bf_c128), "gemm out");
         for (int t = 0; t < x.nterm; ++t) {
           const GemmTerm& T = x.t[t];
           if (T.K <= 0) continue;
           size_t fe = T.op == 0 ? (size_t)(T.K - 1) * T.f_ld + x.M : (size_t)(x.M - 1) * T.f_ld + T.K;
           check_extent(T.F, fe * sizeof(bf_c128), "gemm factor");
-          check_extent(T.in, ((size_t)(x.ncols - 1) * T.in_ld + T.K) * isz, "gemm input");
+          check_extent(T.in, ((size_t)(x.ncols - 1) * T.in_ld + (size_t)(T.K - 1) * T.in_rs + 1) * isz,
+                       "gemm input");
         }
       }
     }
@@ -209,7 +227,8 @@ class Builder {
     if (validating())
       for (auto& x : d) {
         if (x.M <= 0 || x.N <= 0) continue;
-        check_extent(x.in, ((size_t)(x.N - 1) * x.in_ld + x.M) * (in_c64 ? sizeof(bf_c64) : sizeof(bf_c128)),
+        check_extent(x.in, ((size_t)(x.N - 1) * x.in_ld + (size_t)(x.M - 1) * x.in_rs + 1) *
+                               (in_c64 ? sizeof(bf_c64) : sizeof(bf_c128)),
                      "cpqr input");
         check_extent(x.q, (size_t)x.M * std::min(x.M, x.N) * sizeof(bf_c128), "cpqr output");
       }
@@ -368,19 +387,22 @@ class Builder {
       DevBuf<bf_c64> Yp((size_t)n * ycols, s_);
       call_op(true, G.p, m, smax, Yp.p, n, &seg);
 
-      // V stage (shared by the group's samples): P0 = V^H Y', rows by leaf j
+      // V stage (shared by the group's samples): P0 = V^H Y', rows by leaf j,
+      // stored row-major (row stride ycols) so that a block's rows are
+      // contiguous for every later product
       DevBuf<bf_c128> P0buf((size_t)std::max<int64_t>(rows0, 1) * ycols, s_);
       {
         std::vector<GemmDesc> d;
         for (int64_t j = 0; j < nb(); ++j) {
           const Block& V = F_->V[j];
           GemmDesc g{};
-          g.out = P0buf.p + roff0[j];
-          g.out_ld = rows0;
+          g.out = P0buf.p + roff0[j] * ycols;
+          g.out_ld = 1;
+          g.out_rs = ycols;
           g.M = V.cols;
           g.ncols = (int32_t)ycols;
           g.nterm = 1;
-          g.t[0] = GemmTerm{V.p, Yp.p + node_lo(n, L(), j), n, V.rows, V.rows, 1, 0};
+          g.t[0] = GemmTerm{V.p, Yp.p + node_lo(n, L(), j), n, V.rows, V.rows, 1};
           if (g.M > 0) d.push_back(g);
         }
         gemm(d, true);
@@ -390,8 +412,9 @@ class Builder {
       // view[q] is sample i0 + q
       std::vector<Tall<bf_c128>> view(ng);
       for (int64_t q = 0; q < ng; ++q) {
-        view[q].base = P0buf.p + q * smax * rows0;
-        view[q].ld = rows0;
+        view[q].base = P0buf.p + q * smax;
+        view[q].ld = 1;
+        view[q].rs = ycols;
         view[q].roff = roff0;
       }
       std::vector<DevBuf<bf_c128>> keep;
@@ -405,12 +428,14 @@ class Builder {
           int64_t rows = 0;
           next[q].roff.resize(nSl);
           for (int64_t j = 0; j < nSl; ++j) { next[q].roff[j] = rows; rows += F_->kv(lp, ip, j); }
-          next[q].ld = std::max<int64_t>(rows, 1);
+          next[q].ld = 1;                    // row-major, rows x width
+          next[q].rs = width[i0 + q];
           base[q] = tot;
-          tot += next[q].ld * width[i0 + q];
+          tot += std::max<int64_t>(rows, 1) * width[i0 + q];
         }
         DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
         std::vector<GemmDesc> d;
+        d.reserve((size_t)(ng * nSl));
         for (int64_t q = 0; q < ng; ++q) {
           const int64_t ip = (i0 + q) >> (l - lp);
           next[q].base = buf.p + base[q];
@@ -419,15 +444,12 @@ class Builder {
             const int32_t ka = F_->kv(lp - 1, ip >> 1, 2 * j);
             const int32_t kb = F_->kv(lp - 1, ip >> 1, 2 * j + 1);
             GemmDesc g{};
-            g.out = const_cast<bf_c128*>(next[q].base) + next[q].roff[j];
-            g.out_ld = next[q].ld;
+            view_out(g, next[q], next[q].roff[j]);
             g.M = Wb.cols;
             g.ncols = width[i0 + q];
             g.nterm = 2;
-            g.t[0] = GemmTerm{Wb.p, view[q].base + view[q].roff[2 * j], view[q].ld, Wb.rows, ka, 1,
-                              0};
-            g.t[1] = GemmTerm{Wb.p + ka, view[q].base + view[q].roff[2 * j + 1], view[q].ld,
-                              Wb.rows, kb, 1, 0};
+            g.t[0] = view_term(Wb.p, view[q], view[q].roff[2 * j], Wb.rows, ka);
+            g.t[1] = view_term(Wb.p + ka, view[q], view[q].roff[2 * j + 1], Wb.rows, kb);
             if (g.M > 0) d.push_back(g);
           }
         }
@@ -443,8 +465,9 @@ class Builder {
         for (int64_t j = 0; j < nS; ++j) {
           const int64_t i = i0 + a;
           const int32_t M = F_->kv(l - 1, i >> 1, 2 * j) + F_->kv(l - 1, i >> 1, 2 * j + 1);
-          q[(size_t)(a * nS + j)] =
-              QRDesc{view[a].base + view[a].roff[2 * j], nullptr, view[a].ld, M, width[i]};
+          QRDesc qd{view[a].at(view[a].roff[2 * j]), nullptr, view[a].ld, M, width[i]};
+          qd.in_rs = view[a].rs;
+          q[(size_t)(a * nS + j)] = qd;
         }
       std::vector<Block> blocks;
       auto ranks = cpqr(q, false, blocks);
@@ -492,19 +515,21 @@ class Builder {
       DevBuf<bf_c64> Y((size_t)m * ycols, s_);
       call_op(false, Om.p, n, smax, Y.p, m, &seg);
 
-      // U^H stage (shared by the group's samples): PL rows by leaf i
+      // U^H stage (shared by the group's samples): PL rows by leaf i, stored
+      // row-major (row stride ycols)
       DevBuf<bf_c128> PL((size_t)std::max<int64_t>(rowsL, 1) * ycols, s_);
       {
         std::vector<GemmDesc> d;
         for (int64_t i = 0; i < nb(); ++i) {
           const Block& U = F_->U[i];
           GemmDesc g{};
-          g.out = PL.p + roffL[i];
-          g.out_ld = rowsL;
+          g.out = PL.p + roffL[i] * ycols;
+          g.out_ld = 1;
+          g.out_rs = ycols;
           g.M = U.cols;
           g.ncols = (int32_t)ycols;
           g.nterm = 1;
-          g.t[0] = GemmTerm{U.p, Y.p + node_lo(m, L(), i), m, U.rows, U.rows, 1, 0};
+          g.t[0] = GemmTerm{U.p, Y.p + node_lo(m, L(), i), m, U.rows, U.rows, 1};
           if (g.M > 0) d.push_back(g);
         }
         gemm(d, true);
@@ -513,8 +538,9 @@ class Builder {
       // view[q] is sample j0 + q
       std::vector<Tall<bf_c128>> view(ng);
       for (int64_t q = 0; q < ng; ++q) {
-        view[q].base = PL.p + q * smax * rowsL;
-        view[q].ld = rowsL;
+        view[q].base = PL.p + q * smax;
+        view[q].ld = 1;
+        view[q].rs = ycols;
         view[q].roff = roffL;
       }
       std::vector<DevBuf<bf_c128>> keep;
@@ -528,12 +554,14 @@ class Builder {
           int64_t rows = 0;
           next[q].roff.resize(nTl);
           for (int64_t i = 0; i < nTl; ++i) { next[q].roff[i] = rows; rows += F_->ku(lp, i, jp); }
-          next[q].ld = std::max<int64_t>(rows, 1);
+          next[q].ld = 1;                    // row-major, rows x width
+          next[q].rs = width[j0 + q];
           base[q] = tot;
-          tot += next[q].ld * width[j0 + q];
+          tot += std::max<int64_t>(rows, 1) * width[j0 + q];
         }
         DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
         std::vector<GemmDesc> d;
+        d.reserve((size_t)(ng * nTl));
         for (int64_t q = 0; q < ng; ++q) {
           const int64_t jp = (j0 + q) >> (lp - l);
           next[q].base = buf.p + base[q];
@@ -542,15 +570,12 @@ class Builder {
             const int32_t k1 = F_->ku(lp + 1, 2 * i, jp >> 1);
             const int32_t k2 = F_->ku(lp + 1, 2 * i + 1, jp >> 1);
             GemmDesc g{};
-            g.out = const_cast<bf_c128*>(next[q].base) + next[q].roff[i];
-            g.out_ld = next[q].ld;
+            view_out(g, next[q], next[q].roff[i]);
             g.M = Rb.cols;
             g.ncols = width[j0 + q];
             g.nterm = 2;
-            g.t[0] = GemmTerm{Rb.p, view[q].base + view[q].roff[2 * i], view[q].ld, Rb.rows, k1,
-                              1, 0};
-            g.t[1] = GemmTerm{Rb.p + k1, view[q].base + view[q].roff[2 * i + 1], view[q].ld,
-                              Rb.rows, k2, 1, 0};
+            g.t[0] = view_term(Rb.p, view[q], view[q].roff[2 * i], Rb.rows, k1);
+            g.t[1] = view_term(Rb.p + k1, view[q], view[q].roff[2 * i + 1], Rb.rows, k2);
             if (g.M > 0) d.push_back(g);
           }
         }
@@ -567,8 +592,9 @@ class Builder {
         for (int64_t q = 0; q < ng; ++q) {
           const int64_t j = j0 + q;
           const int32_t M = F_->ku(l + 1, 2 * i, j >> 1) + F_->ku(l + 1, 2 * i + 1, j >> 1);
-          zq[(size_t)(i * ng + q)] =
-              QRDesc{view[q].base + view[q].roff[2 * i], nullptr, view[q].ld, M, width[j]};
+          QRDesc qd{view[q].at(view[q].roff[2 * i]), nullptr, view[q].ld, M, width[j]};
+          qd.in_rs = view[q].rs;
+          zq[(size_t)(i * ng + q)] = qd;
         }
       std::vector<Block> blocks;
       auto ranks = cpqr(zq, false, blocks);
@@ -604,9 +630,10 @@ class Builder {
         view[q].roff[t] = rows;
         rows += F_->kv(0, 0, (j << lmv) + t);
       }
-      view[q].ld = std::max<int64_t>(rows, 1);
+      view[q].ld = 1;                        // row-major, rows x width
+      view[q].rs = width[j];
       base[q] = tot;
-      tot += view[q].ld * width[j];
+      tot += std::max<int64_t>(rows, 1) * width[j];
     }
     DevBuf<bf_c128> buf0((size_t)std::max<int64_t>(tot, 1), s_);
     {
@@ -618,12 +645,11 @@ class Builder {
           const int64_t jl = (j << lmv) + t;
           const Block& V = F_->V[jl];
           GemmDesc g{};
-          g.out = const_cast<bf_c128*>(view[q].base) + view[q].roff[t];
-          g.out_ld = view[q].ld;
+          view_out(g, view[q], view[q].roff[t]);
           g.M = V.cols;
           g.ncols = width[j];
           g.nterm = 1;
-          g.t[0] = GemmTerm{V.p, Om.p + node_lo(n, L(), jl), n, V.rows, V.rows, 1, 0};
+          g.t[0] = GemmTerm{V.p, Om.p + node_lo(n, L(), jl), n, V.rows, V.rows, 1};
           if (g.M > 0) d.push_back(g);
         }
       }
@@ -646,9 +672,10 @@ class Builder {
             next[q].roff[i * nSub + t] = rows;
             rows += F_->kv(lp, i, (j << (lmv - lp)) + t);
           }
-        next[q].ld = std::max<int64_t>(rows, 1);
+        next[q].ld = 1;                      // row-major, rows x width
+        next[q].rs = width[j];
         base[q] = tot;
-        tot += next[q].ld * width[j];
+        tot += std::max<int64_t>(rows, 1) * width[j];
       }
       DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
       std::vector<GemmDesc> d;
@@ -664,14 +691,12 @@ class Builder {
             // previous level's local indices: (i >> 1, 2t) and (i >> 1, 2t + 1)
             const int64_t pa = (lp == 1) ? 2 * t : (i >> 1) * nSubPrev + 2 * t;
             GemmDesc g{};
-            g.out = const_cast<bf_c128*>(next[q].base) + next[q].roff[i * nSub + t];
-            g.out_ld = next[q].ld;
+            view_out(g, next[q], next[q].roff[i * nSub + t]);
             g.M = Wb.cols;
             g.ncols = width[j];
             g.nterm = 2;
-            g.t[0] = GemmTerm{Wb.p, view[q].base + view[q].roff[pa], view[q].ld, Wb.rows, ka, 1, 0};
-            g.t[1] = GemmTerm{Wb.p + ka, view[q].base + view[q].roff[pa + 1], view[q].ld, Wb.rows,
-                              kb, 1, 0};
+            g.t[0] = view_term(Wb.p, view[q], view[q].roff[pa], Wb.rows, ka);
+            g.t[1] = view_term(Wb.p + ka, view[q], view[q].roff[pa + 1], Wb.rows, kb);
             if (g.M > 0) d.push_back(g);
           }
       }
@@ -713,7 +738,8 @@ class Builder {
           g.M = Rb.cols;
           g.ncols = width[j0 + q];
           g.nterm = 1;
-          g.t[0] = GemmTerm{Rb.p, zq[lb].in, zq[lb].in_ld, Rb.rows, Rb.rows, 1, 0};
+          g.t[0] = GemmTerm{Rb.p, zq[lb].in, zq[lb].in_ld, Rb.rows, Rb.rows, 1};
+          g.t[0].in_rs = (int32_t)zq[lb].in_rs;
           if (g.M > 0) d.push_back(g);
         }
       gemm(d, false);
@@ -748,8 +774,9 @@ class Builder {
         if (ku == 0 || kv == 0) continue;
         BF_CHECK(width[j] >= kv, BF_EINVAL, "centre sample narrower than the row rank");
         const Tall<bf_c128>& xv = xview[q];
-        LSDesc ls{C + coff[lb], xv.base + xv.roff[xblock(i, j)], Bst.p + boff[lb],
-                  (int64_t)std::max(ku, 1), xv.ld, ku, kv, width[j], 0};
+        LSDesc ls{C + coff[lb], xv.at(xv.roff[xblock(i, j)]), Bst.p + boff[lb],
+                  (int64_t)std::max(ku, 1), xv.ld, ku, kv, width[j]};
+        ls.rsx = (int32_t)xv.rs;
         d.push_back(ls);
         maxS = std::max(maxS, width[j]);
         maxK = std::max(maxK, std::max(ku, kv));
@@ -757,7 +784,8 @@ class Builder {
     if (validating())
       for (auto& x : d) {
         check_extent(x.C, ((size_t)(x.s - 1) * x.ldc + x.kU) * sizeof(bf_c128), "lsq C");
-        check_extent(x.X, ((size_t)(x.s - 1) * x.ldx + x.kV) * sizeof(bf_c128), "lsq X");
+        check_extent(x.X, ((size_t)(x.s - 1) * x.ldx + (size_t)(x.kV - 1) * x.rsx + 1) *
+                              sizeof(bf_c128), "lsq X");
         check_extent(x.B, (size_t)x.kU * x.kV * sizeof(bf_c128), "lsq B");
       }
     if (!d.empty()) {
@@ -801,7 +829,7 @@ class Builder {
       g.M = U.cols;
       g.ncols = s;
       g.nterm = 1;
-      g.t[0] = GemmTerm{U.p, Y.p + node_lo(m, L(), i), m, U.rows, U.rows, 1, 0};
+      g.t[0] = GemmTerm{U.p, Y.p + node_lo(m, L(), i), m, U.rows, U.rows, 1};
       if (g.M > 0) d.push_back(g);
     }
     gemm(d, true);

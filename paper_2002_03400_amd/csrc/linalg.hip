@@ -64,13 +64,13 @@ __device__ __forceinline__ void cg_stage(cd (*fs)[ROWS], const GemmTerm& T, int 
 }
 
 template <typename Tin, int ROWS>
-__device__ __forceinline__ void cg_accum(cd* acc, const cd (*fs)[ROWS], const Tin* ip, int kt,
-                                         int wave, int mr) {
+__device__ __forceinline__ void cg_accum(cd* acc, const cd (*fs)[ROWS], const Tin* ip, int64_t rs,
+                                         int kt, int wave, int mr) {
   int k = 0;
   for (; k + 4 <= kt; k += 4) {
     cd x[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = load_c<Tin>(ip + k + u);
+    for (int u = 0; u < 4; ++u) x[u] = load_c<Tin>(ip + (k + u) * rs);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -78,7 +78,7 @@ __device__ __forceinline__ void cg_accum(cd* acc, const cd (*fs)[ROWS], const Ti
         if (wave + 4 * i < mr) cd_fma(acc[i], fs[k + u][wave + 4 * i], x[u]);
   }
   for (; k < kt; ++k) {
-    const cd x = load_c<Tin>(ip + k);
+    const cd x = load_c<Tin>(ip + k * rs);
 #pragma unroll
     for (int i = 0; i < ROWS / 4; ++i)
       if (wave + 4 * i < mr) cd_fma(acc[i], fs[k][wave + 4 * i], x);
@@ -111,14 +111,15 @@ __global__ __launch_bounds__(256) void chain_gemm_kernel(const GemmDesc* __restr
           __syncthreads();
           cg_stage<ROWS, KT>(fs, T, rb, mr, k0, kt);
           __syncthreads();
-          cg_accum<Tin, ROWS>(acc, fs, inp + k0, kt, wave, mr);
+          cg_accum<Tin, ROWS>(acc, fs, inp + k0 * T.in_rs, T.in_rs, kt, wave, mr);
         }
       }
       if (live) {
-        bf_c128* o = d.out + (int64_t)c * d.out_ld + rb;
+        const int64_t ors = d.out_rs;
+        bf_c128* o = d.out + (int64_t)c * d.out_ld + rb * ors;
 #pragma unroll
         for (int i = 0; i < ROWS / 4; ++i)
-          if (wave + 4 * i < mr) o[wave + 4 * i] = bf_c128{acc[i].re, acc[i].im};
+          if (wave + 4 * i < mr) o[(wave + 4 * i) * ors] = bf_c128{acc[i].re, acc[i].im};
       }
     }
   }
@@ -168,18 +169,20 @@ __global__ __launch_bounds__(256) void chain_small_kernel(const GemmDesc* __rest
       const Tin* ip[CS_TC];
 #pragma unroll
       for (int u = 0; u < CS_TC; ++u) ip[u] = in + (int64_t)col[u] * T.in_ld;
+      const int64_t rs = T.in_rs;
 #pragma unroll 2
       for (int k = 0; k < T.K; ++k) {
         const bf_c128 fv = fp[(int64_t)k * fs];
         const cd f{fv.re, sg * fv.im};
 #pragma unroll
         for (int u = 0; u < CS_TC; ++u)
-          if (CG * u < ncc) cd_fma(acc[u], f, load_c<Tin>(ip[u] + k));
+          if (CG * u < ncc) cd_fma(acc[u], f, load_c<Tin>(ip[u] + k * rs));
       }
     }
 #pragma unroll
     for (int u = 0; u < CS_TC; ++u)
-      if (live[u]) d.out[(int64_t)col[u] * d.out_ld + r] = bf_c128{acc[u].re, acc[u].im};
+      if (live[u])
+        d.out[(int64_t)col[u] * d.out_ld + (int64_t)r * d.out_rs] = bf_c128{acc[u].re, acc[u].im};
   }
 }
 
@@ -283,9 +286,16 @@ __global__ __launch_bounds__(NT) void cpqr_kernel(const QRDesc* __restrict__ des
   cd* A = use_lds ? reinterpret_cast<cd*>(reinterpret_cast<char*>(sh) + 64)
                   : reinterpret_cast<cd*>(gscratch + (int64_t)blockIdx.x * scratch_slot);
   const Tin* in = static_cast<const Tin*>(d.in);
-  for (int idx = tid; idx < M * N; idx += NT) {
-    int i = idx % M, j = idx / M;
-    A[idx] = load_c<Tin>(in + (int64_t)j * d.in_ld + i);
+  if (d.in_rs == 1) {        // column-major input: consecutive threads, consecutive rows
+    for (int idx = tid; idx < M * N; idx += NT) {
+      int i = idx % M, j = idx / M;
+      A[idx] = load_c<Tin>(in + (int64_t)j * d.in_ld + i);
+    }
+  } else {                   // row-major input: consecutive threads, consecutive columns
+    for (int idx = tid; idx < M * N; idx += NT) {
+      int j = idx % N, i = idx / N;
+      A[(int64_t)j * M + i] = load_c<Tin>(in + (int64_t)j * d.in_ld + (int64_t)i * d.in_rs);
+    }
   }
   __syncthreads();
   // initial column norms (wave per column) and the total
@@ -463,7 +473,7 @@ __global__ __launch_bounds__(NT) void lsq_kernel(const LSDesc* __restrict__ desc
   cd* CH = XH + (int64_t)S * KV;           // C^H, S x KU, ld S
   for (int idx = tid; idx < S * KV; idx += NT) {
     int i = idx % S, j = idx / S;          // XH[i, j] = conj(X[j, i])
-    bf_c128 x = d.X[(int64_t)i * d.ldx + j];
+    bf_c128 x = d.X[(int64_t)i * d.ldx + (int64_t)j * d.rsx];
     XH[idx] = cd{x.re, -x.im};
   }
   for (int idx = tid; idx < S * KU; idx += NT) {
