@@ -122,7 +122,7 @@ typedef struct {
 /* BF_OPT_CENTER_LEVEL: use center_level.
  * BF_OPT_SEQUENTIAL_LEAF: one black-box call per pass of the adaptive leaf
  *   loops.  By default consecutive passes (each with its own fixed random
- *   block) share one call while their widths add up to at most 48 columns,
+ *   block) share one call while their widths add up to at most 80 columns,
  *   which returns the same products in fewer calls; when the loop stops
  *   before a merged pass, that pass's columns are wasted (and counted in
  *   bf_info's column totals). */

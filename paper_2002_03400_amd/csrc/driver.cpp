@@ -273,12 +273,13 @@ class Builder {
   // ---- adaptive leaf loops (first two loops of Alg. 2) ---------------------
   // Every pass draws a fresh random block whose values are fixed in advance
   // (its own tag), so consecutive passes are merged into one black-box call
-  // while their widths add up to at most LEAF_BATCH_COLS: a built-in product
-  // evaluates each matrix entry once per call, whatever the width.  Merging
+  // while their widths add up to at most LEAF_BATCH_COLS (the widest tile of
+  // the built-in split-BF16 products, which evaluate each matrix entry once
+  // per call up to that width; r = 4, 8, 16, 32 at p = 2 take 68 columns).  Merging
   // changes only how the products are grouped into calls, not their values;
   // a pass the loop does not reach wastes its columns (counted in the stats).
   // BF_OPT_SEQUENTIAL_LEAF makes one call per pass.
-  static constexpr int64_t LEAF_BATCH_COLS = 48;
+  static constexpr int64_t LEAF_BATCH_COLS = 80;
 
   void leaf_loop(bool col_side) {
     const int64_t rows_in = col_side ? F_->n : F_->m;   // rows of the random block

@@ -5,7 +5,9 @@
 // samples: group g is the product with the random block living on node g).
 //
 // Layout: one workgroup of 8 waves owns 128 output rows of one group, up to
-// 48 columns, and one slice of the group's inner range (split-K when there
+// 48 (FP64 path) or 80 (split-BF16 path) columns, every matrix entry being
+// evaluated once for all of them, and one slice of the group's inner range
+// (split-K when there
 // are too few row tiles to fill 256 CUs); chunks of TK inner points (their
 // coordinates and the TK x 64 block of X) are staged in LDS.  Split-K
 // partials go to an FP64 scratch buffer and are summed in a fixed order
@@ -364,12 +366,15 @@ __global__ void split_planes_kernel(const bf_c64* __restrict__ X, int64_t ldx,
 // blocks of Alg. 2, so x = x1 and a real product needs the three MFMAs
 // a1x1 + a2x1 + a3x1) and general (six).  Both are launched; the one that
 // does not match the flag written by split_planes_kernel exits at once.
-// Four waves per SIMD (at most 128 VGPRs): for the 48- and 64-column tiles
-// of the general path this costs a few spilled registers outside the inner
-// loop and is still ~25% faster than the two waves their unconstrained
-// register count allows.
+// Four waves per SIMD (at most 128 VGPRs) up to 64 columns: for the 48- and
+// 64-column tiles of the general path this costs a few spilled registers
+// outside the inner loop and is still ~25% faster than the two waves their
+// unconstrained register count allows.  The 80-column tile (NT = 5) keeps its
+// ~160 registers (two waves per SIMD): its entries serve 25% more columns,
+// which outweighs the lower occupancy where a call would otherwise need a
+// second entry sweep.
 template <class E, int NT, typename Tout, bool EXACT>
-__global__ __launch_bounds__(64 * BF_WAVES) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ __launch_bounds__(64 * BF_WAVES) __attribute__((amdgpu_waves_per_eu(NT > 4 ? 3 : 4, 8)))
 void matfree_bf16_kernel(
     E e, int64_t nout, const uint16_t* __restrict__ Xp, int64_t kpad, int32_t ncols, int32_t c0,
     int32_t width, Tout* __restrict__ Y, int64_t ldy, int64_t ycols,
@@ -565,8 +570,11 @@ static void launch_chunk_bf16(const E& e, int64_t nout, const uint16_t* Xp, int6
   else if (width <= 48)
     launch_bf16<E, 3>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
                       nsplit, inexact, s);
-  else
+  else if (width <= 64)
     launch_bf16<E, 4>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
+                      nsplit, inexact, s);
+  else
+    launch_bf16<E, 5>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
                       nsplit, inexact, s);
 }
 
@@ -641,7 +649,7 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
 
   DevBuf<bf_c128> part;
   if (nsplit > 1) part = DevBuf<bf_c128>((size_t)nsplit * ycols * nout, s);
-  const int64_t maxw = bf16 ? 64 : 48;
+  const int64_t maxw = bf16 ? 80 : 48;
   const int64_t nchunk = (ncols + maxw - 1) / maxw;
   const int64_t cw = (ncols + nchunk - 1) / nchunk;   // balanced widths <= maxw
   for (int64_t c0 = 0; c0 < ncols; c0 += cw) {

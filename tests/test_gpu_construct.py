@@ -235,10 +235,11 @@ def test_centre_level_variants(bf, center, lm):
     np.testing.assert_allclose(H.apply(_t(X), trans=True).cpu().numpy(), ref,
                                atol=2e-6 * np.abs(ref).max())
     # black-box columns: equal up to the widths' dependence on ranks (+-2) and
-    # the merged leaf passes the loop did not reach (at most 10 + 18 columns)
+    # the merged leaf passes the loop did not reach (at most 10 + 18 + 34
+    # columns after the first pass of r0 = 4, p = 2)
     info = H.stats()
     for got, ref in ((info.matvec_cols, Fo.stats["matvec"]), (info.rmatvec_cols, Fo.stats["rmatvec"])):
-        assert 0.95 * ref <= got <= 1.05 * ref + 28
+        assert 0.95 * ref <= got <= 1.05 * ref + 62
 
 
 @pytest.mark.parametrize("center", ["column", "row"])
