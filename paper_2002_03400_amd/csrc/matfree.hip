@@ -320,6 +320,10 @@ constexpr int BF_TK = 64;            // inner points per staged chunk (4 MFMA st
 constexpr int BF_KP = BF_TK + 8;     // padded k stride of the split planes (bank spread)
 constexpr int BF_WAVES = 8;
 constexpr int BF_ROWS = 16 * BF_WAVES;
+// The 80-column tile runs four waves per workgroup (64 rows) so that three of
+// its ~160-register workgroups fit on a CU (the split-K slicing still follows
+// BF_ROWS, so results do not depend on the tile width).
+template <int NT> constexpr int bf_waves() { return NT > 4 ? 4 : BF_WAVES; }
 constexpr int BF_PLANES = 6;         // (term 0..2) x (re, im)
 
 // Xp[(c * 6 + 2 term + part) * kpad + pofs[g] + (j - seg[g])] = term of
@@ -370,11 +374,11 @@ __global__ void split_planes_kernel(const bf_c64* __restrict__ X, int64_t ldx,
 // 64-column tiles of the general path this costs a few spilled registers
 // outside the inner loop and is still ~25% faster than the two waves their
 // unconstrained register count allows.  The 80-column tile (NT = 5) keeps its
-// ~160 registers (two waves per SIMD): its entries serve 25% more columns,
-// which outweighs the lower occupancy where a call would otherwise need a
-// second entry sweep.
+// ~160 registers in four-wave workgroups (three waves per SIMD): its entries
+// serve 25% more columns, so one call replaces the two a 68-column block
+// would otherwise need.
 template <class E, int NT, typename Tout, bool EXACT>
-__global__ __launch_bounds__(64 * BF_WAVES) __attribute__((amdgpu_waves_per_eu(NT > 4 ? 3 : 4, 8)))
+__global__ __launch_bounds__(64 * bf_waves<NT>()) __attribute__((amdgpu_waves_per_eu(NT > 4 ? 3 : 4, 8)))
 void matfree_bf16_kernel(
     E e, int64_t nout, const uint16_t* __restrict__ Xp, int64_t kpad, int32_t ncols, int32_t c0,
     int32_t width, Tout* __restrict__ Y, int64_t ldy, int64_t ycols,
@@ -389,7 +393,8 @@ void matfree_bf16_kernel(
   const int g = blockIdx.y;
   const int z = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t row0 = (int64_t)blockIdx.x * BF_ROWS + wave * 16;
+  constexpr int NW = bf_waves<NT>();
+  const int64_t row0 = (int64_t)blockIdx.x * (16 * NW) + wave * 16;
   const int64_t myrow = row0 + (lane & 15);
   const int kq = lane >> 4;       // which 8 of the step's 32 inner points
   const int lc = lane & 15;
@@ -412,7 +417,7 @@ void matfree_bf16_kernel(
   for (int64_t jb = a; jb < b; jb += BF_TK) {
     __syncthreads();
     // NC columns x (2 NTERM) planes x 8 copies of 16 bytes
-    for (int idx = threadIdx.x; idx < NC * 2 * NTERM * 8; idx += 64 * BF_WAVES) {
+    for (int idx = threadIdx.x; idx < NC * 2 * NTERM * 8; idx += 64 * NW) {
       const int q8 = idx & 7, pl = (idx >> 3) % (2 * NTERM), c = (idx >> 3) / (2 * NTERM);
       u32x4 v = {0u, 0u, 0u, 0u};
       if (c < nc)
@@ -541,15 +546,16 @@ static void launch_bf16(const E& e, int64_t nout, const uint16_t* Xp, int64_t kp
                         int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
                         const int64_t* seg_dev, const int64_t* pofs_dev, int32_t nseg,
                         int32_t nsplit, const unsigned long long* inexact, hipStream_t s) {
-  dim3 grid((unsigned)((nout + BF_ROWS - 1) / BF_ROWS), (unsigned)nseg, (unsigned)nsplit);
+  constexpr int NW = bf_waves<NT>();
+  dim3 grid((unsigned)((nout + 16 * NW - 1) / (16 * NW)), (unsigned)nseg, (unsigned)nsplit);
   const double nc = (double)std::min<int32_t>(16 * NT, width);
   const double nin = (double)g_matfree_nin;
   ProfScope ps(BF_KC_MATFREE, s, 8.0 * (double)nout * nin * nc,
                8.0 * nc * (nin + (double)nout * nseg));
-  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout, true>), grid, dim3(64 * BF_WAVES), 0, s, e,
+  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout, true>), grid, dim3(64 * NW), 0, s, e,
                      nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nsplit,
                      inexact);
-  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout, false>), grid, dim3(64 * BF_WAVES), 0, s, e,
+  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout, false>), grid, dim3(64 * NW), 0, s, e,
                      nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nsplit,
                      inexact);
   BF_HIP(hipGetLastError());
