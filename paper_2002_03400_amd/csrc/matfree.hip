@@ -316,8 +316,12 @@ __device__ __forceinline__ void split3_pk(float x0, float x1, uint32_t& h, uint3
   l = pk_bf16(r0 - __uint_as_float(m << 16), r1 - __uint_as_float(m & 0xffff0000u));
 }
 
-constexpr int BF_TK = 64;            // inner points per staged chunk (4 MFMA steps)
-constexpr int BF_KP = BF_TK + 8;     // padded k stride of the split planes (bank spread)
+// Inner points per staged chunk: 128 (four MFMA steps between barriers) when
+// X is exact in BF16 and only its first term is staged, 64 for the three
+// terms of a general X (keeps two eight-wave workgroups per CU).  Segments
+// of the split planes are padded to the larger one.
+constexpr int BF_TK = 128;
+template <bool EXACT> constexpr int bf_tk() { return EXACT ? 128 : 64; }
 constexpr int BF_WAVES = 8;
 constexpr int BF_ROWS = 16 * BF_WAVES;
 // The 80-column tile runs four waves per workgroup (64 rows) so that three of
@@ -387,9 +391,11 @@ void matfree_bf16_kernel(
   if ((*inexact == 0ull) != EXACT) return;
   constexpr int NC = 16 * NT;
   constexpr int NTERM = EXACT ? 1 : 3;      // staged terms of X
-  __shared__ typename E::Col cols[BF_TK];
+  constexpr int TK = bf_tk<EXACT>();
+  constexpr int KP = TK + 8;                // padded k stride (bank spread)
+  __shared__ typename E::Col cols[TK];
   // split planes: [term][re/im][column][k], 16 bytes = 8 consecutive k
-  __shared__ __attribute__((aligned(16))) uint16_t xs[NTERM][2][NC][BF_KP];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[NTERM][2][NC][KP];
   const int g = blockIdx.y;
   const int z = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -401,7 +407,7 @@ void matfree_bf16_kernel(
   const int64_t j0 = seg[g], j1 = seg[g + 1];
   const int64_t len = j1 - j0;
   // split-K slices are whole chunks, so only a segment's last chunk is ragged
-  const int64_t chunk = ((len + nsplit - 1) / nsplit + BF_TK - 1) / BF_TK * BF_TK;
+  const int64_t chunk = ((len + nsplit - 1) / nsplit + TK - 1) / TK * TK;
   const int64_t a = j0 + (int64_t)z * chunk;
   const int64_t b = (a + chunk < j1) ? a + chunk : j1;
   const int nc = width < NC ? width : NC;
@@ -414,22 +420,23 @@ void matfree_bf16_kernel(
     for (int v = 0; v < 4; ++v) { fr[t][v] = 0.0; fi[t][v] = 0.0; }
   const typename E::Row rw = e.row(myrow < nout ? myrow : nout - 1);
 
-  for (int64_t jb = a; jb < b; jb += BF_TK) {
+  for (int64_t jb = a; jb < b; jb += TK) {
     __syncthreads();
-    // NC columns x (2 NTERM) planes x 8 copies of 16 bytes
-    for (int idx = threadIdx.x; idx < NC * 2 * NTERM * 8; idx += 64 * NW) {
-      const int q8 = idx & 7, pl = (idx >> 3) % (2 * NTERM), c = (idx >> 3) / (2 * NTERM);
+    // NC columns x (2 NTERM) planes x TK/8 copies of 16 bytes
+    constexpr int NQ = TK / 8;
+    for (int idx = threadIdx.x; idx < NC * 2 * NTERM * NQ; idx += 64 * NW) {
+      const int q8 = idx % NQ, pl = (idx / NQ) % (2 * NTERM), c = (idx / NQ) / (2 * NTERM);
       u32x4 v = {0u, 0u, 0u, 0u};
       if (c < nc)
         v = *reinterpret_cast<const u32x4*>(xg + ((int64_t)c * BF_PLANES + pl) * kpad + jb + 8 * q8);
       *reinterpret_cast<u32x4*>(&xs[pl >> 1][pl & 1][c][8 * q8]) = v;
     }
-    if (threadIdx.x < BF_TK) {
+    if (threadIdx.x < TK) {
       const int64_t j = jb + threadIdx.x;
       cols[threadIdx.x] = e.col(j < j1 ? j : j1 - 1);
     }
     __syncthreads();
-    const int nsteps = (int)((b - jb < BF_TK ? b - jb : BF_TK) + 31) >> 5;
+    const int nsteps = (int)((b - jb < TK ? b - jb : TK) + 31) >> 5;
     for (int q = 0; q < nsteps; ++q) {
       const int kb = 32 * q + 8 * kq;
       cf ev[8];
