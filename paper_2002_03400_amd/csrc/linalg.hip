@@ -577,8 +577,8 @@ void launch_c128_to_c64(const bf_c128* in, bf_c64* out, int64_t n, hipStream_t s
 }
 
 __global__ void expand_segments_kernel(const bf_c64* X, int64_t ldx, int64_t rows, int64_t ncols,
-                                       const int64_t* seg, int32_t nseg, bf_c64* out,
-                                       int64_t ldo) {
+                                       const int64_t* seg, int32_t /*nseg: grid y / ncols*/,
+                                       bf_c64* out, int64_t ldo) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t col = blockIdx.y;           // 0 .. nseg*ncols-1
   if (r >= rows) return;

@@ -378,11 +378,13 @@ __global__ void split_planes_kernel(const bf_c64* __restrict__ X, int64_t ldx,
 // 64-column tiles of the general path this costs a few spilled registers
 // outside the inner loop and is still ~25% faster than the two waves their
 // unconstrained register count allows.  The 80-column tile (NT = 5) keeps its
-// ~160 registers in four-wave workgroups (three waves per SIMD): its entries
-// serve 25% more columns, so one call replaces the two a 68-column block
-// would otherwise need.
+// ~160 registers in four-wave workgroups (three waves per SIMD; two on the
+// general path, whose three staged terms need ~250): its entries serve 25%
+// more columns, so one call replaces the two a 68-column block would
+// otherwise need.
 template <class E, int NT, typename Tout, bool EXACT>
-__global__ __launch_bounds__(64 * bf_waves<NT>()) __attribute__((amdgpu_waves_per_eu(NT > 4 ? 3 : 4, 8)))
+__global__ __launch_bounds__(64 * bf_waves<NT>())
+__attribute__((amdgpu_waves_per_eu(NT > 4 ? (EXACT ? 3 : 2) : 4, 8)))
 void matfree_bf16_kernel(
     E e, int64_t nout, const uint16_t* __restrict__ Xp, int64_t kpad, int32_t ncols, int32_t c0,
     int32_t width, Tout* __restrict__ Y, int64_t ldy, int64_t ycols,

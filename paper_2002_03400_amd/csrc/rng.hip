@@ -51,8 +51,9 @@ __device__ __forceinline__ double round_bf16(double x) {
 }
 
 // One thread per entry of a column: grid (ceil(rows/256), ncols).
-__global__ void gauss_samples_kernel(bf_c64* X, int64_t rows, int64_t ncols, int32_t level,
-                                     const uint64_t* tags, const int32_t* widths, uint64_t seed) {
+__global__ void gauss_samples_kernel(bf_c64* X, int64_t rows, int64_t /*ncols: grid y*/,
+                                     int32_t level, const uint64_t* tags, const int32_t* widths,
+                                     uint64_t seed) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t c = blockIdx.y;
   if (r >= rows) return;
