@@ -62,6 +62,13 @@ def parse():
                     help="requests of the Poisson stream at the headline size (0 = skip)")
     ap.add_argument("--mix", type=int, default=0,
                     help="also run the mixed serving stream with this many requests")
+    ap.add_argument("--apply-burst", type=int, default=0,
+                    help="only submit this many 1-column applies at once against one "
+                         "factorization of the headline operator, with and without continuous "
+                         "batching (--batch-cols), and print one JSON line")
+    ap.add_argument("--batch-cols", type=int, default=64,
+                    help="continuous batching of the mixed stream's applies (columns per "
+                         "merged product; 0 = off)")
     ap.add_argument("--exact-scaling", default="",
                     help="only recover exact random butterflies (Sec. 6.1) through the "
                          "butterfly black box: comma-separated entries L or L:r:leaf "
@@ -215,6 +222,41 @@ def variants(sizes, leaf=64, tol=1e-6):
         op.close()
 
 
+def apply_burst(args):
+    """K one-column applies against one factorization of the headline operator
+    (n = 65536), queued behind its construction: the time from the
+    construction's completion until the last apply finished (server clock),
+    and each apply's wait after that point, without and with continuous
+    batching in the request engine."""
+    import torch
+
+    import paper_2002_03400_amd as bf
+    import workloads as wl
+    torch.cuda.init()
+    g = wl.segment_pair(args.n, ppw=args.ppw)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    out = {"workload": f"{args.apply_burst} one-column applies queued behind a construction, "
+                       f"segment kernel n={args.n}"}
+    xs = [torch.randn(args.n, 1, dtype=torch.complex64, device="cuda")
+          for _ in range(args.apply_burst)]
+    torch.cuda.synchronize()
+    for bc in (0, args.batch_cols):
+        for rep in range(2):      # the first round warms the kernels up
+            S = bf.Server(slots=args.slots, batch_cols=bc)
+            tf = S.submit_construct(op, args.tol, args.leaf, seed=3)
+            ts = [S.submit_apply(tf, x) for x in xs]
+            done = S.wait(tf)["finish_ns"]
+            infos = [S.wait(t) for t in ts]
+            S.close()
+        drain = (max(i["finish_ns"] for i in infos) - done) * 1e-9
+        lat = [(i["finish_ns"] - max(done, i["arrival_ns"])) * 1e-9 for i in infos]
+        out[f"batch_cols={bc}"] = {
+            "drain_ms": 1e3 * drain, "applies_per_s": args.apply_burst / max(drain, 1e-9),
+            "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99),
+            "mean_batch": sum(i["batch"] for i in infos) / len(infos)}
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """Three dispatches of a plain 1 GiB device-to-device copy (torch copy_)."""
     import torch
@@ -343,14 +385,14 @@ def apply_roofline(bf, F, n, reps=20):
     return out
 
 
-def run_served(bf, reqs, slots, leaf, keep_last=False):
+def run_served(bf, reqs, slots, leaf, keep_last=False, batch_cols=0):
     """Replay a request stream in real time through the request engine.
     Returns (wall seconds, [latency s of constructions], [latency s of applies],
     last factors or None)."""
     import torch
 
     import workloads as wl
-    S = bf.Server(slots=slots)
+    S = bf.Server(slots=slots, batch_cols=batch_cols)
     ops_ = {}
     tickets = {}
     start = time.perf_counter()
@@ -370,10 +412,13 @@ def run_served(bf, reqs, slots, leaf, keep_last=False):
             X = torch.randn(n, r.nrhs, dtype=torch.complex64, device="cuda")
             tickets[i] = S.submit_apply(tickets[r.target], X)
     lat_c, lat_a = [], []
+    merged = 0
     for i, r in enumerate(reqs):
         info = S.wait(tickets[i])
         (lat_c if r.kind == "construct" else lat_a).append(
             (info["finish_ns"] - info["arrival_ns"]) * 1e-9)
+        merged += r.kind != "construct" and info["batch"] > 1
+    S.merged_applies = merged
     wall = time.perf_counter() - start
     last = None
     if keep_last:
@@ -390,6 +435,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.apply_burst:
+        apply_burst(args)
         return
     if args.variants:
         variants([int(x) for x in args.variants.split(",")])
@@ -457,12 +505,14 @@ def main():
     mix = None
     if args.mix > 0:
         reqs = wl.mixed_stream(args.mix)
-        S, wall_m, lat_mc, lat_ma, _ = run_served(bf, reqs, args.slots, args.leaf)
+        S, wall_m, lat_mc, lat_ma, _ = run_served(bf, reqs, args.slots, args.leaf,
+                                                  batch_cols=args.batch_cols)
         S.close()
         mix = {"requests": args.mix, "constructions": len(lat_mc), "applies": len(lat_ma),
                "wall_s": wall_m, "factorizations_per_s": len(lat_mc) / wall_m,
                "construct_p50_ms": 1e3 * pct(lat_mc, 50), "construct_p99_ms": 1e3 * pct(lat_mc, 99),
-               "apply_p50_ms": 1e3 * pct(lat_ma, 50), "apply_p99_ms": 1e3 * pct(lat_ma, 99)}
+               "apply_p50_ms": 1e3 * pct(lat_ma, 50), "apply_p99_ms": 1e3 * pct(lat_ma, 99),
+               "batch_cols": args.batch_cols, "merged_applies": S.merged_applies}
 
     rel_err, cpu = cpu_baseline_leg(geom, last, args, passes)
     apply_rl = apply_roofline(bf, last, args.n)

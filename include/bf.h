@@ -229,12 +229,22 @@ const char* bf_last_error(void);
 typedef struct bf_server bf_server;
 typedef struct {
   int32_t slots;        /* concurrent requests (streams); 0 = 4 */
-  int32_t reserved;     /* 0 */
+  int32_t batch_cols;   /* 0: every apply is its own product.  > 0: continuous
+                           batching -- a slot that admits an apply also takes the
+                           queued applies against the same factors and direction,
+                           up to this many columns in all, gathers their columns
+                           into one block, applies once and scatters the result
+                           (one launch sequence instead of one per request).
+                           Merged results are those of the merged product: the
+                           same accuracy, but the arithmetic follows the merged
+                           width (a 1-column apply alone sums in FP64, merged
+                           with 4+ others it runs on the matrix cores), so they
+                           can differ from a lone apply in the last bits. */
   int64_t hbm_budget;   /* bytes; 0 = 64 GiB */
 } bf_server_opts;
 typedef struct {
   int32_t status;       /* BF_OK or the request's error code */
-  int32_t reserved;
+  int32_t batch;        /* applies merged into this request's product (1 = alone) */
   int64_t arrival_ns;   /* submit, start, completion: ns since server creation */
   int64_t start_ns;
   int64_t finish_ns;

@@ -70,11 +70,11 @@ KERNEL_CLASSES = ("matfree", "apply", "cpqr", "chain", "lsq", "other")
 
 
 class bf_server_opts(C.Structure):
-    _fields_ = [("slots", C.c_int32), ("reserved", C.c_int32), ("hbm_budget", C.c_int64)]
+    _fields_ = [("slots", C.c_int32), ("batch_cols", C.c_int32), ("hbm_budget", C.c_int64)]
 
 
 class bf_request_info(C.Structure):
-    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("arrival_ns", C.c_int64),
+    _fields_ = [("status", C.c_int32), ("batch", C.c_int32), ("arrival_ns", C.c_int64),
                 ("start_ns", C.c_int64), ("finish_ns", C.c_int64), ("footprint", C.c_int64)]
 
 
@@ -420,9 +420,12 @@ class Server:
     """Request engine: concurrent constructions and applies on `slots` streams
     with admission by estimated device footprint (see include/bf.h)."""
 
-    def __init__(self, slots=4, hbm_budget=0):
+    def __init__(self, slots=4, hbm_budget=0, batch_cols=0):
+        """batch_cols > 0 merges queued applies against the same factors into
+        one product of at most that many columns (continuous batching)."""
         h = C.c_void_p()
-        _check(lib().bf_server_create(C.byref(bf_server_opts(slots, 0, int(hbm_budget))),
+        _check(lib().bf_server_create(C.byref(bf_server_opts(slots, int(batch_cols),
+                                                             int(hbm_budget))),
                                       C.byref(h)), "bf_server_create")
         self._h = h
         self._keep = {}

@@ -12,7 +12,9 @@
 // * Applies wait for the construction they reference; factors stay resident
 //   until their ticket is released.
 // * Results do not depend on the mix: the random matrices are keyed by the
-//   request's own seed and every reduction has a fixed order.
+//   request's own seed and every reduction has a fixed order.  With
+//   continuous batching on (batch_cols > 0), queued applies against the same
+//   factors share one product: their results follow the merged width.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -55,6 +57,7 @@ struct Request {
   int skipped = 0;
   Clock::time_point arrival, start, finish;
   int status = 1;          // 1 pending, 2 running, 0 / <0 done
+  int batch = 1;           // applies merged into this request's product
   bf_factors* F = nullptr; // construct result
   std::string error;
 };
@@ -84,6 +87,7 @@ struct bf_server {
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
   int64_t budget = 0, reserved = 0, next_id = 1;
+  int64_t batch_cols = 0;
   int device = 0;
   bool stopping = false;
   Clock::time_point t0 = Clock::now();
@@ -110,18 +114,96 @@ struct bf_server {
     return nullptr;
   }
 
+  // Continuous batching (called with mu held, r just admitted): the queued
+  // applies against the same factors and direction, up to batch_cols columns
+  // with r, leave the queue with it.
+  std::vector<Request*> take_batch(Request* r) {
+    std::vector<Request*> b{r};
+    if (r->kind != 1 || batch_cols <= 0) return b;
+    int64_t cols = r->ncols;
+    for (size_t q = 0; q < queue.size();) {
+      Request* o = queue[q];
+      if (o->kind == 1 && o->target == r->target && o->trans == r->trans &&
+          cols + o->ncols <= batch_cols && reserved + o->footprint <= budget) {
+        cols += o->ncols;
+        reserved += o->footprint;
+        b.push_back(o);
+        queue.erase(queue.begin() + q);
+      } else {
+        ++q;
+      }
+    }
+    return b;
+  }
+
+  // The applies of a batch as one product: columns gathered into one block,
+  // one bf_apply, results scattered back.
+  static int apply_batch(const bf_factors* T, const std::vector<Request*>& b, hipStream_t s) {
+    if (b.size() == 1) {
+      const Request* r = b[0];
+      int rc = bf_apply(T, r->trans, r->X, r->ldx, r->ncols, r->Y, r->ldy, (void*)s);
+      if (rc == BF_OK && hipStreamSynchronize(s) != hipSuccess) rc = BF_EHIP;
+      return rc;
+    }
+    bf_info I{};
+    if (bf_stats(T, &I) != BF_OK) return BF_EINVAL;
+    const int trans = b[0]->trans;
+    const int64_t rin = trans ? I.m : I.n, rout = trans ? I.n : I.m;
+    int64_t cols = 0;
+    for (auto* r : b) cols += r->ncols;
+    bf_c64 *Xb = nullptr, *Yb = nullptr;
+    if (hipMallocAsync((void**)&Xb, (size_t)std::max<int64_t>(1, rin * cols) * sizeof(bf_c64), s) !=
+            hipSuccess ||
+        hipMallocAsync((void**)&Yb, (size_t)std::max<int64_t>(1, rout * cols) * sizeof(bf_c64), s) !=
+            hipSuccess) {
+      if (Xb) (void)hipFreeAsync(Xb, s);
+      (void)hipStreamSynchronize(s);
+      set_last_error("apply batch: device allocation failed");
+      return BF_ENOMEM;
+    }
+    int rc = BF_OK;
+    int64_t off = 0;
+    for (auto* r : b) {
+      if (r->ncols > 0 &&
+          hipMemcpy2DAsync(Xb + off * rin, rin * sizeof(bf_c64), r->X, r->ldx * sizeof(bf_c64),
+                           rin * sizeof(bf_c64), r->ncols, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = BF_EHIP;
+      off += r->ncols;
+    }
+    if (rc == BF_OK) rc = bf_apply(T, trans, Xb, rin, cols, Yb, rout, (void*)s);
+    off = 0;
+    for (auto* r : b) {
+      if (rc == BF_OK && r->ncols > 0 &&
+          hipMemcpy2DAsync(r->Y, r->ldy * sizeof(bf_c64), Yb + off * rout, rout * sizeof(bf_c64),
+                           rout * sizeof(bf_c64), r->ncols, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = BF_EHIP;
+      off += r->ncols;
+    }
+    (void)hipFreeAsync(Xb, s);
+    (void)hipFreeAsync(Yb, s);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == BF_OK) rc = BF_EHIP;
+    if (rc == BF_EHIP) set_last_error("apply batch: HIP copy or synchronization failed");
+    return rc;
+  }
+
   void run(int slot) {
     (void)hipSetDevice(device);
     hipStream_t s = streams[slot];
     for (;;) {
       Request* r = nullptr;
+      std::vector<Request*> batch;
       {
         std::unique_lock<std::mutex> lk(mu);
         cv_work.wait(lk, [&] { return stopping || (r = admit()) != nullptr; });
         if (!r) return;
         reserved += r->footprint;
-        r->status = 2;
-        r->start = Clock::now();
+        batch = take_batch(r);
+        const auto now = Clock::now();
+        for (auto* q : batch) {
+          q->status = 2;
+          q->start = now;
+          q->batch = (int)batch.size();
+        }
       }
       int rc = BF_OK;
       std::string err;
@@ -140,18 +222,20 @@ struct bf_server {
           rc = BF_EINVAL;
           set_last_error("apply: the referenced construction failed or was released");
         } else {
-          rc = bf_apply(T, r->trans, r->X, r->ldx, r->ncols, r->Y, r->ldy, (void*)s);
-          if (rc == BF_OK && hipStreamSynchronize(s) != hipSuccess) rc = BF_EHIP;
+          rc = apply_batch(T, batch, s);
         }
       }
       if (rc != BF_OK) err = bf_last_error();
       {
         std::lock_guard<std::mutex> lk(mu);
-        reserved -= r->footprint;
+        const auto now = Clock::now();
+        for (auto* q : batch) {
+          reserved -= q->footprint;
+          q->error = err;
+          q->finish = now;
+          q->status = rc;
+        }
         r->F = F;
-        r->error = err;
-        r->finish = Clock::now();
-        r->status = rc;
       }
       cv_done.notify_all();
       cv_work.notify_all();
@@ -168,6 +252,7 @@ int bf_server_create(const bf_server_opts* o, bf_server** out) {
   auto* S = new (std::nothrow) bf_server();
   if (!S) return BF_ENOMEM;
   S->budget = o && o->hbm_budget > 0 ? o->hbm_budget : (int64_t(64) << 30);
+  S->batch_cols = o && o->batch_cols > 0 ? o->batch_cols : 0;
   if (hipGetDevice(&S->device) != hipSuccess) {
     delete S;
     return BF_ENOTSUP;
@@ -289,6 +374,7 @@ int bf_server_wait(bf_server* S, int64_t ticket, bf_request_info* info) {
     info->start_ns = std::chrono::duration_cast<ns>(r->start - S->t0).count();
     info->finish_ns = std::chrono::duration_cast<ns>(r->finish - S->t0).count();
     info->footprint = r->footprint;
+    info->batch = r->batch;
   }
   if (r->status < 0) set_last_error(r->error);
   return r->status;

@@ -92,3 +92,42 @@ def test_budget_serializes_but_completes(bf):
     for (s0, f0), (s1, f1) in zip(spans, spans[1:]):
         assert s1 >= f0          # never two in flight under this budget
     S.close()
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_continuous_batching_of_applies(bf, trans):
+    """Applies queued behind their construction are merged into one product
+    (batch_cols = 64): each result matches its lone apply to single precision,
+    requests are merged (batch > 1), the column cap is respected, and applies
+    against another factorization are not mixed in."""
+    n = 3000
+    g = wl.segment_pair(n, ppw=8.0)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    g2 = wl.segment_pair(n, ppw=6.0)
+    op2 = bf.segkernel(g2.targets, g2.sources, g2.k)
+    S = bf.Server(slots=2, batch_cols=64)
+    t1 = S.submit_construct(op, 1e-6, 32, seed=3)
+    t2 = S.submit_construct(op2, 1e-6, 32, seed=4)
+    rng = np.random.default_rng(6)
+    widths = [1, 3, 5, 1, 16, 2, 30, 4, 1, 7]
+    reqs = []
+    for q, w in enumerate(widths):
+        X = (rng.standard_normal((n, w)) + 1j * rng.standard_normal((n, w))).astype(np.complex64)
+        target = t1 if q % 3 else t2
+        reqs.append((target, X, S.submit_apply(target, _t(X), trans=trans)))
+    infos = [S.wait(t) for _, _, t in reqs]
+    say("batch sizes", [i["batch"] for i in infos])
+    assert max(i["batch"] for i in infos) > 1
+    F1, F2 = S.factors(t1), S.factors(t2)
+    for (target, X, t), info in zip(reqs, infos):
+        F = F1 if target == t1 else F2
+        lone = F.apply(_t(X), trans=trans).cpu().numpy()
+        got = S.result(t).cpu().numpy()
+        assert np.linalg.norm(got - lone) <= 1e-6 * np.linalg.norm(lone), (t, info["batch"])
+    # merged products stay within the column cap and within one factorization
+    starts = {}
+    for (target, X, t), info in zip(reqs, infos):
+        starts.setdefault((info["start_ns"], target), []).append(X.shape[1])
+    for (_, target), cols in starts.items():
+        assert sum(cols) <= 64
+    S.close()
