@@ -361,7 +361,8 @@ def apply_roofline(bf, F, n, reps=20):
     """bf_apply of the benchmarked factors (default arithmetic) at 1, 4, 16
     and 64 right-hand sides: algorithmic bytes (8 per factor entry + 8 per
     input and output value) over the stages' HIP-event time, against the HBM
-    peak; the wall time per apply includes the launches."""
+    peak; the wall time per apply includes the launches, and is taken again
+    with the stages run as one captured HIP graph."""
     import torch
     out = {}
     for s in (1, 4, 16, 64):
@@ -377,7 +378,17 @@ def apply_roofline(bf, F, n, reps=20):
         ap = bf.profile_stop()["apply"]
         kms = ap["ms"] / reps
         gbs = ap["bytes"] / reps / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
-        out[f"s={s}"] = {"kernel_ms": kms, "wall_ms": wall * 1e3,
+        # the same applies as one captured HIP graph each (bf_set_apply_graph_cols)
+        F.set_graph_cols(64)
+        F.apply(X, out=Y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            F.apply(X, out=Y)
+        torch.cuda.synchronize()
+        gwall = (time.perf_counter() - t0) / reps
+        F.set_graph_cols(0)
+        out[f"s={s}"] = {"kernel_ms": kms, "wall_ms": wall * 1e3, "graph_wall_ms": gwall * 1e3,
                          "bytes": ap["bytes"] / reps, "GB_per_s": gbs,
                          "frac_hbm": gbs / PEAK_HBM_GBS,
                          "TFLOP_per_s": ap["flops"] / reps / (kms * 1e-3) / 1e12 if kms > 0 else 0.0,

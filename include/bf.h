@@ -165,12 +165,23 @@ int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64
 int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
              bf_c64* Y, int64_t ldy, void* stream);
 
+/* Applies of at most max_cols columns (0 = off, the default) run their L+3
+ * stage launches as one captured HIP graph: bf_apply copies X into a private
+ * buffer, launches the graph and copies the result out (two device copies
+ * instead of L+2 launch gaps, which bound few-column applies at n <= 65536).
+ * Graphs are cached per direction, column count, apply precision and stream
+ * (at most 16 per factorization; the first call of a key captures it, beyond
+ * 16 keys bf_apply launches the stages directly) and freed with the factors.
+ * Same kernels, same results.  Not to be called while applies of F run. */
+int bf_set_apply_graph_cols(bf_factors* F, int64_t max_cols);
+
 /* Summary of a factorization. */
 typedef struct {
   int64_t m, n;
   int32_t L, lm;
   int32_t max_rank;          /* over every block of every level */
   int32_t v_iters, u_iters;  /* passes of the two adaptive leaf loops */
+  int32_t apply_graphs;      /* captured apply graphs held (bf_set_apply_graph_cols) */
   int64_t matvec_cols;       /* black-box columns used: products with A ... */
   int64_t rmatvec_cols;      /* ... and with A^H (structured samples count s each) */
   int64_t factor_entries;    /* complex entries stored over all factors */

@@ -81,6 +81,7 @@ class bf_request_info(C.Structure):
 class bf_info(C.Structure):
     _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("L", C.c_int32), ("lm", C.c_int32),
                 ("max_rank", C.c_int32), ("v_iters", C.c_int32), ("u_iters", C.c_int32),
+                ("apply_graphs", C.c_int32),
                 ("matvec_cols", C.c_int64), ("rmatvec_cols", C.c_int64),
                 ("factor_entries", C.c_int64), ("device_bytes", C.c_int64)]
 
@@ -131,6 +132,7 @@ SIGNATURES = {
     "bf_operator_destroy": (C.c_int, [C.POINTER(bf_operator)]),
     "bf_op_set_precision": (C.c_int, [C.POINTER(bf_operator), C.c_int]),
     "bf_set_apply_precision": (C.c_int, [_P, C.c_int]),
+    "bf_set_apply_graph_cols": (C.c_int, [_P, C.c_int64]),
 }
 
 
@@ -304,6 +306,7 @@ class Info:
     max_rank: int
     v_iters: int
     u_iters: int
+    apply_graphs: int
     matvec_cols: int
     rmatvec_cols: int
     factor_entries: int
@@ -346,6 +349,11 @@ class Factors:
         ALUs, FP32)."""
         code = {"fp32": 2, "bf16x3": 1}[precision]
         _check(lib().bf_set_apply_precision(self._h, code), "bf_set_apply_precision")
+        return self
+
+    def set_graph_cols(self, max_cols):
+        """Run applies of at most max_cols columns as cached HIP graphs (0: off)."""
+        _check(lib().bf_set_apply_graph_cols(self._h, int(max_cols)), "bf_set_apply_graph_cols")
         return self
 
     def apply(self, X, trans=False, out=None, stream=None):

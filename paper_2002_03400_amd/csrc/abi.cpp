@@ -35,6 +35,8 @@ bool profiling() { return g_prof_on.load(std::memory_order_relaxed); }
 ProfScope::ProfScope(int c, hipStream_t st, double fl, double by)
     : cls(c), s(st), flops(fl), bytes(by) {
   if (!profiling()) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
   if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, s) != hipSuccess) a = nullptr;
 }
 
@@ -493,9 +495,18 @@ int bf_set_apply_precision(bf_factors* F, int precision) {
   return BF_OK;
 }
 
+int bf_set_apply_graph_cols(bf_factors* F, int64_t max_cols) {
+  if (!F || max_cols < 0) return BF_EINVAL;
+  return guarded([&] {
+    if (max_cols > 0 && !F->graphs) F->graphs = new_apply_graph_cache();
+    F->graph_cols = max_cols;
+  });
+}
+
 int bf_stats(const bf_factors* F, bf_info* info) {
   if (!F || !info) return BF_EINVAL;
   *info = F->info;
+  info->apply_graphs = apply_graph_count(F);
   return BF_OK;
 }
 

@@ -470,7 +470,11 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
     hipLaunchKernelGGL(apply_blocked_kernel, dim3((unsigned)nblk, (unsigned)ych), dim3(256), lds_b,
                        s, blks_dev, G, B, ncols);
   }
-  BF_HIP(hipGetLastError());
+  // launch errors of a captured stage surface when the graph is instantiated
+  // (the runtime refuses hipGetLastError on a capturing stream)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs == hipStreamCaptureStatusNone)
+    BF_HIP(hipGetLastError());
 }
 
 template <typename Tout>

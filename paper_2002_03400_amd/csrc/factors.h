@@ -44,6 +44,14 @@ struct ApplyPlan {
 
 }  // namespace bf
 
+struct bf_factors;
+namespace bf {
+struct ApplyGraphCache;
+ApplyGraphCache* new_apply_graph_cache();
+int apply_graph_count(const bf_factors* F);
+void free_apply_graphs(ApplyGraphCache* c);
+}
+
 struct bf_factors {
   int64_t m = 0, n = 0, leaf = 0;
   int L = 0, lm = 0;
@@ -56,6 +64,12 @@ struct bf_factors {
   int apply_prec = BF_PREC_BF16X3;          // bf_set_apply_precision
   bf_info info{};
   int device = 0;
+  int64_t graph_cols = 0;                   // bf_set_apply_graph_cols
+  bf::ApplyGraphCache* graphs = nullptr;    // captured apply graphs (plan.cpp)
+  bf_factors() = default;
+  bf_factors(const bf_factors&) = delete;
+  bf_factors& operator=(const bf_factors&) = delete;
+  ~bf_factors();
 
   int32_t ku(int l, int64_t i, int64_t j) const {
     return kU[(size_t)(l - lm) * ((size_t)1 << L) + (size_t)(i << (L - l)) + (size_t)j];

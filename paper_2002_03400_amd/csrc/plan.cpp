@@ -9,6 +9,7 @@
 // stage multiplies by (e.g. W^H rows for the forward row side) and stored
 // contiguously in stage order, so a stage streams its factor bytes once.
 #include <algorithm>
+#include <mutex>
 
 #include "factors.h"
 
@@ -276,12 +277,13 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
   }
 }
 
-void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
-                   bf_c64* Y, int64_t ldy, hipStream_t s) {
+// The L+3 stage launches of one apply on stream s (buffers: X, two
+// intermediates, Y).
+static void run_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                       int64_t ncols, bf_c64* Y, int64_t ldy, bf_c64* t1, bf_c64* t2,
+                       hipStream_t s) {
   const ApplyPlan& P = trans ? F->adj : F->fwd;
-  if (ncols <= 0) return;
-  DevBuf<bf_c64> t1((size_t)P.tmp_rows * ncols, s), t2((size_t)P.tmp_rows * ncols, s);
-  const bf_c64* bufs[4] = {X, t1.p, t2.p, Y};
+  const bf_c64* bufs[4] = {X, t1, t2, Y};
   // intermediates row-major above the few-column path (see launch_apply_stage)
   const bool rowmajor = ncols > kApplyFewCols;
   const int64_t tld = rowmajor ? 1 : P.tmp_rows, trs = rowmajor ? ncols : 1;
@@ -301,4 +303,142 @@ void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
   }
 }
 
+// ---- applies as captured HIP graphs (bf_set_apply_graph_cols) --------------
+// One graph per (direction, column count, precision, stream): the stage
+// launches read a private input buffer and write a private output buffer, and
+// a call copies X in, launches the graph and copies Y out.  The buffers are
+// plain device allocations made before capture (nothing is allocated or
+// cleared inside the graph).
+struct ApplyGraph {
+  int trans = 0, prec = 0;
+  int64_t ncols = 0;
+  hipStream_t s = nullptr;
+  bf_c64 *Xs = nullptr, *Ys = nullptr, *t1 = nullptr, *t2 = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+struct ApplyGraphCache {
+  std::mutex mu;
+  std::vector<ApplyGraph> g;
+  hipStream_t cap = nullptr;    // private capture stream (the default stream cannot capture)
+};
+constexpr size_t kMaxApplyGraphs = 16;
+
+static void release_graph(ApplyGraph& a) {
+  if (a.exec) (void)hipGraphExecDestroy(a.exec);
+  for (bf_c64* p : {a.Xs, a.Ys, a.t1, a.t2})
+    if (p) (void)hipFree(p);
+  a = ApplyGraph{};
+}
+
+ApplyGraphCache* new_apply_graph_cache() { return new ApplyGraphCache(); }
+
+int apply_graph_count(const bf_factors* F) {
+  if (!F->graphs) return 0;
+  std::lock_guard<std::mutex> lk(F->graphs->mu);
+  return (int)F->graphs->g.size();
+}
+
+void free_apply_graphs(ApplyGraphCache* c) {
+  if (!c) return;
+  for (auto& a : c->g) release_graph(a);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+}
+
+// Capture the graph of one key on the cache's own stream (a graph can be
+// launched on any stream); false (nothing kept) if capture fails.
+static bool capture_graph(const bf_factors* F, ApplyGraphCache* c, ApplyGraph& a) {
+  const ApplyPlan& P = a.trans ? F->adj : F->fwd;
+  const int64_t rin = a.trans ? F->m : F->n, rout = a.trans ? F->n : F->m;
+  const size_t tsz = (size_t)std::max<int64_t>(P.tmp_rows * a.ncols, 1) * sizeof(bf_c64);
+  if (hipMalloc((void**)&a.Xs, (size_t)(rin * a.ncols) * sizeof(bf_c64)) != hipSuccess ||
+      hipMalloc((void**)&a.Ys, (size_t)(rout * a.ncols) * sizeof(bf_c64)) != hipSuccess ||
+      hipMalloc((void**)&a.t1, tsz) != hipSuccess || hipMalloc((void**)&a.t2, tsz) != hipSuccess) {
+    release_graph(a);
+    return false;
+  }
+  if (!c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    c->cap = nullptr;
+    (void)hipGetLastError();
+    release_graph(a);
+    return false;
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    release_graph(a);
+    return false;
+  }
+  bool ok = true;
+  try {
+    run_stages(F, a.trans, a.Xs, rin, a.ncols, a.Ys, rout, a.t1, a.t2, c->cap);
+  } catch (...) {
+    ok = false;
+  }
+  if (hipStreamEndCapture(c->cap, &g) != hipSuccess || !g) ok = false;
+  if (ok && hipGraphInstantiate(&a.exec, g, nullptr, nullptr, 0) != hipSuccess) ok = false;
+  if (g) (void)hipGraphDestroy(g);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->cap, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+    hipGraph_t dead = nullptr;    // never leave the stream capturing
+    (void)hipStreamEndCapture(c->cap, &dead);
+    if (dead) (void)hipGraphDestroy(dead);
+    ok = false;
+  }
+  (void)hipGetLastError();
+  if (!ok) release_graph(a);
+  return ok;
+}
+
+// Runs the apply through a cached graph; false if none could be made (the
+// caller then launches the stages directly).
+static bool apply_graph(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                        int64_t ncols, bf_c64* Y, int64_t ldy, hipStream_t s) {
+  ApplyGraphCache* c = F->graphs;
+  if (!c) return false;
+  hipGraphExec_t exec = nullptr;
+  bf_c64 *Xs = nullptr, *Ys = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (auto& a : c->g)
+      if (a.trans == trans && a.ncols == ncols && a.prec == F->apply_prec && a.s == s) {
+        exec = a.exec;
+        Xs = a.Xs;
+        Ys = a.Ys;
+      }
+    if (!exec) {
+      if (c->g.size() >= kMaxApplyGraphs) return false;
+      ApplyGraph a;
+      a.trans = trans;
+      a.ncols = ncols;
+      a.prec = F->apply_prec;
+      a.s = s;
+      if (!capture_graph(F, c, a)) return false;
+      c->g.push_back(a);
+      exec = a.exec;
+      Xs = a.Xs;
+      Ys = a.Ys;
+    }
+  }
+  const int64_t rin = trans ? F->m : F->n, rout = trans ? F->n : F->m;
+  BF_HIP(hipMemcpy2DAsync(Xs, rin * sizeof(bf_c64), X, ldx * sizeof(bf_c64), rin * sizeof(bf_c64),
+                          ncols, hipMemcpyDeviceToDevice, s));
+  BF_HIP(hipGraphLaunch(exec, s));
+  BF_HIP(hipMemcpy2DAsync(Y, ldy * sizeof(bf_c64), Ys, rout * sizeof(bf_c64),
+                          rout * sizeof(bf_c64), ncols, hipMemcpyDeviceToDevice, s));
+  return true;
+}
+
+void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
+                   bf_c64* Y, int64_t ldy, hipStream_t s) {
+  if (ncols <= 0) return;
+  if (F->graph_cols > 0 && ncols <= F->graph_cols && apply_graph(F, trans, X, ldx, ncols, Y, ldy, s))
+    return;
+  const ApplyPlan& P = trans ? F->adj : F->fwd;
+  DevBuf<bf_c64> t1((size_t)P.tmp_rows * ncols, s), t2((size_t)P.tmp_rows * ncols, s);
+  run_stages(F, trans, X, ldx, ncols, Y, ldy, t1.p, t2.p, s);
+}
+
 }  // namespace bf
+
+bf_factors::~bf_factors() { bf::free_apply_graphs(graphs); }

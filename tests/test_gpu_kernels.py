@@ -291,3 +291,41 @@ def test_apply_precisions(bf, n, leaf):
         lib_rc = bf.lib().bf_set_apply_precision(H._h, 0)
         bf._check(lib_rc, "bf_set_apply_precision")
     H.close()
+
+
+def test_apply_graphs_replay_bitwise(bf):
+    """Applies run as captured HIP graphs (bf_set_apply_graph_cols) give the
+    bits of the directly launched stages, on every replay, with direct applies
+    and host synchronizations between the replays, for both directions, both
+    apply precisions, few-column and matrix-core widths, and above the limit."""
+    import torch
+    n, leaf = 2000, 40
+    g = wl.segment_pair(n, ppw=6.0)
+    op = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    F = obf.construct(op, 1e-6, leaf, seed=2)
+    kU, kV, data = oracle_to_canonical(F)
+    H = bf.import_factors(n, n, leaf, kU, kV, data)
+    rng = np.random.default_rng(11)
+    cases = [(s, trans, prec) for s in (1, 4, 8, 12) for trans in (False, True)
+             for prec in ("bf16x3", "fp32")]
+    Xs = {s: _t(_cg(rng, n, s)) for s in (1, 4, 8, 12)}
+    ref = {}
+    for s, trans, prec in cases:
+        H.set_precision(prec)
+        ref[(s, trans, prec)] = H.apply(Xs[s], trans=trans).cpu().numpy()
+    H.set_graph_cols(8)
+    say("apply graphs")
+    for rep in range(3):
+        for s, trans, prec in cases:
+            H.set_precision(prec)
+            got = H.apply(Xs[s], trans=trans).cpu().numpy()
+            assert np.array_equal(got, ref[(s, trans, prec)]), (rep, s, trans, prec)
+            # direct work between replays on the same stream
+            H.set_graph_cols(0)
+            H.apply(Xs[4], trans=not trans)
+            H.set_graph_cols(8)
+            torch.cuda.synchronize()
+    # one graph per (width <= 8, direction, precision) on this stream; 12 columns ran directly
+    assert H.stats().apply_graphs == 12
+    H.set_graph_cols(0)
+    H.close()
