@@ -30,41 +30,46 @@ static thread_local int64_t g_matfree_nin = 0;
 
 // ---- entry functors ------------------------------------------------------
 
-// sin and cos of (pi / 2) t for a phase t given in quarter revolutions (FP64,
-// |t| < 2^31).  The phase is reduced in FP64 to the nearest quarter
-// revolution, t = q + y with |y| <= 1/2 (exact), so x = (pi / 2) y lies in
-// [-pi/4, pi/4] and only its FP32 rounding (< 5e-8 rad) enters; sin x and
-// cos x are minimax polynomials on that interval (Remez exchange, FP32
-// coefficients; errors 3.6e-9 relative and 5.4e-11 absolute before FP32
-// rounding), then rotated by q quarter turns.
-__device__ __forceinline__ void sincos_quarter(double t, float* s, float* c) {
-  const double q = rint(t);
-  const float x = (float)((t - q) * 1.5707963267948966);
-  const float x2 = x * x;
-  float sp = fmaf(x2, -1.951729937e-4f, 8.332177997e-3f);
-  sp = fmaf(x2, sp, -1.666665524e-1f);
-  const float sv0 = fmaf(x * x2, sp, x);
-  float cp = fmaf(x2, 2.439045056e-5f, -1.388676348e-3f);
-  cp = fmaf(x2, cp, 4.166662320e-2f);
-  cp = fmaf(x2, cp, -0.5f);
-  const float cv0 = fmaf(x2, cp, 1.0f);
-  // quarter turns: (sin, cos) -> (cos, -sin) -> (-sin, -cos) -> (-cos, sin)
-  const int n = (int)q;
-  const float sv = (n & 1) ? cv0 : sv0;
-  const float cv = (n & 1) ? sv0 : cv0;
-  *s = __int_as_float(__float_as_int(sv) ^ ((n & 2) << 30));
-  *c = __int_as_float(__float_as_int(cv) ^ (((n + 1) & 2) << 30));
+// amp * exp(i pi a b) for a phase t = a b given in half revolutions (FP64,
+// |t| < 2^51; a b is never rounded on its own).  The phase is reduced in FP64
+// to the nearest half revolution q by adding 1.5 * 2^52 (the sum rounds to
+// q + 1.5 * 2^52, whose low word holds q mod 2^32, so q's parity is its low
+// bit); y = t - q, |y| <= 1/2, is then formed with one rounding, and only the
+// FP32 rounding of y (< 2^-26 half revolutions, 4.7e-8 rad) enters.  sin(pi y)
+// and cos(pi y) are minimax polynomials in y on [-1/2, 1/2]
+// (linear-programming fit, coefficients rounded to FP32 one at a time from the
+// lowest order, each rounding compensated by refitting the higher ones;
+// errors before FP32 evaluation 2.8e-8 relative -- the FP32 rounding of pi --
+// and 1.2e-9 absolute), and (-1)^q is applied as a sign flip of amp.  An FP32
+// emulation against exp(i theta) in FP64 over 2e6 phases up to 2e4 rad stays
+// within 1.7e-7 (rms 4.3e-8); csrc/fit_cispi.py refits and rechecks.
+__device__ __forceinline__ cf cis_pi(double a, double b, float amp) {
+  constexpr double kRound = 0x1.8p52;
+  const double v = fma(a, b, kRound);
+  const float y = (float)fma(a, b, kRound - v);
+  const uint32_t flip = (uint32_t)__double2loint(v) << 31;
+  const float y2 = y * y;
+  float sp = fmaf(y2, 0x1.3b9a6ep-4f, -0x1.323be0p-1f);
+  sp = fmaf(y2, sp, 0x1.46690ap+1f);
+  sp = fmaf(y2, sp, -0x1.4abbd0p+2f);
+  sp = fmaf(y2, sp, 0x1.921fb6p+1f);
+  float cp = fmaf(y2, -0x1.88bf7ap-6f, 0x1.e0a362p-3f);
+  cp = fmaf(y2, cp, -0x1.55cd2ap+0f);
+  cp = fmaf(y2, cp, 0x1.03c1d4p+2f);
+  cp = fmaf(y2, cp, -0x1.3bd3ccp+2f);
+  const float am = __uint_as_float(__float_as_uint(amp) ^ flip);
+  return cf{fmaf(y2, cp, 1.0f) * am, (y * sp) * am};
 }
 
 // exp(i k r)/r, r = |p - q|: 1/r from the FP32 reciprocal square root, r
 // from it and refined by one FP64 Newton step (relative error ~1e-14, so the
 // phase k r stays accurate to ~1e-9 revolutions for k r / 2pi up to 1e5).
-// sign = -1 gives the conjugate (entries of A^H with the point roles
-// swapped).
+// The conjugate (entries of A^H with the point roles swapped) uses the
+// negated phase scale: sin is odd, cos even, and every rounding in cis_pi is
+// symmetric (q = -q' exactly, ties to even), so it is exactly the conjugate.
 struct SegEntry {
   PointSet out, in;
-  double k4;   // k / (pi / 2): k r in quarter revolutions
-  float sign;
+  double k2;   // +-k / pi: k r in half revolutions, the sign selecting A or conj
   struct Row { double x, y; };
   struct Col { double x, y; };
   __device__ Row row(int64_t i) const { return Row{out.x[i], out.y[i]}; }
@@ -76,17 +81,14 @@ struct SegEntry {
     const float inv = __builtin_amdgcn_rsqf(r2f);
     const double rd = (double)(r2f * inv);
     const double rr = fma(fma(-rd, rd, r2), (double)(0.5f * inv), rd);
-    float s, co;
-    sincos_quarter(rr * k4, &s, &co);
-    return cf{co * inv, s * (sign * inv)};
+    return cis_pi(rr, k2, inv);
   }
 };
 
 // The same kernel on 3D points (eq. 3dkernel: the two semi-spheres).
 struct Seg3Entry {
   PointSet out, in;
-  double k4;
-  float sign;
+  double k2;
   struct Row { double x, y, z; };
   struct Col { double x, y, z; };
   __device__ Row row(int64_t i) const { return Row{out.x[i], out.y[i], out.z[i]}; }
@@ -98,45 +100,38 @@ struct Seg3Entry {
     const float inv = __builtin_amdgcn_rsqf(r2f);
     const double rd = (double)(r2f * inv);
     const double rr = fma(fma(-rd, rd, r2), (double)(0.5f * inv), rd);
-    float s, co;
-    sincos_quarter(rr * k4, &s, &co);
-    return cf{co * inv, s * (sign * inv)};
+    return cis_pi(rr, k2, inv);
   }
 };
 
 // exp(2 pi i (j xi / n + c_j |xi|)).  j * xi is an exact integer (< 2^53),
-// so the phase (in quarter revolutions: the exact scalings 4/n and 4 c_j) is
+// so the phase (in half revolutions: the exact scalings 2/n and 2 c_j) is
 // formed in FP64 with one rounding before the reduction.
 // Forward: output index j (row), inner index k (xi = k - n/2).
 struct FioEntry {
   int64_t n;
-  double inv_n4;     // 4 / n
+  double inv_n2;     // 2 / n
   const double* cx;  // c(x_j), FP64
-  struct Row { double j; double c4; };
+  struct Row { double j; double c2; };
   struct Col { double xi; };
-  __device__ Row row(int64_t j) const { return Row{(double)j, 4.0 * cx[j]}; }
+  __device__ Row row(int64_t j) const { return Row{(double)j, 2.0 * cx[j]}; }
   __device__ Col col(int64_t k) const { return Col{(double)(k - n / 2)}; }
   __device__ cf entry(const Row& r, const Col& c) const {
-    const double ph = fma(r.j * c.xi, inv_n4, r.c4 * fabs(c.xi));
-    float s, co;
-    sincos_quarter(ph, &s, &co);
-    return cf{co, s};
+    return cis_pi(fma(r.j * c.xi, inv_n2, r.c2 * fabs(c.xi)), 1.0, 1.0f);
   }
 };
-// Adjoint: output index k, inner index j: conj(A_jk).
+// Adjoint: output index k, inner index j: conj(A_jk), from the negated phase
+// (exact, as for SegEntry).
 struct FioAdjEntry {
   int64_t n;
-  double inv_n4;
+  double inv_n2;
   const double* cx;
   struct Row { double xi; };
-  struct Col { double j; double c4; };
+  struct Col { double j; double c2; };
   __device__ Row row(int64_t k) const { return Row{(double)(k - n / 2)}; }
-  __device__ Col col(int64_t j) const { return Col{(double)j, 4.0 * cx[j]}; }
+  __device__ Col col(int64_t j) const { return Col{(double)j, 2.0 * cx[j]}; }
   __device__ cf entry(const Row& r, const Col& c) const {
-    const double ph = fma(c.j * r.xi, inv_n4, c.c4 * fabs(r.xi));
-    float s, co;
-    sincos_quarter(ph, &s, &co);
-    return cf{co, -s};
+    return cis_pi(fma(c.j * r.xi, inv_n2, c.c2 * fabs(r.xi)), -1.0, 1.0f);
   }
 };
 
@@ -699,10 +694,10 @@ void launch_segkernel(int prec, PointSet out_pts, int64_t nout, PointSet in_pts,
                       bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
                       hipStream_t s) {
   if (out_pts.z && in_pts.z) {
-    Seg3Entry e{out_pts, in_pts, 4.0 * k_over_2pi, (float)sign};
+    Seg3Entry e{out_pts, in_pts, 2.0 * (double)sign * k_over_2pi};
     run_matfree(prec, e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   } else {
-    SegEntry e{out_pts, in_pts, 4.0 * k_over_2pi, (float)sign};
+    SegEntry e{out_pts, in_pts, 2.0 * (double)sign * k_over_2pi};
     run_matfree(prec, e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   }
 }
@@ -711,10 +706,10 @@ void launch_fio(int prec, int64_t n, const double* cx_dev, int adjoint, const bf
                 int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg_host,
                 int32_t nseg, hipStream_t s) {
   if (!adjoint) {
-    FioEntry e{n, 4.0 / (double)n, cx_dev};
+    FioEntry e{n, 2.0 / (double)n, cx_dev};
     run_matfree(prec, e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   } else {
-    FioAdjEntry e{n, 4.0 / (double)n, cx_dev};
+    FioAdjEntry e{n, 2.0 / (double)n, cx_dev};
     run_matfree(prec, e, n, n, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   }
 }
