@@ -89,6 +89,109 @@ static void ensure_pool(int dev) {
   });
 }
 
+// Device blocks that outlive the request scope that made them (factor
+// storage, freed with its factors) and the spare blocks a scope holds when it
+// ends are kept per device for later requests instead of going back through
+// hipFreeAsync: giving back a block of ~100 MB took 3-4 ms of host time per
+// call, which sat between consecutive requests.  A kept block carries an event
+// recorded on the stream that freed it, waited for before the block is handed
+// out again.  At most kDevKeepBytes are kept per device; an allocation that
+// fails gives them all back and retries.
+namespace {
+struct BlockInfo {
+  size_t cap;
+  int dev;
+};
+std::mutex g_cap_mu;
+std::unordered_map<void*, BlockInfo> g_cap;   // every block dev_alloc made
+struct KeptBlock {
+  void* p;
+  hipEvent_t ev;
+  hipStream_t s;
+};
+struct DevKeep {
+  std::mutex mu;
+  std::multimap<size_t, KeptBlock> blocks;   // capacity -> block
+  size_t bytes = 0;
+};
+DevKeep g_keep[64];
+constexpr size_t kDevKeepBytes = size_t(16) << 30;
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+BlockInfo block_info(void* p) {
+  std::lock_guard<std::mutex> lk(g_cap_mu);
+  auto it = g_cap.find(p);
+  return it == g_cap.end() ? BlockInfo{0, -1} : it->second;
+}
+
+void give_back(void* p, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_cap_mu);
+    g_cap.erase(p);
+  }
+  (void)hipFreeAsync(p, s);
+}
+
+// keep p (last used on s) for reuse; false: the caller gives it back
+bool keep_block(void* p, hipStream_t s) {
+  const BlockInfo bi = block_info(p);
+  if (bi.cap == 0 || bi.dev < 0 || bi.dev >= 64 || capturing(s)) return false;
+  DevKeep& k = g_keep[bi.dev];
+  {
+    std::lock_guard<std::mutex> lk(k.mu);
+    if (k.bytes + bi.cap > kDevKeepBytes) return false;
+  }
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return false;
+  if (hipEventRecord(ev, s) != hipSuccess) {
+    (void)hipEventDestroy(ev);
+    return false;
+  }
+  std::lock_guard<std::mutex> lk(k.mu);
+  k.blocks.emplace(bi.cap, KeptBlock{p, ev, s});
+  k.bytes += bi.cap;
+  return true;
+}
+
+// a kept block of capacity in [want, 2 want] whose earlier uses have ended
+void* take_kept(int dev, size_t want, size_t* cap) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  DevKeep& k = g_keep[dev];
+  KeptBlock b{nullptr, nullptr, nullptr};
+  {
+    std::lock_guard<std::mutex> lk(k.mu);
+    auto it = k.blocks.lower_bound(want);
+    if (it == k.blocks.end() || it->first > 2 * want) return nullptr;
+    b = it->second;
+    *cap = it->first;
+    k.bytes -= it->first;
+    k.blocks.erase(it);
+  }
+  BF_HIP(hipEventSynchronize(b.ev));
+  (void)hipEventDestroy(b.ev);
+  return b.p;
+}
+
+void release_kept(int dev) {
+  if (dev < 0 || dev >= 64) return;
+  std::multimap<size_t, KeptBlock> all;
+  {
+    std::lock_guard<std::mutex> lk(g_keep[dev].mu);
+    all.swap(g_keep[dev].blocks);
+    g_keep[dev].bytes = 0;
+  }
+  for (auto& kv : all) {
+    (void)hipEventSynchronize(kv.second.ev);
+    (void)hipEventDestroy(kv.second.ev);
+    give_back(kv.second.p, kv.second.s);
+  }
+}
+}  // namespace
+
 struct AllocScope::Cache {
   hipStream_t s = nullptr;
   std::multimap<size_t, void*> free_;          // capacity -> block
@@ -98,7 +201,7 @@ struct AllocScope::Cache {
   Cache* prev = nullptr;
   void trim() {
     for (auto& kv : free_) {
-      (void)hipFreeAsync(kv.second, s);
+      if (!keep_block(kv.second, s)) give_back(kv.second, s);
       cap_.erase(kv.second);
     }
     free_.clear();
@@ -141,27 +244,37 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
   BF_HIP(hipGetDevice(&dev));
   ensure_pool(dev);
   void* p = nullptr;
+  const size_t want = round_block(bytes);
   AllocScope::Cache* c = t_cache;
-  if (c && c->s == s) {
-    const size_t want = round_block(bytes);
+  const bool scoped = c && c->s == s;
+  if (scoped) {
     auto it = c->free_.lower_bound(want);
     if (it != c->free_.end() && it->first <= 2 * want) {
       p = it->second;
       c->free_bytes -= it->first;
       c->free_.erase(it);
-    } else {
-      if (c->free_bytes > kScopeFreeLimit) c->trim();
-      hipError_t e = hipMallocAsync(&p, want, s);
-      if (e != hipSuccess && !c->free_.empty()) {   // give the pool our spare blocks, retry
-        (void)hipGetLastError();
-        c->trim();
-        e = hipMallocAsync(&p, want, s);
-      }
-      BF_HIP(e);
-      c->cap_[p] = want;
     }
-  } else {
-    BF_HIP(hipMallocAsync(&p, bytes, s));
+  }
+  if (!p && !capturing(s)) {
+    size_t cap = 0;
+    p = take_kept(dev, want, &cap);
+    if (p && scoped) c->cap_[p] = cap;
+  }
+  if (!p) {
+    if (scoped && c->free_bytes > kScopeFreeLimit) c->trim();
+    hipError_t e = hipMallocAsync(&p, want, s);
+    if (e != hipSuccess) {   // give the pool every spare block, retry
+      (void)hipGetLastError();
+      if (scoped) c->trim();
+      release_kept(dev);
+      e = hipMallocAsync(&p, want, s);
+    }
+    BF_HIP(e);
+    {
+      std::lock_guard<std::mutex> lk(g_cap_mu);
+      g_cap[p] = BlockInfo{want, dev};
+    }
+    if (scoped) c->cap_[p] = want;
   }
   if (validating()) {
     std::lock_guard<std::mutex> lk(g_reg_mu);
@@ -185,11 +298,91 @@ void dev_free(void* p, hipStream_t s) {
       return;
     }
   }
-  (void)hipFreeAsync(p, s);
+  if (!keep_block(p, s)) give_back(p, s);
 }
 
+// Pinned host blocks shared by every Staging of the process.  A staging area
+// that ends or grows hands its block back here, tagged with an event that
+// completes once the copies issued from it have, and later stagings reuse the
+// blocks: pinning and unpinning many MB costs milliseconds per call
+// (hipHostFree also waits for the device), which would otherwise sit between
+// consecutive requests.  At most kPinnedKeep blocks are kept; they stay
+// pinned until the process ends.
+namespace {
+struct PinnedBlock {
+  char* h;
+  size_t cap;
+  hipEvent_t done;   // null: no copy from the block can be pending
+};
+std::mutex g_pin_mu;
+std::vector<PinnedBlock> g_pinned;
+constexpr size_t kPinnedKeep = 8;
+
+void release_pinned(char* h, size_t cap, hipStream_t s, bool synced) {
+  hipEvent_t ev = nullptr;
+  if (!synced) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    // a capture would make the graph read the block at replay time: keep it
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      ev = nullptr;
+    } else if (hipEventRecord(ev, s) != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      (void)hipStreamSynchronize(s);
+      ev = nullptr;
+    }
+  }
+  PinnedBlock drop{nullptr, 0, nullptr};
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pinned.push_back(PinnedBlock{h, cap, ev});
+    if (g_pinned.size() > kPinnedKeep) {
+      auto it = std::min_element(g_pinned.begin(), g_pinned.end(),
+                                 [](const PinnedBlock& a, const PinnedBlock& b) { return a.cap < b.cap; });
+      drop = *it;
+      g_pinned.erase(it);
+    }
+  }
+  if (drop.h) {
+    if (drop.done) {
+      (void)hipEventSynchronize(drop.done);
+      (void)hipEventDestroy(drop.done);
+    }
+    (void)hipHostFree(drop.h);
+  }
+}
+
+// the smallest kept block of at least `need` bytes, else a new one of `want`
+char* acquire_pinned(size_t need, size_t want, size_t* cap) {
+  PinnedBlock got{nullptr, 0, nullptr};
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto best = g_pinned.end();
+    for (auto it = g_pinned.begin(); it != g_pinned.end(); ++it)
+      if (it->cap >= need && (best == g_pinned.end() || it->cap < best->cap)) best = it;
+    if (best != g_pinned.end()) {
+      got = *best;
+      g_pinned.erase(best);
+    }
+  }
+  if (got.h) {
+    if (got.done) {
+      BF_HIP(hipEventSynchronize(got.done));
+      (void)hipEventDestroy(got.done);
+    }
+    *cap = got.cap;
+    return got.h;
+  }
+  void* p = nullptr;
+  BF_HIP(hipHostMalloc(&p, want, hipHostMallocDefault));
+  *cap = want;
+  return static_cast<char*>(p);
+}
+}  // namespace
+
 Staging::~Staging() {
-  if (h) (void)hipHostFree(h);
+  if (h) release_pinned(h, cap, last, false);
 }
 
 void* Staging::alloc(size_t bytes, hipStream_t s) {
@@ -197,16 +390,14 @@ void* Staging::alloc(size_t bytes, hipStream_t s) {
   if (off + need > cap) {
     if (h) {
       // earlier copies from the old block may still be in flight
-      BF_HIP(hipStreamSynchronize(s));
-      BF_HIP(hipHostFree(h));
+      BF_HIP(hipStreamSynchronize(last));
+      release_pinned(h, cap, last, true);
       h = nullptr;
     }
-    cap = std::max<size_t>(std::max<size_t>(2 * cap, need), 1 << 20);
-    void* p = nullptr;
-    BF_HIP(hipHostMalloc(&p, cap, hipHostMallocDefault));
-    h = static_cast<char*>(p);
+    h = acquire_pinned(need, std::max<size_t>(std::max<size_t>(2 * cap, need), 1 << 20), &cap);
     off = 0;
   }
+  last = s;
   void* r = h + off;
   off += need;
   return r;

@@ -117,10 +117,13 @@ struct DevBuf {
 
 // Pinned host staging for descriptor uploads: a bump allocator whose space is
 // recycled only after the owning stream has been synchronized (reset()), so
-// in-flight host-to-device copies never see their source overwritten.
+// in-flight host-to-device copies never see their source overwritten.  Its
+// blocks come from a process-wide set of pinned blocks and go back to it (with
+// an event marking the end of their copies) when the staging grows or ends.
 struct Staging {
   char* h = nullptr;
   size_t cap = 0, off = 0;
+  hipStream_t last = nullptr;                  // stream of the latest copy out of h
   ~Staging();
   void* alloc(size_t bytes, hipStream_t s);   // may synchronize s to grow
   void reset() { off = 0; }                    // caller has synchronized the stream

@@ -450,6 +450,7 @@ void matfree_bf16_kernel(
       }
 #pragma unroll
       for (int p = 0; p < 3; ++p) an[p] = ai[p] ^ 0x80008000u;   // -ai, both halves
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         u32x4 xr[NTERM], xi[NTERM];
@@ -479,6 +480,7 @@ void matfree_bf16_kernel(
           fi[t][v] += (double)I[v];
         }
       }
+      __builtin_amdgcn_s_setprio(0);
     }
   }
   // accumulator layout of a 16x16 MFMA tile on gfx950: lane l, register v
