@@ -61,15 +61,18 @@ __device__ __forceinline__ cf cis_pi(double a, double b, float amp) {
   return cf{fmaf(y2, cp, 1.0f) * am, (y * sp) * am};
 }
 
-// exp(i k r)/r, r = |p - q|: 1/r from the FP32 reciprocal square root, r
-// from it and refined by one FP64 Newton step (relative error ~1e-14, so the
-// phase k r stays accurate to ~1e-9 revolutions for k r / 2pi up to 1e5).
-// The conjugate (entries of A^H with the point roles swapped) uses the
-// negated phase scale: sin is odd, cos even, and every rounding in cis_pi is
-// symmetric (q = -q' exactly, ties to even), so it is exactly the conjugate.
+// exp(i k r)/r, r = |p - q|: y = 1/r from the FP32 reciprocal square root
+// (the amplitude), and the phase k r = k h (1 + e / 2) with h = r^2 y and
+// e = 1 - r^2 y^2 in FP64 -- one Newton step for 1/sqrt(r^2) folded into the
+// phase scale, relative error ~1.5 (2^-23)^2 ~ 1e-14, so k r stays accurate
+// to ~1e-9 revolutions for k r / 2pi up to 1e5.  The conjugate (entries of
+// A^H with the point roles swapped) uses the negated phase scale: sin is odd,
+// cos even, and every rounding here and in cis_pi is symmetric (q = -q'
+// exactly, ties to even), so it is exactly the conjugate.
 struct SegEntry {
   PointSet out, in;
   double k2;   // +-k / pi: k r in half revolutions, the sign selecting A or conj
+  double k2h;  // k2 / 2
   struct Row { double x, y; };
   struct Col { double x, y; };
   __device__ Row row(int64_t i) const { return Row{out.x[i], out.y[i]}; }
@@ -77,18 +80,16 @@ struct SegEntry {
   __device__ cf entry(const Row& r, const Col& c) const {
     const double dx = r.x - c.x, dy = r.y - c.y;
     const double r2 = fma(dx, dx, dy * dy);
-    const float r2f = (float)r2;
-    const float inv = __builtin_amdgcn_rsqf(r2f);
-    const double rd = (double)(r2f * inv);
-    const double rr = fma(fma(-rd, rd, r2), (double)(0.5f * inv), rd);
-    return cis_pi(rr, k2, inv);
+    const float inv = __builtin_amdgcn_rsqf((float)r2);
+    const double y = (double)inv, h = r2 * y;
+    return cis_pi(h, fma(fma(-h, y, 1.0), k2h, k2), inv);
   }
 };
 
 // The same kernel on 3D points (eq. 3dkernel: the two semi-spheres).
 struct Seg3Entry {
   PointSet out, in;
-  double k2;
+  double k2, k2h;
   struct Row { double x, y, z; };
   struct Col { double x, y, z; };
   __device__ Row row(int64_t i) const { return Row{out.x[i], out.y[i], out.z[i]}; }
@@ -96,11 +97,9 @@ struct Seg3Entry {
   __device__ cf entry(const Row& r, const Col& c) const {
     const double dx = r.x - c.x, dy = r.y - c.y, dz = r.z - c.z;
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const float r2f = (float)r2;
-    const float inv = __builtin_amdgcn_rsqf(r2f);
-    const double rd = (double)(r2f * inv);
-    const double rr = fma(fma(-rd, rd, r2), (double)(0.5f * inv), rd);
-    return cis_pi(rr, k2, inv);
+    const float inv = __builtin_amdgcn_rsqf((float)r2);
+    const double y = (double)inv, h = r2 * y;
+    return cis_pi(h, fma(fma(-h, y, 1.0), k2h, k2), inv);
   }
 };
 
@@ -696,10 +695,10 @@ void launch_segkernel(int prec, PointSet out_pts, int64_t nout, PointSet in_pts,
                       bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,
                       hipStream_t s) {
   if (out_pts.z && in_pts.z) {
-    Seg3Entry e{out_pts, in_pts, 2.0 * (double)sign * k_over_2pi};
+    Seg3Entry e{out_pts, in_pts, 2.0 * (double)sign * k_over_2pi, (double)sign * k_over_2pi};
     run_matfree(prec, e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   } else {
-    SegEntry e{out_pts, in_pts, 2.0 * (double)sign * k_over_2pi};
+    SegEntry e{out_pts, in_pts, 2.0 * (double)sign * k_over_2pi, (double)sign * k_over_2pi};
     run_matfree(prec, e, nout, nin, X, ldx, ncols, Y, ldy, seg_host, nseg, s);
   }
 }
