@@ -25,7 +25,8 @@ template <> __device__ __forceinline__ cd load_c<bf_c128>(const bf_c128* p) {
 
 // ---------------------------------------------------------------- gemm ----
 // grid (ndesc, ceil(max_ncols / 64)); a workgroup of 4 waves computes rows
-// 0..M-1 of one descriptor (in row blocks of 32, or 64 when some M > 32) for
+// 0..M-1 of one descriptor (in row blocks of 20, 24, 32 or 64: the smallest
+// that holds the launch's largest M) for
 // the 64-column chunk blockIdx.y.
 // Lane l of every wave owns column l of the chunk and wave w the rows w,
 // w+4, ... of the block.  op(F) is staged in LDS in chunks of 64 (or 32)
@@ -85,10 +86,12 @@ __device__ __forceinline__ void cg_accum(cd* acc, const cd (*fs)[ROWS], const Ti
   }
 }
 
-// ROWS x KT = 2048 entries of op(F) in LDS (32 KB): 32 x 64 or 64 x 32.
+// ROWS x KT entries of op(F) in LDS: 20 / 24 / 32 x 64 or 64 x 32 (at most
+// 32 KB).  Each wave owns ROWS / 4 rows, so a ROWS close above the launch's
+// largest M leaves few idle row slots (M = 19 on 20 rows instead of 32).
 template <typename Tin, int ROWS>
 __global__ __launch_bounds__(256) void chain_gemm_kernel(const GemmDesc* __restrict__ descs) {
-  constexpr int KT = 2048 / ROWS;
+  constexpr int KT = ROWS > 32 ? 32 : 64;
   __shared__ cd fs[KT][ROWS];
   const GemmDesc d = descs[blockIdx.x];
   if (d.M <= 0 || (int)blockIdx.y * CG_COLS >= d.ncols) return;
@@ -203,7 +206,11 @@ static void launch_chain_t(const GemmDesc* d_dev, int32_t ndesc, int32_t max_nco
   }
   const int nchunk = (max_ncols + CG_COLS - 1) / CG_COLS;
   dim3 grid((unsigned)ndesc, (unsigned)std::min(nchunk, CG_YMAX));
-  if (max_M <= 32)
+  if (max_M <= 20)
+    hipLaunchKernelGGL((chain_gemm_kernel<Tin, 20>), grid, dim3(256), 0, s, d_dev);
+  else if (max_M <= 24)
+    hipLaunchKernelGGL((chain_gemm_kernel<Tin, 24>), grid, dim3(256), 0, s, d_dev);
+  else if (max_M <= 32)
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 32>), grid, dim3(256), 0, s, d_dev);
   else
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 64>), grid, dim3(256), 0, s, d_dev);
