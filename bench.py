@@ -83,6 +83,11 @@ def parse():
                     help="only compare the hybrid (l_m = L/2), column-wise (l_m = 0) and "
                          "row-wise (l_m = L) constructions of the segment-kernel operator at "
                          "these comma-separated n (leaf 64, tol 1e-6); one JSON line each")
+    ap.add_argument("--precision-form", type=int, default=0, metavar="N",
+                    help="only run the precision comparison on the 1D Fourier integral "
+                         "operator of size N (e.g. 262144; leaf 16, tol 1e-6): matrix-free construction with the split-BF16 and FP64 black "
+                         "boxes, recompression with the butterfly as black box (FP32 and "
+                         "split-BF16 applies) and apply rates; one JSON line each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (reference "
                          "dispatch for calibrating rocprofv3 byte counters) and exit")
@@ -180,6 +185,88 @@ def em3d(cases, tols):
             F.close()
         op.close()
         torch.cuda.empty_cache()
+
+
+def precision_form(n, leaf=16, tol=1e-6):
+    """Precision form: A_jk = exp(2 pi i (x_j xi_k + c(x_j)|xi_k|)) (the 1D
+    Fourier integral operator), leaf 16, tol 1e-6.  (1) Matrix-free
+    construction with the split-BF16 black box and with the FP64 one;
+    (2) recompression of the first result with the butterfly itself as the
+    black box, its applies in FP32 and in split-BF16; (3) apply rates of that
+    butterfly at 1, 16 and 64 right-hand sides.  Errors ||A W - F W|| / ||A W||
+    on 16 Gaussian columns W, A W from the FP64-accumulating black box.  Times
+    are the second of two runs (the first loads the kernels)."""
+    import torch
+
+    import paper_2002_03400_amd as bf
+    import workloads as wl
+    torch.cuda.init()
+    op = bf.fio(n)
+    Om = torch.from_numpy(wl.test_columns(n, 16, 1001).astype(np.complex64)).cuda()
+    op.set_precision("fp64")
+    ref = op.matvec(Om)
+
+    def rel(F):
+        return float((F.apply(Om) - ref).norm() / ref.norm())
+
+    def timed(o, seed):
+        bf.construct(o, tol, leaf, seed=seed).close()
+        bf.profile_start()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = bf.construct(o, tol, leaf, seed=seed)
+        torch.cuda.synchronize()
+        return F, time.perf_counter() - t0, bf.profile_stop()
+
+    keep = None
+    for prec in ("bf16x3", "fp64"):
+        op.set_precision(prec)
+        F, dt, prof = timed(op, 5)
+        st = F.stats()
+        print(json.dumps({
+            "workload": "1D Fourier integral operator, matrix-free black box",
+            "n": n, "L": F.L, "leaf": leaf, "tol": tol, "black_box": prec, "seconds": dt,
+            "rel_err": rel(F), "max_rank": st.max_rank, "factor_entries": st.factor_entries,
+            "device_bytes": st.device_bytes,
+            "phase_ms": {k: v["ms"] for k, v in prof.items()}}), flush=True)
+        if prec == "bf16x3":
+            keep = F
+        else:
+            F.close()
+    op.set_precision("bf16x3")
+    opb = bf.from_factors(keep)
+    for aprec in ("fp32", "bf16x3"):
+        keep.set_precision(aprec)
+        G, dt, prof = timed(opb, 7)
+        st = G.stats()
+        ap = prof.get("apply", {"ms": 0.0, "flops": 0.0})
+        print(json.dumps({
+            "workload": "recompression of the FIO butterfly, the butterfly as black box",
+            "n": n, "leaf": leaf, "tol": tol, "apply_precision": aprec, "seconds": dt,
+            "rel_err": rel(G), "max_rank": st.max_rank, "factor_entries": st.factor_entries,
+            "apply_ms": ap["ms"], "apply_TFLOP_per_s": ap["flops"] / max(ap["ms"], 1e-9) / 1e9,
+            "phase_ms": {k: v["ms"] for k, v in prof.items()}}), flush=True)
+        G.close()
+    fe = keep.stats().factor_entries
+    for aprec in ("fp32", "bf16x3"):
+        keep.set_precision(aprec)
+        out = {}
+        for s in (1, 16, 64):
+            X = torch.randn(n, s, dtype=torch.complex64, device="cuda")
+            keep.apply(X)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                keep.apply(X)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 5
+            gbs = 8.0 * fe / dt / 1e9
+            out[f"s={s}"] = {"ms": 1e3 * dt, "factor_GB_per_s": gbs, "frac_hbm": gbs / 8000.0,
+                             "TFLOP_per_s": 8.0 * fe * s / dt / 1e12}
+        print(json.dumps({"workload": "applies of the FIO butterfly", "n": n,
+                          "precision": aprec, "factor_bytes": 8 * fe, "applies": out}), flush=True)
+    keep.close()
+    op.close()
 
 
 def variants(sizes, leaf=64, tol=1e-6):
@@ -452,6 +539,9 @@ def main():
         return
     if args.variants:
         variants([int(x) for x in args.variants.split(",")])
+        return
+    if args.precision_form:
+        precision_form(args.precision_form)
         return
     if args.em3d:
         em3d([tuple(int(x) for x in e.split(":")) for e in args.em3d.split(",")],
