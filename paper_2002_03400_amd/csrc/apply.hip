@@ -90,11 +90,8 @@ __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __
   }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-#pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) {
-      acc[c].re += __shfl_xor(acc[c].re, off, 16);
-      acc[c].im += __shfl_xor(acc[c].im, off, 16);
-    }
+    acc[c].re = row16_sum(acc[c].re);
+    acc[c].im = row16_sum(acc[c].im);
   }
   if (live && q == 0) {
     bf_c64* out = B.p[rr.out_buf] + rr.out;
