@@ -262,6 +262,37 @@ def test_centre_level_exact_recovery(bf, center):
         bf.construct(op, 1e-5, 8, seed=5, center=6)
 
 
+def test_reused_device_blocks_do_not_change_results(bf):
+    """Device blocks and pinned staging are recycled across requests (their
+    old contents are never cleared): a construction repeated after others of
+    different sizes, precisions and operators, whose factors were freed in
+    between, gives bitwise the same factors, applies and ranks."""
+    g = wl.segment_pair(3000, ppw=8.0, m=2500)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    say("block reuse: reference")
+    first = bf.construct(op, 1e-6, 48, seed=11)
+    ref = first.export()
+    X = _t(np.random.default_rng(5).standard_normal((3000, 7)) + 0j)
+    Yref = first.apply(X).cpu().numpy()
+    first.close()
+    held = []
+    for n, tol, prec in ((6000, 1e-4, "bf16x3"), (1024, 1e-7, "fp64"), (4096, 1e-6, "bf16x3")):
+        gg = wl.segment_pair(n, ppw=6.0)
+        o = bf.segkernel(gg.targets, gg.sources, gg.k)
+        o.set_precision(prec)
+        H = bf.construct(o, tol, 32, seed=n)
+        H.apply(_t(np.ones((n, 3), complex)))
+        held.append(H)
+    for H in held[:2]:
+        H.close()
+    say("block reuse: repeat")
+    again = bf.construct(op, 1e-6, 48, seed=11)
+    assert np.array_equal(again.export(), ref)
+    assert np.array_equal(again.apply(X).cpu().numpy(), Yref)
+    again.close()
+    held[2].close()
+
+
 def test_merged_leaf_passes_same_result(bf):
     """Leaf-loop passes merged into one black-box call give bitwise the same
     factors as one call per pass; only the call count differs."""
