@@ -215,8 +215,20 @@ int bf_export(const bf_factors* F, bf_c128* data, int64_t* count);
 int bf_import(int64_t m, int64_t n, int64_t leaf, const int32_t* kU, const int32_t* kV,
               const bf_c128* data, int64_t count, void* stream, bf_factors** out);
 
-/* Release a handle (waits for `stream` work that uses it to be enqueued before). */
+/* Release a handle (waits for `stream` work that uses it to be enqueued before).
+ * Its device memory is kept by the library for later requests on the same
+ * device (up to 16 GB per device, each block reused only after the work
+ * enqueued on `stream` before this call has finished), as is the pinned host
+ * memory of descriptor uploads; bf_release_cached_memory gives both back. */
 int bf_free(bf_factors* F, void* stream);
+
+/* Return every device block and pinned host block the library keeps for
+ * reuse: waits for the work that last used them, frees them and trims each
+ * device's stream-ordered memory pool to what is still allocated, so the
+ * memory is available to other allocators again.  Live factor handles,
+ * operators and servers are unaffected.  Must not overlap with other calls
+ * into the library (it synchronizes every device it has used). */
+int bf_release_cached_memory(void);
 
 /* Text for an error code (static storage). */
 const char* bf_strerror(int code);

@@ -102,6 +102,7 @@ SIGNATURES = {
     "bf_import": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _I32P, _I32P, _P, C.c_int64, _P,
                             C.POINTER(_P)]),
     "bf_free": (C.c_int, [_P, _P]),
+    "bf_release_cached_memory": (C.c_int, []),
     "bf_strerror": (C.c_char_p, [C.c_int]),
     "bf_last_error": (C.c_char_p, []),
     "bf_server_create": (C.c_int, [C.POINTER(bf_server_opts), C.POINTER(_P)]),
@@ -498,6 +499,12 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def release_cached_memory():
+    """Give back the device and pinned host blocks the library keeps for
+    reuse after factors and temporaries are freed (bf_release_cached_memory)."""
+    _check(lib().bf_release_cached_memory(), "bf_release_cached_memory")
 
 
 def profile_start():

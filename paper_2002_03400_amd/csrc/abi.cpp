@@ -78,8 +78,11 @@ void check_extent(const void* p, size_t bytes, const char* what) {
   throw Error(BF_EINVAL, std::string("bounds check failed: ") + what);
 }
 
+static std::atomic<bool> g_dev_used[64];   // devices whose pool dev_alloc has used
+
 static void ensure_pool(int dev) {
   if (dev < 0 || dev >= 64) return;
+  g_dev_used[dev].store(true);
   std::call_once(g_pool_once[dev], [dev]() {
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
@@ -106,8 +109,7 @@ std::mutex g_cap_mu;
 std::unordered_map<void*, BlockInfo> g_cap;   // every block dev_alloc made
 struct KeptBlock {
   void* p;
-  hipEvent_t ev;
-  hipStream_t s;
+  hipEvent_t ev;   // recorded on the freeing stream, which may be gone by now
 };
 struct DevKeep {
   std::mutex mu;
@@ -152,7 +154,7 @@ bool keep_block(void* p, hipStream_t s) {
     return false;
   }
   std::lock_guard<std::mutex> lk(k.mu);
-  k.blocks.emplace(bi.cap, KeptBlock{p, ev, s});
+  k.blocks.emplace(bi.cap, KeptBlock{p, ev});
   k.bytes += bi.cap;
   return true;
 }
@@ -161,7 +163,7 @@ bool keep_block(void* p, hipStream_t s) {
 void* take_kept(int dev, size_t want, size_t* cap) {
   if (dev < 0 || dev >= 64) return nullptr;
   DevKeep& k = g_keep[dev];
-  KeptBlock b{nullptr, nullptr, nullptr};
+  KeptBlock b{nullptr, nullptr};
   {
     std::lock_guard<std::mutex> lk(k.mu);
     auto it = k.blocks.lower_bound(want);
@@ -176,7 +178,9 @@ void* take_kept(int dev, size_t want, size_t* cap) {
   return b.p;
 }
 
-void release_kept(int dev) {
+// gives every kept block of dev back to the pool on stream s (live; the
+// blocks' own freeing streams may have been destroyed since)
+void release_kept(int dev, hipStream_t s) {
   if (dev < 0 || dev >= 64) return;
   std::multimap<size_t, KeptBlock> all;
   {
@@ -187,7 +191,7 @@ void release_kept(int dev) {
   for (auto& kv : all) {
     (void)hipEventSynchronize(kv.second.ev);
     (void)hipEventDestroy(kv.second.ev);
-    give_back(kv.second.p, kv.second.s);
+    give_back(kv.second.p, s);
   }
 }
 }  // namespace
@@ -266,7 +270,7 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
     if (e != hipSuccess) {   // give the pool every spare block, retry
       (void)hipGetLastError();
       if (scoped) c->trim();
-      release_kept(dev);
+      release_kept(dev, s);
       e = hipMallocAsync(&p, want, s);
     }
     BF_HIP(e);
@@ -350,6 +354,21 @@ void release_pinned(char* h, size_t cap, hipStream_t s, bool synced) {
       (void)hipEventDestroy(drop.done);
     }
     (void)hipHostFree(drop.h);
+  }
+}
+
+void release_all_pinned() {
+  std::vector<PinnedBlock> all;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    all.swap(g_pinned);
+  }
+  for (auto& b : all) {
+    if (b.done) {
+      (void)hipEventSynchronize(b.done);
+      (void)hipEventDestroy(b.done);
+    }
+    (void)hipHostFree(b.h);
   }
 }
 
@@ -838,6 +857,25 @@ int bf_import(int64_t m, int64_t n, int64_t leaf, const int32_t* kU, const int32
   }
   *out = F;
   return BF_OK;
+}
+
+int bf_release_cached_memory(void) {
+  return guarded([&] {
+    int cur = 0;
+    BF_HIP(hipGetDevice(&cur));
+    int ndev = 0;
+    BF_HIP(hipGetDeviceCount(&ndev));
+    for (int dev = 0; dev < ndev && dev < 64; ++dev) {
+      if (!g_dev_used[dev].load()) continue;
+      BF_HIP(hipSetDevice(dev));
+      release_kept(dev, nullptr);
+      BF_HIP(hipDeviceSynchronize());
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) BF_HIP(hipMemPoolTrimTo(pool, 0));
+    }
+    BF_HIP(hipSetDevice(cur));
+    release_all_pinned();
+  });
 }
 
 int bf_free(bf_factors* F, void* stream) {

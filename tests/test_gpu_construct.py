@@ -291,6 +291,18 @@ def test_reused_device_blocks_do_not_change_results(bf):
     assert np.array_equal(again.apply(X).cpu().numpy(), Yref)
     again.close()
     held[2].close()
+    # giving the kept memory back returns it to the device; later requests
+    # allocate afresh and still agree bitwise
+    import torch
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    bf.release_cached_memory()
+    free1 = torch.cuda.mem_get_info()[0]
+    say("release cached memory: free", free0 >> 20, "->", free1 >> 20, "MiB")
+    assert free1 > free0
+    once_more = bf.construct(op, 1e-6, 48, seed=11)
+    assert np.array_equal(once_more.export(), ref)
+    once_more.close()
 
 
 def test_merged_leaf_passes_same_result(bf):
