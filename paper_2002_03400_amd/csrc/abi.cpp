@@ -98,8 +98,9 @@ static void ensure_pool(int dev) {
 // hipFreeAsync: giving back a block of ~100 MB took 3-4 ms of host time per
 // call, which sat between consecutive requests.  A kept block carries an event
 // recorded on the stream that freed it, waited for before the block is handed
-// out again.  At most kDevKeepBytes are kept per device; an allocation that
-// fails gives them all back and retries.
+// out again (by the new user's stream on the device, so the host never waits).
+// At most kDevKeepBytes are kept per device; an allocation that fails gives
+// them all back and retries.
 namespace {
 struct BlockInfo {
   size_t cap;
@@ -159,8 +160,30 @@ bool keep_block(void* p, hipStream_t s) {
   return true;
 }
 
-// a kept block of capacity in [want, 2 want] whose earlier uses have ended
-void* take_kept(int dev, size_t want, size_t* cap) {
+// Events of kept blocks handed out while their work was still pending: the
+// new user's stream waits for them on the device, and they are destroyed
+// once complete.
+std::mutex g_retired_mu;
+std::vector<hipEvent_t> g_retired;
+
+void retire_event(hipEvent_t ev) {
+  std::lock_guard<std::mutex> lk(g_retired_mu);
+  for (size_t i = 0; i < g_retired.size();) {
+    if (hipEventQuery(g_retired[i]) == hipSuccess) {
+      (void)hipEventDestroy(g_retired[i]);
+      g_retired[i] = g_retired.back();
+      g_retired.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  if (ev) g_retired.push_back(ev);
+}
+
+// a kept block of capacity in [want, 2 want], made safe for use on s: if the
+// work that last used it may still run, s waits for its event on the device
+// (the host never blocks here)
+void* take_kept(int dev, size_t want, hipStream_t s, size_t* cap) {
   if (dev < 0 || dev >= 64) return nullptr;
   DevKeep& k = g_keep[dev];
   KeptBlock b{nullptr, nullptr};
@@ -173,8 +196,13 @@ void* take_kept(int dev, size_t want, size_t* cap) {
     k.bytes -= it->first;
     k.blocks.erase(it);
   }
-  BF_HIP(hipEventSynchronize(b.ev));
-  (void)hipEventDestroy(b.ev);
+  if (hipEventQuery(b.ev) == hipSuccess) {
+    (void)hipEventDestroy(b.ev);
+    retire_event(nullptr);
+  } else {
+    BF_HIP(hipStreamWaitEvent(s, b.ev, 0));
+    retire_event(b.ev);
+  }
   return b.p;
 }
 
@@ -261,7 +289,7 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
   }
   if (!p && !capturing(s)) {
     size_t cap = 0;
-    p = take_kept(dev, want, &cap);
+    p = take_kept(dev, want, s, &cap);
     if (p && scoped) c->cap_[p] = cap;
   }
   if (!p) {
@@ -377,19 +405,20 @@ char* acquire_pinned(size_t need, size_t want, size_t* cap) {
   PinnedBlock got{nullptr, 0, nullptr};
   {
     std::lock_guard<std::mutex> lk(g_pin_mu);
+    // only blocks whose copies have finished: the host writes into it next,
+    // and waiting here would stall the host behind the device
     auto best = g_pinned.end();
     for (auto it = g_pinned.begin(); it != g_pinned.end(); ++it)
-      if (it->cap >= need && (best == g_pinned.end() || it->cap < best->cap)) best = it;
+      if (it->cap >= need && (best == g_pinned.end() || it->cap < best->cap) &&
+          (!it->done || hipEventQuery(it->done) == hipSuccess))
+        best = it;
     if (best != g_pinned.end()) {
       got = *best;
       g_pinned.erase(best);
     }
   }
   if (got.h) {
-    if (got.done) {
-      BF_HIP(hipEventSynchronize(got.done));
-      (void)hipEventDestroy(got.done);
-    }
+    if (got.done) (void)hipEventDestroy(got.done);   // complete (queried above)
     *cap = got.cap;
     return got.h;
   }
