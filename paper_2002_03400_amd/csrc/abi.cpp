@@ -199,9 +199,12 @@ void* take_kept(int dev, size_t want, hipStream_t s, size_t* cap) {
   if (hipEventQuery(b.ev) == hipSuccess) {
     (void)hipEventDestroy(b.ev);
     retire_event(nullptr);
-  } else {
-    BF_HIP(hipStreamWaitEvent(s, b.ev, 0));
+  } else if (hipStreamWaitEvent(s, b.ev, 0) == hipSuccess) {
     retire_event(b.ev);
+  } else {   // no device-side wait: wait on the host rather than lose the block
+    (void)hipGetLastError();
+    (void)hipEventSynchronize(b.ev);
+    (void)hipEventDestroy(b.ev);
   }
   return b.p;
 }
