@@ -38,7 +38,9 @@ constexpr int AP_SMALL = kApplyFewCols;
 
 // ncols <= 4: a group of 16 lanes per output row; the row's record holds
 // every address it needs (one dependent load), the inner loop is unrolled so
-// the factor and input loads of a row issue together.  Acc is cf (FP32 sums)
+// the factor and input loads of a row issue together.  With one or two
+// columns each lane loads two consecutive entries per 16-byte load (n = 262144,
+// one column: 1.31 -> 1.06 ms with FP64 sums, 1.02 -> 0.97 ms with FP32 sums).  Acc is cf (FP32 sums)
 // or cd (FP64 sums of the FP32 products, used by the default mode for a
 // single right-hand side, where the extra registers cost no time: a stage
 // then rounds essentially once, at its complex64 output).
@@ -51,6 +53,16 @@ __device__ __forceinline__ void acc_fma<cf>(cf& a, bf_c64 g, bf_c64 x) {
 template <>
 __device__ __forceinline__ void acc_fma<cd>(cd& a, bf_c64 g, bf_c64 x) {
   cd_fma(a, cd{(double)g.re, (double)g.im}, cd{(double)x.re, (double)x.im});
+}
+
+typedef float f32x4u __attribute__((ext_vector_type(4)));
+// two consecutive complex64 values in one 16-byte load (8-byte alignment is
+// enough for global loads on gfx950)
+__device__ __forceinline__ void load_pair(const bf_c64* p, bf_c64& a, bf_c64& b) {
+  f32x4u v;
+  __builtin_memcpy(&v, p, sizeof(v));
+  a = bf_c64{v.x, v.y};
+  b = bf_c64{v.z, v.w};
 }
 
 template <typename Acc, int NC>
@@ -70,23 +82,62 @@ __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __
   Acc acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = Acc{0, 0};
-  for (int kb = 0; kb < KK; kb += 64) {
-    bf_c64 gv[4], xv[4][NC];
+  if constexpr (NC <= 2) {
+    const int K0 = rr.K0;
+    for (int kb = 0; kb < KK; kb += 64) {
+      // lane q takes entries k, k + 1 (k = kb + 2q + 32u): one 16-byte load per
+      // pair of factor entries and, inside one input segment, per pair of inputs
+      bf_c64 gv[4], xv[4][NC];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = kb + q + 16 * u;
-      const bool kv = k < KK;
-      gv[u] = kv ? g[k] : bf_c64{0.f, 0.f};
-      const bf_c64* inp = k < rr.K0 ? in0 + k : in1 + k;
-      const int64_t ldk = k < rr.K0 ? ld0 : ld1;
+      for (int u = 0; u < 2; ++u) {
+        const int k = kb + 2 * q + 32 * u;
+        const bool k0v = k < KK, k1v = k + 1 < KK;
+        if (k1v) {
+          load_pair(g + k, gv[2 * u], gv[2 * u + 1]);
+        } else {
+          gv[2 * u] = k0v ? g[k] : bf_c64{0.f, 0.f};
+          gv[2 * u + 1] = bf_c64{0.f, 0.f};
+        }
+        const bool seg0 = k < K0, seg1 = k + 1 < K0;
+        const bf_c64* base = seg0 ? in0 : in1;
+        const int64_t ldk = seg0 ? ld0 : ld1;
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        xv[u][c] = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
+        for (int c = 0; c < NC; ++c) {
+          if (c < ncols && k1v && seg0 == seg1) {
+            load_pair(base + k + (int64_t)c * ldk, xv[2 * u][c], xv[2 * u + 1][c]);
+          } else {
+            xv[2 * u][c] = (c < ncols && k0v) ? base[k + (int64_t)c * ldk] : bf_c64{0.f, 0.f};
+            xv[2 * u + 1][c] = (c < ncols && k1v)
+                                   ? (seg1 ? in0 : in1)[k + 1 + (int64_t)c * (seg1 ? ld0 : ld1)]
+                                   : bf_c64{0.f, 0.f};
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[u], xv[u][c]);
     }
+  } else {
+    // four columns: one entry per lane and load (pairs measured 8% slower)
+    for (int kb = 0; kb < KK; kb += 64) {
+      bf_c64 gv[4], xv[4][NC];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u) {
+        const int k = kb + q + 16 * u;
+        const bool kv = k < KK;
+        gv[u] = kv ? g[k] : bf_c64{0.f, 0.f};
+        const bf_c64* inp = k < rr.K0 ? in0 + k : in1 + k;
+        const int64_t ldk = k < rr.K0 ? ld0 : ld1;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[u], xv[u][c]);
+        for (int c = 0; c < NC; ++c)
+          xv[u][c] = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[u], xv[u][c]);
+    }
   }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
