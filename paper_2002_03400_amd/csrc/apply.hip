@@ -36,11 +36,13 @@ struct ApplyBufs {
 
 constexpr int AP_SMALL = kApplyFewCols;
 
-// ncols <= 4: a group of 16 lanes per output row; the row's record holds
-// every address it needs (one dependent load), the inner loop is unrolled so
-// the factor and input loads of a row issue together.  With one or two
-// columns each lane loads two consecutive entries per 16-byte load (n = 262144,
-// one column: 1.31 -> 1.06 ms with FP64 sums, 1.02 -> 0.97 ms with FP32 sums).  Acc is cf (FP32 sums)
+// ncols <= 4: a group of AP_LPR = 8 lanes per output row (32 rows per
+// workgroup); the row's record holds every address it needs (one dependent
+// load), the inner loop is unrolled so the factor and input loads of a row
+// issue together.  With one or two columns each lane loads two consecutive
+// entries per 16-byte load.  At n = 262144, one column: 1.31 ms with 16 lanes
+// and 8-byte loads, 1.06 ms with pairs, 0.84 ms with pairs on 8 lanes (FP64
+// sums); four columns 1.88 -> 1.52 ms on 8 lanes.  Acc is cf (FP32 sums)
 // or cd (FP64 sums of the FP32 products, used by the default mode for a
 // single right-hand side, where the extra registers cost no time: a stage
 // then rounds essentially once, at its complex64 output).
@@ -65,13 +67,15 @@ __device__ __forceinline__ void load_pair(const bf_c64* p, bf_c64& a, bf_c64& b)
   b = bf_c64{v.z, v.w};
 }
 
+constexpr int AP_LPR = 8;   // lanes per output row of the few-column kernel
+
 template <typename Acc, int NC>
 __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __restrict__ rows,
                                                            int32_t nrows,
                                                            const bf_c64* __restrict__ G,
                                                            ApplyBufs B, int32_t ncols) {
-  const int q = threadIdx.x & 15;
-  const int64_t R = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int q = threadIdx.x & (AP_LPR - 1);
+  const int64_t R = (int64_t)blockIdx.x * (256 / AP_LPR) + (threadIdx.x / AP_LPR);
   const bool live = R < nrows;
   const ApplyRowRec rr = rows[live ? R : 0];
   const int KK = live ? rr.KK : 0;
@@ -84,13 +88,13 @@ __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __
   for (int c = 0; c < NC; ++c) acc[c] = Acc{0, 0};
   if constexpr (NC <= 2) {
     const int K0 = rr.K0;
-    for (int kb = 0; kb < KK; kb += 64) {
-      // lane q takes entries k, k + 1 (k = kb + 2q + 32u): one 16-byte load per
+    for (int kb = 0; kb < KK; kb += 4 * AP_LPR) {
+      // lane q takes entries k, k + 1 (k = kb + 2q + 16u): one 16-byte load per
       // pair of factor entries and, inside one input segment, per pair of inputs
       bf_c64 gv[4], xv[4][NC];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int k = kb + 2 * q + 32 * u;
+        const int k = kb + 2 * q + 2 * AP_LPR * u;
         const bool k0v = k < KK, k1v = k + 1 < KK;
         if (k1v) {
           load_pair(g + k, gv[2 * u], gv[2 * u + 1]);
@@ -120,11 +124,11 @@ __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __
     }
   } else {
     // four columns: one entry per lane and load (pairs measured 8% slower)
-    for (int kb = 0; kb < KK; kb += 64) {
+    for (int kb = 0; kb < KK; kb += 4 * AP_LPR) {
       bf_c64 gv[4], xv[4][NC];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int k = kb + q + 16 * u;
+        const int k = kb + q + AP_LPR * u;
         const bool kv = k < KK;
         gv[u] = kv ? g[k] : bf_c64{0.f, 0.f};
         const bf_c64* inp = k < rr.K0 ? in0 + k : in1 + k;
@@ -141,8 +145,8 @@ __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __
   }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    acc[c].re = row16_sum(acc[c].re);
-    acc[c].im = row16_sum(acc[c].im);
+    acc[c].re = row8_sum(acc[c].re);
+    acc[c].im = row8_sum(acc[c].im);
   }
   if (live && q == 0) {
     bf_c64* out = B.p[rr.out_buf] + rr.out;
@@ -487,7 +491,7 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
   if (ncols <= AP_SMALL) {
     // the row records address column-major buffers
     for (int i = 0; i < 4; ++i) BF_CHECK(rss[i] == 1, BF_EINVAL, "few-column apply needs column-major buffers");
-    const dim3 grid((unsigned)((nrows + 15) / 16));
+    const dim3 grid((unsigned)((nrows + 256 / AP_LPR - 1) / (256 / AP_LPR)));
     const int nc = (int)ncols;
 #define AP_STREAM(ACC, N) \
     hipLaunchKernelGGL((apply_stream_kernel<ACC, N>), grid, dim3(256), 0, s, rows_dev, nrows, G, B, nc)

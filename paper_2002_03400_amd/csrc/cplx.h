@@ -88,6 +88,24 @@ __device__ __forceinline__ double row16_sum<double>(double v) {
   return v;
 }
 
+// The same over each group of 8 lanes (the first three steps).
+template <typename T>
+__device__ __forceinline__ T row8_sum(T v);
+template <>
+__device__ __forceinline__ float row8_sum<float>(float v) {
+  v += dpp_f32<0xB1>(v);
+  v += dpp_f32<0x4E>(v);
+  v += dpp_f32<0x141>(v);
+  return v;
+}
+template <>
+__device__ __forceinline__ double row8_sum<double>(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  return v;
+}
+
 // Wavefront (64 lanes) sum, every lane gets the result: row sums as above,
 // then (row 0 + row 1) + (row 2 + row 3) from lanes 0, 16, 32, 48.  Fixed
 // order, so results are deterministic.  All 64 lanes must be active.
