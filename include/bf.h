@@ -410,6 +410,18 @@ int bf_operator_destroy(bf_operator* op);
 enum { BF_PREC_FP64 = 0, BF_PREC_BF16X3 = 1, BF_PREC_FP32 = 2 };
 int bf_op_set_precision(bf_operator* op, int precision);
 
+/* Tile-width autotuner of the built-in black boxes (off by default; for
+ * callers that construct many operators of a few shapes).  When enabled, the
+ * first split-BF16 product of each shape class (operator kind, column count,
+ * and the powers of two at or above the row count, inner length and segment
+ * count) runs once per candidate column-chunk bound (48, 64, 80 columns),
+ * timed on its stream, and later products of the class use the fastest.  The
+ * candidates give bitwise the same products, so results never depend on it;
+ * the tuning product synchronizes its stream once.  bf_autotune_entries
+ * reports how many shape classes have been tuned. */
+int bf_set_autotune(int enable);
+int bf_autotune_entries(int64_t* entries);
+
 /* Arithmetic of bf_apply (and of the factors as a black box, bf_op_factors)
  * for F (eq. hybrid_butterfly_mat, complex64 data in both modes):
  *   BF_PREC_FP32   : FP32 multiply-adds and sums on the vector ALUs;

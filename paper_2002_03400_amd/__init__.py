@@ -103,6 +103,8 @@ SIGNATURES = {
                             C.POINTER(_P)]),
     "bf_free": (C.c_int, [_P, _P]),
     "bf_release_cached_memory": (C.c_int, []),
+    "bf_set_autotune": (C.c_int, [C.c_int]),
+    "bf_autotune_entries": (C.c_int, [C.POINTER(C.c_int64)]),
     "bf_strerror": (C.c_char_p, [C.c_int]),
     "bf_last_error": (C.c_char_p, []),
     "bf_server_create": (C.c_int, [C.POINTER(bf_server_opts), C.POINTER(_P)]),
@@ -505,6 +507,18 @@ def release_cached_memory():
     """Give back the device and pinned host blocks the library keeps for
     reuse after factors and temporaries are freed (bf_release_cached_memory)."""
     _check(lib().bf_release_cached_memory(), "bf_release_cached_memory")
+
+
+def set_autotune(enable=True):
+    """Tile-width autotuner of the built-in black boxes (bf_set_autotune)."""
+    _check(lib().bf_set_autotune(1 if enable else 0), "bf_set_autotune")
+
+
+def autotune_entries() -> int:
+    """Shape classes the autotuner has timed so far."""
+    n = C.c_int64(0)
+    _check(lib().bf_autotune_entries(C.byref(n)), "bf_autotune_entries")
+    return n.value
 
 
 def profile_start():

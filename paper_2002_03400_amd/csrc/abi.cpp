@@ -1076,6 +1076,17 @@ int bf_op_compose(const bf_operator* a1, const bf_operator* a2, bf_operator* out
   return BF_OK;
 }
 
+int bf_set_autotune(int enable) {
+  set_autotune(enable);
+  return BF_OK;
+}
+
+int bf_autotune_entries(int64_t* entries) {
+  if (!entries) return BF_EINVAL;
+  *entries = autotune_entries();
+  return BF_OK;
+}
+
 int bf_op_set_precision(bf_operator* op, int precision) {
   if (!op || !op->user || (precision != BF_PREC_FP64 && precision != BF_PREC_BF16X3))
     return BF_EINVAL;

@@ -283,6 +283,9 @@ struct PointSet {     // structure-of-arrays FP64 coordinates on the device
 };
 // Y[:, g*ncols + c] = sum_{j in seg_g} E(i, j) X[j, c], E = kernel entries of
 // op(A) (sign = +1: A, sign = -1: A^H, points swapped by the caller).
+// Black-box tile-width autotuner (see matfree.hip); process-wide.
+void set_autotune(int on);
+int64_t autotune_entries();
 void launch_segkernel(int prec, PointSet out_pts, int64_t nout, PointSet in_pts, int64_t nin,
                       double k_over_2pi, int sign, const bf_c64* X, int64_t ldx, int64_t ncols,
                       bf_c64* Y, int64_t ldy, const int64_t* seg_host, int32_t nseg,

@@ -18,6 +18,11 @@
 // 10^4..10^5 terms of one output would carry a relative rounding error of
 // order 1e-6..1e-5 -- the size of the tolerances of interest, inflating every
 // sampled rank -- so products are accumulated in FP64 on the matrix cores.
+#include <array>
+#include <atomic>
+#include <map>
+#include <mutex>
+
 #include "bf_internal.h"
 #include "cplx.h"
 
@@ -70,6 +75,7 @@ __device__ __forceinline__ cf cis_pi(double a, double b, float amp) {
 // cos even, and every rounding here and in cis_pi is symmetric (q = -q'
 // exactly, ties to even), so it is exactly the conjugate.
 struct SegEntry {
+  static constexpr int kKind = 1;
   PointSet out, in;
   double k2;   // +-k / pi: k r in half revolutions, the sign selecting A or conj
   double k2h;  // k2 / 2
@@ -88,6 +94,7 @@ struct SegEntry {
 
 // The same kernel on 3D points (eq. 3dkernel: the two semi-spheres).
 struct Seg3Entry {
+  static constexpr int kKind = 2;
   PointSet out, in;
   double k2, k2h;
   struct Row { double x, y, z; };
@@ -108,6 +115,7 @@ struct Seg3Entry {
 // formed in FP64 with one rounding before the reduction.
 // Forward: output index j (row), inner index k (xi = k - n/2).
 struct FioEntry {
+  static constexpr int kKind = 3;
   int64_t n;
   double inv_n2;     // 2 / n
   const double* cx;  // c(x_j), FP64
@@ -122,6 +130,7 @@ struct FioEntry {
 // Adjoint: output index k, inner index j: conj(A_jk), from the negated phase
 // (exact, as for SegEntry).
 struct FioAdjEntry {
+  static constexpr int kKind = 4;
   int64_t n;
   double inv_n2;
   const double* cx;
@@ -135,6 +144,7 @@ struct FioAdjEntry {
 };
 
 struct DenseEntry {
+  static constexpr int kKind = 5;
   const bf_c64* A;
   int64_t lda;
   int adjoint;
@@ -589,6 +599,32 @@ static void launch_chunk_bf16(const E& e, int64_t nout, const uint16_t* Xp, int6
                       nsplit, inexact, s);
 }
 
+// ---- tile-width autotuner -------------------------------------------------
+// Off by default (bf_set_autotune).  When on, the first split-BF16 product of
+// each shape class (operator kind, column count, and the powers of two at or
+// above the output rows, input points and segment count) runs once with each
+// column-chunk bound in {48, 64, 80} -- the 48-, 64- and 80-column tiles --
+// timed with events on its stream, and the fastest bound is kept for the
+// class.  Every chunking gives bitwise the same products (a column's sums do
+// not depend on the other columns of its tile; split-K follows the row tiles
+// only), so the candidates' outputs are interchangeable and tuning changes
+// speed only.  The first product of a class synchronizes its stream once.
+static std::atomic<int> g_autotune{0};
+static std::mutex g_tune_mu;
+static std::map<std::array<int64_t, 5>, int64_t> g_tuned;
+
+void set_autotune(int on) { g_autotune.store(on ? 1 : 0); }
+int64_t autotune_entries() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int64_t)g_tuned.size();
+}
+
+static int64_t pow2_at_least(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
 template <class E>
 static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const bf_c64* X,
                         int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
@@ -660,27 +696,65 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
 
   DevBuf<bf_c128> part;
   if (nsplit > 1) part = DevBuf<bf_c128>((size_t)nsplit * ycols * nout, s);
-  const int64_t maxw = bf16 ? 80 : 48;
-  const int64_t nchunk = (ncols + maxw - 1) / maxw;
-  const int64_t cw = (ncols + nchunk - 1) / nchunk;   // balanced widths <= maxw
-  for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
-    const int32_t w = (int32_t)std::min<int64_t>(cw, ncols - c0);
-    if (bf16) {
-      if (nsplit > 1)
-        launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, part.p, nout,
-                          ycols, seg_dev.p, pofs_dev, nseg, nsplit, inexact, s);
-      else
-        launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols,
-                          seg_dev.p, pofs_dev, nseg, nsplit, inexact, s);
-    } else {
-      if (nsplit > 1)
-        launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, part.p, nout, ycols,
-                     seg_dev.p, nseg, nsplit, s);
-      else
-        launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols, seg_dev.p,
-                     nseg, nsplit, s);
+  // one product, in column chunks of at most maxw columns (balanced widths)
+  auto run_chunks = [&](int64_t maxw) {
+    const int64_t nchunk = (ncols + maxw - 1) / maxw;
+    const int64_t cw = (ncols + nchunk - 1) / nchunk;
+    for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
+      const int32_t w = (int32_t)std::min<int64_t>(cw, ncols - c0);
+      if (bf16) {
+        if (nsplit > 1)
+          launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, part.p, nout,
+                            ycols, seg_dev.p, pofs_dev, nseg, nsplit, inexact, s);
+        else
+          launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, Y, ldy,
+                            ycols, seg_dev.p, pofs_dev, nseg, nsplit, inexact, s);
+      } else {
+        if (nsplit > 1)
+          launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, part.p, nout, ycols,
+                       seg_dev.p, nseg, nsplit, s);
+        else
+          launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, Y, ldy, ycols,
+                       seg_dev.p, nseg, nsplit, s);
+      }
+    }
+  };
+  int64_t maxw = bf16 ? 80 : 48;
+  hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+  if (bf16 && ncols > 48 && g_autotune.load() && hipStreamIsCapturing(s, &cst) == hipSuccess &&
+      cst == hipStreamCaptureStatusNone) {
+    const std::array<int64_t, 5> key{E::kKind, ncols, pow2_at_least(nout),
+                                     pow2_at_least(g_matfree_nin), pow2_at_least(nseg)};
+    bool known = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tuned.find(key);
+      if (it != g_tuned.end()) { known = true; maxw = it->second; }
+    }
+    if (!known) {
+      const int64_t cand[3] = {48, 64, 80};
+      hipEvent_t ev[4];
+      for (auto& x : ev) BF_HIP(hipEventCreate(&x));
+      BF_HIP(hipEventRecord(ev[0], s));
+      for (int i = 0; i < 3; ++i) {
+        run_chunks(cand[i]);
+        BF_HIP(hipEventRecord(ev[i + 1], s));
+      }
+      BF_HIP(hipEventSynchronize(ev[3]));
+      float best_ms = 0.f;
+      int64_t best = cand[2];
+      for (int i = 0; i < 3; ++i) {
+        float ms = 0.f;
+        BF_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+        if (i == 0 || ms < best_ms) { best_ms = ms; best = cand[i]; }
+      }
+      for (auto& x : ev) (void)hipEventDestroy(x);
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tuned[key] = best;
+      maxw = 0;   // the product is already computed (by every candidate alike)
     }
   }
+  if (maxw > 0) run_chunks(maxw);
   if (nsplit > 1) {
     int64_t tot = nout * ycols;
     ProfScope ps(BF_KC_OTHER, s, 0.0, 16.0 * nsplit * tot + 8.0 * tot);

@@ -159,6 +159,40 @@ def test_segkernel_wide_and_split(bf):
     assert _rel(Y, ref.matvec(X)) < 3e-6
 
 
+def test_autotuned_tile_widths_do_not_change_products(bf):
+    """The opt-in tile-width autotuner times candidate column chunkings on the
+    first product of a shape class and reuses the fastest; every candidate
+    gives bitwise the same product, so tuned, cached and untuned products agree
+    exactly, and so do constructions."""
+    from oracle import philox
+    n = 6000
+    g = wl.segment_pair(n, ppw=8.0, m=3000)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    say("autotune")
+    X = _cg(np.random.default_rng(9), n, 70)
+    Xb = philox.round_bf16(X.real) + 1j * philox.round_bf16(X.imag)
+    ref = op.matvec(_t(Xb)).cpu().numpy()
+    ref_g = op.matvec(_t(X)).cpu().numpy()
+    gg = wl.segment_pair(2048, ppw=8.0)
+    opc = bf.segkernel(gg.targets, gg.sources, gg.k)
+    fa = bf.construct(opc, 1e-6, 32, seed=21).export()
+    bf.set_autotune(True)
+    try:
+        n0 = bf.autotune_entries()
+        tuned = op.matvec(_t(Xb)).cpu().numpy()
+        n1 = bf.autotune_entries()
+        cached = op.matvec(_t(Xb)).cpu().numpy()
+        tuned_g = op.matvec(_t(X)).cpu().numpy()
+        fb = bf.construct(opc, 1e-6, 32, seed=21).export()
+        fc = bf.construct(opc, 1e-6, 32, seed=21).export()
+    finally:
+        bf.set_autotune(False)
+    assert n1 == n0 + 1
+    assert np.array_equal(tuned, ref) and np.array_equal(cached, ref)
+    assert np.array_equal(tuned_g, ref_g)
+    assert np.array_equal(fa, fb) and np.array_equal(fa, fc)
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
 def test_helmholtz3d_products(bf, prec):
     """eq. 3dkernel between the two semi-spheres: plain and structured
