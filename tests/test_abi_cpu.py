@@ -44,6 +44,11 @@ def test_argument_errors_without_device():
     assert lib.bf_op_fio(7, None) == -1
     assert lib.bf_set_apply_precision(None, 1) == -1
     assert lib.bf_op_set_precision(None, 1) == -1
+    # the autotuner switch and its counter touch no device
+    assert lib.bf_autotune_entries(None) == -1
+    n = C.c_int64(-1)
+    assert lib.bf_set_autotune(0) == 0
+    assert lib.bf_autotune_entries(C.byref(n)) == 0 and n.value == 0
 
 
 def test_precision_enum_matches_header():
