@@ -100,7 +100,8 @@ static void ensure_pool(int dev) {
 // recorded on the stream that freed it, waited for before the block is handed
 // out again (by the new user's stream on the device, so the host never waits).
 // At most kDevKeepBytes are kept per device; an allocation that fails gives
-// them all back and retries.
+// them all back and retries, and bf_release_cached_memory gives them back on
+// request.
 namespace {
 struct BlockInfo {
   size_t cap;
@@ -342,7 +343,7 @@ void dev_free(void* p, hipStream_t s) {
 // blocks: pinning and unpinning many MB costs milliseconds per call
 // (hipHostFree also waits for the device), which would otherwise sit between
 // consecutive requests.  At most kPinnedKeep blocks are kept; they stay
-// pinned until the process ends.
+// pinned until bf_release_cached_memory or the end of the process.
 namespace {
 struct PinnedBlock {
   char* h;
