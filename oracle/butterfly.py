@@ -86,7 +86,7 @@ def _H(a):
 
 # ---------------------------------------------------------------- Alg. 2 --
 
-def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Factors:
+def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None, rule="fro") -> Factors:
     """Alg. 2.  ``op`` has ``m, n, matvec(X, support), rmatvec(X, support)``.
 
     ``lm`` is the level of the centre factor B (eq. hybrid_butterfly_mat);
@@ -94,7 +94,11 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Facto
     the column-wise factorization of Sec. 3.3.1 (E^0 = B^0 V^0) and lm = L
     the row-wise one of Sec. 3.3.2 (F^L = U^L B^L), the variants Sec. 4 says
     the same algorithm builds at a higher cost.  Negative lm counts from
-    L + 1 (-1 is L)."""
+    L + 1 (-1 is L).
+
+    ``rule`` is the truncation rule of Alg. 1 (``cpqr.cpqr_truncated``):
+    "fro", the relative Frobenius tail of the sample (the reading used
+    throughout), or "diag", |R_kk| <= eps |R_11|, a diagnostic only."""
     m, n = op.m, op.n
     if m <= 0 or n <= 0:
         raise ValueError("empty operator")
@@ -123,13 +127,13 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Facto
     while True:
         cap(r)
         s = r + p
-        G = philox.sample_block(seed, philox.tag(philox.PHASE_V0, it, 0), 0, m, s)
+        G = philox.gaussian_block(seed, philox.tag(philox.PHASE_V0, it, 0), 0, m, s)
         Yp = op.rmatvec(G)
         cols["rmatvec"] += s
         F.V = []
         for j in range(1 << L):
             lo, hi = F.srange(L, j)
-            Q, k = range_basis(Yp[lo:hi], tol)
+            Q, k = range_basis(Yp[lo:hi], tol, rule)
             F.V.append(Q)
             F.kV[0][(0, j)] = k
         cols["v_iters"] += 1
@@ -143,13 +147,13 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Facto
     while True:
         cap(r)
         s = r + p
-        Om = philox.sample_block(seed, philox.tag(philox.PHASE_U0, it, 0), 0, n, s)
+        Om = philox.gaussian_block(seed, philox.tag(philox.PHASE_U0, it, 0), 0, n, s)
         Y = op.matvec(Om)
         cols["matvec"] += s
         F.U = []
         for i in range(1 << L):
             lo, hi = F.trange(L, i)
-            Q, k = range_basis(Y[lo:hi], tol)
+            Q, k = range_basis(Y[lo:hi], tol, rule)
             F.U.append(Q)
             F.kU[L][(i, 0)] = k
         cols["u_iters"] += 1
@@ -165,7 +169,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Facto
                     for j in range(1 << (L - l))) + p
             lo, hi = F.trange(l, i)
             G = np.zeros((m, s), np.complex128)
-            G[lo:hi] = philox.sample_block(seed, philox.tag(philox.PHASE_W, l, i), lo, hi - lo, s)
+            G[lo:hi] = philox.gaussian_block(seed, philox.tag(philox.PHASE_W, l, i), lo, hi - lo, s)
             Yp = op.rmatvec(G, support=(lo, hi))
             cols["rmatvec"] += s
             # V-chain^H: V^0 then W^1 .. W^{l-1} on the T-ancestors of tau
@@ -176,7 +180,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Facto
                      for jj in range(1 << (L - lp))]
             for j in range(1 << (L - l)):
                 Z = np.vstack([P[2 * j], P[2 * j + 1]])
-                Q, k = range_basis(Z, tol)
+                Q, k = range_basis(Z, tol, rule)
                 F.W[l][(i, j)] = Q
                 F.kV[l][(i, j)] = k
 
@@ -190,7 +194,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Facto
             s += p
             lo, hi = F.srange(L - l, j)
             Om = np.zeros((n, s), np.complex128)
-            Om[lo:hi] = philox.sample_block(seed, philox.tag(philox.PHASE_R, l, j), lo, hi - lo, s)
+            Om[lo:hi] = philox.gaussian_block(seed, philox.tag(philox.PHASE_R, l, j), lo, hi - lo, s)
             Y = op.matvec(Om, support=(lo, hi))
             cols["matvec"] += s
             # U-chain^H: U^L then R^{L-1} .. R^{l+1} on the S-ancestors of nu
@@ -202,7 +206,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Facto
             Zs = []
             for i in range(1 << l):
                 Z = np.vstack([P[2 * i], P[2 * i + 1]])
-                Q, k = range_basis(Z, tol)
+                Q, k = range_basis(Z, tol, rule)
                 F.R[l][(i, j)] = Q
                 F.kU[l][(i, j)] = k
                 Zs.append(Z)
@@ -217,7 +221,7 @@ def construct(op, tol, leaf, p=2, r0=4, seed=0, max_rank=None, lm=None) -> Facto
         # B_{i,0} = (U_i^H A Omega)(V_{i,0}^H Omega)^+ with the leaf column
         # bases themselves (no R level) and the full-height row bases
         s = max(max(F.kU[L][(i, 0)], F.kV[L][(i, 0)]) for i in range(1 << L)) + p
-        Om = philox.sample_block(seed, philox.tag(philox.PHASE_R, L, 0), 0, n, s)
+        Om = philox.gaussian_block(seed, philox.tag(philox.PHASE_R, L, 0), 0, n, s)
         Y = op.matvec(Om)
         cols["matvec"] += s
         X = _x_chain(F, Om, 0)

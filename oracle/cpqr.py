@@ -13,14 +13,21 @@ norms are recomputed from the trailing submatrix at every step, never
 downdated.  Reflectors are complex Householder H = I - 2 v v^H / (v^H v) with
 v = x - alpha e_1, alpha = -exp(i arg x_0) ||x||, so H x = alpha e_1 and the
 diagonal of R is alpha (no cancellation when forming v_0).
+
+``rule="diag"`` selects the other reading of the tolerance, kept only as a
+diagnostic: stop at the first k >= 1 whose pivot |R[k, k]| (the largest
+trailing column norm, which pivoting brings to the diagonal) is at most
+eps |R[0, 0]|.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def cpqr_truncated(W: np.ndarray, eps: float):
+def cpqr_truncated(W: np.ndarray, eps: float, rule: str = "fro"):
     """Return (Q_k, k, perm, R_k) with W[:, perm] ~= Q_k R_k, Q_k (M x k)."""
+    if rule not in ("fro", "diag"):
+        raise ValueError(f"unknown truncation rule {rule!r}")
     A = np.array(W, dtype=np.complex128, copy=True)
     M, N = A.shape
     perm = np.arange(N)
@@ -30,19 +37,25 @@ def cpqr_truncated(W: np.ndarray, eps: float):
     kmax = min(M, N)
     refl = []
     rank = kmax
+    r00 = 0.0
     for k in range(kmax):
+        norms = np.sum(np.abs(A[k:, k:]) ** 2, axis=0)
         if k >= 1:
-            trailing = np.linalg.norm(A[k:, k:])
-            if trailing <= eps * total:
+            if rule == "fro":
+                stop = np.linalg.norm(A[k:, k:]) <= eps * total
+            else:
+                stop = np.sqrt(norms.max()) <= eps * r00
+            if stop:
                 rank = k
                 break
-        norms = np.sum(np.abs(A[k:, k:]) ** 2, axis=0)
         p = k + int(np.argmax(norms))          # first maximum: lowest index
         if p != k:
             A[:, [k, p]] = A[:, [p, k]]
             perm[[k, p]] = perm[[p, k]]
         x = A[k:, k]
         xn = np.linalg.norm(x)
+        if k == 0:
+            r00 = xn
         phase = x[0] / abs(x[0]) if x[0] != 0 else 1.0
         alpha = -phase * xn
         v = x.copy()
@@ -61,7 +74,7 @@ def cpqr_truncated(W: np.ndarray, eps: float):
     return Q, rank, perm, R
 
 
-def range_basis(W: np.ndarray, eps: float):
+def range_basis(W: np.ndarray, eps: float, rule: str = "fro"):
     """Alg. 1 step 3 on a sample W = A Omega: orthonormal basis Q_k and rank k."""
-    Q, k, _, _ = cpqr_truncated(W, eps)
+    Q, k, _, _ = cpqr_truncated(W, eps, rule)
     return Q, k

@@ -16,12 +16,9 @@ Weyl-sequence key schedule.  The complex normal has E|g|^2 = 1 (real and
 imaginary parts N(0, 1/2)); complex data are the paper's "trivial extension"
 of its real algorithms (Sec. 2.1).
 
-The random matrices of the construction use ``sample_block``: the same
-draw with the real and imaginary parts each rounded to the nearest BF16 value
-(8 significant bits, ties to even).  The paper asks only for Gaussian random
-matrices; the rounded entries (each part within 2^-8 relative of the draw)
-stay i.i.d. and symmetric with variance 1/2 per part to within 1e-5, and
-being exact in BF16 they let the device multiply them without splitting.
+The construction's random matrices (``gaussian_block``) are these draws
+themselves: i.i.d. complex normal entries, as Alg. 1 step 1 and Sec. 4.1 ask.
+How a device stores or rounds them is its own choice and not the oracle's.
 
 Tags: ``tag(phase, level, node) = phase << 56 | level << 40 | node``.
 """
@@ -119,22 +116,3 @@ def gaussian_block(seed: int, tg: int, row0: int, nrows: int, ncols: int) -> np.
     rad = np.sqrt(-2.0 * np.log(u0)) / math.sqrt(2.0)
     ang = 2.0 * math.pi * u1
     return (rad * np.cos(ang) + 1j * (rad * np.sin(ang))).astype(np.complex128)
-
-
-def round_bf16(x: np.ndarray) -> np.ndarray:
-    """Round FP64 values to the nearest BF16 value (8 significant bits, ties to
-    even), returned as FP64.  Integer rounding of the 52-bit fraction to 7 bits:
-    add half an ulp minus one plus the kept lsb, then clear the dropped bits."""
-    b = np.ascontiguousarray(x, dtype=np.float64).copy().view(np.uint64)
-    drop = np.uint64((1 << 45) - 1)            # the 45 dropped fraction bits
-    half = np.uint64((1 << 44) - 1)            # half an ulp of the kept bits, minus one
-    lsb = (b >> np.uint64(45)) & np.uint64(1)
-    b = (b + half + lsb) & ~drop
-    return b.view(np.float64)
-
-
-def sample_block(seed: int, tg: int, row0: int, nrows: int, ncols: int) -> np.ndarray:
-    """Random-matrix entries of the construction: ``gaussian_block`` with the
-    real and imaginary parts rounded to BF16."""
-    g = gaussian_block(seed, tg, row0, nrows, ncols)
-    return (round_bf16(g.real) + 1j * round_bf16(g.imag)).astype(np.complex128)

@@ -1,5 +1,6 @@
 """Conversion between the oracle's Factors and the library's canonical factor
-layout (pure data reshuffling; used by the parity tests only)."""
+layout (pure data reshuffling; used by the parity tests only), and test inputs
+that are exact in BF16."""
 import numpy as np
 
 from oracle import butterfly as obf
@@ -55,3 +56,13 @@ def canonical_to_oracle(m, n, L, kU, kV, data, lm=None):
     F.V = [take(F.srange(L, j)[1] - F.srange(L, j)[0], kv(0, 0, j)) for j in range(1 << L)]
     assert off == len(data)
     return F
+
+
+def bf16_exact(X):
+    """X with the real and imaginary parts rounded to BF16 by torch's
+    float32 -> bfloat16 conversion (round to nearest even): test inputs that
+    the split-BF16 products take on their exact-input path."""
+    import torch
+    re = torch.from_numpy(np.ascontiguousarray(X.real, np.float32)).to(torch.bfloat16).double().numpy()
+    im = torch.from_numpy(np.ascontiguousarray(X.imag, np.float32)).to(torch.bfloat16).double().numpy()
+    return re + 1j * im

@@ -67,7 +67,7 @@ def test_hemispheres_parity(bf, n, leaf, tol, r0):
     A = op_o.dense()
     rel = np.linalg.norm(A - D) / np.linalg.norm(A)
     say("3D dense reconstruction", rel)
-    assert rel <= 2.0 * e_or + 1e-12
+    assert rel <= 2.0 * e_or
 
 
 def test_progress_reports(bf):

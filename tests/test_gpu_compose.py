@@ -56,12 +56,12 @@ def test_recompress_product(bf, n, leaf):
     e_gpu = np.linalg.norm(F.apply(_t(Om)).cpu().numpy() - exact) / np.linalg.norm(exact)
     e_or = np.linalg.norm(obf.apply(Fo, Om) - exact) / np.linalg.norm(exact)
     say("compose errors oracle", e_or, "gpu", e_gpu, "ranks", F.stats().max_rank)
-    assert e_gpu <= 2 * e_or + 1e-6
+    assert e_gpu <= 2 * e_or
     # the product's adjoint through the recompressed factors
     Z = wl.test_columns(n, 3, 7)
     exactH = r2.rmatvec(r1.rmatvec(Z))
     e_h = np.linalg.norm(F.apply(_t(Z), trans=True).cpu().numpy() - exactH) / np.linalg.norm(exactH)
-    assert e_h <= 2 * e_or + 1e-6
+    assert e_h <= 2 * e_or
 
 
 @pytest.mark.parametrize("n,leaf", [(2048, 16), (3000, 24)])
@@ -92,13 +92,13 @@ def test_fio_construction_and_recompression(bf, n, leaf):
             F.close()
     say("fio errors oracle", e_or, "gpu", errs)
     for e in errs.values():
-        assert e <= 2 * e_or + 1e-6
+        assert e <= 2 * e_or
     # the two black-box precisions agree to the tolerance's order
-    assert abs(errs["bf16x3"] - errs["fp64"]) <= 0.5 * e_or + 1e-6
+    assert abs(errs["bf16x3"] - errs["fp64"]) <= 0.5 * e_or
     G = bf.construct(bf.from_factors(Fk), tol, leaf, seed=32)
     e_re = np.linalg.norm(G.apply(_t(Om)).cpu().numpy() - AOm) / np.linalg.norm(AOm)
     say("fio recompressed", e_re)
     # recompressing a tol-accurate butterfly at tol: errors add at most
-    assert e_re <= errs["bf16x3"] + 2 * e_or + 1e-6
+    assert e_re <= errs["bf16x3"] + 2 * e_or
     G.close()
     Fk.close()

@@ -142,7 +142,7 @@ def test_ragged_and_degenerate_shapes(bf, m, n, leaf):
     e_gpu = _err(AOm, H.apply(_t(Om)).cpu().numpy())
     e_or = _err(AOm, obf.apply(Fo, Om))
     say("ragged errors", e_or, e_gpu)
-    assert e_gpu <= 2 * e_or + 2e-6
+    assert e_gpu <= 2 * e_or
 
 
 def test_rank_cap_error(bf):
@@ -177,7 +177,7 @@ def test_sample_groups(bf, m, n, leaf):
     eo = _err(AOm, obf.apply(Fo, Om))
     say("groups errors", ea, eb, "oracle", eo)
     assert abs(ea - eb) <= 0.05 * ea + 1e-8
-    assert eb <= 2 * eo + 1e-7
+    assert eb <= 2 * eo
     with pytest.raises(bf.BFError):
         bf.construct(op, 1e-6, leaf, seed=12, work_bytes=-1)
 

@@ -11,7 +11,7 @@ from oracle import butterfly as obf
 from oracle import cpqr as ocpqr
 from oracle import operators as ops
 from oracle import philox
-from tests.bfconv import oracle_to_canonical
+from tests.bfconv import bf16_exact, oracle_to_canonical
 
 pytestmark = pytest.mark.gpu
 
@@ -164,13 +164,12 @@ def test_autotuned_tile_widths_do_not_change_products(bf):
     first product of a shape class and reuses the fastest; every candidate
     gives bitwise the same product, so tuned, cached and untuned products agree
     exactly, and so do constructions."""
-    from oracle import philox
     n = 6000
     g = wl.segment_pair(n, ppw=8.0, m=3000)
     op = bf.segkernel(g.targets, g.sources, g.k)
     say("autotune")
     X = _cg(np.random.default_rng(9), n, 70)
-    Xb = philox.round_bf16(X.real) + 1j * philox.round_bf16(X.imag)
+    Xb = bf16_exact(X)
     ref = op.matvec(_t(Xb)).cpu().numpy()
     ref_g = op.matvec(_t(X)).cpu().numpy()
     gg = wl.segment_pair(2048, ppw=8.0)
@@ -225,14 +224,13 @@ def test_segkernel_bf16_exact_inputs(bf, ncols):
     three-product path, general inputs the six-product path, a mix the general
     one; all agree with the FP64 products (ragged chunks, split-K, every tile
     width)."""
-    from oracle import philox
     m, n = 517, 9000
     g = wl.segment_pair(n, ppw=8.0, m=m)
     say("segkernel exact inputs", ncols)
     op = bf.segkernel(g.targets, g.sources, g.k)
     ref = ops.SegmentKernelOp(g.targets, g.sources, g.k)
     X = _cg(np.random.default_rng(ncols), n, ncols)
-    Xb = philox.round_bf16(X.real) + 1j * philox.round_bf16(X.imag)
+    Xb = bf16_exact(X)
     Xm = Xb.copy()
     Xm[1234, ncols - 1] = X[1234, ncols - 1]
     for Z in (Xb, X, Xm):
