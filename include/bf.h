@@ -165,6 +165,25 @@ int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64
 int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
              bf_c64* Y, int64_t ldy, void* stream);
 
+/*
+ * bf_apply without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and results as bf_apply
+ * (launched stage by stage, never through a cached graph, never profiled).
+ * The two ping-pong intermediates live in a fixed scratch array of
+ * bf_apply_noalloc_scratch_bytes() bytes (64 MiB) per device, which the
+ * library holds on every device it runs on until the process ends; they need
+ * 2 x (largest level rank sum) x ncols complex64 values, and larger requests
+ * return BF_EINVAL (nothing is launched).  Every call on a device uses that
+ * device's one array: calls that overlap on one GPU (other streams, other
+ * threads) race and give wrong results, so callers serialize them.  F must
+ * live on the current device.  The first call on a device looks up the
+ * array's address (no allocation).
+ */
+int bf_apply_noalloc(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                     int64_t ncols, bf_c64* Y, int64_t ldy, void* stream);
+int64_t bf_apply_noalloc_scratch_bytes(void);
+
 /* Applies of at most max_cols columns (0 = off, the default) run their L+3
  * stage launches as one captured HIP graph: bf_apply copies X into a private
  * buffer, launches the graph and copies the result out (two device copies

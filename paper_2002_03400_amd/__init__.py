@@ -96,6 +96,8 @@ SIGNATURES = {
     "bf_construct": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, C.c_double, C.c_int64,
                                C.POINTER(bf_opts), _P, C.POINTER(_P)]),
     "bf_apply": (C.c_int, [_P, C.c_int, _P, C.c_int64, C.c_int64, _P, C.c_int64, _P]),
+    "bf_apply_noalloc": (C.c_int, [_P, C.c_int, _P, C.c_int64, C.c_int64, _P, C.c_int64, _P]),
+    "bf_apply_noalloc_scratch_bytes": (C.c_int64, []),
     "bf_stats": (C.c_int, [_P, C.POINTER(bf_info)]),
     "bf_ranks": (C.c_int, [_P, _I32P, _I32P]),
     "bf_export": (C.c_int, [_P, _P, _I64P]),

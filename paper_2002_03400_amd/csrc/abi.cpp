@@ -732,6 +732,16 @@ int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64
   });
 }
 
+int bf_apply_noalloc(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                     int64_t ncols, bf_c64* Y, int64_t ldy, void* stream) {
+  if (!F || !X || !Y || ncols < 0 || (trans != 0 && trans != 1)) return BF_EINVAL;
+  const int64_t rin = trans ? F->m : F->n, rout = trans ? F->n : F->m;
+  if (ldx < rin || ldy < rout) return BF_EINVAL;
+  return guarded([&] { apply_noalloc(F, trans, X, ldx, ncols, Y, ldy, (hipStream_t)stream); });
+}
+
+int64_t bf_apply_noalloc_scratch_bytes(void) { return (int64_t)noalloc_scratch_bytes(); }
+
 int bf_set_apply_precision(bf_factors* F, int precision) {
   if (!F || (precision != BF_PREC_FP32 && precision != BF_PREC_BF16X3)) return BF_EINVAL;
   F->apply_prec = precision;

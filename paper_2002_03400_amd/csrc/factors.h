@@ -88,9 +88,21 @@ struct bf_factors {
 namespace bf {
 // Build the forward and adjoint apply plans (packs the complex64 blocks).
 void build_apply_plans(bf_factors* F, hipStream_t s);
+// The L+3 stage launches of one apply with caller-provided ping-pong
+// intermediates t1, t2 (each room for plan.tmp_rows x ncols values); prof
+// brackets each launch for bf_profile_* (creates events; off for callers that
+// must not allocate).
+void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                      int64_t ncols, bf_c64* Y, int64_t ldy, bf_c64* t1, bf_c64* t2,
+                      hipStream_t s, bool prof);
 // Apply (Y = F X or F^H X), complex64.
 void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
                    bf_c64* Y, int64_t ldy, hipStream_t s);
+// bf_apply_noalloc: run_apply_stages with the intermediates in the library's
+// fixed per-device scratch array (noalloc.hip); BF_EINVAL if they do not fit.
+void apply_noalloc(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
+                   bf_c64* Y, int64_t ldy, hipStream_t s);
+size_t noalloc_scratch_bytes();
 // Canonical-order block list (U, R^{L-1..lm}, B, W^{lm..1}, V).
 std::vector<Block> canonical_blocks(const bf_factors* F);
 }  // namespace bf

@@ -279,9 +279,9 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
 
 // The L+3 stage launches of one apply on stream s (buffers: X, two
 // intermediates, Y).
-static void run_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
-                       int64_t ncols, bf_c64* Y, int64_t ldy, bf_c64* t1, bf_c64* t2,
-                       hipStream_t s) {
+void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                      int64_t ncols, bf_c64* Y, int64_t ldy, bf_c64* t1, bf_c64* t2,
+                      hipStream_t s, bool prof) {
   const ApplyPlan& P = trans ? F->adj : F->fwd;
   const bf_c64* bufs[4] = {X, t1, t2, Y};
   // intermediates row-major above the few-column path (see launch_apply_stage)
@@ -297,9 +297,17 @@ static void run_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t 
     double by = 8.0 * st.macs;
     if (k == 0) by += 8.0 * (double)rin * ncols;
     if (k + 1 == P.stages.size()) by += 8.0 * (double)rout * ncols;
-    ProfScope ps(BF_KC_APPLY, s, 8.0 * st.macs * ncols, by);
-    launch_apply_stage(P.blks.p + st.blk_off, st.nblk, P.rows.p + st.row_off, st.nrows, st.maxMK,
-                       st.maxKK, st.maxM, P.G.p, bufs, lds, rss, ncols, F->apply_prec, s);
+    auto launch = [&] {
+      launch_apply_stage(P.blks.p + st.blk_off, st.nblk, P.rows.p + st.row_off, st.nrows,
+                         st.maxMK, st.maxKK, st.maxM, P.G.p, bufs, lds, rss, ncols,
+                         F->apply_prec, s);
+    };
+    if (prof) {
+      ProfScope ps(BF_KC_APPLY, s, 8.0 * st.macs * ncols, by);
+      launch();
+    } else {
+      launch();
+    }
   }
 }
 
@@ -371,7 +379,7 @@ static bool capture_graph(const bf_factors* F, ApplyGraphCache* c, ApplyGraph& a
   }
   bool ok = true;
   try {
-    run_stages(F, a.trans, a.Xs, rin, a.ncols, a.Ys, rout, a.t1, a.t2, c->cap);
+    run_apply_stages(F, a.trans, a.Xs, rin, a.ncols, a.Ys, rout, a.t1, a.t2, c->cap, true);
   } catch (...) {
     ok = false;
   }
@@ -436,7 +444,7 @@ void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
     return;
   const ApplyPlan& P = trans ? F->adj : F->fwd;
   DevBuf<bf_c64> t1((size_t)P.tmp_rows * ncols, s), t2((size_t)P.tmp_rows * ncols, s);
-  run_stages(F, trans, X, ldx, ncols, Y, ldy, t1.p, t2.p, s);
+  run_apply_stages(F, trans, X, ldx, ncols, Y, ldy, t1.p, t2.p, s, true);
 }
 
 }  // namespace bf
