@@ -42,6 +42,10 @@ METRIC = "factorizations/s + p50/p99 latency at n=64K, rel err ≤1e-6 vs FP64 o
 PEAK_FP32_TFLOPS = 157.3
 VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
 PEAK_HBM_GBS = 8000.0
+# MI355X dense BF16 matrix-core peak (no sparsity): the black-box kernel's
+# complex multiply-adds run there, so its roofline fraction is its algorithmic
+# MAC flops (8 per complex multiply-add of A(:, seg) X(seg, :)) over this peak.
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 
 
 def parse():
@@ -58,10 +62,12 @@ def parse():
                     help="budget of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots", type=int, default=4, help="device slots of the served runs")
-    ap.add_argument("--stream", type=int, default=12,
-                    help="requests of the Poisson stream at the headline size (0 = skip)")
-    ap.add_argument("--mix", type=int, default=0,
-                    help="also run the mixed serving stream with this many requests")
+    ap.add_argument("--stream", type=int, default=64,
+                    help="requests of each Poisson stream at the headline size, run at 0.5x, "
+                         "1x and 2x the measured capacity (0 = skip)")
+    ap.add_argument("--mix", type=int, default=256,
+                    help="requests of the mixed serving stream (0 = skip); run served and "
+                         "through the per-request path")
     ap.add_argument("--apply-burst", type=int, default=0,
                     help="only submit this many 1-column applies at once against one "
                          "factorization of the headline operator, with and without continuous "
@@ -394,26 +400,48 @@ def pct(xs, q):
     return xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def cpu_baseline_leg(geom, F_gpu, args, passes):
-    """The FP64 oracle on the host: (a) the reference rows of the error check,
-    (b) the oracle's construction time estimated from a timed slice of its
-    black-box product (the dominant cost of Alg. 2: every adaptive pass and
-    every sweep level evaluates all m*n kernel entries once)."""
-    import torch
-
+def error_rows(geom, nrows):
+    """FP64 oracle reference of the error check: sampled rows of A times 16
+    Gaussian test columns (Sec. 6 error measure), computed once per operator."""
     import workloads as wl
+    from oracle import operators as ops
+    n = geom.sources.shape[0]
+    Om = wl.test_columns(n, 16, 1001)
+    rows = np.sort(np.random.default_rng(0).choice(n, min(nrows, n), replace=False))
+    ref = ops.segment_kernel_entries(geom.targets, geom.sources, geom.k, rows=rows) @ Om
+    return Om, rows, ref
+
+
+def sampled_err(F_gpu, chk):
+    """Relative error of a GPU factorization on the oracle's sampled rows."""
+    import torch
+    Om, rows, ref = chk
+    got = F_gpu.apply(torch.from_numpy(Om.astype(np.complex64)).cuda()).cpu().numpy()[rows]
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_leg(geom, args, passes):
+    """The FP64 oracle on the host: (a) its construction time at the benchmark
+    size estimated from a timed slice of its black-box product (the dominant
+    cost of Alg. 2: every adaptive pass and every sweep level evaluates all
+    m*n kernel entries once), (b) a whole oracle construction (Alg. 2 end to
+    end) timed at n = 1024, leaf 32, tol 1e-6 for scale."""
+    import workloads as wl
+    from oracle import butterfly as obf
     from oracle import operators as ops
 
     n = args.n
-    # (a) error of the GPU factorization on sampled rows, FP64 reference
-    Om = wl.test_columns(n, 16, 1001)
-    rows = np.sort(np.random.default_rng(0).choice(n, min(args.rows, n), replace=False))
-    ref = ops.segment_kernel_entries(geom.targets, geom.sources, geom.k, rows=rows) @ Om
-    got = F_gpu.apply(torch.from_numpy(Om.astype(np.complex64)).cuda()).cpu().numpy()[rows]
-    rel_err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    if args.no_cpu_baseline:
-        return rel_err, None
-    # (b) time the oracle's matvec on row slices of one pass (s = 40 columns)
+    # (a) the oracle's matvec on row slices of one pass (s = 40 columns)
     op = ops.SegmentKernelOp(geom.targets, geom.sources, geom.k)
     X = wl.test_columns(n, 40, 7)
     slice_rows = 512
@@ -427,12 +455,18 @@ def cpu_baseline_leg(geom, F_gpu, args, passes):
     t = time.perf_counter() - t0
     per_pass = t * n / done
     est = per_pass * passes
+    # (b) a complete oracle construction at n = 1024
+    g1 = wl.segment_pair(1024, ppw=args.ppw)
+    op1 = ops.SegmentKernelOp(g1.targets, g1.sources, g1.k)
+    t0 = time.perf_counter()
+    obf.construct(op1, 1e-6, 32, seed=1)
+    c1_s = time.perf_counter() - t0
     try:
         from threadpoolctl import threadpool_info
         blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         blas = 1
-    return rel_err, {
+    return {
         "value": 1.0 / est, "unit": "factorizations/s", "cores": int(blas),
         "kind": "oracle",
         "sample": (f"oracle FP64 black-box product of {done} of {n} rows of one pass "
@@ -441,6 +475,8 @@ def cpu_baseline_leg(geom, F_gpu, args, passes):
                    f"elementwise numpy single-threaded, BLAS {blas} threads; "
                    f"host cores {os.cpu_count()}"),
         "est_seconds_per_factorization": est,
+        "cpu_model": cpu_model(),
+        "oracle_construction_n1024_s": c1_s,
     }
 
 
@@ -483,10 +519,10 @@ def apply_roofline(bf, F, n, reps=20):
     return out
 
 
-def run_served(bf, reqs, slots, leaf, keep_last=False, batch_cols=0):
+def run_served(bf, reqs, slots, leaf, keep_all=False, batch_cols=0):
     """Replay a request stream in real time through the request engine.
-    Returns (wall seconds, [latency s of constructions], [latency s of applies],
-    last factors or None)."""
+    Returns (server, wall seconds, [latency s of constructions], [latency s of
+    applies], [borrowed factors of every construction] if keep_all else [])."""
     import torch
 
     import workloads as wl
@@ -518,11 +554,10 @@ def run_served(bf, reqs, slots, leaf, keep_last=False, batch_cols=0):
         merged += r.kind != "construct" and info["batch"] > 1
     S.merged_applies = merged
     wall = time.perf_counter() - start
-    last = None
-    if keep_last:
-        last_i = max(i for i, r in enumerate(reqs) if r.kind == "construct")
-        last = S.factors(tickets[last_i])
-    return S, wall, lat_c, lat_a, last
+    kept = []
+    if keep_all:
+        kept = [S.factors(tickets[i]) for i, r in enumerate(reqs) if r.kind == "construct"]
+    return S, wall, lat_c, lat_a, kept
 
 
 def main():
@@ -587,44 +622,61 @@ def main():
     passes = info.v_iters + info.u_iters + info.L
 
     per_request_fs = args.steps / total
+    chk = error_rows(geom, args.rows)
+    rel_err = sampled_err(last, chk)
 
-    # served closed loop: all K requests submitted at once, `slots` in flight
+    # served closed loop: all K requests submitted at once, `slots` in flight;
+    # every served factorization is checked against the oracle rows
     import workloads as wl
     reqs = [wl.Request(0.0, "construct", args.n, args.ppw, args.tol, 3 + k) for k in range(args.steps)]
-    S, wall, lat_c, _, _ = run_served(bf, reqs, args.slots, args.leaf)
+    S, wall, lat_c, _, kept = run_served(bf, reqs, args.slots, args.leaf, keep_all=True)
     served_fs = args.steps / wall
+    served_errs = [sampled_err(Fk, chk) for Fk in kept]
     S.close()
-    stream = None
+    streams = None
     if args.stream > 0:
-        rate = 0.8 * max(served_fs, per_request_fs)
-        reqs = wl.poisson_stream(args.stream, rate, n=args.n, ppw=args.ppw, tol=args.tol)
-        S, wall_s, lat_s, _, _ = run_served(bf, reqs, args.slots, args.leaf)
-        S.close()
-        stream = {"requests": args.stream, "rate_per_s": rate, "wall_s": wall_s,
-                  "p50_ms": 1e3 * pct(lat_s, 50), "p99_ms": 1e3 * pct(lat_s, 99),
-                  "completed_per_s": args.stream / wall_s}
+        cap = max(served_fs, per_request_fs)
+        streams = {}
+        for mult in (0.5, 1.0, 2.0):
+            reqs = wl.poisson_stream(args.stream, mult * cap, n=args.n, ppw=args.ppw,
+                                     tol=args.tol)
+            S, wall_s, lat_s, _, _ = run_served(bf, reqs, args.slots, args.leaf)
+            S.close()
+            streams[f"{mult:g}x"] = {
+                "requests": args.stream, "rate_per_s": mult * cap, "wall_s": wall_s,
+                "p50_ms": 1e3 * pct(lat_s, 50), "p99_ms": 1e3 * pct(lat_s, 99),
+                "completed_per_s": args.stream / wall_s}
     mix = None
     if args.mix > 0:
         reqs = wl.mixed_stream(args.mix)
-        S, wall_m, lat_mc, lat_ma, _ = run_served(bf, reqs, args.slots, args.leaf,
-                                                  batch_cols=args.batch_cols)
-        S.close()
-        mix = {"requests": args.mix, "constructions": len(lat_mc), "applies": len(lat_ma),
-               "wall_s": wall_m, "factorizations_per_s": len(lat_mc) / wall_m,
-               "construct_p50_ms": 1e3 * pct(lat_mc, 50), "construct_p99_ms": 1e3 * pct(lat_mc, 99),
-               "apply_p50_ms": 1e3 * pct(lat_ma, 50), "apply_p99_ms": 1e3 * pct(lat_ma, 99),
-               "batch_cols": args.batch_cols, "merged_applies": S.merged_applies}
+        mix = {"requests": args.mix,
+               "constructions": sum(r.kind == "construct" for r in reqs),
+               "applies": sum(r.kind != "construct" for r in reqs)}
+        # served: `slots` device slots with continuous batching of applies;
+        # per-request path: one slot, every request its own launches
+        for name, slots, bc in (("served", args.slots, args.batch_cols), ("per_request", 1, 0)):
+            S, wall_m, lat_mc, lat_ma, _ = run_served(bf, reqs, slots, args.leaf, batch_cols=bc)
+            S.close()
+            mix[name] = {"slots": slots, "batch_cols": bc, "wall_s": wall_m,
+                         "factorizations_per_s": len(lat_mc) / wall_m,
+                         "construct_p50_ms": 1e3 * pct(lat_mc, 50),
+                         "construct_p99_ms": 1e3 * pct(lat_mc, 99),
+                         "apply_p50_ms": 1e3 * pct(lat_ma, 50),
+                         "apply_p99_ms": 1e3 * pct(lat_ma, 99),
+                         "merged_applies": S.merged_applies}
 
-    rel_err, cpu = cpu_baseline_leg(geom, last, args, passes)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_leg(geom, args, passes)
     apply_rl = apply_roofline(bf, last, args.n)
 
     mf = prof["matfree"]
+    # algorithmic work of the black-box launches: 8 flops per complex
+    # multiply-add of every sampled column with every kernel entry of its
+    # segment (counted by the library per launch), over their event time
     mac_tflops = mf["flops"] / (mf["ms"] * 1e-3) / 1e12 if mf["ms"] > 0 else 0.0
-    # every launch of this workload (sample widths <= 64, one column chunk)
+    # every launch of this workload (sample widths <= 80, one column chunk)
     # evaluates each of the m*n kernel entries once
     evals_per_s = mf["launches"] * float(args.n) * args.n / max(1e-30, mf["ms"] * 1e-3)
     vpe = measured_valu_per_entry()
-    achieved = evals_per_s * vpe * 4.0 / 1e12 if vpe else None
     out = {
         "metric": METRIC,
         "value": max(per_request_fs, served_fs),
@@ -637,10 +689,14 @@ def main():
         "p99_ms": 1e3 * pct(lat, 99),
         "per_request_fs": per_request_fs,
         "served_fs": served_fs,
+        "served_p50_ms": 1e3 * pct(lat_c, 50),
+        "served_p99_ms": 1e3 * pct(lat_c, 99),
         "slots": args.slots,
-        "poisson_stream": stream,
+        "poisson_streams": streams,
         "mixed_stream": mix,
         "rel_err": rel_err,
+        "served_rel_err_max": max(served_errs) if served_errs else None,
+        "served_checked": len(served_errs),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -657,17 +713,20 @@ def main():
         },
         "roofline": {
             "kernel": "matfree_bf16_kernel<SegEntry> (black-box products, split-BF16 MFMA)",
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_FP32_TFLOPS,
+            "bound": "mfma",
+            "achieved": mac_tflops,
+            "peak": PEAK_BF16_MFMA_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS if achieved is not None else None,
-            "work": ("vector-ALU issue of the entry evaluations: entries/s x lane-instructions "
-                     "per entry x 4 FP32 flops per issue slot"),
+            "frac": mac_tflops / PEAK_BF16_MFMA_TFLOPS,
+            "work": ("algorithmic complex multiply-adds of the black-box products, 8 flops each, "
+                     "per launch over the launch's HIP-event time; peak = MI355X dense BF16 "
+                     "matrix-core rate"),
+            "flops_per_launch": mf["flops"] / max(1, mf["launches"]),
             "entry_evals_per_s": evals_per_s,
             "valu_instr_per_entry": vpe,
             "valu_issue_frac": evals_per_s * vpe / VALU_LANE_INSTR_PER_S if vpe else None,
-            "mac_tflops": mac_tflops,
+            "mfma_busy_frac": profile_value("matfree_segkernel_n65536_valu_mfma.md",
+                                            "mfma_busy_frac"),
             "traffic": measured_traffic(),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
             "algorithmic_bytes_per_launch": mf["bytes"] / max(1, mf["launches"]),
