@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the n=262144 FIO butterfly's apply roofline in the default line")
     ap.add_argument("--slots", type=int, default=4, help="device slots of the served runs")
     ap.add_argument("--stream", type=int, default=64,
                     help="requests of each Poisson stream at the headline size, run at 0.5x, "
@@ -72,6 +74,8 @@ def parse():
                     help="only submit this many 1-column applies at once against one "
                          "factorization of the headline operator, with and without continuous "
                          "batching (--batch-cols), and print one JSON line")
+    ap.add_argument("--solve-rounds", type=int, default=0, choices=(0, 1),
+                    help="served runs: cross-request solve rounds in the request engine")
     ap.add_argument("--batch-cols", type=int, default=64,
                     help="continuous batching of the mixed stream's applies (columns per "
                          "merged product; 0 = off)")
@@ -94,6 +98,12 @@ def parse():
                          "operator of size N (e.g. 262144; leaf 16, tol 1e-6): matrix-free construction with the split-BF16 and FP64 black "
                          "boxes, recompression with the butterfly as black box (FP32 and "
                          "split-BF16 applies) and apply rates; one JSON line each")
+    ap.add_argument("--compose", type=int, default=0, metavar="N",
+                    help="only run the category (ii) recompression at size N (e.g. 65536): "
+                         "B1 ~ A(X0,X1) and B2 ~ A(X1,X2) built matrix-free on the GPU (three "
+                         "segments y = 0, 1, 2, 8 points per wavelength, leaf 64, tol 1e-6), "
+                         "the composition B1 B2 recompressed with Alg. 2, error against FP64 "
+                         "A01 (A12 Omega) on sampled rows; one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (reference "
                          "dispatch for calibrating rocprofv3 byte counters) and exit")
@@ -350,6 +360,87 @@ def apply_burst(args):
     print(json.dumps(out), flush=True)
 
 
+def _kernel_rows_times(args):
+    """Rows [r0, r1) of the FP64 kernel matrix times X (process-pool worker)."""
+    from oracle import operators as ops
+    t, src, k, r0, r1, X = args
+    return ops.segment_kernel_entries(t, src, k, rows=slice(r0, r1)) @ X
+
+
+def compose(n, leaf=64, tol=1e-6, rows=128, workers=12):
+    """Category (ii) of Sec. 1 at size n: two butterflies B1 ~ A(X0, X1) and
+    B2 ~ A(X1, X2) built on the GPU from the matrix-free black box, their
+    composition recompressed into one butterfly by Alg. 2 with the two
+    butterflies' applies as the black box.  Errors on 16 Gaussian columns:
+    against the FP64 product A01 (A12 Omega) of the oracle's kernel entries on
+    `rows` sampled rows (A12 Omega in full, row blocks over a process pool),
+    and against the composition B1 (B2 Omega) on every row."""
+    import multiprocessing as mp
+
+    import torch
+
+    import paper_2002_03400_amd as bf
+    import workloads as wl
+    from oracle import operators as ops
+    torch.cuda.init()
+    g01, g12 = wl.segment_triple(n, ppw=8.0)
+    o1 = bf.segkernel(g01.targets, g01.sources, g01.k)
+    o2 = bf.segkernel(g12.targets, g12.sources, g12.k)
+    bf.construct(o1, tol, leaf, seed=20).close()            # kernels loaded, tuner classes timed
+    times = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B1 = bf.construct(o1, tol, leaf, seed=21)
+    torch.cuda.synchronize()
+    times["B1_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    B2 = bf.construct(o2, tol, leaf, seed=22)
+    torch.cuda.synchronize()
+    times["B2_s"] = time.perf_counter() - t0
+    prod = bf.compose(bf.from_factors(B1), bf.from_factors(B2))
+    F = bf.construct(prod, tol, leaf, seed=30)               # untimed: first recompression
+    F.close()
+    bf.profile_start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = bf.construct(prod, tol, leaf, seed=23)
+    torch.cuda.synchronize()
+    times["recompress_s"] = time.perf_counter() - t0
+    prof = bf.profile_stop()
+    st = F.stats()
+    Om = wl.test_columns(n, 16, 1001)
+    Omd = torch.from_numpy(Om.astype(np.complex64)).cuda()
+    FO = F.apply(Omd)
+    BB = B1.apply(B2.apply(Omd))
+    err_bb = float((FO - BB).norm() / BB.norm())
+    # FP64 reference: A12 Omega in full, then sampled rows of A01
+    t0 = time.perf_counter()
+    step = max(1, (1 << 22) // n)
+    jobs = [(g12.targets, g12.sources, g12.k, r0, min(n, r0 + step), Om)
+            for r0 in range(0, n, step)]
+    # fresh interpreters: the workers never touch the GPU this process holds
+    with mp.get_context("spawn").Pool(workers) as pool:
+        A12Om = np.concatenate(pool.map(_kernel_rows_times, jobs), axis=0)
+    sel = np.sort(np.random.default_rng(0).choice(n, min(rows, n), replace=False))
+    ref = ops.segment_kernel_entries(g01.targets, g01.sources, g01.k, rows=sel) @ A12Om
+    ref_s = time.perf_counter() - t0
+    got = FO.cpu().numpy()[sel]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    b1s, b2s = B1.stats(), B2.stats()
+    print(json.dumps({
+        "workload": (f"category (ii) recompression: B1 B2, three unit segments y=0,1,2, "
+                     f"n={n}, 8 points/wavelength, leaf {leaf}, tol {tol:g}"),
+        "n": n, "leaf": leaf, "tol": tol, "L": st.L, "max_rank": st.max_rank,
+        "B1_max_rank": b1s.max_rank, "B2_max_rank": b2s.max_rank, **times,
+        "matvec_cols": st.matvec_cols, "rmatvec_cols": st.rmatvec_cols,
+        "rel_err_vs_fp64": err, "rows_checked": int(len(sel)),
+        "rel_err_vs_B1B2": err_bb, "fp64_reference_s": ref_s,
+        "phase_ms": {k: v["ms"] for k, v in prof.items()}}), flush=True)
+    F.close()
+    B1.close()
+    B2.close()
+
+
 def copy_calibration():
     """Three dispatches of a plain 1 GiB device-to-device copy (torch copy_)."""
     import torch
@@ -480,15 +571,15 @@ def cpu_baseline_leg(geom, args, passes):
     }
 
 
-def apply_roofline(bf, F, n, reps=20):
-    """bf_apply of the benchmarked factors (default arithmetic) at 1, 4, 16
-    and 64 right-hand sides: algorithmic bytes (8 per factor entry + 8 per
-    input and output value) over the stages' HIP-event time, against the HBM
-    peak; the wall time per apply includes the launches, and is taken again
-    with the stages run as one captured HIP graph."""
+def apply_roofline(bf, F, n, reps=20, sizes=(1, 4, 16, 64)):
+    """bf_apply of the given factors (default arithmetic) at `sizes` right-hand
+    sides: algorithmic bytes (8 per factor entry + 8 per input and output
+    value) over the launches' HIP-event time, against the HBM peak; the wall
+    time per apply includes the launches, and is taken again with the
+    launches run as one captured HIP graph."""
     import torch
     out = {}
-    for s in (1, 4, 16, 64):
+    for s in sizes:
         X = torch.randn(n, s, dtype=torch.complex64, device="cuda")
         Y = F.apply(X)
         torch.cuda.synchronize()
@@ -515,18 +606,39 @@ def apply_roofline(bf, F, n, reps=20):
                          "bytes": ap["bytes"] / reps, "GB_per_s": gbs,
                          "frac_hbm": gbs / PEAK_HBM_GBS,
                          "TFLOP_per_s": ap["flops"] / reps / (kms * 1e-3) / 1e12 if kms > 0 else 0.0,
-                         "stages": ap["launches"] // reps}
+                         "launches": ap["launches"] // reps}
     return out
 
 
-def run_served(bf, reqs, slots, leaf, keep_all=False, batch_cols=0):
+def c5_apply(bf, n=262144, leaf=16, tol=1e-6):
+    """The precision-form workload's butterfly (1D Fourier integral operator,
+    n = 262144, leaf 16, tol 1e-6, built matrix-free with the split-BF16 black
+    box) and its apply roofline at 1, 4 and 16 right-hand sides."""
+    import torch
+    op = bf.fio(n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = bf.construct(op, tol, leaf, seed=5)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = F.stats()
+    out = {"workload": f"1D Fourier integral operator butterfly, n={n}, leaf {leaf}, tol {tol:g}",
+           "construct_s": dt, "L": st.L, "max_rank": st.max_rank,
+           "factor_GB": 8.0 * st.factor_entries / 1e9,
+           "apply": apply_roofline(bf, F, n, reps=10, sizes=(1, 4, 16))}
+    F.close()
+    op.close()
+    return out
+
+
+def run_served(bf, reqs, slots, leaf, keep_all=False, batch_cols=0, rounds=False):
     """Replay a request stream in real time through the request engine.
     Returns (server, wall seconds, [latency s of constructions], [latency s of
     applies], [borrowed factors of every construction] if keep_all else [])."""
     import torch
 
     import workloads as wl
-    S = bf.Server(slots=slots, batch_cols=batch_cols)
+    S = bf.Server(slots=slots, batch_cols=batch_cols, solve_rounds=rounds)
     ops_ = {}
     tickets = {}
     start = time.perf_counter()
@@ -577,6 +689,9 @@ def main():
         return
     if args.precision_form:
         precision_form(args.precision_form)
+        return
+    if args.compose:
+        compose(args.compose)
         return
     if args.em3d:
         em3d([tuple(int(x) for x in e.split(":")) for e in args.em3d.split(",")],
@@ -629,7 +744,8 @@ def main():
     # every served factorization is checked against the oracle rows
     import workloads as wl
     reqs = [wl.Request(0.0, "construct", args.n, args.ppw, args.tol, 3 + k) for k in range(args.steps)]
-    S, wall, lat_c, _, kept = run_served(bf, reqs, args.slots, args.leaf, keep_all=True)
+    S, wall, lat_c, _, kept = run_served(bf, reqs, args.slots, args.leaf, keep_all=True,
+                                         rounds=bool(args.solve_rounds))
     served_fs = args.steps / wall
     served_errs = [sampled_err(Fk, chk) for Fk in kept]
     S.close()
@@ -640,7 +756,8 @@ def main():
         for mult in (0.5, 1.0, 2.0):
             reqs = wl.poisson_stream(args.stream, mult * cap, n=args.n, ppw=args.ppw,
                                      tol=args.tol)
-            S, wall_s, lat_s, _, _ = run_served(bf, reqs, args.slots, args.leaf)
+            S, wall_s, lat_s, _, _ = run_served(bf, reqs, args.slots, args.leaf,
+                                                rounds=bool(args.solve_rounds))
             S.close()
             streams[f"{mult:g}x"] = {
                 "requests": args.stream, "rate_per_s": mult * cap, "wall_s": wall_s,
@@ -655,9 +772,11 @@ def main():
         # served: `slots` device slots with continuous batching of applies;
         # per-request path: one slot, every request its own launches
         for name, slots, bc in (("served", args.slots, args.batch_cols), ("per_request", 1, 0)):
-            S, wall_m, lat_mc, lat_ma, _ = run_served(bf, reqs, slots, args.leaf, batch_cols=bc)
+            S, wall_m, lat_mc, lat_ma, _ = run_served(bf, reqs, slots, args.leaf, batch_cols=bc,
+                                                      rounds=bool(args.solve_rounds) and slots > 1)
             S.close()
             mix[name] = {"slots": slots, "batch_cols": bc, "wall_s": wall_m,
+                         "solve_rounds": bool(args.solve_rounds) and slots > 1,
                          "factorizations_per_s": len(lat_mc) / wall_m,
                          "construct_p50_ms": 1e3 * pct(lat_mc, 50),
                          "construct_p99_ms": 1e3 * pct(lat_mc, 99),
@@ -667,6 +786,7 @@ def main():
 
     cpu = None if args.no_cpu_baseline else cpu_baseline_leg(geom, args, passes)
     apply_rl = apply_roofline(bf, last, args.n)
+    c5 = None if args.no_c5 else c5_apply(bf)
 
     mf = prof["matfree"]
     # algorithmic work of the black-box launches: 8 flops per complex
@@ -692,6 +812,7 @@ def main():
         "served_p50_ms": 1e3 * pct(lat_c, 50),
         "served_p99_ms": 1e3 * pct(lat_c, 99),
         "slots": args.slots,
+        "solve_rounds": bool(args.solve_rounds),
         "poisson_streams": streams,
         "mixed_stream": mix,
         "rel_err": rel_err,
@@ -735,6 +856,7 @@ def main():
         },
         "phase_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
         "apply_roofline": apply_rl,
+        "apply_roofline_c5": c5,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -26,6 +26,7 @@
 #ifndef BF_H
 #define BF_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -54,8 +55,8 @@ enum {
 #define BF_MAX_BLOCK_COLS 2048
 
 /*
- * Black-box product (the input of Alg. 2: "routine for multiplying K(T,S)
- * and its transpose with arbitrary matrices").  Writes Y = op(A) X on
+ * Black-box product (Alg. 2, input: products of A and of A^H with any block
+ * of columns the algorithm chooses).  Writes Y = op(A) X on
  * `stream`, op = A for the matvec callback (X has n rows, Y has m rows) and
  * op = A^H for the rmatvec callback (X has m rows, Y has n rows).
  *
@@ -133,6 +134,27 @@ enum { BF_PHASE_LEAF_V = 0, BF_PHASE_LEAF_U = 1, BF_PHASE_W = 2, BF_PHASE_R = 3 
 typedef struct bf_factors bf_factors;
 
 /*
+ * Device-memory provider of a call, e.g. a framework's caching allocator
+ * (the Python binding passes one backed by torch's).  alloc returns `bytes`
+ * of device memory on the current device for use in stream order on `stream`
+ * (NULL on failure: the call then fails with BF_ENOMEM); free returns a block
+ * once the work enqueued on `stream` before the call no longer needs it
+ * (stream-ordered, like hipFreeAsync).  With an allocator, every device block
+ * the call needs comes from it: sample, product and solver workspace, and for
+ * bf_construct / bf_import the factor storage, which goes back to it at
+ * bf_free, so ctx and both functions must stay valid until every handle built
+ * with them is freed.  Blocks from an allocator are never kept by the library.
+ * Not covered: the private buffers of captured apply graphs
+ * (bf_set_apply_graph_cols) and pinned host staging.  NULL = the library's
+ * own stream-ordered pool, with device blocks kept for reuse across calls.
+ */
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, void* stream);
+} bf_alloc;
+
+/*
  * Alg. 2: adaptive randomized hybrid butterfly construction.
  *   matvec, rmatvec, user : the black box (see bf_op_fn); both required.
  *   m, n                  : operator size (rows = targets T, cols = sources S).
@@ -143,6 +165,7 @@ typedef struct bf_factors bf_factors;
  *                           L is the smallest level count with
  *                           ceil(max(m,n)/2^L) <= leaf.
  *   opts                  : NULL or knobs above.
+ *   alloc                 : NULL or the device-memory provider (bf_alloc).
  *   stream                : all device work and callbacks use this stream.
  *   out                   : receives the factor handle (owned by the caller,
  *                           release with bf_free).
@@ -152,29 +175,33 @@ typedef struct bf_factors bf_factors;
  * Blocks on the host: syncs once per adaptive iteration and per level.
  */
 int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64_t n,
-                 double tol, int64_t leaf, const bf_opts* opts, void* stream,
-                 bf_factors** out);
+                 double tol, int64_t leaf, const bf_opts* opts, const bf_alloc* alloc,
+                 void* stream, bf_factors** out);
 
 /*
  * Apply the factorization (eq. hybrid_butterfly_mat, right to left):
  *   trans = 0 : Y = F X,   X is n x ncols (ldx >= n), Y is m x ncols (ldy >= m)
  *   trans = 1 : Y = F^H X, X is m x ncols,            Y is n x ncols
  * complex64 data (arithmetic: bf_set_apply_precision).  X, Y are caller-owned device buffers
- * and must not overlap.  Reentrant across streams for one handle.
+ * and must not overlap.  alloc: NULL or the provider of the intermediates
+ * (bf_alloc).  Reentrant across streams for one handle.
  */
 int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
-             bf_c64* Y, int64_t ldy, void* stream);
+             bf_c64* Y, int64_t ldy, const bf_alloc* alloc, void* stream);
 
 /*
  * bf_apply without any allocation, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same arguments, kernels and results as bf_apply
  * (launched stage by stage, never through a cached graph, never profiled).
- * The two ping-pong intermediates live in a fixed scratch array of
+ * The intermediates live in a fixed scratch array of
  * bf_apply_noalloc_scratch_bytes() bytes (64 MiB) per device, which the
- * library holds on every device it runs on until the process ends; they need
- * 2 x (largest level rank sum) x ncols complex64 values, and larger requests
- * return BF_EINVAL (nothing is launched).  Every call on a device uses that
+ * library holds on every device it runs on until the process ends.  A call is
+ * accepted when the stage-by-stage apply's two ping-pong intermediates fit
+ * (2 x (largest level rank sum) x ncols complex64 values); it then runs like
+ * bf_apply (fused stages for up to 16 columns when their larger intermediate
+ * also fits, else stage by stage).  Larger requests return BF_EINVAL
+ * (nothing is launched).  Every call on a device uses that
  * device's one array: calls that overlap on one GPU (other streams, other
  * threads) race and give wrong results, so callers serialize them.  F must
  * live on the current device.  The first call on a device looks up the
@@ -193,6 +220,13 @@ int64_t bf_apply_noalloc_scratch_bytes(void);
  * 16 keys bf_apply launches the stages directly) and freed with the factors.
  * Same kernels, same results.  Not to be called while applies of F run. */
 int bf_set_apply_graph_cols(bf_factors* F, int64_t max_cols);
+
+/* Applies of 1 to 16 columns run fused: consecutive stages share one launch,
+ * each workgroup taking a group of blocks that depend only on each other
+ * (about 4 launches instead of L + 3 at L = 10).  enable = 0 runs every
+ * stage as its own launch (the path used above 16 columns).  Default 1.  Not
+ * synchronized with applies in flight on F. */
+int bf_set_apply_fusion(bf_factors* F, int enable);
 
 /* Summary of a factorization. */
 typedef struct {
@@ -228,17 +262,20 @@ int bf_ranks(const bf_factors* F, int32_t* kU, int32_t* kV);
  * V_{0,j}: n_j x kV(0,0,j).
  * bf_export writes `count` entries (query with data == NULL to get count).
  * bf_import builds a handle from ranks + data (used for exact-butterfly black
- * boxes and for applying externally built factors).
+ * boxes and for applying externally built factors); alloc as for bf_construct.
  */
 int bf_export(const bf_factors* F, bf_c128* data, int64_t* count);
 int bf_import(int64_t m, int64_t n, int64_t leaf, const int32_t* kU, const int32_t* kV,
-              const bf_c128* data, int64_t count, void* stream, bf_factors** out);
+              const bf_c128* data, int64_t count, const bf_alloc* alloc, void* stream,
+              bf_factors** out);
 
-/* Release a handle (waits for `stream` work that uses it to be enqueued before).
- * Its device memory is kept by the library for later requests on the same
- * device (up to 16 GB per device, each block reused only after the work
- * enqueued on `stream` before this call has finished), as is the pinned host
- * memory of descriptor uploads; bf_release_cached_memory gives both back. */
+/* Release a handle.  Its device blocks are reused only after the work
+ * enqueued on `stream` before this call has finished; with stream NULL the
+ * call first waits for all work on the handle's device (the null stream does
+ * not order non-blocking streams).  Blocks from a caller's bf_alloc go back to
+ * it; the library's own are kept for later requests on the same device (up to
+ * 16 GB per device), as is the pinned host memory of descriptor uploads;
+ * bf_release_cached_memory gives both back. */
 int bf_free(bf_factors* F, void* stream);
 
 /* Return every device block and pinned host block the library keeps for
@@ -283,6 +320,22 @@ typedef struct {
                            with 4+ others it runs on the matrix cores), so they
                            can differ from a lone apply in the last bits. */
   int64_t hbm_budget;   /* bytes; 0 = 64 GiB */
+  const bf_alloc* alloc;  /* NULL or the device-memory provider of every request
+                             (bf_alloc; copied at creation, must outlive the
+                             server and every factor it holds) */
+  int32_t solve_rounds; /* 0: every construction launches its own level solves.
+                           1: cross-request solve rounds -- the batched
+                           truncated QRs (Alg. 1 step 3) and centre-block least
+                           squares (Sec. 4.4) that in-flight constructions reach
+                           within a short window (60 us, or until every
+                           construction in flight has joined) run as one
+                           persistent launch over a device work list of
+                           (request, block) items, replayed from a captured
+                           HIP graph (one per LDS size class); blocks too large
+                           for the LDS keep their own launches.  Each block runs
+                           the code of its own launch: results are bitwise
+                           those without rounds. */
+  int32_t reserved;     /* 0 */
 } bf_server_opts;
 typedef struct {
   int32_t status;       /* BF_OK or the request's error code */
@@ -310,6 +363,9 @@ int bf_server_factors(bf_server* S, int64_t ticket, const bf_factors** F);
 /* Forget a finished request; for a construction, free its factors (refused
    while applies that reference it are queued or running). */
 int bf_server_release(bf_server* S, int64_t ticket);
+/* Solve rounds launched so far and the blocks they held (0, 0 without
+   solve_rounds). */
+int bf_server_rounds(bf_server* S, int64_t* rounds, int64_t* items);
 
 /* ---------------------------------------------------------------------------
  * Profiling: while enabled, every launch of the library's kernels is
@@ -429,17 +485,38 @@ int bf_operator_destroy(bf_operator* op);
 enum { BF_PREC_FP64 = 0, BF_PREC_BF16X3 = 1, BF_PREC_FP32 = 2 };
 int bf_op_set_precision(bf_operator* op, int precision);
 
-/* Tile-width autotuner of the built-in black boxes (off by default; for
- * callers that construct many operators of a few shapes).  When enabled, the
- * first split-BF16 product of each shape class (operator kind, column count,
- * and the powers of two at or above the row count, inner length and segment
- * count) runs once per candidate column-chunk bound (48, 64, 80 columns),
- * timed on its stream, and later products of the class use the fastest.  The
- * candidates give bitwise the same products, so results never depend on it;
- * the tuning product synchronizes its stream once.  bf_autotune_entries
- * reports how many shape classes have been tuned. */
+/* Launch-shape autotuner (on by default).  For each kernel family and shape
+ * class it keeps the fastest of a few launch variants that give bitwise the
+ * same results, timed on the first launch of the class (which then runs
+ * every candidate in turn on its stream and synchronizes it once; launches
+ * under HIP graph capture and bf_apply_noalloc never time, they use the
+ * table or the default rule):
+ *   black-box column tile : 48, 64 or 80 columns, split-BF16 products of more
+ *                           than 48 columns (class: operator kind, column
+ *                           count, powers of two above the row count, inner
+ *                           length and segment count);
+ *   chain tile height     : 8, 16, 20, 24, 32 or 64 rows, at least the
+ *                           launch's largest block (class: input type,
+ *                           largest block, powers of two above the block and
+ *                           column counts);
+ *   CPQR workgroup        : 256 or 512 threads for blocks held in LDS (class:
+ *                           input type, powers of two above the largest
+ *                           block's rows and columns and the block count);
+ *   few-column apply      : fused stages or one launch per stage, 1 to 4
+ *                           columns (class: direction, columns, powers of two
+ *                           above m and n, L, apply precision).
+ * Without the tuner every family uses its rule (80-column tiles, the
+ * smallest tile height, 256 threads, fused applies).  The table is
+ * process-wide; the first lookup loads the file named by the environment
+ * variable BF_TUNE_FILE or, if unset, tune_gfx950.tsv beside libbf.so (when
+ * present).  bf_autotune_save writes the table (path NULL or "": that same
+ * default file), bf_autotune_load merges a file into it, bf_autotune_clear
+ * empties it, bf_autotune_entries counts its classes. */
 int bf_set_autotune(int enable);
 int bf_autotune_entries(int64_t* entries);
+int bf_autotune_save(const char* path);
+int bf_autotune_load(const char* path);
+int bf_autotune_clear(void);
 
 /* Arithmetic of bf_apply (and of the factors as a black box, bf_op_factors)
  * for F (eq. hybrid_butterfly_mat, complex64 data in both modes):

@@ -1,5 +1,5 @@
-"""FP64 black-box operators for Alg. 2 (its input: "black-box routine for
-multiplying K(T,S) and its transpose with arbitrary matrices").
+"""FP64 black-box operators for Alg. 2 (Alg. 2, input: products of A and of
+A^H with any block of columns the algorithm chooses).
 
 Complex data: every transpose of the paper becomes the conjugate transpose
 (Sec. 2.1 extends the real algorithms to complex matrices), so the second

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libbf.so")
 __all__ = ["BFError", "lib", "Operator", "Factors", "construct", "segkernel", "helmholtz3d", "fio",
            "dense",
            "from_factors", "compose", "import_factors", "gauss", "cpqr_batched", "lsq_batched",
-           "num_levels", "LIB_PATH", "profile_start", "profile_stop", "Server"]
+           "num_levels", "LIB_PATH", "profile_start", "profile_stop", "Server", "TorchAllocator",
+           "torch_allocator"]
 
 
 class BFError(RuntimeError):
@@ -69,8 +70,18 @@ class bf_kernel_stats(C.Structure):
 KERNEL_CLASSES = ("matfree", "apply", "cpqr", "chain", "lsq", "other")
 
 
+ALLOCFN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREEFN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class bf_alloc(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("alloc", ALLOCFN), ("free", FREEFN)]
+
+
 class bf_server_opts(C.Structure):
-    _fields_ = [("slots", C.c_int32), ("batch_cols", C.c_int32), ("hbm_budget", C.c_int64)]
+    _fields_ = [("slots", C.c_int32), ("batch_cols", C.c_int32), ("hbm_budget", C.c_int64),
+                ("alloc", C.POINTER(bf_alloc)), ("solve_rounds", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class bf_request_info(C.Structure):
@@ -94,19 +105,23 @@ _I32P = C.POINTER(C.c_int32)
 # name -> (restype, argtypes); every symbol of include/bf.h
 SIGNATURES = {
     "bf_construct": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, C.c_double, C.c_int64,
-                               C.POINTER(bf_opts), _P, C.POINTER(_P)]),
-    "bf_apply": (C.c_int, [_P, C.c_int, _P, C.c_int64, C.c_int64, _P, C.c_int64, _P]),
+                               C.POINTER(bf_opts), C.POINTER(bf_alloc), _P, C.POINTER(_P)]),
+    "bf_apply": (C.c_int, [_P, C.c_int, _P, C.c_int64, C.c_int64, _P, C.c_int64,
+                           C.POINTER(bf_alloc), _P]),
     "bf_apply_noalloc": (C.c_int, [_P, C.c_int, _P, C.c_int64, C.c_int64, _P, C.c_int64, _P]),
     "bf_apply_noalloc_scratch_bytes": (C.c_int64, []),
     "bf_stats": (C.c_int, [_P, C.POINTER(bf_info)]),
     "bf_ranks": (C.c_int, [_P, _I32P, _I32P]),
     "bf_export": (C.c_int, [_P, _P, _I64P]),
-    "bf_import": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _I32P, _I32P, _P, C.c_int64, _P,
-                            C.POINTER(_P)]),
+    "bf_import": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _I32P, _I32P, _P, C.c_int64,
+                            C.POINTER(bf_alloc), _P, C.POINTER(_P)]),
     "bf_free": (C.c_int, [_P, _P]),
     "bf_release_cached_memory": (C.c_int, []),
     "bf_set_autotune": (C.c_int, [C.c_int]),
     "bf_autotune_entries": (C.c_int, [C.POINTER(C.c_int64)]),
+    "bf_autotune_save": (C.c_int, [C.c_char_p]),
+    "bf_autotune_load": (C.c_int, [C.c_char_p]),
+    "bf_autotune_clear": (C.c_int, []),
     "bf_strerror": (C.c_char_p, [C.c_int]),
     "bf_last_error": (C.c_char_p, []),
     "bf_server_create": (C.c_int, [C.POINTER(bf_server_opts), C.POINTER(_P)]),
@@ -118,6 +133,7 @@ SIGNATURES = {
     "bf_server_wait": (C.c_int, [_P, C.c_int64, C.POINTER(bf_request_info)]),
     "bf_server_factors": (C.c_int, [_P, C.c_int64, C.POINTER(_P)]),
     "bf_server_release": (C.c_int, [_P, C.c_int64]),
+    "bf_server_rounds": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "bf_profile_start": (C.c_int, []),
     "bf_profile_stop": (C.c_int, [C.POINTER(bf_kernel_stats)]),
     "bf_gauss": (C.c_int, [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
@@ -138,6 +154,7 @@ SIGNATURES = {
     "bf_op_set_precision": (C.c_int, [C.POINTER(bf_operator), C.c_int]),
     "bf_set_apply_precision": (C.c_int, [_P, C.c_int]),
     "bf_set_apply_graph_cols": (C.c_int, [_P, C.c_int64]),
+    "bf_set_apply_fusion": (C.c_int, [_P, C.c_int]),
 }
 
 
@@ -193,6 +210,79 @@ def _colmajor(x):
 def _empty_colmajor(rows, cols, dtype, device):
     torch = _torch()
     return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+class TorchAllocator:
+    """A bf_alloc backed by torch's CUDA caching allocator, so the library's
+    device memory (workspace and factor storage) is torch's: it shows in
+    torch.cuda.memory_allocated and is reused by torch afterwards.  A block is
+    given back on the stream it was allocated on; when the library frees it on
+    another stream, the allocating stream first waits for that stream's work."""
+
+    def __init__(self):
+        import threading
+        self._live = {}
+        self._lock = threading.Lock()
+        self._alloc_cb = ALLOCFN(self._alloc)
+        self._free_cb = FREEFN(self._free)
+        self.struct = bf_alloc(None, self._alloc_cb, self._free_cb)
+
+    @staticmethod
+    def _stream_obj(ptr, dev):
+        torch = _torch()
+        return torch.cuda.default_stream(dev) if not ptr else torch.cuda.ExternalStream(ptr, device=dev)
+
+    def _alloc(self, _ctx, size, stream):
+        torch = _torch()
+        try:
+            dev = torch.cuda.current_device()
+            p = torch.cuda.caching_allocator_alloc(int(size), dev, int(stream or 0))
+        except Exception:
+            return None
+        with self._lock:
+            self._live[p] = (int(stream or 0), dev)
+        return p
+
+    def _free(self, _ctx, ptr, stream):
+        torch = _torch()
+        with self._lock:
+            s_alloc, dev = self._live.pop(ptr)
+        s_free = int(stream or 0)
+        if s_free != s_alloc:
+            ev = torch.cuda.Event()
+            ev.record(self._stream_obj(s_free, dev))
+            self._stream_obj(s_alloc, dev).wait_event(ev)
+        torch.cuda.caching_allocator_delete(ptr)
+
+    def live_blocks(self):
+        with self._lock:
+            return len(self._live)
+
+
+_TORCH_ALLOC = None
+
+
+def torch_allocator() -> TorchAllocator:
+    """The process-wide TorchAllocator (created on first use)."""
+    global _TORCH_ALLOC
+    if _TORCH_ALLOC is None:
+        _TORCH_ALLOC = TorchAllocator()
+    return _TORCH_ALLOC
+
+
+def _allocator(which):
+    """None (the library's own pool), "torch" or a TorchAllocator."""
+    if which is None:
+        return None
+    if which == "torch":
+        return torch_allocator()
+    if isinstance(which, TorchAllocator):
+        return which
+    raise ValueError(f"unknown allocator {which!r}")
+
+
+def _alloc_ptr(a):
+    return C.byref(a.struct) if a is not None else None
 
 
 def num_levels(m, n, leaf):
@@ -321,9 +411,10 @@ class Info:
 class Factors:
     """Handle of a hybrid butterfly factorization (owned; freed on close)."""
 
-    def __init__(self, handle, leaf):
+    def __init__(self, handle, leaf, allocator=None):
         self._h = handle
         self.leaf = leaf
+        self._alloc = allocator   # kept alive until the factors are freed
         inf = self.stats()
         self.m, self.n, self.L, self.lm = inf.m, inf.n, inf.L, inf.lm
 
@@ -356,12 +447,19 @@ class Factors:
         _check(lib().bf_set_apply_precision(self._h, code), "bf_set_apply_precision")
         return self
 
+    def set_fusion(self, enable):
+        """Fused stages for applies of 1 to 16 columns (default True)."""
+        _check(lib().bf_set_apply_fusion(self._h, int(bool(enable))), "bf_set_apply_fusion")
+        return self
+
     def set_graph_cols(self, max_cols):
         """Run applies of at most max_cols columns as cached HIP graphs (0: off)."""
         _check(lib().bf_set_apply_graph_cols(self._h, int(max_cols)), "bf_set_apply_graph_cols")
         return self
 
-    def apply(self, X, trans=False, out=None, stream=None):
+    def apply(self, X, trans=False, out=None, stream=None, allocator="torch"):
+        """Y = F X (or F^H X); the intermediates come from `allocator` ("torch":
+        torch's caching allocator; None: the library's pool)."""
         X = _dev_c64(X)
         X, ldx = _colmajor(X)
         rows_out = self.n if trans else self.m
@@ -369,13 +467,17 @@ class Factors:
             out = _empty_colmajor(rows_out, X.shape[1], X.dtype, X.device)
         Y, ldy = _colmajor(out)
         _check(lib().bf_apply(self._h, int(bool(trans)), X.data_ptr(), ldx, X.shape[1],
-                              Y.data_ptr(), ldy, _stream(stream)), "bf_apply")
+                              Y.data_ptr(), ldy, _alloc_ptr(_allocator(allocator)),
+                              _stream(stream)), "bf_apply")
         return Y
 
     def close(self, stream=None):
+        """Free the factors; their memory is reused only after the work already
+        enqueued on `stream` (default: torch's current stream) has finished."""
         if self._h:
-            lib().bf_free(self._h, _stream(stream) if stream is not None else None)
+            lib().bf_free(self._h, _stream(stream))
             self._h = None
+            self._alloc = None
 
     def __del__(self):
         try:
@@ -386,7 +488,7 @@ class Factors:
 
 def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed: int = 0,
               max_rank: int = 0, stream=None, work_bytes: int = 0, progress=None,
-              center="hybrid", merge_leaf: bool = True) -> Factors:
+              center="hybrid", merge_leaf: bool = True, allocator="torch") -> Factors:
     """Alg. 2 on the device; returns the factor handle.  work_bytes bounds the
     device memory of one sweep level's samples (0: 8 GiB).  progress(phase,
     level), if given, is called after each leaf-loop iteration and sweep level
@@ -394,7 +496,9 @@ def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed
     "hybrid" (floor(L/2)), "column" (0: column-wise factorization), "row" (L:
     row-wise), or an integer level (negative counts from L + 1).  merge_leaf:
     consecutive passes of the adaptive leaf loops share a black-box call
-    (same results, fewer calls); False makes one call per pass."""
+    (same results, fewer calls); False makes one call per pass.  allocator:
+    where the device memory comes from -- "torch" (torch's caching allocator,
+    default) or None (the library's own pool)."""
     o = bf_opts(p, r0, max_rank, 0, seed, work_bytes)
     lm = CENTERS[center] if isinstance(center, str) else int(center)
     if lm is not None:
@@ -406,20 +510,24 @@ def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed
     if progress is not None:
         cb = PROGRESSFN(lambda _u, ph, lv: progress(PHASES[ph], lv))
         o.progress = cb
+    a = _allocator(allocator)
     h = C.c_void_p()
     _check(lib().bf_construct(op._op.matvec, op._op.rmatvec, op._op.user, op.m, op.n, float(tol),
-                              int(leaf), C.byref(o), _stream(stream), C.byref(h)), "bf_construct")
-    return Factors(h, leaf)
+                              int(leaf), C.byref(o), _alloc_ptr(a), _stream(stream), C.byref(h)),
+           "bf_construct")
+    return Factors(h, leaf, a)
 
 
-def import_factors(m, n, leaf, kU, kV, data, stream=None) -> Factors:
+def import_factors(m, n, leaf, kU, kV, data, stream=None, allocator="torch") -> Factors:
     kU = np.ascontiguousarray(kU, np.int32).ravel()
     kV = np.ascontiguousarray(kV, np.int32).ravel()
     data = np.ascontiguousarray(data, np.complex128)
+    a = _allocator(allocator)
     h = C.c_void_p()
     _check(lib().bf_import(m, n, leaf, kU.ctypes.data_as(_I32P), kV.ctypes.data_as(_I32P),
-                           data.ctypes.data, len(data), _stream(stream), C.byref(h)), "bf_import")
-    return Factors(h, leaf)
+                           data.ctypes.data, len(data), _alloc_ptr(a), _stream(stream),
+                           C.byref(h)), "bf_import")
+    return Factors(h, leaf, a)
 
 
 class _Borrowed(Factors):
@@ -433,13 +541,21 @@ class Server:
     """Request engine: concurrent constructions and applies on `slots` streams
     with admission by estimated device footprint (see include/bf.h)."""
 
-    def __init__(self, slots=4, hbm_budget=0, batch_cols=0):
+    def __init__(self, slots=4, hbm_budget=0, batch_cols=0, allocator="torch",
+                 solve_rounds=False):
         """batch_cols > 0 merges queued applies against the same factors into
-        one product of at most that many columns (continuous batching)."""
+        one product of at most that many columns (continuous batching).
+        allocator: device memory of every request -- "torch" (torch's caching
+        allocator, default) or None (the library's own pool).  solve_rounds:
+        the level solves of in-flight constructions share persistent launches
+        (cross-request rounds, replayed from captured graphs)."""
+        self._alloc = _allocator(allocator)
+        o = bf_server_opts(slots, int(batch_cols), int(hbm_budget))
+        o.solve_rounds = int(bool(solve_rounds))
+        if self._alloc is not None:
+            o.alloc = C.pointer(self._alloc.struct)
         h = C.c_void_p()
-        _check(lib().bf_server_create(C.byref(bf_server_opts(slots, int(batch_cols),
-                                                             int(hbm_budget))),
-                                      C.byref(h)), "bf_server_create")
+        _check(lib().bf_server_create(C.byref(o), C.byref(h)), "bf_server_create")
         self._h = h
         self._keep = {}
 
@@ -488,6 +604,12 @@ class Server:
         _check(lib().bf_server_factors(self._h, ticket, C.byref(h)), "bf_server_factors")
         return _Borrowed(h, 0)
 
+    def rounds(self):
+        """(solve rounds launched, blocks they held)."""
+        r, i = C.c_int64(), C.c_int64()
+        _check(lib().bf_server_rounds(self._h, C.byref(r), C.byref(i)), "bf_server_rounds")
+        return r.value, i.value
+
     def release(self, ticket):
         _check(lib().bf_server_release(self._h, ticket), "bf_server_release")
         self._keep.pop(ticket, None)
@@ -512,15 +634,30 @@ def release_cached_memory():
 
 
 def set_autotune(enable=True):
-    """Tile-width autotuner of the built-in black boxes (bf_set_autotune)."""
+    """Launch-shape autotuner (bf_set_autotune; on by default)."""
     _check(lib().bf_set_autotune(1 if enable else 0), "bf_set_autotune")
 
 
 def autotune_entries() -> int:
-    """Shape classes the autotuner has timed so far."""
+    """Shape classes in the autotuner's table (loaded or timed)."""
     n = C.c_int64(0)
     _check(lib().bf_autotune_entries(C.byref(n)), "bf_autotune_entries")
     return n.value
+
+
+def autotune_save(path=None):
+    """Write the autotuner's table (default: tune_gfx950.tsv beside libbf.so)."""
+    _check(lib().bf_autotune_save(path.encode() if path else None), "bf_autotune_save")
+
+
+def autotune_load(path=None):
+    """Merge a saved table into the autotuner's."""
+    _check(lib().bf_autotune_load(path.encode() if path else None), "bf_autotune_load")
+
+
+def autotune_clear():
+    """Empty the autotuner's table (classes are timed again on first use)."""
+    _check(lib().bf_autotune_clear(), "bf_autotune_clear")
 
 
 def profile_start():

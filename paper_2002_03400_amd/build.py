@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbf.so")
 SOURCES = ["rng.hip", "matfree.hip", "linalg.hip", "apply.hip", "driver.cpp", "plan.cpp", "abi.cpp",
-           "server.cpp", "noalloc.hip"]
+           "server.cpp", "noalloc.hip", "rounds.cpp", "tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

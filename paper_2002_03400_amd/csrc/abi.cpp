@@ -106,6 +106,7 @@ namespace {
 struct BlockInfo {
   size_t cap;
   int dev;
+  UserAlloc ua;   // ua.alloc != nullptr: the block came from a caller's bf_alloc
 };
 std::mutex g_cap_mu;
 std::unordered_map<void*, BlockInfo> g_cap;   // every block dev_alloc made
@@ -129,21 +130,31 @@ bool capturing(hipStream_t s) {
 BlockInfo block_info(void* p) {
   std::lock_guard<std::mutex> lk(g_cap_mu);
   auto it = g_cap.find(p);
-  return it == g_cap.end() ? BlockInfo{0, -1} : it->second;
+  return it == g_cap.end() ? BlockInfo{0, -1, UserAlloc{}} : it->second;
 }
 
+// return p to where it came from: the caller's allocator or the device pool
 void give_back(void* p, hipStream_t s) {
+  UserAlloc ua{};
   {
     std::lock_guard<std::mutex> lk(g_cap_mu);
-    g_cap.erase(p);
+    auto it = g_cap.find(p);
+    if (it != g_cap.end()) {
+      ua = it->second.ua;
+      g_cap.erase(it);
+    }
   }
-  (void)hipFreeAsync(p, s);
+  if (ua.alloc)
+    ua.free(ua.ctx, p, (void*)s);
+  else
+    (void)hipFreeAsync(p, s);
 }
 
 // keep p (last used on s) for reuse; false: the caller gives it back
+// (blocks of a caller's allocator always go back to it)
 bool keep_block(void* p, hipStream_t s) {
   const BlockInfo bi = block_info(p);
-  if (bi.cap == 0 || bi.dev < 0 || bi.dev >= 64 || capturing(s)) return false;
+  if (bi.cap == 0 || bi.dev < 0 || bi.dev >= 64 || bi.ua.alloc || capturing(s)) return false;
   DevKeep& k = g_keep[bi.dev];
   {
     std::lock_guard<std::mutex> lk(k.mu);
@@ -245,6 +256,18 @@ struct AllocScope::Cache {
   }
 };
 static thread_local AllocScope::Cache* t_cache = nullptr;
+static thread_local const UserAlloc* t_user = nullptr;
+
+UseAllocator::UseAllocator(const bf_alloc* a) : prev_(t_user) {
+  if (!a) return;
+  BF_CHECK(a->alloc && a->free, BF_EINVAL, "bf_alloc: alloc and free are both required");
+  ua_ = UserAlloc{a->ctx, a->alloc, a->free};
+  t_user = &ua_;
+  set_ = true;
+}
+UseAllocator::~UseAllocator() {
+  if (set_) t_user = prev_;
+}
 // free blocks a scope may hold before it returns them to the pool
 static constexpr size_t kScopeFreeLimit = size_t(8) << 30;
 
@@ -291,6 +314,17 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
       c->free_.erase(it);
     }
   }
+  if (!p && t_user) {   // the caller's allocator (bf_alloc) instead of the pool
+    p = t_user->alloc(t_user->ctx, want, (void*)s);
+    BF_CHECK(p != nullptr, BF_ENOMEM,
+             "bf_alloc: the caller's allocator returned NULL for " + std::to_string(want) +
+                 " bytes");
+    {
+      std::lock_guard<std::mutex> lk(g_cap_mu);
+      g_cap[p] = BlockInfo{want, dev, *t_user};
+    }
+    if (scoped) c->cap_[p] = want;
+  }
   if (!p && !capturing(s)) {
     size_t cap = 0;
     p = take_kept(dev, want, s, &cap);
@@ -308,7 +342,7 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
     BF_HIP(e);
     {
       std::lock_guard<std::mutex> lk(g_cap_mu);
-      g_cap[p] = BlockInfo{want, dev};
+      g_cap[p] = BlockInfo{want, dev, UserAlloc{}};
     }
     if (scoped) c->cap_[p] = want;
   }
@@ -706,14 +740,17 @@ int bf_profile_stop(bf_kernel_stats* out) {
 }
 
 int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64_t n, double tol,
-                 int64_t leaf, const bf_opts* opts, void* stream, bf_factors** out) {
-  if (!matvec || !rmatvec || !out || m <= 0 || n <= 0 || !(tol > 0.0 && tol < 1.0) || leaf < 1) {
+                 int64_t leaf, const bf_opts* opts, const bf_alloc* alloc, void* stream,
+                 bf_factors** out) {
+  if (!matvec || !rmatvec || !out || m <= 0 || n <= 0 || !(tol > 0.0 && tol < 1.0) || leaf < 1 ||
+      (alloc && (!alloc->alloc || !alloc->free))) {
     set_last_error("bf_construct: invalid argument");
     return BF_EINVAL;
   }
   bf_factors* F = nullptr;
   int rc = guarded([&] {
     check_device();
+    UseAllocator ua(alloc);
     AllocScope scope((hipStream_t)stream);
     F = construct(matvec, rmatvec, user, m, n, tol, leaf, opts, (hipStream_t)stream);
   });
@@ -722,11 +759,13 @@ int bf_construct(bf_op_fn matvec, bf_op_fn rmatvec, void* user, int64_t m, int64
 }
 
 int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
-             bf_c64* Y, int64_t ldy, void* stream) {
+             bf_c64* Y, int64_t ldy, const bf_alloc* alloc, void* stream) {
   if (!F || !X || !Y || ncols < 0 || (trans != 0 && trans != 1)) return BF_EINVAL;
+  if (alloc && (!alloc->alloc || !alloc->free)) return BF_EINVAL;
   const int64_t rin = trans ? F->m : F->n, rout = trans ? F->n : F->m;
   if (ldx < rin || ldy < rout) return BF_EINVAL;
   return guarded([&] {
+    UseAllocator ua(alloc);
     AllocScope scope((hipStream_t)stream);
     apply_factors(F, trans, X, ldx, ncols, Y, ldy, (hipStream_t)stream);
   });
@@ -741,6 +780,12 @@ int bf_apply_noalloc(const bf_factors* F, int trans, const bf_c64* X, int64_t ld
 }
 
 int64_t bf_apply_noalloc_scratch_bytes(void) { return (int64_t)noalloc_scratch_bytes(); }
+
+int bf_set_apply_fusion(bf_factors* F, int enable) {
+  if (!F || (enable != 0 && enable != 1)) return BF_EINVAL;
+  F->apply_fuse = enable;
+  return BF_OK;
+}
 
 int bf_set_apply_precision(bf_factors* F, int precision) {
   if (!F || (precision != BF_PREC_FP32 && precision != BF_PREC_BF16X3)) return BF_EINVAL;
@@ -817,12 +862,15 @@ int bf_export(const bf_factors* F, bf_c128* data, int64_t* count) {
 }
 
 int bf_import(int64_t m, int64_t n, int64_t leaf, const int32_t* kU, const int32_t* kV,
-              const bf_c128* data, int64_t count, void* stream, bf_factors** out) {
+              const bf_c128* data, int64_t count, const bf_alloc* alloc, void* stream,
+              bf_factors** out) {
   if (m <= 0 || n <= 0 || leaf < 1 || !kU || !kV || !out || (count > 0 && !data)) return BF_EINVAL;
+  if (alloc && (!alloc->alloc || !alloc->free)) return BF_EINVAL;
   bf_factors* F = new (std::nothrow) bf_factors();
   if (!F) return BF_ENOMEM;
   int rc = guarded([&] {
     check_device();
+    UseAllocator ua(alloc);
     hipStream_t s = (hipStream_t)stream;
     F->m = m;
     F->n = n;
@@ -924,6 +972,15 @@ int bf_release_cached_memory(void) {
 int bf_free(bf_factors* F, void* stream) {
   if (!F) return BF_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  if (!s) {
+    // the null stream does not order work on non-blocking streams: wait for
+    // everything on the factors' device before their blocks can be reused
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(F->device) == hipSuccess) {
+      (void)hipDeviceSynchronize();
+      (void)hipSetDevice(cur);
+    }
+  }
   for (auto& b : F->store) b.s = s;
   for (auto* P : {&F->fwd, &F->adj}) {
     P->G.s = s;
@@ -1095,6 +1152,23 @@ int bf_set_autotune(int enable) {
 int bf_autotune_entries(int64_t* entries) {
   if (!entries) return BF_EINVAL;
   *entries = autotune_entries();
+  return BF_OK;
+}
+
+int bf_autotune_save(const char* path) {
+  return guarded([&] {
+    BF_CHECK(tune_save(path) == BF_OK, BF_EINVAL, "bf_autotune_save: cannot write the table");
+  });
+}
+
+int bf_autotune_load(const char* path) {
+  return guarded([&] {
+    BF_CHECK(tune_load(path) == BF_OK, BF_EINVAL, "bf_autotune_load: cannot read the table");
+  });
+}
+
+int bf_autotune_clear(void) {
+  tune_clear();
   return BF_OK;
 }
 

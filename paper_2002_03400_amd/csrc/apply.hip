@@ -447,6 +447,164 @@ __global__ __launch_bounds__(256) void apply_mfma_small_kernel(const ApplyBlk* _
   }
 }
 
+// ---- fused stages (few right-hand sides) ---------------------------------
+//
+// One launch runs several consecutive stages.  The blocks of those stages
+// split into groups that depend only on each other (each block's inputs are
+// produced inside its group, or come from the launch's input buffer), and
+// workgroup w runs group w stage after stage, with a barrier between stages:
+// an apply of 13 stages becomes 4 launches instead of 13 dependent ones.
+// Rows follow the few-column kernel above (8 lanes per output row, same
+// summation order, so 1, 2 and 4 columns give its results bit for bit); 8 and
+// 16 columns take one or two entries per lane and step.  Intermediates of a
+// launch are written to global memory and read back by the same workgroup
+// after the barrier (each stage writes its own rows, so workgroups never
+// overwrite what another still reads).
+template <typename Acc, int NC>
+__device__ __forceinline__ void fused_row(const ApplyRowRec& rr, int q, const bf_c64* __restrict__ G,
+                                          const ApplyBufs& B, int ncols) {
+  const int KK = rr.KK;
+  const bf_c64* g = G + rr.g;
+  const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
+  const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
+  const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
+  Acc acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = Acc{0, 0};
+  if constexpr (NC <= 2) {
+    const int K0 = rr.K0;
+    for (int kb = 0; kb < KK; kb += 4 * AP_LPR) {
+      bf_c64 gv[4], xv[4][NC];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = kb + 2 * q + 2 * AP_LPR * u;
+        const bool k0v = k < KK, k1v = k + 1 < KK;
+        if (k1v) {
+          load_pair(g + k, gv[2 * u], gv[2 * u + 1]);
+        } else {
+          gv[2 * u] = k0v ? g[k] : bf_c64{0.f, 0.f};
+          gv[2 * u + 1] = bf_c64{0.f, 0.f};
+        }
+        const bool seg0 = k < K0, seg1 = k + 1 < K0;
+        const bf_c64* base = seg0 ? in0 : in1;
+        const int64_t ldk = seg0 ? ld0 : ld1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          if (c < ncols && k1v && seg0 == seg1) {
+            load_pair(base + k + (int64_t)c * ldk, xv[2 * u][c], xv[2 * u + 1][c]);
+          } else {
+            xv[2 * u][c] = (c < ncols && k0v) ? base[k + (int64_t)c * ldk] : bf_c64{0.f, 0.f};
+            xv[2 * u + 1][c] = (c < ncols && k1v)
+                                   ? (seg1 ? in0 : in1)[k + 1 + (int64_t)c * (seg1 ? ld0 : ld1)]
+                                   : bf_c64{0.f, 0.f};
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[u], xv[u][c]);
+    }
+  } else {
+    // one entry per lane and load; U entries per lane and step keep the
+    // registers of the loaded inputs near 32 whatever the column count
+    constexpr int U = NC >= 16 ? 1 : (NC >= 8 ? 2 : 4);
+    for (int kb = 0; kb < KK; kb += U * AP_LPR) {
+      bf_c64 gv[U], xv[U][NC];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = kb + q + AP_LPR * u;
+        const bool kv = k < KK;
+        gv[u] = kv ? g[k] : bf_c64{0.f, 0.f};
+        const bf_c64* inp = k < rr.K0 ? in0 + k : in1 + k;
+        const int64_t ldk = k < rr.K0 ? ld0 : ld1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          xv[u][c] = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[u], xv[u][c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    acc[c].re = row8_sum(acc[c].re);
+    acc[c].im = row8_sum(acc[c].im);
+  }
+  if (q == 0) {
+    bf_c64* out = B.p[rr.out_buf] + rr.out;
+    const int64_t ldo = B.ld[rr.out_buf];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
+  }
+}
+
+// off[w * (nstage + 1) + t] .. off[w * (nstage + 1) + t + 1]: the row records
+// of workgroup w's group in stage t (records grouped by workgroup, then stage).
+// NT threads per workgroup: NT / 8 rows of a stage at a time.  Rows are
+// independent, so NT changes the schedule only, never the results.
+template <typename Acc, int NC, int NT>
+__global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __restrict__ rows,
+                                                         const int32_t* __restrict__ off,
+                                                         int32_t nstage,
+                                                         const bf_c64* __restrict__ G,
+                                                         ApplyBufs B, int32_t ncols) {
+  const int q = threadIdx.x & (AP_LPR - 1);
+  const int rl = threadIdx.x / AP_LPR;
+  const int32_t* o = off + (int64_t)blockIdx.x * (nstage + 1);
+  for (int t = 0; t < nstage; ++t) {
+    const int32_t r0 = o[t], r1 = o[t + 1];
+    for (int32_t R = r0 + rl; R < r1; R += NT / AP_LPR) fused_row<Acc, NC>(rows[R], q, G, B, ncols);
+    if (t + 1 < nstage) __syncthreads();
+  }
+}
+
+void launch_apply_fused(const ApplyRowRec* rows_dev, const int32_t* off_dev, int32_t nwg,
+                        int32_t nstage, int32_t threads, const bf_c64* G,
+                        const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
+                        int prec, hipStream_t s) {
+  if (nwg <= 0 || ncols <= 0) return;
+  BF_CHECK(ncols <= kApplyFusedCols, BF_EINVAL, "fused apply: too many right-hand sides");
+  BF_CHECK(threads == 256 || threads == 512 || threads == 1024, BF_EINVAL,
+           "fused apply: 256, 512 or 1024 threads per workgroup");
+  ApplyBufs B;
+  for (int i = 0; i < 4; ++i) {
+    B.p[i] = const_cast<bf_c64*>(bufs[i]);
+    B.ld[i] = lds[i];
+    B.rs[i] = 1;
+  }
+  const int nc = (int)ncols;
+  const dim3 grid((unsigned)nwg);
+#define AP_FUSED_T(ACC, N, T) \
+  hipLaunchKernelGGL((apply_fused_kernel<ACC, N, T>), grid, dim3(T), 0, s, rows_dev, off_dev, \
+                     nstage, G, B, nc)
+#define AP_FUSED(ACC, N) \
+  do { \
+    if (threads == 256) AP_FUSED_T(ACC, N, 256); \
+    else if (threads == 512) AP_FUSED_T(ACC, N, 512); \
+    else AP_FUSED_T(ACC, N, 1024); \
+  } while (0)
+  if (nc == 1) {
+    if (prec == BF_PREC_FP32) AP_FUSED(cf, 1); else AP_FUSED(cd, 1);
+  } else if (nc == 2) {
+    AP_FUSED(cf, 2);
+  } else if (nc <= 4) {
+    AP_FUSED(cf, 4);
+  } else if (nc <= 8) {
+    AP_FUSED(cf, 8);
+  } else {
+    AP_FUSED(cf, 16);
+  }
+#undef AP_FUSED
+#undef AP_FUSED_T
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs == hipStreamCaptureStatusNone)
+    BF_HIP(hipGetLastError());
+}
+
 constexpr size_t AP_LDS_LIMIT = 160 * 1024;
 
 // One workgroup per block: row r of block b multiplies packed row r of its

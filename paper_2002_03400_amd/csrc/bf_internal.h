@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -61,6 +63,29 @@ struct ProfScope {
 
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+
+// A caller's device-memory provider (bf_alloc).  While a UseAllocator is
+// alive on a thread, every device block the thread allocates comes from it
+// (recycled within an AllocScope like pool blocks) and goes back to it when
+// freed, whenever that is (factor storage at bf_free); such blocks are never
+// kept by the library.  A null bf_alloc leaves the library's own pool in use.
+struct UserAlloc {
+  void* ctx = nullptr;
+  void* (*alloc)(void*, size_t, void*) = nullptr;
+  void (*free)(void*, void*, void*) = nullptr;
+};
+class UseAllocator {
+ public:
+  explicit UseAllocator(const bf_alloc* a);
+  ~UseAllocator();
+  UseAllocator(const UseAllocator&) = delete;
+  UseAllocator& operator=(const UseAllocator&) = delete;
+
+ private:
+  UserAlloc ua_{};
+  const UserAlloc* prev_ = nullptr;
+  bool set_ = false;
+};
 
 struct Staging;
 // Recycling scope of one request.  While an AllocScope is alive on a thread,
@@ -210,6 +235,51 @@ struct LSDesc {
 };
 void launch_lsq(const LSDesc* d_dev, int32_t nblk, int32_t maxS, int32_t maxK, hipStream_t s);
 
+// Cross-request solve rounds: one persistent launch over a work list of
+// blocks from several requests' batched QRs and least squares (LDS path
+// only: each block's need, solve_lds_qr / solve_lds_lsq, must be at most
+// solve_lds_limit()).  nitems is a device int read by the kernel.
+enum { kSolveQR = 0, kSolveLSQ = 1 };
+struct SolveWork {
+  const void* descs;   // QRDesc* or LSDesc* (device)
+  int32_t* ranks;      // QR: rank of block b at ranks[b] (device)
+  double tol;
+  int32_t kind;
+  int32_t in_c64;
+};
+struct SolveItem {
+  int32_t work, block;
+};
+size_t solve_lds_qr(int32_t maxM, int32_t maxN);
+size_t solve_lds_lsq(int32_t maxS, int32_t maxK);
+size_t solve_lds_limit();
+void launch_solve_round(const SolveWork* works, const SolveItem* items, const int32_t* nitems,
+                        int32_t grid, size_t lds, hipStream_t s);
+// Hands a level's batched solves to the solve rounds of the calling thread's
+// request engine, if it has them (blocks until the round is launched; the
+// stream s then waits for it); false: the caller launches them itself.
+// cost[b]: estimated work of block b (orders the round's work list).
+bool round_solve(int kind, const void* descs_dev, int32_t n, const std::vector<double>& cost,
+                 double tol, bool in_c64, int32_t* ranks_dev, size_t lds, hipStream_t s);
+
+class SolveRounds;
+SolveRounds* new_solve_rounds(int device);
+void delete_solve_rounds(SolveRounds* R);
+void solve_rounds_stats(const SolveRounds* R, int64_t* rounds, int64_t* items);
+// While alive, the calling thread's constructions hand their level solves to
+// R (round_solve) and count as in flight for its round windows.
+class RoundsScope {
+ public:
+  explicit RoundsScope(SolveRounds* R);
+  ~RoundsScope();
+  RoundsScope(const RoundsScope&) = delete;
+  RoundsScope& operator=(const RoundsScope&) = delete;
+
+ private:
+  SolveRounds* R_;
+  SolveRounds* prev_;
+};
+
 // complex128 -> complex64 copy (contiguous)
 void launch_c128_to_c64(const bf_c128* in, bf_c64* out, int64_t n, hipStream_t s);
 
@@ -240,6 +310,9 @@ void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* row
 // Up to this many right-hand sides a stage runs the few-column kernel, whose
 // row records address column-major buffers.
 constexpr int kApplyFewCols = 4;
+// Up to this many right-hand sides an apply runs its stages fused (several
+// stages per launch, launch_apply_fused), column-major throughout.
+constexpr int kApplyFusedCols = 16;
 // maxMK / maxKK / maxM: largest M*(K0+K1), K0+K1 and M over the stage's
 // blocks.  Buffer i holds element (r, c) at bufs[i][r * rss[i] + c * lds[i]]
 // (column-major: rss = 1; with at most kApplyFewCols columns every buffer must be).
@@ -249,6 +322,16 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
                         int32_t nrows, int32_t maxMK, int32_t maxKK, int32_t maxM, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], const int64_t rss[4],
                         int64_t ncols, int prec, hipStream_t s);
+
+// Fused stages: workgroup w runs the row records [off[w*(nstage+1)+t],
+// off[w*(nstage+1)+t+1]) of stage t for t = 0..nstage-1, with a barrier
+// between stages; buffers column-major (element (r, c) at bufs[i][r + c*lds[i]]).
+// ncols <= kApplyFusedCols; FP64 sums for one column unless prec is FP32.
+// threads: 256, 512 or 1024 per workgroup (8 per row being computed).
+void launch_apply_fused(const ApplyRowRec* rows_dev, const int32_t* off_dev, int32_t nwg,
+                        int32_t nstage, int32_t threads, const bf_c64* G,
+                        const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
+                        int prec, hipStream_t s);
 
 // Gather (and optionally conjugate-transpose) factor sub-blocks into an
 // arena: element (r, k) of the M x K result goes to
@@ -275,6 +358,28 @@ void launch_expand_segments(const bf_c64* X, int64_t ldx, int64_t rows, int64_t 
                             const int64_t* seg_dev, int32_t nseg, bf_c64* out, int64_t ldo,
                             hipStream_t s);
 
+// -------------------------------------------------------------- autotuner --
+// Family, then kTuneKeyFields class fields (powers of two of the sizes that
+// matter, column counts, flags).  tune_choose runs run(c) for the class's
+// chosen candidate c -- or, the first time a class is seen (tuner on, stream
+// not capturing), every candidate in turn, timed, keeping the fastest -- and
+// returns it; with the tuner off or a single candidate it runs `fallback`,
+// and so it does for an unknown class under capture or when may_time is
+// false (callers that must not create events).  Candidates must give bitwise
+// the same results.
+enum { kTuneMatfreeWidth = 0, kTuneChainRows = 1, kTuneCpqrThreads = 2, kTuneApplyFused = 3,
+       kTuneFamilies = 4 };
+constexpr int kTuneKeyFields = 5;
+using TuneKey = std::array<int64_t, 1 + kTuneKeyFields>;
+int64_t pow2_ceil(int64_t v);
+bool autotune_on();
+int64_t tune_choose(const TuneKey& key, const std::vector<int64_t>& cand, int64_t fallback,
+                    hipStream_t s, const std::function<void(int64_t)>& run,
+                    bool may_time = true);
+int tune_save(const char* path);
+int tune_load(const char* path);
+void tune_clear();
+
 // ------------------------------------------------- matrix-free operators --
 struct PointSet {     // structure-of-arrays FP64 coordinates on the device
   const double* x;
@@ -283,7 +388,7 @@ struct PointSet {     // structure-of-arrays FP64 coordinates on the device
 };
 // Y[:, g*ncols + c] = sum_{j in seg_g} E(i, j) X[j, c], E = kernel entries of
 // op(A) (sign = +1: A, sign = -1: A^H, points swapped by the caller).
-// Black-box tile-width autotuner (see matfree.hip); process-wide.
+// The autotuner's switch and table size (tune.cpp); process-wide.
 void set_autotune(int on);
 int64_t autotune_entries();
 void launch_segkernel(int prec, PointSet out_pts, int64_t nout, PointSet in_pts, int64_t nin,

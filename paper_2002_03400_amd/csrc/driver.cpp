@@ -234,7 +234,14 @@ class Builder {
       }
     auto dd = upload(d, s_, st_);
     DevBuf<int32_t> rk(nblk, s_);
-    launch_cpqr(dd.p, (int32_t)nblk, maxM, maxN, tol_, in_c64, rk.p, s_);
+    // in a request engine with solve rounds, this level's QRs join the other
+    // in-flight constructions' in one launch (same per-block code)
+    std::vector<double> cost(nblk);
+    for (size_t b = 0; b < nblk; ++b)
+      cost[b] = (double)in[b].M * in[b].N * std::min(in[b].M, in[b].N);
+    if (!round_solve(kSolveQR, dd.p, (int32_t)nblk, cost, tol_, in_c64, rk.p,
+                     solve_lds_qr(maxM, maxN), s_))
+      launch_cpqr(dd.p, (int32_t)nblk, maxM, maxN, tol_, in_c64, rk.p, s_);
     std::vector<int32_t> ranks(nblk);
     int32_t* hr = static_cast<int32_t*>(st_.alloc(nblk * sizeof(int32_t), s_));
     BF_HIP(hipMemcpyAsync(hr, rk.p, nblk * sizeof(int32_t), hipMemcpyDeviceToHost, s_));
@@ -791,7 +798,12 @@ class Builder {
       }
     if (!d.empty()) {
       auto dd = upload(d, s_, st_);
-      launch_lsq(dd.p, (int32_t)d.size(), maxS, maxK, s_);
+      std::vector<double> cost(d.size());
+      for (size_t b = 0; b < d.size(); ++b)
+        cost[b] = (double)d[b].s * d[b].kV * (d[b].kU + d[b].kV);
+      if (!round_solve(kSolveLSQ, dd.p, (int32_t)d.size(), cost, 0.0, false, nullptr,
+                       solve_lds_lsq(maxS, maxK), s_))
+        launch_lsq(dd.p, (int32_t)d.size(), maxS, maxK, s_);
     }
     F_->store.push_back(std::move(Bst));
   }

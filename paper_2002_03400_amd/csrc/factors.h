@@ -34,12 +34,28 @@ struct Stage {
   double macs = 0;   // complex multiply-adds per right-hand side
 };
 
+// Consecutive stages run as one launch (launch_apply_fused): workgroup w
+// takes records foff[off_off + w*(nstage+1) + t] .. +1 of stage t.
+struct FusedSeg {
+  int64_t off_off = 0;
+  int32_t nwg = 0, nstage = 0;
+  int32_t first_stage = 0;
+  int32_t max_rows = 0;   // most rows one group has in one stage
+  double macs = 0;        // complex multiply-adds per right-hand side
+};
+
 struct ApplyPlan {
   DevBuf<bf_c64> G;              // packed blocks of every stage (row-major per block)
   DevBuf<ApplyBlk> blks;         // output blocks of all stages, stage after stage
   DevBuf<ApplyRowRec> rows;      // output rows of all stages (few right-hand sides)
   std::vector<Stage> stages;     // in execution order
   int64_t tmp_rows = 0;          // rows of each ping-pong intermediate
+  // fused schedule (few right-hand sides): every stage but the last writes its
+  // own rows of one tall intermediate of fused_rows rows
+  DevBuf<ApplyRowRec> frows;     // row records grouped by segment, workgroup, stage
+  DevBuf<int32_t> foff;
+  std::vector<FusedSeg> segs;
+  int64_t fused_rows = 0;
 };
 
 }  // namespace bf
@@ -62,6 +78,7 @@ struct bf_factors {
   std::vector<int32_t> kU, kV;              // ranks, layout of bf_ranks
   bf::ApplyPlan fwd, adj;
   int apply_prec = BF_PREC_BF16X3;          // bf_set_apply_precision
+  int apply_fuse = 1;                       // bf_set_apply_fusion
   bf_info info{};
   int device = 0;
   int64_t graph_cols = 0;                   // bf_set_apply_graph_cols
@@ -88,18 +105,22 @@ struct bf_factors {
 namespace bf {
 // Build the forward and adjoint apply plans (packs the complex64 blocks).
 void build_apply_plans(bf_factors* F, hipStream_t s);
-// The L+3 stage launches of one apply with caller-provided ping-pong
-// intermediates t1, t2 (each room for plan.tmp_rows x ncols values); prof
-// brackets each launch for bf_profile_* (creates events; off for callers that
-// must not allocate).
-void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
-                      int64_t ncols, bf_c64* Y, int64_t ldy, bf_c64* t1, bf_c64* t2,
-                      hipStream_t s, bool prof);
+// Device bytes of intermediates an apply of ncols columns uses: the fused
+// schedule's tall buffer for up to kApplyFusedCols columns, else (or with
+// staged = true) two ping-pong buffers of plan.tmp_rows rows.
+size_t apply_scratch_bytes(const bf_factors* F, int trans, int64_t ncols, bool staged = false);
+// One apply with caller-provided intermediates (scratch, scratch_bytes): the
+// fused schedule when ncols allows it and the scratch holds it, else the L+3
+// stage launches (BF_EINVAL if neither fits).  prof brackets each launch for
+// bf_profile_* (creates events; off for callers that must not allocate).
+void run_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
+               bf_c64* Y, int64_t ldy, void* scratch, size_t scratch_bytes, hipStream_t s,
+               bool prof);
 // Apply (Y = F X or F^H X), complex64.
 void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
                    bf_c64* Y, int64_t ldy, hipStream_t s);
-// bf_apply_noalloc: run_apply_stages with the intermediates in the library's
-// fixed per-device scratch array (noalloc.hip); BF_EINVAL if they do not fit.
+// bf_apply_noalloc: run_apply with the intermediates in the library's fixed
+// per-device scratch array (noalloc.hip); BF_EINVAL if they do not fit.
 void apply_noalloc(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
                    bf_c64* Y, int64_t ldy, hipStream_t s);
 size_t noalloc_scratch_bytes();

@@ -189,14 +189,17 @@ __global__ __launch_bounds__(256) void chain_small_kernel(const GemmDesc* __rest
   }
 }
 
+// One launch with tile height `rows`: 8 or 16 (chain_small_kernel, every
+// descriptor's M at most that) or 20 / 24 / 32 / 64 (chain_gemm_kernel, row
+// blocks of that height).  Every height gives the same FP64 operation order.
 template <typename Tin>
-static void launch_chain_t(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols,
-                           int32_t max_M, hipStream_t s) {
-  if (max_M <= 16) {
-    const int cw = (max_M <= 8 ? 8 : 4) * CS_TC;
+static void launch_chain_rows(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, int rows,
+                              hipStream_t s) {
+  if (rows <= 16) {
+    const int cw = (rows <= 8 ? 8 : 4) * CS_TC;
     dim3 grid((unsigned)((ndesc + 3) / 4),
               (unsigned)std::min((max_ncols + cw - 1) / cw, CG_YMAX));
-    if (max_M <= 8)
+    if (rows <= 8)
       hipLaunchKernelGGL((chain_small_kernel<Tin, 8>), grid, dim3(256), 0, s, d_dev,
                          (int64_t)ndesc);
     else
@@ -206,14 +209,30 @@ static void launch_chain_t(const GemmDesc* d_dev, int32_t ndesc, int32_t max_nco
   }
   const int nchunk = (max_ncols + CG_COLS - 1) / CG_COLS;
   dim3 grid((unsigned)ndesc, (unsigned)std::min(nchunk, CG_YMAX));
-  if (max_M <= 20)
+  if (rows <= 20)
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 20>), grid, dim3(256), 0, s, d_dev);
-  else if (max_M <= 24)
+  else if (rows <= 24)
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 24>), grid, dim3(256), 0, s, d_dev);
-  else if (max_M <= 32)
+  else if (rows <= 32)
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 32>), grid, dim3(256), 0, s, d_dev);
   else
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 64>), grid, dim3(256), 0, s, d_dev);
+}
+
+// Tile heights at least the launch's largest M (32 and 64 above 64 rows);
+// the smallest is the rule without the autotuner.
+template <typename Tin>
+static void launch_chain_t(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols,
+                           int32_t max_M, hipStream_t s) {
+  std::vector<int64_t> cand;
+  for (int h : {8, 16, 20, 24, 32, 64})
+    if (h >= max_M) cand.push_back(h);
+  if (cand.empty()) cand = {32, 64};
+  const TuneKey key{kTuneChainRows, sizeof(Tin) == sizeof(bf_c64) ? 1 : 0, max_M,
+                    pow2_ceil(ndesc), pow2_ceil(max_ncols), 0};
+  tune_choose(key, cand, cand.front(), s, [&](int64_t h) {
+    launch_chain_rows<Tin>(d_dev, ndesc, max_ncols, (int)h, s);
+  });
 }
 
 void launch_chain_gemm(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, int32_t max_M,
@@ -272,17 +291,16 @@ __device__ __forceinline__ void reflect_column(cd* A, int M, int k, int j, const
   }
 }
 
+// One block by one workgroup of NT threads (every thread calls it with the
+// same descriptor; returns together).  smem: the workgroup's dynamic LDS;
+// gslot: the block's global scratch slot when use_lds == 0.
 template <typename Tin, int NT>
-__global__ __launch_bounds__(NT) void cpqr_kernel(const QRDesc* __restrict__ descs,
-                                                          double tol, int32_t* __restrict__ ranks,
-                                                          bf_c128* __restrict__ gscratch,
-                                                          int64_t scratch_slot, int use_lds) {
-  extern __shared__ double smem_raw[];
-  const QRDesc d = descs[blockIdx.x];
+__device__ void cpqr_block(const QRDesc& d, double tol, int32_t* __restrict__ rank_out,
+                           double* smem_raw, bf_c128* gslot, int use_lds) {
   const int M = d.M, N = d.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (M == 0 || N == 0) {
-    if (tid == 0) ranks[blockIdx.x] = 0;
+    if (tid == 0) *rank_out = 0;
     return;
   }
   // LDS layout: [norm2 N][vn2 N][tmp M (cd)][QRShared][A M*N (cd) if use_lds]
@@ -291,7 +309,7 @@ __global__ __launch_bounds__(NT) void cpqr_kernel(const QRDesc* __restrict__ des
   cd* tmp = reinterpret_cast<cd*>(vn2 + N);
   QRShared* sh = reinterpret_cast<QRShared*>(tmp + M);
   cd* A = use_lds ? reinterpret_cast<cd*>(reinterpret_cast<char*>(sh) + 64)
-                  : reinterpret_cast<cd*>(gscratch + (int64_t)blockIdx.x * scratch_slot);
+                  : reinterpret_cast<cd*>(gslot);
   const Tin* in = static_cast<const Tin*>(d.in);
   if (d.in_rs == 1) {        // column-major input: consecutive threads, consecutive rows
     for (int idx = tid; idx < M * N; idx += NT) {
@@ -410,7 +428,17 @@ __global__ __launch_bounds__(NT) void cpqr_kernel(const QRDesc* __restrict__ des
     cd a = A[idx];
     d.q[idx] = bf_c128{a.re, a.im};
   }
-  if (tid == 0) ranks[blockIdx.x] = rank;
+  if (tid == 0) *rank_out = rank;
+}
+
+template <typename Tin, int NT>
+__global__ __launch_bounds__(NT) void cpqr_kernel(const QRDesc* __restrict__ descs,
+                                                  double tol, int32_t* __restrict__ ranks,
+                                                  bf_c128* __restrict__ gscratch,
+                                                  int64_t scratch_slot, int use_lds) {
+  extern __shared__ double smem_raw[];
+  cpqr_block<Tin, NT>(descs[blockIdx.x], tol, ranks + blockIdx.x, smem_raw,
+                      gscratch + (int64_t)blockIdx.x * scratch_slot, use_lds);
 }
 
 static size_t cpqr_lds_bytes(int M, int N, bool with_block) {
@@ -429,13 +457,22 @@ void launch_cpqr(const QRDesc* d_dev, int32_t nblk, int32_t maxM, int32_t maxN, 
   ProfScope ps(BF_KC_CPQR, s, 0.0, 0.0);
   size_t lds = cpqr_lds_bytes(maxM, maxN, true);
   if (lds <= LDS_LIMIT) {
-    auto kern = in_c64 ? cpqr_kernel<bf_c64, QR_THREADS> : cpqr_kernel<bf_c128, QR_THREADS>;
-    if (lds > 64 * 1024)
-      BF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds));
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(QR_THREADS), lds, s, d_dev, tol,
-                       ranks_dev, (bf_c128*)nullptr, (int64_t)0, 1);
-    BF_HIP(hipGetLastError());
+    // 256 or 512 threads: each column's updates and sums stay with one wave
+    // either way, so both give the same bits
+    auto run = [&](int64_t nt) {
+      auto kern = nt == 512 ? (in_c64 ? cpqr_kernel<bf_c64, 512> : cpqr_kernel<bf_c128, 512>)
+                            : (in_c64 ? cpqr_kernel<bf_c64, QR_THREADS>
+                                      : cpqr_kernel<bf_c128, QR_THREADS>);
+      if (lds > 64 * 1024)
+        BF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+      hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3((unsigned)nt), lds, s, d_dev, tol,
+                         ranks_dev, (bf_c128*)nullptr, (int64_t)0, 1);
+      BF_HIP(hipGetLastError());
+    };
+    const TuneKey key{kTuneCpqrThreads, in_c64 ? 1 : 0, pow2_ceil(maxM), pow2_ceil(maxN),
+                      pow2_ceil(nblk), 0};
+    tune_choose(key, {QR_THREADS, 512}, QR_THREADS, s, run);
     return;
   }
   // Blocks too large for LDS live in a global scratch slot each (L2-resident
@@ -463,11 +500,7 @@ void launch_cpqr(const QRDesc* d_dev, int32_t nblk, int32_t maxM, int32_t maxN, 
 //   X^H = Q_x R_x (Householder, no pivoting), then R_x B^H = Q_x^H C^H.
 // Both X^H (s x kV) and C^H (s x kU) are held in LDS and reduced together.
 template <int NT>
-__global__ __launch_bounds__(NT) void lsq_kernel(const LSDesc* __restrict__ descs,
-                                                 bf_c128* __restrict__ gscratch,
-                                                 int64_t scratch_slot, int use_lds) {
-  extern __shared__ double smem_raw[];
-  const LSDesc d = descs[blockIdx.x];
+__device__ void lsq_block(const LSDesc& d, double* smem_raw, bf_c128* gslot, int use_lds) {
   const int S = d.s, KV = d.kV, KU = d.kU;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (KU == 0 || KV == 0) return;
@@ -476,7 +509,7 @@ __global__ __launch_bounds__(NT) void lsq_kernel(const LSDesc* __restrict__ desc
   double* vn2 = smem_raw;
   cd* diag = reinterpret_cast<cd*>(vn2 + KV);
   cd* XH = use_lds ? diag + KV                              // X^H, S x KV, ld S
-                   : reinterpret_cast<cd*>(gscratch + (int64_t)blockIdx.x * scratch_slot);
+                   : reinterpret_cast<cd*>(gslot);
   cd* CH = XH + (int64_t)S * KV;           // C^H, S x KU, ld S
   for (int idx = tid; idx < S * KV; idx += NT) {
     int i = idx % S, j = idx / S;          // XH[i, j] = conj(X[j, i])
@@ -538,6 +571,15 @@ __global__ __launch_bounds__(NT) void lsq_kernel(const LSDesc* __restrict__ desc
   }
 }
 
+template <int NT>
+__global__ __launch_bounds__(NT) void lsq_kernel(const LSDesc* __restrict__ descs,
+                                                 bf_c128* __restrict__ gscratch,
+                                                 int64_t scratch_slot, int use_lds) {
+  extern __shared__ double smem_raw[];
+  lsq_block<NT>(descs[blockIdx.x], smem_raw, gscratch + (int64_t)blockIdx.x * scratch_slot,
+                use_lds);
+}
+
 void launch_lsq(const LSDesc* d_dev, int32_t nblk, int32_t maxS, int32_t maxK, hipStream_t s) {
   if (nblk <= 0) return;
   BF_CHECK(maxK <= BF_MAX_BLOCK_COLS && maxS <= 2 * BF_MAX_BLOCK_COLS, BF_ERANK,
@@ -569,6 +611,55 @@ void launch_lsq(const LSDesc* d_dev, int32_t nblk, int32_t maxS, int32_t maxK, h
                        s, d_dev + b0, scratch.p, slot, 0);
     BF_HIP(hipGetLastError());
   }
+}
+
+// ------------------------------------------------ cross-request rounds ----
+// One persistent launch for the level solves of every construction in flight
+// (request engine): item i of the work list is block items[i].block of work
+// items[i].work, a work being one request's batch of truncated pivoted QRs
+// (Alg. 1 step 3 on a level's Z blocks) or centre-block least squares (eq.
+// Bij read from its argmin).  Items come sorted by estimated cost and
+// workgroup g takes items g, g + G, g + 2G, ... of the nitems[0] items.  Each
+// block runs the same code as cpqr_kernel / lsq_kernel on their LDS path, so
+// its result does not depend on the other requests of the round.
+__global__ __launch_bounds__(QR_THREADS) void solve_round_kernel(const SolveWork* __restrict__ works,
+                                                                 const SolveItem* __restrict__ items,
+                                                                 const int32_t* __restrict__ nitems) {
+  extern __shared__ double smem_raw[];
+  const int32_t n = *nitems;
+  for (int32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const SolveItem item = items[it];
+    const SolveWork w = works[item.work];
+    if (w.kind == kSolveQR) {
+      const QRDesc d = static_cast<const QRDesc*>(w.descs)[item.block];
+      if (w.in_c64)
+        cpqr_block<bf_c64, QR_THREADS>(d, w.tol, w.ranks + item.block, smem_raw, nullptr, 1);
+      else
+        cpqr_block<bf_c128, QR_THREADS>(d, w.tol, w.ranks + item.block, smem_raw, nullptr, 1);
+    } else {
+      const LSDesc d = static_cast<const LSDesc*>(w.descs)[item.block];
+      lsq_block<QR_THREADS>(d, smem_raw, nullptr, 1);
+    }
+    __syncthreads();   // the next item reuses the LDS
+  }
+}
+
+size_t solve_lds_qr(int32_t maxM, int32_t maxN) { return cpqr_lds_bytes(maxM, maxN, true); }
+size_t solve_lds_lsq(int32_t maxS, int32_t maxK) {
+  return (sizeof(double) + sizeof(cd)) * (size_t)maxK + sizeof(cd) * (size_t)maxS * (2 * maxK);
+}
+size_t solve_lds_limit() { return LDS_LIMIT; }
+
+void launch_solve_round(const SolveWork* works, const SolveItem* items, const int32_t* nitems,
+                        int32_t grid, size_t lds, hipStream_t s) {
+  if (lds > 64 * 1024)
+    BF_HIP(hipFuncSetAttribute((const void*)solve_round_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(solve_round_kernel, dim3((unsigned)grid), dim3(QR_THREADS), lds, s, works,
+                     items, nitems);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs == hipStreamCaptureStatusNone)
+    BF_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------- misc ----

@@ -599,31 +599,12 @@ static void launch_chunk_bf16(const E& e, int64_t nout, const uint16_t* Xp, int6
                       nsplit, inexact, s);
 }
 
-// ---- tile-width autotuner -------------------------------------------------
-// Off by default (bf_set_autotune).  When on, the first split-BF16 product of
-// each shape class (operator kind, column count, and the powers of two at or
-// above the output rows, input points and segment count) runs once with each
-// column-chunk bound in {48, 64, 80} -- the 48-, 64- and 80-column tiles --
-// timed with events on its stream, and the fastest bound is kept for the
-// class.  Every chunking gives bitwise the same products (a column's sums do
-// not depend on the other columns of its tile; split-K follows the row tiles
-// only), so the candidates' outputs are interchangeable and tuning changes
-// speed only.  The first product of a class synchronizes its stream once.
-static std::atomic<int> g_autotune{0};
-static std::mutex g_tune_mu;
-static std::map<std::array<int64_t, 5>, int64_t> g_tuned;
-
-void set_autotune(int on) { g_autotune.store(on ? 1 : 0); }
-int64_t autotune_entries() {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  return (int64_t)g_tuned.size();
-}
-
-static int64_t pow2_at_least(int64_t v) {
-  int64_t p = 1;
-  while (p < v) p <<= 1;
-  return p;
-}
+// Column tiles of a product: with more than 48 split-BF16 columns the 48-,
+// 64- and 80-column tiles are all usable and the autotuner picks per shape
+// class (operator kind, column count, and the powers of two at or above the
+// output rows, input points and segment count).  Every chunking gives bitwise
+// the same products: a column's sums do not depend on the other columns of
+// its tile, and split-K follows the row tiles only.
 
 template <class E>
 static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const bf_c64* X,
@@ -719,42 +700,13 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
       }
     }
   };
-  int64_t maxw = bf16 ? 80 : 48;
-  hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
-  if (bf16 && ncols > 48 && g_autotune.load() && hipStreamIsCapturing(s, &cst) == hipSuccess &&
-      cst == hipStreamCaptureStatusNone) {
-    const std::array<int64_t, 5> key{E::kKind, ncols, pow2_at_least(nout),
-                                     pow2_at_least(g_matfree_nin), pow2_at_least(nseg)};
-    bool known = false;
-    {
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      auto it = g_tuned.find(key);
-      if (it != g_tuned.end()) { known = true; maxw = it->second; }
-    }
-    if (!known) {
-      const int64_t cand[3] = {48, 64, 80};
-      hipEvent_t ev[4];
-      for (auto& x : ev) BF_HIP(hipEventCreate(&x));
-      BF_HIP(hipEventRecord(ev[0], s));
-      for (int i = 0; i < 3; ++i) {
-        run_chunks(cand[i]);
-        BF_HIP(hipEventRecord(ev[i + 1], s));
-      }
-      BF_HIP(hipEventSynchronize(ev[3]));
-      float best_ms = 0.f;
-      int64_t best = cand[2];
-      for (int i = 0; i < 3; ++i) {
-        float ms = 0.f;
-        BF_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
-        if (i == 0 || ms < best_ms) { best_ms = ms; best = cand[i]; }
-      }
-      for (auto& x : ev) (void)hipEventDestroy(x);
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tuned[key] = best;
-      maxw = 0;   // the product is already computed (by every candidate alike)
-    }
+  if (bf16 && ncols > 48) {
+    const TuneKey key{kTuneMatfreeWidth, E::kKind, ncols, pow2_ceil(nout),
+                      pow2_ceil(g_matfree_nin), pow2_ceil(nseg)};
+    tune_choose(key, {48, 64, 80}, 80, s, [&](int64_t w) { run_chunks(w); });
+  } else {
+    run_chunks(bf16 ? 80 : 48);
   }
-  if (maxw > 0) run_chunks(maxw);
   if (nsplit > 1) {
     int64_t tot = nout * ycols;
     ProfScope ps(BF_KC_OTHER, s, 0.0, 16.0 * nsplit * tot + 8.0 * tot);

@@ -1,6 +1,6 @@
-// Allocation-free apply (bf_apply_noalloc): the same stage kernels as bf_apply
-// (eq. hybrid_butterfly_mat), with the two ping-pong intermediates placed in a
-// fixed device array instead of memory from the stream-ordered pool, for
+// Allocation-free apply (bf_apply_noalloc): the same kernels as bf_apply
+// (eq. hybrid_butterfly_mat), with the intermediates placed in a fixed device
+// array instead of memory from the stream-ordered pool, for
 // callers that cannot allocate (code under HIP graph capture, tight serving
 // loops).
 //
@@ -50,21 +50,16 @@ void apply_noalloc(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
   BF_HIP(hipGetDevice(&dev));
   BF_CHECK(dev == F->device, BF_EINVAL,
            "bf_apply_noalloc: the factors live on another device than the current one");
-  const ApplyPlan& P = trans ? F->adj : F->fwd;
-  // two intermediates of tmp_rows x ncols complex64 values, the second at a
-  // 256-byte boundary
-  const size_t one = (size_t)P.tmp_rows * (size_t)ncols * sizeof(bf_c64);
-  const size_t off = (one + 255) & ~size_t(255);
-  BF_CHECK(ncols <= (int64_t)(kScratchBytes / sizeof(bf_c64)) && off + one <= kScratchBytes,
+  // the fused schedule's intermediates when they fit, else the two ping-pong
+  // buffers of the stage-by-stage apply (the second at a 256-byte boundary)
+  const size_t staged = apply_scratch_bytes(F, trans, ncols, true);
+  BF_CHECK(ncols <= (int64_t)(kScratchBytes / sizeof(bf_c64)) && staged <= kScratchBytes,
            BF_EINVAL,
-           "bf_apply_noalloc: " + std::to_string(P.tmp_rows) + " intermediate rows x " +
-               std::to_string(ncols) + " columns need 2 x " + std::to_string(one) +
-               " bytes of scratch, more than the " + std::to_string(kScratchBytes) +
-               " bytes available");
+           "bf_apply_noalloc: " + std::to_string(ncols) + " columns need " +
+               std::to_string(staged) + " bytes of scratch, more than the " +
+               std::to_string(kScratchBytes) + " bytes available");
   if (ncols == 0) return;
-  char* base = static_cast<char*>(scratch_address(dev));
-  run_apply_stages(F, trans, X, ldx, ncols, Y, ldy, reinterpret_cast<bf_c64*>(base),
-                   reinterpret_cast<bf_c64*>(base + off), s, false);
+  run_apply(F, trans, X, ldx, ncols, Y, ldy, scratch_address(dev), kScratchBytes, s, false);
 }
 
 }  // namespace bf

@@ -10,6 +10,7 @@
 // contiguously in stage order, so a stage streams its factor bytes once.
 #include <algorithm>
 #include <mutex>
+#include <unordered_map>
 
 #include "factors.h"
 
@@ -103,6 +104,157 @@ struct PlanBuilder {
   }
 };
 
+// Workgroups a fused launch should keep: below this many groups a stage is
+// not added to the launch unless its groups are small (kFusedSmallRows rows
+// over the whole launch), which keeps small factorizations to few launches.
+constexpr int64_t kFusedMinGroups = 256;
+constexpr int64_t kFusedSmallRows = 512;
+
+struct UnionFind {
+  std::vector<int32_t> p;
+  explicit UnionFind(size_t n) : p(n) {
+    for (size_t i = 0; i < n; ++i) p[i] = (int32_t)i;
+  }
+  int32_t find(int32_t x) {
+    while (p[x] != x) x = p[x] = p[p[x]];
+    return x;
+  }
+  bool unite(int32_t a, int32_t b) {
+    a = find(a);
+    b = find(b);
+    if (a == b) return false;
+    if (a < b) std::swap(a, b);
+    p[a] = b;
+    return true;
+  }
+};
+
+// The fused schedule of a plan: every stage t but the last writes rows
+// [base_t, base_t + rows_t) of one tall intermediate (buffer 1), every stage
+// after the first reads the previous stage's rows there; consecutive stages
+// are grouped into launches, each launch's blocks split into independent
+// groups (one workgroup each), and the groups' blocks re-indexed as row
+// records ordered by launch, group and stage.
+void build_fused(const PlanBuilder& pb, ApplyPlan& plan, Staging& st, hipStream_t s) {
+  const auto& stg = pb.stages;
+  const int ns = (int)stg.size();
+  if (ns == 0) return;
+  std::vector<int64_t> base(ns, 0);
+  int64_t tot = 0;
+  for (int t = 0; t + 1 < ns; ++t) {
+    base[t] = tot;
+    tot += stg[t].nrows;
+  }
+  const size_t nb = pb.blks.size();
+  // producers: for each block of stage t > 0, the blocks of stage t - 1 whose
+  // output rows its two input ranges read (stage blocks are sorted by row);
+  // block b's are prod[poff[b] .. poff[b + 1])
+  std::vector<int64_t> poff(nb + 1, 0);
+  std::vector<int32_t> prod;
+  prod.reserve(2 * nb);
+  for (int t = 1; t < ns; ++t) {
+    const int64_t p0 = stg[t - 1].blk_off, pn = stg[t - 1].nblk;
+    std::vector<int64_t> starts((size_t)pn);
+    for (int64_t k = 0; k < pn; ++k) starts[(size_t)k] = pb.blks[(size_t)(p0 + k)].out_row;
+    for (int64_t b = stg[t].blk_off; b < stg[t].blk_off + stg[t].nblk; ++b) {
+      const ApplyBlk& bk = pb.blks[(size_t)b];
+      const int64_t rr[2][2] = {{bk.in_row0, bk.K0}, {bk.in_row1, bk.K1}};
+      for (auto& r : rr) {
+        if (r[1] <= 0) continue;
+        auto it = std::upper_bound(starts.begin(), starts.end(), r[0]);
+        int64_t k = (int64_t)(it - starts.begin()) - 1;
+        for (; k >= 0 && k < pn && starts[(size_t)k] < r[0] + r[1]; ++k) {
+          const ApplyBlk& pk = pb.blks[(size_t)(p0 + k)];
+          if (pk.out_row + pk.M > r[0]) prod.push_back((int32_t)(p0 + k));
+        }
+      }
+      poff[(size_t)b + 1] = (int64_t)prod.size();
+    }
+  }
+  std::vector<ApplyBlk> fb;
+  std::vector<int32_t> off;
+  fb.reserve(nb);
+  int64_t rec = 0;
+  UnionFind uf(nb);
+  int a = 0;
+  while (a < ns) {
+    // grow the launch [a, e) while it keeps enough groups (or stays small)
+    int64_t groups = stg[a].nblk;
+    int e = a + 1;
+    while (e < ns) {
+      UnionFind trial = uf;
+      int64_t g = groups + stg[e].nblk;
+      for (int64_t b = stg[e].blk_off; b < stg[e].blk_off + stg[e].nblk; ++b)
+        for (int64_t k = poff[(size_t)b]; k < poff[(size_t)b + 1]; ++k)
+          if (trial.unite((int32_t)b, prod[(size_t)k])) --g;
+      int64_t rows_max = 0;
+      if (g < kFusedMinGroups) {
+        std::unordered_map<int32_t, int64_t> rows;
+        for (int t = a; t <= e; ++t)
+          for (int64_t b = stg[t].blk_off; b < stg[t].blk_off + stg[t].nblk; ++b)
+            rows_max = std::max(rows_max, rows[trial.find((int32_t)b)] += pb.blks[(size_t)b].M);
+      }
+      if (g < kFusedMinGroups && rows_max > kFusedSmallRows) break;
+      uf = std::move(trial);
+      groups = g;
+      ++e;
+    }
+    // groups in order of their first block; records by group, then stage
+    std::unordered_map<int32_t, int32_t> gid;
+    std::vector<std::vector<std::vector<int32_t>>> members;
+    for (int t = a; t < e; ++t)
+      for (int64_t b = stg[t].blk_off; b < stg[t].blk_off + stg[t].nblk; ++b) {
+        const int32_t r = uf.find((int32_t)b);
+        auto it = gid.find(r);
+        if (it == gid.end()) {
+          it = gid.emplace(r, (int32_t)members.size()).first;
+          members.emplace_back(e - a);
+        }
+        members[(size_t)it->second][(size_t)(t - a)].push_back((int32_t)b);
+      }
+    FusedSeg seg;
+    seg.off_off = (int64_t)off.size();
+    seg.nwg = (int32_t)members.size();
+    seg.nstage = e - a;
+    seg.first_stage = a;
+    for (int t = a; t < e; ++t) seg.macs += stg[t].macs;
+    for (auto& grp : members) {
+      for (int t = a; t < e; ++t) {
+        off.push_back((int32_t)rec);
+        int64_t rows_gs = 0;
+        for (int32_t b : grp[(size_t)(t - a)]) rows_gs += pb.blks[(size_t)b].M;
+        seg.max_rows = (int32_t)std::max<int64_t>(seg.max_rows, rows_gs);
+        for (int32_t b : grp[(size_t)(t - a)]) {
+          ApplyBlk bk = pb.blks[(size_t)b];
+          if (t + 1 < ns) {
+            bk.out_buf = 1;
+            bk.out_row += base[t];
+          }
+          if (t > 0) {
+            bk.in_buf0 = 1;
+            bk.in_buf1 = 1;
+            bk.in_row0 += base[t - 1];
+            bk.in_row1 += base[t - 1];
+          }
+          bk.row_rec = rec;
+          rec += bk.M;
+          fb.push_back(bk);
+        }
+      }
+      off.push_back((int32_t)rec);
+    }
+    BF_CHECK(rec < INT32_MAX, BF_EINVAL, "fused apply: too many row records");
+    plan.segs.push_back(seg);
+    a = e;
+  }
+  plan.fused_rows = std::max<int64_t>(tot, 1);
+  auto fbd = upload(fb, s, st);
+  plan.foff = upload(off, s, st);
+  plan.frows = DevBuf<ApplyRowRec>((size_t)std::max<int64_t>(rec, 1), s);
+  launch_expand_rows(fbd.p, (int32_t)fb.size(), plan.frows.p, s);
+  BF_HIP(hipStreamSynchronize(s));   // fbd is released at return
+}
+
 void finish(PlanBuilder& pb, ApplyPlan& plan, int64_t tmp_rows, hipStream_t s,
             int64_t rows_in, int64_t rows_out) {
   if (validating()) {
@@ -139,6 +291,7 @@ void finish(PlanBuilder& pb, ApplyPlan& plan, int64_t tmp_rows, hipStream_t s,
     ProfScope ps(BF_KC_OTHER, s, 0.0, 0.0);
     launch_pack_c64(dd.p, (int32_t)cnt, plan.G.p, s);
   }
+  build_fused(pb, plan, st, s);
   BF_HIP(hipStreamSynchronize(s));
   st.reset();
 }
@@ -279,7 +432,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
 
 // The L+3 stage launches of one apply on stream s (buffers: X, two
 // intermediates, Y).
-void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+static void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
                       int64_t ncols, bf_c64* Y, int64_t ldy, bf_c64* t1, bf_c64* t2,
                       hipStream_t s, bool prof) {
   const ApplyPlan& P = trans ? F->adj : F->fwd;
@@ -311,6 +464,79 @@ void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t l
   }
 }
 
+// The fused launches of one apply (ncols <= kApplyFusedCols): intermediates
+// in one column-major tall buffer T of plan.fused_rows rows.
+static void run_fused(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                      int64_t ncols, bf_c64* Y, int64_t ldy, bf_c64* T, hipStream_t s,
+                      bool prof) {
+  const ApplyPlan& P = trans ? F->adj : F->fwd;
+  const bf_c64* bufs[4] = {X, T, T, Y};
+  const int64_t lds[4] = {ldx, P.fused_rows, P.fused_rows, ldy};
+  const int64_t rin = trans ? F->m : F->n, rout = trans ? F->n : F->m;
+  for (size_t k = 0; k < P.segs.size(); ++k) {
+    const FusedSeg& sg = P.segs[k];
+    double by = 8.0 * sg.macs;
+    if (k == 0) by += 8.0 * (double)rin * ncols;
+    if (k + 1 == P.segs.size()) by += 8.0 * (double)rout * ncols;
+    // 8 threads per row: enough for the launch's largest group-stage in one
+    // pass, within 256..1024
+    int32_t threads = 256;
+    while (threads < 1024 && threads < 8 * sg.max_rows) threads *= 2;
+    auto launch = [&] {
+      launch_apply_fused(P.frows.p, P.foff.p + sg.off_off, sg.nwg, sg.nstage, threads, P.G.p,
+                         bufs, lds, ncols, F->apply_prec, s);
+    };
+    if (prof) {
+      ProfScope ps(BF_KC_APPLY, s, 8.0 * sg.macs * ncols, by);
+      launch();
+    } else {
+      launch();
+    }
+  }
+}
+
+static bool fused_ok(const bf_factors* F, int trans, int64_t ncols) {
+  const ApplyPlan& P = trans ? F->adj : F->fwd;
+  return F->apply_fuse && ncols > 0 && ncols <= kApplyFusedCols && !P.segs.empty();
+}
+
+size_t apply_scratch_bytes(const bf_factors* F, int trans, int64_t ncols, bool staged) {
+  const ApplyPlan& P = trans ? F->adj : F->fwd;
+  if (!staged && fused_ok(F, trans, ncols))
+    return (size_t)P.fused_rows * (size_t)ncols * sizeof(bf_c64);
+  const size_t one = (size_t)P.tmp_rows * (size_t)std::max<int64_t>(ncols, 0) * sizeof(bf_c64);
+  return ((one + 255) & ~size_t(255)) + one;
+}
+
+void run_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
+               bf_c64* Y, int64_t ldy, void* scratch, size_t scratch_bytes, hipStream_t s,
+               bool prof) {
+  if (ncols <= 0) return;
+  char* base = static_cast<char*>(scratch);
+  const ApplyPlan& P = trans ? F->adj : F->fwd;
+  const size_t one = (size_t)P.tmp_rows * (size_t)ncols * sizeof(bf_c64);
+  const bool fused = fused_ok(F, trans, ncols) &&
+                     scratch_bytes >= apply_scratch_bytes(F, trans, ncols);
+  const bool staged = scratch_bytes >= apply_scratch_bytes(F, trans, ncols, true);
+  BF_CHECK(fused || staged, BF_EINVAL, "apply: scratch too small for the intermediates");
+  auto run = [&](int64_t f) {
+    if (f)
+      run_fused(F, trans, X, ldx, ncols, Y, ldy, reinterpret_cast<bf_c64*>(base), s, prof);
+    else
+      run_apply_stages(F, trans, X, ldx, ncols, Y, ldy, reinterpret_cast<bf_c64*>(base),
+                       reinterpret_cast<bf_c64*>(base + ((one + 255) & ~size_t(255))), s, prof);
+  };
+  if (fused && staged && ncols <= kApplyFewCols) {
+    // up to 4 columns both run the same row kernel (same bits): the autotuner
+    // picks per shape class; fused is the rule without it
+    const TuneKey key{kTuneApplyFused, trans, ncols, pow2_ceil(F->m), pow2_ceil(F->n),
+                      F->L * 64 + F->apply_prec};
+    tune_choose(key, {1, 0}, 1, s, run, prof);
+    return;
+  }
+  run(fused ? 1 : 0);
+}
+
 // ---- applies as captured HIP graphs (bf_set_apply_graph_cols) --------------
 // One graph per (direction, column count, precision, stream): the stage
 // launches read a private input buffer and write a private output buffer, and
@@ -321,7 +547,9 @@ struct ApplyGraph {
   int trans = 0, prec = 0;
   int64_t ncols = 0;
   hipStream_t s = nullptr;
-  bf_c64 *Xs = nullptr, *Ys = nullptr, *t1 = nullptr, *t2 = nullptr;
+  bf_c64 *Xs = nullptr, *Ys = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
   hipGraphExec_t exec = nullptr;
 };
 struct ApplyGraphCache {
@@ -333,7 +561,7 @@ constexpr size_t kMaxApplyGraphs = 16;
 
 static void release_graph(ApplyGraph& a) {
   if (a.exec) (void)hipGraphExecDestroy(a.exec);
-  for (bf_c64* p : {a.Xs, a.Ys, a.t1, a.t2})
+  for (void* p : {(void*)a.Xs, (void*)a.Ys, a.tmp})
     if (p) (void)hipFree(p);
   a = ApplyGraph{};
 }
@@ -358,10 +586,10 @@ void free_apply_graphs(ApplyGraphCache* c) {
 static bool capture_graph(const bf_factors* F, ApplyGraphCache* c, ApplyGraph& a) {
   const ApplyPlan& P = a.trans ? F->adj : F->fwd;
   const int64_t rin = a.trans ? F->m : F->n, rout = a.trans ? F->n : F->m;
-  const size_t tsz = (size_t)std::max<int64_t>(P.tmp_rows * a.ncols, 1) * sizeof(bf_c64);
+  a.tmp_bytes = std::max<size_t>(apply_scratch_bytes(F, a.trans, a.ncols), 256);
   if (hipMalloc((void**)&a.Xs, (size_t)(rin * a.ncols) * sizeof(bf_c64)) != hipSuccess ||
       hipMalloc((void**)&a.Ys, (size_t)(rout * a.ncols) * sizeof(bf_c64)) != hipSuccess ||
-      hipMalloc((void**)&a.t1, tsz) != hipSuccess || hipMalloc((void**)&a.t2, tsz) != hipSuccess) {
+      hipMalloc(&a.tmp, a.tmp_bytes) != hipSuccess) {
     release_graph(a);
     return false;
   }
@@ -379,7 +607,7 @@ static bool capture_graph(const bf_factors* F, ApplyGraphCache* c, ApplyGraph& a
   }
   bool ok = true;
   try {
-    run_apply_stages(F, a.trans, a.Xs, rin, a.ncols, a.Ys, rout, a.t1, a.t2, c->cap, true);
+    run_apply(F, a.trans, a.Xs, rin, a.ncols, a.Ys, rout, a.tmp, a.tmp_bytes, c->cap, true);
   } catch (...) {
     ok = false;
   }
@@ -442,9 +670,9 @@ void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
   if (ncols <= 0) return;
   if (F->graph_cols > 0 && ncols <= F->graph_cols && apply_graph(F, trans, X, ldx, ncols, Y, ldy, s))
     return;
-  const ApplyPlan& P = trans ? F->adj : F->fwd;
-  DevBuf<bf_c64> t1((size_t)P.tmp_rows * ncols, s), t2((size_t)P.tmp_rows * ncols, s);
-  run_apply_stages(F, trans, X, ldx, ncols, Y, ldy, t1.p, t2.p, s, true);
+  const size_t need = apply_scratch_bytes(F, trans, ncols);
+  DevBuf<char> tmp(need, s);
+  run_apply(F, trans, X, ldx, ncols, Y, ldy, tmp.p, need, s, true);
 }
 
 }  // namespace bf

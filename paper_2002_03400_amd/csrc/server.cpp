@@ -88,6 +88,9 @@ struct bf_server {
   std::vector<hipStream_t> streams;
   int64_t budget = 0, reserved = 0, next_id = 1;
   int64_t batch_cols = 0;
+  bf_alloc alloc{};          // the caller's allocator (bf_server_opts.alloc), if any
+  bool has_alloc = false;
+  SolveRounds* rounds = nullptr;   // cross-request solve rounds (bf_server_opts.solve_rounds)
   int device = 0;
   bool stopping = false;
   Clock::time_point t0 = Clock::now();
@@ -138,10 +141,11 @@ struct bf_server {
 
   // The applies of a batch as one product: columns gathered into one block,
   // one bf_apply, results scattered back.
-  static int apply_batch(const bf_factors* T, const std::vector<Request*>& b, hipStream_t s) {
+  int apply_batch(const bf_factors* T, const std::vector<Request*>& b, hipStream_t s) {
+    const bf_alloc* al = has_alloc ? &alloc : nullptr;
     if (b.size() == 1) {
       const Request* r = b[0];
-      int rc = bf_apply(T, r->trans, r->X, r->ldx, r->ncols, r->Y, r->ldy, (void*)s);
+      int rc = bf_apply(T, r->trans, r->X, r->ldx, r->ncols, r->Y, r->ldy, al, (void*)s);
       if (rc == BF_OK && hipStreamSynchronize(s) != hipSuccess) rc = BF_EHIP;
       return rc;
     }
@@ -151,16 +155,19 @@ struct bf_server {
     const int64_t rin = trans ? I.m : I.n, rout = trans ? I.n : I.m;
     int64_t cols = 0;
     for (auto* r : b) cols += r->ncols;
-    bf_c64 *Xb = nullptr, *Yb = nullptr;
-    if (hipMallocAsync((void**)&Xb, (size_t)std::max<int64_t>(1, rin * cols) * sizeof(bf_c64), s) !=
-            hipSuccess ||
-        hipMallocAsync((void**)&Yb, (size_t)std::max<int64_t>(1, rout * cols) * sizeof(bf_c64), s) !=
-            hipSuccess) {
-      if (Xb) (void)hipFreeAsync(Xb, s);
+    // gathered columns: from the caller's allocator if one was given, else the pool
+    UseAllocator ua(al);
+    DevBuf<bf_c64> xb, yb;
+    try {
+      xb = DevBuf<bf_c64>((size_t)std::max<int64_t>(1, rin * cols), s);
+      yb = DevBuf<bf_c64>((size_t)std::max<int64_t>(1, rout * cols), s);
+    } catch (const Error&) {
+      xb.reset();
       (void)hipStreamSynchronize(s);
       set_last_error("apply batch: device allocation failed");
       return BF_ENOMEM;
     }
+    bf_c64 *Xb = xb.p, *Yb = yb.p;
     int rc = BF_OK;
     int64_t off = 0;
     for (auto* r : b) {
@@ -170,7 +177,7 @@ struct bf_server {
         rc = BF_EHIP;
       off += r->ncols;
     }
-    if (rc == BF_OK) rc = bf_apply(T, trans, Xb, rin, cols, Yb, rout, (void*)s);
+    if (rc == BF_OK) rc = bf_apply(T, trans, Xb, rin, cols, Yb, rout, al, (void*)s);
     off = 0;
     for (auto* r : b) {
       if (rc == BF_OK && r->ncols > 0 &&
@@ -179,8 +186,8 @@ struct bf_server {
         rc = BF_EHIP;
       off += r->ncols;
     }
-    (void)hipFreeAsync(Xb, s);
-    (void)hipFreeAsync(Yb, s);
+    xb.reset();
+    yb.reset();
     if (hipStreamSynchronize(s) != hipSuccess && rc == BF_OK) rc = BF_EHIP;
     if (rc == BF_EHIP) set_last_error("apply batch: HIP copy or synchronization failed");
     return rc;
@@ -209,8 +216,10 @@ struct bf_server {
       std::string err;
       bf_factors* F = nullptr;
       if (r->kind == 0) {
+        RoundsScope rs(rounds);
         rc = bf_construct(r->op.matvec, r->op.rmatvec, r->op.user, r->op.m, r->op.n, r->tol,
-                          r->leaf, r->has_opts ? &r->opts : nullptr, (void*)s, &F);
+                          r->leaf, r->has_opts ? &r->opts : nullptr,
+                          has_alloc ? &alloc : nullptr, (void*)s, &F);
       } else {
         const bf_factors* T = nullptr;
         {
@@ -253,14 +262,32 @@ int bf_server_create(const bf_server_opts* o, bf_server** out) {
   if (!S) return BF_ENOMEM;
   S->budget = o && o->hbm_budget > 0 ? o->hbm_budget : (int64_t(64) << 30);
   S->batch_cols = o && o->batch_cols > 0 ? o->batch_cols : 0;
+  if (o && o->alloc) {
+    if (!o->alloc->alloc || !o->alloc->free) {
+      delete S;
+      return BF_EINVAL;
+    }
+    S->alloc = *o->alloc;
+    S->has_alloc = true;
+  }
   if (hipGetDevice(&S->device) != hipSuccess) {
     delete S;
     return BF_ENOTSUP;
+  }
+  if (o && o->solve_rounds) {
+    try {
+      S->rounds = new_solve_rounds(S->device);
+    } catch (const std::exception& e) {
+      set_last_error(std::string("bf_server_create: solve rounds: ") + e.what());
+      delete S;
+      return BF_EHIP;
+    }
   }
   for (int k = 0; k < slots; ++k) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
       for (auto x : S->streams) (void)hipStreamDestroy(x);
+      delete_solve_rounds(S->rounds);
       delete S;
       return BF_EHIP;
     }
@@ -292,7 +319,14 @@ int bf_server_destroy(bf_server* S) {
     delete kv.second;
   }
   for (auto st : S->streams) (void)hipStreamDestroy(st);
+  delete_solve_rounds(S->rounds);
   delete S;
+  return BF_OK;
+}
+
+int bf_server_rounds(bf_server* S, int64_t* rounds, int64_t* items) {
+  if (!S || !rounds || !items) return BF_EINVAL;
+  solve_rounds_stats(S->rounds, rounds, items);
   return BF_OK;
 }
 

@@ -36,8 +36,9 @@ def test_argument_errors_without_device():
     h = C.c_void_p()
     o = bf.bf_opts(2, 4, 0, 0, 0)
     # NULL callbacks, m <= 0, tol outside (0,1), leaf < 1
-    assert lib.bf_construct(None, None, None, 10, 10, 1e-6, 4, C.byref(o), None, C.byref(h)) == -1
-    assert lib.bf_apply(None, 0, None, 1, 1, None, 1, None) == -1
+    assert lib.bf_construct(None, None, None, 10, 10, 1e-6, 4, C.byref(o), None, None,
+                            C.byref(h)) == -1
+    assert lib.bf_apply(None, 0, None, 1, 1, None, 1, None, None) == -1
     assert lib.bf_stats(None, None) == -1
     assert lib.bf_free(None, None) == -1
     assert lib.bf_strerror(-4) == b"rank cap exceeded or block too large"
@@ -48,7 +49,8 @@ def test_argument_errors_without_device():
     assert lib.bf_autotune_entries(None) == -1
     n = C.c_int64(-1)
     assert lib.bf_set_autotune(0) == 0
-    assert lib.bf_autotune_entries(C.byref(n)) == 0 and n.value == 0
+    assert lib.bf_autotune_entries(C.byref(n)) == 0 and n.value >= 0
+    assert lib.bf_set_autotune(1) == 0
 
 
 def test_precision_enum_matches_header():
@@ -74,7 +76,7 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("no C compiler")
     structs = {"bf_opts": bf.bf_opts, "bf_info": bf.bf_info, "bf_operator": bf.bf_operator,
                "bf_kernel_stats": bf.bf_kernel_stats, "bf_server_opts": bf.bf_server_opts,
-               "bf_request_info": bf.bf_request_info}
+               "bf_request_info": bf.bf_request_info, "bf_alloc": bf.bf_alloc}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bf.h"', "int main(void) {"]
     for name, py in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
@@ -92,3 +94,45 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(name, "size")] == C.sizeof(py), name
         for fname, _ in py._fields_:
             assert got[(name, fname)] == getattr(py, fname).offset, (name, fname)
+
+
+def test_allocator_without_functions_is_rejected():
+    """A bf_alloc must carry both functions; the check comes before any device
+    work (also for the request engine, whose options copy the allocator)."""
+    if not os.path.exists(bf.LIB_PATH):
+        pytest.skip("libbf.so not built")
+    lib = bf.lib()
+    half = bf.bf_alloc(None, bf.ALLOCFN(lambda c, n, s: None), bf.FREEFN())
+    h = C.c_void_p()
+    o = bf.bf_opts(2, 4, 0, 0, 0)
+    cb = bf.OPFN(lambda *a: 0)
+    assert lib.bf_construct(cb, cb, None, 10, 10, 1e-6, 4, C.byref(o), C.byref(half), None,
+                            C.byref(h)) == -1
+    assert not h.value
+    so = bf.bf_server_opts(1, 0, 0, C.pointer(half))
+    assert lib.bf_server_create(C.byref(so), C.byref(h)) == -1
+
+
+def test_autotuner_table_round_trip(tmp_path):
+    """The tuner's table is written and read back as text (one class per line:
+    family, five class fields, choice) without a device; unknown families are
+    ignored and a missing file is an error."""
+    if not os.path.exists(bf.LIB_PATH):
+        pytest.skip("libbf.so not built")
+    lib = bf.lib()
+    src = tmp_path / "in.tsv"
+    src.write_text("# family  class fields (5)  choice\n"
+                   "chain_rows 1 19 1024 64 0 20\n"
+                   "cpqr_threads 0 64 64 1024 0 512\n"
+                   "no_such_family 1 2 3 4 5 6\n")
+    assert lib.bf_autotune_clear() == 0
+    assert lib.bf_autotune_load(str(src).encode()) == 0
+    n = C.c_int64(-1)
+    assert lib.bf_autotune_entries(C.byref(n)) == 0 and n.value == 2
+    out = tmp_path / "out.tsv"
+    assert lib.bf_autotune_save(str(out).encode()) == 0
+    lines = [l.split() for l in out.read_text().splitlines() if l and not l.startswith("#")]
+    assert sorted(lines) == sorted([["chain_rows", "1", "19", "1024", "64", "0", "20"],
+                                    ["cpqr_threads", "0", "64", "64", "1024", "0", "512"]])
+    assert lib.bf_autotune_load(str(tmp_path / "missing.tsv").encode()) == -1
+    assert lib.bf_autotune_clear() == 0

@@ -25,5 +25,6 @@ def test_help_lists_every_mode():
     assert r.returncode == 0
     for flag in ("--steps", "--warmup", "--exact-scaling", "--em3d", "--variants",
                  "--precision-form", "--apply-burst", "--mix", "--batch-cols",
-                 "--copy-calibration", "--no-cpu-baseline"):
+                 "--copy-calibration", "--no-cpu-baseline", "--compose",
+                 "--solve-rounds"):
         assert flag in r.stdout, flag

@@ -330,5 +330,5 @@ def test_unknown_option_flags_rejected(bf):
     o = bf.bf_opts(2, 4, 0, 8, 0, 0)
     h = C.c_void_p()
     rc = bf.lib().bf_construct(op._op.matvec, op._op.rmatvec, op._op.user, op.m, op.n, 1e-6, 32,
-                               C.byref(o), None, C.byref(h))
+                               C.byref(o), None, None, C.byref(h))
     assert rc == -1 and not h.value

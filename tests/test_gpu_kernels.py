@@ -16,6 +16,13 @@ from tests.bfconv import bf16_exact, oracle_to_canonical
 pytestmark = pytest.mark.gpu
 
 
+def _same_bits(a, b):
+    """Bitwise equality of two complex64 device tensors (any strides)."""
+    x = np.ascontiguousarray(a.cpu().numpy()).view(np.uint32)
+    y = np.ascontiguousarray(b.cpu().numpy()).view(np.uint32)
+    return x.shape == y.shape and np.array_equal(x, y)
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
@@ -160,23 +167,25 @@ def test_segkernel_wide_and_split(bf):
 
 
 def test_autotuned_tile_widths_do_not_change_products(bf):
-    """The opt-in tile-width autotuner times candidate column chunkings on the
-    first product of a shape class and reuses the fastest; every candidate
-    gives bitwise the same product, so tuned, cached and untuned products agree
-    exactly, and so do constructions."""
+    """The autotuner times candidate column chunkings on the first product of a
+    shape class and reuses the fastest; every candidate gives bitwise the same
+    product, so tuned, cached and untuned products agree exactly, and so do
+    constructions."""
     n = 6000
     g = wl.segment_pair(n, ppw=8.0, m=3000)
     op = bf.segkernel(g.targets, g.sources, g.k)
     say("autotune")
     X = _cg(np.random.default_rng(9), n, 70)
     Xb = bf16_exact(X)
-    ref = op.matvec(_t(Xb)).cpu().numpy()
-    ref_g = op.matvec(_t(X)).cpu().numpy()
     gg = wl.segment_pair(2048, ppw=8.0)
     opc = bf.segkernel(gg.targets, gg.sources, gg.k)
-    fa = bf.construct(opc, 1e-6, 32, seed=21).export()
-    bf.set_autotune(True)
+    bf.set_autotune(False)
     try:
+        ref = op.matvec(_t(Xb)).cpu().numpy()
+        ref_g = op.matvec(_t(X)).cpu().numpy()
+        fa = bf.construct(opc, 1e-6, 32, seed=21).export()
+        bf.autotune_clear()
+        bf.set_autotune(True)
         n0 = bf.autotune_entries()
         tuned = op.matvec(_t(Xb)).cpu().numpy()
         n1 = bf.autotune_entries()
@@ -185,11 +194,88 @@ def test_autotuned_tile_widths_do_not_change_products(bf):
         fb = bf.construct(opc, 1e-6, 32, seed=21).export()
         fc = bf.construct(opc, 1e-6, 32, seed=21).export()
     finally:
-        bf.set_autotune(False)
+        bf.set_autotune(True)
     assert n1 == n0 + 1
     assert np.array_equal(tuned, ref) and np.array_equal(cached, ref)
     assert np.array_equal(tuned_g, ref_g)
     assert np.array_equal(fa, fb) and np.array_equal(fa, fc)
+
+
+# candidates of each tuned family (include/bf.h, bf_set_autotune)
+TUNE_CANDIDATES = {"matfree_width": [48, 64, 80], "chain_rows": [8, 16, 20, 24, 32, 64],
+                   "cpqr_threads": [256, 512], "apply_fused": [1, 0]}
+
+
+def _tune_rows(path):
+    rows = []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        rows.append((f[0], [int(x) for x in f[1:-1]], int(f[-1])))
+    return rows
+
+
+def _valid(fam, fields, c):
+    if fam == "chain_rows":      # tile heights at least the launch's largest block
+        m = fields[1]
+        return c >= m if m <= 64 else c in (32, 64)
+    return True
+
+
+def test_every_autotuner_candidate_gives_the_same_bits(bf, tmp_path):
+    """Every family the tuner covers -- black-box column tile, chain tile
+    height, CPQR workgroup, fused or staged few-column apply -- and every one
+    of its candidates gives the bits of the untuned rule: the table is saved,
+    rewritten with each candidate in turn for every class, loaded, and the
+    construction and applies repeated against the untuned reference."""
+    import torch
+    g = wl.segment_pair(4096, ppw=8.0)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    X = _t(_cg(np.random.default_rng(3), 4096, 3))
+
+    def run():
+        F = bf.construct(op, 1e-6, 64, seed=31)
+        out = [F.export()]
+        for c in (1, 2, 3):
+            for trans in (False, True):
+                out.append(np.ascontiguousarray(F.apply(X[:, :c], trans=trans).cpu().numpy()))
+        torch.cuda.synchronize()
+        F.close()
+        return out
+
+    bf.set_autotune(False)
+    try:
+        ref = run()
+        bf.autotune_clear()
+        bf.set_autotune(True)
+        tuned = run()
+        path = str(tmp_path / "tune.tsv")
+        bf.autotune_save(path)
+        rows = _tune_rows(path)
+        say("tuned classes", len(rows), sorted({r[0] for r in rows}))
+        assert {r[0] for r in rows} == set(TUNE_CANDIDATES)
+        for a, b in zip(ref, tuned):
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+        for trial in range(max(len(v) for v in TUNE_CANDIDATES.values())):
+            forced = str(tmp_path / f"forced{trial}.tsv")
+            with open(forced, "w") as f:
+                for fam, fields, _ in rows:
+                    ok = [c for c in TUNE_CANDIDATES[fam] if _valid(fam, fields, c)]
+                    f.write(" ".join([fam] + [str(x) for x in fields] +
+                                     [str(ok[trial % len(ok)])]) + "\n")
+            bf.autotune_clear()
+            bf.autotune_load(forced)
+            say("forced candidates, trial", trial)
+            got = run()
+            for a, b in zip(ref, got):
+                assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), trial
+        # a saved table restores every class
+        bf.autotune_clear()
+        bf.autotune_load(path)
+        assert bf.autotune_entries() == len(rows)
+    finally:
+        bf.set_autotune(True)
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
@@ -322,6 +408,66 @@ def test_apply_precisions(bf, n, leaf):
     with pytest.raises(bf.BFError):
         lib_rc = bf.lib().bf_set_apply_precision(H._h, 0)
         bf._check(lib_rc, "bf_set_apply_precision")
+    H.close()
+
+
+@pytest.mark.parametrize("n,leaf", [(2000, 40), (4096, 16)])
+def test_fused_apply_matches_staged(bf, n, leaf):
+    """Applies of 1 to 16 columns run several stages per launch
+    (bf_set_apply_fusion): bitwise the stage-by-stage results for 1 to 4
+    columns (same row kernel and summation order), within the apply tolerance
+    of the oracle's FP64 apply for every column from 5 to 16, forward and
+    adjoint, in both apply precisions."""
+    g = wl.segment_pair(n, ppw=6.0)
+    op = ops.SegmentKernelOp(g.targets, g.sources, g.k)
+    F = obf.construct(op, 1e-6, leaf, seed=3)
+    kU, kV, data = oracle_to_canonical(F)
+    say("fused apply", n, leaf, F.L)
+    H = bf.import_factors(n, n, leaf, kU, kV, data)
+    rng = np.random.default_rng(11)
+    for prec in ("bf16x3", "fp32"):
+        H.set_precision(prec)
+        for s in (1, 2, 3, 4, 5, 8, 11, 16):
+            X = _cg(rng, n, s)
+            got = {}
+            for fuse in (True, False):
+                H.set_fusion(fuse)
+                got[fuse] = (H.apply(_t(X)).cpu().numpy(), H.apply(_t(X), trans=True).cpu().numpy())
+            H.set_fusion(True)
+            ref, refh = obf.apply(F, X), obf.apply_adjoint(F, X)
+            say("fused", prec, s, _rel(got[True][0], ref), _rel(got[True][1], refh))
+            if s <= 4:
+                for d in (0, 1):
+                    assert np.array_equal(got[True][d].view(np.uint64),
+                                          got[False][d].view(np.uint64)), (prec, s, d)
+            for d, r in ((0, ref), (1, refh)):
+                assert _rel(got[True][d], r) < 1e-6, (prec, s, d)
+                for c in range(s):
+                    assert np.linalg.norm(got[True][d][:, c] - r[:, c]) <= 2e-6 * np.linalg.norm(r[:, c])
+    H.close()
+
+
+def test_fused_apply_ragged_shapes(bf):
+    """Fused applies of GPU-built factors with m != n and uneven node sizes
+    agree with the stage-by-stage apply (bitwise up to 4 columns)."""
+    import torch
+    g = wl.segment_pair(1500, ppw=8.0, m=1100)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    H = bf.construct(op, 1e-6, 24, seed=4)
+    rng = np.random.default_rng(12)
+    for s in (1, 3, 7, 16):
+        for trans, rows in ((False, 1500), (True, 1100)):
+            X = _t(_cg(rng, rows, s))
+            H.set_fusion(True)
+            a = H.apply(X, trans=trans)
+            H.set_fusion(False)
+            b = H.apply(X, trans=trans)
+            torch.cuda.synchronize()
+            if s <= 4:
+                assert _same_bits(a, b), (s, trans)
+            else:
+                assert float((a - b).norm() / b.norm()) < 1e-6, (s, trans)
+    H.set_fusion(True)
     H.close()
 
 

@@ -31,7 +31,12 @@ def _t(x):
     return torch.from_numpy(np.asarray(x, np.complex64)).cuda()
 
 
-def test_mix_equals_alone(bf):
+@pytest.mark.parametrize("rounds", [False, True])
+def test_mix_equals_alone(bf, rounds):
+    """Constructions of several sizes, wavenumbers and tolerances run together
+    on 4 slots give bitwise the factors each gives alone, with and without
+    cross-request solve rounds (their QRs and least squares then share
+    persistent launches)."""
     import torch
     specs = [(2048, 8.0, 1e-6, 11), (3000, 4.0, 1e-4, 12), (4096, 16.0, 1e-6, 13),
              (2500, 6.0, 1e-6, 14), (5000, 8.0, 1e-4, 15), (2048, 12.0, 1e-4, 16)]
@@ -45,14 +50,22 @@ def test_mix_equals_alone(bf):
         F = bf.construct(op, tol, 64, seed=seed)
         alone.append(F.export())
         F.close()
-    say("mix")
-    S = bf.Server(slots=4)
+    say("mix", "rounds" if rounds else "")
+    S = bf.Server(slots=4, solve_rounds=rounds)
     tickets = [S.submit_construct(op, tol, 64, seed=seed) for op, (n, ppw, tol, seed) in zip(opsl, specs)]
     for t, a in zip(tickets, alone):
         info = S.wait(t)
         assert info["finish_ns"] >= info["start_ns"] >= info["arrival_ns"]
         got = S.factors(t).export()
         assert np.array_equal(got, a)
+    nr, ni = S.rounds()
+    say("solve rounds", nr, "items", ni)
+    if rounds:
+        # the QRs of every leaf-loop pass and sweep level and the centre
+        # least squares of every construction went through rounds
+        assert nr > 0 and ni > 0
+    else:
+        assert (nr, ni) == (0, 0)
     # applies against resident factors, from several requests at once
     X = [_t(wl.test_columns(n, 3, 5)) for (n, _, _, _) in specs]
     at = [S.submit_apply(t, x) for t, x in zip(tickets, X)]

@@ -54,7 +54,8 @@ def _pair(bf, F, trans, ncols, seed):
     s = torch.cuda.current_stream().cuda_stream
     lib = bf.lib()
     say(f"apply n={F.n} trans={trans} ncols={ncols}")
-    rc0 = lib.bf_apply(F._h, trans, Xd.data_ptr(), rows_in, ncols, Y0.data_ptr(), rows_out, s)
+    rc0 = lib.bf_apply(F._h, trans, Xd.data_ptr(), rows_in, ncols, Y0.data_ptr(), rows_out,
+                       None, s)
     assert rc0 == 0, bf.lib().bf_last_error()
     rc1 = lib.bf_apply_noalloc(F._h, trans, Xd.data_ptr(), rows_in, ncols, Y1.data_ptr(),
                                rows_out, s)
