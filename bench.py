@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--mix", type=int, default=256,
                     help="requests of the mixed serving stream (0 = skip); run served and "
                          "through the per-request path")
+    ap.add_argument("--mix-rate", type=float, default=160.0,
+                    help="Poisson arrival rate (requests/s) of the mixed stream")
     ap.add_argument("--apply-burst", type=int, default=0,
                     help="only submit this many 1-column applies at once against one "
                          "factorization of the headline operator, with and without continuous "
@@ -765,8 +767,8 @@ def main():
                 "completed_per_s": args.stream / wall_s}
     mix = None
     if args.mix > 0:
-        reqs = wl.mixed_stream(args.mix)
-        mix = {"requests": args.mix,
+        reqs = wl.mixed_stream(args.mix, rate=args.mix_rate)
+        mix = {"requests": args.mix, "rate_per_s": args.mix_rate,
                "constructions": sum(r.kind == "construct" for r in reqs),
                "applies": sum(r.kind != "construct" for r in reqs)}
         # served: `slots` device slots with continuous batching of applies;

@@ -542,11 +542,104 @@ __device__ __forceinline__ void fused_row(const ApplyRowRec& rr, int q, const bf
   }
 }
 
+// Inner index of slot j of lane q in a row: the few-column kernel's order
+// (pairs 2q, 2q + 1 in steps of 16 for one or two columns, q in steps of 8
+// otherwise), so that every path sums a row's terms in the same order.
+template <int NC>
+__device__ __forceinline__ int fused_k(int q, int j) {
+  if constexpr (NC <= 2)
+    return 2 * q + (j & 1) + 16 * (j >> 1);
+  else
+    return q + 8 * j;
+}
+
+constexpr int AF_PF = 8;   // factor entries per lane fetched ahead (rows of up to 64 terms)
+
+__device__ __forceinline__ void fused_fetch_g(const ApplyRowRec& rr, bool has, int q,
+                                              const bf_c64* __restrict__ G, bf_c64 (&g)[AF_PF],
+                                              int nc_small) {
+#pragma unroll
+  for (int j = 0; j < AF_PF; ++j) {
+    const int k = nc_small ? 2 * q + (j & 1) + 16 * (j >> 1) : q + 8 * j;
+    g[j] = (has && k < rr.KK) ? G[rr.g + k] : bf_c64{0.f, 0.f};
+  }
+}
+
+// One output row whose first AF_PF factor entries per lane are in g: the
+// inputs of those slots are loaded together (in chunks of 4 columns), then
+// further slots (rows of more than 64 terms) stream from memory.  Same
+// slots, same order as fused_row.
+template <typename Acc, int NC>
+__device__ __forceinline__ void fused_row_pre(const ApplyRowRec& rr, const bf_c64 (&g)[AF_PF], int q,
+                                              const bf_c64* __restrict__ G, const ApplyBufs& B,
+                                              int ncols) {
+  const int KK = rr.KK, K0 = rr.K0;
+  const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
+  const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
+  const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
+  constexpr int CH = NC < 4 ? NC : 4;
+  Acc acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = Acc{0, 0};
+  // slots j < AF_PF: factor entries already in registers
+#pragma unroll
+  for (int c0 = 0; c0 < NC; c0 += CH) {
+    bf_c64 xv[AF_PF][CH];
+#pragma unroll
+    for (int j = 0; j < AF_PF; ++j) {
+      const int k = fused_k<NC>(q, j);
+      const bool kv = k < KK;
+      const bf_c64* inp = k < K0 ? in0 + k : in1 + k;
+      const int64_t ldk = k < K0 ? ld0 : ld1;
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+        xv[j][c] = (kv && c0 + c < ncols) ? inp[(int64_t)(c0 + c) * ldk] : bf_c64{0.f, 0.f};
+    }
+#pragma unroll
+    for (int j = 0; j < AF_PF; ++j)
+#pragma unroll
+      for (int c = 0; c < CH; ++c) acc_fma(acc[c0 + c], g[j], xv[j][c]);
+  }
+  // further slots
+  for (int j0 = AF_PF; fused_k<NC>(0, j0) < KK; j0 += AF_PF) {
+#pragma unroll
+    for (int jj = 0; jj < AF_PF; ++jj) {
+      const int k = fused_k<NC>(q, j0 + jj);
+      const bool kv = k < KK;
+      const bf_c64 gk = kv ? G[rr.g + k] : bf_c64{0.f, 0.f};
+      const bf_c64* inp = k < K0 ? in0 + k : in1 + k;
+      const int64_t ldk = k < K0 ? ld0 : ld1;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const bf_c64 x = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
+        acc_fma(acc[c], gk, x);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    acc[c].re = row8_sum(acc[c].re);
+    acc[c].im = row8_sum(acc[c].im);
+  }
+  if (q == 0) {
+    bf_c64* out = B.p[rr.out_buf] + rr.out;
+    const int64_t ldo = B.ld[rr.out_buf];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
+  }
+}
+
 // off[w * (nstage + 1) + t] .. off[w * (nstage + 1) + t + 1]: the row records
-// of workgroup w's group in stage t (records grouped by workgroup, then stage).
-// NT threads per workgroup: NT / 8 rows of a stage at a time.  Rows are
-// independent, so NT changes the schedule only, never the results.
-template <typename Acc, int NC, int NT>
+// of workgroup w's group in stage t (records grouped by workgroup, then
+// stage).  NT threads, NT / 8 rows of a stage at a time; rows are
+// independent, so NT changes the schedule only, never the results.  The
+// first RPT rows of each thread in stage t + 1 (their records, then their
+// factor entries) and their records of stage t + 2 are fetched while stage t
+// computes: after a barrier only the inputs, just written by the workgroup
+// itself, are waited for.  Further rows of a stage take extra passes without
+// fetching ahead.
+template <typename Acc, int NC, int NT, int RPT>
 __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __restrict__ rows,
                                                          const int32_t* __restrict__ off,
                                                          int32_t nstage,
@@ -554,22 +647,89 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
                                                          ApplyBufs B, int32_t ncols) {
   const int q = threadIdx.x & (AP_LPR - 1);
   const int rl = threadIdx.x / AP_LPR;
+  constexpr int RS = NT / AP_LPR;   // rows per pass
   const int32_t* o = off + (int64_t)blockIdx.x * (nstage + 1);
+  if constexpr (NC > 8) {
+    // 16 columns: their inputs and sums fill the registers; no fetching ahead
+    for (int t = 0; t < nstage; ++t) {
+      for (int32_t R = o[t] + rl; R < o[t + 1]; R += RS) fused_row<Acc, NC>(rows[R], q, G, B, ncols);
+      if (t + 1 < nstage) __syncthreads();
+    }
+    return;
+  }
+  constexpr int small = NC <= 2;
+  auto fetch_rec = [&](int t, int i, ApplyRowRec& r) -> bool {
+    const int32_t R = o[t] + rl + i * RS;
+    const bool h = R < o[t + 1];
+    if (h) r = rows[R];
+    return h;
+  };
+  ApplyRowRec rc[RPT], rn[RPT];
+  bool hc[RPT], hn[RPT];
+  bf_c64 gc[RPT][AF_PF], gn[RPT][AF_PF];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    hc[i] = fetch_rec(0, i, rc[i]);
+    hn[i] = nstage > 1 ? fetch_rec(1, i, rn[i]) : false;
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) fused_fetch_g(rc[i], hc[i], q, G, gc[i], small);
   for (int t = 0; t < nstage; ++t) {
-    const int32_t r0 = o[t], r1 = o[t + 1];
-    for (int32_t R = r0 + rl; R < r1; R += NT / AP_LPR) fused_row<Acc, NC>(rows[R], q, G, B, ncols);
+    ApplyRowRec r2[RPT];
+    bool h2[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      if (t + 1 < nstage) fused_fetch_g(rn[i], hn[i], q, G, gn[i], small);
+      h2[i] = t + 2 < nstage ? fetch_rec(t + 2, i, r2[i]) : false;
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (hc[i]) fused_row_pre<Acc, NC>(rc[i], gc[i], q, G, B, ncols);
+    for (int32_t R = o[t] + rl + RPT * RS; R < o[t + 1]; R += RS)
+      fused_row<Acc, NC>(rows[R], q, G, B, ncols);
     if (t + 1 < nstage) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      rc[i] = rn[i];
+      hc[i] = hn[i];
+#pragma unroll
+      for (int j = 0; j < AF_PF; ++j) gc[i][j] = gn[i][j];
+      rn[i] = r2[i];
+      hn[i] = h2[i];
+    }
+  }
+}
+
+// Workgroup shape of a fused launch: 8 threads per row and a stage's rows in
+// one pass of up to 128 rows -- 256 threads with one row each for up to 32
+// rows, else 512 threads with two rows each fetched ahead (one row each for
+// 8 columns; 16 columns fetch nothing ahead and take 1024 threads); larger
+// stages take further passes.
+template <typename Acc, int NC>
+static void launch_fused_nc(dim3 grid, int32_t max_rows, hipStream_t s,
+                            const ApplyRowRec* rows_dev, const int32_t* off_dev, int32_t nstage,
+                            const bf_c64* G, const ApplyBufs& B, int nc) {
+  if (max_rows <= 32) {
+    hipLaunchKernelGGL((apply_fused_kernel<Acc, NC, 256, 1>), grid, dim3(256), 0, s, rows_dev,
+                       off_dev, nstage, G, B, nc);
+  } else if constexpr (NC > 8) {
+    hipLaunchKernelGGL((apply_fused_kernel<Acc, NC, 1024, 1>), grid, dim3(1024), 0, s, rows_dev,
+                       off_dev, nstage, G, B, nc);
+  } else if constexpr (NC == 8) {
+    hipLaunchKernelGGL((apply_fused_kernel<Acc, NC, 512, 1>), grid, dim3(512), 0, s, rows_dev,
+                       off_dev, nstage, G, B, nc);
+  } else {
+    hipLaunchKernelGGL((apply_fused_kernel<Acc, NC, 512, 2>), grid, dim3(512), 0, s, rows_dev,
+                       off_dev, nstage, G, B, nc);
   }
 }
 
 void launch_apply_fused(const ApplyRowRec* rows_dev, const int32_t* off_dev, int32_t nwg,
-                        int32_t nstage, int32_t threads, const bf_c64* G,
+                        int32_t nstage, int32_t max_rows, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
                         int prec, hipStream_t s) {
   if (nwg <= 0 || ncols <= 0) return;
   BF_CHECK(ncols <= kApplyFusedCols, BF_EINVAL, "fused apply: too many right-hand sides");
-  BF_CHECK(threads == 256 || threads == 512 || threads == 1024, BF_EINVAL,
-           "fused apply: 256, 512 or 1024 threads per workgroup");
   ApplyBufs B;
   for (int i = 0; i < 4; ++i) {
     B.p[i] = const_cast<bf_c64*>(bufs[i]);
@@ -578,28 +738,20 @@ void launch_apply_fused(const ApplyRowRec* rows_dev, const int32_t* off_dev, int
   }
   const int nc = (int)ncols;
   const dim3 grid((unsigned)nwg);
-#define AP_FUSED_T(ACC, N, T) \
-  hipLaunchKernelGGL((apply_fused_kernel<ACC, N, T>), grid, dim3(T), 0, s, rows_dev, off_dev, \
-                     nstage, G, B, nc)
-#define AP_FUSED(ACC, N) \
-  do { \
-    if (threads == 256) AP_FUSED_T(ACC, N, 256); \
-    else if (threads == 512) AP_FUSED_T(ACC, N, 512); \
-    else AP_FUSED_T(ACC, N, 1024); \
-  } while (0)
   if (nc == 1) {
-    if (prec == BF_PREC_FP32) AP_FUSED(cf, 1); else AP_FUSED(cd, 1);
+    if (prec == BF_PREC_FP32)
+      launch_fused_nc<cf, 1>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
+    else
+      launch_fused_nc<cd, 1>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   } else if (nc == 2) {
-    AP_FUSED(cf, 2);
+    launch_fused_nc<cf, 2>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   } else if (nc <= 4) {
-    AP_FUSED(cf, 4);
+    launch_fused_nc<cf, 4>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   } else if (nc <= 8) {
-    AP_FUSED(cf, 8);
+    launch_fused_nc<cf, 8>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   } else {
-    AP_FUSED(cf, 16);
+    launch_fused_nc<cf, 16>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   }
-#undef AP_FUSED
-#undef AP_FUSED_T
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs == hipStreamCaptureStatusNone)
     BF_HIP(hipGetLastError());

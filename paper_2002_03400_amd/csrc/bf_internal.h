@@ -327,9 +327,9 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
 // off[w*(nstage+1)+t+1]) of stage t for t = 0..nstage-1, with a barrier
 // between stages; buffers column-major (element (r, c) at bufs[i][r + c*lds[i]]).
 // ncols <= kApplyFusedCols; FP64 sums for one column unless prec is FP32.
-// threads: 256, 512 or 1024 per workgroup (8 per row being computed).
+// max_rows: the most rows one workgroup has in one stage (sizes the workgroup).
 void launch_apply_fused(const ApplyRowRec* rows_dev, const int32_t* off_dev, int32_t nwg,
-                        int32_t nstage, int32_t threads, const bf_c64* G,
+                        int32_t nstage, int32_t max_rows, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], int64_t ncols,
                         int prec, hipStream_t s);
 

@@ -104,11 +104,19 @@ struct PlanBuilder {
   }
 };
 
-// Workgroups a fused launch should keep: below this many groups a stage is
-// not added to the launch unless its groups are small (kFusedSmallRows rows
-// over the whole launch), which keeps small factorizations to few launches.
+// A stage joins a fused launch while every group keeps at most
+// kFusedMaxStageRows rows per stage (one pass of a 1024-thread workgroup, so
+// each thread's row of the next stage can be fetched ahead) and the launch
+// keeps kFusedMinGroups workgroups -- or its groups stay small
+// (kFusedSmallRows rows over the whole launch), which keeps small
+// factorizations to few launches.
+constexpr int64_t kFusedMaxStageRows = 128;
 constexpr int64_t kFusedMinGroups = 256;
 constexpr int64_t kFusedSmallRows = 512;
+// Stages with more factor bytes than this stream at HBM rate on their own
+// (each launch then fills the device); only smaller, latency-bound stages
+// are fused.
+constexpr double kFusedMaxStageBytes = 16.0 * (1 << 20);
 
 struct UnionFind {
   std::vector<int32_t> p;
@@ -181,19 +189,28 @@ void build_fused(const PlanBuilder& pb, ApplyPlan& plan, Staging& st, hipStream_
     // grow the launch [a, e) while it keeps enough groups (or stays small)
     int64_t groups = stg[a].nblk;
     int e = a + 1;
-    while (e < ns) {
+    while (e < ns && 8.0 * stg[a].macs <= kFusedMaxStageBytes &&
+           8.0 * stg[e].macs <= kFusedMaxStageBytes) {
       UnionFind trial = uf;
       int64_t g = groups + stg[e].nblk;
       for (int64_t b = stg[e].blk_off; b < stg[e].blk_off + stg[e].nblk; ++b)
         for (int64_t k = poff[(size_t)b]; k < poff[(size_t)b + 1]; ++k)
           if (trial.unite((int32_t)b, prod[(size_t)k])) --g;
-      int64_t rows_max = 0;
-      if (g < kFusedMinGroups) {
+      // rows per group over the launch, and per group and stage
+      int64_t rows_max = 0, stage_rows_max = 0;
+      {
         std::unordered_map<int32_t, int64_t> rows;
-        for (int t = a; t <= e; ++t)
-          for (int64_t b = stg[t].blk_off; b < stg[t].blk_off + stg[t].nblk; ++b)
-            rows_max = std::max(rows_max, rows[trial.find((int32_t)b)] += pb.blks[(size_t)b].M);
+        for (int t = a; t <= e; ++t) {
+          std::unordered_map<int32_t, int64_t> srows;
+          for (int64_t b = stg[t].blk_off; b < stg[t].blk_off + stg[t].nblk; ++b) {
+            const int32_t r = trial.find((int32_t)b);
+            const int64_t M = pb.blks[(size_t)b].M;
+            rows_max = std::max(rows_max, rows[r] += M);
+            stage_rows_max = std::max(stage_rows_max, srows[r] += M);
+          }
+        }
       }
+      if (stage_rows_max > kFusedMaxStageRows) break;
       if (g < kFusedMinGroups && rows_max > kFusedSmallRows) break;
       uf = std::move(trial);
       groups = g;
@@ -246,6 +263,10 @@ void build_fused(const PlanBuilder& pb, ApplyPlan& plan, Staging& st, hipStream_
     BF_CHECK(rec < INT32_MAX, BF_EINVAL, "fused apply: too many row records");
     plan.segs.push_back(seg);
     a = e;
+  }
+  if (plan.segs.size() == (size_t)ns) {   // nothing fused: the stage kernels serve better
+    plan.segs.clear();
+    return;
   }
   plan.fused_rows = std::max<int64_t>(tot, 1);
   auto fbd = upload(fb, s, st);
@@ -478,12 +499,8 @@ static void run_fused(const bf_factors* F, int trans, const bf_c64* X, int64_t l
     double by = 8.0 * sg.macs;
     if (k == 0) by += 8.0 * (double)rin * ncols;
     if (k + 1 == P.segs.size()) by += 8.0 * (double)rout * ncols;
-    // 8 threads per row: enough for the launch's largest group-stage in one
-    // pass, within 256..1024
-    int32_t threads = 256;
-    while (threads < 1024 && threads < 8 * sg.max_rows) threads *= 2;
     auto launch = [&] {
-      launch_apply_fused(P.frows.p, P.foff.p + sg.off_off, sg.nwg, sg.nstage, threads, P.G.p,
+      launch_apply_fused(P.frows.p, P.foff.p + sg.off_off, sg.nwg, sg.nstage, sg.max_rows, P.G.p,
                          bufs, lds, ncols, F->apply_prec, s);
     };
     if (prof) {
