@@ -630,6 +630,75 @@ __device__ __forceinline__ void fused_row_pre(const ApplyRowRec& rr, const bf_c6
   }
 }
 
+// fused_row_pre in two halves, so that a stage's input loads can be issued
+// before the next stage's fetches (memory results return in issue order: a
+// wait for the inputs would otherwise wait for those fetches too).
+template <int NC>
+__device__ __forceinline__ void fused_in_load(const ApplyRowRec& rr, int q, const ApplyBufs& B,
+                                              int ncols, bf_c64 (&xv)[AF_PF][NC]) {
+  const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
+  const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
+  const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
+#pragma unroll
+  for (int j = 0; j < AF_PF; ++j) {
+    const int k = fused_k<NC>(q, j);
+    const bool kv = k < rr.KK;
+    const bf_c64* inp = k < rr.K0 ? in0 + k : in1 + k;
+    const int64_t ldk = k < rr.K0 ? ld0 : ld1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      xv[j][c] = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
+  }
+}
+
+template <typename Acc, int NC>
+__device__ __forceinline__ void fused_row_fin(const ApplyRowRec& rr, const bf_c64 (&g)[AF_PF],
+                                              const bf_c64 (&xv)[AF_PF][NC], int q,
+                                              const bf_c64* __restrict__ G, const ApplyBufs& B,
+                                              int ncols) {
+  const int KK = rr.KK, K0 = rr.K0;
+  Acc acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = Acc{0, 0};
+#pragma unroll
+  for (int j = 0; j < AF_PF; ++j)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc_fma(acc[c], g[j], xv[j][c]);
+  // further slots (rows of more than 64 terms)
+  if (fused_k<NC>(0, AF_PF) < KK) {
+    const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
+    const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
+    const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
+    for (int j0 = AF_PF; fused_k<NC>(0, j0) < KK; j0 += AF_PF) {
+#pragma unroll
+      for (int jj = 0; jj < AF_PF; ++jj) {
+        const int k = fused_k<NC>(q, j0 + jj);
+        const bool kv = k < KK;
+        const bf_c64 gk = kv ? G[rr.g + k] : bf_c64{0.f, 0.f};
+        const bf_c64* inp = k < K0 ? in0 + k : in1 + k;
+        const int64_t ldk = k < K0 ? ld0 : ld1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const bf_c64 x = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
+          acc_fma(acc[c], gk, x);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    acc[c].re = row8_sum(acc[c].re);
+    acc[c].im = row8_sum(acc[c].im);
+  }
+  if (q == 0) {
+    bf_c64* out = B.p[rr.out_buf] + rr.out;
+    const int64_t ldo = B.ld[rr.out_buf];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
+  }
+}
+
 // off[w * (nstage + 1) + t] .. off[w * (nstage + 1) + t + 1]: the row records
 // of workgroup w's group in stage t (records grouped by workgroup, then
 // stage).  NT threads, NT / 8 rows of a stage at a time; rows are
@@ -675,6 +744,17 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
 #pragma unroll
   for (int i = 0; i < RPT; ++i) fused_fetch_g(rc[i], hc[i], q, G, gc[i], small);
   for (int t = 0; t < nstage; ++t) {
+    // inputs of the first row first, then the next stages' fetches, then the
+    // arithmetic: the first row waits for its inputs only
+    constexpr int NCI = NC <= 4 ? NC : 1;
+    constexpr int RI = NC == 1 ? RPT : 1;   // rows whose inputs go first
+    bf_c64 xv0[RI][AF_PF][NCI];
+    if constexpr (NC <= 4) {
+#pragma unroll
+      for (int i = 0; i < RI; ++i)
+        if (hc[i]) fused_in_load<NC>(rc[i], q, B, ncols, xv0[i]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
     ApplyRowRec r2[RPT];
     bool h2[RPT];
 #pragma unroll
@@ -682,9 +762,18 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
       if (t + 1 < nstage) fused_fetch_g(rn[i], hn[i], q, G, gn[i], small);
       h2[i] = t + 2 < nstage ? fetch_rec(t + 2, i, r2[i]) : false;
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = 0; i < RPT; ++i)
-      if (hc[i]) fused_row_pre<Acc, NC>(rc[i], gc[i], q, G, B, ncols);
+    for (int i = 0; i < RPT; ++i) {
+      if (!hc[i]) continue;
+      if constexpr (NC <= 4) {
+        if (i < RI) {
+          fused_row_fin<Acc, NC>(rc[i], gc[i], xv0[i < RI ? i : 0], q, G, B, ncols);
+          continue;
+        }
+      }
+      fused_row_pre<Acc, NC>(rc[i], gc[i], q, G, B, ncols);
+    }
     for (int32_t R = o[t] + rl + RPT * RS; R < o[t + 1]; R += RS)
       fused_row<Acc, NC>(rows[R], q, G, B, ncols);
     if (t + 1 < nstage) __syncthreads();
@@ -702,9 +791,10 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
 
 // Workgroup shape of a fused launch: 8 threads per row and a stage's rows in
 // one pass of up to 128 rows -- 256 threads with one row each for up to 32
-// rows, else 512 threads with two rows each fetched ahead (one row each for
-// 8 columns; 16 columns fetch nothing ahead and take 1024 threads); larger
-// stages take further passes.
+// rows, else 512 threads with two rows each fetched ahead for one column
+// (one row each for 2 to 8 columns, whose inputs need the registers; 16
+// columns fetch nothing ahead and take 1024 threads); larger stages take
+// further passes.
 template <typename Acc, int NC>
 static void launch_fused_nc(dim3 grid, int32_t max_rows, hipStream_t s,
                             const ApplyRowRec* rows_dev, const int32_t* off_dev, int32_t nstage,
@@ -715,7 +805,7 @@ static void launch_fused_nc(dim3 grid, int32_t max_rows, hipStream_t s,
   } else if constexpr (NC > 8) {
     hipLaunchKernelGGL((apply_fused_kernel<Acc, NC, 1024, 1>), grid, dim3(1024), 0, s, rows_dev,
                        off_dev, nstage, G, B, nc);
-  } else if constexpr (NC == 8) {
+  } else if constexpr (NC >= 2) {
     hipLaunchKernelGGL((apply_fused_kernel<Acc, NC, 512, 1>), grid, dim3(512), 0, s, rows_dev,
                        off_dev, nstage, G, B, nc);
   } else {

@@ -51,6 +51,7 @@ struct PlanBuilder {
   std::vector<ApplyBlk> blks;
   int64_t nrows = 0;   // row records (expanded from the blocks on the device)
   std::vector<PackDesc> packs;
+  std::vector<int32_t> pack_blk;   // block of each pack descriptor
   std::vector<Stage> stages;
   int64_t goff = 0;
   int cur_in = 0, cur_out = 1;
@@ -87,8 +88,11 @@ struct PlanBuilder {
     int koff = 0;
     for (int q = 0; q < nt; ++q) {
       if (t[q].K > 0)
+      {
         packs.push_back(PackDesc{t[q].b->p, goff + koff, t[q].b->rows, t[q].row0, M, t[q].K,
                                  t[q].conjT, KK, 1, 0});
+        pack_blk.push_back((int32_t)blks.size());
+      }
       koff += t[q].K;
     }
     goff += (int64_t)M * KK;
@@ -143,7 +147,17 @@ struct UnionFind {
 // are grouped into launches, each launch's blocks split into independent
 // groups (one workgroup each), and the groups' blocks re-indexed as row
 // records ordered by launch, group and stage.
-void build_fused(const PlanBuilder& pb, ApplyPlan& plan, Staging& st, hipStream_t s) {
+struct FusedHost {
+  std::vector<ApplyBlk> fb;      // blocks in fused order, fused buffers and rows
+  std::vector<int32_t> off;      // per segment, group and stage: first row record
+  int64_t rec = 0;
+};
+
+// Computes the schedule and lays the packed factor arena out in its order
+// (group after group, stage after stage), so that a workgroup streams one
+// contiguous range per stage; rewrites pb's block offsets and pack
+// destinations accordingly (the arena's size is unchanged).
+void fused_schedule(PlanBuilder& pb, ApplyPlan& plan, FusedHost& fh) {
   const auto& stg = pb.stages;
   const int ns = (int)stg.size();
   if (ns == 0) return;
@@ -179,10 +193,11 @@ void build_fused(const PlanBuilder& pb, ApplyPlan& plan, Staging& st, hipStream_
       poff[(size_t)b + 1] = (int64_t)prod.size();
     }
   }
-  std::vector<ApplyBlk> fb;
-  std::vector<int32_t> off;
+  std::vector<ApplyBlk>& fb = fh.fb;
+  std::vector<int32_t>& off = fh.off;
   fb.reserve(nb);
-  int64_t rec = 0;
+  int64_t rec = 0, gcur = 0;
+  std::vector<int64_t> new_g(nb, 0);
   UnionFind uf(nb);
   int a = 0;
   while (a < ns) {
@@ -242,7 +257,10 @@ void build_fused(const PlanBuilder& pb, ApplyPlan& plan, Staging& st, hipStream_
         for (int32_t b : grp[(size_t)(t - a)]) rows_gs += pb.blks[(size_t)b].M;
         seg.max_rows = (int32_t)std::max<int64_t>(seg.max_rows, rows_gs);
         for (int32_t b : grp[(size_t)(t - a)]) {
+          new_g[(size_t)b] = gcur;
+          gcur += (int64_t)pb.blks[(size_t)b].M * (pb.blks[(size_t)b].K0 + pb.blks[(size_t)b].K1);
           ApplyBlk bk = pb.blks[(size_t)b];
+          bk.g_off = new_g[(size_t)b];
           if (t + 1 < ns) {
             bk.out_buf = 1;
             bk.out_row += base[t];
@@ -266,18 +284,33 @@ void build_fused(const PlanBuilder& pb, ApplyPlan& plan, Staging& st, hipStream_
   }
   if (plan.segs.size() == (size_t)ns) {   // nothing fused: the stage kernels serve better
     plan.segs.clear();
+    fh = FusedHost{};
     return;
   }
   plan.fused_rows = std::max<int64_t>(tot, 1);
-  auto fbd = upload(fb, s, st);
-  plan.foff = upload(off, s, st);
-  plan.frows = DevBuf<ApplyRowRec>((size_t)std::max<int64_t>(rec, 1), s);
-  launch_expand_rows(fbd.p, (int32_t)fb.size(), plan.frows.p, s);
+  fh.rec = rec;
+  // the arena in fused order: every block's packed entries move as a whole
+  for (size_t b = 0; b < nb; ++b) {
+    const int64_t old = pb.blks[b].g_off;
+    pb.blks[b].g_off = new_g[b];
+    new_g[b] -= old;   // now the shift of block b
+  }
+  for (size_t k = 0; k < pb.packs.size(); ++k) pb.packs[k].dst_off += new_g[(size_t)pb.pack_blk[k]];
+}
+
+void build_fused(const FusedHost& fh, ApplyPlan& plan, Staging& st, hipStream_t s) {
+  if (plan.segs.empty()) return;
+  auto fbd = upload(fh.fb, s, st);
+  plan.foff = upload(fh.off, s, st);
+  plan.frows = DevBuf<ApplyRowRec>((size_t)std::max<int64_t>(fh.rec, 1), s);
+  launch_expand_rows(fbd.p, (int32_t)fh.fb.size(), plan.frows.p, s);
   BF_HIP(hipStreamSynchronize(s));   // fbd is released at return
 }
 
 void finish(PlanBuilder& pb, ApplyPlan& plan, int64_t tmp_rows, hipStream_t s,
             int64_t rows_in, int64_t rows_out) {
+  FusedHost fh;
+  fused_schedule(pb, plan, fh);
   if (validating()) {
     const int64_t nr[4] = {rows_in, tmp_rows, tmp_rows, rows_out};
     for (auto& b : pb.blks) {
@@ -312,7 +345,7 @@ void finish(PlanBuilder& pb, ApplyPlan& plan, int64_t tmp_rows, hipStream_t s,
     ProfScope ps(BF_KC_OTHER, s, 0.0, 0.0);
     launch_pack_c64(dd.p, (int32_t)cnt, plan.G.p, s);
   }
-  build_fused(pb, plan, st, s);
+  build_fused(fh, plan, st, s);
   BF_HIP(hipStreamSynchronize(s));
   st.reset();
 }
@@ -500,8 +533,8 @@ static void run_fused(const bf_factors* F, int trans, const bf_c64* X, int64_t l
     if (k == 0) by += 8.0 * (double)rin * ncols;
     if (k + 1 == P.segs.size()) by += 8.0 * (double)rout * ncols;
     auto launch = [&] {
-      launch_apply_fused(P.frows.p, P.foff.p + sg.off_off, sg.nwg, sg.nstage, sg.max_rows, P.G.p,
-                         bufs, lds, ncols, F->apply_prec, s);
+      launch_apply_fused(P.frows.p, P.foff.p + sg.off_off, sg.nwg, sg.nstage, sg.max_rows,
+                         P.G.p, bufs, lds, ncols, F->apply_prec, s);
     };
     if (prof) {
       ProfScope ps(BF_KC_APPLY, s, 8.0 * sg.macs * ncols, by);
