@@ -106,6 +106,9 @@ def parse():
                          "segments y = 0, 1, 2, 8 points per wavelength, leaf 64, tol 1e-6), "
                          "the composition B1 B2 recompressed with Alg. 2, error against FP64 "
                          "A01 (A12 Omega) on sampled rows; one JSON line")
+    ap.add_argument("--save-tune", default="",
+                    help="after the run, write the autotuner's table (with the timed candidates) "
+                         "to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (reference "
                          "dispatch for calibrating rocprofv3 byte counters) and exit")
@@ -862,6 +865,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.save_tune:
+        bf.autotune_save(args.save_tune)
 
 
 if __name__ == "__main__":

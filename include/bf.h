@@ -488,7 +488,8 @@ int bf_op_set_precision(bf_operator* op, int precision);
 /* Launch-shape autotuner (on by default).  For each kernel family and shape
  * class it keeps the fastest of a few launch variants that give bitwise the
  * same results, timed on the first launch of the class (which then runs
- * every candidate in turn on its stream and synchronizes it once; launches
+ * every candidate twice on its stream -- once to warm caches, once timed --
+ * and synchronizes it once; launches
  * under HIP graph capture and bf_apply_noalloc never time, they use the
  * table or the default rule):
  *   black-box column tile : 48, 64 or 80 columns, split-BF16 products of more

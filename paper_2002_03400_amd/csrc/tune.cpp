@@ -1,8 +1,8 @@
 // Launch-shape autotuner: for each kernel family and shape class, the fastest
-// of a few launch variants that give bitwise the same results, timed once
-// with events on the stream of the first launch of the class (that launch
-// then runs every candidate in turn and keeps the results of the last, which
-// equal the others').  Families and their candidates:
+// of a few launch variants that give bitwise the same results, timed with
+// events on the stream of the first launch of the class (that launch runs
+// every candidate once to warm caches and code, then once more timed, and
+// keeps the results of the last, which equal the others').  Families and their candidates:
 //   black-box column tile   48 / 64 / 80 columns (split-BF16 products of more than 48)
 //   chain tile height       8 / 16 (one wave per descriptor) or 20 / 24 / 32 / 64
 //                           rows, every height at least the launch's largest M
@@ -28,6 +28,7 @@ namespace {
 std::atomic<int> g_on{1};
 std::mutex g_mu;
 std::map<TuneKey, int64_t> g_table;
+std::map<TuneKey, std::vector<std::pair<int64_t, float>>> g_times;   // measured candidates
 std::once_flag g_load_once;
 
 const char* kFamily[kTuneFamilies] = {"matfree_width", "chain_rows", "cpqr_threads",
@@ -128,6 +129,9 @@ int64_t tune_choose(const TuneKey& key, const std::vector<int64_t>& cand, int64_
     run(fallback);
     return fallback;
   }
+  // every candidate once untimed (caches and code warm alike for all), then
+  // once timed
+  for (int64_t c : cand) run(c);
   std::vector<hipEvent_t> ev(cand.size() + 1, nullptr);
   for (auto& e : ev) BF_HIP(hipEventCreate(&e));
   BF_HIP(hipEventRecord(ev[0], s));
@@ -138,9 +142,11 @@ int64_t tune_choose(const TuneKey& key, const std::vector<int64_t>& cand, int64_
   BF_HIP(hipEventSynchronize(ev.back()));
   int64_t best = cand.back();
   float best_ms = 0.f;
+  std::vector<std::pair<int64_t, float>> times;
   for (size_t i = 0; i < cand.size(); ++i) {
     float ms = 0.f;
     BF_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+    times.push_back({cand[i], ms});
     if (i == 0 || ms < best_ms) {
       best_ms = ms;
       best = cand[i];
@@ -149,6 +155,7 @@ int64_t tune_choose(const TuneKey& key, const std::vector<int64_t>& cand, int64_
   for (auto& e : ev) (void)hipEventDestroy(e);
   std::lock_guard<std::mutex> lk(g_mu);
   g_table[key] = best;
+  g_times[key] = times;
   return best;
 }
 
@@ -163,6 +170,12 @@ int tune_save(const char* path) {
     std::fprintf(f, "%s", kFamily[kv.first[0]]);
     for (int i = 0; i < kTuneKeyFields; ++i) std::fprintf(f, " %lld", (long long)kv.first[1 + i]);
     std::fprintf(f, " %lld\n", (long long)kv.second);
+    auto it = g_times.find(kv.first);
+    if (it != g_times.end()) {   // the timed candidates, as a comment line
+      std::fprintf(f, "#   timed:");
+      for (auto& ct : it->second) std::fprintf(f, " %lld=%.4fms", (long long)ct.first, ct.second);
+      std::fprintf(f, "\n");
+    }
   }
   return std::fclose(f) == 0 ? BF_OK : BF_EINVAL;
 }
@@ -180,6 +193,7 @@ void tune_clear() {
   load_default();   // a later first lookup must not bring the file back
   std::lock_guard<std::mutex> lk(g_mu);
   g_table.clear();
+  g_times.clear();
 }
 
 }  // namespace bf
