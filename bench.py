@@ -579,15 +579,27 @@ def cpu_baseline_leg(geom, args, passes):
 def apply_roofline(bf, F, n, reps=20, sizes=(1, 4, 16, 64)):
     """bf_apply of the given factors (default arithmetic) at `sizes` right-hand
     sides: algorithmic bytes (8 per factor entry + 8 per input and output
-    value) over the launches' HIP-event time, against the HBM peak; the wall
-    time per apply includes the launches, and is taken again with the
-    launches run as one captured HIP graph."""
+    value) over the device time of an apply, against the HBM peak.  The device
+    time is one pair of HIP events on the apply's stream around `reps`
+    back-to-back applies (events around every launch would add a few
+    microseconds each, the launches being only a few microseconds long); the
+    sum of per-launch event times is reported beside it, and the host wall
+    time per apply launched directly and as one captured HIP graph."""
     import torch
     out = {}
     for s in sizes:
         X = torch.randn(n, s, dtype=torch.complex64, device="cuda")
         Y = F.apply(X)
+        F.apply(X, out=Y)
         torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            F.apply(X, out=Y)
+        e1.record()
+        torch.cuda.synchronize()
+        kms = e0.elapsed_time(e1) / reps
         bf.profile_start()
         t0 = time.perf_counter()
         for _ in range(reps):
@@ -595,7 +607,6 @@ def apply_roofline(bf, F, n, reps=20, sizes=(1, 4, 16, 64)):
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / reps
         ap = bf.profile_stop()["apply"]
-        kms = ap["ms"] / reps
         gbs = ap["bytes"] / reps / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
         # the same applies as one captured HIP graph each (bf_set_apply_graph_cols)
         F.set_graph_cols(64)
@@ -607,7 +618,8 @@ def apply_roofline(bf, F, n, reps=20, sizes=(1, 4, 16, 64)):
         torch.cuda.synchronize()
         gwall = (time.perf_counter() - t0) / reps
         F.set_graph_cols(0)
-        out[f"s={s}"] = {"kernel_ms": kms, "wall_ms": wall * 1e3, "graph_wall_ms": gwall * 1e3,
+        out[f"s={s}"] = {"kernel_ms": kms, "launch_event_sum_ms": ap["ms"] / reps,
+                         "wall_ms": wall * 1e3, "graph_wall_ms": gwall * 1e3,
                          "bytes": ap["bytes"] / reps, "GB_per_s": gbs,
                          "frac_hbm": gbs / PEAK_HBM_GBS,
                          "TFLOP_per_s": ap["flops"] / reps / (kms * 1e-3) / 1e12 if kms > 0 else 0.0,

@@ -239,6 +239,9 @@ typedef struct {
   int64_t rmatvec_cols;      /* ... and with A^H (structured samples count s each) */
   int64_t factor_entries;    /* complex entries stored over all factors */
   int64_t device_bytes;      /* device memory held by the handle */
+  int32_t fused_launches;    /* launches of a fused 1-16 column apply (0: every stage
+                                is its own launch, L + 3 of them) */
+  int32_t reserved;
 } bf_info;
 int bf_stats(const bf_factors* F, bf_info* info);
 
@@ -488,8 +491,9 @@ int bf_op_set_precision(bf_operator* op, int precision);
 /* Launch-shape autotuner (on by default).  For each kernel family and shape
  * class it keeps the fastest of a few launch variants that give bitwise the
  * same results, timed on the first launch of the class (which then runs
- * every candidate twice on its stream -- once to warm caches, once timed --
- * and synchronizes it once; launches
+ * every candidate four times on its stream -- once to warm caches, then three
+ * interleaved timed rounds, keeping each candidate's fastest -- and
+ * synchronizes it once; launches
  * under HIP graph capture and bf_apply_noalloc never time, they use the
  * table or the default rule):
  *   black-box column tile : 48, 64 or 80 columns, split-BF16 products of more

@@ -94,7 +94,8 @@ class bf_info(C.Structure):
                 ("max_rank", C.c_int32), ("v_iters", C.c_int32), ("u_iters", C.c_int32),
                 ("apply_graphs", C.c_int32),
                 ("matvec_cols", C.c_int64), ("rmatvec_cols", C.c_int64),
-                ("factor_entries", C.c_int64), ("device_bytes", C.c_int64)]
+                ("factor_entries", C.c_int64), ("device_bytes", C.c_int64),
+                ("fused_launches", C.c_int32), ("reserved", C.c_int32)]
 
 
 _LIB = None
@@ -406,6 +407,8 @@ class Info:
     rmatvec_cols: int
     factor_entries: int
     device_bytes: int
+    fused_launches: int
+    reserved: int
 
 
 class Factors:

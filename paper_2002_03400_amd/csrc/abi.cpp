@@ -805,6 +805,7 @@ int bf_stats(const bf_factors* F, bf_info* info) {
   if (!F || !info) return BF_EINVAL;
   *info = F->info;
   info->apply_graphs = apply_graph_count(F);
+  info->fused_launches = (int32_t)F->fwd.segs.size();
   return BF_OK;
 }
 

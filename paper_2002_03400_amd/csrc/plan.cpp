@@ -109,14 +109,16 @@ struct PlanBuilder {
 };
 
 // A stage joins a fused launch while every group keeps at most
-// kFusedMaxStageRows rows per stage (one pass of a 1024-thread workgroup, so
-// each thread's row of the next stage can be fetched ahead) and the launch
-// keeps kFusedMinGroups workgroups -- or its groups stay small
-// (kFusedSmallRows rows over the whole launch), which keeps small
-// factorizations to few launches.
+// kFusedMaxStageRows rows per stage (one pass of a 512-thread workgroup with
+// two rows per thread, so each thread's rows of the next stage can be fetched
+// ahead) and the launch keeps kFusedMinGroups workgroups.  Measured with one
+// event pair around whole applies: with fewer groups (n = 16384, 64 groups)
+// a workgroup's chain of dependent stages is slower than the stage kernels
+// at 2 to 16 columns (80 vs 99 us at 8 columns), with 256 groups (n = 65536)
+// faster at 1 and at 8 to 16 columns (57 vs 62 us at one column, 143 vs
+// 197 us at 8).
 constexpr int64_t kFusedMaxStageRows = 128;
 constexpr int64_t kFusedMinGroups = 256;
-constexpr int64_t kFusedSmallRows = 512;
 // Stages with more factor bytes than this stream at HBM rate on their own
 // (each launch then fills the device); only smaller, latency-bound stages
 // are fused.
@@ -211,22 +213,16 @@ void fused_schedule(PlanBuilder& pb, ApplyPlan& plan, FusedHost& fh) {
       for (int64_t b = stg[e].blk_off; b < stg[e].blk_off + stg[e].nblk; ++b)
         for (int64_t k = poff[(size_t)b]; k < poff[(size_t)b + 1]; ++k)
           if (trial.unite((int32_t)b, prod[(size_t)k])) --g;
-      // rows per group over the launch, and per group and stage
-      int64_t rows_max = 0, stage_rows_max = 0;
-      {
-        std::unordered_map<int32_t, int64_t> rows;
-        for (int t = a; t <= e; ++t) {
-          std::unordered_map<int32_t, int64_t> srows;
-          for (int64_t b = stg[t].blk_off; b < stg[t].blk_off + stg[t].nblk; ++b) {
-            const int32_t r = trial.find((int32_t)b);
-            const int64_t M = pb.blks[(size_t)b].M;
-            rows_max = std::max(rows_max, rows[r] += M);
-            stage_rows_max = std::max(stage_rows_max, srows[r] += M);
-          }
-        }
+      if (g < kFusedMinGroups) break;
+      // rows per group and stage
+      int64_t stage_rows_max = 0;
+      for (int t = a; t <= e; ++t) {
+        std::unordered_map<int32_t, int64_t> srows;
+        for (int64_t b = stg[t].blk_off; b < stg[t].blk_off + stg[t].nblk; ++b)
+          stage_rows_max = std::max(stage_rows_max,
+                                    srows[trial.find((int32_t)b)] += pb.blks[(size_t)b].M);
       }
       if (stage_rows_max > kFusedMaxStageRows) break;
-      if (g < kFusedMinGroups && rows_max > kFusedSmallRows) break;
       uf = std::move(trial);
       groups = g;
       ++e;

@@ -1,8 +1,9 @@
 // Launch-shape autotuner: for each kernel family and shape class, the fastest
 // of a few launch variants that give bitwise the same results, timed with
 // events on the stream of the first launch of the class (that launch runs
-// every candidate once to warm caches and code, then once more timed, and
-// keeps the results of the last, which equal the others').  Families and their candidates:
+// every candidate once to warm caches and code, then three interleaved timed
+// rounds, keeping each candidate's fastest, and keeps the results of the
+// last run, which equal the others').  Families and their candidates:
 //   black-box column tile   48 / 64 / 80 columns (split-BF16 products of more than 48)
 //   chain tile height       8 / 16 (one wave per descriptor) or 20 / 24 / 32 / 64
 //                           rows, every height at least the launch's largest M
@@ -14,6 +15,7 @@
 // once; launches under HIP graph capture never tune.
 #include <dlfcn.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdio>
 #include <map>
@@ -130,22 +132,30 @@ int64_t tune_choose(const TuneKey& key, const std::vector<int64_t>& cand, int64_
     return fallback;
   }
   // every candidate once untimed (caches and code warm alike for all), then
-  // once timed
+  // kTuneRounds interleaved timed rounds; a candidate's time is its fastest
+  // round (robust to other streams' work passing through the device)
+  constexpr int kTuneRounds = 3;
   for (int64_t c : cand) run(c);
-  std::vector<hipEvent_t> ev(cand.size() + 1, nullptr);
+  const size_t nc = cand.size();
+  std::vector<hipEvent_t> ev(nc * kTuneRounds + 1, nullptr);
   for (auto& e : ev) BF_HIP(hipEventCreate(&e));
   BF_HIP(hipEventRecord(ev[0], s));
-  for (size_t i = 0; i < cand.size(); ++i) {
-    run(cand[i]);
-    BF_HIP(hipEventRecord(ev[i + 1], s));
-  }
+  for (int r = 0; r < kTuneRounds; ++r)
+    for (size_t i = 0; i < nc; ++i) {
+      run(cand[i]);
+      BF_HIP(hipEventRecord(ev[r * nc + i + 1], s));
+    }
   BF_HIP(hipEventSynchronize(ev.back()));
   int64_t best = cand.back();
   float best_ms = 0.f;
   std::vector<std::pair<int64_t, float>> times;
-  for (size_t i = 0; i < cand.size(); ++i) {
+  for (size_t i = 0; i < nc; ++i) {
     float ms = 0.f;
-    BF_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+    for (int r = 0; r < kTuneRounds; ++r) {
+      float m = 0.f;
+      BF_HIP(hipEventElapsedTime(&m, ev[r * nc + i], ev[r * nc + i + 1]));
+      ms = r == 0 ? m : std::min(ms, m);
+    }
     times.push_back({cand[i], ms});
     if (i == 0 || ms < best_ms) {
       best_ms = ms;

@@ -11,7 +11,7 @@ from oracle import butterfly as obf
 from oracle import cpqr as ocpqr
 from oracle import operators as ops
 from oracle import philox
-from tests.bfconv import bf16_exact, oracle_to_canonical
+from tests.bfconv import bf16_exact, canonical_to_oracle, oracle_to_canonical
 
 pytestmark = pytest.mark.gpu
 
@@ -232,16 +232,20 @@ def test_every_autotuner_candidate_gives_the_same_bits(bf, tmp_path):
     import torch
     g = wl.segment_pair(4096, ppw=8.0)
     op = bf.segkernel(g.targets, g.sources, g.k)
-    X = _t(_cg(np.random.default_rng(3), 4096, 3))
+    # applies of an exact rank-8 butterfly with L = 10 (1024 blocks a stage,
+    # enough groups for fused launches)
+    kU, kV, data = wl.exact_butterfly_canonical(10, 8, seed=5, leaf=8)
+    E = bf.import_factors(8192, 8192, 8, kU, kV, data)
+    X = _t(_cg(np.random.default_rng(3), 8192, 3))
 
     def run():
         F = bf.construct(op, 1e-6, 64, seed=31)
         out = [F.export()]
+        F.close()
         for c in (1, 2, 3):
             for trans in (False, True):
-                out.append(np.ascontiguousarray(F.apply(X[:, :c], trans=trans).cpu().numpy()))
+                out.append(np.ascontiguousarray(E.apply(X[:, :c], trans=trans).cpu().numpy()))
         torch.cuda.synchronize()
-        F.close()
         return out
 
     bf.set_autotune(False)
@@ -276,6 +280,7 @@ def test_every_autotuner_candidate_gives_the_same_bits(bf, tmp_path):
         assert bf.autotune_entries() == len(rows)
     finally:
         bf.set_autotune(True)
+        E.close()
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
@@ -411,30 +416,34 @@ def test_apply_precisions(bf, n, leaf):
     H.close()
 
 
-@pytest.mark.parametrize("n,leaf", [(2000, 40), (4096, 16)])
-def test_fused_apply_matches_staged(bf, n, leaf):
+@pytest.mark.parametrize("L,r,leaf", [(10, 8, 8), (11, 6, 6)])
+def test_fused_apply_matches_staged(bf, L, r, leaf):
     """Applies of 1 to 16 columns run several stages per launch
-    (bf_set_apply_fusion): bitwise the stage-by-stage results for 1 to 4
-    columns (same row kernel and summation order), within the apply tolerance
-    of the oracle's FP64 apply for every column from 5 to 16, forward and
-    adjoint, in both apply precisions."""
-    g = wl.segment_pair(n, ppw=6.0)
-    op = ops.SegmentKernelOp(g.targets, g.sources, g.k)
-    F = obf.construct(op, 1e-6, leaf, seed=3)
-    kU, kV, data = oracle_to_canonical(F)
-    say("fused apply", n, leaf, F.L)
+    (bf_set_apply_fusion) when every launch keeps 256 groups (here exact
+    butterflies of Sec. 6.1 with 1024 and 2048 blocks a level): bitwise the
+    stage-by-stage results for 1 to 4 columns (same row kernel and summation
+    order), within the apply tolerance of the oracle's FP64 apply of the same
+    factors for every column from 5 to 16, forward and adjoint, in both apply
+    precisions."""
+    n = leaf << L
+    kU, kV, data = wl.exact_butterfly_canonical(L, r, seed=L, leaf=leaf)
+    F = canonical_to_oracle(n, n, L, kU, kV, data)
+    say("fused apply", n, leaf, L)
     H = bf.import_factors(n, n, leaf, kU, kV, data)
+    assert H.stats().fused_launches >= 2
     rng = np.random.default_rng(11)
+    cases = []
+    for s in (1, 2, 3, 4, 5, 8, 11, 16):
+        X = _cg(rng, n, s)
+        cases.append((s, X, obf.apply(F, X), obf.apply_adjoint(F, X)))
     for prec in ("bf16x3", "fp32"):
         H.set_precision(prec)
-        for s in (1, 2, 3, 4, 5, 8, 11, 16):
-            X = _cg(rng, n, s)
+        for s, X, ref, refh in cases:
             got = {}
             for fuse in (True, False):
                 H.set_fusion(fuse)
                 got[fuse] = (H.apply(_t(X)).cpu().numpy(), H.apply(_t(X), trans=True).cpu().numpy())
             H.set_fusion(True)
-            ref, refh = obf.apply(F, X), obf.apply_adjoint(F, X)
             say("fused", prec, s, _rel(got[True][0], ref), _rel(got[True][1], refh))
             if s <= 4:
                 for d in (0, 1):
@@ -448,15 +457,17 @@ def test_fused_apply_matches_staged(bf, n, leaf):
 
 
 def test_fused_apply_ragged_shapes(bf):
-    """Fused applies of GPU-built factors with m != n and uneven node sizes
-    agree with the stage-by-stage apply (bitwise up to 4 columns)."""
+    """Fused applies of GPU-built factors with m != n, uneven node sizes and
+    uneven ranks (L = 10, leaves of 12 to 16 points) agree with the
+    stage-by-stage apply (bitwise up to 4 columns)."""
     import torch
-    g = wl.segment_pair(1500, ppw=8.0, m=1100)
+    g = wl.segment_pair(15000, ppw=8.0, m=11000)
     op = bf.segkernel(g.targets, g.sources, g.k)
-    H = bf.construct(op, 1e-6, 24, seed=4)
+    H = bf.construct(op, 1e-4, 16, seed=4)
+    assert H.L == 10 and H.stats().fused_launches >= 2
     rng = np.random.default_rng(12)
     for s in (1, 3, 7, 16):
-        for trans, rows in ((False, 1500), (True, 1100)):
+        for trans, rows in ((False, 15000), (True, 11000)):
             X = _t(_cg(rng, rows, s))
             H.set_fusion(True)
             a = H.apply(X, trans=trans)
