@@ -581,19 +581,33 @@ def apply_roofline(bf, F, n, reps=20, sizes=(1, 4, 16, 64)):
     sides: algorithmic bytes (8 per factor entry + 8 per input and output
     value) over the device time of an apply, against the HBM peak.  The device
     time is one pair of HIP events on the apply's stream around `reps`
-    back-to-back applies (events around every launch would add a few
-    microseconds each, the launches being only a few microseconds long); the
-    sum of per-launch event times is reported beside it, and the host wall
-    time per apply launched directly and as one captured HIP graph."""
+    back-to-back applies, queued while a spin kernel holds the stream so that
+    the host's launch cost does not leave the device idle between them (events
+    around every launch would add a few microseconds each, the launches being
+    only a few microseconds long); the sum of per-launch event times is
+    reported beside it, and the host wall time per apply launched directly and
+    as one captured HIP graph."""
     import torch
     out = {}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    # spin-kernel cycles per millisecond on this device
+    torch.cuda._sleep(1000)
+    e0.record()
+    torch.cuda._sleep(20_000_000)
+    e1.record()
+    torch.cuda.synchronize()
+    cyc_per_ms = 20_000_000 / max(e0.elapsed_time(e1), 1e-3)
     for s in sizes:
         X = torch.randn(n, s, dtype=torch.complex64, device="cuda")
         Y = F.apply(X)
         F.apply(X, out=Y)
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        F.apply(X, out=Y)
+        torch.cuda.synchronize()
+        host_ms = (time.perf_counter() - t0) * 1e3
+        torch.cuda._sleep(int(cyc_per_ms * (2.0 * reps * host_ms + 2.0)))
         e0.record()
         for _ in range(reps):
             F.apply(X, out=Y)

@@ -42,19 +42,14 @@ constexpr int AP_SMALL = kApplyFewCols;
 // issue together.  With one or two columns each lane loads two consecutive
 // entries per 16-byte load.  At n = 262144, one column: 1.31 ms with 16 lanes
 // and 8-byte loads, 1.06 ms with pairs, 0.84 ms with pairs on 8 lanes (FP64
-// sums); four columns 1.88 -> 1.52 ms on 8 lanes.  Acc is cf (FP32 sums)
-// or cd (FP64 sums of the FP32 products, used by the default mode for a
-// single right-hand side, where the extra registers cost no time: a stage
-// then rounds essentially once, at its complex64 output).
+// sums); four columns 1.88 -> 1.52 ms on 8 lanes.  Sums are FP32 (Acc = cf):
+// FP64 sums of the FP32 products, once the default for one column, held a
+// stage at 3.6-3.9 TB/s where FP32 sums reach 5.3 (the block kernel below).
 template <typename Acc>
 __device__ __forceinline__ void acc_fma(Acc& a, bf_c64 g, bf_c64 x);
 template <>
 __device__ __forceinline__ void acc_fma<cf>(cf& a, bf_c64 g, bf_c64 x) {
   cf_fma(a, cf{g.re, g.im}, cf{x.re, x.im});
-}
-template <>
-__device__ __forceinline__ void acc_fma<cd>(cd& a, bf_c64 g, bf_c64 x) {
-  cd_fma(a, cd{(double)g.re, (double)g.im}, cd{(double)x.re, (double)x.im});
 }
 
 typedef float f32x4u __attribute__((ext_vector_type(4)));
@@ -154,6 +149,120 @@ __global__ __launch_bounds__(256) void apply_stream_kernel(const ApplyRowRec* __
 #pragma unroll
     for (int c = 0; c < NC; ++c)
       if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
+  }
+}
+
+// Slot j of lane q in a row of the few-column kernels: pairs 2q, 2q + 1 in
+// steps of 16 for one or two columns, q in steps of 8 otherwise -- the order
+// of apply_stream_kernel, which every few-column path keeps so that all of
+// them sum a row's terms in the same order.
+template <int NC>
+__device__ __forceinline__ int fused_k(int q, int j) {
+  if constexpr (NC <= 2)
+    return 2 * q + (j & 1) + 16 * (j >> 1);
+  else
+    return q + 8 * j;
+}
+
+// ncols <= 4 on stages whose rows have at most 32 * IT terms: one wave per
+// block, no row records.  The wave reads its block's descriptor once; each
+// lane holds the inputs of its slots (the same slots in every row of the
+// block) in registers and streams the factor rows RG groups of 8 rows at a
+// time.  Slots and summation order are apply_stream_kernel's, so both give
+// the same bits.  Dropping the 48-byte records and the per-row input loads
+// took one 200 MB stage of the n = 262144 FIO butterfly from 4.2-4.5 to
+// 5.3-5.4 TB/s of factor bytes in a stand-alone probe that kept the factors
+// out of the last-level cache (a read-only sum of the same bytes: 6.0 TB/s).
+template <int NC, int IT, int RG>
+__global__ __launch_bounds__(256) void apply_blockrows_kernel(const ApplyBlk* __restrict__ blks,
+                                                              int32_t nblk,
+                                                              const bf_c64* __restrict__ G,
+                                                              ApplyBufs B, int32_t ncols) {
+  const int b = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (b >= nblk) return;
+  const int lane = threadIdx.x & 63, q = lane & (AP_LPR - 1), rs = lane / AP_LPR;
+  const ApplyBlk bk = blks[b];
+  const int KK = bk.K0 + bk.K1, K0 = bk.K0;
+  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0;
+  const bf_c64* in1 = B.p[bk.in_buf1] + bk.in_row1 - K0;
+  const int64_t ld0 = B.ld[bk.in_buf0], ld1 = B.ld[bk.in_buf1];
+  constexpr int S = 4 * IT;   // slots per lane
+  bf_c64 xv[S][NC];
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const int k = fused_k<NC>(q, j);
+    if constexpr (NC <= 2) {
+      if (j & 1) continue;   // pairs: slot j + 1 is entry k + 1
+      const bool k0v = k < KK, k1v = k + 1 < KK;
+      const bool seg0 = k < K0, seg1 = k + 1 < K0;
+      const bf_c64* base = seg0 ? in0 : in1;
+      const int64_t ldk = seg0 ? ld0 : ld1;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (c < ncols && k1v && seg0 == seg1) {
+          load_pair(base + k + (int64_t)c * ldk, xv[j][c], xv[j + 1][c]);
+        } else {
+          xv[j][c] = (c < ncols && k0v) ? base[k + (int64_t)c * ldk] : bf_c64{0.f, 0.f};
+          xv[j + 1][c] = (c < ncols && k1v)
+                             ? (seg1 ? in0 : in1)[k + 1 + (int64_t)c * (seg1 ? ld0 : ld1)]
+                             : bf_c64{0.f, 0.f};
+        }
+      }
+    } else {
+      const bool kv = k < KK;
+      const bf_c64* inp = k < K0 ? in0 + k : in1 + k;
+      const int64_t ldk = k < K0 ? ld0 : ld1;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        xv[j][c] = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
+    }
+  }
+  bf_c64* out = B.p[bk.out_buf] + bk.out_row;
+  const int64_t ldo = B.ld[bk.out_buf];
+  for (int r0 = 0; r0 < bk.M; r0 += AP_LPR * RG) {
+    bf_c64 gv[RG][S];
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+      const int r = r0 + AP_LPR * i + rs;
+      const bf_c64* g = G + bk.g_off + (int64_t)r * KK;
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const int k = fused_k<NC>(q, j);
+        if constexpr (NC <= 2) {
+          if (j & 1) continue;
+          const bool k0v = r < bk.M && k < KK, k1v = r < bk.M && k + 1 < KK;
+          if (k1v) {
+            load_pair(g + k, gv[i][j], gv[i][j + 1]);
+          } else {
+            gv[i][j] = k0v ? g[k] : bf_c64{0.f, 0.f};
+            gv[i][j + 1] = bf_c64{0.f, 0.f};
+          }
+        } else {
+          gv[i][j] = (r < bk.M && k < KK) ? g[k] : bf_c64{0.f, 0.f};
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+      cf acc[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = cf{0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < S; ++j)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[i][j], xv[j][c]);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        acc[c].re = row8_sum(acc[c].re);
+        acc[c].im = row8_sum(acc[c].im);
+      }
+      const int r = r0 + AP_LPR * i + rs;
+      if (q == 0 && r < bk.M) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (c < ncols) out[r + (int64_t)c * ldo] = bf_c64{acc[c].re, acc[c].im};
+      }
+    }
   }
 }
 
@@ -542,17 +651,6 @@ __device__ __forceinline__ void fused_row(const ApplyRowRec& rr, int q, const bf
   }
 }
 
-// Inner index of slot j of lane q in a row: the few-column kernel's order
-// (pairs 2q, 2q + 1 in steps of 16 for one or two columns, q in steps of 8
-// otherwise), so that every path sums a row's terms in the same order.
-template <int NC>
-__device__ __forceinline__ int fused_k(int q, int j) {
-  if constexpr (NC <= 2)
-    return 2 * q + (j & 1) + 16 * (j >> 1);
-  else
-    return q + 8 * j;
-}
-
 constexpr int AF_PF = 8;   // factor entries per lane fetched ahead (rows of up to 64 terms)
 
 __device__ __forceinline__ void fused_fetch_g(const ApplyRowRec& rr, bool has, int q,
@@ -828,11 +926,9 @@ void launch_apply_fused(const ApplyRowRec* rows_dev, const int32_t* off_dev, int
   }
   const int nc = (int)ncols;
   const dim3 grid((unsigned)nwg);
+  (void)prec;
   if (nc == 1) {
-    if (prec == BF_PREC_FP32)
-      launch_fused_nc<cf, 1>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
-    else
-      launch_fused_nc<cd, 1>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
+    launch_fused_nc<cf, 1>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   } else if (nc == 2) {
     launch_fused_nc<cf, 2>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   } else if (nc <= 4) {
@@ -880,7 +976,7 @@ void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* row
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
                         int32_t nrows, int32_t maxMK, int32_t maxKK, int32_t maxM, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], const int64_t rss[4],
-                        int64_t ncols, int prec, hipStream_t s) {
+                        int64_t ncols, int prec, hipStream_t s, bool may_time) {
   if (nblk <= 0 || ncols <= 0) return;
   ApplyBufs B;
   for (int i = 0; i < 4; ++i) {
@@ -891,17 +987,44 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
   if (ncols <= AP_SMALL) {
     // the row records address column-major buffers
     for (int i = 0; i < 4; ++i) BF_CHECK(rss[i] == 1, BF_EINVAL, "few-column apply needs column-major buffers");
-    const dim3 grid((unsigned)((nrows + 256 / AP_LPR - 1) / (256 / AP_LPR)));
     const int nc = (int)ncols;
-#define AP_STREAM(ACC, N) \
-    hipLaunchKernelGGL((apply_stream_kernel<ACC, N>), grid, dim3(256), 0, s, rows_dev, nrows, G, B, nc)
-    if (prec == BF_PREC_FP32) {
-      if (nc == 1) AP_STREAM(cf, 1); else if (nc == 2) AP_STREAM(cf, 2); else AP_STREAM(cf, 4);
+    const int ncl = nc == 1 ? 1 : (nc == 2 ? 2 : 4);
+    auto rec = [&] {
+      const dim3 grid((unsigned)((nrows + 256 / AP_LPR - 1) / (256 / AP_LPR)));
+      if (ncl == 1)
+        hipLaunchKernelGGL((apply_stream_kernel<cf, 1>), grid, dim3(256), 0, s, rows_dev, nrows, G, B, nc);
+      else if (ncl == 2)
+        hipLaunchKernelGGL((apply_stream_kernel<cf, 2>), grid, dim3(256), 0, s, rows_dev, nrows, G, B, nc);
+      else
+        hipLaunchKernelGGL((apply_stream_kernel<cf, 4>), grid, dim3(256), 0, s, rows_dev, nrows, G, B, nc);
+    };
+    // one wave per block while a block's rows fit 3 x 32 terms and 128 rows
+    // (a wave walks all of its block's rows); the record kernel otherwise
+    const int it = (maxKK + 31) / 32;
+    if (it < 1 || it > 3 || maxM > 128) {
+      rec();
     } else {
-      // FP64 sums cost nothing at one right-hand side and ~2x at four
-      if (nc == 1) AP_STREAM(cd, 1); else if (nc == 2) AP_STREAM(cf, 2); else AP_STREAM(cf, 4);
+      auto run = [&](int64_t c) {
+        if (!c) {
+          rec();
+          return;
+        }
+        const dim3 grid((unsigned)((nblk + 3) / 4));
+#define AP_BR(N, I, R) \
+  hipLaunchKernelGGL((apply_blockrows_kernel<N, I, R>), grid, dim3(256), 0, s, blks_dev, nblk, G, B, nc)
+        if (ncl == 1) {
+          if (it == 1) AP_BR(1, 1, 4); else if (it == 2) AP_BR(1, 2, 2); else AP_BR(1, 3, 1);
+        } else if (ncl == 2) {
+          if (it == 1) AP_BR(2, 1, 4); else if (it == 2) AP_BR(2, 2, 2); else AP_BR(2, 3, 1);
+        } else {
+          if (it == 1) AP_BR(4, 1, 2); else if (it == 2) AP_BR(4, 2, 1); else AP_BR(4, 3, 1);
+        }
+#undef AP_BR
+      };
+      // both kernels give the same bits: the autotuner picks per shape class
+      tune_choose(TuneKey{kTuneApplyRows, ncl, it, pow2_ceil(nblk), pow2_ceil(maxM), 0}, {1, 0}, 1,
+                  s, run, may_time);
     }
-#undef AP_STREAM
   } else if (prec == BF_PREC_BF16X3 && ncols >= AM_MIN_COLS) {
     const int64_t ych = (ncols + AP_CW - 1) / AP_CW;
     BF_CHECK(ych <= 65535, BF_EINVAL, "too many right-hand sides");

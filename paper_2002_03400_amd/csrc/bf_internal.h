@@ -321,12 +321,12 @@ constexpr int kApplyFusedCols = 16;
 void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRec* rows_dev,
                         int32_t nrows, int32_t maxMK, int32_t maxKK, int32_t maxM, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], const int64_t rss[4],
-                        int64_t ncols, int prec, hipStream_t s);
+                        int64_t ncols, int prec, hipStream_t s, bool may_time = true);
 
 // Fused stages: workgroup w runs the row records [off[w*(nstage+1)+t],
 // off[w*(nstage+1)+t+1]) of stage t for t = 0..nstage-1, with a barrier
 // between stages; buffers column-major (element (r, c) at bufs[i][r + c*lds[i]]).
-// ncols <= kApplyFusedCols; FP64 sums for one column unless prec is FP32.
+// ncols <= kApplyFusedCols; FP32 sums whatever prec.
 // max_rows: the most rows one workgroup has in one stage (sizes the workgroup).
 void launch_apply_fused(const ApplyRowRec* rows_dev, const int32_t* off_dev, int32_t nwg,
                         int32_t nstage, int32_t max_rows, const bf_c64* G,
@@ -368,7 +368,7 @@ void launch_expand_segments(const bf_c64* X, int64_t ldx, int64_t rows, int64_t 
 // false (callers that must not create events).  Candidates must give bitwise
 // the same results.
 enum { kTuneMatfreeWidth = 0, kTuneChainRows = 1, kTuneCpqrThreads = 2, kTuneApplyFused = 3,
-       kTuneFamilies = 4 };
+       kTuneApplyRows = 4, kTuneFamilies = 5 };
 constexpr int kTuneKeyFields = 5;
 using TuneKey = std::array<int64_t, 1 + kTuneKeyFields>;
 int64_t pow2_ceil(int64_t v);

@@ -503,7 +503,7 @@ static void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, in
     auto launch = [&] {
       launch_apply_stage(P.blks.p + st.blk_off, st.nblk, P.rows.p + st.row_off, st.nrows,
                          st.maxMK, st.maxKK, st.maxM, P.G.p, bufs, lds, rss, ncols,
-                         F->apply_prec, s);
+                         F->apply_prec, s, prof);
     };
     if (prof) {
       ProfScope ps(BF_KC_APPLY, s, 8.0 * st.macs * ncols, by);

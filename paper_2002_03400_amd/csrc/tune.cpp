@@ -34,7 +34,7 @@ std::map<TuneKey, std::vector<std::pair<int64_t, float>>> g_times;   // measured
 std::once_flag g_load_once;
 
 const char* kFamily[kTuneFamilies] = {"matfree_width", "chain_rows", "cpqr_threads",
-                                      "apply_fused"};
+                                      "apply_fused", "apply_rows"};
 
 std::string default_path() {
   if (const char* e = std::getenv("BF_TUNE_FILE")) return e;
@@ -116,16 +116,24 @@ int64_t tune_choose(const TuneKey& key, const std::vector<int64_t>& cand, int64_
     return fallback;
   }
   load_default();
+  // look the class up under the lock, run outside it: a candidate may itself
+  // launch tuned kernels (a staged apply's stages)
+  int64_t known = 0;
+  bool found = false;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_table.find(key);
     if (it != g_table.end()) {
       for (int64_t c : cand)
         if (c == it->second) {
-          run(c);
-          return c;
+          known = c;
+          found = true;
         }
     }
+  }
+  if (found) {
+    run(known);
+    return known;
   }
   if (!may_time || capturing(s)) {
     run(fallback);

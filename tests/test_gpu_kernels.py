@@ -1,6 +1,7 @@
 """GPU parity of the batched building blocks against the oracle (through the
 C ABI).  Each test prints the case it runs before touching the device."""
 import math
+import os
 import sys
 
 import numpy as np
@@ -203,7 +204,7 @@ def test_autotuned_tile_widths_do_not_change_products(bf):
 
 # candidates of each tuned family (include/bf.h, bf_set_autotune)
 TUNE_CANDIDATES = {"matfree_width": [48, 64, 80], "chain_rows": [8, 16, 20, 24, 32, 64],
-                   "cpqr_threads": [256, 512], "apply_fused": [1, 0]}
+                   "cpqr_threads": [256, 512], "apply_fused": [1, 0], "apply_rows": [1, 0]}
 
 
 def _tune_rows(path):
@@ -281,6 +282,64 @@ def test_every_autotuner_candidate_gives_the_same_bits(bf, tmp_path):
     finally:
         bf.set_autotune(True)
         E.close()
+
+
+@pytest.mark.parametrize("L,r,leaf", [(10, 8, 8), (9, 20, 24), (8, 40, 40)])
+def test_block_and_record_kernels_give_the_same_bits(bf, tmp_path, L, r, leaf):
+    """Stage-by-stage applies of 1 to 4 columns: the one-wave-per-block kernel
+    (inputs held in registers, rows of up to 32, 64 or 96 terms -- here 16,
+    40 and 80) and the row-record kernel, each forced through the autotuner's
+    table, give the same bits, forward and adjoint; both are within 2e-6 of
+    the oracle's FP64 apply in every column."""
+    import torch
+    n = leaf << L
+    kU, kV, data = wl.exact_butterfly_canonical(L, r, seed=L + r, leaf=leaf)
+    F = canonical_to_oracle(n, n, L, kU, kV, data)
+    H = bf.import_factors(n, n, leaf, kU, kV, data)
+    H.set_fusion(False)
+    say("block vs record kernel", L, r, leaf)
+    rng = np.random.default_rng(L)
+    cases = [(s, _cg(rng, n, s)) for s in (1, 2, 3, 4)]
+    path = str(tmp_path / "tune.tsv")
+    try:
+        bf.set_autotune(True)
+        bf.autotune_clear()
+        got = {}
+        for choice in (None, 1, 0):
+            if choice is not None:
+                rows = _tune_rows(path)
+                assert any(fam == "apply_rows" for fam, _, _ in rows)
+                with open(path, "w") as f:
+                    for fam, fields, c in rows:
+                        f.write(" ".join([fam] + [str(x) for x in fields] +
+                                         [str(choice if fam == "apply_rows" else c)]) + "\n")
+                bf.autotune_clear()
+                bf.autotune_load(path)
+            out = []
+            for s, X in cases:
+                for trans in (False, True):
+                    out.append(np.ascontiguousarray(H.apply(_t(X), trans=trans).cpu().numpy()))
+            torch.cuda.synchronize()
+            if choice is None:
+                bf.autotune_save(path)
+            got[choice] = out
+        for a, b, c in zip(got[None], got[1], got[0]):
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+            assert np.array_equal(a.view(np.uint64), c.view(np.uint64))
+        i = 0
+        for s, X in cases:
+            for ref in (obf.apply(F, X), obf.apply_adjoint(F, X)):
+                y = got[1][i]
+                i += 1
+                for col in range(s):
+                    assert np.linalg.norm(y[:, col] - ref[:, col]) <= 2e-6 * np.linalg.norm(ref[:, col])
+    finally:
+        bf.autotune_clear()
+        saved = os.path.join(os.path.dirname(bf.__file__), "tune_gfx950.tsv")
+        if os.path.exists(saved):   # the table saved beside the library
+            bf.autotune_load(saved)
+        bf.set_autotune(True)
+        H.close()
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
