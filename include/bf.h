@@ -199,7 +199,7 @@ int bf_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64
  * library holds on every device it runs on until the process ends.  A call is
  * accepted when the stage-by-stage apply's two ping-pong intermediates fit
  * (2 x (largest level rank sum) x ncols complex64 values); it then runs like
- * bf_apply (fused stages for up to 16 columns when their larger intermediate
+ * bf_apply (fused stages for up to 4 columns when their larger intermediate
  * also fits, else stage by stage).  Larger requests return BF_EINVAL
  * (nothing is launched).  Every call on a device uses that
  * device's one array: calls that overlap on one GPU (other streams, other
@@ -221,11 +221,13 @@ int64_t bf_apply_noalloc_scratch_bytes(void);
  * Same kernels, same results.  Not to be called while applies of F run. */
 int bf_set_apply_graph_cols(bf_factors* F, int64_t max_cols);
 
-/* Applies of 1 to 16 columns run fused: consecutive stages share one launch,
- * each workgroup taking a group of blocks that depend only on each other
- * (about 4 launches instead of L + 3 at L = 10).  enable = 0 runs every
- * stage as its own launch (the path used above 16 columns).  Default 1.  Not
- * synchronized with applies in flight on F. */
+/* Applies of 1 to 4 columns may run fused: consecutive stages share one
+ * launch, each workgroup taking a group of blocks that depend only on each
+ * other (about 4 launches instead of L + 3 at L = 10; planned only where a
+ * launch keeps at least 256 groups and its stages are small enough to be
+ * bound by latency; the autotuner then picks fused or staged, same bits).
+ * enable = 0 runs every stage as its own launch (the path used above 4
+ * columns).  Default 1.  Not synchronized with applies in flight on F. */
 int bf_set_apply_fusion(bf_factors* F, int enable);
 
 /* Summary of a factorization. */
@@ -509,9 +511,20 @@ int bf_op_set_precision(bf_operator* op, int precision);
  *                           block's rows and columns and the block count);
  *   few-column apply      : fused stages or one launch per stage, 1 to 4
  *                           columns (class: direction, columns, powers of two
- *                           above m and n, L, apply precision).
+ *                           above m and n, L, apply precision);
+ *   few-column stage      : one wave per block with its inputs in registers
+ *                           or one 8-lane group per row record, stages whose
+ *                           rows have at most 96 terms and blocks at most 128
+ *                           rows (class: columns, 32-term chunks per row,
+ *                           powers of two above the block count and rows);
+ *   matrix-core stage     : one workgroup per block and 64 columns, or one
+ *                           wave per block and 1, 2, 4 ... or all of its
+ *                           16-column tiles, blocks of 17 to 64 rows (class:
+ *                           power of two above the column count, 16-row tiles,
+ *                           powers of two above the block count and terms).
  * Without the tuner every family uses its rule (80-column tiles, the
- * smallest tile height, 256 threads, fused applies).  The table is
+ * smallest tile height, 256 threads, fused applies, one wave per block; for
+ * matrix-core stages all tiles per wave from 4096 blocks, else one).  The table is
  * process-wide; the first lookup loads the file named by the environment
  * variable BF_TUNE_FILE or, if unset, tune_gfx950.tsv beside libbf.so (when
  * present).  bf_autotune_save writes the table (path NULL or "": that same
@@ -531,7 +544,7 @@ int bf_autotune_clear(void);
  *                    three BF16 terms (products kept to 2^-24 relative),
  *                    FP32 sums rounded once per 32-term matrix instruction
  *                    (faster than FP32 and about twice as accurate); 1 to 4
- *                    on the vector ALUs, with FP64 sums for a single one.
+ *                    on the vector ALUs with FP32 sums, as in BF_PREC_FP32.
  * Not synchronized with applies in flight on F: set it before applying.
  * Returns BF_EINVAL for a null F or another value. */
 int bf_set_apply_precision(bf_factors* F, int precision);

@@ -444,14 +444,14 @@ class Factors:
     def set_precision(self, precision):
         """Arithmetic of apply and of the factors as a black box: 'bf16x3' (BF16
         matrix cores for >= 5 right-hand sides, operands split into three BF16
-        terms; vector ALUs below, FP64 sums for one; default) or 'fp32' (vector
+        terms; vector ALUs with FP32 sums below; default) or 'fp32' (vector
         ALUs, FP32)."""
         code = {"fp32": 2, "bf16x3": 1}[precision]
         _check(lib().bf_set_apply_precision(self._h, code), "bf_set_apply_precision")
         return self
 
     def set_fusion(self, enable):
-        """Fused stages for applies of 1 to 16 columns (default True)."""
+        """Fused stages for applies of 1 to 4 columns (default True)."""
         _check(lib().bf_set_apply_fusion(self._h, int(bool(enable))), "bf_set_apply_fusion")
         return self
 

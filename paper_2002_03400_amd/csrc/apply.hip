@@ -556,6 +556,91 @@ __global__ __launch_bounds__(256) void apply_mfma_small_kernel(const ApplyBlk* _
   }
 }
 
+// Blocks of up to 64 rows: one wave per block and ctw 16-column tiles, the
+// tiles one after another (stages of few blocks take one tile per wave, so
+// that the device fills; stages of many blocks all tiles per wave, so that a
+// block's factor rows are read from memory once and from the cache for its
+// further tiles).  Per tile and 32-term chunk the wave loads and splits its
+// B operands once, then each 16-row tile's A operands straight from the
+// factor rows, and runs the 24 MFMAs of that row tile: the operands, products
+// and their order are apply_mfma_kernel's (same bits) without its LDS passes
+// and barriers.
+__global__ __launch_bounds__(256) void apply_mfma_wave_kernel(const ApplyBlk* __restrict__ blks,
+                                                              int32_t nblk,
+                                                              const bf_c64* __restrict__ G,
+                                                              ApplyBufs B, int64_t ncols,
+                                                              int32_t ctw) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t bi = (int64_t)blockIdx.x * 4 + wave;
+  if (bi >= nblk) return;
+  const ApplyBlk bk = blks[bi];
+  const int M = bk.M, K0 = bk.K0, KK = bk.K0 + bk.K1;
+  const int lc = lane & 15, kq = lane >> 4;
+  const int rt_n = (M + 15) >> 4;   // at most 4
+  const bf_c64* gb = G + bk.g_off;
+  const int64_t rs0 = B.rs[bk.in_buf0], rs1 = B.rs[bk.in_buf1];
+  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0 * rs0;
+  const bf_c64* in1 = B.p[bk.in_buf1] + (bk.in_row1 - K0) * rs1;   // indexed by k >= K0
+  const int64_t ld0 = B.ld[bk.in_buf0], ld1 = B.ld[bk.in_buf1];
+  const int64_t rso = B.rs[bk.out_buf], ldo = B.ld[bk.out_buf];
+  bf_c64* ob = B.p[bk.out_buf] + bk.out_row * rso;
+  // column tiles [blockIdx.y * ctw, (blockIdx.y + 1) * ctw) of this block
+  const int64_t cbeg = (int64_t)blockIdx.y * ctw * 16;
+  const int64_t cend = cbeg + (int64_t)ctw * 16 < ncols ? cbeg + (int64_t)ctw * 16 : ncols;
+  for (int64_t c0 = cbeg; c0 < cend; c0 += 16) {
+    const int64_t col = c0 + lc;
+    const bool cv = col < ncols;
+    afloatx4 R[4], I[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) { R[t] = afloatx4{0.f, 0.f, 0.f, 0.f}; I[t] = R[t]; }
+    for (int k0 = 0; k0 < KK; k0 += AM_KT) {
+      const int kb = k0 + 8 * kq;
+      bf_c64 v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kb + e;
+        bf_c64 x = {0.f, 0.f};
+        if (cv && k < KK) x = k < K0 ? in0[col * ld0 + k * rs0] : in1[col * ld1 + k * rs1];
+        v[e] = x;
+      }
+      au32x4 xb[6];
+      am_split8(v, xb);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < rt_n) {
+          const int r = t * 16 + lc;
+          const bf_c64* grow = gb + (int64_t)r * KK;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            v[e] = (r < M && kb + e < KK) ? grow[kb + e] : bf_c64{0.f, 0.f};
+          au32x4 ga[6], gn[3];
+          am_split8(v, ga);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) gn[q] = ga[2 * q + 1] ^ 0x80008000u;
+#define AM_MM(A, Bv, C) \
+  C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(abf16x8, A), \
+                                              __builtin_bit_cast(abf16x8, Bv), C, 0, 0, 0);
+#define AM_PAIR(P, Q) AM_MM(ga[2 * P], xb[2 * Q], R[t]) AM_MM(gn[P], xb[2 * Q + 1], R[t]) \
+                      AM_MM(ga[2 * P], xb[2 * Q + 1], I[t]) AM_MM(ga[2 * P + 1], xb[2 * Q], I[t])
+          AM_PAIR(2, 0) AM_PAIR(0, 2) AM_PAIR(1, 1) AM_PAIR(1, 0) AM_PAIR(0, 1) AM_PAIR(0, 0)
+#undef AM_PAIR
+#undef AM_MM
+        }
+      }
+    }
+    // 16x16 tile layout: lane l, register v -> row 4 (l / 16) + v, column l % 16
+    if (cv) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = t * 16 + 4 * kq + v;
+          if (t < rt_n && r < M) ob[col * ldo + r * rso] = bf_c64{R[t][v], I[t][v]};
+        }
+    }
+  }
+}
+
 // ---- fused stages (few right-hand sides) ---------------------------------
 //
 // One launch runs several consecutive stages.  The blocks of those stages
@@ -563,9 +648,9 @@ __global__ __launch_bounds__(256) void apply_mfma_small_kernel(const ApplyBlk* _
 // produced inside its group, or come from the launch's input buffer), and
 // workgroup w runs group w stage after stage, with a barrier between stages:
 // an apply of 13 stages becomes 4 launches instead of 13 dependent ones.
-// Rows follow the few-column kernel above (8 lanes per output row, same
-// summation order, so 1, 2 and 4 columns give its results bit for bit); 8 and
-// 16 columns take one or two entries per lane and step.  Intermediates of a
+// Rows follow the few-column kernels above (8 lanes per output row, same
+// slots and summation order, so 1 to 4 columns give their results bit for
+// bit).  Intermediates of a
 // launch are written to global memory and read back by the same workgroup
 // after the barrier (each stage writes its own rows, so workgroups never
 // overwrite what another still reads).
@@ -615,9 +700,8 @@ __device__ __forceinline__ void fused_row(const ApplyRowRec& rr, int q, const bf
         for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[u], xv[u][c]);
     }
   } else {
-    // one entry per lane and load; U entries per lane and step keep the
-    // registers of the loaded inputs near 32 whatever the column count
-    constexpr int U = NC >= 16 ? 1 : (NC >= 8 ? 2 : 4);
+    // one entry per lane and load, 4 per lane and step
+    constexpr int U = 4;
     for (int kb = 0; kb < KK; kb += U * AP_LPR) {
       bf_c64 gv[U], xv[U][NC];
 #pragma unroll
@@ -816,14 +900,6 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
   const int rl = threadIdx.x / AP_LPR;
   constexpr int RS = NT / AP_LPR;   // rows per pass
   const int32_t* o = off + (int64_t)blockIdx.x * (nstage + 1);
-  if constexpr (NC > 8) {
-    // 16 columns: their inputs and sums fill the registers; no fetching ahead
-    for (int t = 0; t < nstage; ++t) {
-      for (int32_t R = o[t] + rl; R < o[t + 1]; R += RS) fused_row<Acc, NC>(rows[R], q, G, B, ncols);
-      if (t + 1 < nstage) __syncthreads();
-    }
-    return;
-  }
   constexpr int small = NC <= 2;
   auto fetch_rec = [&](int t, int i, ApplyRowRec& r) -> bool {
     const int32_t R = o[t] + rl + i * RS;
@@ -844,14 +920,11 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
   for (int t = 0; t < nstage; ++t) {
     // inputs of the first row first, then the next stages' fetches, then the
     // arithmetic: the first row waits for its inputs only
-    constexpr int NCI = NC <= 4 ? NC : 1;
     constexpr int RI = NC == 1 ? RPT : 1;   // rows whose inputs go first
-    bf_c64 xv0[RI][AF_PF][NCI];
-    if constexpr (NC <= 4) {
+    bf_c64 xv0[RI][AF_PF][NC];
 #pragma unroll
-      for (int i = 0; i < RI; ++i)
-        if (hc[i]) fused_in_load<NC>(rc[i], q, B, ncols, xv0[i]);
-    }
+    for (int i = 0; i < RI; ++i)
+      if (hc[i]) fused_in_load<NC>(rc[i], q, B, ncols, xv0[i]);
     __builtin_amdgcn_sched_barrier(0);
     ApplyRowRec r2[RPT];
     bool h2[RPT];
@@ -864,13 +937,10 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       if (!hc[i]) continue;
-      if constexpr (NC <= 4) {
-        if (i < RI) {
-          fused_row_fin<Acc, NC>(rc[i], gc[i], xv0[i < RI ? i : 0], q, G, B, ncols);
-          continue;
-        }
-      }
-      fused_row_pre<Acc, NC>(rc[i], gc[i], q, G, B, ncols);
+      if (i < RI)
+        fused_row_fin<Acc, NC>(rc[i], gc[i], xv0[i < RI ? i : 0], q, G, B, ncols);
+      else
+        fused_row_pre<Acc, NC>(rc[i], gc[i], q, G, B, ncols);
     }
     for (int32_t R = o[t] + rl + RPT * RS; R < o[t + 1]; R += RS)
       fused_row<Acc, NC>(rows[R], q, G, B, ncols);
@@ -890,18 +960,14 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
 // Workgroup shape of a fused launch: 8 threads per row and a stage's rows in
 // one pass of up to 128 rows -- 256 threads with one row each for up to 32
 // rows, else 512 threads with two rows each fetched ahead for one column
-// (one row each for 2 to 8 columns, whose inputs need the registers; 16
-// columns fetch nothing ahead and take 1024 threads); larger stages take
-// further passes.
+// (one row each for 2 to 4 columns, whose inputs need the registers); larger
+// stages take further passes.
 template <typename Acc, int NC>
 static void launch_fused_nc(dim3 grid, int32_t max_rows, hipStream_t s,
                             const ApplyRowRec* rows_dev, const int32_t* off_dev, int32_t nstage,
                             const bf_c64* G, const ApplyBufs& B, int nc) {
   if (max_rows <= 32) {
     hipLaunchKernelGGL((apply_fused_kernel<Acc, NC, 256, 1>), grid, dim3(256), 0, s, rows_dev,
-                       off_dev, nstage, G, B, nc);
-  } else if constexpr (NC > 8) {
-    hipLaunchKernelGGL((apply_fused_kernel<Acc, NC, 1024, 1>), grid, dim3(1024), 0, s, rows_dev,
                        off_dev, nstage, G, B, nc);
   } else if constexpr (NC >= 2) {
     hipLaunchKernelGGL((apply_fused_kernel<Acc, NC, 512, 1>), grid, dim3(512), 0, s, rows_dev,
@@ -931,12 +997,8 @@ void launch_apply_fused(const ApplyRowRec* rows_dev, const int32_t* off_dev, int
     launch_fused_nc<cf, 1>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   } else if (nc == 2) {
     launch_fused_nc<cf, 2>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
-  } else if (nc <= 4) {
-    launch_fused_nc<cf, 4>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
-  } else if (nc <= 8) {
-    launch_fused_nc<cf, 8>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   } else {
-    launch_fused_nc<cf, 16>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
+    launch_fused_nc<cf, 4>(grid, max_rows, s, rows_dev, off_dev, nstage, G, B, nc);
   }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs == hipStreamCaptureStatusNone)
@@ -1028,12 +1090,39 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
   } else if (prec == BF_PREC_BF16X3 && ncols >= AM_MIN_COLS) {
     const int64_t ych = (ncols + AP_CW - 1) / AP_CW;
     BF_CHECK(ych <= 65535, BF_EINVAL, "too many right-hand sides");
-    if (maxM <= 16)
-      hipLaunchKernelGGL(apply_mfma_small_kernel, dim3((unsigned)((nblk + 3) / 4), (unsigned)ych),
-                         dim3(256), 0, s, blks_dev, nblk, G, B, ncols);
-    else
+    auto wg = [&] {
       hipLaunchKernelGGL(apply_mfma_kernel, dim3((unsigned)nblk, (unsigned)ych), dim3(256), 0, s,
                          blks_dev, G, B, ncols);
+    };
+    if (maxM <= 16) {
+      hipLaunchKernelGGL(apply_mfma_small_kernel, dim3((unsigned)((nblk + 3) / 4), (unsigned)ych),
+                         dim3(256), 0, s, blks_dev, nblk, G, B, ncols);
+    } else if (maxM <= 64) {
+      // one workgroup per block (0) or one wave per block and c column tiles
+      // (c = 1, 2, 4, ..., all): same bits, tuned per class; the rule
+      // without the tuner fills the device with one tile per wave when the
+      // stage has few blocks
+      const int64_t nct = (ncols + 15) / 16;
+      std::vector<int64_t> cand;
+      for (int64_t c = 1; c < nct; c *= 2) cand.push_back(c);
+      cand.push_back(nct);
+      cand.push_back(0);
+      auto run = [&](int64_t c) {
+        if (c) {
+          const int64_t gy = (nct + c - 1) / c;
+          BF_CHECK(gy <= 65535, BF_EINVAL, "too many right-hand sides");
+          hipLaunchKernelGGL(apply_mfma_wave_kernel, dim3((unsigned)((nblk + 3) / 4), (unsigned)gy),
+                             dim3(256), 0, s, blks_dev, nblk, G, B, ncols, (int32_t)c);
+        } else {
+          wg();
+        }
+      };
+      tune_choose(TuneKey{kTuneApplyMfma, pow2_ceil(ncols), (maxM + 15) / 16, pow2_ceil(nblk),
+                          pow2_ceil(maxKK), 0},
+                  cand, nblk >= 4096 ? nct : 1, s, run, may_time);
+    } else {
+      wg();
+    }
   } else {
     const size_t lds_b = sizeof(cf) * ((size_t)maxMK + (size_t)maxKK * AP_CW);
     BF_CHECK(lds_b <= AP_LDS_LIMIT, BF_ERANK, "apply block too large for LDS");

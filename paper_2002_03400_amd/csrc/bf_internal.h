@@ -312,7 +312,7 @@ void launch_expand_rows(const ApplyBlk* blks_dev, int32_t nblk, ApplyRowRec* row
 constexpr int kApplyFewCols = 4;
 // Up to this many right-hand sides an apply runs its stages fused (several
 // stages per launch, launch_apply_fused), column-major throughout.
-constexpr int kApplyFusedCols = 16;
+constexpr int kApplyFusedCols = kApplyFewCols;
 // maxMK / maxKK / maxM: largest M*(K0+K1), K0+K1 and M over the stage's
 // blocks.  Buffer i holds element (r, c) at bufs[i][r * rss[i] + c * lds[i]]
 // (column-major: rss = 1; with at most kApplyFewCols columns every buffer must be).
@@ -368,7 +368,7 @@ void launch_expand_segments(const bf_c64* X, int64_t ldx, int64_t rows, int64_t 
 // false (callers that must not create events).  Candidates must give bitwise
 // the same results.
 enum { kTuneMatfreeWidth = 0, kTuneChainRows = 1, kTuneCpqrThreads = 2, kTuneApplyFused = 3,
-       kTuneApplyRows = 4, kTuneFamilies = 5 };
+       kTuneApplyRows = 4, kTuneApplyMfma = 5, kTuneFamilies = 6 };
 constexpr int kTuneKeyFields = 5;
 using TuneKey = std::array<int64_t, 1 + kTuneKeyFields>;
 int64_t pow2_ceil(int64_t v);

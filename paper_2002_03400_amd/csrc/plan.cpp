@@ -115,8 +115,9 @@ struct PlanBuilder {
 // event pair around whole applies: with fewer groups (n = 16384, 64 groups)
 // a workgroup's chain of dependent stages is slower than the stage kernels
 // at 2 to 16 columns (80 vs 99 us at 8 columns), with 256 groups (n = 65536)
-// faster at 1 and at 8 to 16 columns (57 vs 62 us at one column, 143 vs
-// 197 us at 8).
+// faster at one column (57 vs 62 us).  Above 4 columns the stage-by-stage
+// matrix-core apply is faster at every size measured (n = 65536, 16 columns:
+// 117 vs 189 us), so only applies of up to 4 columns fuse.
 constexpr int64_t kFusedMaxStageRows = 128;
 constexpr int64_t kFusedMinGroups = 256;
 // Stages with more factor bytes than this stream at HBM rate on their own

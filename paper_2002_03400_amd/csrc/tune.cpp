@@ -34,7 +34,7 @@ std::map<TuneKey, std::vector<std::pair<int64_t, float>>> g_times;   // measured
 std::once_flag g_load_once;
 
 const char* kFamily[kTuneFamilies] = {"matfree_width", "chain_rows", "cpqr_threads",
-                                      "apply_fused", "apply_rows"};
+                                      "apply_fused", "apply_rows", "apply_mfma"};
 
 std::string default_path() {
   if (const char* e = std::getenv("BF_TUNE_FILE")) return e;

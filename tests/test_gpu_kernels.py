@@ -204,7 +204,8 @@ def test_autotuned_tile_widths_do_not_change_products(bf):
 
 # candidates of each tuned family (include/bf.h, bf_set_autotune)
 TUNE_CANDIDATES = {"matfree_width": [48, 64, 80], "chain_rows": [8, 16, 20, 24, 32, 64],
-                   "cpqr_threads": [256, 512], "apply_fused": [1, 0], "apply_rows": [1, 0]}
+                   "cpqr_threads": [256, 512], "apply_fused": [1, 0], "apply_rows": [1, 0],
+                   "apply_mfma": [1, 2, 0]}
 
 
 def _tune_rows(path):
@@ -221,13 +222,16 @@ def _valid(fam, fields, c):
     if fam == "chain_rows":      # tile heights at least the launch's largest block
         m = fields[1]
         return c >= m if m <= 64 else c in (32, 64)
+    if fam == "apply_mfma":      # column tiles per wave, at most the apply's tiles
+        return c <= max(1, fields[0] // 16)
     return True
 
 
 def test_every_autotuner_candidate_gives_the_same_bits(bf, tmp_path):
     """Every family the tuner covers -- black-box column tile, chain tile
-    height, CPQR workgroup, fused or staged few-column apply -- and every one
-    of its candidates gives the bits of the untuned rule: the table is saved,
+    height, CPQR workgroup, fused or staged few-column apply, block or record
+    few-column kernel, wave or workgroup matrix-core apply -- and every one of
+    its candidates gives the bits of the untuned rule: the table is saved,
     rewritten with each candidate in turn for every class, loaded, and the
     construction and applies repeated against the untuned reference."""
     import torch
@@ -238,10 +242,15 @@ def test_every_autotuner_candidate_gives_the_same_bits(bf, tmp_path):
     kU, kV, data = wl.exact_butterfly_canonical(10, 8, seed=5, leaf=8)
     E = bf.import_factors(8192, 8192, 8, kU, kV, data)
     X = _t(_cg(np.random.default_rng(3), 8192, 3))
+    # 20 columns through the matrix-core stages of the constructed factors
+    # (blocks of 17 to 64 rows)
+    X20 = _t(_cg(np.random.default_rng(4), 4096, 20))
 
     def run():
         F = bf.construct(op, 1e-6, 64, seed=31)
         out = [F.export()]
+        for trans in (False, True):
+            out.append(np.ascontiguousarray(F.apply(X20, trans=trans).cpu().numpy()))
         F.close()
         for c in (1, 2, 3):
             for trans in (False, True):
@@ -337,6 +346,65 @@ def test_block_and_record_kernels_give_the_same_bits(bf, tmp_path, L, r, leaf):
         bf.autotune_clear()
         saved = os.path.join(os.path.dirname(bf.__file__), "tune_gfx950.tsv")
         if os.path.exists(saved):   # the table saved beside the library
+            bf.autotune_load(saved)
+        bf.set_autotune(True)
+        H.close()
+
+
+@pytest.mark.parametrize("L,r,leaf", [(9, 20, 24), (8, 40, 40), (7, 30, 64)])
+def test_mfma_wave_and_workgroup_kernels_give_the_same_bits(bf, tmp_path, L, r, leaf):
+    """Stage-by-stage split-BF16 applies of 5 to 100 columns on blocks of 17
+    to 64 rows: one workgroup per block and 64 columns, and one wave per
+    block with 1, 2, ... or all of its 16-column tiles, each forced through
+    the autotuner's table, give the same bits, forward and adjoint, and are
+    within 2e-6 of the oracle's FP64 apply in every column."""
+    import torch
+    n = leaf << L
+    kU, kV, data = wl.exact_butterfly_canonical(L, r, seed=L + r, leaf=leaf)
+    F = canonical_to_oracle(n, n, L, kU, kV, data)
+    H = bf.import_factors(n, n, leaf, kU, kV, data)
+    say("mfma wave vs workgroup", L, r, leaf)
+    rng = np.random.default_rng(L + 1)
+    cases = [(s, _cg(rng, n, s)) for s in (5, 16, 20, 64, 100)]
+    path = str(tmp_path / "tune.tsv")
+
+    def run():
+        out = []
+        for s, X in cases:
+            for trans in (False, True):
+                out.append(np.ascontiguousarray(H.apply(_t(X), trans=trans).cpu().numpy()))
+        torch.cuda.synchronize()
+        return out
+
+    try:
+        bf.set_autotune(True)
+        bf.autotune_clear()
+        ref = run()
+        bf.autotune_save(path)
+        rows = _tune_rows(path)
+        assert any(fam == "apply_mfma" for fam, _, _ in rows)
+        for pick in ("workgroup", "one", "all"):
+            with open(path, "w") as f:
+                for fam, fields, c in rows:
+                    if fam == "apply_mfma":
+                        c = {"workgroup": 0, "one": 1, "all": max(1, fields[0] // 16)}[pick]
+                    f.write(" ".join([fam] + [str(x) for x in fields] + [str(c)]) + "\n")
+            bf.autotune_clear()
+            bf.autotune_load(path)
+            say("forced", pick)
+            for a, b in zip(ref, run()):
+                assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), pick
+        i = 0
+        for s, X in cases:
+            for want in (obf.apply(F, X), obf.apply_adjoint(F, X)):
+                y = ref[i]
+                i += 1
+                for col in range(s):
+                    assert np.linalg.norm(y[:, col] - want[:, col]) <= 2e-6 * np.linalg.norm(want[:, col])
+    finally:
+        bf.autotune_clear()
+        saved = os.path.join(os.path.dirname(bf.__file__), "tune_gfx950.tsv")
+        if os.path.exists(saved):
             bf.autotune_load(saved)
         bf.set_autotune(True)
         H.close()
@@ -444,8 +512,8 @@ def test_apply_of_oracle_factors(bf, n, leaf):
 def test_apply_precisions(bf, n, leaf):
     """Applies of imported oracle factors with FP32 vector arithmetic and
     with the default arithmetic (split-BF16 matrix cores from 5 right-hand
-    sides, FP64 sums below), forward and adjoint, against the oracle's FP64
-    apply; the default is at least as accurate."""
+    sides, the FP32 vector path below), forward and adjoint, against the
+    oracle's FP64 apply; the default is at least as accurate."""
     g = wl.segment_pair(n, ppw=6.0)
     op = ops.SegmentKernelOp(g.targets, g.sources, g.k)
     F = obf.construct(op, 1e-6, leaf, seed=2)
@@ -477,13 +545,13 @@ def test_apply_precisions(bf, n, leaf):
 
 @pytest.mark.parametrize("L,r,leaf", [(10, 8, 8), (11, 6, 6)])
 def test_fused_apply_matches_staged(bf, L, r, leaf):
-    """Applies of 1 to 16 columns run several stages per launch
+    """Applies of 1 to 4 columns run several stages per launch
     (bf_set_apply_fusion) when every launch keeps 256 groups (here exact
     butterflies of Sec. 6.1 with 1024 and 2048 blocks a level): bitwise the
-    stage-by-stage results for 1 to 4 columns (same row kernel and summation
-    order), within the apply tolerance of the oracle's FP64 apply of the same
-    factors for every column from 5 to 16, forward and adjoint, in both apply
-    precisions."""
+    stage-by-stage results (same slots and summation order) and within the
+    apply tolerance of the oracle's FP64 apply of the same factors, forward
+    and adjoint, in both apply precisions; 5 to 16 columns (stage by stage
+    whatever the switch) within the same tolerance."""
     n = leaf << L
     kU, kV, data = wl.exact_butterfly_canonical(L, r, seed=L, leaf=leaf)
     F = canonical_to_oracle(n, n, L, kU, kV, data)
