@@ -173,12 +173,17 @@ __device__ __forceinline__ int fused_k(int q, int j) {
 // took one 200 MB stage of the n = 262144 FIO butterfly from 4.2-4.5 to
 // 5.3-5.4 TB/s of factor bytes in a stand-alone probe that kept the factors
 // out of the last-level cache (a read-only sum of the same bytes: 6.0 TB/s).
-template <int NC, int IT, int RG>
+template <int NC, int IT, int RG, bool XL>
 __global__ __launch_bounds__(256) void apply_blockrows_kernel(const ApplyBlk* __restrict__ blks,
                                                               int32_t nblk,
                                                               const bf_c64* __restrict__ G,
                                                               ApplyBufs B, int32_t ncols) {
-  const int b = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  constexpr int S = 4 * IT;   // slots per lane
+  // XL: the block's inputs in LDS (32 IT rows x NC columns per wave), read
+  // per slot, instead of S x NC registers per lane
+  __shared__ __attribute__((aligned(16))) bf_c64 xsh[XL ? 4 : 1][XL ? 32 * IT * NC : 1];
+  const int wave = threadIdx.x >> 6;
+  const int b = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + wave));
   if (b >= nblk) return;
   const int lane = threadIdx.x & 63, q = lane & (AP_LPR - 1), rs = lane / AP_LPR;
   const ApplyBlk bk = blks[b];
@@ -186,40 +191,58 @@ __global__ __launch_bounds__(256) void apply_blockrows_kernel(const ApplyBlk* __
   const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0;
   const bf_c64* in1 = B.p[bk.in_buf1] + bk.in_row1 - K0;
   const int64_t ld0 = B.ld[bk.in_buf0], ld1 = B.ld[bk.in_buf1];
-  constexpr int S = 4 * IT;   // slots per lane
-  bf_c64 xv[S][NC];
+  bf_c64 xv[XL ? 1 : S][NC];
+  if constexpr (XL) {
+    bf_c64* xw = xsh[wave];
+    for (int e = lane; e < 32 * IT * NC; e += 64) {
+      const int k = e / NC, c = e % NC;
+      bf_c64 x = {0.f, 0.f};
+      if (k < KK && c < ncols) x = k < K0 ? in0[k + (int64_t)c * ld0] : in1[k + (int64_t)c * ld1];
+      xw[e] = x;
+    }
+    // the wave's own LDS writes, read back by its other lanes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
 #pragma unroll
-  for (int j = 0; j < S; ++j) {
-    const int k = fused_k<NC>(q, j);
-    if constexpr (NC <= 2) {
-      if (j & 1) continue;   // pairs: slot j + 1 is entry k + 1
-      const bool k0v = k < KK, k1v = k + 1 < KK;
-      const bool seg0 = k < K0, seg1 = k + 1 < K0;
-      const bf_c64* base = seg0 ? in0 : in1;
-      const int64_t ldk = seg0 ? ld0 : ld1;
+    for (int j = 0; j < S; ++j) {
+      const int k = fused_k<NC>(q, j);
+      if constexpr (NC <= 2) {
+        if (j & 1) continue;   // pairs: slot j + 1 is entry k + 1
+        const bool k0v = k < KK, k1v = k + 1 < KK;
+        const bool seg0 = k < K0, seg1 = k + 1 < K0;
+        const bf_c64* base = seg0 ? in0 : in1;
+        const int64_t ldk = seg0 ? ld0 : ld1;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        if (c < ncols && k1v && seg0 == seg1) {
-          load_pair(base + k + (int64_t)c * ldk, xv[j][c], xv[j + 1][c]);
-        } else {
-          xv[j][c] = (c < ncols && k0v) ? base[k + (int64_t)c * ldk] : bf_c64{0.f, 0.f};
-          xv[j + 1][c] = (c < ncols && k1v)
-                             ? (seg1 ? in0 : in1)[k + 1 + (int64_t)c * (seg1 ? ld0 : ld1)]
-                             : bf_c64{0.f, 0.f};
+        for (int c = 0; c < NC; ++c) {
+          if (c < ncols && k1v && seg0 == seg1) {
+            load_pair(base + k + (int64_t)c * ldk, xv[j][c], xv[j + 1][c]);
+          } else {
+            xv[j][c] = (c < ncols && k0v) ? base[k + (int64_t)c * ldk] : bf_c64{0.f, 0.f};
+            xv[j + 1][c] = (c < ncols && k1v)
+                               ? (seg1 ? in0 : in1)[k + 1 + (int64_t)c * (seg1 ? ld0 : ld1)]
+                               : bf_c64{0.f, 0.f};
+          }
         }
-      }
-    } else {
-      const bool kv = k < KK;
-      const bf_c64* inp = k < K0 ? in0 + k : in1 + k;
-      const int64_t ldk = k < K0 ? ld0 : ld1;
+      } else {
+        const bool kv = k < KK;
+        const bf_c64* inp = k < K0 ? in0 + k : in1 + k;
+        const int64_t ldk = k < K0 ? ld0 : ld1;
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        xv[j][c] = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
+        for (int c = 0; c < NC; ++c)
+          xv[j][c] = (kv && c < ncols) ? inp[(int64_t)c * ldk] : bf_c64{0.f, 0.f};
+      }
     }
   }
   bf_c64* out = B.p[bk.out_buf] + bk.out_row;
   const int64_t ldo = B.ld[bk.out_buf];
   for (int r0 = 0; r0 < bk.M; r0 += AP_LPR * RG) {
+    // an offset the compiler cannot see through (an empty asm statement), so
+    // that the LDS reads stay inside the loop instead of being hoisted into
+    // registers
+    int xo = 0;
+    if constexpr (XL) asm volatile("" : "+s"(xo));
     bf_c64 gv[RG][S];
 #pragma unroll
     for (int i = 0; i < RG; ++i) {
@@ -248,9 +271,16 @@ __global__ __launch_bounds__(256) void apply_blockrows_kernel(const ApplyBlk* __
 #pragma unroll
       for (int c = 0; c < NC; ++c) acc[c] = cf{0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < S; ++j)
+      for (int j = 0; j < S; ++j) {
+        if constexpr (XL) {
+          const bf_c64* xr = xsh[wave] + xo + fused_k<NC>(q, j) * NC;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[i][j], xv[j][c]);
+          for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[i][j], xr[c]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc_fma(acc[c], gv[i][j], xv[j][c]);
+        }
+      }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         acc[c].re = row8_sum(acc[c].re);
@@ -1072,20 +1102,40 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
           return;
         }
         const dim3 grid((unsigned)((nblk + 3) / 4));
-#define AP_BR(N, I, R) \
-  hipLaunchKernelGGL((apply_blockrows_kernel<N, I, R>), grid, dim3(256), 0, s, blks_dev, nblk, G, B, nc)
+#define AP_BR(N, I, R, X)                                                                   \
+  hipLaunchKernelGGL((apply_blockrows_kernel<N, I, R, X>), grid, dim3(256), 0, s, blks_dev, \
+                     nblk, G, B, nc)
+        const bool xl = c >= 8;
+        const int rg = (int)(c & 7);
         if (ncl == 1) {
-          if (it == 1) AP_BR(1, 1, 4); else if (it == 2) AP_BR(1, 2, 2); else AP_BR(1, 3, 1);
+          if (it == 1) { if (rg == 4) AP_BR(1, 1, 4, false); else if (rg == 2) AP_BR(1, 1, 2, false); else AP_BR(1, 1, 1, false); }
+          else if (it == 2) { if (rg == 2) AP_BR(1, 2, 2, false); else AP_BR(1, 2, 1, false); }
+          else { if (rg == 2) AP_BR(1, 3, 2, false); else AP_BR(1, 3, 1, false); }
         } else if (ncl == 2) {
-          if (it == 1) AP_BR(2, 1, 4); else if (it == 2) AP_BR(2, 2, 2); else AP_BR(2, 3, 1);
+          if (it == 1) { if (rg == 4) AP_BR(2, 1, 4, false); else if (rg == 2) AP_BR(2, 1, 2, false); else AP_BR(2, 1, 1, false); }
+          else if (it == 2) { if (rg == 2) AP_BR(2, 2, 2, false); else AP_BR(2, 2, 1, false); }
+          else { if (rg == 2) AP_BR(2, 3, 2, false); else AP_BR(2, 3, 1, false); }
+        } else if (xl) {
+          if (it == 1) { if (rg == 2) AP_BR(4, 1, 2, true); else AP_BR(4, 1, 1, true); }
+          else if (it == 2) { if (rg == 2) AP_BR(4, 2, 2, true); else AP_BR(4, 2, 1, true); }
+          else { if (rg == 2) AP_BR(4, 3, 2, true); else AP_BR(4, 3, 1, true); }
         } else {
-          if (it == 1) AP_BR(4, 1, 2); else if (it == 2) AP_BR(4, 2, 1); else AP_BR(4, 3, 1);
+          if (it == 1) { if (rg == 2) AP_BR(4, 1, 2, false); else AP_BR(4, 1, 1, false); }
+          else if (it == 2) AP_BR(4, 2, 1, false);
+          else AP_BR(4, 3, 1, false);
         }
 #undef AP_BR
       };
-      // both kernels give the same bits: the autotuner picks per shape class
-      tune_choose(TuneKey{kTuneApplyRows, ncl, it, pow2_ceil(nblk), pow2_ceil(maxM), 0}, {1, 0}, 1,
-                  s, run, may_time);
+      // record kernel (0) or block kernel with rg = c & 7 groups of 8 rows
+      // loaded together and, from c = 8 on, its inputs in LDS: all give the
+      // same bits; the autotuner picks per shape class
+      std::vector<int64_t> cand;
+      if (ncl <= 2)
+        cand = it == 1 ? std::vector<int64_t>{4, 2, 1, 0} : std::vector<int64_t>{1, 2, 0};
+      else
+        cand = it == 1 ? std::vector<int64_t>{2, 1, 9, 10, 0} : std::vector<int64_t>{1, 9, 10, 0};
+      tune_choose(TuneKey{kTuneApplyRows, ncl, it, pow2_ceil(nblk), pow2_ceil(maxM), 0}, cand,
+                  cand.front(), s, run, may_time);
     }
   } else if (prec == BF_PREC_BF16X3 && ncols >= AM_MIN_COLS) {
     const int64_t ych = (ncols + AP_CW - 1) / AP_CW;
