@@ -71,7 +71,7 @@ enum {
  *                 may come in several calls (see bf_opts.work_bytes).
  *
  * X and Y are device buffers owned by the library for the duration of the
- * call; the callback must not keep them.  Return 0 on success; any nonzero
+ * call; the callback must not keep them, nor write X.  Return 0 on success; any nonzero
  * value aborts the construction with BF_ECALLBACK.
  */
 typedef int (*bf_op_fn)(void* user, const bf_c64* X, int64_t ldx, int64_t ncols,

@@ -401,5 +401,16 @@ void launch_fio(int prec, int64_t n, const double* cx_dev, int adjoint, const bf
 void launch_dense(int prec, const bf_c64* A, int64_t m, int64_t n, int64_t lda, int adjoint,
                   const bf_c64* X, int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
                   const int64_t* seg_host, int32_t nseg, hipStream_t s);
+// Black-box inputs known to be exact in BF16: the construction driver marks
+// the random block it passes to the operator, for the duration of the call
+// and on its own thread; a built-in operator handed that very buffer (not a
+// copy or a transform of it, which a user callback wrapping it might pass)
+// launches only its kernel variant for BF16-exact inputs.
+struct ExactInputScope {
+  explicit ExactInputScope(const void* x);
+  ~ExactInputScope();
+  const void* prev;
+};
+bool input_known_exact(const void* x);
 
 }  // namespace bf

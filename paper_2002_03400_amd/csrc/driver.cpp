@@ -154,9 +154,12 @@ class Builder {
                                 std::to_string(cap_));
   }
 
+  // X is always one of this construction's random blocks (gauss, gauss_into:
+  // Gaussians stored rounded to BF16, zero padding), hence exact in BF16
   void call_op(bool adjoint, const bf_c64* X, int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
                const std::vector<int64_t>* seg) {
     bf_op_fn fn = adjoint ? rmv_ : mv_;
+    ExactInputScope ex(X);
     int rc = fn(user_, X, ldx, ncols, Y, ldy, seg ? seg->data() : nullptr,
                 seg ? (int32_t)(seg->size() - 1) : 0, (void*)s_);
     if (rc != 0)
@@ -891,6 +894,12 @@ std::vector<Block> canonical_blocks(const bf_factors* F) {
   for (auto& b : F->V) out.push_back(b);
   return out;
 }
+
+thread_local const void* t_exact_input = nullptr;
+
+ExactInputScope::ExactInputScope(const void* x) : prev(t_exact_input) { t_exact_input = x; }
+ExactInputScope::~ExactInputScope() { t_exact_input = prev; }
+bool input_known_exact(const void* x) { return x != nullptr && x == t_exact_input; }
 
 bf_factors* construct(bf_op_fn mv, bf_op_fn rmv, void* user, int64_t m, int64_t n, double tol,
                       int64_t leaf, const bf_opts* o, hipStream_t s) {

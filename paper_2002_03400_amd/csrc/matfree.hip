@@ -374,32 +374,41 @@ __global__ void split_planes_kernel(const bf_c64* __restrict__ X, int64_t ldx,
   if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(inexact, 1ull);
 }
 
-template <class E, int NT, bool EXACT>
-struct BfShared {
-  static constexpr int NC = 16 * NT;
-  static constexpr int NTERM = EXACT ? 1 : 3;   // staged terms of X
-  static constexpr int TK = bf_tk<EXACT>();
-  static constexpr int KP = TK + 8;             // padded k stride (bank spread)
-  typename E::Col cols[TK];
-  // split planes: [term][re/im][column][k], 16 bytes = 8 consecutive k
-  __attribute__((aligned(16))) uint16_t xs[NTERM][2][NC][KP];
-};
-
-// One workgroup tile: rows [bx * 16 NW, (bx + 1) * 16 NW), segment g, split z.
+// Two instantiations per shape: EXACT (X exact in BF16, e.g. the random
+// blocks of Alg. 2, so x = x1 and a real product needs the three MFMAs
+// a1x1 + a2x1 + a3x1) and general (six).  Both are launched; the one that
+// does not match the flag written by split_planes_kernel exits at once.  When
+// the construction driver marks the input as one of its random blocks
+// (input_known_exact), only the EXACT variant is launched.
+// Four waves per SIMD (at most 128 VGPRs) up to 64 columns: for the 48- and
+// 64-column tiles of the general path this costs a few spilled registers
+// outside the inner loop and is still ~25% faster than the two waves their
+// unconstrained register count allows.  The 80-column tile (NT = 5) keeps its
+// ~160 registers in four-wave workgroups (three waves per SIMD; two on the
+// general path, whose three staged terms need ~250): its entries serve 25%
+// more columns, so one call replaces the two a 68-column block would
+// otherwise need.
 template <class E, int NT, typename Tout, bool EXACT>
-__device__ __forceinline__ void matfree_bf16_tile(
-    BfShared<E, NT, EXACT>& sh, int64_t bx, int g, int z, const E& e, int64_t nout,
-    const uint16_t* __restrict__ Xp, int64_t kpad, int32_t ncols, int32_t c0, int32_t width,
-    Tout* __restrict__ Y, int64_t ldy, int64_t ycols, const int64_t* __restrict__ seg,
-    const int64_t* __restrict__ pofs, int32_t nsplit) {
+__global__ __launch_bounds__(64 * bf_waves<NT>())
+__attribute__((amdgpu_waves_per_eu(NT > 4 ? (EXACT ? 3 : 2) : 4, 8)))
+void matfree_bf16_kernel(
+    E e, int64_t nout, const uint16_t* __restrict__ Xp, int64_t kpad, int32_t ncols, int32_t c0,
+    int32_t width, Tout* __restrict__ Y, int64_t ldy, int64_t ycols,
+    const int64_t* __restrict__ seg, const int64_t* __restrict__ pofs, int32_t nsplit,
+    const unsigned long long* __restrict__ inexact) {
+  if ((*inexact == 0ull) != EXACT) return;
   constexpr int NC = 16 * NT;
   constexpr int NTERM = EXACT ? 1 : 3;      // staged terms of X
   constexpr int TK = bf_tk<EXACT>();
-  auto& cols = sh.cols;
-  auto& xs = sh.xs;
+  constexpr int KP = TK + 8;                // padded k stride (bank spread)
+  __shared__ typename E::Col cols[TK];
+  // split planes: [term][re/im][column][k], 16 bytes = 8 consecutive k
+  __shared__ __attribute__((aligned(16))) uint16_t xs[NTERM][2][NC][KP];
+  const int g = blockIdx.y;
+  const int z = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int NW = bf_waves<NT>();
-  const int64_t row0 = bx * (16 * NW) + wave * 16;
+  const int64_t row0 = (int64_t)blockIdx.x * (16 * NW) + wave * 16;
   const int64_t myrow = row0 + (lane & 15);
   const int kq = lane >> 4;       // which 8 of the step's 32 inner points
   const int lc = lane & 15;
@@ -506,48 +515,6 @@ __device__ __forceinline__ void matfree_bf16_tile(
   }
 }
 
-// Two instantiations per shape: EXACT (X exact in BF16, e.g. the random
-// blocks of Alg. 2, so x = x1 and a real product needs the three MFMAs
-// a1x1 + a2x1 + a3x1) and general (six).  Both are launched; the one that
-// does not match the flag written by split_planes_kernel exits at once.  The
-// exact variant runs one workgroup per tile (grid gx x gy x gz); the general
-// one, launched on every black-box call but used only for inputs that are
-// not exact in BF16, walks the tiles from a grid of at most kBfGeneralWgs
-// workgroups, so that its exit costs a few thousand workgroups instead of up
-// to half a million (0.2-1.1 ms per call at n = 65536).
-// Four waves per SIMD (at most 128 VGPRs) up to 64 columns: for the 48- and
-// 64-column tiles of the general path this costs a few spilled registers
-// outside the inner loop and is still ~25% faster than the two waves their
-// unconstrained register count allows.  The 80-column tile (NT = 5) keeps its
-// ~160 registers in four-wave workgroups (three waves per SIMD; two on the
-// general path, whose three staged terms need ~250): its entries serve 25%
-// more columns, so one call replaces the two a 68-column block would
-// otherwise need.
-constexpr int64_t kBfGeneralWgs = 4096;
-
-template <class E, int NT, typename Tout, bool EXACT>
-__global__ __launch_bounds__(64 * bf_waves<NT>())
-__attribute__((amdgpu_waves_per_eu(NT > 4 ? (EXACT ? 3 : 2) : 4, 8)))
-void matfree_bf16_kernel(
-    E e, int64_t nout, const uint16_t* __restrict__ Xp, int64_t kpad, int32_t ncols, int32_t c0,
-    int32_t width, Tout* __restrict__ Y, int64_t ldy, int64_t ycols,
-    const int64_t* __restrict__ seg, const int64_t* __restrict__ pofs, int32_t nsplit,
-    const unsigned long long* __restrict__ inexact, int32_t gx, int32_t gy) {
-  if ((*inexact == 0ull) != EXACT) return;
-  __shared__ BfShared<E, NT, EXACT> sh;
-  if constexpr (EXACT) {
-    matfree_bf16_tile<E, NT, Tout, EXACT>(sh, blockIdx.x, blockIdx.y, blockIdx.z, e, nout, Xp,
-                                          kpad, ncols, c0, width, Y, ldy, ycols, seg, pofs,
-                                          nsplit);
-  } else {
-    const int64_t total = (int64_t)gx * gy * nsplit;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x)
-      matfree_bf16_tile<E, NT, Tout, EXACT>(sh, t % gx, (int)((t / gx) % gy), (int)(t / ((int64_t)gx * gy)),
-                                            e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols,
-                                            seg, pofs, nsplit);
-  }
-}
-
 // Y(:, col) = sum_z P[z](:, col) over the FP64 split planes (fixed order).
 __global__ void split_reduce_kernel(const bf_c128* __restrict__ P, int64_t nout, int64_t ycols,
                                     int32_t nsplit, bf_c64* __restrict__ Y, int64_t ldy) {
@@ -595,21 +562,21 @@ template <class E, int NT, typename Tout>
 static void launch_bf16(const E& e, int64_t nout, const uint16_t* Xp, int64_t kpad, int32_t ncols,
                         int32_t c0, int32_t width, Tout* Y, int64_t ldy, int64_t ycols,
                         const int64_t* seg_dev, const int64_t* pofs_dev, int32_t nseg,
-                        int32_t nsplit, const unsigned long long* inexact, hipStream_t s) {
+                        int32_t nsplit, const unsigned long long* inexact, bool known_exact,
+                        hipStream_t s) {
   constexpr int NW = bf_waves<NT>();
   dim3 grid((unsigned)((nout + 16 * NW - 1) / (16 * NW)), (unsigned)nseg, (unsigned)nsplit);
   const double nc = (double)std::min<int32_t>(16 * NT, width);
   const double nin = (double)g_matfree_nin;
   ProfScope ps(BF_KC_MATFREE, s, 8.0 * (double)nout * nin * nc,
                8.0 * nc * (nin + (double)nout * nseg));
-  const int64_t tiles = (int64_t)grid.x * grid.y * grid.z;
   hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout, true>), grid, dim3(64 * NW), 0, s, e,
                      nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nsplit,
-                     inexact, (int32_t)grid.x, (int32_t)grid.y);
-  hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout, false>),
-                     dim3((unsigned)std::min<int64_t>(tiles, kBfGeneralWgs)), dim3(64 * NW), 0, s,
-                     e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev,
-                     nsplit, inexact, (int32_t)grid.x, (int32_t)grid.y);
+                     inexact);
+  if (!known_exact)
+    hipLaunchKernelGGL((matfree_bf16_kernel<E, NT, Tout, false>), grid, dim3(64 * NW), 0, s, e,
+                       nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nsplit,
+                       inexact);
   BF_HIP(hipGetLastError());
 }
 
@@ -618,22 +585,22 @@ static void launch_chunk_bf16(const E& e, int64_t nout, const uint16_t* Xp, int6
                               int32_t ncols, int32_t c0, int32_t width, Tout* Y, int64_t ldy,
                               int64_t ycols, const int64_t* seg_dev, const int64_t* pofs_dev,
                               int32_t nseg, int32_t nsplit, const unsigned long long* inexact,
-                              hipStream_t s) {
+                              bool known_exact, hipStream_t s) {
   if (width <= 16)
     launch_bf16<E, 1>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
-                      nsplit, inexact, s);
+                      nsplit, inexact, known_exact, s);
   else if (width <= 32)
     launch_bf16<E, 2>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
-                      nsplit, inexact, s);
+                      nsplit, inexact, known_exact, s);
   else if (width <= 48)
     launch_bf16<E, 3>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
-                      nsplit, inexact, s);
+                      nsplit, inexact, known_exact, s);
   else if (width <= 64)
     launch_bf16<E, 4>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
-                      nsplit, inexact, s);
+                      nsplit, inexact, known_exact, s);
   else
     launch_bf16<E, 5>(e, nout, Xp, kpad, ncols, c0, width, Y, ldy, ycols, seg_dev, pofs_dev, nseg,
-                      nsplit, inexact, s);
+                      nsplit, inexact, known_exact, s);
 }
 
 // Column tiles of a product: with more than 48 split-BF16 columns the 48-,
@@ -649,6 +616,7 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
                         const int64_t* seg_host, int32_t nseg, hipStream_t s) {
   if (nout <= 0 || ncols <= 0) return;
   const bool bf16 = prec == BF_PREC_BF16X3;
+  const bool known_exact = bf16 && input_known_exact(X);
   std::vector<int64_t> segv;
   if (seg_host) {
     segv.assign(seg_host, seg_host + nseg + 1);
@@ -723,10 +691,10 @@ static void run_matfree(int prec, const E& e, int64_t nout, int64_t nin, const b
       if (bf16) {
         if (nsplit > 1)
           launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, part.p, nout,
-                            ycols, seg_dev.p, pofs_dev, nseg, nsplit, inexact, s);
+                            ycols, seg_dev.p, pofs_dev, nseg, nsplit, inexact, known_exact, s);
         else
           launch_chunk_bf16(e, nout, planes.p, kpad, (int32_t)ncols, (int32_t)c0, w, Y, ldy,
-                            ycols, seg_dev.p, pofs_dev, nseg, nsplit, inexact, s);
+                            ycols, seg_dev.p, pofs_dev, nseg, nsplit, inexact, known_exact, s);
       } else {
         if (nsplit > 1)
           launch_chunk(e, nout, X, ldx, (int32_t)ncols, (int32_t)c0, w, part.p, nout, ycols,
