@@ -126,8 +126,19 @@ typedef struct {
  *   block) share one call while their widths add up to at most 80 columns,
  *   which returns the same products in fewer calls; when the loop stops
  *   before a merged pass, that pass's columns are wasted (and counted in
- *   bf_info's column totals). */
-enum { BF_OPT_CENTER_LEVEL = 1, BF_OPT_SEQUENTIAL_LEAF = 2 };
+ *   bf_info's column totals).
+ * BF_OPT_SEQUENTIAL_SWEEP: one black-box call per sweep level.  By default,
+ *   for the built-in operators that evaluate every kernel entry once per call
+ *   (bf_op_segkernel, bf_op_helmholtz3d, bf_op_fio, bf_op_dense) and the
+ *   default centre level, a W or R level whose samples leave room in one
+ *   80-column tile also draws the next level's samples (at a width guessed
+ *   from its own, the next level's exact widths needing its ranks) and makes
+ *   one call over the next level's segments for both: the next level's
+ *   products are those of its own call bit for bit, this level's are the
+ *   sums of the halves over each node's two children (one more rounding).
+ *   A guess that proves too small costs the next level its own call; the
+ *   drawn columns are counted in bf_info's column totals either way. */
+enum { BF_OPT_CENTER_LEVEL = 1, BF_OPT_SEQUENTIAL_LEAF = 2, BF_OPT_SEQUENTIAL_SWEEP = 4 };
 
 enum { BF_PHASE_LEAF_V = 0, BF_PHASE_LEAF_U = 1, BF_PHASE_W = 2, BF_PHASE_R = 3 };
 

@@ -59,6 +59,7 @@ class bf_opts(C.Structure):
 
 BF_OPT_CENTER_LEVEL = 1
 BF_OPT_SEQUENTIAL_LEAF = 2
+BF_OPT_SEQUENTIAL_SWEEP = 4
 CENTERS = {"hybrid": None, "column": 0, "row": -1}
 
 
@@ -491,7 +492,8 @@ class Factors:
 
 def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed: int = 0,
               max_rank: int = 0, stream=None, work_bytes: int = 0, progress=None,
-              center="hybrid", merge_leaf: bool = True, allocator="torch") -> Factors:
+              center="hybrid", merge_leaf: bool = True, merge_sweeps: bool = True,
+              allocator="torch") -> Factors:
     """Alg. 2 on the device; returns the factor handle.  work_bytes bounds the
     device memory of one sweep level's samples (0: 8 GiB).  progress(phase,
     level), if given, is called after each leaf-loop iteration and sweep level
@@ -499,7 +501,10 @@ def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed
     "hybrid" (floor(L/2)), "column" (0: column-wise factorization), "row" (L:
     row-wise), or an integer level (negative counts from L + 1).  merge_leaf:
     consecutive passes of the adaptive leaf loops share a black-box call
-    (same results, fewer calls); False makes one call per pass.  allocator:
+    (same results, fewer calls); False makes one call per pass.  merge_sweeps:
+    consecutive sweep levels may share a black-box call (built-in operators
+    that evaluate their entries on the fly; bf.h BF_OPT_SEQUENTIAL_SWEEP);
+    False makes one call per level.  allocator:
     where the device memory comes from -- "torch" (torch's caching allocator,
     default) or None (the library's own pool)."""
     o = bf_opts(p, r0, max_rank, 0, seed, work_bytes)
@@ -509,6 +514,8 @@ def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed
         o.center_level = lm
     if not merge_leaf:
         o.flags |= BF_OPT_SEQUENTIAL_LEAF
+    if not merge_sweeps:
+        o.flags |= BF_OPT_SEQUENTIAL_SWEEP
     cb = None    # held until bf_construct returns
     if progress is not None:
         cb = PROGRESSFN(lambda _u, ph, lv: progress(PHASES[ph], lv))

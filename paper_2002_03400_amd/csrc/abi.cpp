@@ -673,6 +673,11 @@ static int compose_rmv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64
   return compose_apply(u, 1, X, ldx, nc, Y, ldy, seg, nseg, st);
 }
 
+bool entrywise_operator(bf_op_fn mv, bf_op_fn rmv) {
+  return (mv == seg_mv && rmv == seg_rmv) || (mv == fio_mv && rmv == fio_rmv) ||
+         (mv == dense_mv && rmv == dense_rmv);
+}
+
 static void check_device() {
   int dev = 0;
   hipDeviceProp_t prop;

@@ -401,6 +401,15 @@ void launch_fio(int prec, int64_t n, const double* cx_dev, int adjoint, const bf
 void launch_dense(int prec, const bf_c64* A, int64_t m, int64_t n, int64_t lda, int adjoint,
                   const bf_c64* X, int64_t ldx, int64_t ncols, bf_c64* Y, int64_t ldy,
                   const int64_t* seg_host, int32_t nseg, hipStream_t s);
+// Y0 (rows x nseg*s0) = the sums of the column pairs of Yb (rows x 2 nseg*w)
+// that hold the two halves of every node's product: Y0(:, g s0 + c) =
+// Yb(:, 2g w + off + c) + Yb(:, (2g+1) w + off + c).
+void launch_sum_halves(const bf_c64* Yb, int64_t rows, int64_t nseg, int32_t w, int32_t off,
+                       int32_t s0, bf_c64* Y0, hipStream_t s);
+// Built-in operators whose black-box call evaluates every kernel entry once
+// per call (its cost nearly independent of the column count up to the widest
+// column tile): the construction may then merge sweep levels.
+bool entrywise_operator(bf_op_fn mv, bf_op_fn rmv);
 // Black-box inputs known to be exact in BF16: the construction driver marks
 // the random block it passes to the operator, for the duration of the call
 // and on its own thread; a built-in operator handed that very buffer (not a

@@ -81,10 +81,13 @@ class Builder {
       progress_user_ = o->progress_user;
       merge_leaf_ = (o->flags & BF_OPT_SEQUENTIAL_LEAF) == 0;
     }
+    merge_sweeps_ = entrywise_operator(mv, rmv) &&
+                    !(o && (o->flags & (BF_OPT_SEQUENTIAL_SWEEP | BF_OPT_CENTER_LEVEL)));
     BF_CHECK(p_ >= 0 && r0_ >= 1 && cap_ >= 0 && (!o || o->work_bytes >= 0), BF_EINVAL,
              "bad bf_opts");
-    BF_CHECK(!o || (o->flags & ~(BF_OPT_CENTER_LEVEL | BF_OPT_SEQUENTIAL_LEAF)) == 0, BF_EINVAL,
-             "unknown bf_opts flags");
+    BF_CHECK(!o || (o->flags & ~(BF_OPT_CENTER_LEVEL | BF_OPT_SEQUENTIAL_LEAF |
+                                 BF_OPT_SEQUENTIAL_SWEEP)) == 0,
+             BF_EINVAL, "unknown bf_opts flags");
     F_->L = num_levels(m, n, leaf);
     F_->lm = F_->L / 2;
     if (o && (o->flags & BF_OPT_CENTER_LEVEL)) {
@@ -138,6 +141,29 @@ class Builder {
   int64_t mv_cols_ = 0, rmv_cols_ = 0;
   int v_iters_ = 0, u_iters_ = 0;
   bool merge_leaf_ = true;
+  // Sweep levels two at a time.  For a built-in operator that evaluates the
+  // kernel entries on the fly, a black-box call costs about the same for 40
+  // columns as for 80 (its vector ALUs evaluate every entry once per call;
+  // the matrix cores multiplying them have room).  A sweep level then draws
+  // the next level's samples too (twice as many nodes, each one of its nodes'
+  // children), at a width guessed from its own (the next level's widths need
+  // its ranks), and makes one call over the next level's segments with both
+  // blocks side by side: the next level's products come out as its own call
+  // would give them (the same random columns -- Philox counters keyed by row
+  // and column -- and sums that do not depend on the other columns), this
+  // level's as the sums of the halves over each node's two children.  When
+  // the next level comes and every node's width fits the guess, its call is
+  // skipped; otherwise it makes its own and the early columns are wasted
+  // (both are counted in bf_info's column totals).
+  bool merge_sweeps_ = false;
+  static constexpr int32_t kMergeCols = 80;   // the widest column tile of the black boxes
+  struct Ahead {
+    int level = -1;            // sweep level the products belong to (-1: none)
+    int32_t width = 0;         // every node's sample width
+    DevBuf<bf_c64> Y;          // out rows x (nodes * width), node-major
+    DevBuf<bf_c64> Om;         // in rows x width (ld in rows): the random block first
+  };
+  Ahead ahead_;
   void (*progress_)(void*, int32_t, int32_t) = nullptr;
   void* progress_user_ = nullptr;
   void report(int32_t phase, int32_t level) const {
@@ -170,6 +196,12 @@ class Builder {
   DevBuf<bf_c64> gauss(int64_t rows, int64_t ncols, int level, const std::vector<uint64_t>& tags,
                        const std::vector<int32_t>& widths) {
     DevBuf<bf_c64> X((size_t)rows * ncols, s_);
+    gauss_at(X.p, rows, ncols, level, tags, widths);
+    return X;
+  }
+  // The structured random block of a level into rows x ncols at X (ld rows).
+  void gauss_at(bf_c64* X, int64_t rows, int64_t ncols, int level,
+                const std::vector<uint64_t>& tags, const std::vector<int32_t>& widths) {
     if (validating()) {
       BF_CHECK(tags.size() == (size_t(1) << level) && widths.size() == tags.size(), BF_EINVAL,
                "bounds check failed: sample tags");
@@ -177,8 +209,38 @@ class Builder {
     }
     auto dt = upload(tags, s_, st_);
     auto dw = upload(widths, s_, st_);
-    launch_gauss_samples(X.p, rows, ncols, level, dt.p, dw.p, seed_, s_);
-    return X;
+    launch_gauss_samples(X, rows, ncols, level, dt.p, dw.p, seed_, s_);
+  }
+
+  // One black-box call for a sweep level's samples (nseg nodes of input-tree
+  // level tl, widths `width`, at most s0) and the next level's (2 nseg nodes
+  // of level tl + 1, all spec wide, tags ntags): X = [next level's block |
+  // this level's block] over the next level's segments.  Returns this level's
+  // products (out_rows x nseg s0, node-major); the next level's go to ahead_.
+  DevBuf<bf_c64> merged_call(bool adjoint, int64_t in_rows, int64_t out_rows, int tl,
+                             int64_t nseg, const std::vector<uint64_t>& tags,
+                             const std::vector<int32_t>& width, int32_t s0, int32_t spec,
+                             int next_level, const std::vector<uint64_t>& ntags) {
+    const int64_t n2 = 2 * nseg;
+    const int32_t w = spec + s0;
+    DevBuf<bf_c64> X((size_t)in_rows * w, s_);
+    gauss_at(X.p, in_rows, spec, tl + 1, ntags, std::vector<int32_t>((size_t)n2, spec));
+    gauss_at(X.p + (size_t)in_rows * spec, in_rows, s0, tl, tags, width);
+    std::vector<int64_t> seg((size_t)n2 + 1);
+    for (int64_t i = 0; i <= n2; ++i) seg[(size_t)i] = node_lo(in_rows, tl + 1, i);
+    DevBuf<bf_c64> Yb((size_t)out_rows * n2 * w, s_);
+    call_op(adjoint, X.p, in_rows, w, Yb.p, out_rows, &seg);
+    DevBuf<bf_c64> Y0((size_t)out_rows * nseg * s0, s_);
+    launch_sum_halves(Yb.p, out_rows, nseg, w, spec, s0, Y0.p, s_);
+    ahead_.level = next_level;
+    ahead_.width = spec;
+    ahead_.Y = DevBuf<bf_c64>((size_t)out_rows * n2 * spec, s_);
+    const size_t blk = (size_t)out_rows * spec;
+    for (int64_t g = 0; g < n2; ++g)
+      BF_HIP(hipMemcpyAsync(ahead_.Y.p + (size_t)g * blk, Yb.p + (size_t)g * out_rows * w,
+                            blk * sizeof(bf_c64), hipMemcpyDeviceToDevice, s_));
+    ahead_.Om = std::move(X);
+    return Y0;
   }
 
   void gemm(const std::vector<GemmDesc>& d, bool in_c64) {
@@ -382,21 +444,48 @@ class Builder {
       tags[i] = make_tag(PHASE_W, l, i);
       smax = std::max(smax, width[i]);
     }
-    auto G = gauss(m, smax, l, tags, width);
-    for (auto w : width) rmv_cols_ += w;
     int64_t rows0 = 0;
     std::vector<int64_t> roff0(nb());
     for (int64_t j = 0; j < nb(); ++j) { roff0[j] = rows0; rows0 += F_->kv(0, 0, j); }
     // per sample: Y' (n x smax c64), the leaf stage and two chain stages (FP64)
-    const int64_t gsz = group_size(nT, (double)smax * (8.0 * n + 48.0 * (double)rows0));
+    auto sample_bytes = [&](int32_t w) { return (double)w * (8.0 * n + 48.0 * (double)rows0); };
+    // the whole level's products, when they come from a merged call
+    DevBuf<bf_c64> G, Ypre;
+    Ahead ah = std::move(ahead_);
+    ahead_ = Ahead{};
+    bool use_ahead = ah.level == l && group_size(nT, sample_bytes(ah.width)) == nT;
+    for (auto w : width) use_ahead = use_ahead && w <= ah.width;
+    if (use_ahead) {
+      smax = ah.width;
+      Ypre = std::move(ah.Y);
+    } else {
+      const int32_t spec = merge_sweeps_ && l < lm() ? std::min(smax + 2, kMergeCols - smax) : 0;
+      if (spec >= smax && group_size(nT, sample_bytes(smax)) == nT &&
+          group_size(2 * nT, sample_bytes(spec)) == 2 * nT) {
+        std::vector<uint64_t> ntags((size_t)(2 * nT));
+        for (int64_t i = 0; i < 2 * nT; ++i) ntags[(size_t)i] = make_tag(PHASE_W, l + 1, i);
+        Ypre = merged_call(true, m, n, l, nT, tags, width, smax, spec, l + 1, ntags);
+        rmv_cols_ += 2 * nT * spec;
+      } else {
+        G = gauss(m, smax, l, tags, width);
+      }
+      for (auto w : width) rmv_cols_ += w;
+    }
+    const int64_t gsz = group_size(nT, sample_bytes(smax));
+    BF_CHECK(!Ypre.p || gsz == nT, BF_EINVAL, "internal: merged sweep level split in groups");
     F_->W[l].assign((size_t)nb(), Block{});
     for (int64_t i0 = 0; i0 < nT; i0 += gsz) {
       const int64_t i1 = std::min(nT, i0 + gsz), ng = i1 - i0;
       std::vector<int64_t> seg(ng + 1);
       for (int64_t i = 0; i <= ng; ++i) seg[i] = node_lo(m, l, i0 + i);
       const int64_t ycols = ng * smax;
-      DevBuf<bf_c64> Yp((size_t)n * ycols, s_);
-      call_op(true, G.p, m, smax, Yp.p, n, &seg);
+      DevBuf<bf_c64> Yp;
+      if (Ypre.p) {
+        Yp = std::move(Ypre);
+      } else {
+        Yp = DevBuf<bf_c64>((size_t)n * ycols, s_);
+        call_op(true, G.p, m, smax, Yp.p, n, &seg);
+      }
 
       // V stage (shared by the group's samples): P0 = V^H Y', rows by leaf j,
       // stored row-major (row stride ycols) so that a block's rows are
@@ -509,13 +598,37 @@ class Builder {
       tags[j] = make_tag(PHASE_R, l, j);
       smax = std::max(smax, width[j]);
     }
-    auto Om = gauss(n, smax, L() - l, tags, width);
-    for (auto w : width) mv_cols_ += w;
     int64_t rowsL = 0;
     std::vector<int64_t> roffL(nb());
     for (int64_t i = 0; i < nb(); ++i) { roffL[i] = rowsL; rowsL += F_->ku(L(), i, 0); }
     // per sample: Y (m x smax c64), the leaf stage and two chain stages (FP64)
-    const int64_t gsz = group_size(nS, (double)smax * (8.0 * m + 48.0 * (double)rowsL));
+    auto sample_bytes = [&](int32_t w) { return (double)w * (8.0 * m + 48.0 * (double)rowsL); };
+    // the whole level's products, when they come from a merged call (the
+    // random block Om is kept for the centre level)
+    DevBuf<bf_c64> Om, Ypre;
+    Ahead ah = std::move(ahead_);
+    ahead_ = Ahead{};
+    bool use_ahead = ah.level == l && group_size(nS, sample_bytes(ah.width)) == nS;
+    for (auto w : width) use_ahead = use_ahead && w <= ah.width;
+    if (use_ahead) {
+      smax = ah.width;
+      Ypre = std::move(ah.Y);
+      Om = std::move(ah.Om);
+    } else {
+      const int32_t spec = merge_sweeps_ && l > lm() ? std::min(smax + 2, kMergeCols - smax) : 0;
+      if (spec >= smax && group_size(nS, sample_bytes(smax)) == nS &&
+          group_size(2 * nS, sample_bytes(spec)) == 2 * nS) {
+        std::vector<uint64_t> ntags((size_t)(2 * nS));
+        for (int64_t j = 0; j < 2 * nS; ++j) ntags[(size_t)j] = make_tag(PHASE_R, l - 1, j);
+        Ypre = merged_call(false, n, m, L() - l, nS, tags, width, smax, spec, l - 1, ntags);
+        mv_cols_ += 2 * nS * spec;
+      } else {
+        Om = gauss(n, smax, L() - l, tags, width);
+      }
+      for (auto w : width) mv_cols_ += w;
+    }
+    const int64_t gsz = group_size(nS, sample_bytes(smax));
+    BF_CHECK(!Ypre.p || gsz == nS, BF_EINVAL, "internal: merged sweep level split in groups");
     F_->R[l - lm()].assign((size_t)nb(), Block{});
     if (l == lm()) F_->B.assign((size_t)nb(), Block{});
     for (int64_t j0 = 0; j0 < nS; j0 += gsz) {
@@ -523,8 +636,13 @@ class Builder {
       std::vector<int64_t> seg(ng + 1);
       for (int64_t q = 0; q <= ng; ++q) seg[q] = node_lo(n, L() - l, j0 + q);
       const int64_t ycols = ng * smax;
-      DevBuf<bf_c64> Y((size_t)m * ycols, s_);
-      call_op(false, Om.p, n, smax, Y.p, m, &seg);
+      DevBuf<bf_c64> Y;
+      if (Ypre.p) {
+        Y = std::move(Ypre);
+      } else {
+        Y = DevBuf<bf_c64>((size_t)m * ycols, s_);
+        call_op(false, Om.p, n, smax, Y.p, m, &seg);
+      }
 
       // U^H stage (shared by the group's samples): PL rows by leaf i, stored
       // row-major (row stride ycols)

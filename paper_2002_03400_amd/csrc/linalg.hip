@@ -685,6 +685,27 @@ __global__ void expand_segments_kernel(const bf_c64* X, int64_t ldx, int64_t row
   if (r >= seg[g] && r < seg[g + 1]) v = X[c * ldx + r];
   out[col * ldo + r] = v;
 }
+// Y0(:, g s0 + c) = Yb(:, 2g w + off + c) + Yb(:, (2g+1) w + off + c): a
+// level's products from the halves computed over its nodes' two children.
+__global__ void sum_halves_kernel(const bf_c64* __restrict__ Yb, int64_t rows, int32_t w,
+                                  int32_t off, int32_t s0, bf_c64* __restrict__ Y0) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t col = blockIdx.y;    // 0 .. nseg*s0-1
+  if (r >= rows) return;
+  const int64_t g = col / s0, c = col % s0;
+  const bf_c64 a = Yb[((2 * g) * w + off + c) * rows + r];
+  const bf_c64 b = Yb[((2 * g + 1) * w + off + c) * rows + r];
+  Y0[col * rows + r] = bf_c64{a.re + b.re, a.im + b.im};
+}
+void launch_sum_halves(const bf_c64* Yb, int64_t rows, int64_t nseg, int32_t w, int32_t off,
+                       int32_t s0, bf_c64* Y0, hipStream_t s) {
+  if (rows <= 0 || nseg <= 0 || s0 <= 0) return;
+  BF_CHECK(nseg * s0 <= 65535, BF_EINVAL, "too many summed columns");
+  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)(nseg * s0));
+  hipLaunchKernelGGL(sum_halves_kernel, grid, dim3(256), 0, s, Yb, rows, w, off, s0, Y0);
+  BF_HIP(hipGetLastError());
+}
+
 void launch_expand_segments(const bf_c64* X, int64_t ldx, int64_t rows, int64_t ncols,
                             const int64_t* seg_dev, int32_t nseg, bf_c64* out, int64_t ldo,
                             hipStream_t s) {

@@ -305,6 +305,51 @@ def test_reused_device_blocks_do_not_change_results(bf):
     once_more.close()
 
 
+@pytest.mark.parametrize("n,tol", [(16384, 1e-6), (8192, 1e-4)])
+def test_merged_sweep_levels(bf, n, tol):
+    """Consecutive sweep levels sharing one black-box call (the default for
+    the built-in operators that evaluate their entries on the fly) against one
+    call per level: the same ranks, factors that agree to the tolerance, an
+    apply error on 16 Gaussian columns within 5% of the level-by-level
+    construction's, fewer black-box launches, and bitwise repeatable."""
+    import torch
+    g = wl.segment_pair(n, ppw=8.0)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    say("merged sweep levels", n, tol)
+    runs = {}
+    bf.set_autotune(False)    # launch counts without the tuner's timing runs
+    try:
+        for merge in (True, False):
+            bf.profile_start()
+            H = bf.construct(op, tol, 64, seed=9, merge_sweeps=merge)
+            torch.cuda.synchronize()
+            calls = bf.profile_stop()["matfree"]["launches"]
+            runs[merge] = (H, calls)
+    finally:
+        bf.set_autotune(True)
+    (Hm, cm), (Hs, cs) = runs[True], runs[False]
+    say("black-box launches merged", cm, "level by level", cs)
+    assert cm < cs
+    for a, b in zip(Hm.ranks(), Hs.ranks()):
+        assert np.array_equal(a, b)
+    # reference products from the FP64 black box (checked against the oracle
+    # by test_gpu_kernels)
+    Om = wl.test_columns(n, 16, 77)
+    ref64 = bf.segkernel(g.targets, g.sources, g.k).set_precision("fp64")
+    ref = ref64.matvec(_t(Om)).cpu().numpy()
+    em = _err(ref, Hm.apply(_t(Om)).cpu().numpy())
+    es = _err(ref, Hs.apply(_t(Om)).cpu().numpy())
+    say("errors merged", em, "level by level", es)
+    assert em <= 1.05 * es
+    # bitwise repeatable (tuned launch shapes give the same bits)
+    again = bf.construct(op, tol, 64, seed=9)
+    assert np.array_equal(again.export(), Hm.export())
+    again.close()
+    Hm.close()
+    Hs.close()
+    ref64.close()
+
+
 def test_merged_leaf_passes_same_result(bf):
     """Leaf-loop passes merged into one black-box call give bitwise the same
     factors as one call per pass; only the call count differs."""
