@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--stream", type=int, default=64,
                     help="requests of each Poisson stream at the headline size, run at 0.5x, "
                          "1x and 2x the measured capacity (0 = skip)")
+    ap.add_argument("--max-constructs-line", type=int, default=1, choices=[0, 1],
+                    help="also run the Poisson streams with at most 2 constructions at once "
+                         "(bf_server_opts.max_constructs; keys 0.5x_max2, ...)")
     ap.add_argument("--mix", type=int, default=256,
                     help="requests of the mixed serving stream (0 = skip); run served and "
                          "through the per-request path")
@@ -662,14 +665,16 @@ def c5_apply(bf, n=262144, leaf=16, tol=1e-6):
     return out
 
 
-def run_served(bf, reqs, slots, leaf, keep_all=False, batch_cols=0, rounds=False):
+def run_served(bf, reqs, slots, leaf, keep_all=False, batch_cols=0, rounds=False,
+               max_constructs=0):
     """Replay a request stream in real time through the request engine.
     Returns (server, wall seconds, [latency s of constructions], [latency s of
     applies], [borrowed factors of every construction] if keep_all else [])."""
     import torch
 
     import workloads as wl
-    S = bf.Server(slots=slots, batch_cols=batch_cols, solve_rounds=rounds)
+    S = bf.Server(slots=slots, batch_cols=batch_cols, solve_rounds=rounds,
+                  max_constructs=max_constructs)
     ops_ = {}
     tickets = {}
     start = time.perf_counter()
@@ -784,16 +789,23 @@ def main():
     if args.stream > 0:
         cap = max(served_fs, per_request_fs)
         streams = {}
-        for mult in (0.5, 1.0, 2.0):
-            reqs = wl.poisson_stream(args.stream, mult * cap, n=args.n, ppw=args.ppw,
-                                     tol=args.tol)
-            S, wall_s, lat_s, _, _ = run_served(bf, reqs, args.slots, args.leaf,
-                                                rounds=bool(args.solve_rounds))
-            S.close()
-            streams[f"{mult:g}x"] = {
-                "requests": args.stream, "rate_per_s": mult * cap, "wall_s": wall_s,
-                "p50_ms": 1e3 * pct(lat_s, 50), "p99_ms": 1e3 * pct(lat_s, 99),
-                "completed_per_s": args.stream / wall_s}
+        # the same streams again with at most 2 constructions at once
+        # (bf_server_opts.max_constructs): latency against throughput
+        for cap_c, suffix in ((0, ""), (2, "_max2")):
+            if cap_c and (args.max_constructs_line == 0 or cap_c >= args.slots):
+                continue
+            for mult in (0.5, 1.0, 2.0):
+                reqs = wl.poisson_stream(args.stream, mult * cap, n=args.n, ppw=args.ppw,
+                                         tol=args.tol)
+                S, wall_s, lat_s, _, _ = run_served(bf, reqs, args.slots, args.leaf,
+                                                    rounds=bool(args.solve_rounds),
+                                                    max_constructs=cap_c)
+                S.close()
+                streams[f"{mult:g}x{suffix}"] = {
+                    "requests": args.stream, "rate_per_s": mult * cap, "wall_s": wall_s,
+                    "max_constructs": cap_c,
+                    "p50_ms": 1e3 * pct(lat_s, 50), "p99_ms": 1e3 * pct(lat_s, 99),
+                    "completed_per_s": args.stream / wall_s}
     mix = None
     if args.mix > 0:
         reqs = wl.mixed_stream(args.mix, rate=args.mix_rate)

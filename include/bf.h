@@ -332,9 +332,9 @@ typedef struct {
                            (one launch sequence instead of one per request).
                            Merged results are those of the merged product: the
                            same accuracy, but the arithmetic follows the merged
-                           width (a 1-column apply alone sums in FP64, merged
-                           with 4+ others it runs on the matrix cores), so they
-                           can differ from a lone apply in the last bits. */
+                           width (a 1-column apply alone runs on the vector
+                           ALUs, merged with 4+ others on the matrix cores), so
+                           they can differ from a lone apply in the last bits. */
   int64_t hbm_budget;   /* bytes; 0 = 64 GiB */
   const bf_alloc* alloc;  /* NULL or the device-memory provider of every request
                              (bf_alloc; copied at creation, must outlive the
@@ -351,7 +351,14 @@ typedef struct {
                            for the LDS keep their own launches.  Each block runs
                            the code of its own launch: results are bitwise
                            those without rounds. */
-  int32_t reserved;     /* 0 */
+  int32_t max_constructs; /* 0: every slot may run a construction.  > 0: at most
+                           this many constructions run at once; further ones
+                           wait in the queue while applies still take the idle
+                           slots.  Constructions that share the device each take
+                           proportionally longer, so a cap below `slots` trades
+                           a little throughput for latency (n = 65536, 4 slots,
+                           Poisson arrivals at half the capacity: p99 447 ms
+                           uncapped, 272 ms with 2 slots). */
 } bf_server_opts;
 typedef struct {
   int32_t status;       /* BF_OK or the request's error code */

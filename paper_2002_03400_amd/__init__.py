@@ -82,7 +82,7 @@ class bf_alloc(C.Structure):
 class bf_server_opts(C.Structure):
     _fields_ = [("slots", C.c_int32), ("batch_cols", C.c_int32), ("hbm_budget", C.c_int64),
                 ("alloc", C.POINTER(bf_alloc)), ("solve_rounds", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("max_constructs", C.c_int32)]
 
 
 class bf_request_info(C.Structure):
@@ -552,16 +552,19 @@ class Server:
     with admission by estimated device footprint (see include/bf.h)."""
 
     def __init__(self, slots=4, hbm_budget=0, batch_cols=0, allocator="torch",
-                 solve_rounds=False):
+                 solve_rounds=False, max_constructs=0):
         """batch_cols > 0 merges queued applies against the same factors into
         one product of at most that many columns (continuous batching).
         allocator: device memory of every request -- "torch" (torch's caching
         allocator, default) or None (the library's own pool).  solve_rounds:
         the level solves of in-flight constructions share persistent launches
-        (cross-request rounds, replayed from captured graphs)."""
+        (cross-request rounds, replayed from captured graphs).  max_constructs
+        > 0: at most that many constructions run at once (applies still take
+        the idle slots)."""
         self._alloc = _allocator(allocator)
         o = bf_server_opts(slots, int(batch_cols), int(hbm_budget))
         o.solve_rounds = int(bool(solve_rounds))
+        o.max_constructs = int(max_constructs)
         if self._alloc is not None:
             o.alloc = C.pointer(self._alloc.struct)
         h = C.c_void_p()

@@ -88,6 +88,8 @@ struct bf_server {
   std::vector<hipStream_t> streams;
   int64_t budget = 0, reserved = 0, next_id = 1;
   int64_t batch_cols = 0;
+  int32_t max_constructs = 0;   // bf_server_opts.max_constructs (0: no cap)
+  int32_t running_constructs = 0;
   bf_alloc alloc{};          // the caller's allocator (bf_server_opts.alloc), if any
   bool has_alloc = false;
   SolveRounds* rounds = nullptr;   // cross-request solve rounds (bf_server_opts.solve_rounds)
@@ -103,9 +105,15 @@ struct bf_server {
     return it == all.end() || it->second->status <= 0;
   }
 
+  // a construction waits while max_constructs others run (applies do not)
+  bool capped(const Request* r) const {
+    return r->kind == 0 && max_constructs > 0 && running_constructs >= max_constructs;
+  }
+
   Request* admit() {   // called with mu held
     for (size_t q = 0; q < queue.size(); ++q) {
       Request* r = queue[q];
+      if (capped(r)) continue;
       const bool fits = reserved + r->footprint <= budget || reserved == 0;
       if (ready(r) && fits) {
         queue.erase(queue.begin() + q);
@@ -204,6 +212,7 @@ struct bf_server {
         cv_work.wait(lk, [&] { return stopping || (r = admit()) != nullptr; });
         if (!r) return;
         reserved += r->footprint;
+        if (r->kind == 0) ++running_constructs;
         batch = take_batch(r);
         const auto now = Clock::now();
         for (auto* q : batch) {
@@ -244,6 +253,7 @@ struct bf_server {
           q->finish = now;
           q->status = rc;
         }
+        if (r->kind == 0) --running_constructs;
         r->F = F;
       }
       cv_done.notify_all();
@@ -262,6 +272,11 @@ int bf_server_create(const bf_server_opts* o, bf_server** out) {
   if (!S) return BF_ENOMEM;
   S->budget = o && o->hbm_budget > 0 ? o->hbm_budget : (int64_t(64) << 30);
   S->batch_cols = o && o->batch_cols > 0 ? o->batch_cols : 0;
+  if (o && o->max_constructs < 0) {
+    delete S;
+    return BF_EINVAL;
+  }
+  S->max_constructs = o ? o->max_constructs : 0;
   if (o && o->alloc) {
     if (!o->alloc->alloc || !o->alloc->free) {
       delete S;

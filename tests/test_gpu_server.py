@@ -31,6 +31,45 @@ def _t(x):
     return torch.from_numpy(np.asarray(x, np.complex64)).cuda()
 
 
+def test_max_constructs_runs_constructions_one_at_a_time(bf):
+    """bf_server_opts.max_constructs = 1 on 4 slots: the queued constructions
+    run one after another (each starts once the previous one has finished),
+    an apply against a finished construction still takes an idle slot beside
+    them, and the factors are bitwise those of each construction alone."""
+    import torch
+    specs = [(2048, 8.0, 1e-6, 21), (3000, 8.0, 1e-6, 22), (2500, 6.0, 1e-6, 23)]
+    opsl = []
+    for n, ppw, tol, seed in specs:
+        g = wl.segment_pair(n, ppw=ppw)
+        opsl.append(bf.segkernel(g.targets, g.sources, g.k))
+    say("alone")
+    alone = []
+    for op, (n, ppw, tol, seed) in zip(opsl, specs):
+        F = bf.construct(op, tol, 64, seed=seed)
+        alone.append(F.export())
+        F.close()
+    say("capped server")
+    S = bf.Server(slots=4, max_constructs=1)
+    t0 = S.submit_construct(opsl[0], specs[0][2], 64, seed=specs[0][3])
+    S.wait(t0)
+    rest = [S.submit_construct(op, tol, 64, seed=seed)
+            for op, (n, ppw, tol, seed) in zip(opsl[1:], specs[1:])]
+    ta = S.submit_apply(t0, _t(np.ones((specs[0][0], 1))))
+    infos = [S.wait(t) for t in rest]
+    ia = S.wait(ta)
+    torch.cuda.synchronize()
+    first, second = sorted(infos, key=lambda i: i["start_ns"])
+    say("constructions", first["start_ns"], first["finish_ns"], second["start_ns"],
+        "apply", ia["start_ns"])
+    assert second["start_ns"] >= first["finish_ns"]
+    assert ia["start_ns"] < second["finish_ns"]
+    for t, a in zip([t0] + rest, alone):
+        assert np.array_equal(S.factors(t).export(), a)
+    S.close()
+    with pytest.raises(bf.BFError):
+        bf.Server(slots=2, max_constructs=-1)
+
+
 @pytest.mark.parametrize("rounds", [False, True])
 def test_mix_equals_alone(bf, rounds):
     """Constructions of several sizes, wavenumbers and tolerances run together
