@@ -356,9 +356,11 @@ typedef struct {
                            wait in the queue while applies still take the idle
                            slots.  Constructions that share the device each take
                            proportionally longer, so a cap below `slots` trades
-                           a little throughput for latency (n = 65536, 4 slots,
-                           Poisson arrivals at half the capacity: p99 447 ms
-                           uncapped, 272 ms with 2 slots). */
+                           some throughput for tail latency under light load
+                           (n = 65536, 4 slots, Poisson arrivals at half the
+                           capacity: p99 359 ms uncapped, 268 ms with at most 2
+                           constructions; at full load the cap costs 4% of the
+                           throughput and the queue grows). */
 } bf_server_opts;
 typedef struct {
   int32_t status;       /* BF_OK or the request's error code */
