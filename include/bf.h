@@ -131,9 +131,10 @@ typedef struct {
  *   for the built-in operators that evaluate every kernel entry once per call
  *   (bf_op_segkernel, bf_op_helmholtz3d, bf_op_fio, bf_op_dense) and the
  *   default centre level, a W or R level whose samples leave room in one
- *   80-column tile also draws the next level's samples (at a width guessed
- *   from its own, the next level's exact widths needing its ranks) and makes
- *   one call over the next level's segments for both: the next level's
+ *   80-column tile also draws the next level's samples (as wide as that room,
+ *   the next level's exact widths needing this level's ranks; not from the
+ *   first level when the leaf bases have full rank) and makes one call over
+ *   the next level's segments for both: the next level's
  *   products are those of its own call bit for bit, this level's are the
  *   sums of the halves over each node's two children (one more rounding).
  *   A guess that proves too small costs the next level its own call; the
@@ -252,8 +253,12 @@ typedef struct {
   int64_t rmatvec_cols;      /* ... and with A^H (structured samples count s each) */
   int64_t factor_entries;    /* complex entries stored over all factors */
   int64_t device_bytes;      /* device memory held by the handle */
-  int32_t fused_launches;    /* launches of a fused 1-16 column apply (0: every stage
+  int32_t fused_launches;    /* launches of a fused 1-4 column apply (0: every stage
                                 is its own launch, L + 3 of them) */
+  int32_t merged_levels;     /* sweep levels whose products came from the previous
+                                level's black-box call (BF_OPT_SEQUENTIAL_SWEEP) */
+  int32_t merge_misses;      /* sweep levels drawn ahead whose guessed width proved
+                                too small (they made their own call) */
   int32_t reserved;
 } bf_info;
 int bf_stats(const bf_factors* F, bf_info* info);

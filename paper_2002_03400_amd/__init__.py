@@ -96,7 +96,8 @@ class bf_info(C.Structure):
                 ("apply_graphs", C.c_int32),
                 ("matvec_cols", C.c_int64), ("rmatvec_cols", C.c_int64),
                 ("factor_entries", C.c_int64), ("device_bytes", C.c_int64),
-                ("fused_launches", C.c_int32), ("reserved", C.c_int32)]
+                ("fused_launches", C.c_int32), ("merged_levels", C.c_int32),
+                ("merge_misses", C.c_int32), ("reserved", C.c_int32)]
 
 
 _LIB = None
@@ -409,6 +410,8 @@ class Info:
     factor_entries: int
     device_bytes: int
     fused_launches: int
+    merged_levels: int
+    merge_misses: int
     reserved: int
 
 

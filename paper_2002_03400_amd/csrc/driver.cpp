@@ -140,6 +140,7 @@ class Builder {
   Staging& st_ = scope_staging(s_) ? *scope_staging(s_) : own_st_;
   int64_t mv_cols_ = 0, rmv_cols_ = 0;
   int v_iters_ = 0, u_iters_ = 0;
+  int merged_levels_ = 0, merge_misses_ = 0;
   bool merge_leaf_ = true;
   // Sweep levels two at a time.  For a built-in operator that evaluates the
   // kernel entries on the fly, a black-box call costs about the same for 40
@@ -210,6 +211,20 @@ class Builder {
     auto dt = upload(tags, s_, st_);
     auto dw = upload(widths, s_, st_);
     launch_gauss_samples(X, rows, ncols, level, dt.p, dw.p, seed_, s_);
+  }
+
+  // The guess for the next level's widths is all the room the 80-column tile
+  // leaves beside this level's, taken when it is at least this level's
+  // width.  Leaf bases of full rank (rank = leaf size: the FIO at leaf 16)
+  // mean the ranks still grow after the leaves, so the first sweep level
+  // does not guess.
+  bool leaves_saturated(bool col_side) const {
+    const int64_t N = col_side ? F_->m : F_->n;
+    for (int64_t j = 0; j < nb(); ++j) {
+      const int32_t k = col_side ? F_->ku(L(), j, 0) : F_->kv(0, 0, j);
+      if (k > 0 && k >= node_lo(N, L(), j + 1) - node_lo(N, L(), j)) return true;
+    }
+    return false;
   }
 
   // One black-box call for a sweep level's samples (nseg nodes of input-tree
@@ -455,11 +470,13 @@ class Builder {
     ahead_ = Ahead{};
     bool use_ahead = ah.level == l && group_size(nT, sample_bytes(ah.width)) == nT;
     for (auto w : width) use_ahead = use_ahead && w <= ah.width;
+    if (ah.level == l) (use_ahead ? merged_levels_ : merge_misses_)++;
     if (use_ahead) {
       smax = ah.width;
       Ypre = std::move(ah.Y);
     } else {
-      const int32_t spec = merge_sweeps_ && l < lm() ? std::min(smax + 2, kMergeCols - smax) : 0;
+      const int32_t spec = merge_sweeps_ && l < lm() && !(l == 1 && leaves_saturated(false))
+                               ? kMergeCols - smax : 0;
       if (spec >= smax && group_size(nT, sample_bytes(smax)) == nT &&
           group_size(2 * nT, sample_bytes(spec)) == 2 * nT) {
         std::vector<uint64_t> ntags((size_t)(2 * nT));
@@ -610,12 +627,14 @@ class Builder {
     ahead_ = Ahead{};
     bool use_ahead = ah.level == l && group_size(nS, sample_bytes(ah.width)) == nS;
     for (auto w : width) use_ahead = use_ahead && w <= ah.width;
+    if (ah.level == l) (use_ahead ? merged_levels_ : merge_misses_)++;
     if (use_ahead) {
       smax = ah.width;
       Ypre = std::move(ah.Y);
       Om = std::move(ah.Om);
     } else {
-      const int32_t spec = merge_sweeps_ && l > lm() ? std::min(smax + 2, kMergeCols - smax) : 0;
+      const int32_t spec = merge_sweeps_ && l > lm() && !(l == L() - 1 && leaves_saturated(true))
+                               ? kMergeCols - smax : 0;
       if (spec >= smax && group_size(nS, sample_bytes(smax)) == nS &&
           group_size(2 * nS, sample_bytes(spec)) == 2 * nS) {
         std::vector<uint64_t> ntags((size_t)(2 * nS));
@@ -991,6 +1010,8 @@ class Builder {
     I.max_rank = kmax;
     I.v_iters = v_iters_;
     I.u_iters = u_iters_;
+    I.merged_levels = merged_levels_;
+    I.merge_misses = merge_misses_;
     I.matvec_cols = mv_cols_;
     I.rmatvec_cols = rmv_cols_;
     I.factor_entries = entries;
