@@ -537,11 +537,17 @@ int bf_op_set_precision(bf_operator* op, int precision);
  *   few-column apply      : fused stages or one launch per stage, 1 to 4
  *                           columns (class: direction, columns, powers of two
  *                           above m and n, L, apply precision);
- *   few-column stage      : one wave per block with its inputs in registers
- *                           or one 8-lane group per row record, stages whose
- *                           rows have at most 96 terms and blocks at most 128
- *                           rows (class: columns, 32-term chunks per row,
- *                           powers of two above the block count and rows);
+ *   few-column stage      : a block kernel (1, 2 or 4 row groups per load,
+ *                           inputs in registers or LDS, and below 4096 blocks
+ *                           one, two or four waves per block) or one 8-lane
+ *                           group per row record, stages whose rows have at
+ *                           most 96 terms and blocks at most 128 rows (class:
+ *                           columns, 32-term chunks per row, powers of two
+ *                           above the block count and rows); stages of more
+ *                           than 64 MB are not timed (repeated launches would
+ *                           find part of their factors in the last-level
+ *                           cache) and take one row group per load with the
+ *                           inputs in registers (1-2 columns) or LDS (4);
  *   matrix-core stage     : one workgroup per block and 64 columns, or one
  *                           wave per block and 1, 2, 4 ... or all of its
  *                           16-column tiles, blocks of 17 to 64 rows (class:

@@ -173,17 +173,24 @@ __device__ __forceinline__ int fused_k(int q, int j) {
 // took one 200 MB stage of the n = 262144 FIO butterfly from 4.2-4.5 to
 // 5.3-5.4 TB/s of factor bytes in a stand-alone probe that kept the factors
 // out of the last-level cache (a read-only sum of the same bytes: 6.0 TB/s).
-template <int NC, int IT, int RG, bool XL>
+template <int NC, int IT, int RG, bool XL, bool MW>
 __global__ __launch_bounds__(256) void apply_blockrows_kernel(const ApplyBlk* __restrict__ blks,
                                                               int32_t nblk,
                                                               const bf_c64* __restrict__ G,
-                                                              ApplyBufs B, int32_t ncols) {
+                                                              ApplyBufs B, int32_t ncols,
+                                                              int32_t wpb) {
   constexpr int S = 4 * IT;   // slots per lane
   // XL: the block's inputs in LDS (32 IT rows x NC columns per wave), read
   // per slot, instead of S x NC registers per lane
   __shared__ __attribute__((aligned(16))) bf_c64 xsh[XL ? 4 : 1][XL ? 32 * IT * NC : 1];
   const int wave = threadIdx.x >> 6;
-  const int b = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + wave));
+  // MW: wpb waves per block, wave `part` taking row groups part, part + wpb,
+  // ... (a separate instantiation: the runtime stride costs the one-wave
+  // kernel a fifth of its speed on the streaming stages)
+  const int wid = (int)(blockIdx.x * 4 + wave);
+  const int b = __builtin_amdgcn_readfirstlane(MW ? wid / wpb : wid);
+  const int part = MW ? __builtin_amdgcn_readfirstlane(wid % wpb) : 0;
+  const int rstep = MW ? wpb * AP_LPR * RG : AP_LPR * RG;
   if (b >= nblk) return;
   const int lane = threadIdx.x & 63, q = lane & (AP_LPR - 1), rs = lane / AP_LPR;
   const ApplyBlk bk = blks[b];
@@ -237,7 +244,7 @@ __global__ __launch_bounds__(256) void apply_blockrows_kernel(const ApplyBlk* __
   }
   bf_c64* out = B.p[bk.out_buf] + bk.out_row;
   const int64_t ldo = B.ld[bk.out_buf];
-  for (int r0 = 0; r0 < bk.M; r0 += AP_LPR * RG) {
+  for (int r0 = part * AP_LPR * RG; r0 < bk.M; r0 += rstep) {
     // an offset the compiler cannot see through (an empty asm statement), so
     // that the LDS reads stay inside the loop instead of being hoisted into
     // registers
@@ -1101,12 +1108,29 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
           rec();
           return;
         }
-        const dim3 grid((unsigned)((nblk + 3) / 4));
-#define AP_BR(N, I, R, X)                                                                   \
-  hipLaunchKernelGGL((apply_blockrows_kernel<N, I, R, X>), grid, dim3(256), 0, s, blks_dev, \
-                     nblk, G, B, nc)
-        const bool xl = c >= 8;
+        const int wpb = (int)((c >> 4) & 3) + 1;
+        const dim3 grid((unsigned)(((int64_t)nblk * wpb + 3) / 4));
+#define AP_BR(N, I, R, X)                                                                      \
+  hipLaunchKernelGGL((apply_blockrows_kernel<N, I, R, X, false>), grid, dim3(256), 0, s, blks_dev, \
+                     nblk, G, B, nc, 1)
+#define AP_BRM(N, I, X)                                                                       \
+  hipLaunchKernelGGL((apply_blockrows_kernel<N, I, 1, X, true>), grid, dim3(256), 0, s, blks_dev, \
+                     nblk, G, B, nc, wpb)
+        const bool xl = (c >> 3) & 1;
         const int rg = (int)(c & 7);
+        if (wpb > 1) {
+          // one row group per load, several waves per block
+          if (ncl == 1) {
+            if (it == 1) AP_BRM(1, 1, false); else if (it == 2) AP_BRM(1, 2, false); else AP_BRM(1, 3, false);
+          } else if (ncl == 2) {
+            if (it == 1) AP_BRM(2, 1, false); else if (it == 2) AP_BRM(2, 2, false); else AP_BRM(2, 3, false);
+          } else if (xl) {
+            if (it == 1) AP_BRM(4, 1, true); else if (it == 2) AP_BRM(4, 2, true); else AP_BRM(4, 3, true);
+          } else {
+            if (it == 1) AP_BRM(4, 1, false); else if (it == 2) AP_BRM(4, 2, false); else AP_BRM(4, 3, false);
+          }
+          return;
+        }
         if (ncl == 1) {
           if (it == 1) { if (rg == 4) AP_BR(1, 1, 4, false); else if (rg == 2) AP_BR(1, 1, 2, false); else AP_BR(1, 1, 1, false); }
           else if (it == 2) { if (rg == 2) AP_BR(1, 2, 2, false); else AP_BR(1, 2, 1, false); }
@@ -1125,17 +1149,35 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
           else AP_BR(4, 3, 1, false);
         }
 #undef AP_BR
+#undef AP_BRM
       };
       // record kernel (0) or block kernel with rg = c & 7 groups of 8 rows
-      // loaded together and, from c = 8 on, its inputs in LDS: all give the
-      // same bits; the autotuner picks per shape class
+      // loaded together, its inputs in LDS when bit 3 is set, and
+      // ((c >> 4) & 3) + 1 waves sharing each block's row groups (stages of
+      // few blocks, which one wave per block leaves idle): all give the same
+      // bits; the autotuner picks per shape class
       std::vector<int64_t> cand;
       if (ncl <= 2)
         cand = it == 1 ? std::vector<int64_t>{4, 2, 1, 0} : std::vector<int64_t>{1, 2, 0};
       else
         cand = it == 1 ? std::vector<int64_t>{2, 1, 9, 10, 0} : std::vector<int64_t>{1, 9, 10, 0};
-      tune_choose(TuneKey{kTuneApplyRows, ncl, it, pow2_ceil(nblk), pow2_ceil(maxM), 0}, cand,
-                  cand.front(), s, run, may_time);
+      if (nblk < 4096) {
+        for (int64_t w : {16, 48}) {
+          cand.push_back(1 + w);
+          if (ncl > 2) cand.push_back(9 + w);
+        }
+      }
+      // Stages larger than the last-level cache are not timed: repeated
+      // launches of one stage find part of its factors in that cache, which
+      // favours other variants than the cold stream of a real apply.  They
+      // take the rule measured on cold data (one row group per load, inputs
+      // in registers for 1-2 columns and in LDS for 4).
+      const int64_t rule = ncl > 2 ? 9 : 1;
+      if ((double)nrows * (double)maxKK * sizeof(bf_c64) > 64.0 * (1 << 20))
+        run(rule);
+      else
+        tune_choose(TuneKey{kTuneApplyRows, ncl, it, pow2_ceil(nblk), pow2_ceil(maxM), 0}, cand,
+                    rule, s, run, may_time);
     }
   } else if (prec == BF_PREC_BF16X3 && ncols >= AM_MIN_COLS) {
     const int64_t ych = (ncols + AP_CW - 1) / AP_CW;

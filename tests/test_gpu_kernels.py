@@ -204,7 +204,8 @@ def test_autotuned_tile_widths_do_not_change_products(bf):
 
 # candidates of each tuned family (include/bf.h, bf_set_autotune)
 TUNE_CANDIDATES = {"matfree_width": [48, 64, 80], "chain_rows": [8, 16, 20, 24, 32, 64],
-                   "cpqr_threads": [256, 512], "apply_fused": [1, 0], "apply_rows": [1, 0, 2, 4, 9, 10],
+                   "cpqr_threads": [256, 512], "apply_fused": [1, 0],
+                   "apply_rows": [1, 0, 2, 4, 9, 10, 17, 49, 25, 57],
                    "apply_mfma": [1, 2, 0]}
 
 
@@ -224,11 +225,13 @@ def _valid(fam, fields, c):
         return c >= m if m <= 64 else c in (32, 64)
     if fam == "apply_mfma":      # column tiles per wave, at most the apply's tiles
         return c <= max(1, fields[0] // 16)
-    if fam == "apply_rows":      # record kernel, or row groups (+ 8: inputs in LDS)
-        ncl, it = fields[0], fields[1]
-        if ncl <= 2:
-            return c in ((4, 2, 1, 0) if it == 1 else (1, 2, 0))
-        return c in ((2, 1, 9, 10, 0) if it == 1 else (1, 9, 10, 0))
+    if fam == "apply_rows":      # record kernel, or row groups (+ 8: inputs in LDS,
+        ncl, it = fields[0], fields[1]   # + 16 / 48: 2 / 4 waves per block)
+        ok = ((4, 2, 1, 0) if it == 1 else (1, 2, 0)) if ncl <= 2 else \
+             ((2, 1, 9, 10, 0) if it == 1 else (1, 9, 10, 0))
+        if fields[2] < 4096:
+            ok += (17, 49) if ncl <= 2 else (17, 49, 25, 57)
+        return c in ok
     return True
 
 
@@ -300,12 +303,13 @@ def test_every_autotuner_candidate_gives_the_same_bits(bf, tmp_path):
 
 @pytest.mark.parametrize("L,r,leaf", [(10, 8, 8), (9, 20, 24), (8, 40, 40)])
 def test_block_and_record_kernels_give_the_same_bits(bf, tmp_path, L, r, leaf):
-    """Stage-by-stage applies of 1 to 4 columns: the one-wave-per-block kernel
-    (rows of up to 32, 64 or 96 terms -- here 16, 40 and 80 -- with 1, 2 or
-    4 groups of 8 rows loaded together, inputs in registers or, for 3 and 4
-    columns, in LDS) and the row-record kernel, each variant forced through
-    the autotuner's table, give the same bits, forward and adjoint; all are
-    within 2e-6 of the oracle's FP64 apply in every column."""
+    """Stage-by-stage applies of 1 to 4 columns: the block kernel (rows of up
+    to 32, 64 or 96 terms -- here 16, 40 and 80 -- with 1, 2 or 4 groups of 8
+    rows loaded together, inputs in registers or, for 3 and 4 columns, in
+    LDS, one, two or four waves per block) and the row-record kernel, each
+    variant forced through the autotuner's table, give the same bits, forward
+    and adjoint; all are within 2e-6 of the oracle's FP64 apply in every
+    column."""
     import torch
     n = leaf << L
     kU, kV, data = wl.exact_butterfly_canonical(L, r, seed=L + r, leaf=leaf)
@@ -321,7 +325,7 @@ def test_block_and_record_kernels_give_the_same_bits(bf, tmp_path, L, r, leaf):
         bf.autotune_clear()
         got = {}
         rows = None
-        for choice in (None, 0, 1, 2, 4, 9, 10):
+        for choice in (None, 0, 1, 2, 4, 9, 10, 17, 49, 25, 57):
             if choice is not None:
                 if rows is None:
                     rows = _tune_rows(path)
