@@ -28,6 +28,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# per-request constructions run their two sides on two streams (bf_opts
+# BF_OPT_ONE_STREAM off; the request engine keeps one stream per request)
+TWO_SIDES = True
 METRIC = "factorizations/s + p50/p99 latency at n=64K, rel err ≤1e-6 vs FP64 oracle"
 # MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 2.4 GHz x 64 flops/clock
 # (16 lanes, a packed dual FMA per lane) = 157.3 TFLOP/s.  The vector ALUs
@@ -67,6 +70,9 @@ def parse():
     ap.add_argument("--stream", type=int, default=64,
                     help="requests of each Poisson stream at the headline size, run at 0.5x, "
                          "1x and 2x the measured capacity (0 = skip)")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="run each per-request construction's two sides on one stream and "
+                         "thread (bf_opts BF_OPT_ONE_STREAM; the request engine always does)")
     ap.add_argument("--max-constructs-line", type=int, default=1, choices=[0, 1],
                     help="also run the Poisson streams with at most 2 constructions at once "
                          "(bf_server_opts.max_constructs; keys 0.5x_max2, ...)")
@@ -748,8 +754,10 @@ def main():
     torch.cuda.init()
     geom = wl.segment_pair(args.n, ppw=args.ppw)
     op = bf.segkernel(geom.targets, geom.sources, geom.k)
+    global TWO_SIDES
+    TWO_SIDES = not args.one_stream
     for w in range(args.warmup):
-        bf.construct(op, args.tol, args.leaf, seed=10_000 + w).close()
+        bf.construct(op, args.tol, args.leaf, seed=10_000 + w, two_sides=TWO_SIDES).close()
     torch.cuda.synchronize()
 
     lat = []
@@ -759,7 +767,7 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         ta = time.perf_counter()
-        F = bf.construct(op, args.tol, args.leaf, seed=3 + k)
+        F = bf.construct(op, args.tol, args.leaf, seed=3 + k, two_sides=TWO_SIDES)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ta)
         if last is not None:
@@ -855,6 +863,7 @@ def main():
         "served_p50_ms": 1e3 * pct(lat_c, 50),
         "served_p99_ms": 1e3 * pct(lat_c, 99),
         "slots": args.slots,
+        "two_sides": TWO_SIDES,
         "solve_rounds": bool(args.solve_rounds),
         "poisson_streams": streams,
         "mixed_stream": mix,

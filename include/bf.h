@@ -138,8 +138,24 @@ typedef struct {
  *   products are those of its own call bit for bit, this level's are the
  *   sums of the halves over each node's two children (one more rounding).
  *   A guess that proves too small costs the next level its own call; the
- *   drawn columns are counted in bf_info's column totals either way. */
-enum { BF_OPT_CENTER_LEVEL = 1, BF_OPT_SEQUENTIAL_LEAF = 2, BF_OPT_SEQUENTIAL_SWEEP = 4 };
+ *   drawn columns are counted in bf_info's column totals either way.
+ * BF_OPT_ONE_STREAM: run the whole construction on `stream` from the calling
+ *   thread.  By default, for the built-in operators (and compositions of
+ *   them) with no progress callback and outside cross-request solve rounds,
+ *   the row side of Alg. 2 (leaf V loop, W levels 1..l_m) runs on a second
+ *   stream driven by a second host thread while the calling thread runs the
+ *   column side (leaf U loop, R levels L-1..l_m+1); the two meet at the
+ *   centre level.  The sides enqueue the same work either way, so the factors
+ *   are the same bit for bit; each side's samples count against work_bytes
+ *   separately, so up to twice that may be in use at once.  The second
+ *   stream waits for the work enqueued on `stream` before the call, and
+ *   `stream` waits for the second stream before the centre level. */
+enum {
+  BF_OPT_CENTER_LEVEL = 1,
+  BF_OPT_SEQUENTIAL_LEAF = 2,
+  BF_OPT_SEQUENTIAL_SWEEP = 4,
+  BF_OPT_ONE_STREAM = 8
+};
 
 enum { BF_PHASE_LEAF_V = 0, BF_PHASE_LEAF_U = 1, BF_PHASE_W = 2, BF_PHASE_R = 3 };
 
@@ -379,7 +395,9 @@ int bf_server_create(const bf_server_opts* opts, bf_server** out);
 /* Finishes every request that can still run, then frees all resident factors. */
 int bf_server_destroy(bf_server* S);
 /* Queue a construction; the operator (its callbacks and user data) must stay
-   valid until the request completes.  Writes the request's ticket. */
+   valid until the request completes.  Writes the request's ticket.  The
+   engine runs every construction on its slot's one stream (it adds
+   BF_OPT_ONE_STREAM to opts): the slots already overlap requests. */
 int bf_server_submit_construct(bf_server* S, const bf_operator* op, double tol, int64_t leaf,
                                const bf_opts* opts, int64_t* ticket);
 /* Queue Y = F X (trans 0) or F^H X (trans 1) with the factors of construction

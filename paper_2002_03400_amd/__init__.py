@@ -60,6 +60,7 @@ class bf_opts(C.Structure):
 BF_OPT_CENTER_LEVEL = 1
 BF_OPT_SEQUENTIAL_LEAF = 2
 BF_OPT_SEQUENTIAL_SWEEP = 4
+BF_OPT_ONE_STREAM = 8
 CENTERS = {"hybrid": None, "column": 0, "row": -1}
 
 
@@ -496,7 +497,7 @@ class Factors:
 def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed: int = 0,
               max_rank: int = 0, stream=None, work_bytes: int = 0, progress=None,
               center="hybrid", merge_leaf: bool = True, merge_sweeps: bool = True,
-              allocator="torch") -> Factors:
+              two_sides: bool = True, allocator="torch") -> Factors:
     """Alg. 2 on the device; returns the factor handle.  work_bytes bounds the
     device memory of one sweep level's samples (0: 8 GiB).  progress(phase,
     level), if given, is called after each leaf-loop iteration and sweep level
@@ -507,7 +508,10 @@ def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed
     (same results, fewer calls); False makes one call per pass.  merge_sweeps:
     consecutive sweep levels may share a black-box call (built-in operators
     that evaluate their entries on the fly; bf.h BF_OPT_SEQUENTIAL_SWEEP);
-    False makes one call per level.  allocator:
+    False makes one call per level.  two_sides: the row side of Alg. 2 may run
+    on a second stream and host thread beside the column side (built-in
+    operators without a progress callback; bf.h BF_OPT_ONE_STREAM; same
+    factors); False keeps everything on `stream`.  allocator:
     where the device memory comes from -- "torch" (torch's caching allocator,
     default) or None (the library's own pool)."""
     o = bf_opts(p, r0, max_rank, 0, seed, work_bytes)
@@ -519,6 +523,8 @@ def construct(op: Operator, tol: float, leaf: int, p: int = 2, r0: int = 4, seed
         o.flags |= BF_OPT_SEQUENTIAL_LEAF
     if not merge_sweeps:
         o.flags |= BF_OPT_SEQUENTIAL_SWEEP
+    if not two_sides:
+        o.flags |= BF_OPT_ONE_STREAM
     cb = None    # held until bf_construct returns
     if progress is not None:
         cb = PROGRESSFN(lambda _u, ph, lv: progress(PHASES[ph], lv))

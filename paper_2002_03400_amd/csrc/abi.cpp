@@ -265,6 +265,13 @@ UseAllocator::UseAllocator(const bf_alloc* a) : prev_(t_user) {
   t_user = &ua_;
   set_ = true;
 }
+UseAllocator::UseAllocator(const UserAlloc* ua) : prev_(t_user) {
+  if (!ua) return;
+  ua_ = *ua;
+  t_user = &ua_;
+  set_ = true;
+}
+const UserAlloc* current_user_alloc() { return t_user; }
 UseAllocator::~UseAllocator() {
   if (set_) t_user = prev_;
 }
@@ -676,6 +683,16 @@ static int compose_rmv(void* u, const bf_c64* X, int64_t ldx, int64_t nc, bf_c64
 bool entrywise_operator(bf_op_fn mv, bf_op_fn rmv) {
   return (mv == seg_mv && rmv == seg_rmv) || (mv == fio_mv && rmv == fio_rmv) ||
          (mv == dense_mv && rmv == dense_rmv);
+}
+
+bool builtin_operator(bf_op_fn mv, bf_op_fn rmv, void* user) {
+  if (entrywise_operator(mv, rmv) || (mv == factors_mv && rmv == factors_rmv)) return true;
+  if (mv == compose_mv && rmv == compose_rmv) {
+    auto* c = static_cast<ComposeCtx*>(static_cast<OpHeader*>(user)->ctx);
+    return builtin_operator(c->a1.matvec, c->a1.rmatvec, c->a1.user) &&
+           builtin_operator(c->a2.matvec, c->a2.rmatvec, c->a2.user);
+  }
+  return false;
 }
 
 static void check_device() {

@@ -77,6 +77,8 @@ struct UserAlloc {
 class UseAllocator {
  public:
   explicit UseAllocator(const bf_alloc* a);
+  // the same provider on another thread (nullptr: none)
+  explicit UseAllocator(const UserAlloc* ua);
   ~UseAllocator();
   UseAllocator(const UseAllocator&) = delete;
   UseAllocator& operator=(const UseAllocator&) = delete;
@@ -268,6 +270,8 @@ void delete_solve_rounds(SolveRounds* R);
 void solve_rounds_stats(const SolveRounds* R, int64_t* rounds, int64_t* items);
 // While alive, the calling thread's constructions hand their level solves to
 // R (round_solve) and count as in flight for its round windows.
+// true while this thread takes part in cross-request solve rounds
+bool solve_rounds_active();
 class RoundsScope {
  public:
   explicit RoundsScope(SolveRounds* R);
@@ -410,6 +414,12 @@ void launch_sum_halves(const bf_c64* Yb, int64_t rows, int64_t nseg, int32_t w, 
 // per call (its cost nearly independent of the column count up to the widest
 // column tile): the construction may then merge sweep levels.
 bool entrywise_operator(bf_op_fn mv, bf_op_fn rmv);
+// true for the library's own operators (entrywise ones, factors as a black
+// box, and compositions of those): their products may be requested from two
+// host threads on two streams at once
+bool builtin_operator(bf_op_fn mv, bf_op_fn rmv, void* user);
+// the caller's provider in force on this thread (nullptr: the library's pool)
+const UserAlloc* current_user_alloc();
 // Black-box inputs known to be exact in BF16: the construction driver marks
 // the random block it passes to the operator, for the duration of the call
 // and on its own thread; a built-in operator handed that very buffer (not a

@@ -23,7 +23,12 @@
 // its argmin, B = (R^H Z) X^+; at l = l_m the sample width also covers the
 // V-side ranks; every sample has its own width.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <exception>
+#include <memory>
+#include <mutex>
+#include <thread>
 
 #include "factors.h"
 
@@ -62,6 +67,43 @@ inline void view_out(GemmDesc& g, const Tall<bf_c128>& v, int64_t row) {
   g.out_rs = (int32_t)v.rs;
 }
 
+// Second streams for the row side of constructions, kept for reuse (one per
+// construction running its two sides at once; default priority).
+std::mutex g_side_mu;
+std::vector<hipStream_t> g_side_free[64];
+
+struct SideStream {
+  int dev;
+  hipStream_t s = nullptr;
+  explicit SideStream(int d) : dev(d) {
+    BF_CHECK(dev >= 0 && dev < 64, BF_EINVAL, "device index out of range");
+    {
+      std::lock_guard<std::mutex> lk(g_side_mu);
+      if (!g_side_free[dev].empty()) {
+        s = g_side_free[dev].back();
+        g_side_free[dev].pop_back();
+      }
+    }
+    if (!s) BF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  }
+  ~SideStream() {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    g_side_free[dev].push_back(s);
+  }
+  SideStream(const SideStream&) = delete;
+  SideStream& operator=(const SideStream&) = delete;
+};
+
+// `to` waits on the device for the work enqueued on `from` so far
+void stream_after(hipStream_t to, hipStream_t from) {
+  hipEvent_t e = nullptr;
+  BF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipError_t r = hipEventRecord(e, from);
+  if (r == hipSuccess) r = hipStreamWaitEvent(to, e, 0);
+  (void)hipEventDestroy(e);
+  BF_HIP(r);
+}
+
 class Builder {
  public:
   Builder(bf_op_fn mv, bf_op_fn rmv, void* user, int64_t m, int64_t n, double tol, int64_t leaf,
@@ -86,7 +128,7 @@ class Builder {
     BF_CHECK(p_ >= 0 && r0_ >= 1 && cap_ >= 0 && (!o || o->work_bytes >= 0), BF_EINVAL,
              "bad bf_opts");
     BF_CHECK(!o || (o->flags & ~(BF_OPT_CENTER_LEVEL | BF_OPT_SEQUENTIAL_LEAF |
-                                 BF_OPT_SEQUENTIAL_SWEEP)) == 0,
+                                 BF_OPT_SEQUENTIAL_SWEEP | BF_OPT_ONE_STREAM)) == 0,
              BF_EINVAL, "unknown bf_opts flags");
     F_->L = num_levels(m, n, leaf);
     F_->lm = F_->L / 2;
@@ -102,19 +144,54 @@ class Builder {
     F_->kV.assign((size_t)(F_->lm + 1) * nb, 0);
     F_->R.resize(F_->L - F_->lm);
     F_->W.resize(F_->lm + 1);
+    two_sides_ = F_->L >= 2 && !progress_ && !(o && (o->flags & BF_OPT_ONE_STREAM)) &&
+                 !solve_rounds_active() && builtin_operator(mv, rmv, user);
+  }
+  // The row side's builder (leaf V loop and W levels) of `main`, for its own
+  // stream: the same parameters, factors of the same shape.
+  Builder(const Builder& main, hipStream_t s)
+      : mv_(main.mv_), rmv_(main.rmv_), user_(main.user_), tol_(main.tol_), s_(s) {
+    p_ = main.p_;
+    r0_ = main.r0_;
+    cap_ = main.cap_;
+    seed_ = main.seed_;
+    work_ = main.work_;
+    merge_leaf_ = main.merge_leaf_;
+    merge_sweeps_ = main.merge_sweeps_;
+    stop_ = &main.stop_side_;
+    const bf_factors* G = main.F_;
+    F_ = new bf_factors();
+    F_->m = G->m;
+    F_->n = G->n;
+    F_->leaf = G->leaf;
+    F_->L = G->L;
+    F_->lm = G->lm;
+    F_->device = G->device;
+    F_->kU.assign(G->kU.size(), 0);
+    F_->kV.assign(G->kV.size(), 0);
+    F_->R.resize(G->R.size());
+    F_->W.resize(G->W.size());
   }
   ~Builder() { delete F_; }
 
   bf_factors* run() {
-    leaf_loop(false);
-    leaf_loop(true);
-    for (int l = 1; l <= F_->lm; ++l) {
-      w_level(l);
-      report(BF_PHASE_W, l);
+    if (two_sides_) {
+      run_sides();
+    } else {
+      leaf_loop(false);
+      leaf_loop(true);
+      for (int l = 1; l <= F_->lm; ++l) {
+        w_level(l);
+        report(BF_PHASE_W, l);
+      }
+      for (int l = F_->L - 1; l > F_->lm; --l) {
+        r_level(l);
+        report(BF_PHASE_R, l);
+      }
     }
-    for (int l = F_->L - 1; l >= F_->lm; --l) {
-      r_level(l);
-      report(BF_PHASE_R, l);
+    if (F_->lm < F_->L) {
+      r_level(F_->lm);
+      report(BF_PHASE_R, F_->lm);
     }
     if (F_->lm == F_->L) {
       centre_at_leaves();
@@ -127,6 +204,78 @@ class Builder {
   }
 
  private:
+  // What the row side hands back: its factors, ranks, storage and counts.
+  struct RowSide {
+    std::vector<Block> V;
+    std::vector<std::vector<Block>> W;
+    std::vector<int32_t> kV;
+    std::vector<DevBuf<bf_c128>> store;
+    int v_iters = 0, merged = 0, misses = 0;
+    int64_t rmv_cols = 0;
+  };
+
+  // The two sides of Alg. 2 meet only at the centre level: the row side
+  // (leaf V loop, W levels 1..l_m) needs the black box's A^H products and
+  // its own ranks, the column side (leaf U loop, R levels L-1..l_m+1) A's
+  // products and its ranks.  The row side runs on a second stream, driven
+  // by a second host thread, while this thread drives the column side; each
+  // side's partial products, solves and rank reads then overlap the other
+  // side's black-box products.  Both enqueue exactly the work they would
+  // enqueue one after the other, so the factors are the same bit for bit.
+  void run_sides() {
+    SideStream side(F_->device);
+    stream_after(side.s, s_);   // the caller's earlier work on s_ comes first
+    const UserAlloc* ua = current_user_alloc();
+    std::exception_ptr err;
+    RowSide rs;
+    std::thread th([&] {
+      try {
+        BF_HIP(hipSetDevice(F_->device));
+        UseAllocator use(ua);
+        AllocScope scope(side.s);
+        Builder vb(*this, side.s);
+        vb.leaf_loop(false);
+        for (int l = 1; l <= vb.lm(); ++l) vb.w_level(l);
+        rs.V = std::move(vb.F_->V);
+        rs.W = std::move(vb.F_->W);
+        rs.kV = std::move(vb.F_->kV);
+        rs.store = std::move(vb.F_->store);
+        rs.v_iters = vb.v_iters_;
+        rs.merged = vb.merged_levels_;
+        rs.misses = vb.merge_misses_;
+        rs.rmv_cols = vb.rmv_cols_;
+      } catch (...) {
+        err = std::current_exception();
+      }
+    });
+    struct Joiner {
+      std::thread& t;
+      std::atomic<bool>& stop;
+      ~Joiner() {
+        if (t.joinable()) {
+          stop = true;   // this side failed: the other stops at its next level
+          t.join();
+        }
+      }
+    } joiner{th, stop_side_};
+    leaf_loop(true);
+    for (int l = F_->L - 1; l > F_->lm; --l) r_level(l);
+    th.join();
+    if (err) std::rethrow_exception(err);
+    stream_after(s_, side.s);
+    F_->V = std::move(rs.V);
+    F_->W = std::move(rs.W);
+    F_->kV = std::move(rs.kV);
+    for (auto& b : rs.store) F_->store.push_back(std::move(b));
+    v_iters_ = rs.v_iters;
+    merged_levels_ += rs.merged;
+    merge_misses_ += rs.misses;
+    rmv_cols_ += rs.rmv_cols;
+  }
+  void check_stop() const {
+    if (stop_ && stop_->load()) throw Error(BF_EINVAL, "construction stopped: the other side failed");
+  }
+
   bf_op_fn mv_, rmv_;
   void* user_;
   double tol_;
@@ -142,6 +291,9 @@ class Builder {
   int v_iters_ = 0, u_iters_ = 0;
   int merged_levels_ = 0, merge_misses_ = 0;
   bool merge_leaf_ = true;
+  bool two_sides_ = false;                  // run_sides() (else one stream, one thread)
+  std::atomic<bool> stop_side_{false};      // set when the column side fails
+  const std::atomic<bool>* stop_ = nullptr; // the row side's view of it
   // Sweep levels two at a time.  For a built-in operator that evaluates the
   // kernel entries on the fly, a black-box call costs about the same for 40
   // columns as for 80 (its vector ALUs evaluate every entry once per call;
@@ -376,6 +528,7 @@ class Builder {
     std::vector<int64_t> boff;         // column offset of each pass in the batch
     int bstart = 0, bend = 0;          // passes [bstart, bend) are in Y
     for (int it = 0;; ++it) {
+      check_stop();
       check_cap(r);
       const int64_t s = r + p_;
       BF_CHECK(s <= 65535, BF_ERANK, "sample width too large");
@@ -445,6 +598,7 @@ class Builder {
 
   // ---- W sweep, level l (Sec. 4.3) ------------------------------------------
   void w_level(int l) {
+    check_stop();
     const int64_t m = F_->m, n = F_->n;
     const int64_t nT = int64_t(1) << l, nS = int64_t(1) << (L() - l);
     std::vector<int32_t> width(nT);

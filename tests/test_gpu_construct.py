@@ -386,8 +386,66 @@ def test_unknown_option_flags_rejected(bf):
     import ctypes as C
     g = wl.segment_pair(256, ppw=8.0)
     op = bf.segkernel(g.targets, g.sources, g.k)
-    o = bf.bf_opts(2, 4, 0, 8, 0, 0)
+    o = bf.bf_opts(2, 4, 0, 16, 0, 0)
     h = C.c_void_p()
     rc = bf.lib().bf_construct(op._op.matvec, op._op.rmatvec, op._op.user, op.m, op.n, 1e-6, 32,
                                C.byref(o), None, None, C.byref(h))
     assert rc == -1 and not h.value
+
+
+def _two_sides_case(bf, kind):
+    if kind == "segment":
+        g = wl.segment_pair(8192, ppw=8.0)
+        return bf.segkernel(g.targets, g.sources, g.k), 1e-6, 64, []
+    if kind == "fio":
+        return bf.fio(4096), 1e-6, 16, []
+    if kind == "ragged":
+        g = wl.segment_pair(3000, ppw=6.0, m=2100)
+        return bf.segkernel(g.targets, g.sources, g.k), 1e-5, 40, []
+    # recompression: the product of two butterflies as the black box
+    g01, g12 = wl.segment_triple(2048, ppw=8.0)
+    B1 = bf.construct(bf.segkernel(g01.targets, g01.sources, g01.k), 1e-6, 32, seed=21)
+    B2 = bf.construct(bf.segkernel(g12.targets, g12.sources, g12.k), 1e-6, 32, seed=22)
+    return bf.compose(bf.from_factors(B1), bf.from_factors(B2)), 1e-6, 32, [B1, B2]
+
+
+@pytest.mark.parametrize("kind", ["segment", "fio", "ragged", "compose"])
+@pytest.mark.parametrize("allocator", ["torch", None])
+def test_two_sides_give_the_same_factors(bf, kind, allocator):
+    """The row side on its own stream and host thread beside the column side
+    (the default for built-in operators) enqueues the same work as the
+    one-stream run: bitwise the same factors, ranks and column counts."""
+    op, tol, leaf, keep = _two_sides_case(bf, kind)
+    say("two sides", kind, allocator)
+    A = bf.construct(op, tol, leaf, seed=5, allocator=allocator)
+    B = bf.construct(op, tol, leaf, seed=5, allocator=allocator, two_sides=False)
+    a, b = A.stats(), B.stats()
+    assert a.L >= 2
+    for f in ("max_rank", "v_iters", "u_iters", "matvec_cols", "rmatvec_cols", "merged_levels",
+              "merge_misses", "factor_entries"):
+        assert getattr(a, f) == getattr(b, f), f
+    assert np.array_equal(A.export(), B.export())
+    X = _t(wl.test_columns(op.n, 3, 4))
+    assert bool((A.apply(X) == B.apply(X)).all())
+    for H in (A, B, *keep):
+        H.close()
+
+
+def test_rank_cap_with_two_sides(bf):
+    """A rank-cap failure with the sides on two threads: the row side stops in
+    its leaf loop (leaves of 64 sources need r above 8), the column side
+    (leaves of 4 targets) later at an R level; the call raises BF_ERANK as in
+    the one-stream run whichever thread fails first, and the next
+    constructions are unaffected."""
+    g = wl.segment_pair(2048, ppw=8.0, m=128)
+    op = bf.segkernel(g.targets, g.sources, g.k)
+    say("row-side error")
+    for two in (True, False):
+        with pytest.raises(bf.BFError) as ei:
+            bf.construct(op, 1e-6, 64, seed=1, max_rank=8, two_sides=two)
+        assert ei.value.code == -4
+    H = bf.construct(op, 1e-6, 64, seed=1)
+    H2 = bf.construct(op, 1e-6, 64, seed=1, two_sides=False)
+    assert np.array_equal(H.export(), H2.export())
+    H.close()
+    H2.close()
