@@ -678,6 +678,97 @@ __global__ __launch_bounds__(256) void apply_mfma_wave_kernel(const ApplyBlk* __
   }
 }
 
+// The same work for stages of few blocks (every wave of the stage resident at
+// once, so the stage lasts one wave's chain of memory trips): each 32-term
+// chunk issues its B-operand loads and the A-operand loads of all RT row
+// tiles before any arithmetic, one trip per chunk instead of one per row
+// tile.  The extra live registers cost a wave per SIMD, which stages of
+// many blocks need more.  Same operands, products and order: same bits.
+template <int RT>
+__global__ __launch_bounds__(256) void apply_mfma_wave_lf_kernel(const ApplyBlk* __restrict__ blks,
+                                                                 int32_t nblk,
+                                                                 const bf_c64* __restrict__ G,
+                                                                 ApplyBufs B, int64_t ncols,
+                                                                 int32_t ctw) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t bi = (int64_t)blockIdx.x * 4 + wave;
+  if (bi >= nblk) return;
+  const ApplyBlk bk = blks[bi];
+  const int M = bk.M, K0 = bk.K0, KK = bk.K0 + bk.K1;
+  const int lc = lane & 15, kq = lane >> 4;
+  const int rt_n = (M + 15) >> 4;   // at most RT
+  const bf_c64* gb = G + bk.g_off;
+  const int64_t rs0 = B.rs[bk.in_buf0], rs1 = B.rs[bk.in_buf1];
+  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0 * rs0;
+  const bf_c64* in1 = B.p[bk.in_buf1] + (bk.in_row1 - K0) * rs1;   // indexed by k >= K0
+  const int64_t ld0 = B.ld[bk.in_buf0], ld1 = B.ld[bk.in_buf1];
+  const int64_t rso = B.rs[bk.out_buf], ldo = B.ld[bk.out_buf];
+  bf_c64* ob = B.p[bk.out_buf] + bk.out_row * rso;
+  const int64_t cbeg = (int64_t)blockIdx.y * ctw * 16;
+  const int64_t cend = cbeg + (int64_t)ctw * 16 < ncols ? cbeg + (int64_t)ctw * 16 : ncols;
+  for (int64_t c0 = cbeg; c0 < cend; c0 += 16) {
+    const int64_t col = c0 + lc;
+    const bool cv = col < ncols;
+    afloatx4 R[RT], I[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) { R[t] = afloatx4{0.f, 0.f, 0.f, 0.f}; I[t] = R[t]; }
+    for (int k0 = 0; k0 < KK; k0 += AM_KT) {
+      const int kb = k0 + 8 * kq;
+      bf_c64 xv[8], gv[RT][8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kb + e;
+        bf_c64 x = {0.f, 0.f};
+        if (cv && k < KK) x = k < K0 ? in0[col * ld0 + k * rs0] : in1[col * ld1 + k * rs1];
+        xv[e] = x;
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int r = t * 16 + lc;
+        const bf_c64* grow = gb + (int64_t)r * KK;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          gv[t][e] = (r < M && kb + e < KK) ? grow[kb + e] : bf_c64{0.f, 0.f};
+      }
+      au32x4 xb[6];
+      am_split8(xv, xb);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        if (t < rt_n) {
+          au32x4 ga[6], gn[3];
+          am_split8(gv[t], ga);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) gn[q] = ga[2 * q + 1] ^ 0x80008000u;
+#define AM_MM(A, Bv, C) \
+  C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(abf16x8, A), \
+                                              __builtin_bit_cast(abf16x8, Bv), C, 0, 0, 0);
+#define AM_PAIR(P, Q) AM_MM(ga[2 * P], xb[2 * Q], R[t]) AM_MM(gn[P], xb[2 * Q + 1], R[t]) \
+                      AM_MM(ga[2 * P], xb[2 * Q + 1], I[t]) AM_MM(ga[2 * P + 1], xb[2 * Q], I[t])
+          AM_PAIR(2, 0) AM_PAIR(0, 2) AM_PAIR(1, 1) AM_PAIR(1, 0) AM_PAIR(0, 1) AM_PAIR(0, 0)
+#undef AM_PAIR
+#undef AM_MM
+        }
+      }
+    }
+    if (cv) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = t * 16 + 4 * kq + v;
+          if (t < rt_n && r < M) ob[col * ldo + r * rso] = bf_c64{R[t][v], I[t][v]};
+        }
+    }
+  }
+}
+
+template <int RT>
+static void launch_wave_lf(dim3 grid, hipStream_t s, const ApplyBlk* blks, int32_t nblk,
+                           const bf_c64* G, const ApplyBufs& B, int64_t ncols, int32_t ctw) {
+  hipLaunchKernelGGL((apply_mfma_wave_lf_kernel<RT>), grid, dim3(256), 0, s, blks, nblk, G, B,
+                     ncols, ctw);
+}
+
 // ---- fused stages (few right-hand sides) ---------------------------------
 //
 // One launch runs several consecutive stages.  The blocks of those stages
@@ -1203,8 +1294,17 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
         if (c) {
           const int64_t gy = (nct + c - 1) / c;
           BF_CHECK(gy <= 65535, BF_EINVAL, "too many right-hand sides");
-          hipLaunchKernelGGL(apply_mfma_wave_kernel, dim3((unsigned)((nblk + 3) / 4), (unsigned)gy),
-                             dim3(256), 0, s, blks_dev, nblk, G, B, ncols, (int32_t)c);
+          const dim3 grid((unsigned)((nblk + 3) / 4), (unsigned)gy);
+          const int rt = (maxM + 15) / 16;
+          if (nblk * gy >= 4096)
+            hipLaunchKernelGGL(apply_mfma_wave_kernel, grid, dim3(256), 0, s, blks_dev, nblk, G, B,
+                               ncols, (int32_t)c);
+          else if (rt == 2)
+            launch_wave_lf<2>(grid, s, blks_dev, nblk, G, B, ncols, (int32_t)c);
+          else if (rt == 3)
+            launch_wave_lf<3>(grid, s, blks_dev, nblk, G, B, ncols, (int32_t)c);
+          else
+            launch_wave_lf<4>(grid, s, blks_dev, nblk, G, B, ncols, (int32_t)c);
         } else {
           wg();
         }
