@@ -11,8 +11,11 @@ r0 = 4.  Each step uses a fresh seed (a new construction request); inputs
 timed back to back (closed loop); the line reports factorizations/s, p50/p99
 latency, the relative error of the last factorization against the FP64
 oracle on sampled rows (16 Gaussian test columns, Sec. 6 error measure), the
-roofline of the dominant kernel measured with HIP events over the timed
-region, and the FP64 oracle timed on a bounded sample on the host.
+roofline of the dominant kernel measured with HIP events on each of its
+launches (over --roofline-steps further constructions of the same workload on
+one stream: the timed loop runs each construction's two sides side by side,
+so its black-box launches share the device and each one's events would span
+the other's work), and the FP64 oracle timed on a bounded sample on the host.
 """
 from __future__ import annotations
 
@@ -55,6 +58,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--roofline-steps", type=int, default=2,
+                    help="one-stream constructions after the timed loop whose kernels give the "
+                         "roofline and the per-phase times (each kernel alone on the device)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--ppw", type=float, default=8.0)
@@ -762,7 +768,6 @@ def main():
 
     lat = []
     last = None
-    bf.profile_start()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -775,9 +780,18 @@ def main():
         last = F
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = bf.profile_stop()
     total = t1 - t0
     info = last.stats()
+    # kernel roofline and phase split: further constructions of the same
+    # workload on one stream, each kernel timed by its own HIP events with no
+    # other kernel sharing the device (the two sides of the timed loop run
+    # their black-box launches side by side, which stretches each launch)
+    bf.profile_start()
+    torch.cuda.synchronize()
+    for k in range(args.roofline_steps):
+        bf.construct(op, args.tol, args.leaf, seed=3 + args.steps + k, two_sides=False).close()
+    torch.cuda.synchronize()
+    prof = bf.profile_stop()
     passes = info.v_iters + info.u_iters + info.L
 
     per_request_fs = args.steps / total
@@ -906,7 +920,8 @@ def main():
             "avg_launch_ms": mf["ms"] / max(1, mf["launches"]),
             "launches": mf["launches"],
         },
-        "phase_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
+        "phase_ms_per_step": {k: v["ms"] / max(1, args.roofline_steps) for k, v in prof.items()},
+        "roofline_steps": args.roofline_steps,
         "apply_roofline": apply_rl,
         "apply_roofline_c5": c5,
         "cpu_baseline": cpu,
