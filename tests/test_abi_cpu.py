@@ -59,6 +59,16 @@ def test_precision_enum_matches_header():
     assert vals == {"BF_PREC_FP64": 0, "BF_PREC_BF16X3": 1, "BF_PREC_FP32": 2}
 
 
+def test_option_flags_match_header():
+    """The bf_opts flag bits the binding passes are the header's."""
+    text = open(HEADER).read()
+    flags = dict((k, int(v)) for k, v in re.findall(r"(BF_OPT_[A-Z_]+)\s*=\s*(\d+)", text))
+    assert flags == {"BF_OPT_CENTER_LEVEL": 1, "BF_OPT_SEQUENTIAL_LEAF": 2,
+                     "BF_OPT_SEQUENTIAL_SWEEP": 4, "BF_OPT_ONE_STREAM": 8}
+    for k, v in flags.items():
+        assert getattr(bf, k) == v
+
+
 def test_error_codes_match_header():
     text = open(HEADER).read()
     codes = dict((k, int(v)) for k, v in re.findall(r"(BF_E[A-Z]+)\s*=\s*(-\d+)", text))
