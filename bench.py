@@ -726,32 +726,46 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the build targets a single MI355X)", file=sys.stderr)
         sys.exit(2)
+    if run_mode(args):
+        if args.save_tune:
+            import paper_2002_03400_amd as bf
+            bf.autotune_save(args.save_tune)
+        return
+    headline(args)
+
+
+def run_mode(args):
+    """The measurement modes other than the headline line; True if one ran."""
     if args.copy_calibration:
         copy_calibration()
-        return
+        return True
     if args.apply_burst:
         apply_burst(args)
-        return
+        return True
     if args.variants:
         variants([int(x) for x in args.variants.split(",")])
-        return
+        return True
     if args.precision_form:
         precision_form(args.precision_form)
-        return
+        return True
     if args.compose:
         compose(args.compose)
-        return
+        return True
     if args.em3d:
         em3d([tuple(int(x) for x in e.split(":")) for e in args.em3d.split(",")],
              [float(t) for t in args.em3d_tols.split(",")])
-        return
+        return True
     if args.exact_scaling:
         cases = []
         for e in args.exact_scaling.split(","):
             f = [int(x) for x in e.split(":")]
             cases.append((f[0], f[1], f[2]) if len(f) == 3 else (f[0], 8, 8))
         exact_scaling(cases)
-        return
+        return True
+    return False
+
+
+def headline(args):
     import torch
 
     import paper_2002_03400_amd as bf

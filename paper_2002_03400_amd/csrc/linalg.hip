@@ -86,8 +86,8 @@ __device__ __forceinline__ void cg_accum(cd* acc, const cd (*fs)[ROWS], const Ti
   }
 }
 
-// ROWS x KT entries of op(F) in LDS: 20 / 24 / 32 x 64 or 64 x 32 (at most
-// 32 KB).  Each wave owns ROWS / 4 rows, so a ROWS close above the launch's
+// ROWS x KT entries of op(F) in LDS: 20 / 24 / 32 x 64 or 40 / 48 / 64 x 32
+// (at most 32 KB).  Each wave owns ROWS / 4 rows, so a ROWS close above the launch's
 // largest M leaves few idle row slots (M = 19 on 20 rows instead of 32).
 template <typename Tin, int ROWS>
 __global__ __launch_bounds__(256) void chain_gemm_kernel(const GemmDesc* __restrict__ descs) {
@@ -190,8 +190,10 @@ __global__ __launch_bounds__(256) void chain_small_kernel(const GemmDesc* __rest
 }
 
 // One launch with tile height `rows`: 8 or 16 (chain_small_kernel, every
-// descriptor's M at most that) or 20 / 24 / 32 / 64 (chain_gemm_kernel, row
-// blocks of that height).  Every height gives the same FP64 operation order.
+// descriptor's M at most that) or 20 / 24 / 32 / 40 / 48 / 64
+// (chain_gemm_kernel, row blocks of that height: ranks of 33 to 48 leave
+// fewer idle rows on 40 or 48 than on 64).  Every height gives the same FP64
+// operation order.
 template <typename Tin>
 static void launch_chain_rows(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols, int rows,
                               hipStream_t s) {
@@ -215,6 +217,10 @@ static void launch_chain_rows(const GemmDesc* d_dev, int32_t ndesc, int32_t max_
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 24>), grid, dim3(256), 0, s, d_dev);
   else if (rows <= 32)
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 32>), grid, dim3(256), 0, s, d_dev);
+  else if (rows <= 40)
+    hipLaunchKernelGGL((chain_gemm_kernel<Tin, 40>), grid, dim3(256), 0, s, d_dev);
+  else if (rows <= 48)
+    hipLaunchKernelGGL((chain_gemm_kernel<Tin, 48>), grid, dim3(256), 0, s, d_dev);
   else
     hipLaunchKernelGGL((chain_gemm_kernel<Tin, 64>), grid, dim3(256), 0, s, d_dev);
 }
@@ -225,7 +231,7 @@ template <typename Tin>
 static void launch_chain_t(const GemmDesc* d_dev, int32_t ndesc, int32_t max_ncols,
                            int32_t max_M, hipStream_t s) {
   std::vector<int64_t> cand;
-  for (int h : {8, 16, 20, 24, 32, 64})
+  for (int h : {8, 16, 20, 24, 32, 40, 48, 64})
     if (h >= max_M) cand.push_back(h);
   if (cand.empty()) cand = {32, 64};
   const TuneKey key{kTuneChainRows, sizeof(Tin) == sizeof(bf_c64) ? 1 : 0, max_M,

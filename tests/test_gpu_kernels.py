@@ -203,7 +203,7 @@ def test_autotuned_tile_widths_do_not_change_products(bf):
 
 
 # candidates of each tuned family (include/bf.h, bf_set_autotune)
-TUNE_CANDIDATES = {"matfree_width": [48, 64, 80], "chain_rows": [8, 16, 20, 24, 32, 64],
+TUNE_CANDIDATES = {"matfree_width": [48, 64, 80], "chain_rows": [8, 16, 20, 24, 32, 40, 48, 64],
                    "cpqr_threads": [256, 512], "apply_fused": [1, 0],
                    "apply_rows": [1, 0, 2, 4, 9, 10, 17, 49, 25, 57],
                    "apply_mfma": [1, 2, 0]}
