@@ -545,7 +545,7 @@ int bf_op_set_precision(bf_operator* op, int precision);
  *                           than 48 columns (class: operator kind, column
  *                           count, powers of two above the row count, inner
  *                           length and segment count);
- *   chain tile height     : 8, 16, 20, 24, 32 or 64 rows, at least the
+ *   chain tile height     : 8, 16, 20, 24, 32, 40, 48 or 64 rows, at least the
  *                           launch's largest block (class: input type,
  *                           largest block, powers of two above the block and
  *                           column counts);
