@@ -625,10 +625,17 @@ static int factors_apply(void* user, int trans, const bf_c64* X, int64_t ldx, in
       apply_factors(c->F, trans, X, ldx, ncols, Y, ldy, s);
       return;
     }
-    // segments in chunks: the expanded input and the apply's two intermediates
-    // take 8 (rows_in + 2 tmp_rows) bytes per expanded column; keep them
-    // under 4 GiB per chunk
     const ApplyPlan& P = trans ? c->F->adj : c->F->fwd;
+    // segments that are nodes of the input-side tree: the stages that keep
+    // them apart run once on X (two intermediates of 8 tmp_rows bytes per
+    // column for the rest, at most 4 GiB)
+    const int64_t tree_cols =
+        std::max<int64_t>(ncols, (int64_t)((double)(int64_t(4) << 30) / (16.0 * (double)P.tmp_rows)));
+    if (apply_structured(c->F, trans, X, ldx, ncols, Y, ldy, seg, nseg, tree_cols, s))
+      return;
+    // other segments in chunks: the expanded input and the apply's two
+    // intermediates take 8 (rows_in + 2 tmp_rows) bytes per expanded column;
+    // keep them under 4 GiB per chunk
     const double per_col = 8.0 * (double)(rows_in + 2 * P.tmp_rows);
     const int64_t max_cols = std::max<int64_t>(ncols, (int64_t)((double)(int64_t(4) << 30) / per_col));
     const int32_t per_chunk = (int32_t)std::max<int64_t>(1, max_cols / std::max<int64_t>(ncols, 1));

@@ -362,6 +362,13 @@ void launch_expand_segments(const bf_c64* X, int64_t ldx, int64_t rows, int64_t 
                             const int64_t* seg_dev, int32_t nseg, bf_c64* out, int64_t ldo,
                             hipStream_t s);
 
+// E(r, (g - g0) s + c) = C(r, c) for rows r of segment g (rowseg[r] = g, -1:
+// none), zero in every other column of E (rows x ng s); element (r, c) of C
+// at C[r crs + c cld], of E at E[r ers + col eld].
+void launch_expand_by_segment(const bf_c64* C, int64_t crs, int64_t cld, const int32_t* rowseg,
+                              int64_t rows, int32_t s, int32_t g0, int32_t ng, bf_c64* E,
+                              int64_t ers, int64_t eld, hipStream_t st);
+
 // -------------------------------------------------------------- autotuner --
 // Family, then kTuneKeyFields class fields (powers of two of the sizes that
 // matter, column counts, flags).  tune_choose runs run(c) for the class's

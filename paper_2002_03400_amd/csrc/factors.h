@@ -32,6 +32,13 @@ struct Stage {
   int32_t nrows = 0;
   int32_t maxMK = 0, maxKK = 0, maxM = 0;
   double macs = 0;   // complex multiply-adds per right-hand side
+  // level of the input-side tree node each output block belongs to (the
+  // source tree for the forward apply, the target tree for the adjoint; the
+  // node indices are ApplyPlan::node): a structured sample whose segments are
+  // nodes at level tl stays within its segments through every stage with
+  // level >= tl.  -1: the output rows mix all of them (the last stage).
+  int32_t level = -1;
+  int32_t out_buf = 0;   // buffer the stage writes (1, 2: intermediates; 3: output)
 };
 
 // Consecutive stages run as one launch (launch_apply_fused): workgroup w
@@ -50,6 +57,11 @@ struct ApplyPlan {
   DevBuf<ApplyRowRec> rows;      // output rows of all stages (few right-hand sides)
   std::vector<Stage> stages;     // in execution order
   int64_t tmp_rows = 0;          // rows of each ping-pong intermediate
+  // host copies of every block's output rows and input-side tree node (see
+  // Stage::level), for applies to structured samples
+  std::vector<int64_t> out_row;
+  std::vector<int32_t> out_m;
+  std::vector<int64_t> node;
   // fused schedule (few right-hand sides): every stage but the last writes its
   // own rows of one tall intermediate of fused_rows rows
   DevBuf<ApplyRowRec> frows;     // row records grouped by segment, workgroup, stage
@@ -119,6 +131,16 @@ void run_apply(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int
 // Apply (Y = F X or F^H X), complex64.
 void apply_factors(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,
                    bf_c64* Y, int64_t ldy, hipStream_t s);
+// Structured samples (Sec. 4.1) through the factors: Y[:, g ncols + c] =
+// op(F)(:, seg_g) X(seg_g, c) for the nseg row segments of X.  When the
+// segments are consecutive nodes of one level of the input-side tree, the
+// stages that keep every segment apart run once on X itself (ncols columns:
+// each of their output rows belongs to one segment), and only the later
+// stages run on the block-diagonal expansion (nseg ncols columns, in chunks
+// of at most max_cols).  Returns false (nothing launched) for other segments.
+bool apply_structured(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                      int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg, int32_t nseg,
+                      int64_t max_cols, hipStream_t s);
 // bf_apply_noalloc: run_apply with the intermediates in the library's fixed
 // per-device scratch array (noalloc.hip); BF_EINVAL if they do not fit.
 void apply_noalloc(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx, int64_t ncols,

@@ -723,4 +723,40 @@ void launch_expand_segments(const bf_c64* X, int64_t ldx, int64_t rows, int64_t 
   BF_HIP(hipGetLastError());
 }
 
+// E(r, (g - g0) s + c) = C(r, c) for the rows r of segment g (rowseg[r] = g,
+// g0 <= g < g0 + ng), zero elsewhere: the block-diagonal expansion of an
+// intermediate whose rows each belong to one segment.  Element (r, c) of C is
+// C[r crs + c cld], element (r, col) of E is E[r ers + col eld].  Consecutive
+// threads take consecutive columns of one row (row-major E) or consecutive
+// rows of one column (column-major E).
+__global__ void expand_by_segment_kernel(const bf_c64* __restrict__ C, int64_t crs, int64_t cld,
+                                         const int32_t* __restrict__ rowseg, int64_t rows,
+                                         int32_t s, int32_t g0, int32_t ng, bf_c64* __restrict__ E,
+                                         int64_t ers, int64_t eld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t w = (int64_t)ng * s;
+  if (idx >= rows * w) return;
+  int64_t r, col;
+  if (eld == 1) {
+    r = idx / w;
+    col = idx % w;
+  } else {
+    col = idx / rows;
+    r = idx % rows;
+  }
+  const int64_t g = col / s, c = col % s;
+  bf_c64 v = {0.f, 0.f};
+  if (rowseg[r] == g0 + g) v = C[r * crs + c * cld];
+  E[r * ers + col * eld] = v;
+}
+void launch_expand_by_segment(const bf_c64* C, int64_t crs, int64_t cld, const int32_t* rowseg,
+                              int64_t rows, int32_t s, int32_t g0, int32_t ng, bf_c64* E,
+                              int64_t ers, int64_t eld, hipStream_t st) {
+  const int64_t tot = rows * (int64_t)ng * s;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(expand_by_segment_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                     st, C, crs, cld, rowseg, rows, s, g0, ng, E, ers, eld);
+  BF_HIP(hipGetLastError());
+}
+
 }  // namespace bf

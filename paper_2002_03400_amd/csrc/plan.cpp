@@ -57,8 +57,12 @@ struct PlanBuilder {
   int cur_in = 0, cur_out = 1;
   Stage cur;
 
-  void begin(int in, int out) {
+  std::vector<int64_t> node;   // input-side tree node of every block (Stage::level)
+
+  void begin(int in, int out, int level = -1) {
     cur = Stage{};
+    cur.level = level;
+    cur.out_buf = out;
     cur.blk_off = (int64_t)blks.size();
     cur.row_off = nrows;
     cur_in = in;
@@ -70,8 +74,9 @@ struct PlanBuilder {
   }
   // out rows [out_row, out_row + M) = sum of the terms; the terms' factor
   // slices are packed side by side into one row-major M x (K0 + K1) block
-  void add(int64_t out_row, int M, const TermSpec* t, int nt) {
+  void add(int64_t out_row, int M, const TermSpec* t, int nt, int64_t nd = 0) {
     if (M <= 0) return;
+    node.push_back(nd);
     const int K0 = nt > 0 ? t[0].K : 0, K1 = nt > 1 ? t[1].K : 0;
     const int KK = K0 + K1;
     ApplyBlk bk{};
@@ -335,6 +340,13 @@ void finish(PlanBuilder& pb, ApplyPlan& plan, int64_t tmp_rows, hipStream_t s,
   launch_expand_rows(plan.blks.p, (int32_t)pb.blks.size(), plan.rows.p, s);
   plan.stages = pb.stages;
   plan.tmp_rows = std::max<int64_t>(tmp_rows, 1);
+  plan.out_row.resize(pb.blks.size());
+  plan.out_m.resize(pb.blks.size());
+  for (size_t b = 0; b < pb.blks.size(); ++b) {
+    plan.out_row[b] = pb.blks[b].out_row;
+    plan.out_m[b] = pb.blks[b].M;
+  }
+  plan.node = pb.node;
   for (size_t o = 0; o < pb.packs.size(); o += 60000) {
     size_t cnt = std::min<size_t>(60000, pb.packs.size() - o);
     std::vector<PackDesc> part(pb.packs.begin() + o, pb.packs.begin() + o + cnt);
@@ -362,37 +374,37 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
   {
     PlanBuilder pb{F};
     int a = 1, b = 2;
-    pb.begin(0, a);
+    pb.begin(0, a, L);
     for (int64_t j = 0; j < (int64_t(1) << L); ++j) {
       const Block& V = F->V[j];
       TermSpec t = pb.term(V, 0, V.cols, V.rows, 1, node_lo(n, L, j));
-      pb.add(iv[0].off[j], V.cols, &t, 1);
+      pb.add(iv[0].off[j], V.cols, &t, 1, j);
     }
     pb.end();
     for (int l = 1; l <= lm; ++l) {
-      pb.begin(a, b);
+      pb.begin(a, b, L - l);
       for (int64_t i = 0; i < (int64_t(1) << l); ++i)
         for (int64_t j = 0; j < (int64_t(1) << (L - l)); ++j) {
           const Block& Wb = F->W[l][bidx(l, i, j)];
           const int ka = F->kv(l - 1, i >> 1, 2 * j), kb = F->kv(l - 1, i >> 1, 2 * j + 1);
           TermSpec t[2] = {pb.term(Wb, 0, Wb.cols, ka, 1, iv[l - 1].off[bidx(l - 1, i >> 1, 2 * j)]),
                             pb.term(Wb, ka, Wb.cols, kb, 1, iv[l - 1].off[bidx(l - 1, i >> 1, 2 * j + 1)])};
-          pb.add(iv[l].off[bidx(l, i, j)], Wb.cols, t, 2);
+          pb.add(iv[l].off[bidx(l, i, j)], Wb.cols, t, 2, j);
         }
       pb.end();
       std::swap(a, b);
     }
-    pb.begin(a, b);
+    pb.begin(a, b, L - lm);
     for (int64_t i = 0; i < (int64_t(1) << lm); ++i)
       for (int64_t j = 0; j < (int64_t(1) << (L - lm)); ++j) {
         const Block& Bb = F->B[bidx(lm, i, j)];
         TermSpec t = pb.term(Bb, 0, Bb.rows, Bb.cols, 0, iv[lm].off[bidx(lm, i, j)]);
-        pb.add(iu[lm].off[bidx(lm, i, j)], Bb.rows, &t, 1);
+        pb.add(iu[lm].off[bidx(lm, i, j)], Bb.rows, &t, 1, j);
       }
     pb.end();
     std::swap(a, b);
     for (int l = lm; l < L; ++l) {
-      pb.begin(a, b);
+      pb.begin(a, b, L - l - 1);
       for (int64_t ic = 0; ic < (int64_t(1) << (l + 1)); ++ic)
         for (int64_t jc = 0; jc < (int64_t(1) << (L - l - 1)); ++jc) {
           const int64_t i = ic >> 1;
@@ -404,7 +416,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
             const int k1 = F->ku(l + 1, 2 * i, jc);
             t[q] = pb.term(Rb, (ic & 1) ? k1 : 0, Mo, Rb.cols, 0, iu[l].off[bidx(l, i, j)]);
           }
-          pb.add(iu[l + 1].off[bidx(l + 1, ic, jc)], Mo, t, 2);
+          pb.add(iu[l + 1].off[bidx(l + 1, ic, jc)], Mo, t, 2, jc);
         }
       pb.end();
       std::swap(a, b);
@@ -423,37 +435,37 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
   {
     PlanBuilder pb{F};
     int a = 1, b = 2;
-    pb.begin(0, a);
+    pb.begin(0, a, L);
     for (int64_t i = 0; i < (int64_t(1) << L); ++i) {
       const Block& U = F->U[i];
       TermSpec t = pb.term(U, 0, U.cols, U.rows, 1, node_lo(m, L, i));
-      pb.add(iu[L].off[i], U.cols, &t, 1);
+      pb.add(iu[L].off[i], U.cols, &t, 1, i);
     }
     pb.end();
     for (int l = L - 1; l >= lm; --l) {
-      pb.begin(a, b);
+      pb.begin(a, b, l);
       for (int64_t i = 0; i < (int64_t(1) << l); ++i)
         for (int64_t j = 0; j < (int64_t(1) << (L - l)); ++j) {
           const Block& Rb = F->R[l - lm][bidx(l, i, j)];
           const int k1 = F->ku(l + 1, 2 * i, j >> 1), k2 = F->ku(l + 1, 2 * i + 1, j >> 1);
           TermSpec t[2] = {pb.term(Rb, 0, Rb.cols, k1, 1, iu[l + 1].off[bidx(l + 1, 2 * i, j >> 1)]),
                             pb.term(Rb, k1, Rb.cols, k2, 1, iu[l + 1].off[bidx(l + 1, 2 * i + 1, j >> 1)])};
-          pb.add(iu[l].off[bidx(l, i, j)], Rb.cols, t, 2);
+          pb.add(iu[l].off[bidx(l, i, j)], Rb.cols, t, 2, i);
         }
       pb.end();
       std::swap(a, b);
     }
-    pb.begin(a, b);
+    pb.begin(a, b, lm);
     for (int64_t i = 0; i < (int64_t(1) << lm); ++i)
       for (int64_t j = 0; j < (int64_t(1) << (L - lm)); ++j) {
         const Block& Bb = F->B[bidx(lm, i, j)];
         TermSpec t = pb.term(Bb, 0, Bb.cols, Bb.rows, 1, iu[lm].off[bidx(lm, i, j)]);
-        pb.add(iv[lm].off[bidx(lm, i, j)], Bb.cols, &t, 1);
+        pb.add(iv[lm].off[bidx(lm, i, j)], Bb.cols, &t, 1, i);
       }
     pb.end();
     std::swap(a, b);
     for (int l = lm; l >= 1; --l) {
-      pb.begin(a, b);
+      pb.begin(a, b, l - 1);
       for (int64_t ip = 0; ip < (int64_t(1) << (l - 1)); ++ip)
         for (int64_t jp = 0; jp < (int64_t(1) << (L - l + 1)); ++jp) {
           const int64_t j = jp >> 1;
@@ -465,7 +477,7 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
             const int ka = F->kv(l - 1, ip, 2 * j);
             t[q] = pb.term(Wb, (jp & 1) ? ka : 0, Mo, Wb.cols, 0, iv[l].off[bidx(l, i, j)]);
           }
-          pb.add(iv[l - 1].off[bidx(l - 1, ip, jp)], Mo, t, 2);
+          pb.add(iv[l - 1].off[bidx(l - 1, ip, jp)], Mo, t, 2, ip);
         }
       pb.end();
       std::swap(a, b);
@@ -481,20 +493,26 @@ void build_apply_plans(bf_factors* F, hipStream_t s) {
   }
 }
 
-// The L+3 stage launches of one apply on stream s (buffers: X, two
-// intermediates, Y).
-static void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
-                      int64_t ncols, bf_c64* Y, int64_t ldy, bf_c64* t1, bf_c64* t2,
-                      hipStream_t s, bool prof) {
-  const ApplyPlan& P = trans ? F->adj : F->fwd;
-  const bf_c64* bufs[4] = {X, t1, t2, Y};
-  // intermediates row-major above the few-column path (see launch_apply_stage)
+// Layout of an intermediate of an apply with ncols columns: row-major above
+// the few-column path (see launch_apply_stage), else column-major.
+static void tmp_layout(const ApplyPlan& P, int64_t ncols, int64_t* ld, int64_t* rs) {
   const bool rowmajor = ncols > kApplyFewCols;
-  const int64_t tld = rowmajor ? 1 : P.tmp_rows, trs = rowmajor ? ncols : 1;
+  *ld = rowmajor ? 1 : P.tmp_rows;
+  *rs = rowmajor ? ncols : 1;
+}
+
+// Stage launches [k0, k1) of one apply on stream s (buffers: X, two
+// intermediates, Y; every intermediate in tmp_layout for ncols).
+static void run_stage_range(const bf_factors* F, int trans, size_t k0, size_t k1,
+                            const bf_c64* const bufs[4], int64_t ldx, int64_t ldy, int64_t ncols,
+                            hipStream_t s, bool prof) {
+  const ApplyPlan& P = trans ? F->adj : F->fwd;
+  int64_t tld, trs;
+  tmp_layout(P, ncols, &tld, &trs);
   const int64_t lds[4] = {ldx, tld, tld, ldy};
   const int64_t rss[4] = {1, trs, trs, 1};
   const int64_t rin = trans ? F->m : F->n, rout = trans ? F->n : F->m;
-  for (size_t k = 0; k < P.stages.size(); ++k) {
+  for (size_t k = k0; k < k1; ++k) {
     const Stage& st = P.stages[k];
     // algorithmic bytes: this stage's factor entries once, plus the caller's
     // input (first stage) and output (last stage); intermediates excluded
@@ -513,6 +531,16 @@ static void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, in
       launch();
     }
   }
+}
+
+// The L+3 stage launches of one apply on stream s (buffers: X, two
+// intermediates, Y).
+static void run_apply_stages(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                      int64_t ncols, bf_c64* Y, int64_t ldy, bf_c64* t1, bf_c64* t2,
+                      hipStream_t s, bool prof) {
+  const ApplyPlan& P = trans ? F->adj : F->fwd;
+  const bf_c64* bufs[4] = {X, t1, t2, Y};
+  run_stage_range(F, trans, 0, P.stages.size(), bufs, ldx, ldy, ncols, s, prof);
 }
 
 // The fused launches of one apply (ncols <= kApplyFusedCols): intermediates
@@ -709,6 +737,74 @@ static bool apply_graph(const bf_factors* F, int trans, const bf_c64* X, int64_t
   BF_HIP(hipGraphLaunch(exec, s));
   BF_HIP(hipMemcpy2DAsync(Y, ldy * sizeof(bf_c64), Ys, rout * sizeof(bf_c64),
                           rout * sizeof(bf_c64), ncols, hipMemcpyDeviceToDevice, s));
+  return true;
+}
+
+bool apply_structured(const bf_factors* F, int trans, const bf_c64* X, int64_t ldx,
+                      int64_t ncols, bf_c64* Y, int64_t ldy, const int64_t* seg, int32_t nseg,
+                      int64_t max_cols, hipStream_t s) {
+  const ApplyPlan& P = trans ? F->adj : F->fwd;
+  const int64_t rin = trans ? F->m : F->n;
+  if (ncols <= 0 || nseg < 2 || P.stages.size() < 2) return false;
+  // the level tl whose consecutive nodes i0, i0 + 1, ... the segments are
+  int tl = -1;
+  int64_t i0 = 0;
+  for (int l = 1; l <= F->L && tl < 0; ++l) {
+    // node_lo(rin, l, i) = floor(i rin / 2^l): seg[0]'s node is one of two
+    const int64_t q = (seg[0] << l) / rin;
+    for (int64_t first = q; first <= q + 1 && tl < 0; ++first) {
+      bool ok = first >= 0 && first + nseg <= (int64_t(1) << l);
+      for (int32_t g = 0; ok && g <= nseg; ++g) ok = seg[g] == node_lo(rin, l, first + g);
+      if (ok) {
+        tl = l;
+        i0 = first;
+      }
+    }
+  }
+  if (tl < 0) return false;
+  // stages [0, ks) keep every segment apart
+  size_t ks = 0;
+  while (ks < P.stages.size() && P.stages[ks].level >= tl) ++ks;
+  if (ks == 0 || ks == P.stages.size()) return false;
+  const Stage& last = P.stages[ks - 1];
+  // segment (relative to i0) of every intermediate row written by stage ks - 1
+  std::vector<int32_t> rowseg((size_t)P.tmp_rows, -1);
+  for (int64_t b = last.blk_off; b < last.blk_off + last.nblk; ++b) {
+    const int64_t g = (P.node[(size_t)b] >> (last.level - tl)) - i0;
+    if (g < 0 || g >= nseg) continue;
+    for (int64_t r = P.out_row[(size_t)b]; r < P.out_row[(size_t)b] + P.out_m[(size_t)b]; ++r)
+      rowseg[(size_t)r] = (int32_t)g;
+  }
+  Staging local;
+  Staging& st = scope_staging(s) ? *scope_staging(s) : local;
+  auto rs_dev = upload(rowseg, s, st);
+  // stages [0, ks) on X itself
+  const size_t one = (size_t)P.tmp_rows * (size_t)ncols;
+  DevBuf<bf_c64> c1(one, s), c2(one, s);
+  {
+    const bf_c64* bufs[4] = {X, c1.p, c2.p, nullptr};
+    run_stage_range(F, trans, 0, ks, bufs, ldx, ldy, ncols, s, true);
+  }
+  const bf_c64* C = last.out_buf == 1 ? c1.p : c2.p;
+  int64_t cld, crs;
+  tmp_layout(P, ncols, &cld, &crs);
+  // stages [ks, end) on the block-diagonal expansion, nseg_c segments at a time
+  const int32_t per = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nseg, max_cols / ncols));
+  const int64_t wcols = (int64_t)per * ncols;
+  DevBuf<bf_c64> e1((size_t)P.tmp_rows * (size_t)wcols, s), e2((size_t)P.tmp_rows * (size_t)wcols, s);
+  for (int32_t g0 = 0; g0 < nseg; g0 += per) {
+    const int32_t ng = std::min(per, nseg - g0);
+    const int64_t ec = (int64_t)ng * ncols;
+    int64_t eld, ers;
+    tmp_layout(P, ec, &eld, &ers);
+    bf_c64* E = last.out_buf == 1 ? e1.p : e2.p;
+    bf_c64* T = last.out_buf == 1 ? e2.p : e1.p;
+    launch_expand_by_segment(C, crs, cld, rs_dev.p, P.tmp_rows, (int32_t)ncols, g0, ng, E, ers,
+                             eld, s);
+    const bf_c64* bufs[4] = {X, last.out_buf == 1 ? E : T, last.out_buf == 1 ? T : E,
+                             Y + (int64_t)g0 * ncols * ldy};
+    run_stage_range(F, trans, ks, P.stages.size(), bufs, ldx, ldy, ec, s, true);
+  }
   return true;
 }
 

@@ -102,3 +102,44 @@ def test_fio_construction_and_recompression(bf, n, leaf):
     assert e_re <= errs["bf16x3"] + 2 * e_or
     G.close()
     Fk.close()
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_structured_samples_through_factors(bf, trans):
+    """A butterfly as the black box of structured samples (Sec. 4.1): the
+    product for row segments that are nodes of one tree level (all of them, or
+    a run of consecutive ones, as a level split into sample groups gives) runs
+    the stages that keep the segments apart once on the sample itself.  It
+    must equal the definition of the callback: the factors applied to the
+    block-diagonal expansion of the sample -- bitwise at 5 or more columns
+    (the same matrix-core arithmetic per column), to complex64 rounding at
+    fewer (vector-ALU stages on the sample, matrix-core ones on the
+    expansion).  Segments that are not tree nodes take the expansion path."""
+    import torch
+    n, leaf = 4096, 32
+    g = wl.segment_pair(n, ppw=8.0, m=3000)
+    F = bf.construct(bf.segkernel(g.targets, g.sources, g.k), 1e-6, leaf, seed=41)
+    L = F.L
+    op = bf.from_factors(F)
+    rows_in = F.m if trans else F.n
+    lo = lambda l, i: (i * rows_in) >> l
+    cases = [[lo(1, i) for i in range(3)], [lo(3, i) for i in range(9)],
+             [lo(5, i) for i in range(3, 13)], [lo(L, i) for i in range(40, 57)],
+             [0, 100, 1000, rows_in]]   # not tree nodes
+    rng = np.random.default_rng(8)
+    for seg in cases:
+        for s in (3, 6, 20):
+            X = (rng.standard_normal((rows_in, s)) + 1j * rng.standard_normal((rows_in, s))).astype(np.complex64)
+            Xd = torch.from_numpy(X).cuda()
+            got = (op.rmatvec if trans else op.matvec)(Xd, seg=seg)
+            E = torch.zeros((rows_in, (len(seg) - 1) * s), dtype=torch.complex64, device="cuda")
+            for q in range(len(seg) - 1):
+                E[seg[q]:seg[q + 1], q * s:(q + 1) * s] = Xd[seg[q]:seg[q + 1]]
+            ref = F.apply(E, trans=trans)
+            say("structured", trans, len(seg) - 1, s)
+            if s >= 5:
+                assert bool((got == ref).all()), (seg[:3], s)
+            else:
+                err = float((got - ref).norm() / ref.norm())
+                assert err <= 1e-6, (seg[:3], s, err)
+    F.close()
