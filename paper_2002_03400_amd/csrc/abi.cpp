@@ -627,10 +627,11 @@ static int factors_apply(void* user, int trans, const bf_c64* X, int64_t ldx, in
     }
     const ApplyPlan& P = trans ? c->F->adj : c->F->fwd;
     // segments that are nodes of the input-side tree: the stages that keep
-    // them apart run once on X (two intermediates of 8 tmp_rows bytes per
-    // column for the rest, at most 4 GiB)
+    // them apart run once on X, later ones on windows of the segments below
+    // each node, the rest on the expansion (each phase two intermediates of
+    // 8 tmp_rows bytes per column, at most 16 GiB)
     const int64_t tree_cols =
-        std::max<int64_t>(ncols, (int64_t)((double)(int64_t(4) << 30) / (16.0 * (double)P.tmp_rows)));
+        std::max<int64_t>(ncols, (int64_t)((double)(int64_t(16) << 30) / (16.0 * (double)P.tmp_rows)));
     if (apply_structured(c->F, trans, X, ldx, ncols, Y, ldy, seg, nseg, tree_cols, s))
       return;
     // other segments in chunks: the expanded input and the apply's two

@@ -769,6 +769,123 @@ static void launch_wave_lf(dim3 grid, hipStream_t s, const ApplyBlk* blks, int32
                      ncols, ctw);
 }
 
+// A merging stage of a structured sample's windows (see apply_structured):
+// every intermediate row holds only the columns of the segments below its
+// node, so an output row's window is its two children's windows side by
+// side -- the first `win` columns come from term 0 (inputs k < K0, the first
+// child) and the rest from term 1 (the second child).  Each lane takes the
+// term of its own column (the B operand is per column); chunks of 32 inner
+// indices that only the other term touches are skipped.  The products are
+// those of the block-diagonal expansion, whose other entries are zeros, in
+// the same order: same bits.  One wave per block and 16-column tile.
+template <int RT>
+__global__ __launch_bounds__(256) void apply_mfma_window_kernel(const ApplyBlk* __restrict__ blks,
+                                                                int32_t nblk,
+                                                                const bf_c64* __restrict__ G,
+                                                                ApplyBufs B, int64_t ncols,
+                                                                int64_t win) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t bi = (int64_t)blockIdx.x * 4 + wave;
+  if (bi >= nblk) return;
+  const ApplyBlk bk = blks[bi];
+  const int M = bk.M, K0 = bk.K0, KK = bk.K0 + bk.K1;
+  const int lc = lane & 15, kq = lane >> 4;
+  const int rt_n = (M + 15) >> 4;   // at most RT
+  const bf_c64* gb = G + bk.g_off;
+  const int64_t rs0 = B.rs[bk.in_buf0], rs1 = B.rs[bk.in_buf1];
+  const bf_c64* in0 = B.p[bk.in_buf0] + bk.in_row0 * rs0;
+  const bf_c64* in1 = B.p[bk.in_buf1] + (bk.in_row1 - K0) * rs1;   // indexed by k >= K0
+  const int64_t ld0 = B.ld[bk.in_buf0], ld1 = B.ld[bk.in_buf1];
+  const int64_t rso = B.rs[bk.out_buf], ldo = B.ld[bk.out_buf];
+  bf_c64* ob = B.p[bk.out_buf] + bk.out_row * rso;
+  const int64_t c0 = (int64_t)blockIdx.y * 16;
+  const int64_t col = c0 + lc;
+  const bool cv = col < ncols;
+  const bool second = col >= win;   // this lane's column belongs to term 1
+  const int kbeg = c0 >= win ? (K0 / AM_KT) * AM_KT : 0;
+  const int kend = c0 + 15 < win ? K0 : KK;
+  afloatx4 R[RT], I[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) { R[t] = afloatx4{0.f, 0.f, 0.f, 0.f}; I[t] = R[t]; }
+  for (int k0 = kbeg; k0 < kend; k0 += AM_KT) {
+    const int kb = k0 + 8 * kq;
+    bf_c64 v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = kb + e;
+      bf_c64 x = {0.f, 0.f};
+      if (cv && k < KK) {
+        if (k < K0) {
+          if (!second) x = in0[col * ld0 + k * rs0];
+        } else if (second) {
+          x = in1[(col - win) * ld1 + k * rs1];
+        }
+      }
+      v[e] = x;
+    }
+    au32x4 xb[6];
+    am_split8(v, xb);
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      if (t < rt_n) {
+        const int r = t * 16 + lc;
+        const bf_c64* grow = gb + (int64_t)r * KK;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          v[e] = (r < M && kb + e < KK) ? grow[kb + e] : bf_c64{0.f, 0.f};
+        au32x4 ga[6], gn[3];
+        am_split8(v, ga);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) gn[q] = ga[2 * q + 1] ^ 0x80008000u;
+#define AM_MM(A, Bv, C) \
+  C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(abf16x8, A), \
+                                              __builtin_bit_cast(abf16x8, Bv), C, 0, 0, 0);
+#define AM_PAIR(P, Q) AM_MM(ga[2 * P], xb[2 * Q], R[t]) AM_MM(gn[P], xb[2 * Q + 1], R[t]) \
+                      AM_MM(ga[2 * P], xb[2 * Q + 1], I[t]) AM_MM(ga[2 * P + 1], xb[2 * Q], I[t])
+        AM_PAIR(2, 0) AM_PAIR(0, 2) AM_PAIR(1, 1) AM_PAIR(1, 0) AM_PAIR(0, 1) AM_PAIR(0, 0)
+#undef AM_PAIR
+#undef AM_MM
+      }
+    }
+  }
+  if (cv) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = t * 16 + 4 * kq + v;
+        if (t < rt_n && r < M) ob[col * ldo + r * rso] = bf_c64{R[t][v], I[t][v]};
+      }
+  }
+}
+
+void launch_apply_window_stage(const ApplyBlk* blks_dev, int32_t nblk, int32_t maxM,
+                               const bf_c64* G, const bf_c64* const bufs[4],
+                               const int64_t lds[4], const int64_t rss[4], int64_t ncols,
+                               int64_t win, hipStream_t s) {
+  if (nblk <= 0 || ncols <= 0) return;
+  BF_CHECK(maxM <= 64 && win > 0 && win < ncols, BF_EINVAL, "window stage: bad shape");
+  ApplyBufs B;
+  for (int i = 0; i < 4; ++i) {
+    B.p[i] = const_cast<bf_c64*>(bufs[i]);
+    B.ld[i] = lds[i];
+    B.rs[i] = rss[i];
+  }
+  const int64_t gy = (ncols + 15) / 16;
+  BF_CHECK(gy <= 65535, BF_EINVAL, "window stage: too many columns");
+  const dim3 grid((unsigned)((nblk + 3) / 4), (unsigned)gy);
+  const int rt = (maxM + 15) / 16;
+  if (rt <= 1)
+    hipLaunchKernelGGL((apply_mfma_window_kernel<1>), grid, dim3(256), 0, s, blks_dev, nblk, G, B, ncols, win);
+  else if (rt == 2)
+    hipLaunchKernelGGL((apply_mfma_window_kernel<2>), grid, dim3(256), 0, s, blks_dev, nblk, G, B, ncols, win);
+  else if (rt == 3)
+    hipLaunchKernelGGL((apply_mfma_window_kernel<3>), grid, dim3(256), 0, s, blks_dev, nblk, G, B, ncols, win);
+  else
+    hipLaunchKernelGGL((apply_mfma_window_kernel<4>), grid, dim3(256), 0, s, blks_dev, nblk, G, B, ncols, win);
+  BF_HIP(hipGetLastError());
+}
+
 // ---- fused stages (few right-hand sides) ---------------------------------
 //
 // One launch runs several consecutive stages.  The blocks of those stages

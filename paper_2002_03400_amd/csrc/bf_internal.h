@@ -326,6 +326,15 @@ void launch_apply_stage(const ApplyBlk* blks_dev, int32_t nblk, const ApplyRowRe
                         int32_t nrows, int32_t maxMK, int32_t maxKK, int32_t maxM, const bf_c64* G,
                         const bf_c64* const bufs[4], const int64_t lds[4], const int64_t rss[4],
                         int64_t ncols, int prec, hipStream_t s, bool may_time = true);
+// A merging stage on windowed intermediates of a structured sample (split-BF16
+// matrix cores, blocks of at most 64 rows): output columns [0, win) of a
+// block come from its first term and its first input's columns, columns
+// [win, ncols) from its second term and its second input's columns
+// [0, ncols - win).
+void launch_apply_window_stage(const ApplyBlk* blks_dev, int32_t nblk, int32_t maxM,
+                               const bf_c64* G, const bf_c64* const bufs[4],
+                               const int64_t lds[4], const int64_t rss[4], int64_t ncols,
+                               int64_t win, hipStream_t s);
 
 // Fused stages: workgroup w runs the row records [off[w*(nstage+1)+t],
 // off[w*(nstage+1)+t+1]) of stage t for t = 0..nstage-1, with a barrier

@@ -745,7 +745,8 @@ bool apply_structured(const bf_factors* F, int trans, const bf_c64* X, int64_t l
                       int64_t max_cols, hipStream_t s) {
   const ApplyPlan& P = trans ? F->adj : F->fwd;
   const int64_t rin = trans ? F->m : F->n;
-  if (ncols <= 0 || nseg < 2 || P.stages.size() < 2) return false;
+  const size_t nst = P.stages.size();
+  if (ncols <= 0 || nseg < 2 || nst < 2) return false;
   // the level tl whose consecutive nodes i0, i0 + 1, ... the segments are
   int tl = -1;
   int64_t i0 = 0;
@@ -764,20 +765,31 @@ bool apply_structured(const bf_factors* F, int trans, const bf_c64* X, int64_t l
   if (tl < 0) return false;
   // stages [0, ks) keep every segment apart
   size_t ks = 0;
-  while (ks < P.stages.size() && P.stages[ks].level >= tl) ++ks;
-  if (ks == 0 || ks == P.stages.size()) return false;
-  const Stage& last = P.stages[ks - 1];
-  // segment (relative to i0) of every intermediate row written by stage ks - 1
-  std::vector<int32_t> rowseg((size_t)P.tmp_rows, -1);
-  for (int64_t b = last.blk_off; b < last.blk_off + last.nblk; ++b) {
-    const int64_t g = (P.node[(size_t)b] >> (last.level - tl)) - i0;
-    if (g < 0 || g >= nseg) continue;
-    for (int64_t r = P.out_row[(size_t)b]; r < P.out_row[(size_t)b] + P.out_m[(size_t)b]; ++r)
-      rowseg[(size_t)r] = (int32_t)g;
+  while (ks < nst && P.stages[ks].level >= tl) ++ks;
+  if (ks == 0 || ks == nst) return false;
+  // Windowed stages [ks, kw) (down to level tl - c): every row keeps just the
+  // columns of the segments below its node, 2^(tl - level) ncols of them, and a
+  // merging stage puts its two children's windows side by side.  Taken when
+  // the segments are a whole level (so that windows are whole subtrees), on
+  // the matrix-core path with blocks of at most 64 rows, and with c such that
+  // a window of 2^c ncols columns over every intermediate row fits the budget.
+  int c = 0;
+  size_t kw = ks;
+  if (i0 == 0 && nseg == (int64_t(1) << tl) && F->apply_prec == BF_PREC_BF16X3 &&
+      ncols > kApplyFewCols) {
+    while (c < tl && (ncols << (c + 1)) <= max_cols) ++c;
+    while (kw + 1 < nst && P.stages[kw].level >= tl - c &&
+           (P.stages[kw].level == P.stages[kw - 1].level || P.stages[kw].maxM <= 64))
+      ++kw;
+    // the windows end at the last stage taken
+    c = kw > ks ? tl - P.stages[kw - 1].level : 0;
+    if (c <= 0) {
+      c = 0;
+      kw = ks;
+    }
   }
   Staging local;
   Staging& st = scope_staging(s) ? *scope_staging(s) : local;
-  auto rs_dev = upload(rowseg, s, st);
   // stages [0, ks) on X itself
   const size_t one = (size_t)P.tmp_rows * (size_t)ncols;
   DevBuf<bf_c64> c1(one, s), c2(one, s);
@@ -785,25 +797,67 @@ bool apply_structured(const bf_factors* F, int trans, const bf_c64* X, int64_t l
     const bf_c64* bufs[4] = {X, c1.p, c2.p, nullptr};
     run_stage_range(F, trans, 0, ks, bufs, ldx, ldy, ncols, s, true);
   }
-  const bf_c64* C = last.out_buf == 1 ? c1.p : c2.p;
+  const bf_c64* C = P.stages[ks - 1].out_buf == 1 ? c1.p : c2.p;
+  int64_t cw = ncols;   // columns of C's rows
+  DevBuf<bf_c64> w1, w2;
+  if (kw > ks) {
+    const size_t wsz = (size_t)P.tmp_rows * (size_t)(ncols << c);
+    w1 = DevBuf<bf_c64>(wsz, s);
+    w2 = DevBuf<bf_c64>(wsz, s);
+    bf_c64* nxt = w1.p;
+    for (size_t k = ks; k < kw; ++k) {
+      const Stage& sk = P.stages[k];
+      const bool merge = sk.level < P.stages[k - 1].level;
+      const int64_t wo = merge ? 2 * cw : cw;
+      const int in_idx = P.stages[k - 1].out_buf, out_idx = sk.out_buf;
+      const bf_c64* bufs[4] = {X, nullptr, nullptr, nullptr};
+      bufs[in_idx] = C;
+      bufs[out_idx] = nxt;
+      const int64_t lds[4] = {ldx, 1, 1, ldy};
+      int64_t rss[4] = {1, 1, 1, 1};
+      rss[in_idx] = cw;
+      rss[out_idx] = wo;
+      ProfScope ps(BF_KC_APPLY, s, 8.0 * sk.macs * (double)cw, 8.0 * sk.macs);
+      if (merge)
+        launch_apply_window_stage(P.blks.p + sk.blk_off, sk.nblk, sk.maxM, P.G.p, bufs, lds, rss,
+                                  wo, cw, s);
+      else
+        launch_apply_stage(P.blks.p + sk.blk_off, sk.nblk, P.rows.p + sk.row_off, sk.nrows,
+                           sk.maxMK, sk.maxKK, sk.maxM, P.G.p, bufs, lds, rss, wo,
+                           F->apply_prec, s, true);
+      C = nxt;
+      nxt = nxt == w1.p ? w2.p : w1.p;
+      cw = wo;
+    }
+  }
+  // the rows written by stage kw - 1 each belong to one group of 2^c
+  // segments: the block-diagonal expansion of those groups for the rest
+  const int tg = tl - c;
+  const int32_t ngroups = nseg >> c;
+  const Stage& last = P.stages[kw - 1];
+  std::vector<int32_t> rowseg((size_t)P.tmp_rows, -1);
+  for (int64_t b = last.blk_off; b < last.blk_off + last.nblk; ++b) {
+    const int64_t g = (P.node[(size_t)b] >> (last.level - tg)) - (i0 >> c);
+    if (g < 0 || g >= ngroups) continue;
+    for (int64_t r = P.out_row[(size_t)b]; r < P.out_row[(size_t)b] + P.out_m[(size_t)b]; ++r)
+      rowseg[(size_t)r] = (int32_t)g;
+  }
+  auto rs_dev = upload(rowseg, s, st);
   int64_t cld, crs;
-  tmp_layout(P, ncols, &cld, &crs);
-  // stages [ks, end) on the block-diagonal expansion, nseg_c segments at a time
-  const int32_t per = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nseg, max_cols / ncols));
-  const int64_t wcols = (int64_t)per * ncols;
+  tmp_layout(P, cw, &cld, &crs);
+  const int32_t per = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ngroups, max_cols / cw));
+  const int64_t wcols = (int64_t)per * cw;
   DevBuf<bf_c64> e1((size_t)P.tmp_rows * (size_t)wcols, s), e2((size_t)P.tmp_rows * (size_t)wcols, s);
-  for (int32_t g0 = 0; g0 < nseg; g0 += per) {
-    const int32_t ng = std::min(per, nseg - g0);
-    const int64_t ec = (int64_t)ng * ncols;
+  for (int32_t g0 = 0; g0 < ngroups; g0 += per) {
+    const int32_t ng = std::min(per, ngroups - g0);
+    const int64_t ec = (int64_t)ng * cw;
     int64_t eld, ers;
     tmp_layout(P, ec, &eld, &ers);
-    bf_c64* E = last.out_buf == 1 ? e1.p : e2.p;
-    bf_c64* T = last.out_buf == 1 ? e2.p : e1.p;
-    launch_expand_by_segment(C, crs, cld, rs_dev.p, P.tmp_rows, (int32_t)ncols, g0, ng, E, ers,
+    launch_expand_by_segment(C, crs, cld, rs_dev.p, P.tmp_rows, (int32_t)cw, g0, ng, e1.p, ers,
                              eld, s);
-    const bf_c64* bufs[4] = {X, last.out_buf == 1 ? E : T, last.out_buf == 1 ? T : E,
-                             Y + (int64_t)g0 * ncols * ldy};
-    run_stage_range(F, trans, ks, P.stages.size(), bufs, ldx, ldy, ec, s, true);
+    const bf_c64* bufs[4] = {X, last.out_buf == 1 ? e1.p : e2.p, last.out_buf == 1 ? e2.p : e1.p,
+                             Y + (int64_t)g0 * cw * ldy};
+    run_stage_range(F, trans, kw, nst, bufs, ldx, ldy, ec, s, true);
   }
   return true;
 }

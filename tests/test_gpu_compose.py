@@ -109,12 +109,14 @@ def test_structured_samples_through_factors(bf, trans):
     """A butterfly as the black box of structured samples (Sec. 4.1): the
     product for row segments that are nodes of one tree level (all of them, or
     a run of consecutive ones, as a level split into sample groups gives) runs
-    the stages that keep the segments apart once on the sample itself.  It
-    must equal the definition of the callback: the factors applied to the
-    block-diagonal expansion of the sample -- bitwise at 5 or more columns
-    (the same matrix-core arithmetic per column), to complex64 rounding at
-    fewer (vector-ALU stages on the sample, matrix-core ones on the
-    expansion).  Segments that are not tree nodes take the expansion path."""
+    the stages that keep the segments apart once on the sample itself, and for
+    whole levels the next merging stages on per-node windows of the segments
+    below each node.  It must equal the definition of the callback: the
+    factors applied to the block-diagonal expansion of the sample -- bitwise
+    at 5 or more columns (the same matrix-core arithmetic per column), to
+    complex64 rounding at fewer (vector-ALU stages on the sample, matrix-core
+    ones on the expansion).  Segments that are not tree nodes take the
+    expansion path."""
     import torch
     n, leaf = 4096, 32
     g = wl.segment_pair(n, ppw=8.0, m=3000)
@@ -124,6 +126,7 @@ def test_structured_samples_through_factors(bf, trans):
     rows_in = F.m if trans else F.n
     lo = lambda l, i: (i * rows_in) >> l
     cases = [[lo(1, i) for i in range(3)], [lo(3, i) for i in range(9)],
+             [lo(5, i) for i in range(33)], [lo(L, i) for i in range((1 << L) + 1)],
              [lo(5, i) for i in range(3, 13)], [lo(L, i) for i in range(40, 57)],
              [0, 100, 1000, rows_in]]   # not tree nodes
     rng = np.random.default_rng(8)
