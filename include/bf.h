@@ -513,9 +513,11 @@ int bf_op_dense(const bf_c64* A, int64_t m, int64_t n, int64_t lda, bf_operator*
  * samples (seg != NULL) whose segments are consecutive nodes of one level of
  * the input-side tree (the source tree for matvec, the target tree for
  * rmatvec; what bf_construct passes) run the apply stages that keep the
- * segments apart once on X itself and the rest on the block-diagonal
- * expansion; other segments are expanded first.  Both give the product the
- * callback contract defines (bitwise the same for 5 or more columns). */
+ * segments apart once on X itself, for a whole level with split-BF16 applies
+ * the next merging stages on per-node windows of the segments below each
+ * node, and the rest on the block-diagonal expansion (up to 16 GiB of
+ * intermediates); other segments are expanded first.  All give the product
+ * the callback contract defines (bitwise the same for 5 or more columns). */
 int bf_op_factors(const bf_factors* F, bf_operator* out);
 
 /* Composition A = A1 A2 (A1: m x k, A2: k x n), e.g. the product of two
