@@ -691,38 +691,51 @@ class Builder {
       std::vector<DevBuf<bf_c128>> keep;
       for (int lp = 1; lp < l; ++lp) {
         const int64_t nSl = int64_t(1) << (L() - lp);
+        // the samples of one node ip of this stage share its W blocks and its
+        // output rows: they sit side by side (smax columns each, zero beyond a
+        // sample's width), so each block is one product over all of them
+        const int sh = l - lp;
         std::vector<int64_t> base(ng);
         std::vector<Tall<bf_c128>> next(ng);
         int64_t tot = 0;
-        for (int64_t q = 0; q < ng; ++q) {
-          const int64_t ip = (i0 + q) >> (l - lp);
+        for (int64_t qa = 0; qa < ng;) {
+          const int64_t ip = (i0 + qa) >> sh;
+          int64_t qe = qa;
+          while (qe < ng && ((i0 + qe) >> sh) == ip) ++qe;
           int64_t rows = 0;
-          next[q].roff.resize(nSl);
-          for (int64_t j = 0; j < nSl; ++j) { next[q].roff[j] = rows; rows += F_->kv(lp, ip, j); }
-          next[q].ld = 1;                    // row-major, rows x width
-          next[q].rs = width[i0 + q];
-          base[q] = tot;
-          tot += std::max<int64_t>(rows, 1) * width[i0 + q];
+          std::vector<int64_t> roff((size_t)nSl);
+          for (int64_t j = 0; j < nSl; ++j) { roff[(size_t)j] = rows; rows += F_->kv(lp, ip, j); }
+          const int64_t gw = (qe - qa) * smax;
+          for (int64_t q = qa; q < qe; ++q) {
+            next[q].roff = roff;
+            next[q].ld = 1;                  // row-major, rows x (group width)
+            next[q].rs = gw;
+            base[q] = tot + (q - qa) * smax;
+          }
+          tot += std::max<int64_t>(rows, 1) * gw;
+          qa = qe;
         }
         DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
+        for (int64_t q = 0; q < ng; ++q) next[q].base = buf.p + base[q];
         std::vector<GemmDesc> d;
-        d.reserve((size_t)(ng * nSl));
-        for (int64_t q = 0; q < ng; ++q) {
-          const int64_t ip = (i0 + q) >> (l - lp);
-          next[q].base = buf.p + base[q];
+        for (int64_t qa = 0; qa < ng;) {
+          const int64_t ip = (i0 + qa) >> sh;
+          int64_t qe = qa;
+          while (qe < ng && ((i0 + qe) >> sh) == ip) ++qe;
           for (int64_t j = 0; j < nSl; ++j) {
             const Block& Wb = F_->W[lp][(size_t)((ip << (L() - lp)) + j)];
             const int32_t ka = F_->kv(lp - 1, ip >> 1, 2 * j);
             const int32_t kb = F_->kv(lp - 1, ip >> 1, 2 * j + 1);
             GemmDesc g{};
-            view_out(g, next[q], next[q].roff[j]);
+            view_out(g, next[qa], next[qa].roff[j]);
             g.M = Wb.cols;
-            g.ncols = width[i0 + q];
+            g.ncols = (int32_t)((qe - qa) * smax);
             g.nterm = 2;
-            g.t[0] = view_term(Wb.p, view[q], view[q].roff[2 * j], Wb.rows, ka);
-            g.t[1] = view_term(Wb.p + ka, view[q], view[q].roff[2 * j + 1], Wb.rows, kb);
+            g.t[0] = view_term(Wb.p, view[qa], view[qa].roff[2 * j], Wb.rows, ka);
+            g.t[1] = view_term(Wb.p + ka, view[qa], view[qa].roff[2 * j + 1], Wb.rows, kb);
             if (g.M > 0) d.push_back(g);
           }
+          qa = qe;
         }
         gemm(d, false);
         if (keep.size() >= 1) keep.erase(keep.begin());   // two stages alive at most
@@ -848,38 +861,50 @@ class Builder {
       std::vector<DevBuf<bf_c128>> keep;
       for (int lp = L() - 1; lp > l; --lp) {
         const int64_t nTl = int64_t(1) << lp;
+        // the samples of one node jp of this stage share its R blocks and its
+        // output rows: side by side as in the W sweep
+        const int sh = lp - l;
         std::vector<int64_t> base(ng);
         std::vector<Tall<bf_c128>> next(ng);
         int64_t tot = 0;
-        for (int64_t q = 0; q < ng; ++q) {
-          const int64_t jp = (j0 + q) >> (lp - l);
+        for (int64_t qa = 0; qa < ng;) {
+          const int64_t jp = (j0 + qa) >> sh;
+          int64_t qe = qa;
+          while (qe < ng && ((j0 + qe) >> sh) == jp) ++qe;
           int64_t rows = 0;
-          next[q].roff.resize(nTl);
-          for (int64_t i = 0; i < nTl; ++i) { next[q].roff[i] = rows; rows += F_->ku(lp, i, jp); }
-          next[q].ld = 1;                    // row-major, rows x width
-          next[q].rs = width[j0 + q];
-          base[q] = tot;
-          tot += std::max<int64_t>(rows, 1) * width[j0 + q];
+          std::vector<int64_t> roff((size_t)nTl);
+          for (int64_t i = 0; i < nTl; ++i) { roff[(size_t)i] = rows; rows += F_->ku(lp, i, jp); }
+          const int64_t gw = (qe - qa) * smax;
+          for (int64_t q = qa; q < qe; ++q) {
+            next[q].roff = roff;
+            next[q].ld = 1;                  // row-major, rows x (group width)
+            next[q].rs = gw;
+            base[q] = tot + (q - qa) * smax;
+          }
+          tot += std::max<int64_t>(rows, 1) * gw;
+          qa = qe;
         }
         DevBuf<bf_c128> buf((size_t)std::max<int64_t>(tot, 1), s_);
+        for (int64_t q = 0; q < ng; ++q) next[q].base = buf.p + base[q];
         std::vector<GemmDesc> d;
-        d.reserve((size_t)(ng * nTl));
-        for (int64_t q = 0; q < ng; ++q) {
-          const int64_t jp = (j0 + q) >> (lp - l);
-          next[q].base = buf.p + base[q];
+        for (int64_t qa = 0; qa < ng;) {
+          const int64_t jp = (j0 + qa) >> sh;
+          int64_t qe = qa;
+          while (qe < ng && ((j0 + qe) >> sh) == jp) ++qe;
           for (int64_t i = 0; i < nTl; ++i) {
             const Block& Rb = F_->R[lp - lm()][(size_t)((i << (L() - lp)) + jp)];
             const int32_t k1 = F_->ku(lp + 1, 2 * i, jp >> 1);
             const int32_t k2 = F_->ku(lp + 1, 2 * i + 1, jp >> 1);
             GemmDesc g{};
-            view_out(g, next[q], next[q].roff[i]);
+            view_out(g, next[qa], next[qa].roff[i]);
             g.M = Rb.cols;
-            g.ncols = width[j0 + q];
+            g.ncols = (int32_t)((qe - qa) * smax);
             g.nterm = 2;
-            g.t[0] = view_term(Rb.p, view[q], view[q].roff[2 * i], Rb.rows, k1);
-            g.t[1] = view_term(Rb.p + k1, view[q], view[q].roff[2 * i + 1], Rb.rows, k2);
+            g.t[0] = view_term(Rb.p, view[qa], view[qa].roff[2 * i], Rb.rows, k1);
+            g.t[1] = view_term(Rb.p + k1, view[qa], view[qa].roff[2 * i + 1], Rb.rows, k2);
             if (g.M > 0) d.push_back(g);
           }
+          qa = qe;
         }
         gemm(d, false);
         if (!keep.empty()) keep.erase(keep.begin());   // two stages alive at most
