@@ -516,7 +516,7 @@ int bf_op_dense(const bf_c64* A, int64_t m, int64_t n, int64_t lda, bf_operator*
  * segments apart once on X itself, for a whole level with split-BF16 applies
  * the next merging stages on per-node windows of the segments below each
  * node, and the rest on the block-diagonal expansion (up to 16 GiB of
- * intermediates); other segments are expanded first.  All give the product
+ * intermediates at once); other segments are expanded first.  All give the product
  * the callback contract defines (bitwise the same for 5 or more columns). */
 int bf_op_factors(const bf_factors* F, bf_operator* out);
 

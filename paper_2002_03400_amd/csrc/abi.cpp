@@ -629,9 +629,10 @@ static int factors_apply(void* user, int trans, const bf_c64* X, int64_t ldx, in
     // segments that are nodes of the input-side tree: the stages that keep
     // them apart run once on X, later ones on windows of the segments below
     // each node, the rest on the expansion (each phase two intermediates of
-    // 8 tmp_rows bytes per column, at most 16 GiB)
+    // 8 tmp_rows bytes per column, at most 8 GiB; both phases' buffers are
+    // alive at the end)
     const int64_t tree_cols =
-        std::max<int64_t>(ncols, (int64_t)((double)(int64_t(16) << 30) / (16.0 * (double)P.tmp_rows)));
+        std::max<int64_t>(ncols, (int64_t)((double)(int64_t(8) << 30) / (16.0 * (double)P.tmp_rows)));
     if (apply_structured(c->F, trans, X, ldx, ncols, Y, ldy, seg, nseg, tree_cols, s))
       return;
     // other segments in chunks: the expanded input and the apply's two
