@@ -32,7 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # per-request constructions run their two sides on two streams (bf_opts
-# BF_OPT_ONE_STREAM off; the request engine keeps one stream per request)
+# BF_OPT_ONE_STREAM off; the request engine with several slots keeps one
+# stream per request, with one slot the two sides)
 TWO_SIDES = True
 METRIC = "factorizations/s + p50/p99 latency at n=64K, rel err ≤1e-6 vs FP64 oracle"
 # MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 2.4 GHz x 64 flops/clock
@@ -849,7 +850,8 @@ def headline(args):
                "constructions": sum(r.kind == "construct" for r in reqs),
                "applies": sum(r.kind != "construct" for r in reqs)}
         # served: `slots` device slots with continuous batching of applies;
-        # per-request path: one slot, every request its own launches
+        # per-request path: one slot, every request its own launches (its two
+        # sides on two streams, as in the closed loop)
         for name, slots, bc in (("served", args.slots, args.batch_cols), ("per_request", 1, 0)):
             S, wall_m, lat_mc, lat_ma, _ = run_served(bf, reqs, slots, args.leaf, batch_cols=bc,
                                                       rounds=bool(args.solve_rounds) and slots > 1)

@@ -395,9 +395,10 @@ int bf_server_create(const bf_server_opts* opts, bf_server** out);
 /* Finishes every request that can still run, then frees all resident factors. */
 int bf_server_destroy(bf_server* S);
 /* Queue a construction; the operator (its callbacks and user data) must stay
-   valid until the request completes.  Writes the request's ticket.  The
-   engine runs every construction on its slot's one stream (it adds
-   BF_OPT_ONE_STREAM to opts): the slots already overlap requests. */
+   valid until the request completes.  Writes the request's ticket.  With
+   more than one slot the engine runs every construction on its slot's one
+   stream (it adds BF_OPT_ONE_STREAM to opts): the slots already overlap
+   requests. */
 int bf_server_submit_construct(bf_server* S, const bf_operator* op, double tol, int64_t leaf,
                                const bf_opts* opts, int64_t* ticket);
 /* Queue Y = F X (trans 0) or F^H X (trans 1) with the factors of construction

@@ -358,9 +358,10 @@ int bf_server_submit_construct(bf_server* S, const bf_operator* op, double tol, 
   r->leaf = leaf;
   if (opts) r->opts = *opts;
   else r->opts = bf_opts{2, 4, 0, 0, 0, 0, nullptr, nullptr, 0, 0};
-  // one stream per construction: the slots already overlap requests, and
-  // a second stream per request measured 1-2% fewer constructions per second
-  r->opts.flags |= BF_OPT_ONE_STREAM;
+  // one stream per construction when there are several slots: they already
+  // overlap requests, and a second stream per request measured 1-2% fewer
+  // constructions per second; a single slot keeps the two sides apart
+  if (S->streams.size() > 1) r->opts.flags |= BF_OPT_ONE_STREAM;
   r->has_opts = true;
   r->footprint = construct_footprint(op->m, op->n, leaf);
   r->arrival = Clock::now();
