@@ -895,18 +895,31 @@ void launch_apply_window_stage(const ApplyBlk* blks_dev, int32_t nblk, int32_t m
 // an apply of 13 stages becomes 4 launches instead of 13 dependent ones.
 // Rows follow the few-column kernels above (8 lanes per output row, same
 // slots and summation order, so 1 to 4 columns give their results bit for
-// bit).  Intermediates of a
-// launch are written to global memory and read back by the same workgroup
-// after the barrier (each stage writes its own rows, so workgroups never
-// overwrite what another still reads).
+// bit).  Inside a launch a group's intermediates stay in its workgroup's
+// LDS (a stage writes one half, the next stage reads it after the barrier
+// and writes the other); the last stage of a launch writes global memory,
+// each launch its own rows of the tall intermediate, so workgroups never
+// overwrite what another still reads.
+
+// Buffer i of a fused launch: the caller's buffers, or (kFusedLdsBuf) the
+// workgroup's LDS matrix of 2 kFusedLdsRows rows per column.
+__device__ __forceinline__ bf_c64* fused_buf(const ApplyBufs& B, bf_c64* lds, int i) {
+  return i == kFusedLdsBuf ? lds : B.p[i];
+}
+__device__ __forceinline__ int64_t fused_ld(const ApplyBufs& B, int i) {
+  return i == kFusedLdsBuf ? 2 * kFusedLdsRows : B.ld[i];
+}
+
 template <typename Acc, int NC>
 __device__ __forceinline__ void fused_row(const ApplyRowRec& rr, int q, const bf_c64* __restrict__ G,
-                                          const ApplyBufs& B, int ncols) {
+                                          const ApplyBufs& B, bf_c64* lds, int ncols) {
   const int KK = rr.KK;
   const bf_c64* g = G + rr.g;
-  const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
-  const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
-  const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
+  const bf_c64* in0 = fused_buf(B, lds, rr.in_buf0) + rr.in0;
+  const bf_c64* in1 = fused_buf(B, lds, rr.in_buf1) + rr.in1;
+  const int64_t ld0 = fused_ld(B, rr.in_buf0), ld1 = fused_ld(B, rr.in_buf1);
+  // 16-byte input loads from global memory only (LDS rows are 8-byte aligned)
+  const bool pair_in = rr.in_buf0 != kFusedLdsBuf;
   Acc acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = Acc{0, 0};
@@ -929,7 +942,7 @@ __device__ __forceinline__ void fused_row(const ApplyRowRec& rr, int q, const bf
         const int64_t ldk = seg0 ? ld0 : ld1;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          if (c < ncols && k1v && seg0 == seg1) {
+          if (c < ncols && k1v && seg0 == seg1 && pair_in) {
             load_pair(base + k + (int64_t)c * ldk, xv[2 * u][c], xv[2 * u + 1][c]);
           } else {
             xv[2 * u][c] = (c < ncols && k0v) ? base[k + (int64_t)c * ldk] : bf_c64{0.f, 0.f};
@@ -972,8 +985,8 @@ __device__ __forceinline__ void fused_row(const ApplyRowRec& rr, int q, const bf
     acc[c].im = row8_sum(acc[c].im);
   }
   if (q == 0) {
-    bf_c64* out = B.p[rr.out_buf] + rr.out;
-    const int64_t ldo = B.ld[rr.out_buf];
+    bf_c64* out = fused_buf(B, lds, rr.out_buf) + rr.out;
+    const int64_t ldo = fused_ld(B, rr.out_buf);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
       if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
@@ -999,11 +1012,11 @@ __device__ __forceinline__ void fused_fetch_g(const ApplyRowRec& rr, bool has, i
 template <typename Acc, int NC>
 __device__ __forceinline__ void fused_row_pre(const ApplyRowRec& rr, const bf_c64 (&g)[AF_PF], int q,
                                               const bf_c64* __restrict__ G, const ApplyBufs& B,
-                                              int ncols) {
+                                              bf_c64* lds, int ncols) {
   const int KK = rr.KK, K0 = rr.K0;
-  const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
-  const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
-  const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
+  const bf_c64* in0 = fused_buf(B, lds, rr.in_buf0) + rr.in0;
+  const bf_c64* in1 = fused_buf(B, lds, rr.in_buf1) + rr.in1;
+  const int64_t ld0 = fused_ld(B, rr.in_buf0), ld1 = fused_ld(B, rr.in_buf1);
   constexpr int CH = NC < 4 ? NC : 4;
   Acc acc[NC];
 #pragma unroll
@@ -1049,8 +1062,8 @@ __device__ __forceinline__ void fused_row_pre(const ApplyRowRec& rr, const bf_c6
     acc[c].im = row8_sum(acc[c].im);
   }
   if (q == 0) {
-    bf_c64* out = B.p[rr.out_buf] + rr.out;
-    const int64_t ldo = B.ld[rr.out_buf];
+    bf_c64* out = fused_buf(B, lds, rr.out_buf) + rr.out;
+    const int64_t ldo = fused_ld(B, rr.out_buf);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
       if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
@@ -1062,10 +1075,10 @@ __device__ __forceinline__ void fused_row_pre(const ApplyRowRec& rr, const bf_c6
 // wait for the inputs would otherwise wait for those fetches too).
 template <int NC>
 __device__ __forceinline__ void fused_in_load(const ApplyRowRec& rr, int q, const ApplyBufs& B,
-                                              int ncols, bf_c64 (&xv)[AF_PF][NC]) {
-  const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
-  const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
-  const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
+                                              bf_c64* lds, int ncols, bf_c64 (&xv)[AF_PF][NC]) {
+  const bf_c64* in0 = fused_buf(B, lds, rr.in_buf0) + rr.in0;
+  const bf_c64* in1 = fused_buf(B, lds, rr.in_buf1) + rr.in1;
+  const int64_t ld0 = fused_ld(B, rr.in_buf0), ld1 = fused_ld(B, rr.in_buf1);
 #pragma unroll
   for (int j = 0; j < AF_PF; ++j) {
     const int k = fused_k<NC>(q, j);
@@ -1082,7 +1095,7 @@ template <typename Acc, int NC>
 __device__ __forceinline__ void fused_row_fin(const ApplyRowRec& rr, const bf_c64 (&g)[AF_PF],
                                               const bf_c64 (&xv)[AF_PF][NC], int q,
                                               const bf_c64* __restrict__ G, const ApplyBufs& B,
-                                              int ncols) {
+                                              bf_c64* lds, int ncols) {
   const int KK = rr.KK, K0 = rr.K0;
   Acc acc[NC];
 #pragma unroll
@@ -1093,9 +1106,9 @@ __device__ __forceinline__ void fused_row_fin(const ApplyRowRec& rr, const bf_c6
     for (int c = 0; c < NC; ++c) acc_fma(acc[c], g[j], xv[j][c]);
   // further slots (rows of more than 64 terms)
   if (fused_k<NC>(0, AF_PF) < KK) {
-    const bf_c64* in0 = B.p[rr.in_buf0] + rr.in0;
-    const bf_c64* in1 = B.p[rr.in_buf1] + rr.in1;
-    const int64_t ld0 = B.ld[rr.in_buf0], ld1 = B.ld[rr.in_buf1];
+    const bf_c64* in0 = fused_buf(B, lds, rr.in_buf0) + rr.in0;
+    const bf_c64* in1 = fused_buf(B, lds, rr.in_buf1) + rr.in1;
+    const int64_t ld0 = fused_ld(B, rr.in_buf0), ld1 = fused_ld(B, rr.in_buf1);
     for (int j0 = AF_PF; fused_k<NC>(0, j0) < KK; j0 += AF_PF) {
 #pragma unroll
       for (int jj = 0; jj < AF_PF; ++jj) {
@@ -1118,8 +1131,8 @@ __device__ __forceinline__ void fused_row_fin(const ApplyRowRec& rr, const bf_c6
     acc[c].im = row8_sum(acc[c].im);
   }
   if (q == 0) {
-    bf_c64* out = B.p[rr.out_buf] + rr.out;
-    const int64_t ldo = B.ld[rr.out_buf];
+    bf_c64* out = fused_buf(B, lds, rr.out_buf) + rr.out;
+    const int64_t ldo = fused_ld(B, rr.out_buf);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
       if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
@@ -1133,7 +1146,7 @@ __device__ __forceinline__ void fused_row_fin(const ApplyRowRec& rr, const bf_c6
 // first RPT rows of each thread in stage t + 1 (their records, then their
 // factor entries) and their records of stage t + 2 are fetched while stage t
 // computes: after a barrier only the inputs, just written by the workgroup
-// itself, are waited for.  Further rows of a stage take extra passes without
+// itself (to LDS), are waited for.  Further rows of a stage take extra passes without
 // fetching ahead.
 template <typename Acc, int NC, int NT, int RPT>
 __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __restrict__ rows,
@@ -1146,6 +1159,7 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
   constexpr int RS = NT / AP_LPR;   // rows per pass
   const int32_t* o = off + (int64_t)blockIdx.x * (nstage + 1);
   constexpr int small = NC <= 2;
+  __shared__ bf_c64 lds[2 * kFusedLdsRows * NC];
   auto fetch_rec = [&](int t, int i, ApplyRowRec& r) -> bool {
     const int32_t R = o[t] + rl + i * RS;
     const bool h = R < o[t + 1];
@@ -1169,7 +1183,7 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
     bf_c64 xv0[RI][AF_PF][NC];
 #pragma unroll
     for (int i = 0; i < RI; ++i)
-      if (hc[i]) fused_in_load<NC>(rc[i], q, B, ncols, xv0[i]);
+      if (hc[i]) fused_in_load<NC>(rc[i], q, B, lds, ncols, xv0[i]);
     __builtin_amdgcn_sched_barrier(0);
     ApplyRowRec r2[RPT];
     bool h2[RPT];
@@ -1183,12 +1197,12 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
     for (int i = 0; i < RPT; ++i) {
       if (!hc[i]) continue;
       if (i < RI)
-        fused_row_fin<Acc, NC>(rc[i], gc[i], xv0[i < RI ? i : 0], q, G, B, ncols);
+        fused_row_fin<Acc, NC>(rc[i], gc[i], xv0[i < RI ? i : 0], q, G, B, lds, ncols);
       else
-        fused_row_pre<Acc, NC>(rc[i], gc[i], q, G, B, ncols);
+        fused_row_pre<Acc, NC>(rc[i], gc[i], q, G, B, lds, ncols);
     }
     for (int32_t R = o[t] + rl + RPT * RS; R < o[t + 1]; R += RS)
-      fused_row<Acc, NC>(rows[R], q, G, B, ncols);
+      fused_row<Acc, NC>(rows[R], q, G, B, lds, ncols);
     if (t + 1 < nstage) __syncthreads();
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {

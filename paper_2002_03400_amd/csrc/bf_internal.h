@@ -317,6 +317,13 @@ constexpr int kApplyFewCols = 4;
 // Up to this many right-hand sides an apply runs its stages fused (several
 // stages per launch, launch_apply_fused), column-major throughout.
 constexpr int kApplyFusedCols = kApplyFewCols;
+// Rows of one group and stage in a fused launch of several stages.  Such a
+// group's intermediates stay in its workgroup's LDS: row records with buffer
+// index kFusedLdsBuf address a column-major LDS matrix of 2 kFusedLdsRows
+// rows per column, a stage writing the half (stage - first stage) & 1 and
+// the next stage reading it there.
+constexpr int kFusedLdsRows = 128;
+constexpr int kFusedLdsBuf = 4;
 // maxMK / maxKK / maxM: largest M*(K0+K1), K0+K1 and M over the stage's
 // blocks.  Buffer i holds element (r, c) at bufs[i][r * rss[i] + c * lds[i]]
 // (column-major: rss = 1; with at most kApplyFewCols columns every buffer must be).

@@ -123,7 +123,7 @@ struct PlanBuilder {
 // faster at one column (57 vs 62 us).  Above 4 columns the stage-by-stage
 // matrix-core apply is faster at every size measured (n = 65536, 16 columns:
 // 117 vs 189 us), so only applies of up to 4 columns fuse.
-constexpr int64_t kFusedMaxStageRows = 128;
+constexpr int64_t kFusedMaxStageRows = kFusedLdsRows;
 constexpr int64_t kFusedMinGroups = 256;
 // Stages with more factor bytes than this stream at HBM rate on their own
 // (each launch then fills the device); only smaller, latency-bound stages
@@ -149,12 +149,13 @@ struct UnionFind {
   }
 };
 
-// The fused schedule of a plan: every stage t but the last writes rows
-// [base_t, base_t + rows_t) of one tall intermediate (buffer 1), every stage
-// after the first reads the previous stage's rows there; consecutive stages
-// are grouped into launches, each launch's blocks split into independent
-// groups (one workgroup each), and the groups' blocks re-indexed as row
-// records ordered by launch, group and stage.
+// The fused schedule of a plan: consecutive stages are grouped into
+// launches, each launch's blocks split into independent groups (one
+// workgroup each), and the groups' blocks re-indexed as row records ordered
+// by launch, group and stage.  The last stage of a launch (unless it is the
+// plan's last) writes rows [base_t, base_t + rows_t) of one tall intermediate
+// (buffer 1), which the next launch's first stage reads; inside a launch a
+// group's stages hand their rows over in its workgroup's LDS.
 struct FusedHost {
   std::vector<ApplyBlk> fb;      // blocks in fused order, fused buffers and rows
   std::vector<int32_t> off;      // per segment, group and stage: first row record
@@ -205,7 +206,7 @@ void fused_schedule(PlanBuilder& pb, ApplyPlan& plan, FusedHost& fh) {
   std::vector<int32_t>& off = fh.off;
   fb.reserve(nb);
   int64_t rec = 0, gcur = 0;
-  std::vector<int64_t> new_g(nb, 0);
+  std::vector<int64_t> new_g(nb, 0), lds_row(nb, 0);
   UnionFind uf(nb);
   int a = 0;
   while (a < ns) {
@@ -253,6 +254,39 @@ void fused_schedule(PlanBuilder& pb, ApplyPlan& plan, FusedHost& fh) {
     seg.first_stage = a;
     for (int t = a; t < e; ++t) seg.macs += stg[t].macs;
     for (auto& grp : members) {
+      // Within the launch the group's stages pass their rows through LDS:
+      // stage t's blocks (sorted by output row) get consecutive rows of LDS
+      // half (t - a) & 1, and an input range of stage t + 1, whose producers
+      // all lie in the group, maps to as many consecutive LDS rows.
+      bool in_lds = e - a >= 2;
+      for (int t = a; in_lds && t + 1 < e; ++t) {
+        int64_t r = 0;
+        for (int32_t b : grp[(size_t)(t - a)]) {
+          lds_row[(size_t)b] = ((t - a) & 1) * kFusedLdsRows + r;
+          r += pb.blks[(size_t)b].M;
+        }
+        in_lds = r <= kFusedLdsRows;
+      }
+      // LDS row of row x of stage t's output in the group, or -1
+      auto lds_of = [&](int t, int64_t x) -> int64_t {
+        const auto& pg = grp[(size_t)(t - a)];
+        auto it = std::upper_bound(pg.begin(), pg.end(), x, [&](int64_t v, int32_t b) {
+          return v < pb.blks[(size_t)b].out_row;
+        });
+        if (it == pg.begin()) return -1;
+        const ApplyBlk& pk = pb.blks[(size_t)*(it - 1)];
+        return x < pk.out_row + pk.M ? lds_row[(size_t)*(it - 1)] + (x - pk.out_row) : -1;
+      };
+      for (int t = a + 1; in_lds && t < e; ++t)
+        for (int32_t b : grp[(size_t)(t - a)]) {
+          const ApplyBlk& bk = pb.blks[(size_t)b];
+          const int64_t rr[2][2] = {{bk.in_row0, bk.K0}, {bk.in_row1, bk.K1}};
+          for (auto& r : rr) {
+            if (r[1] <= 0) continue;
+            const int64_t f = lds_of(t - 1, r[0]), l = lds_of(t - 1, r[0] + r[1] - 1);
+            if (f < 0 || l != f + r[1] - 1) in_lds = false;
+          }
+        }
       for (int t = a; t < e; ++t) {
         off.push_back((int32_t)rec);
         int64_t rows_gs = 0;
@@ -263,11 +297,19 @@ void fused_schedule(PlanBuilder& pb, ApplyPlan& plan, FusedHost& fh) {
           gcur += (int64_t)pb.blks[(size_t)b].M * (pb.blks[(size_t)b].K0 + pb.blks[(size_t)b].K1);
           ApplyBlk bk = pb.blks[(size_t)b];
           bk.g_off = new_g[(size_t)b];
-          if (t + 1 < ns) {
+          if (in_lds && t + 1 < e) {
+            bk.out_buf = kFusedLdsBuf;
+            bk.out_row = lds_row[(size_t)b];
+          } else if (t + 1 < ns) {
             bk.out_buf = 1;
             bk.out_row += base[t];
           }
-          if (t > 0) {
+          if (in_lds && t > a) {
+            bk.in_buf0 = kFusedLdsBuf;
+            bk.in_buf1 = kFusedLdsBuf;
+            bk.in_row0 = bk.K0 > 0 ? lds_of(t - 1, bk.in_row0) : 0;
+            bk.in_row1 = bk.K1 > 0 ? lds_of(t - 1, bk.in_row1) : 0;
+          } else if (t > 0) {
             bk.in_buf0 = 1;
             bk.in_buf1 = 1;
             bk.in_row0 += base[t - 1];
