@@ -901,25 +901,60 @@ void launch_apply_window_stage(const ApplyBlk* blks_dev, int32_t nblk, int32_t m
 // each launch its own rows of the tall intermediate, so workgroups never
 // overwrite what another still reads.
 
-// Buffer i of a fused launch: the caller's buffers, or (kFusedLdsBuf) the
-// workgroup's LDS matrix of 2 kFusedLdsRows rows per column.
-__device__ __forceinline__ bf_c64* fused_buf(const ApplyBufs& B, bf_c64* lds, int i) {
-  return i == kFusedLdsBuf ? lds : B.p[i];
+// Inputs of a fused row: LI, from the workgroup's LDS matrix of
+// 2 kFusedLdsRows rows per column (records with buffer kFusedLdsBuf), else
+// from the caller's buffers.  A row's two input ranges are both in LDS or
+// both in global memory, and so are all rows of a group's stage: callers
+// pick the instantiation per row, a uniform branch, so that every access
+// has a known address space (LDS or global, never flat).
+template <bool LI>
+__device__ __forceinline__ const bf_c64* fused_in(const ApplyBufs& B, const bf_c64* lds, int i,
+                                                  int64_t off) {
+  if constexpr (LI) return lds + off;
+  else return B.p[i] + off;
 }
-__device__ __forceinline__ int64_t fused_ld(const ApplyBufs& B, int i) {
-  return i == kFusedLdsBuf ? 2 * kFusedLdsRows : B.ld[i];
+template <bool LI>
+__device__ __forceinline__ int64_t fused_in_ld(const ApplyBufs& B, int i) {
+  if constexpr (LI) return 2 * kFusedLdsRows;
+  else return B.ld[i];
+}
+// The row's sums (lane q = 0 of the row) to LDS or to the caller's buffer.
+template <typename Acc, int NC>
+__device__ __forceinline__ void fused_store(const ApplyRowRec& rr, const ApplyBufs& B, bf_c64* lds,
+                                            const Acc (&acc)[NC], int ncols) {
+  if (rr.out_buf == kFusedLdsBuf) {
+    // relaxed workgroup-scope atomic stores (plain LDS writes): unlike ordinary
+    // stores they are never merged with the global branch's into one flat
+    // store through a selected pointer
+    uint64_t* out = reinterpret_cast<uint64_t*>(lds + rr.out);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < ncols) {
+        const bf_c64 v{(float)acc[c].re, (float)acc[c].im};
+        uint64_t bits;
+        __builtin_memcpy(&bits, &v, sizeof(bits));
+        __hip_atomic_store(out + (int64_t)c * 2 * kFusedLdsRows, bits, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+  } else {
+    bf_c64* out = B.p[rr.out_buf] + rr.out;
+    const int64_t ldo = B.ld[rr.out_buf];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
+  }
 }
 
-template <typename Acc, int NC>
+template <typename Acc, int NC, bool LI>
 __device__ __forceinline__ void fused_row(const ApplyRowRec& rr, int q, const bf_c64* __restrict__ G,
                                           const ApplyBufs& B, bf_c64* lds, int ncols) {
   const int KK = rr.KK;
   const bf_c64* g = G + rr.g;
-  const bf_c64* in0 = fused_buf(B, lds, rr.in_buf0) + rr.in0;
-  const bf_c64* in1 = fused_buf(B, lds, rr.in_buf1) + rr.in1;
-  const int64_t ld0 = fused_ld(B, rr.in_buf0), ld1 = fused_ld(B, rr.in_buf1);
+  const bf_c64* in0 = fused_in<LI>(B, lds, rr.in_buf0, rr.in0);
+  const bf_c64* in1 = fused_in<LI>(B, lds, rr.in_buf1, rr.in1);
+  const int64_t ld0 = fused_in_ld<LI>(B, rr.in_buf0), ld1 = fused_in_ld<LI>(B, rr.in_buf1);
   // 16-byte input loads from global memory only (LDS rows are 8-byte aligned)
-  const bool pair_in = rr.in_buf0 != kFusedLdsBuf;
+  constexpr bool pair_in = !LI;
   Acc acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = Acc{0, 0};
@@ -984,13 +1019,7 @@ __device__ __forceinline__ void fused_row(const ApplyRowRec& rr, int q, const bf
     acc[c].re = row8_sum(acc[c].re);
     acc[c].im = row8_sum(acc[c].im);
   }
-  if (q == 0) {
-    bf_c64* out = fused_buf(B, lds, rr.out_buf) + rr.out;
-    const int64_t ldo = fused_ld(B, rr.out_buf);
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
-  }
+  if (q == 0) fused_store<Acc, NC>(rr, B, lds, acc, ncols);
 }
 
 constexpr int AF_PF = 8;   // factor entries per lane fetched ahead (rows of up to 64 terms)
@@ -1009,14 +1038,14 @@ __device__ __forceinline__ void fused_fetch_g(const ApplyRowRec& rr, bool has, i
 // inputs of those slots are loaded together (in chunks of 4 columns), then
 // further slots (rows of more than 64 terms) stream from memory.  Same
 // slots, same order as fused_row.
-template <typename Acc, int NC>
+template <typename Acc, int NC, bool LI>
 __device__ __forceinline__ void fused_row_pre(const ApplyRowRec& rr, const bf_c64 (&g)[AF_PF], int q,
                                               const bf_c64* __restrict__ G, const ApplyBufs& B,
                                               bf_c64* lds, int ncols) {
   const int KK = rr.KK, K0 = rr.K0;
-  const bf_c64* in0 = fused_buf(B, lds, rr.in_buf0) + rr.in0;
-  const bf_c64* in1 = fused_buf(B, lds, rr.in_buf1) + rr.in1;
-  const int64_t ld0 = fused_ld(B, rr.in_buf0), ld1 = fused_ld(B, rr.in_buf1);
+  const bf_c64* in0 = fused_in<LI>(B, lds, rr.in_buf0, rr.in0);
+  const bf_c64* in1 = fused_in<LI>(B, lds, rr.in_buf1, rr.in1);
+  const int64_t ld0 = fused_in_ld<LI>(B, rr.in_buf0), ld1 = fused_in_ld<LI>(B, rr.in_buf1);
   constexpr int CH = NC < 4 ? NC : 4;
   Acc acc[NC];
 #pragma unroll
@@ -1061,24 +1090,18 @@ __device__ __forceinline__ void fused_row_pre(const ApplyRowRec& rr, const bf_c6
     acc[c].re = row8_sum(acc[c].re);
     acc[c].im = row8_sum(acc[c].im);
   }
-  if (q == 0) {
-    bf_c64* out = fused_buf(B, lds, rr.out_buf) + rr.out;
-    const int64_t ldo = fused_ld(B, rr.out_buf);
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
-  }
+  if (q == 0) fused_store<Acc, NC>(rr, B, lds, acc, ncols);
 }
 
 // fused_row_pre in two halves, so that a stage's input loads can be issued
 // before the next stage's fetches (memory results return in issue order: a
 // wait for the inputs would otherwise wait for those fetches too).
-template <int NC>
+template <int NC, bool LI>
 __device__ __forceinline__ void fused_in_load(const ApplyRowRec& rr, int q, const ApplyBufs& B,
                                               bf_c64* lds, int ncols, bf_c64 (&xv)[AF_PF][NC]) {
-  const bf_c64* in0 = fused_buf(B, lds, rr.in_buf0) + rr.in0;
-  const bf_c64* in1 = fused_buf(B, lds, rr.in_buf1) + rr.in1;
-  const int64_t ld0 = fused_ld(B, rr.in_buf0), ld1 = fused_ld(B, rr.in_buf1);
+  const bf_c64* in0 = fused_in<LI>(B, lds, rr.in_buf0, rr.in0);
+  const bf_c64* in1 = fused_in<LI>(B, lds, rr.in_buf1, rr.in1);
+  const int64_t ld0 = fused_in_ld<LI>(B, rr.in_buf0), ld1 = fused_in_ld<LI>(B, rr.in_buf1);
 #pragma unroll
   for (int j = 0; j < AF_PF; ++j) {
     const int k = fused_k<NC>(q, j);
@@ -1091,7 +1114,7 @@ __device__ __forceinline__ void fused_in_load(const ApplyRowRec& rr, int q, cons
   }
 }
 
-template <typename Acc, int NC>
+template <typename Acc, int NC, bool LI>
 __device__ __forceinline__ void fused_row_fin(const ApplyRowRec& rr, const bf_c64 (&g)[AF_PF],
                                               const bf_c64 (&xv)[AF_PF][NC], int q,
                                               const bf_c64* __restrict__ G, const ApplyBufs& B,
@@ -1106,9 +1129,9 @@ __device__ __forceinline__ void fused_row_fin(const ApplyRowRec& rr, const bf_c6
     for (int c = 0; c < NC; ++c) acc_fma(acc[c], g[j], xv[j][c]);
   // further slots (rows of more than 64 terms)
   if (fused_k<NC>(0, AF_PF) < KK) {
-    const bf_c64* in0 = fused_buf(B, lds, rr.in_buf0) + rr.in0;
-    const bf_c64* in1 = fused_buf(B, lds, rr.in_buf1) + rr.in1;
-    const int64_t ld0 = fused_ld(B, rr.in_buf0), ld1 = fused_ld(B, rr.in_buf1);
+    const bf_c64* in0 = fused_in<LI>(B, lds, rr.in_buf0, rr.in0);
+    const bf_c64* in1 = fused_in<LI>(B, lds, rr.in_buf1, rr.in1);
+    const int64_t ld0 = fused_in_ld<LI>(B, rr.in_buf0), ld1 = fused_in_ld<LI>(B, rr.in_buf1);
     for (int j0 = AF_PF; fused_k<NC>(0, j0) < KK; j0 += AF_PF) {
 #pragma unroll
       for (int jj = 0; jj < AF_PF; ++jj) {
@@ -1130,13 +1153,7 @@ __device__ __forceinline__ void fused_row_fin(const ApplyRowRec& rr, const bf_c6
     acc[c].re = row8_sum(acc[c].re);
     acc[c].im = row8_sum(acc[c].im);
   }
-  if (q == 0) {
-    bf_c64* out = fused_buf(B, lds, rr.out_buf) + rr.out;
-    const int64_t ldo = fused_ld(B, rr.out_buf);
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c < ncols) out[(int64_t)c * ldo] = bf_c64{(float)acc[c].re, (float)acc[c].im};
-  }
+  if (q == 0) fused_store<Acc, NC>(rr, B, lds, acc, ncols);
 }
 
 // off[w * (nstage + 1) + t] .. off[w * (nstage + 1) + t + 1]: the row records
@@ -1183,7 +1200,12 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
     bf_c64 xv0[RI][AF_PF][NC];
 #pragma unroll
     for (int i = 0; i < RI; ++i)
-      if (hc[i]) fused_in_load<NC>(rc[i], q, B, lds, ncols, xv0[i]);
+      if (hc[i]) {
+        if (rc[i].in_buf0 == kFusedLdsBuf)
+          fused_in_load<NC, true>(rc[i], q, B, lds, ncols, xv0[i]);
+        else
+          fused_in_load<NC, false>(rc[i], q, B, lds, ncols, xv0[i]);
+      }
     __builtin_amdgcn_sched_barrier(0);
     ApplyRowRec r2[RPT];
     bool h2[RPT];
@@ -1196,13 +1218,25 @@ __global__ __launch_bounds__(NT) void apply_fused_kernel(const ApplyRowRec* __re
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       if (!hc[i]) continue;
-      if (i < RI)
-        fused_row_fin<Acc, NC>(rc[i], gc[i], xv0[i < RI ? i : 0], q, G, B, lds, ncols);
-      else
-        fused_row_pre<Acc, NC>(rc[i], gc[i], q, G, B, lds, ncols);
+      const bool li = rc[i].in_buf0 == kFusedLdsBuf;
+      if (i < RI) {
+        if (li)
+          fused_row_fin<Acc, NC, true>(rc[i], gc[i], xv0[i < RI ? i : 0], q, G, B, lds, ncols);
+        else
+          fused_row_fin<Acc, NC, false>(rc[i], gc[i], xv0[i < RI ? i : 0], q, G, B, lds, ncols);
+      } else if (li) {
+        fused_row_pre<Acc, NC, true>(rc[i], gc[i], q, G, B, lds, ncols);
+      } else {
+        fused_row_pre<Acc, NC, false>(rc[i], gc[i], q, G, B, lds, ncols);
+      }
     }
-    for (int32_t R = o[t] + rl + RPT * RS; R < o[t + 1]; R += RS)
-      fused_row<Acc, NC>(rows[R], q, G, B, lds, ncols);
+    for (int32_t R = o[t] + rl + RPT * RS; R < o[t + 1]; R += RS) {
+      const ApplyRowRec rr = rows[R];
+      if (rr.in_buf0 == kFusedLdsBuf)
+        fused_row<Acc, NC, true>(rr, q, G, B, lds, ncols);
+      else
+        fused_row<Acc, NC, false>(rr, q, G, B, lds, ncols);
+    }
     if (t + 1 < nstage) __syncthreads();
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
